@@ -1,0 +1,24 @@
+"""Work and byte accounting for range-query scans.
+
+Each stored value takes 4 bytes (float32 columns, Table 2 sizes are n * m * 4 bytes).
+A single query reads only the columns it queries (vertical partitioning, section 5.5):
+4 * N * k bytes, and writes 4 bytes per result identifier (or N / 8 bytes of bitmap).
+"""
+
+HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E, vendor figure
+FP32_VALU_TFLOPS = 157.3    # MI355X vector fp32, vendor figure
+CUS = 256
+CLOCK_GHZ = 2.4
+
+
+def column_bytes(n_rows: int, n_dims: int) -> int:
+    """Raw size of n_rows x n_dims float32 values."""
+    return 4 * n_rows * n_dims
+
+
+def query_bytes(n_rows: int, k: int, count: int, mode: str = "ids") -> int:
+    """Algorithmic bytes of one single-query scan: every queried column read once, the
+    result written once (ids: 4 B each; bitmap: one bit per row in 64-bit words), plus
+    the 8-byte count."""
+    out = {"ids": 4 * count, "bitmap": 8 * ((n_rows + 63) // 64), "count": 0}[mode]
+    return column_bytes(n_rows, k) + out + 8
