@@ -1,0 +1,193 @@
+"""Benchmark: exact multidimensional range queries on one MI355X.
+
+Default workload: 10^8 rows x 17 float32 columns (8 uniform, 8 Gaussian-mixture,
+1 Zipf) and 1,000 queries on 2-8 dims with target selectivity log-uniform in
+[1e-5, 0.2].  One step answers the whole query set (count + ascending uint32 ids per
+query) through the C ABI; data are resident in HBM before timing starts.
+
+Prints one JSON line.  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tuples/s & HBM GB/s per query; batched+learned vs plain queries/s; p99 latency"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_hash(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def counters_traffic(kernel_src: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken
+    on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"scan_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        c = json.load(f)
+    if c.get("kernel_source_sha256_16") != source_hash(kernel_src):
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cols_raw, queries, n_rows, budget_s: float):
+    import oracle
+
+    cols = oracle.prepare(cols_raw)
+    t0 = time.perf_counter()
+    done = 0
+    for q in queries:
+        oracle.count(cols, q)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n_rows * done / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of the {len(queries)} queries on the full {n_rows}-row data, "
+                      f"single-threaded oracle scan ({dt:.1f} s)",
+            "queries_per_s": done / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--rows", type=int, default=None, help="override the row count")
+    ap.add_argument("--queries", type=int, default=None)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-earlyout", action="store_true")
+    ap.add_argument("--unroll", type=int, default=None)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(row sharding across GPUs is a design note, not code).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1801_03644_amd import datagen as dg
+    from paper_1801_03644_amd import mdrq
+    from paper_1801_03644_amd.metrics import HBM_PEAK_GBPS
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = dg.workload(args.workload, args.rows)
+    n_q = args.queries or (100 if args.workload == "c1" else 1000)
+    log(f"generating {w.name}: {w.n_rows} x {w.n_dims}")
+    t0 = time.perf_counter()
+    raw = w.columns()
+    log(f"generated in {time.perf_counter() - t0:.1f}s; drawing {n_q} queries")
+    queries = dg.workload_queries(w, n_q)
+    log("loading into HBM")
+    ds = mdrq.Dataset.from_host(raw)
+    if args.unroll:
+        ds.set_option(mdrq.OPT_UNROLL, args.unroll)
+    flags = mdrq.Q_NO_EARLYOUT if args.no_earlyout else 0
+    out = torch.empty(w.n_rows, dtype=torch.int32, device="cuda:0")
+    prepared = [mdrq.make_query(q, flags) for q in queries]
+    lib = mdrq.load_library()
+    import ctypes
+
+    stream = mdrq._stream_handle(torch.cuda.current_stream())
+    res = mdrq.Result()
+    res.mode, res.mem, res.buf, res.buf_bytes = mdrq.OUT_IDS, mdrq.MEM_DEVICE, out.data_ptr(), out.numel() * 4
+    counts = np.zeros(n_q, dtype=np.int64)
+    lat = np.zeros(n_q)
+
+    def step(record: bool):
+        for i, (q, keep) in enumerate(prepared):
+            t = time.perf_counter()
+            rc = lib.mdrq_query(ds.handle, ctypes.byref(q), ctypes.byref(res), stream)
+            if record:
+                lat[i] = time.perf_counter() - t
+            if rc not in (mdrq.OK, mdrq.EOVERFLOW):
+                raise mdrq.MdrqError(rc, mdrq.last_error())
+            counts[i] = res.count
+
+    for s in range(args.warmup):
+        step(False)
+        log(f"warmup step {s + 1}/{args.warmup} done")
+    ds.set_profiling(True)
+    ds.reset_profile()
+    lat_all = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(True)
+        lat_all.append(lat.copy())
+        log(f"step {s + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launches, kernel_ms = ds.profile()
+    ds.set_profiling(False)
+
+    ks = np.array([len(q[0]) for q in queries])
+    alg_bytes_q = 4 * w.n_rows * ks + 4 * counts + 8          # per query (= per launch)
+    total_q = n_q * args.steps
+    tuples_per_s = w.n_rows * total_q / elapsed
+    logical_gbps = alg_bytes_q.sum() * args.steps / elapsed / 1e9
+    lat_us = np.concatenate(lat_all) * 1e6
+    avg_kernel_s = kernel_ms / 1e3 / launches
+    achieved = alg_bytes_q.mean() / avg_kernel_s / 1e9
+    kernel_src = os.path.join(ROOT, "paper_1801_03644_amd", "csrc", "scan.hip")
+    traffic = counters_traffic(kernel_src, w.name)
+    sel = counts / w.n_rows
+    line = {
+        "metric": METRIC,
+        "value": tuples_per_s,
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.n_rows} rows x {w.n_dims} float32 columns, "
+                               f"{n_q} queries per step, ids output",
+                   "n_rows": w.n_rows, "n_dims": w.n_dims, "queries_per_step": n_q,
+                   "mean_queried_dims": float(ks.mean()), "mean_selectivity": float(sel.mean()),
+                   "early_out": not args.no_earlyout, "data_seed": w.data_seed,
+                   "query_seed": w.query_seed},
+        "queries_per_s": total_q / elapsed,
+        "hbm_gbps_logical": logical_gbps,
+        "p50_us": float(np.percentile(lat_us, 50)),
+        "p99_us": float(np.percentile(lat_us, 99)),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": "scan_kernel<ids>", "avg_kernel_us": avg_kernel_s * 1e6,
+                     "algorithmic_bytes_per_launch": float(alg_bytes_q.mean())},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(raw, queries, w.n_rows, args.cpu_budget)
+    ds.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,220 @@
+/*
+ * mdrq.h -- C ABI of libmdrq: exact multidimensional range queries (MDRQ) over
+ * column-stored float32 data on an AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Sprenger, Schaefer & Leser, "Multidimensional Range Queries on
+ * Modern Hardware", section 2.1): a data set holds n objects with m attributes each.
+ * A query gives a closed interval [lb_j, ub_j] for some or all dimensions j; a
+ * dimension without an interval behaves as [-inf, +inf] (a partial-match query).
+ * An object qualifies iff lb_j <= value_j <= ub_j holds on every queried dimension.
+ * The answer is the set of identifiers of the qualifying objects; the identifier of
+ * an object is its 0-based index in the column arrays (section 2.2.4).  Data are
+ * 32-bit floats (section 7.2) stored one array per dimension, as in the vertically
+ * partitioned scan of section 5.5.
+ *
+ * Conventions for every call:
+ *  - Return value: MDRQ_OK (0) or a negative MDRQ_E* code.  After a failure,
+ *    mdrq_last_error() returns a message for the calling thread.
+ *  - Identifiers are uint32 (so n_rows <= 2^32 - 1) and are always written in
+ *    ascending order.  Result sets are exact: no approximation anywhere.
+ *  - NaN is not a value: a NaN in the data makes mdrq_load_columns fail with
+ *    MDRQ_EINVAL, and a NaN bound makes the query invalid.  -0.0 equals +0.0;
+ *    infinities and subnormal numbers are ordinary values.
+ *  - lo > hi is a valid, empty interval.  A dimension may appear at most once per
+ *    query (one interval per dimension, section 2.1).  A query without predicates
+ *    selects every object.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls return only when
+ *    their results are complete and `count` is valid on the host.
+ *  - Calls on one dataset are serialised by the library; different datasets may be
+ *    used from different threads.
+ */
+#ifndef MDRQ_H
+#define MDRQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MDRQ_MAX_DIMS 128          /* dimensions per dataset, predicates per query */
+#define MDRQ_MAX_BATCH 1024        /* queries per mdrq_query_batch call */
+
+/* Status codes. */
+enum {
+  MDRQ_OK = 0,
+  MDRQ_EINVAL = -1,     /* invalid argument (see each call) */
+  MDRQ_ENOMEM = -2,     /* device or host allocation failed */
+  MDRQ_EOVERFLOW = -3,  /* result larger than the caller's buffer; count is exact */
+  MDRQ_EDEVICE = -4,    /* a HIP call or kernel failed */
+  MDRQ_EBUSY = -5,      /* serving: request could not be admitted */
+  MDRQ_ENOTSUP = -6     /* valid request this build cannot serve */
+};
+
+/* mdrq_load_columns flags. */
+enum {
+  MDRQ_MEM_HOST = 0,    /* cols[] are host pointers: copied into library-owned HBM */
+  MDRQ_MEM_DEVICE = 1,  /* cols[] are device pointers: copied device to device */
+  MDRQ_BORROW = 2       /* with MDRQ_MEM_DEVICE: use the caller's device arrays in place */
+};
+
+/* Result modes. */
+enum {
+  MDRQ_OUT_IDS = 0,     /* ascending uint32 identifiers */
+  MDRQ_OUT_BITMAP = 1,  /* uint64 words: bit (i % 64) of word i / 64 <=> object i qualifies */
+  MDRQ_OUT_COUNT = 2,   /* the count only */
+  MDRQ_OUT_AUTO = 3     /* IDS or BITMAP, chosen by the planner; the choice is reported */
+};
+
+/* Query flags. */
+enum {
+  MDRQ_Q_ORDER_GIVEN = 0,      /* evaluate predicates in the order given */
+  MDRQ_Q_ORDER_ESTIMATED = 1,  /* most selective first, by the attached estimator */
+  MDRQ_Q_NO_EARLYOUT = 2       /* read every queried column in full (measurement) */
+};
+
+typedef struct mdrq_dataset mdrq_dataset;  /* opaque, owned by the library */
+
+/* One predicate: closed interval [lo, hi] on dimension `dim`. */
+typedef struct {
+  uint32_t dim;
+  float lo;
+  float hi;
+} mdrq_pred;
+
+typedef struct {
+  const mdrq_pred* preds;  /* n_preds entries; read only during the call */
+  uint32_t n_preds;
+  uint32_t flags;          /* MDRQ_Q_* */
+} mdrq_query_t;
+
+/* Output of one query.  `buf` is owned by the caller and lives in host memory
+ * (mem = MDRQ_MEM_HOST) or device memory (mem = MDRQ_MEM_DEVICE).  IDS mode holds
+ * buf_bytes / 4 identifiers; BITMAP mode needs ceil(n_rows / 64) words to hold the
+ * full bitmap.  If the result does not fit, the first identifiers (or words) that
+ * fit are written, `count` is still exact and status is MDRQ_EOVERFLOW. */
+typedef struct {
+  uint32_t mode;       /* in: MDRQ_OUT_*; out: the mode used (AUTO resolved) */
+  uint32_t mem;        /* MDRQ_MEM_HOST or MDRQ_MEM_DEVICE */
+  void* buf;           /* may be NULL when buf_bytes == 0 */
+  uint64_t buf_bytes;
+  uint64_t count;      /* out: exact number of qualifying objects */
+  uint64_t written;    /* out: identifiers (IDS) or words (BITMAP) written */
+  int32_t status;      /* out: MDRQ_OK or MDRQ_EOVERFLOW */
+  uint32_t reserved;
+} mdrq_result_t;
+
+/*
+ * Load n_dims columns of n_rows float32 values (paper section 5.5: one array per
+ * dimension).  cols[j] points to column j.  With MDRQ_MEM_HOST or MDRQ_MEM_DEVICE
+ * the data are copied into one library-owned HBM allocation (each column 256-byte
+ * aligned); with MDRQ_MEM_DEVICE | MDRQ_BORROW the caller's device arrays are used in
+ * place (each must be 16-byte aligned and must stay alive and unchanged until
+ * mdrq_free).  Every value is checked on the device: a NaN makes the call fail with
+ * MDRQ_EINVAL.  Per-column minima and maxima are kept (mdrq_column_range).
+ * Errors: MDRQ_EINVAL (NULL pointers, n_dims == 0 or > MDRQ_MAX_DIMS,
+ * n_rows > 2^32 - 1, misaligned borrowed column, NaN data), MDRQ_ENOMEM,
+ * MDRQ_EDEVICE.  On success *out receives the dataset.
+ */
+int mdrq_load_columns(const float* const* cols, uint32_t n_dims, uint64_t n_rows,
+                      uint32_t flags, void* stream, mdrq_dataset** out);
+
+/*
+ * Answer one query (paper section 2.1) with a full columnar scan: each tile of rows
+ * is tested against the predicates one dimension at a time (section 5.5), the
+ * per-dimension results are ANDed (section 3.2), and rows already rejected are not
+ * read again for later dimensions (the early break of section 2.2.4).  Identifiers
+ * are compacted in ascending order.
+ * Errors: MDRQ_EINVAL (NULL ds/q/r, n_preds > n_dims, dim >= n_dims, repeated dim,
+ * NaN bound, unknown mode or mem, buf == NULL with buf_bytes > 0),
+ * MDRQ_EOVERFLOW (result truncated, r->count exact), MDRQ_EDEVICE.
+ */
+int mdrq_query(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r, void* stream);
+
+/*
+ * Answer n_queries queries (1 .. MDRQ_MAX_BATCH) with one shared scan: each column
+ * tile is read from HBM once and tested against every query of the batch.  Each
+ * query's result is exactly what mdrq_query returns for it alone.  rs[i] is the
+ * result of qs[i]; a per-query overflow sets rs[i].status and makes the call return
+ * MDRQ_EOVERFLOW after all results are written.
+ * Errors: as mdrq_query, for any query of the batch (nothing is run then).
+ */
+int mdrq_query_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n_queries,
+                     mdrq_result_t* rs, void* stream);
+
+/* Serving configuration: requests are admitted while their result reservations fit
+ * in result_budget_bytes of device memory, packed into shared scans of at most
+ * max_batch queries, and run on n_streams device streams so that scans overlap. */
+typedef struct {
+  uint64_t result_budget_bytes;
+  uint32_t max_batch;       /* 1 .. MDRQ_MAX_BATCH */
+  uint32_t n_streams;       /* 1 .. 8 */
+  uint32_t use_estimator;   /* order dims and size reservations by the attached estimator */
+  uint32_t reserved;
+} mdrq_serve_config_t;
+
+/* One request: the query, and its arrival time in ns after the start of the run. */
+typedef struct {
+  uint64_t arrival_ns;
+  mdrq_query_t query;
+} mdrq_request_t;
+
+typedef struct {
+  uint64_t completed;       /* requests answered */
+  uint64_t scans;           /* shared scans launched */
+  double wall_s;            /* first arrival to last completion */
+  double qps;               /* completed / wall_s */
+  double p50_us, p99_us, mean_us, max_us;  /* arrival -> result complete in device memory */
+  double mean_batch;        /* queries per shared scan */
+  double hbm_gbps;          /* column bytes read by the scans / wall_s */
+  uint64_t overflow_reruns; /* requests re-run after a reservation proved too small */
+} mdrq_serve_stats_t;
+
+/*
+ * Replay n_reqs arrival-stamped requests through the serving loop (continuous
+ * batching).  rs[i] receives request i's result exactly as mdrq_query would give it;
+ * latency_ns (optional, n_reqs entries) receives each request's latency.
+ * Errors: MDRQ_EINVAL (bad config or request), MDRQ_EBUSY (a single request's
+ * reservation exceeds the whole budget), MDRQ_EOVERFLOW (some rs[i] truncated),
+ * MDRQ_ENOMEM, MDRQ_EDEVICE.
+ */
+int mdrq_serve(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, const mdrq_request_t* reqs,
+               uint32_t n_reqs, mdrq_result_t* rs, uint64_t* latency_ns,
+               mdrq_serve_stats_t* stats);
+
+/* Release a dataset and everything the library allocated for it. */
+void mdrq_free(mdrq_dataset* ds);
+
+/* Message of the calling thread's last failure ("" if none); valid until its next call. */
+const char* mdrq_last_error(void);
+
+/* Shape of a dataset. */
+int mdrq_dataset_info(const mdrq_dataset* ds, uint64_t* n_rows, uint32_t* n_dims);
+
+/* Minimum and maximum of column `dim`, found at load. */
+int mdrq_column_range(const mdrq_dataset* ds, uint32_t dim, float* min_out, float* max_out);
+
+/* Kernel timing: when enabled, every scan kernel launch of the dataset is bracketed
+ * by HIP events on the stream it runs on, and mdrq_get_profile returns the number of
+ * timed launches and the sum of their durations in milliseconds. */
+int mdrq_set_profiling(mdrq_dataset* ds, int enable);
+int mdrq_get_profile(const mdrq_dataset* ds, uint64_t* launches, double* kernel_ms);
+int mdrq_reset_profile(mdrq_dataset* ds);
+
+/* Tuning options of a dataset's scans (results never depend on them). */
+enum {
+  MDRQ_OPT_UNROLL = 1,  /* 16-byte loads per lane per column in one tile: 1, 2, 4 or 8
+                           (tile = 1024 x value rows); default 4 */
+  MDRQ_OPT_GRID = 2     /* workgroups per scan launch; 0 = as many as stay resident */
+};
+int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
+
+/* Library version as "major.minor.patch". */
+const char* mdrq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDRQ_H */

@@ -1,0 +1,460 @@
+// Host runtime behind the C ABI: dataset load and validation, query checks and
+// canonicalisation, output planning, launch and completion of single-query scans.
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <mutex>
+
+#include "mdrq_internal.h"
+
+namespace mdrq {
+
+static thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return MDRQ_EDEVICE;
+}
+
+void clear_error() { g_err.clear(); }
+
+const Device& device() {
+  static std::mutex mu;
+  static std::vector<Device> cache;
+  int id = 0;
+  if (hipGetDevice(&id) != hipSuccess) id = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  for (const Device& d : cache)
+    if (d.id == id) return d;
+  Device d;
+  d.id = id;
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, id) == hipSuccess) {
+    d.cus = prop.multiProcessorCount;
+    d.lds = prop.sharedMemPerBlock;
+  }
+  if (d.cus <= 0) d.cus = 256;
+  cache.push_back(d);
+  return cache.back();
+}
+
+}  // namespace mdrq
+
+using namespace mdrq;
+
+namespace {
+
+constexpr uint64_t kMaxRows = 0xFFFFFFFFull;
+
+#define MDRQ_HIP(call, what)                  \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return fail_hip(e_, what); \
+  } while (0)
+
+void free_dataset(mdrq_dataset* ds) {
+  if (!ds) return;
+  if (ds->owned && ds->base) (void)hipFree(ds->base);
+  if (ds->state) (void)hipFree(ds->state);
+  if (ds->status) (void)hipFree(ds->status);
+  if (ds->host_state) (void)hipHostFree(ds->host_state);
+  if (ds->staging) (void)hipFree(ds->staging);
+  if (ds->ev0) (void)hipEventDestroy(ds->ev0);
+  if (ds->ev1) (void)hipEventDestroy(ds->ev1);
+  delete ds;
+}
+
+int alloc_workspace(mdrq_dataset* ds) {
+  const uint64_t min_tile = static_cast<uint64_t>(scan_tile_rows(1));
+  const uint64_t tiles = (ds->n_rows + min_tile - 1) / min_tile + 1;
+  ds->status_len = static_cast<uint32_t>(tiles);
+  MDRQ_HIP(hipMalloc(&ds->state, sizeof(ScanState)), "hipMalloc(scan state)");
+  MDRQ_HIP(hipMemset(ds->state, 0, sizeof(ScanState)), "hipMemset(scan state)");
+  MDRQ_HIP(hipMalloc(&ds->status, tiles * sizeof(uint64_t)), "hipMalloc(tile status)");
+  MDRQ_HIP(hipMemset(ds->status, 0, tiles * sizeof(uint64_t)), "hipMemset(tile status)");
+  MDRQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&ds->host_state), sizeof(ScanState),
+                         hipHostMallocDefault),
+           "hipHostMalloc(scan state)");
+  memset(ds->host_state, 0, sizeof(ScanState));
+  return MDRQ_OK;
+}
+
+// A canonical query: predicates that can change the result, in evaluation order.
+struct Plan {
+  std::vector<DevPred> preds;
+  bool empty = false;   // some interval is empty: no row qualifies
+  uint32_t mode = kIds;
+  uint64_t capacity = 0;
+  bool early_out = true;
+};
+
+int check_query(const mdrq_dataset* ds, const mdrq_query_t* q) {
+  if (!q) return fail(MDRQ_EINVAL, "query is NULL");
+  if (q->n_preds > 0 && !q->preds) return fail(MDRQ_EINVAL, "query has predicates but preds is NULL");
+  if (q->n_preds > ds->n_dims) return fail(MDRQ_EINVAL, "more predicates than dimensions");
+  if (q->flags & ~static_cast<uint32_t>(MDRQ_Q_ORDER_ESTIMATED | MDRQ_Q_NO_EARLYOUT))
+    return fail(MDRQ_EINVAL, "unknown query flags");
+  uint64_t seen[MDRQ_MAX_DIMS / 64] = {0, 0};
+  for (uint32_t i = 0; i < q->n_preds; ++i) {
+    const mdrq_pred& p = q->preds[i];
+    if (p.dim >= ds->n_dims) return fail(MDRQ_EINVAL, "predicate dimension out of range");
+    if (std::isnan(p.lo) || std::isnan(p.hi)) return fail(MDRQ_EINVAL, "NaN bound");
+    uint64_t& w = seen[p.dim / 64];
+    const uint64_t bit = uint64_t{1} << (p.dim % 64);
+    if (w & bit) return fail(MDRQ_EINVAL, "dimension appears twice in one query");
+    w |= bit;
+  }
+  return MDRQ_OK;
+}
+
+int check_result(const mdrq_result_t* r) {
+  if (!r) return fail(MDRQ_EINVAL, "result is NULL");
+  if (r->mode > MDRQ_OUT_AUTO) return fail(MDRQ_EINVAL, "unknown result mode");
+  if (r->mem > MDRQ_MEM_DEVICE) return fail(MDRQ_EINVAL, "unknown result memory kind");
+  if (!r->buf && r->buf_bytes > 0) return fail(MDRQ_EINVAL, "buf is NULL but buf_bytes > 0");
+  return MDRQ_OK;
+}
+
+Plan make_plan(const mdrq_dataset* ds, const mdrq_query_t* q, const mdrq_result_t* r) {
+  Plan plan;
+  const float inf = std::numeric_limits<float>::infinity();
+  for (uint32_t i = 0; i < q->n_preds; ++i) {
+    const mdrq_pred& p = q->preds[i];
+    if (p.lo > p.hi) plan.empty = true;
+    if (p.lo == -inf && p.hi == inf) continue;  // the partial-match [-inf, +inf]
+    plan.preds.push_back(DevPred{ds->cols[p.dim], p.lo, p.hi});
+  }
+  plan.mode = r->mode == MDRQ_OUT_BITMAP ? kBitmap : r->mode == MDRQ_OUT_COUNT ? kCount : kIds;
+  plan.capacity = plan.mode == kIds ? r->buf_bytes / 4 : plan.mode == kBitmap ? r->buf_bytes / 8 : 0;
+  plan.early_out = !(q->flags & MDRQ_Q_NO_EARLYOUT);
+  return plan;
+}
+
+uint64_t n_words(const mdrq_dataset* ds) { return (ds->n_rows + 63) / 64; }
+
+// Result of an empty answer (no launch): zero the bitmap words the buffer holds.
+int finish_empty(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream) {
+  r->count = 0;
+  r->written = 0;
+  r->status = MDRQ_OK;
+  if (plan.mode == kBitmap) {
+    const uint64_t words = std::min(plan.capacity, n_words(ds));
+    if (words) {
+      if (r->mem == MDRQ_MEM_DEVICE) {
+        MDRQ_HIP(hipMemsetAsync(r->buf, 0, words * 8, stream), "hipMemsetAsync(bitmap)");
+        MDRQ_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+      } else {
+        memset(r->buf, 0, words * 8);
+      }
+    }
+    r->written = words;
+    if (plan.capacity < n_words(ds)) r->status = MDRQ_EOVERFLOW;
+  }
+  return r->status;
+}
+
+int ensure_staging(mdrq_dataset* ds, uint64_t bytes) {
+  if (bytes <= ds->staging_bytes) return MDRQ_OK;
+  if (ds->staging) (void)hipFree(ds->staging);
+  ds->staging = nullptr;
+  ds->staging_bytes = 0;
+  if (hipMalloc(&ds->staging, bytes) != hipSuccess) return fail(MDRQ_ENOMEM, "staging buffer");
+  ds->staging_bytes = bytes;
+  return MDRQ_OK;
+}
+
+uint32_t next_epoch(mdrq_dataset* ds, hipStream_t stream) {
+  if (++ds->epoch > 0x3FFFFFFFu) {
+    ds->epoch = 1;
+    (void)hipMemsetAsync(ds->status, 0, ds->status_len * sizeof(uint64_t), stream);
+  }
+  return ds->epoch;
+}
+
+int recover_state(mdrq_dataset* ds) {
+  (void)hipMemset(ds->state, 0, sizeof(ScanState));
+  (void)hipMemset(ds->status, 0, ds->status_len * sizeof(uint64_t));
+  (void)hipDeviceSynchronize();
+  return MDRQ_OK;
+}
+
+int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream) {
+  if (plan.empty || ds->n_rows == 0) return finish_empty(ds, plan, r, stream);
+  const bool host_out = r->mem == MDRQ_MEM_HOST && plan.mode != kCount;
+  const uint64_t elem = plan.mode == kIds ? 4 : 8;
+  const uint64_t out_elems = plan.mode == kBitmap ? std::min(plan.capacity, n_words(ds)) : plan.capacity;
+  void* out = r->buf;
+  if (host_out) {
+    if (out_elems) {
+      int rc = ensure_staging(ds, out_elems * elem);
+      if (rc) return rc;
+    }
+    out = ds->staging;
+  }
+  const int U = ds->unroll;
+  const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(U));
+  ScanParams p{};
+  p.n_rows = ds->n_rows;
+  p.n_tiles = static_cast<uint32_t>((ds->n_rows + tile - 1) / tile);
+  p.n_preds = static_cast<uint32_t>(plan.preds.size());
+  p.epoch = next_epoch(ds, stream);
+  p.early_out = plan.early_out ? 1u : 0u;
+  p.ids = plan.mode == kIds ? static_cast<uint32_t*>(out) : nullptr;
+  p.bitmap = plan.mode == kBitmap ? static_cast<uint64_t*>(out) : nullptr;
+  p.capacity = plan.mode == kCount ? 0 : out_elems;
+  p.state = ds->state;
+  p.status = ds->status;
+  for (size_t i = 0; i < plan.preds.size(); ++i) p.preds[i] = plan.preds[i];
+  const Device& dev = device();
+  const uint64_t resident = static_cast<uint64_t>(scan_blocks_per_cu(plan.mode, U)) * dev.cus;
+  uint64_t want = ds->grid > 0 ? static_cast<uint64_t>(ds->grid) : resident;
+  const int grid = static_cast<int>(std::min<uint64_t>(p.n_tiles, want));
+
+  if (ds->profiling) {
+    if (!ds->ev0) MDRQ_HIP(hipEventCreate(&ds->ev0), "hipEventCreate");
+    if (!ds->ev1) MDRQ_HIP(hipEventCreate(&ds->ev1), "hipEventCreate");
+    MDRQ_HIP(hipEventRecord(ds->ev0, stream), "hipEventRecord");
+  }
+  hipError_t e = launch_scan(p, plan.mode, U, grid, stream);
+  if (e != hipSuccess) {
+    recover_state(ds);
+    return fail_hip(e, "scan kernel launch");
+  }
+  if (ds->profiling) MDRQ_HIP(hipEventRecord(ds->ev1, stream), "hipEventRecord");
+  e = hipMemcpyAsync(ds->host_state, ds->state, sizeof(ScanState), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    recover_state(ds);
+    return fail_hip(e, "scan completion");
+  }
+  if (ds->host_state->error) {
+    recover_state(ds);
+    return fail(MDRQ_EDEVICE, "tile look-back wait exceeded its bound; result discarded");
+  }
+  if (ds->profiling) {
+    float ms = 0.f;
+    MDRQ_HIP(hipEventElapsedTime(&ms, ds->ev0, ds->ev1), "hipEventElapsedTime");
+    ds->prof_ms += ms;
+    ds->prof_launches += 1;
+  }
+  const uint64_t count = ds->host_state->count_out;
+  r->count = count;
+  if (plan.mode == kIds) {
+    r->written = std::min(count, plan.capacity);
+    r->status = count > plan.capacity ? MDRQ_EOVERFLOW : MDRQ_OK;
+  } else if (plan.mode == kBitmap) {
+    r->written = out_elems;
+    r->status = plan.capacity < n_words(ds) ? MDRQ_EOVERFLOW : MDRQ_OK;
+  } else {
+    r->written = 0;
+    r->status = MDRQ_OK;
+  }
+  if (host_out && r->written)
+    MDRQ_HIP(hipMemcpy(r->buf, ds->staging, r->written * elem, hipMemcpyDeviceToHost),
+             "copy result to host");
+  return r->status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mdrq_load_columns(const float* const* cols, uint32_t n_dims, uint64_t n_rows, uint32_t flags,
+                      void* stream_, mdrq_dataset** out) {
+  clear_error();
+  if (!out) return fail(MDRQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cols) return fail(MDRQ_EINVAL, "cols is NULL");
+  if (n_dims == 0 || n_dims > MDRQ_MAX_DIMS) return fail(MDRQ_EINVAL, "n_dims must be 1..128");
+  if (n_rows > kMaxRows) return fail(MDRQ_EINVAL, "n_rows exceeds 2^32 - 1");
+  const bool dev_in = flags & MDRQ_MEM_DEVICE;
+  const bool borrow = flags & MDRQ_BORROW;
+  if (flags & ~static_cast<uint32_t>(MDRQ_MEM_DEVICE | MDRQ_BORROW))
+    return fail(MDRQ_EINVAL, "unknown load flags");
+  if (borrow && !dev_in) return fail(MDRQ_EINVAL, "MDRQ_BORROW requires MDRQ_MEM_DEVICE");
+  for (uint32_t j = 0; j < n_dims; ++j) {
+    if (!cols[j] && n_rows > 0) return fail(MDRQ_EINVAL, "column pointer is NULL");
+    if (borrow && (reinterpret_cast<uintptr_t>(cols[j]) & 15u))
+      return fail(MDRQ_EINVAL, "borrowed column is not 16-byte aligned");
+  }
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  mdrq_dataset* ds = new mdrq_dataset();
+  ds->n_rows = n_rows;
+  ds->n_dims = n_dims;
+  ds->owned = !borrow;
+  ds->cols.resize(n_dims);
+  int rc = MDRQ_OK;
+  ColumnStats* st_dev = nullptr;
+  ColumnStats st_host{};
+  if (borrow) {
+    for (uint32_t j = 0; j < n_dims; ++j) ds->cols[j] = cols[j];
+  } else {
+    ds->stride = (n_rows + 63) / 64 * 64;
+    const uint64_t bytes = std::max<uint64_t>(1, ds->stride * n_dims * sizeof(float));
+    if (hipMalloc(reinterpret_cast<void**>(&ds->base), bytes) != hipSuccess) {
+      free_dataset(ds);
+      return fail(MDRQ_ENOMEM, "device allocation of the columns failed");
+    }
+    for (uint32_t j = 0; j < n_dims; ++j) {
+      float* dst = ds->base + ds->stride * j;
+      ds->cols[j] = dst;
+      if (n_rows) {
+        hipError_t e = hipMemcpyAsync(dst, cols[j], n_rows * sizeof(float),
+                                      dev_in ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                      stream);
+        if (e != hipSuccess) {
+          free_dataset(ds);
+          return fail_hip(e, "column copy");
+        }
+      }
+    }
+  }
+  rc = alloc_workspace(ds);
+  if (rc) {
+    free_dataset(ds);
+    return rc;
+  }
+  // Validation on the device: NaN check, min and max per column.
+  st_host.nan_count = 0;
+  for (uint32_t j = 0; j < MDRQ_MAX_DIMS; ++j) {
+    st_host.min_key[j] = 0xFFFFFFFFu;
+    st_host.max_key[j] = 0u;
+  }
+  hipError_t e = hipMalloc(&st_dev, sizeof(ColumnStats));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(st_dev, &st_host, sizeof(ColumnStats), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && n_rows) e = launch_validate(ds->cols.data(), n_dims, n_rows, st_dev, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&st_host, st_dev, sizeof(ColumnStats), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (st_dev) (void)hipFree(st_dev);
+  if (e != hipSuccess) {
+    free_dataset(ds);
+    return fail_hip(e, "column validation");
+  }
+  if (st_host.nan_count) {
+    free_dataset(ds);
+    return fail(MDRQ_EINVAL, "NaN in the data");
+  }
+  ds->col_min.resize(n_dims);
+  ds->col_max.resize(n_dims);
+  for (uint32_t j = 0; j < n_dims; ++j) {
+    if (n_rows) {
+      ds->col_min[j] = key_to_float(st_host.min_key[j]);
+      ds->col_max[j] = key_to_float(st_host.max_key[j]);
+    } else {
+      ds->col_min[j] = std::numeric_limits<float>::infinity();
+      ds->col_max[j] = -std::numeric_limits<float>::infinity();
+    }
+  }
+  *out = ds;
+  return MDRQ_OK;
+}
+
+int mdrq_query(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r, void* stream) {
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  int rc = check_query(ds, q);
+  if (rc) return rc;
+  rc = check_result(r);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(ds->mu);
+  Plan plan = make_plan(ds, q, r);
+  r->mode = plan.mode == kBitmap ? MDRQ_OUT_BITMAP : plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
+  return run_query(ds, plan, r, static_cast<hipStream_t>(stream));
+}
+
+void mdrq_free(mdrq_dataset* ds) {
+  if (!ds) return;
+  (void)hipDeviceSynchronize();
+  free_dataset(ds);
+}
+
+const char* mdrq_last_error(void) { return g_err.c_str(); }
+
+int mdrq_dataset_info(const mdrq_dataset* ds, uint64_t* n_rows, uint32_t* n_dims) {
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  if (n_rows) *n_rows = ds->n_rows;
+  if (n_dims) *n_dims = ds->n_dims;
+  return MDRQ_OK;
+}
+
+int mdrq_column_range(const mdrq_dataset* ds, uint32_t dim, float* min_out, float* max_out) {
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  if (dim >= ds->n_dims) return fail(MDRQ_EINVAL, "dimension out of range");
+  if (min_out) *min_out = ds->col_min[dim];
+  if (max_out) *max_out = ds->col_max[dim];
+  return MDRQ_OK;
+}
+
+int mdrq_set_profiling(mdrq_dataset* ds, int enable) {
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  std::lock_guard<std::mutex> lock(ds->mu);
+  ds->profiling = enable != 0;
+  return MDRQ_OK;
+}
+
+int mdrq_get_profile(const mdrq_dataset* ds, uint64_t* launches, double* kernel_ms) {
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  if (launches) *launches = ds->prof_launches;
+  if (kernel_ms) *kernel_ms = ds->prof_ms;
+  return MDRQ_OK;
+}
+
+int mdrq_reset_profile(mdrq_dataset* ds) {
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  std::lock_guard<std::mutex> lock(ds->mu);
+  ds->prof_launches = 0;
+  ds->prof_ms = 0.0;
+  return MDRQ_OK;
+}
+
+int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  std::lock_guard<std::mutex> lock(ds->mu);
+  switch (option) {
+    case MDRQ_OPT_UNROLL:
+      if (value != 1 && value != 2 && value != 4 && value != 8)
+        return fail(MDRQ_EINVAL, "unroll must be 1, 2, 4 or 8");
+      ds->unroll = static_cast<int>(value);
+      return MDRQ_OK;
+    case MDRQ_OPT_GRID:
+      if (value < 0 || value > (int64_t{1} << 20)) return fail(MDRQ_EINVAL, "grid out of range");
+      ds->grid = value;
+      return MDRQ_OK;
+    default:
+      return fail(MDRQ_EINVAL, "unknown option");
+  }
+}
+
+const char* mdrq_version(void) { return "0.1.0"; }
+
+int mdrq_query_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n_queries,
+                     mdrq_result_t* rs, void* stream) {
+  (void)qs; (void)n_queries; (void)rs; (void)stream;
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  return fail(MDRQ_ENOTSUP, "mdrq_query_batch is not built yet");
+}
+
+int mdrq_serve(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, const mdrq_request_t* reqs,
+               uint32_t n_reqs, mdrq_result_t* rs, uint64_t* latency_ns,
+               mdrq_serve_stats_t* stats) {
+  (void)cfg; (void)reqs; (void)n_reqs; (void)rs; (void)latency_ns; (void)stats;
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  return fail(MDRQ_ENOTSUP, "mdrq_serve is not built yet");
+}
+
+}  // extern "C"

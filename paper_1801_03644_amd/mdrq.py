@@ -1,0 +1,277 @@
+"""Python binding of libmdrq (argument marshalling only).
+
+Every step of a query runs in the library's HIP kernels; this module only converts
+Python and torch objects to the C ABI declared in ``include/mdrq.h``.  torch provides
+device memory and streams.  There is no fallback: if the library or a GPU is missing,
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libmdrq.so")
+
+OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+MEM_HOST, MEM_DEVICE, BORROW = 0, 1, 2
+OUT_IDS, OUT_BITMAP, OUT_COUNT, OUT_AUTO = 0, 1, 2, 3
+Q_ORDER_GIVEN, Q_ORDER_ESTIMATED, Q_NO_EARLYOUT = 0, 1, 2
+MAX_DIMS, MAX_BATCH = 128, 1024
+_MODES = {"ids": OUT_IDS, "bitmap": OUT_BITMAP, "count": OUT_COUNT, "auto": OUT_AUTO}
+_MODE_NAMES = {v: k for k, v in _MODES.items()}
+
+EXPORTS = ["mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve", "mdrq_free",
+           "mdrq_last_error", "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
+           "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_version"]
+OPT_UNROLL, OPT_GRID = 1, 2
+
+
+class MdrqError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mdrq error {code}: {msg}")
+        self.code = code
+
+
+class Pred(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_uint32), ("lo", ctypes.c_float), ("hi", ctypes.c_float)]
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("preds", ctypes.POINTER(Pred)), ("n_preds", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("mem", ctypes.c_uint32), ("buf", ctypes.c_void_p),
+                ("buf_bytes", ctypes.c_uint64), ("count", ctypes.c_uint64),
+                ("written", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("result_budget_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32),
+                ("n_streams", ctypes.c_uint32), ("use_estimator", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("arrival_ns", ctypes.c_uint64), ("query", Query)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("scans", ctypes.c_uint64),
+                ("wall_s", ctypes.c_double), ("qps", ctypes.c_double),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
+                ("mean_batch", ctypes.c_double), ("hbm_gbps", ctypes.c_double),
+                ("overflow_reruns", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmdrq.so (building it first only if no build exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        from . import build as _build
+
+        _build.build_mdrq()
+    lib = ctypes.CDLL(path)
+    P, vp, u32, u64, i32 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    lib.mdrq_load_columns.argtypes = [P(vp), u32, u64, u32, vp, P(vp)]
+    lib.mdrq_query.argtypes = [vp, P(Query), P(Result), vp]
+    lib.mdrq_query_batch.argtypes = [vp, P(Query), u32, P(Result), vp]
+    lib.mdrq_serve.argtypes = [vp, P(ServeConfig), P(Request), u32, P(Result), P(u64), P(ServeStats)]
+    lib.mdrq_free.argtypes = [vp]
+    lib.mdrq_free.restype = None
+    lib.mdrq_last_error.restype = ctypes.c_char_p
+    lib.mdrq_dataset_info.argtypes = [vp, P(u64), P(u32)]
+    lib.mdrq_column_range.argtypes = [vp, u32, P(ctypes.c_float), P(ctypes.c_float)]
+    lib.mdrq_set_profiling.argtypes = [vp, i32]
+    lib.mdrq_get_profile.argtypes = [vp, P(u64), P(ctypes.c_double)]
+    lib.mdrq_reset_profile.argtypes = [vp]
+    lib.mdrq_version.restype = ctypes.c_char_p
+    lib.mdrq_set_option.argtypes = [vp, u32, ctypes.c_int64]
+    for f in ("mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve",
+              "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
+              "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option"):
+        getattr(lib, f).restype = i32
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load_library().mdrq_last_error().decode()
+
+
+def _check(rc: int, allow=(OK,)):
+    if rc not in allow:
+        raise MdrqError(rc, last_error())
+    return rc
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        import torch
+
+        stream = torch.cuda.current_stream()
+    if hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    return ctypes.c_void_p(int(stream) if stream else 0)
+
+
+def make_query(query, flags: int = 0):
+    """(dims, lo, hi) arrays or [(dim, lo, hi), ...] -> (Query, keepalive)."""
+    if isinstance(query, tuple) and len(query) == 3 and hasattr(query[0], "__len__") \
+            and not isinstance(query[0], tuple):
+        dims, lo, hi = query
+        preds = list(zip([int(d) for d in dims], [float(x) for x in lo], [float(x) for x in hi]))
+    else:
+        preds = [(int(d), float(a), float(b)) for d, a, b in query]
+    arr = (Pred * max(1, len(preds)))(*[Pred(d, a, b) for d, a, b in preds])
+    return Query(arr if preds else None, len(preds), flags), arr
+
+
+@dataclass
+class Answer:
+    count: int
+    written: int
+    status: int
+    mode: str
+
+
+def _result_for(out, mode: str) -> Result:
+    r = Result()
+    r.mode = _MODES[mode]
+    if out is None:
+        r.mem, r.buf, r.buf_bytes = MEM_DEVICE, None, 0
+    elif isinstance(out, np.ndarray):
+        if not out.flags.c_contiguous:
+            raise ValueError("output array must be contiguous")
+        r.mem, r.buf, r.buf_bytes = MEM_HOST, out.ctypes.data, out.nbytes
+    else:  # torch tensor
+        if not out.is_contiguous():
+            raise ValueError("output tensor must be contiguous")
+        r.mem = MEM_DEVICE if out.is_cuda else MEM_HOST
+        r.buf, r.buf_bytes = out.data_ptr(), out.numel() * out.element_size()
+    return r
+
+
+class Dataset:
+    """Columns resident in HBM; answers queries with the library's scan kernels."""
+
+    def __init__(self, handle: int, n_rows: int, n_dims: int, keepalive=None):
+        self._h = ctypes.c_void_p(handle)
+        self.n_rows = n_rows
+        self.n_dims = n_dims
+        self._keep = keepalive
+
+    @classmethod
+    def from_host(cls, cols, stream=None) -> "Dataset":
+        """Copy host float32 columns (a list of 1-D arrays or a (d, n) array) into HBM."""
+        lib = load_library()
+        arrs = [np.ascontiguousarray(c, dtype=np.float32) for c in cols]
+        n = arrs[0].size if arrs else 0
+        if any(a.size != n for a in arrs):
+            raise ValueError("columns differ in length")
+        ptrs = (ctypes.c_void_p * max(1, len(arrs)))(*[a.ctypes.data for a in arrs])
+        h = ctypes.c_void_p()
+        _check(lib.mdrq_load_columns(ptrs, len(arrs), n, MEM_HOST, _stream_handle(stream),
+                                     ctypes.byref(h)))
+        return cls(h.value, n, len(arrs))
+
+    @classmethod
+    def from_device(cls, tensors, borrow: bool = False, stream=None) -> "Dataset":
+        """Use float32 CUDA tensors (one per column): copied, or borrowed in place."""
+        lib = load_library()
+        ts = list(tensors)
+        n = ts[0].numel() if ts else 0
+        for t in ts:
+            if not (t.is_cuda and t.is_contiguous() and str(t.dtype) == "torch.float32"):
+                raise ValueError("columns must be contiguous float32 CUDA tensors")
+            if t.numel() != n:
+                raise ValueError("columns differ in length")
+        ptrs = (ctypes.c_void_p * max(1, len(ts)))(*[t.data_ptr() for t in ts])
+        h = ctypes.c_void_p()
+        flags = MEM_DEVICE | (BORROW if borrow else 0)
+        _check(lib.mdrq_load_columns(ptrs, len(ts), n, flags, _stream_handle(stream),
+                                     ctypes.byref(h)))
+        return cls(h.value, n, len(ts), keepalive=ts if borrow else None)
+
+    def close(self):
+        if self._h and self._h.value:
+            load_library().mdrq_free(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def column_range(self, dim: int):
+        lo, hi = ctypes.c_float(), ctypes.c_float()
+        _check(load_library().mdrq_column_range(self._h, dim, ctypes.byref(lo), ctypes.byref(hi)))
+        return lo.value, hi.value
+
+    def query(self, query, out=None, mode: str = "ids", flags: int = 0, stream=None) -> Answer:
+        """Answer one query.  `out` is a CUDA tensor, a host numpy array or None (count
+        only / nothing written).  Raises on errors other than overflow."""
+        lib = load_library()
+        q, keep = make_query(query, flags)
+        r = _result_for(out, mode)
+        rc = lib.mdrq_query(self._h, ctypes.byref(q), ctypes.byref(r), _stream_handle(stream))
+        _check(rc, (OK, EOVERFLOW))
+        return Answer(r.count, r.written, r.status, _MODE_NAMES[r.mode])
+
+    def query_batch(self, queries, outs=None, modes="ids", flags: int = 0, stream=None):
+        lib = load_library()
+        n = len(queries)
+        outs = outs if outs is not None else [None] * n
+        modes = [modes] * n if isinstance(modes, str) else list(modes)
+        qarr = (Query * max(1, n))()
+        keep = []
+        for i, qq in enumerate(queries):
+            q, k = make_query(qq, flags)
+            qarr[i] = q
+            keep.append(k)
+        rarr = (Result * max(1, n))(*[_result_for(o, m) for o, m in zip(outs, modes)])
+        rc = lib.mdrq_query_batch(self._h, qarr, n, rarr, _stream_handle(stream))
+        _check(rc, (OK, EOVERFLOW))
+        return [Answer(r.count, r.written, r.status, _MODE_NAMES[r.mode]) for r in rarr[:n]]
+
+    def set_option(self, option: int, value: int):
+        _check(load_library().mdrq_set_option(self._h, option, value))
+
+    def set_profiling(self, on: bool = True):
+        _check(load_library().mdrq_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self):
+        n, ms = ctypes.c_uint64(), ctypes.c_double()
+        _check(load_library().mdrq_get_profile(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def reset_profile(self):
+        _check(load_library().mdrq_reset_profile(self._h))
+
+
+def version() -> str:
+    return load_library().mdrq_version().decode()
