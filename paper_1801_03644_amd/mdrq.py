@@ -74,16 +74,33 @@ class ServeStats(ctypes.Structure):
 _lib = None
 
 
+def _hip_runtimes() -> set:
+    try:
+        with open("/proc/self/maps") as f:
+            return {ln.split()[-1] for ln in f if "libamdhip64" in ln}
+    except OSError:
+        return set()
+
+
 def load_library(path: str = LIB_PATH):
-    """Load libmdrq.so (building it first only if no build exists)."""
+    """Load libmdrq.so (building it first only if no build exists).
+
+    torch is imported first so that the library binds to the HIP runtime torch
+    already loaded (same soname): one runtime per process, shared device memory and
+    streams.  A second HIP runtime in the process is an error."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (loads the process's HIP runtime)
+
     if not os.path.exists(path):
         from . import build as _build
 
         _build.build_mdrq()
     lib = ctypes.CDLL(path)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise RuntimeError(f"two HIP runtimes loaded in one process: {sorted(runtimes)}")
     P, vp, u32, u64, i32 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
     lib.mdrq_load_columns.argtypes = [P(vp), u32, u64, u32, vp, P(vp)]
     lib.mdrq_query.argtypes = [vp, P(Query), P(Result), vp]
