@@ -205,10 +205,20 @@ int mdrq_reset_profile(mdrq_dataset* ds);
 /* Tuning options of a dataset's scans (results never depend on them). */
 enum {
   MDRQ_OPT_UNROLL = 1,  /* 16-byte loads per lane per column in one tile: 1, 2, 4 or 8
-                           (tile = 1024 x value rows); default 4 */
-  MDRQ_OPT_GRID = 2     /* workgroups per scan launch; 0 = as many as stay resident */
+                           (one wave scans 256 x value rows per tile); default 8 */
+  MDRQ_OPT_GRID = 2,    /* workgroups per scan launch; 0 = MDRQ_OPT_BLOCKS_PER_CU per CU */
+  MDRQ_OPT_BLOCKS_PER_CU = 3  /* default launch width: workgroups per CU, 1..8
+                                 (capped by occupancy); default 3 */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
+
+/* Streaming-read ceiling: read the listed columns in full (k entries of dims[],
+ * no predicate, no output) with the scan kernels' launch shape, `iters` times, and
+ * return the mean duration of one pass in *ms.  The read rate 4 * n_rows * k / ms is
+ * the achievable bandwidth the scans are compared against.
+ * Errors: MDRQ_EINVAL (NULL pointers, k == 0, dim out of range), MDRQ_EDEVICE. */
+int mdrq_probe_bandwidth(mdrq_dataset* ds, const uint32_t* dims, uint32_t k, uint32_t iters,
+                         void* stream, double* ms);
 
 /* Library version as "major.minor.patch". */
 const char* mdrq_version(void);

@@ -61,7 +61,9 @@ void free_dataset(mdrq_dataset* ds) {
   if (!ds) return;
   if (ds->owned && ds->base) (void)hipFree(ds->base);
   if (ds->state) (void)hipFree(ds->state);
-  if (ds->status) (void)hipFree(ds->status);
+  if (ds->stage_bitmap) (void)hipFree(ds->stage_bitmap);
+  if (ds->tile_counts) (void)hipFree(ds->tile_counts);
+  if (ds->block_sums) (void)hipFree(ds->block_sums);
   if (ds->host_state) (void)hipHostFree(ds->host_state);
   if (ds->staging) (void)hipFree(ds->staging);
   if (ds->ev0) (void)hipEventDestroy(ds->ev0);
@@ -71,12 +73,12 @@ void free_dataset(mdrq_dataset* ds) {
 
 int alloc_workspace(mdrq_dataset* ds) {
   const uint64_t min_tile = static_cast<uint64_t>(scan_tile_rows(1));
-  const uint64_t tiles = (ds->n_rows + min_tile - 1) / min_tile + 1;
-  ds->status_len = static_cast<uint32_t>(tiles);
+  ds->max_tiles = (ds->n_rows + min_tile - 1) / min_tile + 1;
+  const uint64_t words = (ds->n_rows + 63) / 64 + 1;
   MDRQ_HIP(hipMalloc(&ds->state, sizeof(ScanState)), "hipMalloc(scan state)");
   MDRQ_HIP(hipMemset(ds->state, 0, sizeof(ScanState)), "hipMemset(scan state)");
-  MDRQ_HIP(hipMalloc(&ds->status, tiles * sizeof(uint64_t)), "hipMalloc(tile status)");
-  MDRQ_HIP(hipMemset(ds->status, 0, tiles * sizeof(uint64_t)), "hipMemset(tile status)");
+  MDRQ_HIP(hipMalloc(&ds->stage_bitmap, words * sizeof(uint64_t)), "hipMalloc(stage bitmap)");
+  MDRQ_HIP(hipMalloc(&ds->tile_counts, ds->max_tiles * sizeof(uint32_t)), "hipMalloc(tile counts)");
   MDRQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&ds->host_state), sizeof(ScanState),
                          hipHostMallocDefault),
            "hipHostMalloc(scan state)");
@@ -168,17 +170,9 @@ int ensure_staging(mdrq_dataset* ds, uint64_t bytes) {
   return MDRQ_OK;
 }
 
-uint32_t next_epoch(mdrq_dataset* ds, hipStream_t stream) {
-  if (++ds->epoch > 0x3FFFFFFFu) {
-    ds->epoch = 1;
-    (void)hipMemsetAsync(ds->status, 0, ds->status_len * sizeof(uint64_t), stream);
-  }
-  return ds->epoch;
-}
-
 int recover_state(mdrq_dataset* ds) {
+  (void)hipDeviceSynchronize();
   (void)hipMemset(ds->state, 0, sizeof(ScanState));
-  (void)hipMemset(ds->status, 0, ds->status_len * sizeof(uint64_t));
   (void)hipDeviceSynchronize();
   return MDRQ_OK;
 }
@@ -198,29 +192,57 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
   }
   const int U = ds->unroll;
   const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(U));
+  const uint32_t kmode = plan.mode == kIds ? kStage : plan.mode;
+  const uint64_t n_tiles = (ds->n_rows + tile - 1) / tile;
+  const Device& dev = device();
+  const uint64_t per_cu = std::min<uint64_t>(scan_blocks_per_cu(kmode, U), ds->blocks_per_cu);
+  const uint64_t resident = per_cu * dev.cus;
+  uint64_t want = ds->grid > 0 ? static_cast<uint64_t>(ds->grid) : resident;
+  const uint64_t blocks_needed = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  uint64_t grid = std::min<uint64_t>(blocks_needed, want);
+  // Segments of whole 4096-row compaction chunks.
+  const uint64_t align = std::max<uint64_t>(1, 4096 / tile);
+  const uint64_t seg = ((n_tiles + grid - 1) / grid + align - 1) / align * align;
+  grid = (n_tiles + seg - 1) / seg;
+  if (plan.mode == kIds && grid > ds->block_sums_len) {
+    if (ds->block_sums) (void)hipFree(ds->block_sums);
+    ds->block_sums = nullptr;
+    ds->block_sums_len = 0;
+    if (hipMalloc(&ds->block_sums, grid * sizeof(uint32_t)) != hipSuccess)
+      return fail(MDRQ_ENOMEM, "workgroup count buffer");
+    ds->block_sums_len = grid;
+  }
   ScanParams p{};
   p.n_rows = ds->n_rows;
-  p.n_tiles = static_cast<uint32_t>((ds->n_rows + tile - 1) / tile);
+  p.n_tiles = n_tiles;
   p.n_preds = static_cast<uint32_t>(plan.preds.size());
-  p.epoch = next_epoch(ds, stream);
   p.early_out = plan.early_out ? 1u : 0u;
-  p.ids = plan.mode == kIds ? static_cast<uint32_t*>(out) : nullptr;
-  p.bitmap = plan.mode == kBitmap ? static_cast<uint64_t*>(out) : nullptr;
-  p.capacity = plan.mode == kCount ? 0 : out_elems;
+  p.bitmap = plan.mode == kIds ? ds->stage_bitmap
+             : plan.mode == kBitmap ? static_cast<uint64_t*>(out) : nullptr;
+  p.capacity = plan.mode == kIds ? n_words(ds) : plan.mode == kBitmap ? out_elems : 0;
+  p.seg_tiles = seg;
+  p.tile_counts = ds->tile_counts;
+  p.block_sums = ds->block_sums;
   p.state = ds->state;
-  p.status = ds->status;
   for (size_t i = 0; i < plan.preds.size(); ++i) p.preds[i] = plan.preds[i];
-  const Device& dev = device();
-  const uint64_t resident = static_cast<uint64_t>(scan_blocks_per_cu(plan.mode, U)) * dev.cus;
-  uint64_t want = ds->grid > 0 ? static_cast<uint64_t>(ds->grid) : resident;
-  const int grid = static_cast<int>(std::min<uint64_t>(p.n_tiles, want));
+  CompactParams c{};
+  c.n_tiles = n_tiles;
+  c.n_words = n_words(ds);
+  c.seg_tiles = seg;
+  c.bitmap = ds->stage_bitmap;
+  c.tile_counts = ds->tile_counts;
+  c.block_sums = ds->block_sums;
+  c.ids = static_cast<uint32_t*>(out);
+  c.capacity = plan.mode == kIds ? out_elems : 0;
+  c.count_out = &ds->state->count_out;
 
   if (ds->profiling) {
     if (!ds->ev0) MDRQ_HIP(hipEventCreate(&ds->ev0), "hipEventCreate");
     if (!ds->ev1) MDRQ_HIP(hipEventCreate(&ds->ev1), "hipEventCreate");
     MDRQ_HIP(hipEventRecord(ds->ev0, stream), "hipEventRecord");
   }
-  hipError_t e = launch_scan(p, plan.mode, U, grid, stream);
+  hipError_t e = launch_scan(p, kmode, U, static_cast<int>(grid), stream);
+  if (e == hipSuccess && plan.mode == kIds) e = launch_compact(c, U, static_cast<int>(grid), stream);
   if (e != hipSuccess) {
     recover_state(ds);
     return fail_hip(e, "scan kernel launch");
@@ -429,6 +451,10 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
         return fail(MDRQ_EINVAL, "unroll must be 1, 2, 4 or 8");
       ds->unroll = static_cast<int>(value);
       return MDRQ_OK;
+    case MDRQ_OPT_BLOCKS_PER_CU:
+      if (value < 1 || value > 8) return fail(MDRQ_EINVAL, "blocks per CU must be 1..8");
+      ds->blocks_per_cu = static_cast<int>(value);
+      return MDRQ_OK;
     case MDRQ_OPT_GRID:
       if (value < 0 || value > (int64_t{1} << 20)) return fail(MDRQ_EINVAL, "grid out of range");
       ds->grid = value;
@@ -436,6 +462,41 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
     default:
       return fail(MDRQ_EINVAL, "unknown option");
   }
+}
+
+int mdrq_probe_bandwidth(mdrq_dataset* ds, const uint32_t* dims, uint32_t k, uint32_t iters,
+                         void* stream_, double* ms) {
+  clear_error();
+  if (!ds || !dims || !ms) return fail(MDRQ_EINVAL, "NULL argument");
+  if (k == 0 || k > ds->n_dims) return fail(MDRQ_EINVAL, "k must be 1..n_dims");
+  if (iters == 0) iters = 1;
+  std::lock_guard<std::mutex> lock(ds->mu);
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  ProbeParams p{};
+  p.n_rows = ds->n_rows;
+  p.n_cols = k;
+  for (uint32_t i = 0; i < k; ++i) {
+    if (dims[i] >= ds->n_dims) return fail(MDRQ_EINVAL, "dimension out of range");
+    p.cols[i] = ds->cols[dims[i]];
+  }
+  p.sink = reinterpret_cast<uint32_t*>(ds->state) + offsetof(ScanState, pad) / 4;
+  const Device& dev = device();
+  const int grid = static_cast<int>(static_cast<uint64_t>(scan_blocks_per_cu(kCount, ds->unroll)) * dev.cus);
+  hipEvent_t e0, e1;
+  MDRQ_HIP(hipEventCreate(&e0), "hipEventCreate");
+  MDRQ_HIP(hipEventCreate(&e1), "hipEventCreate");
+  hipError_t e = launch_probe(p, ds->unroll, grid, stream);  // warm-up pass
+  if (e == hipSuccess) e = hipEventRecord(e0, stream);
+  for (uint32_t i = 0; e == hipSuccess && i < iters; ++i) e = launch_probe(p, ds->unroll, grid, stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail_hip(e, "bandwidth probe");
+  *ms = static_cast<double>(t) / iters;
+  return MDRQ_OK;
 }
 
 const char* mdrq_version(void) { return "0.1.0"; }

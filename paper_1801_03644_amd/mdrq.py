@@ -26,8 +26,9 @@ _MODE_NAMES = {v: k for k, v in _MODES.items()}
 
 EXPORTS = ["mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve", "mdrq_free",
            "mdrq_last_error", "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
-           "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_version"]
-OPT_UNROLL, OPT_GRID = 1, 2
+           "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth",
+           "mdrq_version"]
+OPT_UNROLL, OPT_GRID, OPT_BLOCKS_PER_CU = 1, 2, 3
 
 
 class MdrqError(RuntimeError):
@@ -116,9 +117,10 @@ def load_library(path: str = LIB_PATH):
     lib.mdrq_reset_profile.argtypes = [vp]
     lib.mdrq_version.restype = ctypes.c_char_p
     lib.mdrq_set_option.argtypes = [vp, u32, ctypes.c_int64]
+    lib.mdrq_probe_bandwidth.argtypes = [vp, P(u32), u32, u32, vp, P(ctypes.c_double)]
     for f in ("mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve",
               "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
-              "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option"):
+              "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -277,6 +279,14 @@ class Dataset:
 
     def set_option(self, option: int, value: int):
         _check(load_library().mdrq_set_option(self._h, option, value))
+
+    def probe_bandwidth(self, dims, iters: int = 5, stream=None) -> float:
+        """Mean ms of one full read of the listed columns (no predicate, no output)."""
+        arr = (ctypes.c_uint32 * len(dims))(*[int(d) for d in dims])
+        ms = ctypes.c_double()
+        _check(load_library().mdrq_probe_bandwidth(self._h, arr, len(dims), iters,
+                                                   _stream_handle(stream), ctypes.byref(ms)))
+        return ms.value
 
     def set_profiling(self, on: bool = True):
         _check(load_library().mdrq_set_profiling(self._h, 1 if on else 0))
