@@ -46,6 +46,69 @@ def counters_traffic(kernel_src: str, workload: str):
     return c.get("hbm_bytes_per_launch")
 
 
+COPY_BYTES = 1 << 30   # calibration copy for the HBM byte counters
+
+
+def summarize(outdir: str, workload: str):
+    """Turn rocprofv3 CSV output under `outdir` (kernel stats, and FETCH_SIZE /
+    WRITE_SIZE counter runs) into the short summaries kept under profiles/.  Counter
+    values are scaled by what the same counter reads for the calibration copy of
+    COPY_BYTES bytes."""
+    import csv
+    import glob
+
+    prof = os.path.join(ROOT, "profiles")
+    os.makedirs(prof, exist_ok=True)
+    cmd = os.environ.get("MDRQ_PROFILE_CMD", "")
+    for path in glob.glob(os.path.join(outdir, "**", "*kernel_stats.csv"), recursive=True):
+        with open(path) as f:
+            rows = list(csv.DictReader(f))
+        out = os.path.join(prof, f"scan_{workload}_kernel_stats.txt")
+        with open(out, "w") as f:
+            f.write("rocprofv3 --kernel-trace --stats summary\n")
+            f.write(f"command: {cmd}\n\n")
+            f.write(f"{'kernel':72s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}\n")
+            for r in rows:
+                f.write(f"{r.get('Name', '')[:72]:72s} {int(r.get('Calls', 0)):7d} "
+                        f"{float(r.get('AverageNs', 0)) / 1e3:10.2f} "
+                        f"{float(r.get('TotalDurationNs', 0)) / 1e6:10.3f} "
+                        f"{float(r.get('Percentage', 0)):6.2f}\n")
+        log("wrote", out)
+    per = {}       # (counter, kernel) -> values in KiB per dispatch
+    calib = {}     # counter -> largest copy-kernel value (the calibration copy)
+    for path in glob.glob(os.path.join(outdir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                c, k, v = r["Counter_Name"], r["Kernel_Name"], float(r["Counter_Value"])
+                per.setdefault((c, k), []).append(v)
+                if "copyBuffer" in k:
+                    calib[c] = max(calib.get(c, 0.0), v)
+    if not per:
+        return
+    factor = {c: COPY_BYTES / 1024 / v for c, v in calib.items() if v > 0}
+    out = os.path.join(prof, f"scan_{workload}_counters.txt")
+    summary = {"kernel_source_sha256_16": source_hash(os.path.join(
+        ROOT, "paper_1801_03644_amd", "csrc", "scan.hip")), "scale": factor,
+        "copy_bytes": COPY_BYTES, "per_kernel_bytes": {}}
+    with open(out, "w") as f:
+        f.write("rocprofv3 --pmc summary (KiB per dispatch, then bytes after scaling by the "
+                f"calibration copy of {COPY_BYTES} bytes)\n")
+        f.write(f"command: {cmd}\n")
+        f.write(f"scale factors: {json.dumps(factor)}\n\n")
+        for (c, k), v in sorted(per.items()):
+            mean = float(np.mean(v))
+            scaled = mean * 1024 * factor.get(c, 1.0)
+            summary["per_kernel_bytes"].setdefault(k, {})[c] = scaled
+            f.write(f"{k[:72]:72s} {c:10s} n={len(v):4d} mean={mean:14.1f} KiB "
+                    f"-> {scaled / 1e9:9.4f} GB\n")
+    for k, d in summary["per_kernel_bytes"].items():
+        if k.startswith("void mdrq::(anonymous namespace)::scan_kernel<3, 8>"):
+            summary["hbm_bytes_per_launch"] = d.get("FETCH_SIZE", 0.0) + d.get("WRITE_SIZE", 0.0)
+    with open(os.path.join(prof, f"scan_{workload}_counters.json"), "w") as f:
+        json.dump(summary, f, indent=1)
+    log("wrote", out)
+
+
 def cpu_baseline(cols_raw, queries, n_rows, budget_s: float):
     import oracle
 
@@ -76,7 +139,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-earlyout", action="store_true")
     ap.add_argument("--unroll", type=int, default=None)
+    ap.add_argument("--counters", type=int, default=0, metavar="Q",
+                    help="counter-collection run: Q queries once, plus a plain copy of known "
+                         "size for calibration; prints no bench line")
+    ap.add_argument("--summarize", metavar="DIR", default=None,
+                    help="summarise rocprofv3 CSV output found under DIR into profiles/")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize, args.workload)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -126,6 +197,22 @@ def main():
                 raise mdrq.MdrqError(rc, mdrq.last_error())
             counts[i] = res.count
 
+    if args.counters:
+        for q, keep in prepared[:args.counters]:
+            rc = lib.mdrq_query(ds.handle, ctypes.byref(q), ctypes.byref(res), stream)
+            if rc not in (mdrq.OK, mdrq.EOVERFLOW):
+                raise mdrq.MdrqError(rc, mdrq.last_error())
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ks = [len(q[0]) for q in queries[:args.counters]]
+        log(f"counters run done: {args.counters} queries, mean k {np.mean(ks):.3f}; "
+            f"copy of {COPY_BYTES} bytes")
+        ds.close()
+        return
+
     for s in range(args.warmup):
         step(False)
         log(f"warmup step {s + 1}/{args.warmup} done")
@@ -140,17 +227,35 @@ def main():
         log(f"step {s + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    launches, kernel_ms = ds.profile()
+    launches, scan_ms, total_ms = ds.profile()
+    # The same queries with early-out off: every queried column is read in full, so the
+    # algorithmic read bytes are exactly the bytes the scan must fetch.
+    n_ne = min(n_q, 200)
+    ne = [mdrq.make_query(q, mdrq.Q_NO_EARLYOUT) for q in queries[:n_ne]]
+    ds.reset_profile()
+    counts_ne = np.zeros(n_ne, dtype=np.int64)
+    for i, (q, keep) in enumerate(ne):
+        lib.mdrq_query(ds.handle, ctypes.byref(q), ctypes.byref(res), stream)
+        counts_ne[i] = res.count
+    launches_ne, scan_ms_ne, total_ms_ne = ds.profile()
     ds.set_profiling(False)
+    if not np.array_equal(counts_ne, counts[:n_ne]):
+        raise RuntimeError("early-out changed a result count")
 
     ks = np.array([len(q[0]) for q in queries])
-    alg_bytes_q = 4 * w.n_rows * ks + 4 * counts + 8          # per query (= per launch)
+    n_words = (w.n_rows + 63) // 64
+    n_tiles = (w.n_rows + 2047) // 2048           # wave tiles of 2048 rows (default)
+    # Scan kernel, per launch: every queried column once (4 B per row and column), the
+    # staged result bitmap (1 bit per row) and the per-tile counts.
+    scan_bytes_q = 4 * w.n_rows * ks + 8 * n_words + 4 * n_tiles
+    # Whole query: the above plus the compaction (bitmap read back, 4 B per id).
+    query_bytes_q = scan_bytes_q + 8 * n_words + 4 * counts
     total_q = n_q * args.steps
     tuples_per_s = w.n_rows * total_q / elapsed
-    logical_gbps = alg_bytes_q.sum() * args.steps / elapsed / 1e9
     lat_us = np.concatenate(lat_all) * 1e6
-    avg_kernel_s = kernel_ms / 1e3 / launches
-    achieved = alg_bytes_q.mean() / avg_kernel_s / 1e9
+    avg_scan_s = scan_ms / 1e3 / launches
+    avg_query_s = total_ms / 1e3 / launches
+    achieved = scan_bytes_q.mean() / avg_scan_s / 1e9
     kernel_src = os.path.join(ROOT, "paper_1801_03644_amd", "csrc", "scan.hip")
     traffic = counters_traffic(kernel_src, w.name)
     sel = counts / w.n_rows
@@ -174,14 +279,24 @@ def main():
                    "early_out": not args.no_earlyout, "data_seed": w.data_seed,
                    "query_seed": w.query_seed},
         "queries_per_s": total_q / elapsed,
-        "hbm_gbps_logical": logical_gbps,
+        "hbm_gbps_logical": float(query_bytes_q.mean() / avg_query_s / 1e9),
+        "query_device_us": avg_query_s * 1e6,
         "p50_us": float(np.percentile(lat_us, 50)),
         "p99_us": float(np.percentile(lat_us, 99)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "scan_kernel<ids>", "avg_kernel_us": avg_kernel_s * 1e6,
-                     "algorithmic_bytes_per_launch": float(alg_bytes_q.mean())},
+                     "kernel": "scan_kernel<stage,8>", "avg_kernel_us": avg_scan_s * 1e6,
+                     "algorithmic_bytes_per_launch": float(scan_bytes_q.mean()),
+                     "note": "algorithmic bytes count every queried column in full; early-out "
+                             "skips the groups of rows already rejected, so fewer bytes are "
+                             "fetched (see traffic)"},
     }
+    bytes_ne = scan_bytes_q[:n_ne].mean()
+    ach_ne = bytes_ne / (scan_ms_ne / 1e3 / launches_ne) / 1e9
+    line["roofline_no_earlyout"] = {
+        "bound": "hbm", "achieved": ach_ne, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+        "frac": ach_ne / HBM_PEAK_GBPS, "avg_kernel_us": scan_ms_ne / launches_ne * 1e3,
+        "query_device_us": total_ms_ne / launches_ne * 1e3, "queries": n_ne}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(raw, queries, w.n_rows, args.cpu_budget)

@@ -195,17 +195,20 @@ int mdrq_dataset_info(const mdrq_dataset* ds, uint64_t* n_rows, uint32_t* n_dims
 /* Minimum and maximum of column `dim`, found at load. */
 int mdrq_column_range(const mdrq_dataset* ds, uint32_t dim, float* min_out, float* max_out);
 
-/* Kernel timing: when enabled, every scan kernel launch of the dataset is bracketed
- * by HIP events on the stream it runs on, and mdrq_get_profile returns the number of
- * timed launches and the sum of their durations in milliseconds. */
+/* Kernel timing: when enabled, a dataset's query launches are bracketed by HIP events
+ * on the stream they run on.  mdrq_get_profile returns the number of timed queries,
+ * the summed duration of their scan kernels alone (scan_ms: predicate evaluation and
+ * bitmap/count output) and of the whole device work of each query (total_ms: scan plus
+ * ordered compaction), in milliseconds. */
 int mdrq_set_profiling(mdrq_dataset* ds, int enable);
-int mdrq_get_profile(const mdrq_dataset* ds, uint64_t* launches, double* kernel_ms);
+int mdrq_get_profile(const mdrq_dataset* ds, uint64_t* launches, double* scan_ms,
+                     double* total_ms);
 int mdrq_reset_profile(mdrq_dataset* ds);
 
 /* Tuning options of a dataset's scans (results never depend on them). */
 enum {
-  MDRQ_OPT_UNROLL = 1,  /* 16-byte loads per lane per column in one tile: 1, 2, 4 or 8
-                           (one wave scans 256 x value rows per tile); default 8 */
+  MDRQ_OPT_UNROLL = 1,  /* 16-byte loads per lane per column in one tile: 1, 2, 4, 8
+                           or 16 (one wave scans 256 x value rows per tile); default 8 */
   MDRQ_OPT_GRID = 2,    /* workgroups per scan launch; 0 = MDRQ_OPT_BLOCKS_PER_CU per CU */
   MDRQ_OPT_BLOCKS_PER_CU = 3  /* default launch width: workgroups per CU, 1..8
                                  (capped by occupancy); default 3 */

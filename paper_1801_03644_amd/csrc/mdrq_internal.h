@@ -131,9 +131,10 @@ struct mdrq_dataset {
 
   // Profiling.
   bool profiling = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   uint64_t prof_launches = 0;
-  double prof_ms = 0.0;
+  double prof_scan_ms = 0.0;
+  double prof_total_ms = 0.0;
   int unroll = 8;                        // tile height of single-query scans (x 256 rows)
   int64_t grid = 0;                      // workgroups per launch (0 = blocks_per_cu per CU)
   int blocks_per_cu = 3;                 // default launch width, capped by occupancy

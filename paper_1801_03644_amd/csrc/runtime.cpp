@@ -68,6 +68,7 @@ void free_dataset(mdrq_dataset* ds) {
   if (ds->staging) (void)hipFree(ds->staging);
   if (ds->ev0) (void)hipEventDestroy(ds->ev0);
   if (ds->ev1) (void)hipEventDestroy(ds->ev1);
+  if (ds->ev2) (void)hipEventDestroy(ds->ev2);
   delete ds;
 }
 
@@ -239,15 +240,17 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
   if (ds->profiling) {
     if (!ds->ev0) MDRQ_HIP(hipEventCreate(&ds->ev0), "hipEventCreate");
     if (!ds->ev1) MDRQ_HIP(hipEventCreate(&ds->ev1), "hipEventCreate");
+    if (!ds->ev2) MDRQ_HIP(hipEventCreate(&ds->ev2), "hipEventCreate");
     MDRQ_HIP(hipEventRecord(ds->ev0, stream), "hipEventRecord");
   }
   hipError_t e = launch_scan(p, kmode, U, static_cast<int>(grid), stream);
+  if (e == hipSuccess && ds->profiling) e = hipEventRecord(ds->ev1, stream);
   if (e == hipSuccess && plan.mode == kIds) e = launch_compact(c, U, static_cast<int>(grid), stream);
   if (e != hipSuccess) {
     recover_state(ds);
     return fail_hip(e, "scan kernel launch");
   }
-  if (ds->profiling) MDRQ_HIP(hipEventRecord(ds->ev1, stream), "hipEventRecord");
+  if (ds->profiling) MDRQ_HIP(hipEventRecord(ds->ev2, stream), "hipEventRecord");
   e = hipMemcpyAsync(ds->host_state, ds->state, sizeof(ScanState), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
@@ -259,9 +262,11 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
     return fail(MDRQ_EDEVICE, "tile look-back wait exceeded its bound; result discarded");
   }
   if (ds->profiling) {
-    float ms = 0.f;
-    MDRQ_HIP(hipEventElapsedTime(&ms, ds->ev0, ds->ev1), "hipEventElapsedTime");
-    ds->prof_ms += ms;
+    float ms1 = 0.f, ms2 = 0.f;
+    MDRQ_HIP(hipEventElapsedTime(&ms1, ds->ev0, ds->ev1), "hipEventElapsedTime");
+    MDRQ_HIP(hipEventElapsedTime(&ms2, ds->ev0, ds->ev2), "hipEventElapsedTime");
+    ds->prof_scan_ms += ms1;
+    ds->prof_total_ms += ms2;
     ds->prof_launches += 1;
   }
   const uint64_t count = ds->host_state->count_out;
@@ -424,11 +429,13 @@ int mdrq_set_profiling(mdrq_dataset* ds, int enable) {
   return MDRQ_OK;
 }
 
-int mdrq_get_profile(const mdrq_dataset* ds, uint64_t* launches, double* kernel_ms) {
+int mdrq_get_profile(const mdrq_dataset* ds, uint64_t* launches, double* scan_ms,
+                     double* total_ms) {
   clear_error();
   if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
   if (launches) *launches = ds->prof_launches;
-  if (kernel_ms) *kernel_ms = ds->prof_ms;
+  if (scan_ms) *scan_ms = ds->prof_scan_ms;
+  if (total_ms) *total_ms = ds->prof_total_ms;
   return MDRQ_OK;
 }
 
@@ -437,7 +444,8 @@ int mdrq_reset_profile(mdrq_dataset* ds) {
   if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
   std::lock_guard<std::mutex> lock(ds->mu);
   ds->prof_launches = 0;
-  ds->prof_ms = 0.0;
+  ds->prof_scan_ms = 0.0;
+  ds->prof_total_ms = 0.0;
   return MDRQ_OK;
 }
 
@@ -447,8 +455,8 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
   std::lock_guard<std::mutex> lock(ds->mu);
   switch (option) {
     case MDRQ_OPT_UNROLL:
-      if (value != 1 && value != 2 && value != 4 && value != 8)
-        return fail(MDRQ_EINVAL, "unroll must be 1, 2, 4 or 8");
+      if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+        return fail(MDRQ_EINVAL, "unroll must be 1, 2, 4, 8 or 16");
       ds->unroll = static_cast<int>(value);
       return MDRQ_OK;
     case MDRQ_OPT_BLOCKS_PER_CU:

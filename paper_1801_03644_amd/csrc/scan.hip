@@ -28,6 +28,7 @@
 //    the word (consecutive launches on a stream need no memset); in IDS mode the
 //    compaction's last workgroup publishes it.
 #include <cstring>
+#include <type_traits>
 
 #include "mdrq_internal.h"
 
@@ -59,19 +60,24 @@ __device__ __forceinline__ uint32_t or_groups_of_8(uint32_t v) {
   return v;
 }
 
-// Wave-wide sum of a per-lane count in [0, 32].
-__device__ __forceinline__ uint32_t wave_total32(uint32_t c) {
+// Wave-wide sum of a per-lane count in [0, 64].
+__device__ __forceinline__ uint32_t wave_total64(uint32_t c) {
   uint32_t t = 0;
 #pragma unroll
-  for (int b = 0; b < 6; ++b) t += popc64(ballot((c >> b) & 1u)) << b;
+  for (int b = 0; b < 7; ++b) t += popc64(ballot((c >> b) & 1u)) << b;
   return t;
 }
+
+// Per-lane live-row mask of a wave tile: 4 bits per 16-byte group, 4*U bits.
+template <int U>
+using LaneMask = typename std::conditional<(U > 8), uint64_t, uint32_t>::type;
 
 // Live-row mask of one wave tile (bit 4u+e <=> row row0 + 256u + 4*lane + e) after
 // all predicates, for a tile lying entirely below n_rows.
 template <int U>
-__device__ __forceinline__ uint32_t eval_full(const ScanParams& p, uint64_t row0, uint32_t lane) {
-  uint32_t m = static_cast<uint32_t>((uint64_t{1} << (4 * U)) - 1u);
+__device__ __forceinline__ LaneMask<U> eval_full(const ScanParams& p, uint64_t row0, uint32_t lane) {
+  using M = LaneMask<U>;
+  M m = static_cast<M>(~M{0}) >> (8 * sizeof(M) - 4 * U);
   const uint32_t k_end = p.n_preds;
   for (uint32_t k = 0; k < k_end; ++k) {
     if (k > 0 && p.early_out && ballot(m != 0) == 0) break;
@@ -85,7 +91,7 @@ __device__ __forceinline__ uint32_t eval_full(const ScanParams& p, uint64_t row0
       v[u] = need ? *reinterpret_cast<const float4*>(c + 256 * u) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) m &= ~((~hits4(v[u], lo, hi) & 0xFu) << (4 * u));
+    for (int u = 0; u < U; ++u) m &= ~(static_cast<M>(~hits4(v[u], lo, hi) & 0xFu) << (4 * u));
   }
   return m;
 }
@@ -93,11 +99,12 @@ __device__ __forceinline__ uint32_t eval_full(const ScanParams& p, uint64_t row0
 // Same for the last, partial tile: element-wise loads of rows below n_rows only.
 // (Runs once per query: kept as plain loops so it does not raise register pressure.)
 template <int U>
-__device__ uint32_t eval_tail(const ScanParams& p, uint64_t row0, uint32_t lane) {
-  uint32_t m = 0;
+__device__ LaneMask<U> eval_tail(const ScanParams& p, uint64_t row0, uint32_t lane) {
+  using M = LaneMask<U>;
+  M m = 0;
 #pragma unroll 1
   for (int b = 0; b < 4 * U; ++b)
-    if (row0 + 256 * (b >> 2) + 4 * lane + (b & 3) < p.n_rows) m |= 1u << b;
+    if (row0 + 256 * (b >> 2) + 4 * lane + (b & 3) < p.n_rows) m |= M{1} << b;
 #pragma unroll 1
   for (uint32_t k = 0; k < p.n_preds; ++k) {
     const float* c = p.preds[k].col + row0 + 4 * lane;
@@ -105,7 +112,7 @@ __device__ uint32_t eval_tail(const ScanParams& p, uint64_t row0, uint32_t lane)
     const float hi = p.preds[k].hi;
 #pragma unroll 1
     for (int b = 0; b < 4 * U; ++b) {
-      const uint32_t bit = 1u << b;
+      const M bit = M{1} << b;
       if (m & bit) {
         const float x = c[256 * (b >> 2) + (b & 3)];
         if (!(lo <= x && x <= hi)) m &= ~bit;
@@ -135,17 +142,18 @@ __global__ void __launch_bounds__(kBlock) scan_kernel(ScanParams p) {
   for (uint64_t tile = seg_beg + wave; tile < seg_end; tile += kWavesPerBlock) {
     const uint64_t row0 = tile * kTileRows;
     const bool full = row0 + kTileRows <= p.n_rows;
-    const uint32_t m = full ? eval_full<U>(p, row0, lane) : eval_tail<U>(p, row0, lane);
+    const LaneMask<U> m = full ? eval_full<U>(p, row0, lane) : eval_tail<U>(p, row0, lane);
     if constexpr (MODE != kCount) {
       // Word w holds rows 64w .. 64w+63; lanes 8g .. 8g+7 hold 32 consecutive rows.
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const uint32_t v = or_groups_of_8(((m >> (4 * u)) & 0xFu) << (4 * (lane & 7)));
+        const uint32_t nib = static_cast<uint32_t>(m >> (4 * u)) & 0xFu;
+        const uint32_t v = or_groups_of_8(nib << (4 * (lane & 7)));
         const uint64_t dw = ((row0 + 256 * u) >> 6) * 2 + (lane >> 3);
         if ((lane & 7) == 0 && dw < lim) out32[dw] = v;
       }
     }
-    const uint32_t tc = wave_total32(__popc(m));
+    const uint32_t tc = wave_total64(__popcll(static_cast<uint64_t>(m)));
     if constexpr (MODE == kStage) {
       if (lane == 0) p.tile_counts[tile] = tc;
     }
@@ -297,6 +305,7 @@ void* pick(uint32_t mode, int unroll) {
   MDRQ_PICK(2)
   MDRQ_PICK(4)
   MDRQ_PICK(8)
+  MDRQ_PICK(16)
 #undef MDRQ_PICK
   return nullptr;
 }
@@ -402,6 +411,7 @@ hipError_t launch_compact(const CompactParams& c, int unroll, int grid, hipStrea
     case 2: f = reinterpret_cast<const void*>(&compact_kernel<2>); break;
     case 4: f = reinterpret_cast<const void*>(&compact_kernel<4>); break;
     case 8: f = reinterpret_cast<const void*>(&compact_kernel<8>); break;
+    case 16: f = reinterpret_cast<const void*>(&compact_kernel<16>); break;
     default: return hipErrorInvalidValue;
   }
   return hipLaunchKernel(f, dim3(grid), dim3(kBlock), args, 0, stream);
@@ -415,6 +425,7 @@ hipError_t launch_probe(const ProbeParams& p, int unroll, int grid, hipStream_t 
     case 2: f = reinterpret_cast<const void*>(&probe_kernel<2>); break;
     case 4: f = reinterpret_cast<const void*>(&probe_kernel<4>); break;
     case 8: f = reinterpret_cast<const void*>(&probe_kernel<8>); break;
+    case 16: f = reinterpret_cast<const void*>(&probe_kernel<16>); break;
     default: return hipErrorInvalidValue;
   }
   return hipLaunchKernel(f, dim3(grid), dim3(kBlock), args, 0, stream);

@@ -113,7 +113,7 @@ def load_library(path: str = LIB_PATH):
     lib.mdrq_dataset_info.argtypes = [vp, P(u64), P(u32)]
     lib.mdrq_column_range.argtypes = [vp, u32, P(ctypes.c_float), P(ctypes.c_float)]
     lib.mdrq_set_profiling.argtypes = [vp, i32]
-    lib.mdrq_get_profile.argtypes = [vp, P(u64), P(ctypes.c_double)]
+    lib.mdrq_get_profile.argtypes = [vp, P(u64), P(ctypes.c_double), P(ctypes.c_double)]
     lib.mdrq_reset_profile.argtypes = [vp]
     lib.mdrq_version.restype = ctypes.c_char_p
     lib.mdrq_set_option.argtypes = [vp, u32, ctypes.c_int64]
@@ -292,9 +292,11 @@ class Dataset:
         _check(load_library().mdrq_set_profiling(self._h, 1 if on else 0))
 
     def profile(self):
-        n, ms = ctypes.c_uint64(), ctypes.c_double()
-        _check(load_library().mdrq_get_profile(self._h, ctypes.byref(n), ctypes.byref(ms)))
-        return n.value, ms.value
+        """(timed queries, scan-kernel ms, whole-query device ms)."""
+        n, ms1, ms2 = ctypes.c_uint64(), ctypes.c_double(), ctypes.c_double()
+        _check(load_library().mdrq_get_profile(self._h, ctypes.byref(n), ctypes.byref(ms1),
+                                               ctypes.byref(ms2)))
+        return n.value, ms1.value, ms2.value
 
     def reset_profile(self):
         _check(load_library().mdrq_reset_profile(self._h))
