@@ -204,14 +204,23 @@ int mdrq_set_profiling(mdrq_dataset* ds, int enable);
 int mdrq_get_profile(const mdrq_dataset* ds, uint64_t* launches, double* scan_ms,
                      double* total_ms);
 int mdrq_reset_profile(mdrq_dataset* ds);
+/* Shared scans run by mdrq_query_batch and mdrq_serve since the last reset, and their
+ * summed device time (scan and finishing launches) in milliseconds. */
+int mdrq_get_batch_profile(const mdrq_dataset* ds, uint64_t* scans, double* ms);
 
 /* Tuning options of a dataset's scans (results never depend on them). */
 enum {
   MDRQ_OPT_UNROLL = 1,  /* 16-byte loads per lane per column in one tile: 1, 2, 4, 8
                            or 16 (one wave scans 256 x value rows per tile); default 8 */
   MDRQ_OPT_GRID = 2,    /* workgroups per scan launch; 0 = MDRQ_OPT_BLOCKS_PER_CU per CU */
-  MDRQ_OPT_BLOCKS_PER_CU = 3  /* default launch width: workgroups per CU, 1..8
+  MDRQ_OPT_BLOCKS_PER_CU = 3, /* default launch width: workgroups per CU, 1..8
                                  (capped by occupancy); default 3 */
+  MDRQ_OPT_BATCH_WAVES = 4,   /* shared scans: waves per workgroup, 4 or 8; 0 = autotune */
+  MDRQ_OPT_BATCH_GROUP = 5,   /* shared scans: queries per workgroup group (each group
+                                 re-reads the tile); 0 = autotune */
+  MDRQ_OPT_AUTOTUNE = 6       /* 1 (default): on the first batch of a new shape (rows,
+                                 union columns, batch size), time each candidate launch
+                                 configuration and keep the fastest; 0: fixed defaults */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
 

@@ -1,0 +1,387 @@
+// Host side of the batched shared scan: query validation and canonicalisation,
+// grouping of queries into shared scans, the query table, the launch configuration
+// autotuner, and completion.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "mdrq_internal.h"
+
+namespace mdrq {
+namespace {
+
+#define MDRQ_HIP(call, what)                         \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return fail_hip(e_, what); \
+  } while (0)
+
+constexpr uint64_t kTileRows = 4096;
+constexpr uint64_t kMaxLdsTable = 60 * 1024;   // bytes of query table per workgroup
+
+template <typename T>
+int grow_device(T** p, uint64_t* have, uint64_t need, const char* what) {
+  if (need <= *have) return MDRQ_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *have = 0;
+  if (hipMalloc(reinterpret_cast<void**>(p), need * sizeof(T)) != hipSuccess)
+    return fail(MDRQ_ENOMEM, std::string("device allocation failed: ") + what);
+  *have = need;
+  return MDRQ_OK;
+}
+
+int grow_pinned(void** p, uint64_t* have, uint64_t need) {
+  if (need <= *have) return MDRQ_OK;
+  if (*p) (void)hipHostFree(*p);
+  *p = nullptr;
+  *have = 0;
+  if (hipHostMalloc(p, need, hipHostMallocDefault) != hipSuccess)
+    return fail(MDRQ_ENOMEM, "pinned host allocation failed");
+  *have = need;
+  return MDRQ_OK;
+}
+
+// One query of a shared scan.
+struct Item {
+  uint32_t index;         // position in the caller's arrays
+  Plan plan;
+  uint32_t kind;          // BatchKind
+  mdrq_result_t* r;
+};
+
+uint32_t kind_of(uint32_t mode) {
+  switch (mode) {
+    case MDRQ_OUT_COUNT: return kBatchCount;
+    case MDRQ_OUT_BITMAP: return kBatchBitmap;
+    case MDRQ_OUT_AUTO: return kBatchAuto;
+    default: return kBatchIds;
+  }
+}
+
+uint64_t shape_key(uint64_t n_rows, size_t n_slots, size_t n_queries) {
+  const uint64_t lr = n_rows ? 64 - __builtin_clzll(n_rows) : 0;
+  const uint64_t lq = n_queries ? 64 - __builtin_clzll(n_queries) : 0;
+  return (lr << 16) | (static_cast<uint64_t>(n_slots) << 8) | lq;
+}
+
+// Run one shared scan over `items` (all with k <= kMaxSlots, union <= kMaxSlots).
+// ms_out receives the device time of the scan and finish launches.
+int run_shared(mdrq_dataset* ds, std::vector<Item>& items, const BatchConfig& cfg,
+               hipStream_t stream, float* ms_out) {
+  BatchWorkspace& ws = ds->batch;
+  const uint64_t nq = items.size();
+  const uint64_t n_rows = ds->n_rows;
+  const uint64_t nw = n_words(ds);
+  const uint64_t n_tiles = (n_rows + kTileRows - 1) / kTileRows;
+
+  // Union of the queried columns -> register slots.
+  std::vector<int> slot_of(ds->n_dims, -1);
+  std::vector<uint32_t> slot_dim;
+  for (const Item& it : items)
+    for (uint32_t d : it.plan.dims)
+      if (slot_of[d] < 0) {
+        slot_of[d] = static_cast<int>(slot_dim.size());
+        slot_dim.push_back(d);
+      }
+  const int n_slots = static_cast<int>(slot_dim.size());
+
+  // Queries per group: what the configuration asks for, and no more than fits LDS.
+  uint64_t group = cfg.group ? cfg.group : nq;
+  std::vector<uint32_t> group_first, group_table, table;
+  std::vector<BatchOut> outs(nq);
+  uint32_t n_out = 0;
+  for (uint64_t q = 0; q < nq; ++q) {
+    outs[q].kind = items[q].kind;
+    outs[q].out_index = items[q].kind == kBatchCount ? 0u : n_out++;
+  }
+  for (uint64_t q0 = 0; q0 < nq;) {
+    // Grow the group while its table fits.
+    uint64_t words = 0, q1 = q0;
+    while (q1 < nq && q1 - q0 < group) {
+      const uint64_t add = 1 + 1 + 3 * items[q1].plan.preds.size() + 1;
+      if ((words + add) * 4 > kMaxLdsTable && q1 > q0) break;
+      words += add;
+      ++q1;
+    }
+    group_first.push_back(static_cast<uint32_t>(q0));
+    group_table.push_back(static_cast<uint32_t>(table.size()));
+    const uint64_t base = table.size();
+    table.resize(base + (q1 - q0));
+    for (uint64_t q = q0; q < q1; ++q) {
+      table[base + (q - q0)] = static_cast<uint32_t>(table.size() - base);
+      const Plan& pl = items[q].plan;
+      table.push_back(static_cast<uint32_t>(pl.preds.size()) | (outs[q].kind << 8) |
+                      (outs[q].out_index << 16));
+      for (size_t i = 0; i < pl.preds.size(); ++i) {
+        const uint32_t klo = batch_key(pl.preds[i].lo);
+        const uint32_t khi = batch_key(pl.preds[i].hi);
+        table.push_back(static_cast<uint32_t>(slot_of[pl.dims[i]]));
+        table.push_back(klo);
+        table.push_back(khi - klo);
+      }
+    }
+    q0 = q1;
+  }
+  const uint32_t n_groups = static_cast<uint32_t>(group_first.size());
+  group_first.push_back(static_cast<uint32_t>(nq));
+  group_table.push_back(static_cast<uint32_t>(table.size()));
+  uint64_t max_group_words = 0;
+  for (uint32_t g = 0; g < n_groups; ++g)
+    max_group_words = std::max<uint64_t>(max_group_words, (group_table[g + 1] - group_table[g]) +
+                                                              (group_first[g + 1] - group_first[g]));
+
+  // Outputs: device buffers directly, host buffers through device staging.
+  uint64_t stage_need = 0;
+  std::vector<uint64_t> stage_off(nq, 0);
+  for (uint64_t q = 0; q < nq; ++q) {
+    mdrq_result_t* r = items[q].r;
+    if (items[q].kind != kBatchCount && r->mem == MDRQ_MEM_HOST) {
+      stage_off[q] = stage_need;
+      const uint64_t cap = std::min<uint64_t>(r->buf_bytes, std::max<uint64_t>(4 * n_rows, 8 * nw));
+      stage_need += (cap + 255) / 256 * 256;
+    }
+  }
+  int rc = grow_device(reinterpret_cast<uint8_t**>(&ws.d_stage), &ws.d_stage_bytes,
+                       std::max<uint64_t>(stage_need, 1), "batch staging");
+  if (rc) return rc;
+  for (uint64_t q = 0; q < nq; ++q) {
+    mdrq_result_t* r = items[q].r;
+    if (items[q].kind == kBatchCount) {
+      outs[q].buf = nullptr;
+      outs[q].buf_bytes = 0;
+    } else if (r->mem == MDRQ_MEM_HOST) {
+      outs[q].buf = static_cast<uint8_t*>(ws.d_stage) + stage_off[q];
+      outs[q].buf_bytes = std::min<uint64_t>(r->buf_bytes, std::max<uint64_t>(4 * n_rows, 8 * nw));
+    } else {
+      outs[q].buf = r->buf;
+      outs[q].buf_bytes = r->buf_bytes;
+    }
+  }
+
+  // Device buffers.
+  rc = grow_device(&ws.d_words, &ws.d_words_len, std::max<uint64_t>(1, n_out) * nw + 1, "batch bitmaps");
+  if (rc) return rc;
+  rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, nq * n_tiles + 1, "batch tile counts");
+  if (rc) return rc;
+  if (nq > ws.res_len) {
+    if (ws.d_res) (void)hipFree(ws.d_res);
+    if (ws.h_res) (void)hipHostFree(ws.h_res);
+    ws.d_res = ws.h_res = nullptr;
+    ws.res_len = 0;
+    if (hipMalloc(&ws.d_res, nq * 12) != hipSuccess ||
+        hipHostMalloc(&ws.h_res, nq * 12, hipHostMallocDefault) != hipSuccess)
+      return fail(MDRQ_ENOMEM, "batch result buffers");
+    ws.res_len = nq;
+  }
+  // Blob: table, group_first, group_table (uint32), then BatchOut records (8-aligned).
+  const uint64_t words_u32 = table.size() + group_first.size() + group_table.size();
+  const uint64_t outs_off = (words_u32 * 4 + 15) / 16 * 16;
+  const uint64_t blob = outs_off + nq * sizeof(BatchOut);
+  rc = grow_pinned(&ws.h_blob, &ws.h_blob_bytes, blob);
+  if (rc) return rc;
+  rc = grow_device(reinterpret_cast<uint8_t**>(&ws.d_blob), &ws.d_blob_bytes, blob, "batch table");
+  if (rc) return rc;
+  uint32_t* hb = static_cast<uint32_t*>(ws.h_blob);
+  std::memcpy(hb, table.data(), table.size() * 4);
+  std::memcpy(hb + table.size(), group_first.data(), group_first.size() * 4);
+  std::memcpy(hb + table.size() + group_first.size(), group_table.data(), group_table.size() * 4);
+  std::memcpy(static_cast<uint8_t*>(ws.h_blob) + outs_off, outs.data(), nq * sizeof(BatchOut));
+  const uint32_t* db = static_cast<const uint32_t*>(ws.d_blob);
+
+  BatchParams bp{};
+  bp.n_rows = n_rows;
+  bp.n_tiles = n_tiles;
+  bp.n_words = nw;
+  bp.n_slots = static_cast<uint32_t>(n_slots);
+  bp.table = db;
+  bp.group_first = db + table.size();
+  bp.group_table = db + table.size() + group_first.size();
+  bp.words = ws.d_words;
+  bp.tile_counts = ws.d_tile_counts;
+  for (int s = 0; s < n_slots; ++s) bp.slot_cols[s] = ds->cols[slot_dim[s]];
+  BatchFinish fin{};
+  fin.n_tiles = n_tiles;
+  fin.n_words = nw;
+  fin.words = ws.d_words;
+  fin.tile_counts = ws.d_tile_counts;
+  fin.outs = reinterpret_cast<const BatchOut*>(static_cast<const uint8_t*>(ws.d_blob) + outs_off);
+  fin.counts_out = static_cast<uint64_t*>(ws.d_res);
+  fin.kind_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws.d_res) + nq * 8);
+
+  const size_t lds = max_group_words * 4;
+  const int waves = cfg.waves == 8 ? 8 : 4;
+  const int per_cu = batch_blocks_per_cu(std::max(1, n_slots), waves, lds);
+  const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
+  const uint64_t gx = std::max<uint64_t>(1, std::min<uint64_t>(n_tiles, resident / n_groups));
+
+  if (!ws.ev0) MDRQ_HIP(hipEventCreate(&ws.ev0), "hipEventCreate");
+  if (!ws.ev1) MDRQ_HIP(hipEventCreate(&ws.ev1), "hipEventCreate");
+  MDRQ_HIP(hipMemcpyAsync(ws.d_blob, ws.h_blob, blob, hipMemcpyHostToDevice, stream),
+           "copy query table");
+  MDRQ_HIP(hipEventRecord(ws.ev0, stream), "hipEventRecord");
+  if (n_tiles > 0)
+    MDRQ_HIP(launch_batch_scan(bp, std::max(1, n_slots), waves, dim3(static_cast<uint32_t>(gx), n_groups),
+                               lds, stream),
+             "shared scan launch");
+  MDRQ_HIP(launch_batch_finish(fin, static_cast<uint32_t>(nq), stream), "batch finish launch");
+  MDRQ_HIP(hipEventRecord(ws.ev1, stream), "hipEventRecord");
+  MDRQ_HIP(hipMemcpyAsync(ws.h_res, ws.d_res, nq * 12, hipMemcpyDeviceToHost, stream),
+           "copy batch counts");
+  MDRQ_HIP(hipStreamSynchronize(stream), "shared scan completion");
+  float ms = 0.f;
+  MDRQ_HIP(hipEventElapsedTime(&ms, ws.ev0, ws.ev1), "hipEventElapsedTime");
+  if (ms_out) *ms_out = ms;
+
+  const uint64_t* counts = static_cast<const uint64_t*>(ws.h_res);
+  const uint32_t* kinds = reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(ws.h_res) + nq * 8);
+  for (uint64_t q = 0; q < nq; ++q) {
+    mdrq_result_t* r = items[q].r;
+    const uint64_t count = counts[q];
+    const uint32_t kind = kinds[q];
+    r->count = count;
+    r->status = MDRQ_OK;
+    r->written = 0;
+    uint64_t bytes = 0;
+    if (kind == kBatchCount) {
+      r->mode = MDRQ_OUT_COUNT;
+    } else if (kind == kBatchBitmap) {
+      r->mode = MDRQ_OUT_BITMAP;
+      const uint64_t cap = outs[q].buf_bytes / 8;
+      r->written = std::min(cap, nw);
+      if (cap < nw) r->status = MDRQ_EOVERFLOW;
+      bytes = r->written * 8;
+    } else {
+      r->mode = MDRQ_OUT_IDS;
+      const uint64_t cap = outs[q].buf_bytes / 4;
+      r->written = std::min(cap, count);
+      if (count > cap) r->status = MDRQ_EOVERFLOW;
+      bytes = r->written * 4;
+    }
+    if (kind != kBatchCount && r->mem == MDRQ_MEM_HOST && bytes)
+      MDRQ_HIP(hipMemcpy(r->buf, outs[q].buf, bytes, hipMemcpyDeviceToHost), "copy result to host");
+  }
+  return MDRQ_OK;
+}
+
+// Candidate configurations the autotuner tries on a new batch shape.
+std::vector<BatchConfig> candidates(uint64_t nq) {
+  std::vector<BatchConfig> c;
+  for (int w : {4, 8})
+    for (uint64_t g : {nq, (nq + 1) / 2, (nq + 3) / 4, (nq + 7) / 8}) {
+      if (g < 16 && g != nq) continue;
+      BatchConfig b;
+      b.waves = w;
+      b.group = static_cast<uint32_t>(g);
+      bool dup = false;
+      for (const BatchConfig& o : c) dup |= o.waves == b.waves && o.group == b.group;
+      if (!dup) c.push_back(b);
+    }
+  return c;
+}
+
+}  // namespace
+
+// Answer a batch: canonicalise each query, answer empty ones without a launch, run
+// queries that cannot share a scan (more than kMaxSlots predicates) alone, and group
+// the rest into shared scans whose union of columns fits the register slots.
+int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs,
+              hipStream_t stream) {
+  std::vector<Item> shared;
+  std::vector<uint32_t> alone;
+  for (uint32_t i = 0; i < n; ++i) {
+    Plan plan = make_plan(ds, &qs[i], &rs[i]);
+    if (plan.empty || ds->n_rows == 0) {
+      if (rs[i].mode == MDRQ_OUT_AUTO) {
+        plan.mode = kIds;
+        rs[i].mode = MDRQ_OUT_IDS;
+      }
+      int rc = finish_empty(ds, plan, &rs[i], stream);
+      if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
+      continue;
+    }
+    if (plan.preds.size() > static_cast<size_t>(kMaxSlots)) {
+      alone.push_back(i);
+      continue;
+    }
+    shared.push_back(Item{i, std::move(plan), kind_of(rs[i].mode), &rs[i]});
+  }
+  // Greedy grouping: a query joins the current scan while the union fits.
+  size_t pos = 0;
+  while (pos < shared.size()) {
+    std::vector<Item> batch;
+    std::vector<bool> in(ds->n_dims, false);
+    int used = 0;
+    size_t next = pos;
+    while (next < shared.size() && batch.size() < MDRQ_MAX_BATCH) {
+      int add = 0;
+      for (uint32_t d : shared[next].plan.dims) add += in[d] ? 0 : 1;
+      if (used + add > kMaxSlots) break;
+      for (uint32_t d : shared[next].plan.dims) in[d] = true;
+      used += add;
+      batch.push_back(std::move(shared[next]));
+      ++next;
+    }
+    pos = next;
+    BatchConfig cfg;
+    cfg.waves = ds->batch_waves ? ds->batch_waves : 4;
+    cfg.group = ds->batch_group;
+    const bool fixed = ds->batch_waves || ds->batch_group || !ds->autotune;
+    float ms = 0.f;
+    if (fixed) {
+      int rc = run_shared(ds, batch, cfg, stream, &ms);
+      if (rc) return rc;
+    } else {
+      const uint64_t key = shape_key(ds->n_rows, static_cast<size_t>(used), batch.size());
+      const BatchConfig* known = nullptr;
+      for (const auto& kv : ds->tuned)
+        if (kv.first == key) known = &kv.second;
+      if (known) {
+        int rc = run_shared(ds, batch, *known, stream, &ms);
+        if (rc) return rc;
+      } else {
+        // Every candidate computes the same exact results; keep the fastest.
+        BatchConfig best;
+        float best_ms = std::numeric_limits<float>::infinity();
+        for (const BatchConfig& c : candidates(batch.size())) {
+          int rc = run_shared(ds, batch, c, stream, &ms);
+          if (rc) return rc;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+          }
+        }
+        ds->tuned.emplace_back(key, best);
+        ms = best_ms;
+      }
+    }
+    ds->batch_launches += 1;
+    ds->batch_ms += ms;
+  }
+  for (uint32_t i : alone) {
+    Plan plan = make_plan(ds, &qs[i], &rs[i]);
+    if (rs[i].mode == MDRQ_OUT_AUTO) {
+      plan.mode = kIds;
+      rs[i].mode = MDRQ_OUT_IDS;
+    }
+    int rc = run_query(ds, plan, &rs[i], stream);
+    if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
+  }
+  return MDRQ_OK;
+}
+
+void free_batch(BatchWorkspace& ws) {
+  if (ws.d_blob) (void)hipFree(ws.d_blob);
+  if (ws.h_blob) (void)hipHostFree(ws.h_blob);
+  if (ws.d_words) (void)hipFree(ws.d_words);
+  if (ws.d_tile_counts) (void)hipFree(ws.d_tile_counts);
+  if (ws.d_res) (void)hipFree(ws.d_res);
+  if (ws.h_res) (void)hipHostFree(ws.h_res);
+  if (ws.d_stage) (void)hipFree(ws.d_stage);
+  if (ws.ev0) (void)hipEventDestroy(ws.ev0);
+  if (ws.ev1) (void)hipEventDestroy(ws.ev1);
+  ws = BatchWorkspace{};
+}
+
+}  // namespace mdrq

@@ -82,6 +82,50 @@ struct ProbeParams {
 };
 hipError_t launch_probe(const ProbeParams& p, int unroll, int grid, hipStream_t stream);
 
+// ---------------------------------------------------------------- batched scan
+
+constexpr int kMaxSlots = 16;   // union columns one shared scan holds in registers
+
+// Output kind of one query in a shared scan.
+enum BatchKind : uint32_t { kBatchCount = 0, kBatchBitmap = 1, kBatchIds = 2, kBatchAuto = 3 };
+
+struct BatchParams {
+  uint64_t n_rows;
+  uint64_t n_tiles;             // 4096-row tiles
+  uint64_t n_words;             // bitmap words per query
+  uint32_t n_slots;             // union columns held by the scan
+  uint32_t pad;
+  const uint32_t* table;        // per group: [offsets of records][records]
+  const uint32_t* group_first;  // first query of each group (+ end)
+  const uint32_t* group_table;  // first table word of each group (+ end)
+  uint64_t* words;              // bitmap scratch, one row of n_words per output query
+  uint32_t* tile_counts;        // [query][tile]
+  const float* slot_cols[kMaxSlots];
+};
+
+struct BatchOut {
+  uint32_t kind;                // BatchKind; kBatchAuto is resolved on the device
+  uint32_t out_index;           // row of the bitmap scratch
+  void* buf;                    // ids or bitmap words (device)
+  uint64_t buf_bytes;
+};
+
+struct BatchFinish {
+  uint64_t n_tiles;
+  uint64_t n_words;
+  const uint64_t* words;
+  const uint32_t* tile_counts;
+  const BatchOut* outs;
+  uint64_t* counts_out;         // [query] exact count
+  uint32_t* kind_out;           // [query] kind used (kBatchAuto resolved)
+};
+
+uint32_t batch_key(float x);
+int batch_blocks_per_cu(int n_slots, int waves, size_t lds_bytes);
+hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, dim3 grid,
+                             size_t lds_bytes, hipStream_t stream);
+hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream);
+
 // Load-time validation: NaN count and per-column min/max (order-preserving keys).
 struct ColumnStats {
   uint32_t nan_count;
@@ -92,6 +136,16 @@ struct ColumnStats {
 hipError_t launch_validate(const float* const* cols_dev, uint32_t n_dims, uint64_t n_rows,
                            ColumnStats* stats, hipStream_t stream);
 float key_to_float(uint32_t key);
+
+// A canonical query: predicates that can change the result, in evaluation order.
+struct Plan {
+  std::vector<DevPred> preds;
+  std::vector<uint32_t> dims;  // dimension of each entry of preds
+  bool empty = false;          // some interval is empty: no row qualifies
+  uint32_t mode = kIds;
+  uint64_t capacity = 0;
+  bool early_out = true;
+};
 
 // Thread-local error reporting.
 int fail(int code, const std::string& msg);
@@ -105,6 +159,52 @@ struct Device {
 };
 const Device& device();
 
+}  // namespace mdrq
+
+struct mdrq_dataset;
+
+namespace mdrq {
+// Host runtime pieces shared by the single-query and batched paths (runtime.cpp).
+int check_query(const mdrq_dataset* ds, const mdrq_query_t* q);
+int check_result(const mdrq_result_t* r);
+Plan make_plan(const mdrq_dataset* ds, const mdrq_query_t* q, const mdrq_result_t* r);
+uint64_t n_words(const mdrq_dataset* ds);
+int finish_empty(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream);
+int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream);
+}  // namespace mdrq
+
+namespace mdrq {
+struct BatchWorkspace;
+// Batched path (batch_host.cpp).
+int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs,
+              hipStream_t stream);
+void free_batch(BatchWorkspace& ws);
+}  // namespace mdrq
+
+namespace mdrq {
+// Device and pinned buffers of the batched path, grown on demand.
+struct BatchWorkspace {
+  void* d_blob = nullptr;        // table words, group arrays, BatchOut records
+  uint64_t d_blob_bytes = 0;
+  void* h_blob = nullptr;        // pinned staging of the same
+  uint64_t h_blob_bytes = 0;
+  uint64_t* d_words = nullptr;   // bitmap scratch
+  uint64_t d_words_len = 0;
+  uint32_t* d_tile_counts = nullptr;
+  uint64_t d_tile_counts_len = 0;
+  void* d_res = nullptr;         // counts (u64) and kinds (u32) per query
+  void* h_res = nullptr;         // pinned mirror
+  uint64_t res_len = 0;          // queries the two hold
+  void* d_stage = nullptr;       // device staging for host-memory outputs
+  uint64_t d_stage_bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+// Launch configuration of a shared scan.
+struct BatchConfig {
+  int waves = 4;                 // waves per workgroup (4 or 8)
+  uint32_t group = 0;            // queries per workgroup group (0 = all)
+};
 }  // namespace mdrq
 
 // Dataset: columns in HBM plus the workspace of its scans.
@@ -136,6 +236,15 @@ struct mdrq_dataset {
   double prof_scan_ms = 0.0;
   double prof_total_ms = 0.0;
   int unroll = 8;                        // tile height of single-query scans (x 256 rows)
+  // Batched path.
+  mdrq::BatchWorkspace batch;
+  int batch_waves = 0;                   // 0: autotuned
+  uint32_t batch_group = 0;              // 0: autotuned
+  bool autotune = true;
+  std::vector<std::pair<uint64_t, mdrq::BatchConfig>> tuned;  // shape key -> config
+  uint64_t batch_launches = 0;
+  double batch_ms = 0.0;
+
   int64_t grid = 0;                      // workgroups per launch (0 = blocks_per_cu per CU)
   int blocks_per_cu = 3;                 // default launch width, capped by occupancy
 };

@@ -69,6 +69,7 @@ void free_dataset(mdrq_dataset* ds) {
   if (ds->ev0) (void)hipEventDestroy(ds->ev0);
   if (ds->ev1) (void)hipEventDestroy(ds->ev1);
   if (ds->ev2) (void)hipEventDestroy(ds->ev2);
+  free_batch(ds->batch);
   delete ds;
 }
 
@@ -87,14 +88,9 @@ int alloc_workspace(mdrq_dataset* ds) {
   return MDRQ_OK;
 }
 
-// A canonical query: predicates that can change the result, in evaluation order.
-struct Plan {
-  std::vector<DevPred> preds;
-  bool empty = false;   // some interval is empty: no row qualifies
-  uint32_t mode = kIds;
-  uint64_t capacity = 0;
-  bool early_out = true;
-};
+}  // namespace
+
+namespace mdrq {
 
 int check_query(const mdrq_dataset* ds, const mdrq_query_t* q) {
   if (!q) return fail(MDRQ_EINVAL, "query is NULL");
@@ -131,6 +127,7 @@ Plan make_plan(const mdrq_dataset* ds, const mdrq_query_t* q, const mdrq_result_
     if (p.lo > p.hi) plan.empty = true;
     if (p.lo == -inf && p.hi == inf) continue;  // the partial-match [-inf, +inf]
     plan.preds.push_back(DevPred{ds->cols[p.dim], p.lo, p.hi});
+    plan.dims.push_back(p.dim);
   }
   plan.mode = r->mode == MDRQ_OUT_BITMAP ? kBitmap : r->mode == MDRQ_OUT_COUNT ? kCount : kIds;
   plan.capacity = plan.mode == kIds ? r->buf_bytes / 4 : plan.mode == kBitmap ? r->buf_bytes / 8 : 0;
@@ -287,7 +284,7 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
   return r->status;
 }
 
-}  // namespace
+}  // namespace mdrq
 
 extern "C" {
 
@@ -446,6 +443,8 @@ int mdrq_reset_profile(mdrq_dataset* ds) {
   ds->prof_launches = 0;
   ds->prof_scan_ms = 0.0;
   ds->prof_total_ms = 0.0;
+  ds->batch_launches = 0;
+  ds->batch_ms = 0.0;
   return MDRQ_OK;
 }
 
@@ -458,6 +457,18 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
       if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
         return fail(MDRQ_EINVAL, "unroll must be 1, 2, 4, 8 or 16");
       ds->unroll = static_cast<int>(value);
+      return MDRQ_OK;
+    case MDRQ_OPT_BATCH_WAVES:
+      if (value != 0 && value != 4 && value != 8) return fail(MDRQ_EINVAL, "batch waves must be 0, 4 or 8");
+      ds->batch_waves = static_cast<int>(value);
+      return MDRQ_OK;
+    case MDRQ_OPT_BATCH_GROUP:
+      if (value < 0 || value > MDRQ_MAX_BATCH) return fail(MDRQ_EINVAL, "batch group out of range");
+      ds->batch_group = static_cast<uint32_t>(value);
+      return MDRQ_OK;
+    case MDRQ_OPT_AUTOTUNE:
+      ds->autotune = value != 0;
+      if (!ds->autotune) ds->tuned.clear();
       return MDRQ_OK;
     case MDRQ_OPT_BLOCKS_PER_CU:
       if (value < 1 || value > 8) return fail(MDRQ_EINVAL, "blocks per CU must be 1..8");
@@ -511,10 +522,30 @@ const char* mdrq_version(void) { return "0.1.0"; }
 
 int mdrq_query_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n_queries,
                      mdrq_result_t* rs, void* stream) {
-  (void)qs; (void)n_queries; (void)rs; (void)stream;
   clear_error();
   if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
-  return fail(MDRQ_ENOTSUP, "mdrq_query_batch is not built yet");
+  if (!qs || !rs) return fail(MDRQ_EINVAL, "queries or results is NULL");
+  if (n_queries == 0 || n_queries > MDRQ_MAX_BATCH)
+    return fail(MDRQ_EINVAL, "n_queries must be 1..MDRQ_MAX_BATCH");
+  for (uint32_t i = 0; i < n_queries; ++i) {
+    int rc = check_query(ds, &qs[i]);
+    if (!rc) rc = check_result(&rs[i]);
+    if (rc) return fail(rc, "query " + std::to_string(i) + ": " + mdrq_last_error());
+  }
+  std::lock_guard<std::mutex> lock(ds->mu);
+  int rc = run_batch(ds, qs, n_queries, rs, static_cast<hipStream_t>(stream));
+  if (rc) return rc;
+  for (uint32_t i = 0; i < n_queries; ++i)
+    if (rs[i].status == MDRQ_EOVERFLOW) return MDRQ_EOVERFLOW;
+  return MDRQ_OK;
+}
+
+int mdrq_get_batch_profile(const mdrq_dataset* ds, uint64_t* scans, double* ms) {
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  if (scans) *scans = ds->batch_launches;
+  if (ms) *ms = ds->batch_ms;
+  return MDRQ_OK;
 }
 
 int mdrq_serve(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, const mdrq_request_t* reqs,

@@ -27,8 +27,9 @@ _MODE_NAMES = {v: k for k, v in _MODES.items()}
 EXPORTS = ["mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve", "mdrq_free",
            "mdrq_last_error", "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
            "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth",
-           "mdrq_version"]
+           "mdrq_get_batch_profile", "mdrq_version"]
 OPT_UNROLL, OPT_GRID, OPT_BLOCKS_PER_CU = 1, 2, 3
+OPT_BATCH_WAVES, OPT_BATCH_GROUP, OPT_AUTOTUNE = 4, 5, 6
 
 
 class MdrqError(RuntimeError):
@@ -118,9 +119,11 @@ def load_library(path: str = LIB_PATH):
     lib.mdrq_version.restype = ctypes.c_char_p
     lib.mdrq_set_option.argtypes = [vp, u32, ctypes.c_int64]
     lib.mdrq_probe_bandwidth.argtypes = [vp, P(u32), u32, u32, vp, P(ctypes.c_double)]
+    lib.mdrq_get_batch_profile.argtypes = [vp, P(u64), P(ctypes.c_double)]
     for f in ("mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve",
               "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
-              "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth"):
+              "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth",
+              "mdrq_get_batch_profile"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -297,6 +300,12 @@ class Dataset:
         _check(load_library().mdrq_get_profile(self._h, ctypes.byref(n), ctypes.byref(ms1),
                                                ctypes.byref(ms2)))
         return n.value, ms1.value, ms2.value
+
+    def batch_profile(self):
+        """(shared scans, their summed device ms) since the last reset."""
+        n, ms = ctypes.c_uint64(), ctypes.c_double()
+        _check(load_library().mdrq_get_batch_profile(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     def reset_profile(self):
         _check(load_library().mdrq_reset_profile(self._h))

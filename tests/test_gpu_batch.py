@@ -1,0 +1,227 @@
+"""GPU parity of the batched shared scan (mdrq_query_batch).
+
+Each query of a batch must give exactly what the oracle gives for it alone (and what
+mdrq_query gives for it alone): identical counts and ascending id lists, bitmaps that
+decode to the same ids.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1801_03644_amd import datagen as dg
+from paper_1801_03644_amd import mdrq
+from tests.gpu_helpers import bitmap_to_ids, device, run
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def make_outs(n_rows, modes, caps=None):
+    import torch
+
+    outs = []
+    for i, m in enumerate(modes):
+        if m == "count":
+            outs.append(None)
+            continue
+        if m == "bitmap":
+            n = (n_rows + 63) // 64 if caps is None or caps[i] is None else caps[i]
+            outs.append(torch.full((max(1, n),), -1, dtype=torch.int64, device=device())[:n])
+        else:  # ids or auto: room for every row (ids) or the bitmap, whichever is larger
+            n = max(n_rows, 2 * ((n_rows + 63) // 64)) if caps is None or caps[i] is None else caps[i]
+            outs.append(torch.full((max(1, n),), -1, dtype=torch.int32, device=device())[:n])
+    return outs
+
+
+def payload(out, ans, n_rows):
+    if out is None:
+        return None
+    a = out.cpu().numpy().view(np.uint8)
+    if ans.mode == "bitmap":
+        return bitmap_to_ids(a[:8 * ans.written].view(np.uint64), n_rows)[0]
+    return a[:4 * ans.written].view(np.uint32)
+
+
+def check_batch(ds, cols, queries, modes, label="", caps=None):
+    outs = make_outs(ds.n_rows, modes, caps)
+    answers = ds.query_batch(queries, outs, modes)
+    for i, (q, m, a, o) in enumerate(zip(queries, modes, answers, outs)):
+        st, cnt, want = oracle.query(cols, q)
+        assert a.count == cnt, (label, i, m, a.count, cnt)
+        got = payload(o, a, ds.n_rows)
+        if m == "count":
+            assert a.mode == "count"
+            continue
+        if m == "auto":
+            assert a.mode in ("ids", "bitmap")
+            nw = (ds.n_rows + 63) // 64
+            if a.mode == "bitmap":
+                assert 8 * nw < 4 * cnt or 4 * cnt > o.numel() * 4, (label, i)
+        cap = None if caps is None else caps[i]
+        if cap is None:
+            assert a.status == mdrq.OK
+            assert np.array_equal(got, want), (label, i, m)
+        else:
+            if a.mode == "ids":
+                assert a.written == min(cap, cnt)
+                assert np.array_equal(got, want[:cap]), (label, i)
+                assert a.status == (mdrq.EOVERFLOW if cnt > cap else mdrq.OK)
+    return answers
+
+
+def c3_like(n_rows, seed=0):
+    w = dg.workload("c3", n_rows)
+    raw = w.columns()
+    return w, raw
+
+
+def test_batch_matches_oracle_and_singles():
+    w, raw = c3_like(300_001)
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 64, sampler=w.sampler(sample_rows=1 << 16))
+    modes = ["ids", "bitmap", "count", "auto"] * 16
+    with mdrq.Dataset.from_host(raw) as ds:
+        _print("batch 64 on", w.n_rows)
+        check_batch(ds, cols, qs, modes, "c3-like")
+        # the same queries one at a time through mdrq_query
+        for q in qs[:16]:
+            a1, ids1 = run(ds, q)
+            outs = make_outs(ds.n_rows, ["ids"])
+            (a2,) = ds.query_batch([q], outs, ["ids"])
+            assert a1.count == a2.count
+            assert np.array_equal(ids1, payload(outs[0], a2, ds.n_rows))
+
+
+@pytest.mark.parametrize("n", [1, 63, 100, 255, 256, 4095, 4096, 4097, 70001])
+def test_batch_sizes_and_ragged_tails(n):
+    raw = [dg.column(21, j, dg.uniform(), n) for j in range(4)]
+    cols = oracle.prepare(raw)
+    rng = np.random.default_rng(n)
+    qs = [dg.make_query([]), dg.make_query([(0, 0.0, 1.0)])]
+    for _ in range(14):
+        k = int(rng.integers(1, 5))
+        dims = rng.permutation(4)[:k]
+        wdt = float(rng.choice([0.9, 0.5, 0.2, 0.05]))
+        preds = []
+        for j in dims:
+            lo = float(rng.uniform(0, 1 - wdt))
+            preds.append((int(j), lo, lo + wdt))
+        qs.append(dg.make_query(preds))
+    with mdrq.Dataset.from_host(raw) as ds:
+        for Q in (1, 7, 16):
+            modes = (["ids", "bitmap", "count", "auto"] * 4)[:Q]
+            check_batch(ds, cols, qs[:Q], modes, f"n={n} Q={Q}")
+
+
+def test_batch_special_values_degenerate_and_invalid():
+    vals = np.array([-np.inf, -1.0, -0.0, 0.0, 1e-45, 1.1754944e-38, 0.5, 1.0, np.inf],
+                    dtype=np.float32)
+    rng = np.random.default_rng(8)
+    n = 9000
+    raw = [vals[rng.integers(0, len(vals), size=n)].astype(np.float32) for _ in range(3)]
+    cols = oracle.prepare(raw)
+    cands = sorted({float(x) for v in vals for x in
+                    (v, np.nextafter(v, np.float32(np.inf)), np.nextafter(v, np.float32(-np.inf)))})
+    qs = [dg.make_query([(0, 0.5, 0.2)]),                     # empty interval
+          dg.make_query([]),                                   # all rows
+          dg.make_query([(j, -np.inf, np.inf) for j in range(3)]),
+          dg.make_query([(1, -0.0, 0.0)]),
+          dg.make_query([(2, 0.0, -0.0), (0, -np.inf, 0.5)])]
+    for _ in range(59):
+        k = int(rng.integers(1, 4))
+        dims = rng.permutation(3)[:k]
+        qs.append(dg.make_query([(int(j), cands[rng.integers(len(cands))],
+                                  cands[rng.integers(len(cands))]) for j in dims]))
+    modes = (["ids", "bitmap", "auto", "count"] * 16)
+    with mdrq.Dataset.from_host(raw) as ds:
+        check_batch(ds, cols, qs, modes, "special")
+        with pytest.raises(mdrq.MdrqError) as e:
+            ds.query_batch([qs[3], dg.make_query([(1, np.nan, 1.0)])], None, "count")
+        assert e.value.code == mdrq.EINVAL
+        with pytest.raises(mdrq.MdrqError) as e:
+            ds.query_batch([dg.make_query([(0, 0.0, 1.0), (0, 0.1, 0.2)])], None, "count")
+        assert e.value.code == mdrq.EINVAL
+
+
+def test_union_beyond_register_slots_and_long_queries():
+    """20 columns: batches whose union exceeds the 16 register slots are split into
+    several shared scans; a query on more than 16 columns runs alone."""
+    w = dg.workload("c4", 50_000)
+    raw = w.columns()
+    cols = oracle.prepare(raw)
+    rng = np.random.default_rng(4)
+    qs = []
+    for i in range(40):
+        k = 18 if i % 13 == 0 else int(rng.integers(1, 6))
+        dims = rng.permutation(20)[:k]
+        preds = []
+        for j in dims:
+            lo = float(rng.uniform(0, 0.4))
+            preds.append((int(j), lo, lo + (0.6 if k > 10 else 0.4)))
+        qs.append(dg.make_query(preds))
+    with mdrq.Dataset.from_host(raw) as ds:
+        check_batch(ds, cols, qs, ["ids", "auto"] * 20, "union")
+
+
+def test_batch_overflow_and_host_outputs():
+    w, raw = c3_like(120_000)
+    cols = oracle.prepare(raw)
+    q = dg.make_query([(0, 0.1, 0.7), (5, 0.0, 0.9)])
+    st, cnt, want = oracle.query(cols, q)
+    with mdrq.Dataset.from_host(raw) as ds:
+        caps = [0, 1, cnt // 2, cnt - 1, cnt, None]
+        check_batch(ds, cols, [q] * len(caps), ["ids"] * len(caps), "overflow", caps=caps)
+        outs = [np.zeros(w.n_rows, dtype=np.uint32), np.zeros((w.n_rows + 63) // 64, dtype=np.uint64)]
+        a = ds.query_batch([q, q], outs, ["ids", "bitmap"])
+        assert a[0].count == cnt and np.array_equal(outs[0][:a[0].written], want)
+        assert np.array_equal(bitmap_to_ids(outs[1], w.n_rows)[0], want)
+
+
+def test_launch_configurations_give_identical_results():
+    w, raw = c3_like(200_000)
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 48, sampler=w.sampler(sample_rows=1 << 16))
+    with mdrq.Dataset.from_host(raw) as ds:
+        ref = None
+        for waves, group, tune in [(0, 0, 1), (4, 0, 0), (8, 0, 0), (4, 16, 0), (8, 24, 0), (0, 0, 1)]:
+            ds.set_option(mdrq.OPT_BATCH_WAVES, waves)
+            ds.set_option(mdrq.OPT_BATCH_GROUP, group)
+            ds.set_option(mdrq.OPT_AUTOTUNE, tune)
+            outs = make_outs(ds.n_rows, ["ids"] * len(qs))
+            ans = ds.query_batch(qs, outs, "ids")
+            got = [(a.count, payload(o, a, ds.n_rows).tobytes()) for a, o in zip(ans, outs)]
+            if ref is None:
+                ref = got
+                for q, (c, _) in zip(qs, got):
+                    assert c == oracle.count(cols, q)
+            assert got == ref, (waves, group, tune)
+
+
+def test_full_size_c3_batch_sampled():
+    """The c3 shape at full size (5*10^7 x 8): one batch of 256 queries; every count
+    and the ids of a sample of queries against the oracle."""
+    w = dg.workload("c3")
+    _print("c3 full size: generating")
+    raw = w.columns()
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 256)
+    modes = ["auto"] * 256
+    with mdrq.Dataset.from_host(raw) as ds:
+        outs = make_outs(ds.n_rows, ["ids"] * 256, caps=[4_000_000] * 256)
+        _print("c3 full size: batch")
+        ans = ds.query_batch(qs, outs, modes)
+        rng = np.random.default_rng(0)
+        for i in rng.choice(256, size=6, replace=False):
+            st, cnt, want = oracle.query(cols, qs[i])
+            assert ans[i].count == cnt
+            got = payload(outs[i], ans[i], ds.n_rows)
+            if ans[i].status == mdrq.OK:
+                assert np.array_equal(got, want)
+            else:
+                assert np.array_equal(got, want[:len(got)])
+        # counts of all 256 against the single-query path
+        for i, q in enumerate(qs):
+            assert ds.query(q, None, mode="count").count == ans[i].count
