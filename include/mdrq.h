@@ -218,9 +218,12 @@ enum {
   MDRQ_OPT_BATCH_WAVES = 4,   /* shared scans: waves per workgroup, 4 or 8; 0 = autotune */
   MDRQ_OPT_BATCH_GROUP = 5,   /* shared scans: queries per workgroup group (each group
                                  re-reads the tile); 0 = autotune */
-  MDRQ_OPT_AUTOTUNE = 6       /* 1 (default): on the first batch of a new shape (rows,
+  MDRQ_OPT_AUTOTUNE = 6,      /* 1 (default): on the first batch of a new shape (rows,
                                  union columns, batch size), time each candidate launch
                                  configuration and keep the fastest; 0: fixed defaults */
+  MDRQ_OPT_BATCH_ROWS = 7     /* shared scans: 64-row groups each lane holds per chunk,
+                                 4, 8 or 16 (tile height 64 x value rows per wave);
+                                 0 = autotune */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
 

@@ -9,20 +9,21 @@
 // section 2.2.4 per query, the per-dimension results ANDed as in section 3.2.
 //
 // GPU design (the work is VALU-bound once many queries share a tile):
-//  * Lane l of a wave holds rows 64e + l (e = 0..3) of a 256-row chunk, one dword
-//    load per column and e.  Values become order-preserving uint32 keys once per
+//  * Lane l of a wave holds rows 64g + l (g < RG) of a chunk of 64*RG rows, one dword
+//    load per column and g.  Values become order-preserving uint32 keys once per
 //    chunk (-0 mapped to +0), so one predicate on 64 rows is one subtract and one
 //    unsigned compare:  lo <= x <= hi  <=>  key(x) - key(lo) <= key(hi) - key(lo).
-//    The compare lands in a 64-bit wave mask, which is directly bitmap word e of the
-//    chunk (bit l <=> row 64e + l).
-//  * The union's keys sit in registers (D slots x 4); the query table sits in LDS.
-//    Per query, predicates run in the query's order and a query stops as soon as its
-//    four masks are all zero.
-//  * Per (query, 256-row chunk) the four masks are written as bitmap words to
-//    scratch; per (query, 4096-row tile) the count is accumulated in LDS and stored.
+//    The compare lands in a 64-bit wave mask, which is directly bitmap word g of the
+//    chunk (bit l <=> row 64g + l).
+//  * The union's keys sit in registers (D slots x RG); the query table sits in LDS.
+//    Per query, predicates run in the query's order and a query stops as soon as all
+//    its masks are zero.  RG rows per lane amortise the per-predicate table read.
+//  * The bitmap scratch is zeroed first; per (query, chunk) only non-zero masks are
+//    stored; per (query, 4096-row tile) the count is accumulated in LDS and stored.
 //  * A finishing launch takes one workgroup per query: it sums the query's tile
 //    counts and, for identifier output, scans them in LDS and compacts the query's
 //    bitmap into ascending identifiers (tiles without a hit are not read).
+#include <algorithm>
 #include <cstring>
 
 #include "mdrq_internal.h"
@@ -40,25 +41,27 @@ __device__ __forceinline__ uint32_t dkey(float x) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-// Evaluate one predicate of slot S on the four row groups of a chunk.
-#define MDRQ_SLOT_CASE(S)                                              \
-  case S:                                                              \
-    m0 &= ballot(x[S][0] - klo <= kw);                                 \
-    m1 &= ballot(x[S][1] - klo <= kw);                                 \
-    m2 &= ballot(x[S][2] - klo <= kw);                                 \
-    m3 &= ballot(x[S][3] - klo <= kw);                                 \
-    break;
+// One query-table predicate, read from LDS as one 16-byte entry.
+struct TabPred {
+  uint32_t slot, klo, kw, pad;
+};
 
-template <int D, int W>
+// Workgroups stride over 4096-row tiles; within a tile, each wave takes chunks of
+// 64*RG rows (lane l holds rows 64g + l, g < RG).  For each chunk every query of the
+// workgroup's group is evaluated; non-zero wave masks are stored as bitmap words
+// (the scratch was zeroed), and the chunk's count is added to the query's tile
+// count in LDS.
+template <int D, int W, int RG>
 __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
+  static_assert(W * RG <= 64, "a tile must hold at least one chunk per wave");
   extern __shared__ uint32_t lds[];
   const uint32_t group = blockIdx.y;
   const uint32_t q_beg = bp.group_first[group];
   const uint32_t q_end = bp.group_first[group + 1];
   const uint32_t nq = q_end - q_beg;
-  // LDS: [0, nq) per-query tile counts, then the group's table words.
+  // LDS: [0, nq) per-query tile counts, then the group's table words (16-byte aligned).
   uint32_t* s_cnt = lds;
-  uint32_t* s_tab = lds + nq;
+  uint32_t* s_tab = lds + ((nq + 3) & ~3u);
   const uint32_t t_beg = bp.group_table[group];
   const uint32_t t_len = bp.group_table[group + 1] - t_beg;
   for (uint32_t i = threadIdx.x; i < t_len; i += W * 64) s_tab[i] = bp.table[t_beg + i];
@@ -67,68 +70,74 @@ __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
 
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = threadIdx.x / 64;
-  constexpr uint32_t kChunksPerWave = 16 / W;   // a tile is 16 chunks of 256 rows
+  constexpr uint32_t kChunkRows = 64 * RG;
+  constexpr uint32_t kChunksPerWave = 4096 / kChunkRows / W;
   for (uint64_t tile = blockIdx.x; tile < bp.n_tiles; tile += gridDim.x) {
 #pragma unroll 1
     for (uint32_t cw = 0; cw < kChunksPerWave; ++cw) {
-      const uint64_t chunk = tile * 16 + wave * kChunksPerWave + cw;
-      const uint64_t row0 = chunk * 256;
+      const uint64_t row0 = tile * 4096 + (wave * kChunksPerWave + cw) * kChunkRows;
       if (row0 >= bp.n_rows) break;
-      // Slots >= D are never referenced by the table (n_slots <= D); they stay the
-      // constant 0 so that their switch cases fold away.
-      uint32_t x[kMaxSlots][4];
-      uint64_t valid[4];
+      uint32_t x[D][RG];
+      const bool full = row0 + kChunkRows <= bp.n_rows;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint64_t r = row0 + 64 * e + lane;
-        valid[e] = ballot(r < bp.n_rows);
+      for (int g = 0; g < RG; ++g) {
+        const uint64_t r = row0 + 64 * g + lane;
 #pragma unroll
-        for (int s = 0; s < kMaxSlots; ++s)
-          x[s][e] = (s < D && s < static_cast<int>(bp.n_slots) && r < bp.n_rows)
+        for (int s = 0; s < D; ++s)
+          x[s][g] = (s < static_cast<int>(bp.n_slots) && (full || r < bp.n_rows))
                         ? dkey(bp.slot_cols[s][r]) : 0u;
       }
       const uint64_t word0 = row0 / 64;
+      // Records are contiguous: each is a 4-word header and 4 words per predicate.
+      const uint32_t* rec = s_tab + s_tab[0];
 #pragma unroll 1
       for (uint32_t qi = 0; qi < nq; ++qi) {
-        const uint32_t* rec = s_tab + s_tab[qi];
-        const uint32_t head = rec[0];
+        const uint32_t head = __builtin_amdgcn_readfirstlane(rec[0]);
         const uint32_t np = head & 0xFFu;
         const uint32_t kind = (head >> 8) & 0x3u;
-        uint64_t m0 = valid[0], m1 = valid[1], m2 = valid[2], m3 = valid[3];
+        const TabPred* tp = reinterpret_cast<const TabPred*>(rec + 4);
+        rec += 4 + 4 * np;
+        uint64_t m[RG];
+#pragma unroll
+        for (int g = 0; g < RG; ++g) m[g] = ballot(row0 + 64 * g + lane < bp.n_rows);
+        bool dead = false;
 #pragma unroll 1
         for (uint32_t pi = 0; pi < np; ++pi) {
-          const uint32_t slot = __builtin_amdgcn_readfirstlane(rec[1 + 3 * pi]);
-          const uint32_t klo = __builtin_amdgcn_readfirstlane(rec[2 + 3 * pi]);
-          const uint32_t kw = __builtin_amdgcn_readfirstlane(rec[3 + 3 * pi]);
-          switch (slot) {
-            MDRQ_SLOT_CASE(0)
-            MDRQ_SLOT_CASE(1)
-            MDRQ_SLOT_CASE(2)
-            MDRQ_SLOT_CASE(3)
-            MDRQ_SLOT_CASE(4)
-            MDRQ_SLOT_CASE(5)
-            MDRQ_SLOT_CASE(6)
-            MDRQ_SLOT_CASE(7)
-            MDRQ_SLOT_CASE(8)
-            MDRQ_SLOT_CASE(9)
-            MDRQ_SLOT_CASE(10)
-            MDRQ_SLOT_CASE(11)
-            MDRQ_SLOT_CASE(12)
-            MDRQ_SLOT_CASE(13)
-            MDRQ_SLOT_CASE(14)
-            MDRQ_SLOT_CASE(15)
-            default:
+          const TabPred t = tp[pi];
+          const uint32_t slot = __builtin_amdgcn_readfirstlane(t.slot);
+          const uint32_t klo = __builtin_amdgcn_readfirstlane(t.klo);
+          const uint32_t kw = __builtin_amdgcn_readfirstlane(t.kw);
+          // Slot dispatch: register slots cannot be indexed at run time, so a flat
+          // chain of uniform branches; each case updates the masks in place.
+#pragma unroll
+          for (int S = 0; S < D; ++S)
+            if (slot == static_cast<uint32_t>(S)) {
+#pragma unroll
+              for (int g = 0; g < RG; ++g) m[g] &= ballot(x[S][g] - klo <= kw);
+            }
+          // Early break of the whole chunk, tested after every second predicate.
+          if ((pi & 1) && pi + 1 < np) {
+            uint64_t any = 0;
+#pragma unroll
+            for (int g = 0; g < RG; ++g) any |= m[g];
+            if (any == 0) {
+              dead = true;
               break;
+            }
           }
-          if ((m0 | m1 | m2 | m3) == 0) break;
         }
-        const uint32_t c = __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3);
-        if (c != 0 && lane == 0) atomicAdd(&s_cnt[qi], c);
-        if (kind != kBatchCount) {
-          const uint32_t out = head >> 16;
-          uint64_t* words = bp.words + static_cast<uint64_t>(out) * bp.n_words + word0;
-          const uint64_t mv = lane == 0 ? m0 : lane == 1 ? m1 : lane == 2 ? m2 : m3;
-          if (lane < 4 && word0 + lane < bp.n_words) words[lane] = mv;
+        if (dead) continue;
+        uint32_t c = 0;
+#pragma unroll
+        for (int g = 0; g < RG; ++g) c += __popcll(m[g]);
+        if (c != 0) {
+          if (lane == 0) atomicAdd(&s_cnt[qi], c);
+          if (kind != kBatchCount) {
+            uint64_t* words = bp.words + static_cast<uint64_t>(head >> 16) * bp.n_words + word0;
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+              if (m[g] != 0 && lane == 0) words[g] = m[g];
+          }
         }
       }
     }
@@ -140,7 +149,13 @@ __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
     __syncthreads();
   }
 }
-#undef MDRQ_SLOT_CASE
+
+// Zero a range of 64-bit words (the bitmap scratch before a shared scan).
+__global__ void __launch_bounds__(256) zero_words_kernel(uint64_t* w, uint64_t n) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 256;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride)
+    w[i] = 0;
+}
 
 // ---------------------------------------------------------------- per-query finish
 
@@ -260,14 +275,26 @@ __global__ void __launch_bounds__(kFinThreads) batch_finish_kernel(BatchFinish f
   }
 }
 
-template <int D, int W>
+template <int D, int W, int RG>
 const void* scan_fn() {
-  return reinterpret_cast<const void*>(&batch_scan_kernel<D, W>);
+  return reinterpret_cast<const void*>(&batch_scan_kernel<D, W, RG>);
 }
 
-const void* pick_batch(int d, int w) {
-  if (w == 4) return d <= 4 ? scan_fn<4, 4>() : d <= 8 ? scan_fn<8, 4>() : scan_fn<16, 4>();
-  return d <= 4 ? scan_fn<4, 8>() : d <= 8 ? scan_fn<8, 8>() : scan_fn<16, 8>();
+// Register budget: D slots x RG rows per lane stays at or below 128 VGPRs.
+const void* pick_batch(int d, int w, int rg) {
+  const int dd = d <= 4 ? 4 : d <= 8 ? 8 : 16;
+  if (dd == 4) {
+    if (rg == 16) return scan_fn<4, 4, 16>();
+    if (rg == 8) return w == 8 ? scan_fn<4, 8, 8>() : scan_fn<4, 4, 8>();
+    return w == 8 ? scan_fn<4, 8, 4>() : scan_fn<4, 4, 4>();
+  }
+  if (dd == 8) {
+    if (rg == 16) return scan_fn<8, 4, 16>();
+    if (rg == 8) return w == 8 ? scan_fn<8, 8, 8>() : scan_fn<8, 4, 8>();
+    return w == 8 ? scan_fn<8, 8, 4>() : scan_fn<8, 4, 4>();
+  }
+  if (rg >= 8) return w == 8 ? scan_fn<16, 8, 8>() : scan_fn<16, 4, 8>();
+  return w == 8 ? scan_fn<16, 8, 4>() : scan_fn<16, 4, 4>();
 }
 
 }  // namespace
@@ -279,19 +306,36 @@ uint32_t batch_key(float x) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-int batch_blocks_per_cu(int n_slots, int waves, size_t lds_bytes) {
+int batch_rows_per_lane(int n_slots, int waves, int rg) {
+  (void)n_slots;
+  if (rg == 16 && waves == 8) rg = 8;
+  if (n_slots > 8 && rg == 16) rg = 8;
+  return rg == 16 || rg == 8 ? rg : 4;
+}
+
+int batch_blocks_per_cu(int n_slots, int waves, int rg, size_t lds_bytes) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, pick_batch(n_slots, waves), waves * 64,
-                                                   lds_bytes) != hipSuccess)
+  const int w = waves == 8 ? 8 : 4;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &blocks, pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg)), w * 64,
+          lds_bytes) != hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;
 }
 
-hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, dim3 grid,
+hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, dim3 grid,
                              size_t lds_bytes, hipStream_t stream) {
+  const int w = waves == 8 ? 8 : 4;
+  const uint64_t n = bp.n_words * bp.n_out;
+  if (n) {
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
+    zero_words_kernel<<<static_cast<uint32_t>(blocks), 256, 0, stream>>>(bp.words, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   void* args[] = {const_cast<BatchParams*>(&bp)};
-  return hipLaunchKernel(pick_batch(n_slots, waves), grid, dim3(waves * 64), args, lds_bytes,
-                         stream);
+  return hipLaunchKernel(pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg)), grid,
+                         dim3(w * 64), args, lds_bytes, stream);
 }
 
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream) {

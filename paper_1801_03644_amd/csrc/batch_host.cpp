@@ -96,30 +96,36 @@ int run_shared(mdrq_dataset* ds, std::vector<Item>& items, const BatchConfig& cf
     outs[q].kind = items[q].kind;
     outs[q].out_index = items[q].kind == kBatchCount ? 0u : n_out++;
   }
+  // Group table: record offsets (padded to 4 words), then per query a 4-word header
+  // and one 4-word entry (slot, key(lo), key(hi) - key(lo), 0) per predicate.
   for (uint64_t q0 = 0; q0 < nq;) {
-    // Grow the group while its table fits.
+    // Grow the group while its table and counts fit LDS.
     uint64_t words = 0, q1 = q0;
     while (q1 < nq && q1 - q0 < group) {
-      const uint64_t add = 1 + 1 + 3 * items[q1].plan.preds.size() + 1;
-      if ((words + add) * 4 > kMaxLdsTable && q1 > q0) break;
+      const uint64_t add = 4 + 4 * items[q1].plan.preds.size() + 2;  // record, offset, count
+      if ((words + add + 8) * 4 > kMaxLdsTable && q1 > q0) break;
       words += add;
       ++q1;
     }
     group_first.push_back(static_cast<uint32_t>(q0));
     group_table.push_back(static_cast<uint32_t>(table.size()));
     const uint64_t base = table.size();
-    table.resize(base + (q1 - q0));
+    table.resize(base + ((q1 - q0 + 3) & ~uint64_t{3}), 0u);
     for (uint64_t q = q0; q < q1; ++q) {
       table[base + (q - q0)] = static_cast<uint32_t>(table.size() - base);
       const Plan& pl = items[q].plan;
       table.push_back(static_cast<uint32_t>(pl.preds.size()) | (outs[q].kind << 8) |
                       (outs[q].out_index << 16));
+      table.push_back(0u);
+      table.push_back(0u);
+      table.push_back(0u);
       for (size_t i = 0; i < pl.preds.size(); ++i) {
         const uint32_t klo = batch_key(pl.preds[i].lo);
         const uint32_t khi = batch_key(pl.preds[i].hi);
         table.push_back(static_cast<uint32_t>(slot_of[pl.dims[i]]));
         table.push_back(klo);
         table.push_back(khi - klo);
+        table.push_back(0u);
       }
     }
     q0 = q1;
@@ -129,8 +135,9 @@ int run_shared(mdrq_dataset* ds, std::vector<Item>& items, const BatchConfig& cf
   group_table.push_back(static_cast<uint32_t>(table.size()));
   uint64_t max_group_words = 0;
   for (uint32_t g = 0; g < n_groups; ++g)
-    max_group_words = std::max<uint64_t>(max_group_words, (group_table[g + 1] - group_table[g]) +
-                                                              (group_first[g + 1] - group_first[g]));
+    max_group_words = std::max<uint64_t>(
+        max_group_words, (group_table[g + 1] - group_table[g]) +
+                             ((group_first[g + 1] - group_first[g] + 3) & ~uint64_t{3}));
 
   // Outputs: device buffers directly, host buffers through device staging.
   uint64_t stage_need = 0;
@@ -199,6 +206,7 @@ int run_shared(mdrq_dataset* ds, std::vector<Item>& items, const BatchConfig& cf
   bp.group_first = db + table.size();
   bp.group_table = db + table.size() + group_first.size();
   bp.words = ws.d_words;
+  bp.n_out = n_out;
   bp.tile_counts = ws.d_tile_counts;
   for (int s = 0; s < n_slots; ++s) bp.slot_cols[s] = ds->cols[slot_dim[s]];
   BatchFinish fin{};
@@ -212,7 +220,8 @@ int run_shared(mdrq_dataset* ds, std::vector<Item>& items, const BatchConfig& cf
 
   const size_t lds = max_group_words * 4;
   const int waves = cfg.waves == 8 ? 8 : 4;
-  const int per_cu = batch_blocks_per_cu(std::max(1, n_slots), waves, lds);
+  const int rg = batch_rows_per_lane(std::max(1, n_slots), waves, cfg.rows_per_lane);
+  const int per_cu = batch_blocks_per_cu(std::max(1, n_slots), waves, rg, lds);
   const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
   const uint64_t gx = std::max<uint64_t>(1, std::min<uint64_t>(n_tiles, resident / n_groups));
 
@@ -222,8 +231,8 @@ int run_shared(mdrq_dataset* ds, std::vector<Item>& items, const BatchConfig& cf
            "copy query table");
   MDRQ_HIP(hipEventRecord(ws.ev0, stream), "hipEventRecord");
   if (n_tiles > 0)
-    MDRQ_HIP(launch_batch_scan(bp, std::max(1, n_slots), waves, dim3(static_cast<uint32_t>(gx), n_groups),
-                               lds, stream),
+    MDRQ_HIP(launch_batch_scan(bp, std::max(1, n_slots), waves, rg,
+                               dim3(static_cast<uint32_t>(gx), n_groups), lds, stream),
              "shared scan launch");
   MDRQ_HIP(launch_batch_finish(fin, static_cast<uint32_t>(nq), stream), "batch finish launch");
   MDRQ_HIP(hipEventRecord(ws.ev1, stream), "hipEventRecord");
@@ -266,18 +275,21 @@ int run_shared(mdrq_dataset* ds, std::vector<Item>& items, const BatchConfig& cf
 }
 
 // Candidate configurations the autotuner tries on a new batch shape.
-std::vector<BatchConfig> candidates(uint64_t nq) {
+std::vector<BatchConfig> candidates(uint64_t nq, int n_slots) {
   std::vector<BatchConfig> c;
-  for (int w : {4, 8})
-    for (uint64_t g : {nq, (nq + 1) / 2, (nq + 3) / 4, (nq + 7) / 8}) {
-      if (g < 16 && g != nq) continue;
-      BatchConfig b;
-      b.waves = w;
-      b.group = static_cast<uint32_t>(g);
-      bool dup = false;
-      for (const BatchConfig& o : c) dup |= o.waves == b.waves && o.group == b.group;
-      if (!dup) c.push_back(b);
-    }
+  for (int rg : {16, 8, 4})
+    for (int w : {4, 8})
+      for (uint64_t g : {nq, (nq + 1) / 2, (nq + 3) / 4}) {
+        if (g < 16 && g != nq) continue;
+        BatchConfig b;
+        b.waves = w;
+        b.group = static_cast<uint32_t>(g);
+        b.rows_per_lane = batch_rows_per_lane(n_slots, w, rg);
+        bool dup = false;
+        for (const BatchConfig& o : c)
+          dup |= o.waves == b.waves && o.group == b.group && o.rows_per_lane == b.rows_per_lane;
+        if (!dup) c.push_back(b);
+      }
   return c;
 }
 
@@ -327,7 +339,8 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     BatchConfig cfg;
     cfg.waves = ds->batch_waves ? ds->batch_waves : 4;
     cfg.group = ds->batch_group;
-    const bool fixed = ds->batch_waves || ds->batch_group || !ds->autotune;
+    cfg.rows_per_lane = ds->batch_rows ? ds->batch_rows : 16;
+    const bool fixed = ds->batch_waves || ds->batch_group || ds->batch_rows || !ds->autotune;
     float ms = 0.f;
     if (fixed) {
       int rc = run_shared(ds, batch, cfg, stream, &ms);
@@ -344,7 +357,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
         // Every candidate computes the same exact results; keep the fastest.
         BatchConfig best;
         float best_ms = std::numeric_limits<float>::infinity();
-        for (const BatchConfig& c : candidates(batch.size())) {
+        for (const BatchConfig& c : candidates(batch.size(), used)) {
           int rc = run_shared(ds, batch, c, stream, &ms);
           if (rc) return rc;
           if (ms < best_ms) {

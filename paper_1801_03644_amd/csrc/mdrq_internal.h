@@ -99,6 +99,7 @@ struct BatchParams {
   const uint32_t* group_first;  // first query of each group (+ end)
   const uint32_t* group_table;  // first table word of each group (+ end)
   uint64_t* words;              // bitmap scratch, one row of n_words per output query
+  uint64_t n_out;               // rows of the scratch in use (zeroed before the scan)
   uint32_t* tile_counts;        // [query][tile]
   const float* slot_cols[kMaxSlots];
 };
@@ -121,8 +122,9 @@ struct BatchFinish {
 };
 
 uint32_t batch_key(float x);
-int batch_blocks_per_cu(int n_slots, int waves, size_t lds_bytes);
-hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, dim3 grid,
+int batch_rows_per_lane(int n_slots, int waves, int rg);
+int batch_blocks_per_cu(int n_slots, int waves, int rg, size_t lds_bytes);
+hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, dim3 grid,
                              size_t lds_bytes, hipStream_t stream);
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream);
 
@@ -204,6 +206,7 @@ struct BatchWorkspace {
 struct BatchConfig {
   int waves = 4;                 // waves per workgroup (4 or 8)
   uint32_t group = 0;            // queries per workgroup group (0 = all)
+  int rows_per_lane = 16;        // 64-row groups per lane per chunk: 4, 8 or 16
 };
 }  // namespace mdrq
 
@@ -240,6 +243,7 @@ struct mdrq_dataset {
   mdrq::BatchWorkspace batch;
   int batch_waves = 0;                   // 0: autotuned
   uint32_t batch_group = 0;              // 0: autotuned
+  int batch_rows = 0;                    // 64-row groups per lane (4, 8, 16); 0: autotuned
   bool autotune = true;
   std::vector<std::pair<uint64_t, mdrq::BatchConfig>> tuned;  // shape key -> config
   uint64_t batch_launches = 0;

@@ -29,7 +29,7 @@ EXPORTS = ["mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve", 
            "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth",
            "mdrq_get_batch_profile", "mdrq_version"]
 OPT_UNROLL, OPT_GRID, OPT_BLOCKS_PER_CU = 1, 2, 3
-OPT_BATCH_WAVES, OPT_BATCH_GROUP, OPT_AUTOTUNE = 4, 5, 6
+OPT_BATCH_WAVES, OPT_BATCH_GROUP, OPT_AUTOTUNE, OPT_BATCH_ROWS = 4, 5, 6, 7
 
 
 class MdrqError(RuntimeError):
