@@ -1,0 +1,125 @@
+"""Pins for the estimator's CPU reference (oracle/estimator_ref.py): closed forms, known
+values, brute-force derivatives and invariants, none of which reuse its formulas."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import estimator_ref as er
+
+
+def test_bf16_rounding_known_bit_patterns():
+    f = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -9, -2.5, 3.0e38, 1e-40],
+                 dtype=np.float32)
+    r = er.bf16_round(f)
+    bits = r.astype(np.float32).view(np.uint32)
+    assert (bits & 0xFFFF == 0).all()
+    assert r[0] == 1.0
+    assert r[1] == 1.0                    # tie, even upper half stays
+    assert r[2] == 1 + 4 * 2 ** -8        # tie, odd upper half rounds up
+    assert r[3] == 1.0                    # below half
+    assert r[4] == -2.5
+    # nearest: no other bfloat16 value is closer
+    for x, y in zip(f.astype(np.float64), r):
+        up = np.float32(y).view(np.uint32) + np.uint32(0x10000)
+        dn = np.float32(y).view(np.uint32) - np.uint32(0x10000)
+        for z in (up, dn):
+            zz = float(np.uint32(z).view(np.float32))
+            if np.isfinite(zz):
+                assert abs(zz - x) >= abs(y - x)
+
+
+def test_gelu_known_values_and_derivative():
+    assert er.gelu(np.array([0.0]))[0] == 0.0
+    assert abs(er.gelu(np.array([1.0]))[0] - 0.8413447460685429) < 1e-15
+    assert abs(er.gelu(np.array([-1.0]))[0] + 0.15865525393145707) < 1e-15
+    assert abs(er.gelu(np.array([8.0]))[0] - 8.0) < 1e-12
+    z = np.linspace(-4, 4, 41)
+    h = 1e-6
+    fd = (er.gelu(z + h) - er.gelu(z - h)) / (2 * h)
+    assert np.allclose(er.gelu_grad(z), fd, atol=1e-8)
+
+
+def _params(rng, K=12, H=8, O=5, scale=0.5):
+    return {"W1": rng.normal(0, scale, (K, H)), "b1": rng.normal(0, 0.1, H),
+            "W2": rng.normal(0, scale, (H, H)), "b2": rng.normal(0, 0.1, H),
+            "W3": rng.normal(0, scale, (H, O)), "b3": rng.normal(0, 0.1, O)}
+
+
+def test_backward_matches_central_differences():
+    rng = np.random.default_rng(0)
+    p = _params(rng)
+    X = rng.uniform(-1, 1, (7, 12))
+    T = rng.uniform(0, 1, (7, 5))
+    M = (rng.uniform(0, 1, (7, 5)) < 0.7).astype(float)
+    M[:, -1] = 1.0
+
+    def loss(pp):
+        Y, _ = er.forward(pp, X, rounding=False)
+        return er.loss_and_grad_y(Y, T, M)[0]
+
+    Y, cache = er.forward(p, X, rounding=False)
+    _, dY = er.loss_and_grad_y(Y, T, M)
+    g = er.backward(cache, dY, round_like_gpu=False)
+    h = 1e-6
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        flat = p[name].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(12, flat.size), replace=False):
+            pp = {k: v.copy() for k, v in p.items()}
+            pp[name].reshape(-1)[idx] += h
+            lp = loss(pp)
+            pp[name].reshape(-1)[idx] -= 2 * h
+            lm = loss(pp)
+            fd = (lp - lm) / (2 * h)
+            assert abs(g[name].reshape(-1)[idx] - fd) < 1e-6 * max(1.0, abs(fd)), (name, idx)
+
+
+def test_adam_first_steps_closed_form():
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    m = np.zeros(3)
+    v = np.zeros(3)
+    lr = 0.01
+    q, m, v = er.adam_step(p, g, m, v, 1, lr, eps=0.0)
+    assert np.allclose(q, p - lr * np.sign(g))
+    # a constant gradient moves every coordinate by lr per step
+    for t in range(2, 6):
+        q, m, v = er.adam_step(q, g, m, v, t, lr, eps=0.0)
+    assert np.allclose(q, p - 5 * lr * np.sign(g))
+
+
+def test_histogram_boundaries_cdf_and_coverage():
+    s = np.arange(1600, dtype=np.float64)
+    b = er.boundaries(s)
+    assert b.tolist() == [100.0 * i for i in range(16)] + [1599.0]
+    for i in range(16):
+        assert er.hist_cdf(b, 100.0 * i) == i / 16
+    assert er.hist_cdf(b, -1) == 0.0 and er.hist_cdf(b, 1599) == 1.0
+    xs = np.linspace(-10, 1700, 500)
+    cdf = [er.hist_cdf(b, x) for x in xs]
+    assert all(a <= c for a, c in zip(cdf, cdf[1:]))
+    assert (er.coverage(b, 0, 1599) == 1).all()
+    assert (er.coverage(b, 2000, 3000) == 0).all()
+    c = er.coverage(b, 150, 349)
+    assert c[1] == 0.5 and c[2] == 1.0 and abs(c[3] - 0.49) < 1e-12 and c[4] == 0
+
+
+def test_features_unqueried_and_uniform_data():
+    rng = np.random.default_rng(1)
+    sample = np.sort(rng.uniform(0, 1, 16384))
+    b = np.stack([er.boundaries(sample)] * 3)
+    f = er.features((np.array([1]), np.array([0.25]), np.array([0.75])), b).reshape(3, 18)
+    assert (f[0, :2] == -1).all() and (f[0, 2:] == 1).all()
+    assert (f[2, :2] == -1).all()
+    assert abs(f[1, 0] - 0.25) < 0.02 and abs(f[1, 1] - 0.75) < 0.02
+    assert abs(f[1, 2:].sum() / 16 - 0.5) < 0.02
+
+
+def test_targets_and_qerror():
+    y, m = er.targets({2: 0.5, 0: 1e-9}, 1e-3, 4, 1000)
+    assert m.tolist() == [1, 0, 1, 0, 1]
+    assert abs(y[0] - 1.0) < 1e-12            # clamped at 1/N
+    assert abs(y[2] - math.log(2) / math.log(1000)) < 1e-12
+    assert abs(er.selectivity_from_output(y[4:5], 1000)[0] - 1e-3) < 1e-12
+    q = er.qerror([0.1, 0.01, 1e-9], [0.01, 0.1, 1e-12], 1000)
+    assert np.allclose(q, [10, 10, 1])
