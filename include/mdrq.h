@@ -235,6 +235,97 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
 int mdrq_probe_bandwidth(mdrq_dataset* ds, const uint32_t* dims, uint32_t k, uint32_t iters,
                          void* stream, double* ms);
 
+/* ---------------------------------------------------------------- learned estimator
+ *
+ * Evaluating the most selective dimension first lets the early break skip more rows,
+ * but needs selectivity estimates (paper section 2.2.4); learning them is left to
+ * future work (section 8).  An estimator holds, per column, an equi-depth histogram
+ * of MDRQ_EST_BINS bins built on the device from a strided sample, and a small
+ * network (features -> hidden -> hidden -> n_dims + 1, GELU) whose matrix products run
+ * on the matrix cores with bfloat16 operands and float32 accumulation, trained with
+ * Adam on float32 master weights.  Estimates only choose the order of evaluation
+ * (MDRQ_Q_ORDER_ESTIMATED) and reservations in serving: results never depend on them.
+ *
+ * Selectivities s are handled on the log scale y(s) = -ln(max(s, 1/N)) / ln N, s = N^-y.
+ * Features of a query (n_dims * (MDRQ_EST_BINS + 3) values, bfloat16): per dimension,
+ * the histogram CDF H at lo and at hi, the histogram estimate y(H(hi) - H(lo)) and the
+ * covered fraction of each bin; a dimension without a predicate (or with [-inf, +inf])
+ * gives (-1, -1, 0, 1, ..., 1).  The network's n_dims + 1 outputs correct a base
+ * estimate: the histogram estimate of each dimension's predicate alone and, last, of
+ * the whole query as the independence product min(1, sum of the per-dimension y)
+ * (section 2.1).  The output layer starts at zero, so an untrained estimator returns
+ * the base estimate.
+ *
+ * Selectivity arrays (sel) hold n_queries rows of n_dims + 1 floats: entry j < n_dims
+ * is the selectivity of the query's predicate on dimension j alone (-1 if the query
+ * has none there), the last entry the selectivity of the whole query.
+ * Parameters (get/set) are float32 in the order W1 [F x H], b1 [H], W2 [H x H], b2 [H],
+ * W3 [H x O], b3 [O] (row-major, F features, H hidden, O = n_dims + 1).
+ * Estimator calls run on the null stream and return when their results are on the
+ * host.  Free an estimator before its dataset.
+ */
+#define MDRQ_EST_BINS 16
+#define MDRQ_EST_MAX_QUERIES (1u << 22)  /* queries per estimator call */
+
+typedef struct mdrq_estimator mdrq_estimator;  /* opaque, owned by the library */
+
+typedef struct {
+  uint32_t hidden;       /* width of both hidden layers: multiple of 16 in 16..256; 0 = 64 */
+  uint32_t sample_rows;  /* rows sampled per column: 2..16384; 0 = min(16384, n_rows) */
+  uint64_t seed;         /* initial hidden weights (Glorot-uniform, counter-based generator) */
+} mdrq_estimator_config_t;
+
+typedef struct {
+  uint32_t epochs;       /* passes over the training queries, >= 1 */
+  uint32_t batch;        /* queries per Adam step: 1..65536 */
+  float lr;              /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+  uint32_t reserved;
+  uint64_t seed;         /* shuffling of each epoch */
+} mdrq_train_config_t;
+
+/* Build the histograms of every column of ds (a strided sample of sample_rows rows,
+ * sorted on the device) and initialise the network.
+ * Errors: MDRQ_EINVAL (NULL, bad config, empty dataset), MDRQ_ENOMEM, MDRQ_EDEVICE. */
+int mdrq_estimator_create(mdrq_dataset* ds, const mdrq_estimator_config_t* cfg,
+                          mdrq_estimator** out);
+/* Detach (if attached) and release. */
+void mdrq_estimator_free(mdrq_estimator* e);
+/* Histogram boundaries: n_dims rows of MDRQ_EST_BINS + 1 floats (host). */
+int mdrq_estimator_histograms(const mdrq_estimator* e, float* bounds);
+/* Features of n queries (1 .. MDRQ_EST_MAX_QUERIES) as bfloat16 bit patterns, n rows of
+ * n_dims * (MDRQ_EST_BINS + 3) (host).  Errors: as mdrq_query for each query. */
+int mdrq_estimator_features(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n,
+                            uint16_t* out);
+/* Number of float32 parameters; copy them out / in (set also clears Adam's moments). */
+int mdrq_estimator_param_count(const mdrq_estimator* e, uint64_t* count);
+int mdrq_estimator_get_params(const mdrq_estimator* e, float* out);
+int mdrq_estimator_set_params(mdrq_estimator* e, const float* in);
+
+/* Exact selectivities of n queries (training labels), measured with shared count-only
+ * scans: for each query, each predicate alone and the whole query.  sel: n rows of
+ * n_dims + 1 (host).  Errors: as mdrq_query_batch. */
+int mdrq_label_selectivities(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, float* sel);
+
+/* Loss (mean squared error of the outputs against the present targets y(s)) of the
+ * current parameters on n queries taken as one batch (n <= 65536), and its gradient
+ * with respect to the parameters (param_count floats, host).  Nothing is updated. */
+int mdrq_estimator_gradient(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n,
+                            const float* sel, float* loss, float* grad);
+
+/* Train on n labelled queries; epoch_loss (optional, epochs entries) receives the mean
+ * minibatch loss of each epoch.  Errors: MDRQ_EINVAL (bad config, query or label). */
+int mdrq_estimator_train(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n,
+                         const float* sel, const mdrq_train_config_t* cfg, float* epoch_loss);
+
+/* Estimated selectivities of n queries (same layout as sel; 1 for a dimension the
+ * query does not restrict). */
+int mdrq_estimator_predict(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, float* sel);
+
+/* Let queries flagged MDRQ_Q_ORDER_ESTIMATED on ds evaluate their predicates in order of
+ * ascending estimated selectivity (e = NULL detaches; such queries then keep the order
+ * given).  e must have been created on ds. */
+int mdrq_attach_estimator(mdrq_dataset* ds, mdrq_estimator* e);
+
 /* Library version as "major.minor.patch". */
 const char* mdrq_version(void);
 

@@ -14,14 +14,21 @@ work, section 8, and defines selectivity and the independence product, section 2
 * CDF of the histogram, piecewise linear: H(x) = (i + (x - b_i)/(b_{i+1} - b_i)) / B
   on [b_i, b_{i+1}), 0 below b_0, 1 from b_B on; an empty bin (b_i == b_{i+1})
   contributes a step.
-* Features of a query, per dimension j (B + 2 values): queried -> H_j(lo), H_j(hi)
-  and, per bin, the covered fraction |[lo,hi] & [b_i,b_{i+1}]| / (b_{i+1} - b_i)
-  (an empty bin counts as covered iff lo <= b_i <= hi); not queried -> (-1, -1) and
-  all bins covered.
-* Targets: y = -ln(max(s, 1/N)) / ln(N) in [0, 1] for each queried dimension's own
-  selectivity and for the joint selectivity.
-* Network: X -> GELU(X W1 + b1) -> GELU(H1 W2 + b2) -> H2 W3 + b3, GELU(z) =
-  z * Phi(z) (erf form).  Loss: mean of (y_hat - y)^2 over the targets present.
+* Log scale: y(s) = -ln(max(s, 1/N)) / ln(N) in [0, 1], so s = N^-y.
+* Coverage of bin i: |[lo,hi] & [b_i,b_{i+1}]| / (b_{i+1} - b_i) (an empty bin counts
+  as covered iff lo <= b_i <= hi).  Histogram estimate of a predicate: the mean
+  coverage over the bins (H(hi) - H(lo) for lo <= hi, without the cancellation).
+* Features of a query, per dimension j (B + 3 values): restricted -> H_j(lo), H_j(hi),
+  y(histogram estimate) and the B coverages; not restricted (no predicate, or the
+  interval [-inf, +inf]) -> (-1, -1, 0) and all bins covered.
+* Base estimate (d + 1 values): the histogram estimate of each restricted dimension
+  (0 elsewhere) and, last, min(1, their sum) -- the independence product of the
+  per-dimension estimates (section 2.1) on the log scale.
+* Targets: y(s) for each restricted dimension's own selectivity and for the joint
+  selectivity.
+* Network: a learned correction of the base estimate.  X -> GELU(X W1 + b1) ->
+  GELU(H1 W2 + b2) -> H2 W3 + b3 + base, GELU(z) = z * Phi(z) (erf form).  Loss: mean
+  of (y_hat - y)^2 over the targets present.
 * Adam (Kingma & Ba 2015) with bias correction.
 * q-error: max(s_hat / s, s / s_hat), both clamped to at least 1/N.
 """
@@ -77,20 +84,44 @@ def coverage(b: np.ndarray, lo: float, hi: float) -> np.ndarray:
     return out
 
 
-def features(query, bnds: np.ndarray) -> np.ndarray:
-    """bnds: (d, BINS + 1) boundaries; returns d * (BINS + 2) features."""
-    d, nb1 = bnds.shape
-    bins = nb1 - 1
-    f = np.zeros((d, bins + 2))
-    f[:, 0] = -1.0
-    f[:, 1] = -1.0
-    f[:, 2:] = 1.0
+def log_scale(s, n_rows: int):
+    return -math.log(max(s, 1.0 / n_rows)) / math.log(n_rows)
+
+
+def _restricted(query):
     for j, lo, hi in zip(*query):
         j, lo, hi = int(j), float(lo), float(hi)
+        if lo == -math.inf and hi == math.inf:
+            continue  # the partial-match interval restricts nothing (section 2.1)
+        yield j, lo, hi
+
+
+def features(query, bnds: np.ndarray, n_rows: int) -> np.ndarray:
+    """bnds: (d, BINS + 1) boundaries; returns d * (BINS + 3) features."""
+    d, nb1 = bnds.shape
+    bins = nb1 - 1
+    f = np.zeros((d, bins + 3))
+    f[:, 0] = -1.0
+    f[:, 1] = -1.0
+    f[:, 2] = 0.0
+    f[:, 3:] = 1.0
+    for j, lo, hi in _restricted(query):
         f[j, 0] = hist_cdf(bnds[j], lo)
         f[j, 1] = hist_cdf(bnds[j], hi)
-        f[j, 2:] = coverage(bnds[j], lo, hi)
+        f[j, 3:] = coverage(bnds[j], lo, hi)
+        f[j, 2] = log_scale(f[j, 3:].mean(), n_rows)
     return f.reshape(-1)
+
+
+def base(query, bnds: np.ndarray, n_rows: int) -> np.ndarray:
+    """Histogram estimates on the log scale: per restricted dimension, then the
+    independence product, min(1, sum)."""
+    d = bnds.shape[0]
+    out = np.zeros(d + 1)
+    for j, lo, hi in _restricted(query):
+        out[j] = log_scale(coverage(bnds[j], lo, hi).mean(), n_rows)
+    out[d] = min(1.0, out[:d].sum())
+    return out
 
 
 def targets(sel_dims: dict, sel_joint: float, d: int, n_rows: int):
@@ -133,8 +164,9 @@ def _erf(x):
     return np.vectorize(math.erf, otypes=[np.float64])(x)
 
 
-def forward(params: dict, X: np.ndarray, rounding: bool = True):
-    """params: W1 (K x H), b1, W2 (H x H), b2, W3 (H x O), b3 (float32 masters).
+def forward(params: dict, X: np.ndarray, base_y=None, rounding: bool = True):
+    """params: W1 (K x H), b1, W2 (H x H), b2, W3 (H x O), b3 (float32 masters);
+    base_y: (n, O) base estimates added to the output (None: zero).
     Matrix operands are rounded to bfloat16 as on the GPU (rounding=False: no rounding,
     for derivative checks); sums are exact (float64).  Returns (Y, cache)."""
     r = bf16_round if rounding else (lambda a: np.asarray(a, dtype=np.float64))
@@ -146,6 +178,8 @@ def forward(params: dict, X: np.ndarray, rounding: bool = True):
     Z2 = H1 @ W2 + b2
     H2 = r(gelu(Z2).astype(np.float32)) if rounding else gelu(Z2)
     Y = H2 @ W3 + b3
+    if base_y is not None:
+        Y = Y + np.asarray(base_y, dtype=np.float64)
     return Y, {"X": Xb, "W1": W1, "W2": W2, "W3": W3, "Z1": Z1, "H1": H1, "Z2": Z2, "H2": H2}
 
 

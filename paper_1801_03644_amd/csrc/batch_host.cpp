@@ -300,10 +300,19 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots) {
 // the rest into shared scans whose union of columns fits the register slots.
 int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs,
               hipStream_t stream) {
+  std::vector<float> est;  // estimated selectivities, for MDRQ_Q_ORDER_ESTIMATED
+  int erc = estimate_for_order(ds, qs, n, est);
+  if (erc) return erc;
+  auto plan_of = [&](uint32_t i) {
+    Plan plan = make_plan(ds, &qs[i], &rs[i]);
+    if (!est.empty() && (qs[i].flags & MDRQ_Q_ORDER_ESTIMATED))
+      order_plan(plan, &est[static_cast<size_t>(i) * (ds->n_dims + 1)]);
+    return plan;
+  };
   std::vector<Item> shared;
   std::vector<uint32_t> alone;
   for (uint32_t i = 0; i < n; ++i) {
-    Plan plan = make_plan(ds, &qs[i], &rs[i]);
+    Plan plan = plan_of(i);
     if (plan.empty || ds->n_rows == 0) {
       if (rs[i].mode == MDRQ_OUT_AUTO) {
         plan.mode = kIds;
@@ -373,7 +382,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     ds->batch_ms += ms;
   }
   for (uint32_t i : alone) {
-    Plan plan = make_plan(ds, &qs[i], &rs[i]);
+    Plan plan = plan_of(i);
     if (rs[i].mode == MDRQ_OUT_AUTO) {
       plan.mode = kIds;
       rs[i].mode = MDRQ_OUT_IDS;

@@ -1,0 +1,364 @@
+// Learned selectivity estimator: kernels for gfx950.
+//
+// A small MLP (features -> 64 -> 64 -> d+1, GELU) estimates the selectivity of each
+// queried dimension and of the whole query.  The paper notes that evaluating the most
+// selective dimension first needs selectivity estimates (section 2.2.4) and leaves it
+// as future work (section 8); the estimator only orders dimensions and sizes result
+// buffers, so results never depend on it.
+//
+// Kernels:
+//  * sample_sort_kernel: per column, a strided sample of up to 16384 rows sorted by a
+//    bitonic network in LDS; equi-depth boundaries are read off the sorted sample.
+//  * features_kernel: per (query, dimension) the histogram CDF of both bounds and the
+//    covered fraction of each bin, written as bfloat16 rows.
+//  * gemm_bf16_kernel: C = A * B with bfloat16 operands and float32 accumulation on the
+//    matrix cores (v_mfma_f32_16x16x16_bf16); one wave per 16x16 tile of C, operands
+//    read through strides so that transposed products need no copies.
+//  * small elementwise kernels: bias + GELU (and its derivative), the masked squared
+//    loss and its gradient, column sums (bias gradients), Adam, float32 -> bfloat16.
+#include <hip/hip_bfloat16.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "mdrq_internal.h"
+
+namespace mdrq {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// float32 -> bfloat16 bits, round to nearest, ties to even (inputs are finite).
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float z) {
+  const float phi = 0.3989422804014327f * expf(-0.5f * z * z);
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * phi;
+}
+
+// ---------------------------------------------------------------- histograms
+
+constexpr int kSortThreads = 1024;
+
+__global__ void __launch_bounds__(kSortThreads) sample_sort_kernel(HistArgs a) {
+  __shared__ float s[kSampleMax];
+  const uint32_t j = blockIdx.x;
+  const float* col = a.cols[j];
+  const uint32_t m = a.m;          // sample size (<= kSampleMax)
+  const uint32_t p2 = a.m_pow2;    // power of two >= m
+  for (uint32_t i = threadIdx.x; i < p2; i += kSortThreads) {
+    if (i < m) {
+      const uint64_t row = static_cast<uint64_t>(i) * a.n_rows / m;
+      s[i] = col[row];
+    } else {
+      s[i] = INFINITY;
+    }
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= p2; k <<= 1) {
+    for (uint32_t h = k >> 1; h > 0; h >>= 1) {
+      for (uint32_t i = threadIdx.x; i < p2; i += kSortThreads) {
+        const uint32_t o = i ^ h;
+        if (o > i) {
+          const bool up = (i & k) == 0;
+          const float x = s[i], y = s[o];
+          if ((x > y) == up) {
+            s[i] = y;
+            s[o] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x <= kBins) {
+    const uint32_t b = threadIdx.x;
+    const uint32_t idx = b < kBins ? (b * m) / kBins : m - 1;
+    a.bounds[j * (kBins + 1) + b] = s[idx];
+  }
+}
+
+// ---------------------------------------------------------------- features
+
+__device__ float hist_cdf(const float* b, float x) {
+  if (x < b[0]) return 0.0f;
+  if (x >= b[kBins]) return 1.0f;
+  for (int i = 0; i < kBins; ++i)
+    if (b[i] <= x && x < b[i + 1]) return (static_cast<float>(i) + (x - b[i]) / (b[i + 1] - b[i])) / kBins;
+  return 1.0f;
+}
+
+// Log scale of a selectivity: -ln(max(s, 1/N)) / ln N.
+__device__ __forceinline__ float log_scale(float s, float inv_rows, float inv_ln_rows) {
+  return -logf(s > inv_rows ? s : inv_rows) * inv_ln_rows;
+}
+
+// One thread per (query, dimension); qd holds (lo, hi, restricted) per (query, dimension).
+__global__ void features_kernel(FeatureArgs f) {
+  const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<uint64_t>(f.n) * f.d) return;
+  const float* qd = f.qd + t * 3;
+  uint16_t* row = f.x + t * kFeatPerDim;
+  const uint32_t j = static_cast<uint32_t>(t % f.d);
+  const uint64_t q = t / f.d;
+  const float* b = f.bounds + j * (kBins + 1);
+  float* base = f.base + q * (f.d + 1) + j;
+  if (qd[2] == 0.0f) {
+    row[0] = to_bf16(-1.0f);
+    row[1] = to_bf16(-1.0f);
+    row[2] = 0;
+    for (int i = 0; i < kBins; ++i) row[3 + i] = to_bf16(1.0f);
+    *base = 0.0f;
+    return;
+  }
+  const float lo = qd[0], hi = qd[1];
+  row[0] = to_bf16(hist_cdf(b, lo));
+  row[1] = to_bf16(hist_cdf(b, hi));
+  float sum = 0.0f;
+  for (int i = 0; i < kBins; ++i) {
+    const float a0 = b[i], a1 = b[i + 1];
+    float c;
+    if (a1 > a0) {
+      const float top = hi < a1 ? hi : a1;
+      const float bot = lo > a0 ? lo : a0;
+      c = top > bot ? (top - bot) / (a1 - a0) : 0.0f;
+    } else {
+      c = (lo <= a0 && a0 <= hi) ? 1.0f : 0.0f;
+    }
+    row[3 + i] = to_bf16(c);
+    sum += c;
+  }
+  // Histogram estimate: the mean coverage (H(hi) - H(lo) without the cancellation).
+  const float y = log_scale(sum * (1.0f / kBins), f.inv_rows, f.inv_ln_rows);
+  row[2] = to_bf16(y);
+  *base = y;
+}
+
+// Joint base estimate of each query: min(1, sum of its per-dimension estimates), the
+// independence product on the log scale.
+__global__ void base_joint_kernel(float* base, uint32_t n, uint32_t d) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  float* row = base + static_cast<uint64_t>(q) * (d + 1);
+  float s = 0.0f;
+  for (uint32_t j = 0; j < d; ++j) s += row[j];
+  row[d] = s < 1.0f ? s : 1.0f;
+}
+
+// ---------------------------------------------------------------- matrix products
+
+// C[m][n] = sum_k A(m, k) * B(k, n) (+ bias[n]) (+ add[m][n]); A(m,k) = a[m*a_m + k*a_k] and
+// B(k,n) = b[k*b_k + n*b_n] are bfloat16, out of range reads are zero.  One wave
+// computes a 16x16 tile of C with 16x16x16 matrix-core steps.
+__global__ void __launch_bounds__(64) gemm_bf16_kernel(GemmArgs g) {
+  const uint32_t lane = threadIdx.x;
+  const uint32_t m0 = blockIdx.y * 16, n0 = blockIdx.x * 16;
+  const uint32_t r = lane % 16;        // row of A / column of B and C held by this lane
+  const uint32_t kq = (lane / 16) * 4; // first of the 4 k values held by this lane
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (uint32_t k0 = 0; k0 < g.K; k0 += 16) {
+    bf16x4 av, bv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t k = k0 + kq + i;
+      const uint32_t am = m0 + r, bn = n0 + r;
+      av[i] = (am < g.M && k < g.K)
+                  ? static_cast<short>(g.a[static_cast<uint64_t>(am) * g.a_m + static_cast<uint64_t>(k) * g.a_k])
+                  : static_cast<short>(0);
+      bv[i] = (bn < g.N && k < g.K)
+                  ? static_cast<short>(g.b[static_cast<uint64_t>(k) * g.b_k + static_cast<uint64_t>(bn) * g.b_n])
+                  : static_cast<short>(0);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+  }
+  // acc[i] holds C[m0 + 4*(lane/16) + i][n0 + lane%16].
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t m = m0 + kq + i, n = n0 + r;
+    if (m < g.M && n < g.N) {
+      const uint64_t o = static_cast<uint64_t>(m) * g.c_ld + n;
+      float v = acc[i] + (g.bias ? g.bias[n] : 0.0f);
+      if (g.add) v += g.add[o];
+      if (g.c) g.c[o] = v;
+      if (g.act) g.act[o] = to_bf16(g.gelu ? gelu(v) : v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- elementwise
+
+// dY = 2 * mask * (Y - T) / count (float32, and bfloat16 for the products); the
+// loss of the batch is accumulated into *loss.
+__global__ void loss_grad_kernel(LossArgs l) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<uint64_t>(l.rows) * l.cols) return;
+  const float d = (l.y[i] - l.t[i]) * l.mask[i];
+  const float g = 2.0f * d * l.inv_count;
+  if (d != 0.0f) atomicAdd(l.loss, d * d * l.inv_count);
+  l.dy[i] = g;
+  l.dyb[i] = to_bf16(g);
+}
+
+// dZ = dH * gelu'(Z) (float32, and bfloat16 for the products).
+__global__ void gelu_back_kernel(const float* dh, const float* z, float* dz, uint16_t* dzb,
+                                 uint64_t n) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float v = dh[i] * gelu_grad(z[i]);
+  dz[i] = v;
+  dzb[i] = to_bf16(v);
+}
+
+// out[c] = sum over rows r of in[r][c] (bias gradients); one thread per column.
+__global__ void colsum_kernel(const float* in, uint32_t rows, uint32_t cols, float* out) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.0f;
+  for (uint32_t r = 0; r < rows; ++r) s += in[static_cast<uint64_t>(r) * cols + c];
+  out[c] = s;
+}
+
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, uint64_t n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void to_bf16_kernel(const float* src, uint64_t n, uint16_t* dst) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = to_bf16(src[i]);
+}
+
+// Training targets: y = -ln(max(s, 1/N)) / ln N where a selectivity is given (s >= 0),
+// mask 1 there and 0 elsewhere.
+__global__ void targets_kernel(const float* sel, uint64_t n, float inv_rows, float inv_ln_rows,
+                               float* t, float* mask) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float s = sel[i];
+  const bool present = s >= 0.0f;
+  t[i] = present ? -logf(s > inv_rows ? s : inv_rows) * inv_ln_rows : 0.0f;
+  mask[i] = present ? 1.0f : 0.0f;
+}
+
+// Estimates from network outputs: s = N^-clamp(y, 0, 1); 1 for a dimension the query
+// does not restrict.
+__global__ void to_selectivity_kernel(const float* y, const float* qd, uint32_t n, uint32_t d,
+                                      float ln_rows, float* sel) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint32_t o = d + 1;
+  if (i >= static_cast<uint64_t>(n) * o) return;
+  const uint64_t q = i / o;
+  const uint32_t j = static_cast<uint32_t>(i % o);
+  if (j < d && qd[(q * d + j) * 3 + 2] == 0.0f) {
+    sel[i] = 1.0f;
+    return;
+  }
+  const float v = fminf(fmaxf(y[i], 0.0f), 1.0f);
+  sel[i] = expf(-v * ln_rows);
+}
+
+// Gather rows of training data: dst[i] = src[idx[i]] for row-major rows of `width`
+// elements of `elem` bytes (elem 2 or 4).
+__global__ void gather_rows_kernel(const uint8_t* src, const uint32_t* idx, uint32_t n,
+                                   uint32_t row_bytes, uint8_t* dst) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint64_t words = row_bytes / 4;
+  if (i >= static_cast<uint64_t>(n) * words) return;
+  const uint64_t r = i / words, w = i % words;
+  reinterpret_cast<uint32_t*>(dst)[i] =
+      reinterpret_cast<const uint32_t*>(src)[static_cast<uint64_t>(idx[r]) * words + w];
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t t) { return static_cast<uint32_t>((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_sample_sort(const HistArgs& a, uint32_t n_cols, hipStream_t s) {
+  sample_sort_kernel<<<n_cols, kSortThreads, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_features(const FeatureArgs& f, hipStream_t s) {
+  const uint64_t n = static_cast<uint64_t>(f.n) * f.d;
+  if (n == 0) return hipSuccess;
+  features_kernel<<<blocks_for(n, 256), 256, 0, s>>>(f);
+  base_joint_kernel<<<blocks_for(f.n, 256), 256, 0, s>>>(f.base, f.n, f.d);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
+  if (g.M == 0 || g.N == 0) return hipSuccess;
+  gemm_bf16_kernel<<<dim3((g.N + 15) / 16, (g.M + 15) / 16), 64, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_grad(const LossArgs& l, hipStream_t s) {
+  loss_grad_kernel<<<blocks_for(static_cast<uint64_t>(l.rows) * l.cols, 256), 256, 0, s>>>(l);
+  return hipGetLastError();
+}
+
+hipError_t launch_gelu_back(const float* dh, const float* z, float* dz, uint16_t* dzb, uint64_t n,
+                            hipStream_t s) {
+  gelu_back_kernel<<<blocks_for(n, 256), 256, 0, s>>>(dh, z, dz, dzb, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* in, uint32_t rows, uint32_t cols, float* out, hipStream_t s) {
+  colsum_kernel<<<blocks_for(cols, 64), 64, 0, s>>>(in, rows, cols, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, uint64_t n, float lr,
+                       int step, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.0f - powf(b1, static_cast<float>(step));
+  const float c2 = 1.0f - powf(b2, static_cast<float>(step));
+  adam_kernel<<<blocks_for(n, 256), 256, 0, s>>>(p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float* src, uint64_t n, uint16_t* dst, hipStream_t s) {
+  to_bf16_kernel<<<blocks_for(n, 256), 256, 0, s>>>(src, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_targets(const float* sel, uint32_t n, uint32_t o, uint64_t n_rows, float* t,
+                          float* mask, hipStream_t s) {
+  const uint64_t total = static_cast<uint64_t>(n) * o;
+  const double rows = static_cast<double>(n_rows);
+  targets_kernel<<<blocks_for(total, 256), 256, 0, s>>>(
+      sel, total, static_cast<float>(1.0 / rows), static_cast<float>(1.0 / std::log(rows)), t, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_selectivity(const float* y, const float* qd, uint32_t n, uint32_t d,
+                                 uint64_t n_rows, float* sel, hipStream_t s) {
+  const uint64_t total = static_cast<uint64_t>(n) * (d + 1);
+  to_selectivity_kernel<<<blocks_for(total, 256), 256, 0, s>>>(
+      y, qd, n, d, static_cast<float>(std::log(static_cast<double>(n_rows))), sel);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const void* src, const uint32_t* idx, uint32_t n, uint32_t row_bytes,
+                              void* dst, hipStream_t s) {
+  const uint64_t words = static_cast<uint64_t>(n) * (row_bytes / 4);
+  if (words == 0) return hipSuccess;
+  gather_rows_kernel<<<blocks_for(words, 256), 256, 0, s>>>(
+      static_cast<const uint8_t*>(src), idx, n, row_bytes, static_cast<uint8_t*>(dst));
+  return hipGetLastError();
+}
+
+}  // namespace mdrq

@@ -128,6 +128,74 @@ hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int 
                              size_t lds_bytes, hipStream_t stream);
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream);
 
+// ---------------------------------------------------------------- learned estimator
+
+constexpr int kBins = MDRQ_EST_BINS;
+constexpr int kFeatPerDim = kBins + 3;  // H(lo), H(hi), histogram estimate, bins
+constexpr uint32_t kSampleMax = 16384;   // sample rows sorted in LDS per column
+
+struct HistArgs {
+  uint64_t n_rows;
+  uint32_t m;                  // sample size
+  uint32_t m_pow2;             // power of two >= m (sorting network width)
+  float* bounds;               // [column][kBins + 1]
+  const float* cols[MDRQ_MAX_DIMS];
+};
+
+struct FeatureArgs {
+  const float* qd;             // [query][dim] (lo, hi, restricted)
+  const float* bounds;         // [dim][kBins + 1]
+  uint16_t* x;                 // [query][dim * kFeatPerDim] bfloat16 bits
+  float* base;                 // [query][dim + 1] histogram estimates (log scale)
+  uint32_t n, d;
+  float inv_rows;              // 1 / N
+  float inv_ln_rows;           // 1 / ln N
+};
+
+// C = A * B (+ bias) with bfloat16 operands read through element strides.
+struct GemmArgs {
+  const uint16_t* a;
+  const uint16_t* b;
+  uint64_t a_m, a_k, b_k, b_n;
+  uint32_t M, N, K;
+  uint32_t c_ld;
+  const float* bias;           // [N] or null
+  const float* add;            // [M][c_ld] added to the result, or null
+  float* c;                    // float32 result or null
+  uint16_t* act;               // bfloat16 of the result (GELU applied if gelu) or null
+  uint32_t gelu;
+  uint32_t pad;
+};
+
+struct LossArgs {
+  const float* y;              // [rows][cols] network output
+  const float* t;              // targets
+  const float* mask;           // 1 where a target is present
+  float* dy;                   // gradient of the loss
+  uint16_t* dyb;               // the same in bfloat16
+  float* loss;                 // += loss of this batch
+  uint32_t rows, cols;
+  float inv_count;             // 1 / present targets in the batch
+  uint32_t pad;
+};
+
+hipError_t launch_sample_sort(const HistArgs& a, uint32_t n_cols, hipStream_t s);
+hipError_t launch_features(const FeatureArgs& f, hipStream_t s);
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
+hipError_t launch_loss_grad(const LossArgs& l, hipStream_t s);
+hipError_t launch_gelu_back(const float* dh, const float* z, float* dz, uint16_t* dzb, uint64_t n,
+                            hipStream_t s);
+hipError_t launch_colsum(const float* in, uint32_t rows, uint32_t cols, float* out, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, uint64_t n, float lr, int step,
+                       hipStream_t s);
+hipError_t launch_to_bf16(const float* src, uint64_t n, uint16_t* dst, hipStream_t s);
+hipError_t launch_gather_rows(const void* src, const uint32_t* idx, uint32_t n, uint32_t row_bytes,
+                              void* dst, hipStream_t s);
+hipError_t launch_targets(const float* sel, uint32_t n, uint32_t o, uint64_t n_rows, float* t,
+                          float* mask, hipStream_t s);
+hipError_t launch_to_selectivity(const float* y, const float* qd, uint32_t n, uint32_t d,
+                                 uint64_t n_rows, float* sel, hipStream_t s);
+
 // Load-time validation: NaN count and per-column min/max (order-preserving keys).
 struct ColumnStats {
   uint32_t nan_count;
@@ -173,6 +241,16 @@ Plan make_plan(const mdrq_dataset* ds, const mdrq_query_t* q, const mdrq_result_
 uint64_t n_words(const mdrq_dataset* ds);
 int finish_empty(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream);
 int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream);
+}  // namespace mdrq
+
+namespace mdrq {
+// Estimator hooks (estimator_host.cpp): estimated selectivities of the queries that
+// ask for estimated order (rows of n_dims + 1; empty if no estimator is attached),
+// and the reordering of a plan by them.
+int estimate_for_order(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n,
+                       std::vector<float>& est);
+void order_plan(Plan& plan, const float* est_row);
+void detach_estimator(mdrq_dataset* ds);
 }  // namespace mdrq
 
 namespace mdrq {
@@ -248,6 +326,8 @@ struct mdrq_dataset {
   std::vector<std::pair<uint64_t, mdrq::BatchConfig>> tuned;  // shape key -> config
   uint64_t batch_launches = 0;
   double batch_ms = 0.0;
+
+  mdrq_estimator* estimator = nullptr;   // attached estimator (MDRQ_Q_ORDER_ESTIMATED)
 
   int64_t grid = 0;                      // workgroups per launch (0 = blocks_per_cu per CU)
   int blocks_per_cu = 3;                 // default launch width, capped by occupancy

@@ -389,6 +389,12 @@ int mdrq_query(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r, void* 
   if (rc) return rc;
   std::lock_guard<std::mutex> lock(ds->mu);
   Plan plan = make_plan(ds, q, r);
+  if (q->flags & MDRQ_Q_ORDER_ESTIMATED) {
+    std::vector<float> est;
+    rc = estimate_for_order(ds, q, 1, est);
+    if (rc) return rc;
+    if (!est.empty()) order_plan(plan, est.data());
+  }
   r->mode = plan.mode == kBitmap ? MDRQ_OUT_BITMAP : plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
   return run_query(ds, plan, r, static_cast<hipStream_t>(stream));
 }

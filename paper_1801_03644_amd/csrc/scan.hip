@@ -37,11 +37,6 @@ namespace {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
-__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
-                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
-}
-
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return __popcll(m); }
 
 // Bit e of the result <=> lo <= element e <= hi.

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -27,7 +28,13 @@ _MODE_NAMES = {v: k for k, v in _MODES.items()}
 EXPORTS = ["mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve", "mdrq_free",
            "mdrq_last_error", "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
            "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth",
-           "mdrq_get_batch_profile", "mdrq_version"]
+           "mdrq_get_batch_profile", "mdrq_version",
+           "mdrq_estimator_create", "mdrq_estimator_free", "mdrq_estimator_histograms",
+           "mdrq_estimator_features", "mdrq_estimator_param_count", "mdrq_estimator_get_params",
+           "mdrq_estimator_set_params", "mdrq_label_selectivities", "mdrq_estimator_gradient",
+           "mdrq_estimator_train", "mdrq_estimator_predict", "mdrq_attach_estimator"]
+EST_BINS = 16
+EST_FEATS = EST_BINS + 3  # per dimension: H(lo), H(hi), histogram estimate, bins
 OPT_UNROLL, OPT_GRID, OPT_BLOCKS_PER_CU = 1, 2, 3
 OPT_BATCH_WAVES, OPT_BATCH_GROUP, OPT_AUTOTUNE, OPT_BATCH_ROWS = 4, 5, 6, 7
 
@@ -58,6 +65,16 @@ class ServeConfig(ctypes.Structure):
     _fields_ = [("result_budget_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32),
                 ("n_streams", ctypes.c_uint32), ("use_estimator", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32)]
+
+
+class EstimatorConfig(ctypes.Structure):
+    _fields_ = [("hidden", ctypes.c_uint32), ("sample_rows", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
+
+
+class TrainConfig(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
 
 
 class Request(ctypes.Structure):
@@ -120,10 +137,27 @@ def load_library(path: str = LIB_PATH):
     lib.mdrq_set_option.argtypes = [vp, u32, ctypes.c_int64]
     lib.mdrq_probe_bandwidth.argtypes = [vp, P(u32), u32, u32, vp, P(ctypes.c_double)]
     lib.mdrq_get_batch_profile.argtypes = [vp, P(u64), P(ctypes.c_double)]
+    fp, u16p = P(ctypes.c_float), P(ctypes.c_uint16)
+    lib.mdrq_estimator_create.argtypes = [vp, P(EstimatorConfig), P(vp)]
+    lib.mdrq_estimator_free.argtypes = [vp]
+    lib.mdrq_estimator_free.restype = None
+    lib.mdrq_estimator_histograms.argtypes = [vp, fp]
+    lib.mdrq_estimator_features.argtypes = [vp, P(Query), u32, u16p]
+    lib.mdrq_estimator_param_count.argtypes = [vp, P(u64)]
+    lib.mdrq_estimator_get_params.argtypes = [vp, fp]
+    lib.mdrq_estimator_set_params.argtypes = [vp, fp]
+    lib.mdrq_label_selectivities.argtypes = [vp, P(Query), u32, fp]
+    lib.mdrq_estimator_gradient.argtypes = [vp, P(Query), u32, fp, fp, fp]
+    lib.mdrq_estimator_train.argtypes = [vp, P(Query), u32, fp, P(TrainConfig), fp]
+    lib.mdrq_estimator_predict.argtypes = [vp, P(Query), u32, fp]
+    lib.mdrq_attach_estimator.argtypes = [vp, vp]
     for f in ("mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve",
               "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
               "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth",
-              "mdrq_get_batch_profile"):
+              "mdrq_get_batch_profile", "mdrq_estimator_create", "mdrq_estimator_histograms",
+              "mdrq_estimator_features", "mdrq_estimator_param_count", "mdrq_estimator_get_params",
+              "mdrq_estimator_set_params", "mdrq_label_selectivities", "mdrq_estimator_gradient",
+              "mdrq_estimator_train", "mdrq_estimator_predict", "mdrq_attach_estimator"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -194,6 +228,7 @@ class Dataset:
         self.n_rows = n_rows
         self.n_dims = n_dims
         self._keep = keepalive
+        self._estimators = weakref.WeakSet()  # released before the dataset
 
     @classmethod
     def from_host(cls, cols, stream=None) -> "Dataset":
@@ -229,6 +264,8 @@ class Dataset:
 
     def close(self):
         if self._h and self._h.value:
+            for est in list(self._estimators):
+                est.close()
             load_library().mdrq_free(self._h)
             self._h = ctypes.c_void_p()
             self._keep = None
@@ -269,12 +306,7 @@ class Dataset:
         n = len(queries)
         outs = outs if outs is not None else [None] * n
         modes = [modes] * n if isinstance(modes, str) else list(modes)
-        qarr = (Query * max(1, n))()
-        keep = []
-        for i, qq in enumerate(queries):
-            q, k = make_query(qq, flags)
-            qarr[i] = q
-            keep.append(k)
+        qarr, keep = _query_array(queries, flags)
         rarr = (Result * max(1, n))(*[_result_for(o, m) for o, m in zip(outs, modes)])
         rc = lib.mdrq_query_batch(self._h, qarr, n, rarr, _stream_handle(stream))
         _check(rc, (OK, EOVERFLOW))
@@ -309,6 +341,137 @@ class Dataset:
 
     def reset_profile(self):
         _check(load_library().mdrq_reset_profile(self._h))
+
+    def label_selectivities(self, queries) -> np.ndarray:
+        """Exact selectivities (n, n_dims + 1): each predicate alone, then the query;
+        -1 where a query does not restrict a dimension."""
+        qarr, keep = _query_array(queries, 0)
+        out = np.empty((len(queries), self.n_dims + 1), dtype=np.float32)
+        _check(load_library().mdrq_label_selectivities(self._h, qarr, len(queries), _fptr(out)))
+        return out
+
+    def attach_estimator(self, est):
+        """Order MDRQ_Q_ORDER_ESTIMATED queries by `est` (None detaches)."""
+        _check(load_library().mdrq_attach_estimator(self._h, est.handle if est else None))
+
+
+def _query_array(queries, flags: int):
+    qarr = (Query * max(1, len(queries)))()
+    keep = []
+    for i, qq in enumerate(queries):
+        q, k = make_query(qq, flags)
+        qarr[i] = q
+        keep.append(k)
+    return qarr, keep
+
+
+def _fptr(a: np.ndarray):
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Estimator:
+    """Learned selectivity estimator of a dataset (histograms + MLP on the GPU)."""
+
+    def __init__(self, ds: Dataset, hidden: int = 64, sample_rows: int = 0, seed: int = 0):
+        cfg = EstimatorConfig(hidden, sample_rows, seed)
+        h = ctypes.c_void_p()
+        _check(load_library().mdrq_estimator_create(ds.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.ds = ds
+        ds._estimators.add(self)
+        self.n_dims = ds.n_dims
+        self.hidden = hidden or 64
+        n = ctypes.c_uint64()
+        _check(load_library().mdrq_estimator_param_count(self._h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h and self._h.value:
+            load_library().mdrq_estimator_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def histograms(self) -> np.ndarray:
+        out = np.empty((self.n_dims, EST_BINS + 1), dtype=np.float32)
+        _check(load_library().mdrq_estimator_histograms(self._h, _fptr(out)))
+        return out
+
+    def features(self, queries) -> np.ndarray:
+        """bfloat16 bit patterns (n, n_dims * EST_FEATS) as uint16."""
+        qarr, keep = _query_array(queries, 0)
+        out = np.empty((len(queries), self.n_dims * EST_FEATS), dtype=np.uint16)
+        _check(load_library().mdrq_estimator_features(
+            self._h, qarr, len(queries), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))))
+        return out
+
+    def _shapes(self):
+        F, H, O = self.n_dims * EST_FEATS, self.hidden, self.n_dims + 1
+        return [("W1", (F, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (H, O)),
+                ("b3", (O,))]
+
+    def unpack(self, flat: np.ndarray) -> dict:
+        out, at = {}, 0
+        for name, shape in self._shapes():
+            n = int(np.prod(shape))
+            out[name] = flat[at:at + n].reshape(shape)
+            at += n
+        return out
+
+    def pack(self, params: dict) -> np.ndarray:
+        return np.concatenate([np.asarray(params[name], dtype=np.float32).reshape(-1)
+                               for name, _ in self._shapes()])
+
+    def get_params(self) -> dict:
+        flat = np.empty(self.n_params, dtype=np.float32)
+        _check(load_library().mdrq_estimator_get_params(self._h, _fptr(flat)))
+        return self.unpack(flat)
+
+    def set_params(self, params: dict):
+        flat = np.ascontiguousarray(self.pack(params))
+        _check(load_library().mdrq_estimator_set_params(self._h, _fptr(flat)))
+
+    def gradient(self, queries, sel):
+        """(loss, gradient dict) of the current parameters on one batch."""
+        qarr, keep = _query_array(queries, 0)
+        sel = np.ascontiguousarray(sel, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        grad = np.empty(self.n_params, dtype=np.float32)
+        _check(load_library().mdrq_estimator_gradient(self._h, qarr, len(queries), _fptr(sel),
+                                                      _fptr(loss), _fptr(grad)))
+        return float(loss[0]), self.unpack(grad)
+
+    def train(self, queries, sel, epochs: int = 10, batch: int = 256, lr: float = 1e-3,
+              seed: int = 0) -> np.ndarray:
+        """Adam on the labelled queries; returns the mean loss of each epoch."""
+        qarr, keep = _query_array(queries, 0)
+        sel = np.ascontiguousarray(sel, dtype=np.float32)
+        cfg = TrainConfig(epochs, batch, lr, 0, seed)
+        losses = np.zeros(epochs, dtype=np.float32)
+        _check(load_library().mdrq_estimator_train(self._h, qarr, len(queries), _fptr(sel),
+                                                    ctypes.byref(cfg), _fptr(losses)))
+        return losses
+
+    def predict(self, queries) -> np.ndarray:
+        qarr, keep = _query_array(queries, 0)
+        out = np.empty((len(queries), self.n_dims + 1), dtype=np.float32)
+        _check(load_library().mdrq_estimator_predict(self._h, qarr, len(queries), _fptr(out)))
+        return out
 
 
 def version() -> str:

@@ -68,6 +68,28 @@ def test_calls_on_null_dataset_are_rejected():
     lib.mdrq_free(None)
 
 
+def test_estimator_calls_reject_null_arguments():
+    lib = mdrq.load_library()
+    q, keep = mdrq.make_query([(0, 0.0, 1.0)])
+    f = (ctypes.c_float * 8)()
+    n = ctypes.c_uint64()
+    h = ctypes.c_void_p()
+    cfg = mdrq.EstimatorConfig(64, 0, 0)
+    tc = mdrq.TrainConfig(1, 16, 1e-3, 0, 0)
+    assert lib.mdrq_estimator_create(None, ctypes.byref(cfg), ctypes.byref(h)) == mdrq.EINVAL
+    assert lib.mdrq_estimator_histograms(None, f) == mdrq.EINVAL
+    assert lib.mdrq_estimator_features(None, ctypes.byref(q), 1, None) == mdrq.EINVAL
+    assert lib.mdrq_estimator_param_count(None, ctypes.byref(n)) == mdrq.EINVAL
+    assert lib.mdrq_estimator_get_params(None, f) == mdrq.EINVAL
+    assert lib.mdrq_estimator_set_params(None, f) == mdrq.EINVAL
+    assert lib.mdrq_label_selectivities(None, ctypes.byref(q), 1, f) == mdrq.EINVAL
+    assert lib.mdrq_estimator_gradient(None, ctypes.byref(q), 1, f, f, f) == mdrq.EINVAL
+    assert lib.mdrq_estimator_train(None, ctypes.byref(q), 1, f, ctypes.byref(tc), f) == mdrq.EINVAL
+    assert lib.mdrq_estimator_predict(None, ctypes.byref(q), 1, f) == mdrq.EINVAL
+    assert lib.mdrq_attach_estimator(None, None) == mdrq.EINVAL
+    lib.mdrq_estimator_free(None)
+
+
 def test_error_message_is_thread_local():
     import threading
 

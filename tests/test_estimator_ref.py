@@ -108,11 +108,43 @@ def test_features_unqueried_and_uniform_data():
     rng = np.random.default_rng(1)
     sample = np.sort(rng.uniform(0, 1, 16384))
     b = np.stack([er.boundaries(sample)] * 3)
-    f = er.features((np.array([1]), np.array([0.25]), np.array([0.75])), b).reshape(3, 18)
-    assert (f[0, :2] == -1).all() and (f[0, 2:] == 1).all()
+    N = 10**6
+    f = er.features((np.array([1]), np.array([0.25]), np.array([0.75])), b, N).reshape(3, 19)
+    assert (f[0, :2] == -1).all() and f[0, 2] == 0 and (f[0, 3:] == 1).all()
     assert (f[2, :2] == -1).all()
     assert abs(f[1, 0] - 0.25) < 0.02 and abs(f[1, 1] - 0.75) < 0.02
-    assert abs(f[1, 2:].sum() / 16 - 0.5) < 0.02
+    assert abs(f[1, 2] - math.log(2) / math.log(N)) < 0.01
+    assert abs(f[1, 3:].sum() / 16 - 0.5) < 0.02
+    # the partial-match interval [-inf, +inf] restricts nothing: same as no predicate
+    g = er.features((np.array([0, 1]), np.array([-np.inf, 0.25]), np.array([np.inf, 0.75])), b, N)
+    assert np.array_equal(g, f.reshape(-1))
+    # an empty interval (lo > hi) covers nothing, has H(lo) > H(hi) and the smallest
+    # representable selectivity 1/N
+    e = er.features((np.array([2]), np.array([0.6]), np.array([0.4])), b, N).reshape(3, 19)
+    assert e[2, 0] > e[2, 1] and (e[2, 3:] == 0).all() and e[2, 2] == 1.0
+
+
+def test_base_is_the_independence_product():
+    """N^-base[d] is the product of the per-dimension histogram selectivities (section
+    2.1's independence assumption), until it reaches the floor 1/N."""
+    s = np.arange(1600, dtype=np.float64)
+    b = np.stack([er.boundaries(s)] * 4)
+    N = 10**7
+    q = (np.array([0, 2, 3]), np.array([0.0, 100.0, 800.0]), np.array([400.0, 900.0, 1200.0]))
+    base = er.base(q, b, N)
+    per = [400 / 1600, 800 / 1600, 400 / 1600]  # exact on this grid of boundaries
+    assert np.allclose(er.selectivity_from_output(base[[0, 2, 3]], N), per, rtol=1e-12)
+    assert base[1] == 0
+    assert abs(er.selectivity_from_output(base[4:], N)[0] - np.prod(per)) < 1e-15
+    tiny = (np.array([0, 1, 2]), np.array([0.0] * 3), np.array([1.0] * 3))
+    assert er.base(tiny, b, N)[4] == 1.0  # (1/1600)^3 < 1/N: clamped
+    # the base shifts the network output one to one
+    rng = np.random.default_rng(2)
+    p = _params(rng, K=4 * 19, O=5)
+    X = rng.uniform(-1, 1, (3, 4 * 19))
+    Y0, _ = er.forward(p, X, rounding=False)
+    Y1, _ = er.forward(p, X, np.stack([base] * 3), rounding=False)
+    assert np.allclose(Y1 - Y0, base, atol=1e-15)
 
 
 def test_targets_and_qerror():

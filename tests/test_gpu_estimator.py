@@ -1,0 +1,307 @@
+"""GPU parity of the learned selectivity estimator against the CPU reference.
+
+Histograms are exact (a sort); features are bfloat16 roundings of the same fractions
+(at most one bfloat16 unit apart when float32 and float64 land on opposite sides of a
+rounding midpoint); network outputs, losses and gradients use bfloat16 operands with
+float32 accumulation on the GPU and float64 sums of the same bfloat16 operands in the
+reference.  Labels are exact counts.  Orderings chosen from estimates never change a
+result.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import estimator_ref as er
+from paper_1801_03644_amd import datagen as dg
+from paper_1801_03644_amd import mdrq
+from tests.gpu_helpers import run
+
+pytestmark = pytest.mark.gpu
+
+BF16_ULP = 2.0 ** -8  # relative spacing of bfloat16 values (8 significant bits)
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def bits_to_float(b: np.ndarray) -> np.ndarray:
+    return (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def sample_bounds(raw, m):
+    n = len(raw[0])
+    rows = (np.arange(m, dtype=np.uint64) * np.uint64(n)) // np.uint64(m)
+    return np.stack([er.boundaries(np.sort(c[rows].astype(np.float64))) for c in raw])
+
+
+def c4_small(n_rows):
+    w = dg.workload("c4", n_rows)
+    return w, w.columns()
+
+
+def queries_with_edges(w, n, seed):
+    qs = dg.workload_queries(w, n, sampler=w.sampler(sample_rows=1 << 15), seed=seed)
+    qs[0] = dg.make_query([(3, 0.7, 0.2)])                               # empty interval
+    qs[1] = dg.make_query([(0, -np.inf, np.inf), (5, 0.1, 0.4)])         # partial match entry
+    qs[2] = dg.make_query([(7, -5.0, 5.0)])                              # beyond the data range
+    qs[3] = dg.make_query([(9, 0.5, 0.5), (19, -np.inf, 0.3)])           # point and half-open
+    return qs
+
+
+def random_params(est, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, shape in est._shapes():
+        if name.startswith("W"):
+            a = scale * math.sqrt(6.0 / (shape[0] + shape[1]))
+            p[name] = rng.uniform(-a, a, size=shape).astype(np.float32)
+        else:
+            p[name] = rng.normal(0, 0.1, size=shape).astype(np.float32)
+    return p
+
+
+@pytest.mark.parametrize("m", [2, 1000, 16384])
+def test_histograms_are_equi_depth_boundaries_of_the_sample(m):
+    w, raw = c4_small(70_001)
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds, sample_rows=m) as est:
+        got = est.histograms().astype(np.float64)
+    want = sample_bounds(raw, m)
+    assert np.array_equal(got, want)
+
+
+def test_features_match_reference():
+    w, raw = c4_small(50_000)
+    qs = queries_with_edges(w, 300, seed=5)
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds) as est:
+        b = est.histograms().astype(np.float64)
+        got = bits_to_float(est.features(qs))
+    want = np.stack([er.bf16_round(er.features(q, b, 50_000)) for q in qs])
+    diff = np.abs(got - want)
+    assert (diff <= BF16_ULP * np.abs(want) + 1e-30).all()
+    assert (diff == 0).mean() > 0.999
+
+
+def base_ref(bounds, qs, n_rows):
+    return np.stack([er.base(q, bounds, n_rows) for q in qs])
+
+
+def forward_ref(est, params, X, bounds, n_rows, qs):
+    Y, _ = er.forward(params, X, base_ref(bounds, qs, n_rows))
+    s = er.selectivity_from_output(Y, n_rows)
+    for i, (dims, lo, hi) in enumerate(qs):
+        restricted = {int(j) for j, a, c in zip(dims, lo, hi) if not (a == -np.inf and c == np.inf)}
+        for j in range(est.n_dims):
+            if j not in restricted:
+                s[i, j] = 1.0
+    return Y, s
+
+
+def test_forward_matches_reference():
+    w, raw = c4_small(40_000)
+    qs = queries_with_edges(w, 333, seed=6)  # ragged: not a multiple of the 16-row tile
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds, hidden=48) as est:
+        b = est.histograms().astype(np.float64)
+        untrained = est.predict(qs).astype(np.float64)
+        p = random_params(est, 1, scale=2.0)
+        est.set_params(p)
+        X = bits_to_float(est.features(qs))
+        got = est.predict(qs).astype(np.float64)
+        _, want = forward_ref(est, p, X, b, ds.n_rows, qs)
+    # untrained: the output layer is zero, the estimate is the histogram base
+    _, base_s = forward_ref(est, {k: np.zeros_like(v) for k, v in p.items()}, X, b, 40_000, qs)
+    assert np.allclose(untrained, base_s, rtol=1e-5, atol=0)
+    # Compare y = -ln(s) / ln N: a hidden activation whose bfloat16 rounding flips
+    # moves y by at most one bfloat16 unit of that activation times |W3|.
+    ln = math.log(40_000)
+    dy = np.abs(np.log(got) - np.log(want)) / ln
+    assert dy.max() < 2e-2, dy.max()
+    assert np.median(dy) < 1e-4
+
+
+def test_parameters_round_trip_and_invalid():
+    w, raw = c4_small(10_000)
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds, hidden=32, seed=3) as est:
+        p = est.get_params()
+        assert p["W1"].shape == (20 * 19, 32) and p["W3"].shape == (32, 21)
+        assert (p["b1"] == 0).all() and np.abs(p["W2"]).max() <= math.sqrt(6 / 64) + 1e-6
+        assert (p["W3"] == 0).all() and (p["b3"] == 0).all() and np.abs(p["W1"]).max() > 0
+        q = random_params(est, 2)
+        est.set_params(q)
+        r = est.get_params()
+        for k in q:
+            assert np.array_equal(q[k], r[k])
+        q["W2"][0, 0] = np.nan
+        with pytest.raises(mdrq.MdrqError) as e:
+            est.set_params(q)
+        assert e.value.code == mdrq.EINVAL
+        with pytest.raises(mdrq.MdrqError):
+            mdrq.Estimator(ds, hidden=40)
+        with pytest.raises(mdrq.MdrqError):
+            est.predict([dg.make_query([(0, np.nan, 1.0)])])
+
+
+def test_labels_are_exact_counts():
+    w, raw = c4_small(30_011)
+    cols = oracle.prepare(raw)
+    qs = queries_with_edges(w, 120, seed=7)
+    with mdrq.Dataset.from_host(raw) as ds:
+        sel = ds.label_selectivities(qs)
+    n = 30_011
+    for i, (dims, lo, hi) in enumerate(qs):
+        want = np.full(21, -1.0, dtype=np.float32)
+        for j, a, c in zip(dims, lo, hi):
+            if a == -np.inf and c == np.inf:
+                continue
+            want[j] = np.float32(oracle.count(cols, dg.make_query([(j, a, c)])) / n)
+        want[20] = np.float32(oracle.count(cols, (dims, lo, hi)) / n)
+        assert np.array_equal(sel[i], want), i
+
+
+def test_gradient_matches_reference():
+    w, raw = c4_small(40_000)
+    qs = queries_with_edges(w, 301, seed=8)
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds) as est:
+        sel = ds.label_selectivities(qs)
+        p = random_params(est, 4)
+        est.set_params(p)
+        X = bits_to_float(est.features(qs))
+        b = est.histograms().astype(np.float64)
+        loss, g = est.gradient(qs, sel)
+    T, M = [], []
+    for row in sel.astype(np.float64):
+        d = {j: row[j] for j in range(20) if row[j] >= 0}
+        t, m = er.targets(d, row[20], 20, 40_000)
+        T.append(t)
+        M.append(m)
+    T, M = np.array(T), np.array(M)
+    Y, cache = er.forward(p, X, base_ref(b, qs, 40_000))
+    want_loss, dY = er.loss_and_grad_y(Y, T, M)
+    want = er.backward(cache, dY)
+    assert abs(loss - want_loss) <= 1e-3 * want_loss
+    for k in want:
+        a, b = g[k].astype(np.float64), want[k]
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        _print(k, "relative error", rel)
+        assert rel < 2e-2, (k, rel)
+
+
+def test_adam_steps_match_reference():
+    w, raw = c4_small(20_000)
+    qs = queries_with_edges(w, 200, seed=9)
+    lr = 1e-2
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds, hidden=32) as est:
+        sel = ds.label_selectivities(qs)
+        p0 = random_params(est, 5)
+        est.set_params(p0)
+        _, g0 = est.gradient(qs, sel)
+        est.train(qs, sel, epochs=1, batch=len(qs), lr=lr)
+        p1 = est.get_params()
+        _, g1 = est.gradient(qs, sel)
+        est.train(qs, sel, epochs=1, batch=len(qs), lr=lr)
+        p2 = est.get_params()
+    for k in p0:
+        m0 = np.zeros_like(p0[k], dtype=np.float64)
+        r1, m1, v1 = er.adam_step(p0[k].astype(np.float64), g0[k].astype(np.float64), m0, m0, 1, lr)
+        r2, _, _ = er.adam_step(p1[k].astype(np.float64), g1[k].astype(np.float64), m1, v1, 2, lr)
+        # the training step sums its batch in another order than the gradient call:
+        # steps of size about lr may differ where a gradient is within rounding of 0
+        bad1 = np.abs(p1[k] - r1) > 1e-4 * lr + 1e-6
+        bad2 = np.abs(p2[k] - r2) > 1e-4 * lr + 1e-6
+        assert bad1.sum() <= 1e-3 * bad1.size and bad2.sum() <= 1e-3 * bad2.size, k
+
+
+def independence(bounds, q, n_rows):
+    """The histogram independence product (the base estimate) as a selectivity."""
+    return er.selectivity_from_output(er.base(q, bounds, n_rows)[-1:], n_rows)[0]
+
+
+def test_training_learns_and_beats_the_independence_product():
+    """c4 shape (pairs of correlated columns) at 2*10^6 rows, trained on 80000 labelled
+    queries: on 3000 held-out queries the learned joint estimate has a lower held-out
+    loss, geometric-mean q-error and 90th-percentile q-error than the product of the
+    per-dimension histogram estimates (the base it corrects)."""
+    n = 2_000_000
+    w, raw = c4_small(n)
+    samp = w.sampler(sample_rows=1 << 17)
+    train_q = dg.workload_queries(w, 80000, sampler=samp, seed=11)
+    test_q = dg.workload_queries(w, 3000, sampler=samp, seed=12)
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds, seed=1) as est:
+        _print("labelling")
+        s_train = ds.label_selectivities(train_q)
+        s_test = ds.label_selectivities(test_q)
+        _print("training")
+        before, _ = est.gradient(test_q, s_test)
+        losses = est.train(train_q, s_train, epochs=30, batch=256, lr=1e-3, seed=3)
+        after, _ = est.gradient(test_q, s_test)
+        _print("epoch losses", losses[0], losses[-1], "held-out loss", before, after)
+        pred = est.predict(test_q)
+        b = est.histograms().astype(np.float64)
+    learned = er.qerror(pred[:, 20], s_test[:, 20], n)
+    indep = er.qerror([independence(b, q, n) for q in test_q], s_test[:, 20], n)
+    for name, qe in (("learned", learned), ("independence", indep)):
+        _print(name, "q-error median", np.median(qe), "p90", np.percentile(qe, 90),
+               "geometric mean", np.exp(np.log(qe).mean()))
+    assert np.isfinite(losses).all() and losses[-1] < losses[0]
+    assert after < 0.8 * before
+    assert np.log(learned).mean() < np.log(indep).mean()
+    assert np.percentile(learned, 90) < np.percentile(indep, 90)
+    assert np.median(learned) < 1.5
+    # per-dimension estimates stay close to exact
+    mask = s_test[:, :20] >= 0
+    per_dim = er.qerror(pred[:, :20][mask], s_test[:, :20][mask], n)
+    assert np.median(per_dim) < 1.05
+
+
+def test_estimated_order_gives_identical_results_and_is_faster():
+    """Queries whose given order starts with a wide predicate and ends with a narrow
+    one: evaluated in estimated order they read fewer column bytes (the early break
+    skips more tiles), with the same results."""
+    n = 32_000_000
+    raw = [dg.column(31, j, dg.uniform(), n) for j in range(6)]
+    cols = oracle.prepare(raw)
+    rng = np.random.default_rng(3)
+    qs = []
+    for _ in range(24):
+        dims = rng.permutation(6)[:4]
+        widths = [0.95, 0.9, 0.8, 2e-5]
+        preds = []
+        for j, wd in zip(dims, widths):
+            lo = float(rng.uniform(0, 1 - wd))
+            preds.append((int(j), lo, lo + wd))
+        qs.append(dg.make_query(preds))
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds) as est:
+        tq = []
+        for _ in range(3000):
+            k = int(rng.integers(1, 5))
+            dims = rng.permutation(6)[:k]
+            preds = []
+            for j in dims:
+                wd = float(np.exp(rng.uniform(np.log(1e-5), 0)))
+                lo = float(rng.uniform(0, 1 - wd))
+                preds.append((int(j), lo, lo + wd))
+            tq.append(dg.make_query(preds))
+        est.train(tq, ds.label_selectivities(tq), epochs=15, batch=256, lr=2e-3)
+        ds.attach_estimator(est)
+        times = {}
+        for name, flags in (("given", mdrq.Q_ORDER_GIVEN), ("estimated", mdrq.Q_ORDER_ESTIMATED)):
+            for q in qs[:2]:
+                run(ds, q, flags=flags)  # warm up
+            ds.set_profiling(True)
+            ds.reset_profile()
+            for q in qs:
+                a, ids = run(ds, q, flags=flags)
+                st, cnt, want = oracle.query(cols, q)
+                assert a.count == cnt and np.array_equal(ids, want)
+            times[name] = ds.profile()[1]
+            ds.set_profiling(False)
+        _print("scan ms given", times["given"], "estimated", times["estimated"])
+        assert times["estimated"] < 0.6 * times["given"]
+        # batched path with estimated order: same answers
+        outs = [None] * len(qs)
+        a1 = ds.query_batch(qs, outs, "count", flags=mdrq.Q_ORDER_ESTIMATED)
+        for q, a in zip(qs, a1):
+            assert a.count == oracle.count(cols, q)
+        ds.attach_estimator(None)
