@@ -143,14 +143,20 @@ int mdrq_query(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r, void* 
 int mdrq_query_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n_queries,
                      mdrq_result_t* rs, void* stream);
 
-/* Serving configuration: requests are admitted while their result reservations fit
- * in result_budget_bytes of device memory, packed into shared scans of at most
- * max_batch queries, and run on n_streams device streams so that scans overlap. */
+/* Serving configuration.  n_streams workers each own a device stream and an equal share
+ * of result_budget_bytes of device memory for the scans' bitmap rows: a request whose
+ * result needs identifiers or a bitmap reserves one row of ceil(n_rows / 64) words (its
+ * result can never need more), a count-only request reserves none.  A worker that is
+ * idle takes the oldest waiting requests, at most max_batch and as many as its share
+ * holds, and answers them with one batched shared scan (as mdrq_query_batch); requests
+ * that arrive meanwhile wait for the next idle worker (continuous batching), and the
+ * workers' scans overlap on the device. */
 typedef struct {
   uint64_t result_budget_bytes;
   uint32_t max_batch;       /* 1 .. MDRQ_MAX_BATCH */
   uint32_t n_streams;       /* 1 .. 8 */
-  uint32_t use_estimator;   /* order dims and size reservations by the attached estimator */
+  uint32_t use_estimator;   /* 1: every request evaluates its predicates in estimated
+                               order (needs an attached estimator) */
   uint32_t reserved;
 } mdrq_serve_config_t;
 
@@ -166,18 +172,23 @@ typedef struct {
   double wall_s;            /* first arrival to last completion */
   double qps;               /* completed / wall_s */
   double p50_us, p99_us, mean_us, max_us;  /* arrival -> result complete in device memory */
-  double mean_batch;        /* queries per shared scan */
-  double hbm_gbps;          /* column bytes read by the scans / wall_s */
-  uint64_t overflow_reruns; /* requests re-run after a reservation proved too small */
+  double mean_batch;        /* requests per worker batch */
+  double hbm_gbps;          /* column bytes covered by the scans (each union column in
+                               full) / wall_s */
+  uint64_t overflow_reruns; /* always 0: reservations are upper bounds, never re-run */
 } mdrq_serve_stats_t;
 
 /*
- * Replay n_reqs arrival-stamped requests through the serving loop (continuous
- * batching).  rs[i] receives request i's result exactly as mdrq_query would give it;
- * latency_ns (optional, n_reqs entries) receives each request's latency.
- * Errors: MDRQ_EINVAL (bad config or request), MDRQ_EBUSY (a single request's
- * reservation exceeds the whole budget), MDRQ_EOVERFLOW (some rs[i] truncated),
- * MDRQ_ENOMEM, MDRQ_EDEVICE.
+ * Replay n_reqs arrival-stamped requests through the serving loop: request i is
+ * queued when the run's clock reaches reqs[i].arrival_ns.  rs[i] receives request i's
+ * result exactly as mdrq_query would give it; results that are not count-only must be
+ * in device memory.  latency_ns (optional, n_reqs entries) receives each request's
+ * arrival-to-completion time; stats (optional) the summary.  The call returns when
+ * every request is answered.
+ * Errors: MDRQ_EINVAL (bad config or request, host-memory result buffer, use_estimator
+ * without an estimator), MDRQ_EBUSY (one bitmap row exceeds a stream's share of the
+ * budget), MDRQ_EOVERFLOW (some rs[i] truncated; all others complete), MDRQ_ENOMEM,
+ * MDRQ_EDEVICE.
  */
 int mdrq_serve(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, const mdrq_request_t* reqs,
                uint32_t n_reqs, mdrq_result_t* rs, uint64_t* latency_ns,

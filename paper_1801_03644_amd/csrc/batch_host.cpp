@@ -68,9 +68,8 @@ uint64_t shape_key(uint64_t n_rows, size_t n_slots, size_t n_queries) {
 
 // Run one shared scan over `items` (all with k <= kMaxSlots, union <= kMaxSlots).
 // ms_out receives the device time of the scan and finish launches.
-int run_shared(mdrq_dataset* ds, std::vector<Item>& items, const BatchConfig& cfg,
-               hipStream_t stream, float* ms_out) {
-  BatchWorkspace& ws = ds->batch;
+int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
+               const BatchConfig& cfg, hipStream_t stream, float* ms_out) {
   const uint64_t nq = items.size();
   const uint64_t n_rows = ds->n_rows;
   const uint64_t nw = n_words(ds);
@@ -299,7 +298,8 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots) {
 // queries that cannot share a scan (more than kMaxSlots predicates) alone, and group
 // the rest into shared scans whose union of columns fits the register slots.
 int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs,
-              hipStream_t stream) {
+              hipStream_t stream, BatchWorkspace* wsp, bool tune, BatchRunStats* st) {
+  BatchWorkspace& ws = wsp ? *wsp : ds->batch;
   std::vector<float> est;  // estimated selectivities, for MDRQ_Q_ORDER_ESTIMATED
   int erc = estimate_for_order(ds, qs, n, est);
   if (erc) return erc;
@@ -352,34 +352,57 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     const bool fixed = ds->batch_waves || ds->batch_group || ds->batch_rows || !ds->autotune;
     float ms = 0.f;
     if (fixed) {
-      int rc = run_shared(ds, batch, cfg, stream, &ms);
+      int rc = run_shared(ds, ws, batch, cfg, stream, &ms);
       if (rc) return rc;
     } else {
       const uint64_t key = shape_key(ds->n_rows, static_cast<size_t>(used), batch.size());
-      const BatchConfig* known = nullptr;
-      for (const auto& kv : ds->tuned)
-        if (kv.first == key) known = &kv.second;
-      if (known) {
-        int rc = run_shared(ds, batch, *known, stream, &ms);
+      BatchConfig known_cfg;
+      bool known = false;
+      {
+        std::lock_guard<std::mutex> lock(ds->stat_mu);
+        for (const auto& kv : ds->tuned)
+          if (kv.first == key) {
+            known_cfg = kv.second;
+            known = true;
+          }
+        // Without tuning, take a configuration tuned for the same rows and columns.
+        if (!known && !tune)
+          for (const auto& kv : ds->tuned)
+            if ((kv.first >> 8) == (key >> 8)) {
+              known_cfg = kv.second;
+              known = true;
+            }
+      }
+      if (known || !tune) {
+        int rc = run_shared(ds, ws, batch, known ? known_cfg : cfg, stream, &ms);
         if (rc) return rc;
       } else {
         // Every candidate computes the same exact results; keep the fastest.
         BatchConfig best;
         float best_ms = std::numeric_limits<float>::infinity();
         for (const BatchConfig& c : candidates(batch.size(), used)) {
-          int rc = run_shared(ds, batch, c, stream, &ms);
+          int rc = run_shared(ds, ws, batch, c, stream, &ms);
           if (rc) return rc;
           if (ms < best_ms) {
             best_ms = ms;
             best = c;
           }
         }
+        std::lock_guard<std::mutex> lock(ds->stat_mu);
         ds->tuned.emplace_back(key, best);
         ms = best_ms;
       }
     }
-    ds->batch_launches += 1;
-    ds->batch_ms += ms;
+    {
+      std::lock_guard<std::mutex> lock(ds->stat_mu);
+      ds->batch_launches += 1;
+      ds->batch_ms += ms;
+    }
+    if (st) {
+      st->scans += 1;
+      st->column_bytes += 4 * ds->n_rows * static_cast<uint64_t>(used);
+      st->device_ms += ms;
+    }
   }
   for (uint32_t i : alone) {
     Plan plan = plan_of(i);
@@ -390,6 +413,38 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     int rc = run_query(ds, plan, &rs[i], stream);
     if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
   }
+  return MDRQ_OK;
+}
+
+int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queries, uint64_t max_rows) {
+  const uint64_t nw = n_words(ds);
+  const uint64_t n_tiles = (ds->n_rows + kTileRows - 1) / kTileRows;
+  const uint64_t nq = max_queries;
+  int rc = grow_device(&ws.d_words, &ws.d_words_len, std::max<uint64_t>(1, max_rows) * nw + 1, "batch bitmaps");
+  if (rc) return rc;
+  rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, nq * n_tiles + 1, "batch tile counts");
+  if (rc) return rc;
+  if (nq > ws.res_len) {
+    if (ws.d_res) (void)hipFree(ws.d_res);
+    if (ws.h_res) (void)hipHostFree(ws.h_res);
+    ws.d_res = ws.h_res = nullptr;
+    ws.res_len = 0;
+    if (hipMalloc(&ws.d_res, nq * 12) != hipSuccess ||
+        hipHostMalloc(&ws.h_res, nq * 12, hipHostMallocDefault) != hipSuccess)
+      return fail(MDRQ_ENOMEM, "batch result buffers");
+    ws.res_len = nq;
+  }
+  // Query table: at most a 4-word header and 4 words per predicate per query, record
+  // offsets and group arrays; then the output records.
+  const uint64_t blob = (nq * (8 + 4 * kMaxSlots) + 64) * 4 + nq * sizeof(BatchOut) + 16;
+  rc = grow_pinned(&ws.h_blob, &ws.h_blob_bytes, blob);
+  if (rc) return rc;
+  rc = grow_device(reinterpret_cast<uint8_t**>(&ws.d_blob), &ws.d_blob_bytes, blob, "batch table");
+  if (rc) return rc;
+  rc = grow_device(reinterpret_cast<uint8_t**>(&ws.d_stage), &ws.d_stage_bytes, 1, "batch staging");
+  if (rc) return rc;
+  if (!ws.ev0) MDRQ_HIP(hipEventCreate(&ws.ev0), "hipEventCreate");
+  if (!ws.ev1) MDRQ_HIP(hipEventCreate(&ws.ev1), "hipEventCreate");
   return MDRQ_OK;
 }
 

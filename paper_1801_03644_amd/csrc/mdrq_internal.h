@@ -255,9 +255,23 @@ void detach_estimator(mdrq_dataset* ds);
 
 namespace mdrq {
 struct BatchWorkspace;
-// Batched path (batch_host.cpp).
+// What a batched call did: shared scans launched, the column bytes they cover (every
+// union column in full) and their device time.
+struct BatchRunStats {
+  uint64_t scans = 0;
+  uint64_t column_bytes = 0;
+  double device_ms = 0.0;
+};
+// Batched path (batch_host.cpp).  ws: the workspace to use (null: the dataset's own);
+// tune: a new batch shape may be autotuned (otherwise a known or default configuration
+// is used).  Calls with different workspaces may run concurrently.
 int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs,
-              hipStream_t stream);
+              hipStream_t stream, BatchWorkspace* ws = nullptr, bool tune = true,
+              BatchRunStats* st = nullptr);
+// Grow a workspace so that batches of up to max_queries queries, max_rows of them with
+// bitmap rows, run without allocating.
+int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queries,
+                  uint64_t max_rows);
 void free_batch(BatchWorkspace& ws);
 }  // namespace mdrq
 
@@ -298,8 +312,13 @@ struct mdrq_dataset {
   std::vector<const float*> cols;        // device pointer of each column
   std::vector<float> col_min, col_max;
 
-  // Single-query workspace (calls are serialised by `mu`).
+  // Calls on a dataset are serialised by `mu`; inside a call, `single_mu` guards the
+  // single-query workspace and `stat_mu` the counters and the tuned configurations (the
+  // serving loop's workers run batches concurrently).
   std::mutex mu;
+  std::mutex single_mu;
+  std::mutex stat_mu;
+  // Single-query workspace.
   mdrq::ScanState* state = nullptr;      // device
   uint64_t* stage_bitmap = nullptr;      // device, ceil(n_rows / 64) words
   uint32_t* tile_counts = nullptr;       // device, tiles at the smallest tile height

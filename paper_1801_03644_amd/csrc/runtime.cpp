@@ -177,6 +177,7 @@ int recover_state(mdrq_dataset* ds) {
 
 int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream) {
   if (plan.empty || ds->n_rows == 0) return finish_empty(ds, plan, r, stream);
+  std::lock_guard<std::mutex> single(ds->single_mu);
   const bool host_out = r->mem == MDRQ_MEM_HOST && plan.mode != kCount;
   const uint64_t elem = plan.mode == kIds ? 4 : 8;
   const uint64_t out_elems = plan.mode == kBitmap ? std::min(plan.capacity, n_words(ds)) : plan.capacity;
@@ -559,13 +560,5 @@ int mdrq_get_batch_profile(const mdrq_dataset* ds, uint64_t* scans, double* ms) 
   return MDRQ_OK;
 }
 
-int mdrq_serve(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, const mdrq_request_t* reqs,
-               uint32_t n_reqs, mdrq_result_t* rs, uint64_t* latency_ns,
-               mdrq_serve_stats_t* stats) {
-  (void)cfg; (void)reqs; (void)n_reqs; (void)rs; (void)latency_ns; (void)stats;
-  clear_error();
-  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
-  return fail(MDRQ_ENOTSUP, "mdrq_serve is not built yet");
-}
 
 }  // extern "C"

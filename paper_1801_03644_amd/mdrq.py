@@ -342,6 +342,28 @@ class Dataset:
     def reset_profile(self):
         _check(load_library().mdrq_reset_profile(self._h))
 
+    def serve(self, arrivals_ns, queries, outs, modes="ids", max_batch: int = 256,
+              n_streams: int = 2, budget_bytes: int = 1 << 30, use_estimator: bool = False):
+        """Replay requests (arrival time in ns, query) through the serving loop.
+        Returns (answers, latencies in ns, stats dict)."""
+        lib = load_library()
+        n = len(queries)
+        modes = [modes] * n if isinstance(modes, str) else list(modes)
+        qarr, keep = _query_array(queries, 0)
+        reqs = (Request * max(1, n))()
+        for i in range(n):
+            reqs[i].arrival_ns = int(arrivals_ns[i])
+            reqs[i].query = qarr[i]
+        rarr = (Result * max(1, n))(*[_result_for(o, m) for o, m in zip(outs, modes)])
+        lat = (ctypes.c_uint64 * max(1, n))()
+        st = ServeStats()
+        cfg = ServeConfig(int(budget_bytes), max_batch, n_streams, 1 if use_estimator else 0, 0)
+        rc = lib.mdrq_serve(self._h, ctypes.byref(cfg), reqs, n, rarr, lat, ctypes.byref(st))
+        _check(rc, (OK, EOVERFLOW))
+        answers = [Answer(r.count, r.written, r.status, _MODE_NAMES[r.mode]) for r in rarr[:n]]
+        stats = {name: getattr(st, name) for name, _ in ServeStats._fields_}
+        return answers, np.array(lat[:n], dtype=np.uint64), stats
+
     def label_selectivities(self, queries) -> np.ndarray:
         """Exact selectivities (n, n_dims + 1): each predicate alone, then the query;
         -1 where a query does not restrict a dimension."""

@@ -1,0 +1,157 @@
+"""GPU parity of the serving loop (mdrq_serve): every request's result is the oracle's
+and the same as the query alone, whatever it was batched with; admission respects the
+result-memory budget."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1801_03644_amd import datagen as dg
+from paper_1801_03644_amd import mdrq
+from tests.gpu_helpers import bitmap_to_ids, device, run
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def outputs(n_rows, modes, caps=None):
+    import torch
+
+    outs = []
+    for i, m in enumerate(modes):
+        cap = None if caps is None else caps[i]
+        if m == "count":
+            outs.append(None)
+        elif m == "bitmap":
+            n = (n_rows + 63) // 64 if cap is None else cap
+            outs.append(torch.full((max(1, n),), -1, dtype=torch.int64, device=device())[:n])
+        else:
+            n = max(n_rows, 2 * ((n_rows + 63) // 64)) if cap is None else cap
+            outs.append(torch.full((max(1, n),), -1, dtype=torch.int32, device=device())[:n])
+    return outs
+
+
+def payload(out, ans, n_rows):
+    a = out.cpu().numpy().view(np.uint8)
+    if ans.mode == "bitmap":
+        return bitmap_to_ids(a[:8 * ans.written].view(np.uint64), n_rows)[0]
+    return a[:4 * ans.written].view(np.uint32)
+
+
+def poisson(n, rate_per_s, seed):
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1e9 / rate_per_s, size=n)).astype(np.uint64)
+
+
+def c5_small(n_rows):
+    w = dg.workload("c5", n_rows)
+    return w, w.columns()
+
+
+def check(ds, cols, qs, modes, outs, answers, label):
+    for i, (q, m, o, a) in enumerate(zip(qs, modes, outs, answers)):
+        st, cnt, want = oracle.query(cols, q)
+        assert a.count == cnt, (label, i)
+        if m == "count":
+            assert a.mode == "count"
+            continue
+        assert a.status == mdrq.OK, (label, i)
+        assert np.array_equal(payload(o, a, ds.n_rows), want), (label, i, m)
+
+
+def test_serve_results_match_oracle_and_alone():
+    w, raw = c5_small(300_007)
+    cols = oracle.prepare(raw)
+    pool = dg.workload_queries(w, 64, sampler=w.sampler(sample_rows=1 << 16))
+    pool[0] = dg.make_query([])                       # every row
+    pool[1] = dg.make_query([(2, 0.6, 0.1)])          # empty interval
+    pool[2] = dg.make_query([(j, -np.inf, np.inf) for j in range(12)])
+    rng = np.random.default_rng(1)
+    n = 400
+    qs = [pool[i] for i in rng.integers(0, len(pool), size=n)]
+    modes = [["ids", "bitmap", "count", "auto"][i % 4] for i in range(n)]
+    arrivals = poisson(n, 40_000, seed=2)
+    with mdrq.Dataset.from_host(raw) as ds:
+        outs = outputs(ds.n_rows, modes)
+        _print("serve 400 requests")
+        answers, lat, stats = ds.serve(arrivals, qs, outs, modes, max_batch=64, n_streams=2,
+                                       budget_bytes=1 << 26)
+        _print(stats)
+        check(ds, cols, qs, modes, outs, answers, "mix")
+        assert stats["completed"] == n and stats["scans"] >= 1
+        assert stats["p50_us"] <= stats["p99_us"] <= stats["max_us"]
+        assert (lat > 0).all()
+        assert stats["mean_batch"] >= 1.0
+        # the same queries alone
+        for i in range(0, n, 37):
+            if modes[i] != "ids":
+                continue
+            a1, ids1 = run(ds, qs[i])
+            assert a1.count == answers[i].count
+            assert np.array_equal(ids1, payload(outs[i], answers[i], ds.n_rows))
+
+
+def test_admission_by_result_memory():
+    """Each stream's share holds exactly 3 bitmap rows: no worker batch carries more
+    than 3 requests that need one, count-only requests need none."""
+    w, raw = c5_small(100_000)
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 60, sampler=w.sampler(sample_rows=1 << 16))
+    row = 8 * ((100_000 + 63) // 64)
+    with mdrq.Dataset.from_host(raw) as ds:
+        modes = ["ids"] * 60
+        outs = outputs(ds.n_rows, modes)
+        answers, lat, stats = ds.serve(np.zeros(60, dtype=np.uint64), qs, outs, modes,
+                                       max_batch=64, n_streams=2, budget_bytes=2 * 3 * row + 100)
+        check(ds, cols, qs, modes, outs, answers, "admission")
+        assert stats["mean_batch"] <= 3.0 and stats["mean_batch"] >= 1.0
+        cmodes = ["count"] * 60
+        answers, lat, stats = ds.serve(np.zeros(60, dtype=np.uint64), qs, [None] * 60, cmodes,
+                                       max_batch=64, n_streams=2, budget_bytes=0)
+        check(ds, cols, qs, cmodes, [None] * 60, answers, "count only")
+        with pytest.raises(mdrq.MdrqError) as e:
+            ds.serve([0], qs[:1], outputs(ds.n_rows, ["ids"]), "ids", n_streams=2,
+                     budget_bytes=row)
+        assert e.value.code == mdrq.EBUSY
+
+
+def test_serve_overflow_and_invalid():
+    w, raw = c5_small(50_000)
+    cols = oracle.prepare(raw)
+    q = dg.make_query([(0, 0.1, 0.8)])
+    st, cnt, want = oracle.query(cols, q)
+    with mdrq.Dataset.from_host(raw) as ds:
+        outs = outputs(ds.n_rows, ["ids", "ids"], caps=[10, None])
+        answers, lat, stats = ds.serve([0, 0], [q, q], outs, "ids", n_streams=1)
+        assert answers[0].status == mdrq.EOVERFLOW and answers[0].count == cnt
+        assert answers[0].written == 10
+        assert np.array_equal(payload(outs[0], answers[0], ds.n_rows), want[:10])
+        assert answers[1].status == mdrq.OK
+        assert np.array_equal(payload(outs[1], answers[1], ds.n_rows), want)
+        host = [np.zeros(ds.n_rows, dtype=np.uint32)]
+        for kwargs in ({"max_batch": 0}, {"n_streams": 9}, {"use_estimator": True}):
+            with pytest.raises(mdrq.MdrqError) as e:
+                ds.serve([0], [q], outputs(ds.n_rows, ["ids"]), "ids", **kwargs)
+            assert e.value.code == mdrq.EINVAL
+        with pytest.raises(mdrq.MdrqError) as e:
+            ds.serve([0], [q], host, "ids")
+        assert e.value.code == mdrq.EINVAL
+
+
+def test_serve_with_estimated_order_is_exact():
+    w, raw = c5_small(200_000)
+    cols = oracle.prepare(raw)
+    samp = w.sampler(sample_rows=1 << 16)
+    train = dg.workload_queries(w, 2000, sampler=samp, seed=5)
+    qs = dg.workload_queries(w, 120, sampler=samp, seed=6)
+    modes = ["ids", "count", "auto"] * 40
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds) as est:
+        est.train(train, ds.label_selectivities(train), epochs=5, batch=256, lr=2e-3)
+        ds.attach_estimator(est)
+        outs = outputs(ds.n_rows, modes)
+        answers, lat, stats = ds.serve(poisson(120, 50_000, 3), qs, outs, modes, max_batch=32,
+                                       n_streams=3, budget_bytes=1 << 26, use_estimator=True)
+        check(ds, cols, qs, modes, outs, answers, "estimated")
+        ds.attach_estimator(None)
