@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--rows", type=int, default=None, help="override the row count")
     ap.add_argument("--queries", type=int, default=None)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -144,6 +144,11 @@ def main():
                          "size for calibration; prints no bench line")
     ap.add_argument("--summarize", metavar="DIR", default=None,
                     help="summarise rocprofv3 CSV output found under DIR into profiles/")
+    ap.add_argument("--train-queries", type=int, default=200_000, help="c4: training queries")
+    ap.add_argument("--test-queries", type=int, default=10_000, help="c4: held-out queries")
+    ap.add_argument("--epochs", type=int, default=20, help="c4/c5: estimator epochs")
+    ap.add_argument("--rates", default="2000,10000,50000", help="c5: arrival rates (queries/s)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="c5: seconds per rate")
     args = ap.parse_args()
     if args.summarize:
         summarize(args.summarize, args.workload)
@@ -164,6 +169,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload in ("c3", "c4", "c5"):
+        import bench_extra
+
+        line = {"c3": bench_extra.batched, "c4": bench_extra.learned,
+                "c5": bench_extra.serving}[args.workload](args)
+        print(json.dumps(line), flush=True)
+        return
     w = dg.workload(args.workload, args.rows)
     n_q = args.queries or (100 if args.workload == "c1" else 1000)
     log(f"generating {w.name}: {w.n_rows} x {w.n_dims}")

@@ -1,0 +1,365 @@
+"""The batched, learned and serving workloads of bench.py (--workload c3 / c4 / c5).
+
+Each function returns one JSON-ready dict in the same form as bench.py's line: `value`
+is the configuration's headline throughput, with inputs already resident in HBM and
+outputs written to HBM.  Every compared variant must return identical counts (and,
+where checked, identical ids); a mismatch raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import sys
+import time
+
+import numpy as np
+
+METRIC = "tuples/s & HBM GB/s per query; batched+learned vs plain queries/s; p99 latency"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def _line(value, unit, config, steps, warmup, ms_per_step, extra):
+    d = {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+         "warmup": warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+         "config": config}
+    d.update(extra)
+    return d
+
+
+class Runner:
+    """Prepared single-query and batch calls through the C ABI (no per-call Python
+    marshalling in the timed loops)."""
+
+    def __init__(self, ds, queries, out2d, stream):
+        from paper_1801_03644_amd import mdrq
+
+        self.mdrq = mdrq
+        self.lib = mdrq.load_library()
+        self.ds = ds
+        self.stream = stream
+        self.n = len(queries)
+        self.out2d = out2d
+        cap = out2d.shape[1]
+        self.cap = cap
+        self.keep = []
+        self.q = {}
+        for flags in (0, mdrq.Q_ORDER_ESTIMATED):
+            arr = (mdrq.Query * self.n)()
+            for i, q in enumerate(queries):
+                qq, k = mdrq.make_query(q, flags)
+                arr[i] = qq
+                self.keep.append(k)
+            self.q[flags] = arr
+        self.r = (mdrq.Result * self.n)()
+        self.counts = np.zeros(self.n, dtype=np.int64)
+
+    def _result(self, i, slot):
+        r = self.r[i]
+        r.mode, r.mem = self.mdrq.OUT_IDS, self.mdrq.MEM_DEVICE
+        r.buf = self.out2d[slot].data_ptr()
+        r.buf_bytes = self.cap * 4
+        return r
+
+    def plain(self, flags=0, lo=0, hi=None):
+        hi = self.n if hi is None else hi
+        for i in range(lo, hi):
+            r = self._result(i, i % self.out2d.shape[0])
+            rc = self.lib.mdrq_query(self.ds.handle, ctypes.byref(self.q[flags][i]), ctypes.byref(r),
+                                     self.stream)
+            if rc not in (0, self.mdrq.EOVERFLOW):
+                raise self.mdrq.MdrqError(rc, self.mdrq.last_error())
+            self.counts[i] = r.count
+        return self.counts[lo:hi].copy()
+
+    def batch(self, flags=0, lo=0, hi=None, size=1024):
+        hi = self.n if hi is None else hi
+        for a in range(lo, hi, size):
+            b = min(hi, a + size)
+            for i in range(a, b):
+                self._result(i, i - a)
+            qp = ctypes.cast(ctypes.byref(self.q[flags], a * ctypes.sizeof(self.mdrq.Query)),
+                             ctypes.POINTER(self.mdrq.Query))
+            rp = ctypes.cast(ctypes.byref(self.r, a * ctypes.sizeof(self.mdrq.Result)),
+                             ctypes.POINTER(self.mdrq.Result))
+            rc = self.lib.mdrq_query_batch(self.ds.handle, qp, b - a, rp, self.stream)
+            if rc not in (0, self.mdrq.EOVERFLOW):
+                raise self.mdrq.MdrqError(rc, self.mdrq.last_error())
+            for i in range(a, b):
+                self.counts[i] = self.r[i].count
+        return self.counts[lo:hi].copy()
+
+
+def _setup(name, rows):
+    import torch
+
+    from paper_1801_03644_amd import datagen as dg
+    from paper_1801_03644_amd import mdrq
+
+    w = dg.workload(name, rows)
+    log(f"generating {w.name}: {w.n_rows} x {w.n_dims}")
+    t0 = time.perf_counter()
+    raw = w.columns()
+    log(f"generated in {time.perf_counter() - t0:.1f}s; loading into HBM")
+    ds = mdrq.Dataset.from_host(raw)
+    stream = mdrq._stream_handle(torch.cuda.current_stream())
+    return w, raw, ds, stream
+
+
+def _timed(fn, reps=1):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return out, (time.perf_counter() - t0) / reps
+
+
+def _cpu(raw, queries, n_rows, budget):
+    import bench
+
+    return bench.cpu_baseline(raw, queries, n_rows, budget)
+
+
+def batched(args):
+    """c3: batches of 64, 256 and 1024 queries answered by one shared scan each, against
+    the same queries one at a time through mdrq_query; ids output in both."""
+    import torch
+
+    from paper_1801_03644_amd import datagen as dg
+    from paper_1801_03644_amd.metrics import ALU_TESTS_PEAK
+
+    w, raw, ds, stream = _setup("c3", args.rows)
+    n_q = 1024
+    queries = dg.workload_queries(w, n_q)
+    ks = np.array([len(q[0]) for q in queries])
+    cap = min(w.n_rows, 12_000_000)
+    out = torch.empty((n_q, cap), dtype=torch.int32, device="cuda:0")
+    run = Runner(ds, queries, out, stream)
+    reps = max(1, args.steps)
+    res = {}
+    for Q in (64, 256, 1024):
+        log(f"batch size {Q}: plain")
+        run.plain(0, 0, Q)                                   # warm-up
+        c_plain, t_plain = _timed(lambda: run.plain(0, 0, Q), reps)
+        log(f"batch size {Q}: shared scan (the first call autotunes)")
+        run.batch(0, 0, Q, Q)
+        ds.reset_profile()
+        c_batch, t_batch = _timed(lambda: run.batch(0, 0, Q, Q), reps)
+        scans, dev_ms = ds.batch_profile()
+        if not np.array_equal(c_plain, c_batch):
+            raise RuntimeError("batched counts differ from single-query counts")
+        tests = float(ks[:Q].sum()) * w.n_rows
+        res[Q] = {"plain_queries_per_s": Q / t_plain, "batched_queries_per_s": Q / t_batch,
+                  "speedup": t_plain / t_batch, "batch_ms": t_batch * 1e3,
+                  "shared_scans_per_batch": scans / reps, "device_ms_per_batch": dev_ms / reps,
+                  "row_tests_per_s": tests / (dev_ms / reps / 1e3)}
+        log(f"Q={Q}: plain {Q / t_plain:.0f} q/s, batched {Q / t_batch:.0f} q/s")
+    # ids of a few queries of the largest batch against their single-query ids
+    run.batch(0, 0, n_q, n_q)
+    check = [0, 17, 511, 1023]
+    got = [out[i, :min(cap, int(run.counts[i]))].clone() for i in check]
+    for j, i in enumerate(check):
+        run.plain(0, i, i + 1)
+        if not torch.equal(got[j], out[i % out.shape[0], :min(cap, int(run.counts[i]))]):
+            raise RuntimeError("batched ids differ from single-query ids")
+    big = res[1024]
+    ach = big["row_tests_per_s"]
+    line = _line(big["batched_queries_per_s"], "queries/s",
+                 {"workload": f"c3: {w.n_rows} rows x {w.n_dims} float32 columns, batches of "
+                              f"64/256/1024 queries (k 1..8, s 1e-5..0.2), ids output",
+                  "n_rows": w.n_rows, "n_dims": w.n_dims, "mean_queried_dims": float(ks.mean()),
+                  "data_seed": w.data_seed, "query_seed": w.query_seed},
+                 reps, 1, big["batch_ms"],
+                 {"batches": {str(k): v for k, v in res.items()},
+                  "plain_queries_per_s": big["plain_queries_per_s"],
+                  "roofline": {"bound": "alu", "achieved": ach, "peak": ALU_TESTS_PEAK,
+                               "unit": "row-predicate tests/s", "frac": ach / ALU_TESTS_PEAK,
+                               "traffic": None, "kernel": "batch_scan_kernel (+ finish)",
+                               "note": "tests = sum over queries of (queried dims x rows), the "
+                                       "work without early-out; peak = one 32-bit compare per "
+                                       "lane and clock (256 CUs x 64 lanes x 2.4 GHz)"}})
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle baseline")
+        line["cpu_baseline"] = _cpu(raw, queries, w.n_rows, args.cpu_budget)
+    ds.close()
+    return line
+
+
+def _qerror(est, true, n_rows):
+    e = np.maximum(np.asarray(est, dtype=np.float64), 1.0 / n_rows)
+    t = np.maximum(np.asarray(true, dtype=np.float64), 1.0 / n_rows)
+    return np.maximum(e / t, t / e)
+
+
+def _qstats(q):
+    return {"median": float(np.median(q)), "p90": float(np.percentile(q, 90)),
+            "p99": float(np.percentile(q, 99)), "max": float(q.max()),
+            "geometric_mean": float(np.exp(np.log(q).mean()))}
+
+
+def learned(args):
+    """c4: the estimator trained on scan-labelled queries; q-error against the
+    histogram independence product (the untrained estimator returns exactly that); and
+    queries/s of the held-out queries in given and in estimated predicate order, one at
+    a time and in shared scans of 1024."""
+    import torch
+
+    from paper_1801_03644_amd import datagen as dg
+    from paper_1801_03644_amd import mdrq
+
+    w, raw, ds, stream = _setup("c4", args.rows)
+    samp = w.sampler()
+    n_tr, n_te = args.train_queries, args.test_queries
+    train_q = dg.quantile_queries(samp, n_tr, (1, 10), (1e-5, 0.2), w.split_seed)
+    test_q = dg.quantile_queries(samp, n_te, (3, 10), (1e-5, 0.2), w.query_seed)
+    log(f"labelling {n_tr} + {n_te} queries with shared count scans")
+    t0 = time.perf_counter()
+    parts = []
+    for a in range(0, n_tr, 20_000):
+        parts.append(ds.label_selectivities(train_q[a:a + 20_000]))
+        log(f"labelled {min(n_tr, a + 20_000)} training queries ({time.perf_counter() - t0:.1f}s)")
+    s_train = np.concatenate(parts)
+    s_test = ds.label_selectivities(test_q)
+    t_label = time.perf_counter() - t0
+    est = mdrq.Estimator(ds, seed=1)
+    base = est.predict(test_q)                         # untrained: the independence product
+    log(f"training {args.epochs} epochs")
+    t0 = time.perf_counter()
+    losses = est.train(train_q, s_train, epochs=args.epochs, batch=256, lr=1e-3,
+                       seed=w.split_seed)
+    t_train = time.perf_counter() - t0
+    pred = est.predict(test_q)
+    n = w.n_rows
+    mask = s_test[:, :-1] >= 0
+    qerr = {"joint_learned": _qstats(_qerror(pred[:, -1], s_test[:, -1], n)),
+            "joint_independence": _qstats(_qerror(base[:, -1], s_test[:, -1], n)),
+            "per_dim_learned": _qstats(_qerror(pred[:, :-1][mask], s_test[:, :-1][mask], n)),
+            "per_dim_histogram": _qstats(_qerror(base[:, :-1][mask], s_test[:, :-1][mask], n))}
+    ds.attach_estimator(est)
+    cap = min(n, 12_000_000)
+    out = torch.empty((1024, cap), dtype=torch.int32, device="cuda:0")
+    run = Runner(ds, test_q, out, stream)
+    G, E = 0, mdrq.Q_ORDER_ESTIMATED
+    variants = {}
+    log("warm-up")
+    run.plain(G, 0, 200)
+    run.plain(E, 0, 200)
+    run.batch(G, 0, 1024)
+    run.batch(E, 0, 1024)
+    ds.set_profiling(True)
+    for name, fn in (("plain_given_order", lambda: run.plain(G)),
+                     ("plain_estimated_order", lambda: run.plain(E)),
+                     ("batched_given_order", lambda: run.batch(G)),
+                     ("batched_estimated_order", lambda: run.batch(E))):
+        log(name)
+        ds.reset_profile()
+        c, t = _timed(fn)
+        launches, scan_ms, total_ms = ds.profile()
+        variants[name] = {"queries_per_s": n_te / t, "seconds": t, "counts": c}
+        if launches:
+            variants[name]["scan_kernel_us_per_query"] = scan_ms / launches * 1e3
+        log(f"{name}: {n_te / t:.0f} queries/s")
+    ds.set_profiling(False)
+    ref = variants["plain_given_order"]["counts"]
+    for name, v in variants.items():
+        if not np.array_equal(v.pop("counts"), ref):
+            raise RuntimeError(f"{name}: counts differ")
+    if not np.array_equal(ref, np.round(s_test[:, -1].astype(np.float64) * n).astype(np.int64)):
+        # labels are float32 count / N: allow the float32 rounding of the label
+        lab = s_test[:, -1].astype(np.float64) * n
+        if np.abs(lab - ref).max() > 1e-6 * n + 1:
+            raise RuntimeError("labels disagree with the scan counts")
+    best = variants["batched_estimated_order"]["queries_per_s"]
+    line = _line(best, "queries/s",
+                 {"workload": f"c4: {n} rows x {w.n_dims} float32 columns (10 correlated pairs), "
+                              f"{n_tr} training / {n_te} held-out queries, ids output",
+                  "n_rows": n, "n_dims": w.n_dims, "train_queries": n_tr, "test_queries": n_te,
+                  "hidden": 64, "epochs": args.epochs, "data_seed": w.data_seed,
+                  "query_seed": w.query_seed, "split_seed": w.split_seed},
+                 1, 0, variants["batched_estimated_order"]["seconds"] * 1e3,
+                 {"variants": variants, "q_error": qerr,
+                  "speedup_vs_plain_given_order": best / variants["plain_given_order"]["queries_per_s"],
+                  "label_seconds": t_label, "train_seconds": t_train,
+                  "epoch_loss_first_last": [float(losses[0]), float(losses[-1])]})
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle baseline")
+        line["cpu_baseline"] = _cpu(raw, test_q, n, args.cpu_budget)
+    ds.attach_estimator(None)
+    est.close()
+    ds.close()
+    return line
+
+
+def serving(args):
+    """c5: Poisson arrivals at each rate replayed through mdrq_serve (2 streams, shared
+    scans of up to 256, estimated predicate order), results in device memory."""
+    import torch
+
+    from paper_1801_03644_amd import datagen as dg
+    from paper_1801_03644_amd import mdrq
+
+    w, raw, ds, stream = _setup("c5", args.rows)
+    samp = w.sampler()
+    pool = dg.workload_queries(w, 4096, sampler=samp)
+    train_q = dg.quantile_queries(samp, 20_000, (1, 6), (1e-6, 0.1), w.split_seed)
+    log("labelling and training the estimator")
+    est = mdrq.Estimator(ds, seed=1)
+    est.train(train_q, ds.label_selectivities(train_q), epochs=args.epochs, batch=256, lr=1e-3)
+    ds.attach_estimator(est)
+    log("pool counts (single queries)")
+    pool_counts = np.array([ds.query(q, None, mode="count").count for q in pool])
+    n_words = (w.n_rows + 63) // 64
+    n_buf = 1024
+    bufs = torch.empty((n_buf, 2 * n_words), dtype=torch.int32, device="cuda:0")
+    rng = np.random.default_rng(w.split_seed)
+    rates = [float(r) for r in args.rates.split(",")]
+    budget = 8 << 30
+
+    def serve(rate, seconds, seed):
+        n = max(1, int(rate * seconds))
+        r = np.random.default_rng(seed)
+        arrivals = np.cumsum(r.exponential(1e9 / rate, size=n)).astype(np.uint64)
+        pick = r.integers(0, len(pool), size=n)
+        qs = [pool[i] for i in pick]
+        # output buffers are reused cyclically; only counts are checked here
+        outs = [bufs[i % n_buf] for i in range(n)]
+        answers, lat, st = ds.serve(arrivals, qs, outs, "auto", max_batch=256, n_streams=2,
+                                    budget_bytes=budget, use_estimator=True)
+        counts = np.array([a.count for a in answers])
+        if not np.array_equal(counts, pool_counts[pick]):
+            raise RuntimeError("served counts differ from single-query counts")
+        return st
+
+    log("warm-up")
+    serve(rates[0], 0.2, 1)
+    per_rate = {}
+    for i, rate in enumerate(rates):
+        log(f"rate {rate:.0f}/s for {args.serve_seconds}s")
+        st = serve(rate, args.serve_seconds, 100 + i)
+        per_rate[str(int(rate))] = {k: st[k] for k in ("completed", "scans", "wall_s", "qps", "p50_us",
+                                                       "p99_us", "mean_us", "max_us", "mean_batch",
+                                                       "hbm_gbps")}
+        log(f"rate {rate:.0f}: {st['qps']:.0f} q/s, p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us")
+    top = per_rate[str(int(rates[-1]))]
+    line = _line(top["qps"], "queries/s",
+                 {"workload": f"c5: {w.n_rows} rows x {w.n_dims} float32 columns resident, Poisson "
+                              f"arrivals at {args.rates}/s for {args.serve_seconds}s each, pool of "
+                              f"4096 queries (k 1..6, s 1e-6..0.1), auto output",
+                  "n_rows": w.n_rows, "n_dims": w.n_dims, "max_batch": 256, "n_streams": 2,
+                  "result_budget_bytes": budget, "data_seed": w.data_seed,
+                  "query_seed": w.query_seed},
+                 1, 0, top["wall_s"] * 1e3,
+                 {"rates": per_rate, "p50_us": top["p50_us"], "p99_us": top["p99_us"]})
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle baseline")
+        line["cpu_baseline"] = _cpu(raw, pool, w.n_rows, args.cpu_budget)
+    ds.attach_estimator(None)
+    est.close()
+    ds.close()
+    return line

@@ -273,6 +273,55 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   return MDRQ_OK;
 }
 
+// Best-fit decreasing grouping of items into sets whose union of columns has at most
+// kMaxSlots columns and which hold at most MDRQ_MAX_BATCH items.  Each group lists item
+// positions in ascending order.
+std::vector<std::vector<size_t>> group_by_columns(const std::vector<Item>& items, uint32_t n_dims) {
+  struct Group {
+    std::vector<bool> in;
+    int used = 0;
+    std::vector<size_t> members;
+  };
+  std::vector<size_t> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    return items[a].plan.dims.size() > items[b].plan.dims.size();
+  });
+  std::vector<Group> groups;
+  for (size_t i : order) {
+    const std::vector<uint32_t>& dims = items[i].plan.dims;
+    Group* best = nullptr;
+    int best_add = kMaxSlots + 1;
+    for (Group& g : groups) {
+      if (g.members.size() >= MDRQ_MAX_BATCH) continue;
+      int add = 0;
+      for (uint32_t d : dims) add += g.in[d] ? 0 : 1;
+      if (g.used + add <= kMaxSlots && add < best_add) {
+        best = &g;
+        best_add = add;
+        if (add == 0) break;
+      }
+    }
+    if (!best) {
+      groups.push_back(Group{std::vector<bool>(n_dims, false), 0, {}});
+      best = &groups.back();
+    }
+    for (uint32_t d : dims)
+      if (!best->in[d]) {
+        best->in[d] = true;
+        ++best->used;
+      }
+    best->members.push_back(i);
+  }
+  std::vector<std::vector<size_t>> out;
+  out.reserve(groups.size());
+  for (Group& g : groups) {
+    std::sort(g.members.begin(), g.members.end());
+    out.push_back(std::move(g.members));
+  }
+  return out;
+}
+
 // Candidate configurations the autotuner tries on a new batch shape.
 std::vector<BatchConfig> candidates(uint64_t nq, int n_slots) {
   std::vector<BatchConfig> c;
@@ -328,23 +377,23 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     }
     shared.push_back(Item{i, std::move(plan), kind_of(rs[i].mode), &rs[i]});
   }
-  // Greedy grouping: a query joins the current scan while the union fits.
-  size_t pos = 0;
-  while (pos < shared.size()) {
+  // Grouping into shared scans whose union of columns fits the register slots:
+  // best-fit decreasing -- queries with the most columns first, each into the open
+  // group it adds the fewest new columns to (a new group if none has room).  Queries
+  // on overlapping columns share a scan, so each column is read by few scans.
+  std::vector<std::vector<size_t>> groups = group_by_columns(shared, ds->n_dims);
+  for (const std::vector<size_t>& members : groups) {
     std::vector<Item> batch;
     std::vector<bool> in(ds->n_dims, false);
     int used = 0;
-    size_t next = pos;
-    while (next < shared.size() && batch.size() < MDRQ_MAX_BATCH) {
-      int add = 0;
-      for (uint32_t d : shared[next].plan.dims) add += in[d] ? 0 : 1;
-      if (used + add > kMaxSlots) break;
-      for (uint32_t d : shared[next].plan.dims) in[d] = true;
-      used += add;
-      batch.push_back(std::move(shared[next]));
-      ++next;
+    for (size_t m : members) {
+      for (uint32_t d : shared[m].plan.dims)
+        if (!in[d]) {
+          in[d] = true;
+          ++used;
+        }
+      batch.push_back(std::move(shared[m]));
     }
-    pos = next;
     BatchConfig cfg;
     cfg.waves = ds->batch_waves ? ds->batch_waves : 4;
     cfg.group = ds->batch_group;

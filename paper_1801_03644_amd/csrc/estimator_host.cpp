@@ -541,24 +541,34 @@ int mdrq_label_selectivities(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t 
   }
   const uint32_t O = ds->n_dims + 1;
   const double N = static_cast<double>(ds->n_rows);
-  // Expand: every restricting predicate alone, then the whole query.
+  // Expand: the whole queries first, then every restricting predicate alone, grouped
+  // by dimension so that a shared scan holds many predicates on few columns.
   std::vector<mdrq_pred> singles;
-  std::vector<mdrq_query_t> ex;
-  std::vector<std::pair<uint32_t, uint32_t>> where;  // (query, column of sel)
-  for (uint32_t i = 0; i < n; ++i)
-    for (uint32_t k = 0; k < qs[i].n_preds; ++k)
-      if (restricts(qs[i].preds[k])) singles.push_back(qs[i].preds[k]);
-  size_t s = 0;
+  std::vector<std::pair<uint32_t, uint32_t>> single_where;  // (query, dimension)
   for (uint32_t i = 0; i < n; ++i) {
     float* row = sel + static_cast<size_t>(i) * O;
     for (uint32_t j = 0; j < O; ++j) row[j] = -1.0f;
-    for (uint32_t k = 0; k < qs[i].n_preds; ++k) {
-      if (!restricts(qs[i].preds[k])) continue;
-      ex.push_back(mdrq_query_t{&singles[s++], 1, 0});
-      where.emplace_back(i, qs[i].preds[k].dim);
-    }
+    for (uint32_t k = 0; k < qs[i].n_preds; ++k)
+      if (restricts(qs[i].preds[k])) {
+        singles.push_back(qs[i].preds[k]);
+        single_where.emplace_back(i, qs[i].preds[k].dim);
+      }
+  }
+  std::vector<size_t> by_dim(singles.size());
+  for (size_t k = 0; k < by_dim.size(); ++k) by_dim[k] = k;
+  std::stable_sort(by_dim.begin(), by_dim.end(),
+                   [&](size_t a, size_t b) { return singles[a].dim < singles[b].dim; });
+  std::vector<mdrq_query_t> ex;
+  std::vector<std::pair<uint32_t, uint32_t>> where;  // (query, column of sel)
+  ex.reserve(n + singles.size());
+  where.reserve(n + singles.size());
+  for (uint32_t i = 0; i < n; ++i) {
     ex.push_back(mdrq_query_t{qs[i].preds, qs[i].n_preds, 0});
     where.emplace_back(i, ds->n_dims);
+  }
+  for (size_t k : by_dim) {
+    ex.push_back(mdrq_query_t{&singles[k], 1, 0});
+    where.push_back(single_where[k]);
   }
   std::lock_guard<std::mutex> lock(ds->mu);
   std::vector<mdrq_result_t> rs(MDRQ_MAX_BATCH);

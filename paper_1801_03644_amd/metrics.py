@@ -9,6 +9,11 @@ HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E, vendor figure
 FP32_VALU_TFLOPS = 157.3    # MI355X vector fp32, vendor figure
 CUS = 256
 CLOCK_GHZ = 2.4
+# Vector compares: 4 SIMDs x 16 lanes per CU retire one 32-bit compare per lane and clock
+# (a wave64 instruction every 4 clocks per SIMD): 256 * 64 * 2.4e9 = 3.93e13 per second.
+# A range test on one row needs at least one compare (unsigned range trick), so this is
+# the ALU ceiling of row-predicate tests.
+ALU_TESTS_PEAK = CUS * 64 * CLOCK_GHZ * 1e9
 
 
 def column_bytes(n_rows: int, n_dims: int) -> int:
