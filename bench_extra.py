@@ -247,11 +247,11 @@ def learned(args):
     run = Runner(ds, test_q, out, stream)
     G, E = 0, mdrq.Q_ORDER_ESTIMATED
     variants = {}
-    log("warm-up")
+    log("warm-up (the first shared scan of each batch shape autotunes its launch)")
     run.plain(G, 0, 200)
     run.plain(E, 0, 200)
-    run.batch(G, 0, 1024)
-    run.batch(E, 0, 1024)
+    run.batch(G)
+    run.batch(E)
     ds.set_profiling(True)
     for name, fn in (("plain_given_order", lambda: run.plain(G)),
                      ("plain_estimated_order", lambda: run.plain(E)),

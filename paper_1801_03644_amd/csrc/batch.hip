@@ -150,6 +150,170 @@ __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
   }
 }
 
+// ---------------------------------------------------------------- LDS-staged variant
+
+// The query table is read-only for the whole launch and every access to it is
+// wave-uniform: reading it through the constant address space gives scalar loads.
+typedef __attribute__((address_space(4))) const uint32_t cu32;
+typedef __attribute__((address_space(4))) const TabPred ctabpred;
+
+__device__ __forceinline__ TabPred load_pred(ctabpred* p) {
+  TabPred t;
+  t.slot = p->slot;
+  t.klo = p->klo;
+  t.kw = p->kw;
+  t.pad = 0;
+  return t;
+}
+
+// Keys per lane in LDS, as vectors of V = min(RG, 4) consecutive row groups.
+template <int RG>
+struct KeyVec;
+template <>
+struct KeyVec<2> {
+  typedef uint2 type;
+};
+template <>
+struct KeyVec<4> {
+  typedef uint4 type;
+};
+template <>
+struct KeyVec<8> {
+  typedef uint4 type;
+};
+
+// As batch_scan_kernel, for unions of up to kMaxUnion columns: a chunk's keys are
+// staged in LDS instead of registers, so a predicate's column is an LDS address
+// (slot * stride) rather than a register slot found by branching.  Lane l writes and
+// later reads only its own keys, so staging needs no barrier.  Wave layout: for slot
+// s, row-group quad q and lane l, V keys at ((s * RG/V + q) * 64 + l) * V.
+template <int W, int RG>
+__global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
+  static_assert(W * RG <= 64, "a tile must hold at least one chunk per wave");
+  constexpr int V = RG < 4 ? RG : 4;
+  constexpr int NQ = RG / V;
+  typedef typename KeyVec<RG>::type vec;
+  extern __shared__ uint32_t lds[];
+  const uint32_t group = blockIdx.y;
+  const uint32_t q_beg = bp.group_first[group];
+  const uint32_t q_end = bp.group_first[group + 1];
+  const uint32_t nq = q_end - q_beg;
+  const uint32_t ns = bp.n_slots;
+  cu32* gtab = (cu32*)(bp.table) + bp.group_table[group];  // generic -> constant address space
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = threadIdx.x / 64;
+  uint32_t* s_cnt = lds;
+  uint32_t* keys = lds + ((nq + 3) & ~3u) + wave * ns * RG * 64 + lane * V;
+  for (uint32_t i = threadIdx.x; i < nq; i += W * 64) s_cnt[i] = 0;
+  __syncthreads();
+
+  constexpr uint32_t kChunkRows = 64 * RG;
+  constexpr uint32_t kChunksPerWave = 4096 / kChunkRows / W;
+  for (uint64_t tile = blockIdx.x; tile < bp.n_tiles; tile += gridDim.x) {
+#pragma unroll 1
+    for (uint32_t cw = 0; cw < kChunksPerWave; ++cw) {
+      const uint64_t row0 = tile * 4096 + (wave * kChunksPerWave + cw) * kChunkRows;
+      if (row0 >= bp.n_rows) break;
+      const bool full = row0 + kChunkRows <= bp.n_rows;
+      // Stage the keys; rows past the end get 0xFFFFFFFF, above the key of every
+      // non-NaN float, so the first predicate of every query rejects them.
+#pragma unroll 1
+      for (uint32_t s = 0; s < ns; ++s) {
+        const float* col = bp.slot_cols[s];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          uint32_t k[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const uint64_t r = row0 + 64 * (q * V + v) + lane;
+            k[v] = (full || r < bp.n_rows) ? dkey(col[r]) : 0xFFFFFFFFu;
+          }
+          vec kv;
+          if constexpr (V == 2) {
+            kv = vec{k[0], k[1]};
+          } else {
+            kv = vec{k[0], k[1], k[2], k[3]};
+          }
+          *reinterpret_cast<vec*>(keys + (s * NQ + q) * 64 * V) = kv;
+        }
+      }
+      const uint64_t word0 = row0 / 64;
+      cu32* rec = gtab + gtab[0];
+#pragma unroll 1
+      for (uint32_t qi = 0; qi < nq; ++qi) {
+        const uint32_t head = rec[0];
+        const uint32_t np = head & 0xFFu;
+        const uint32_t kind = (head >> 8) & 0x3u;
+        ctabpred* tp = reinterpret_cast<ctabpred*>(rec + 4);
+        rec += 4 + 4 * np;
+        uint64_t m[RG];
+        if (np != 0) {
+#pragma unroll
+          for (int g = 0; g < RG; ++g) m[g] = ~uint64_t{0};
+        } else {  // no predicate: every row of the chunk that exists
+#pragma unroll
+          for (int g = 0; g < RG; ++g) m[g] = ballot(row0 + 64 * g + lane < bp.n_rows);
+        }
+        // Predicates in the query's order, two at a time; the early break of the
+        // whole chunk is tested after each pair.
+        auto apply = [&](const TabPred& t) {
+          const uint32_t* kp = keys + t.slot * (NQ * 64 * V);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const vec kv = *reinterpret_cast<const vec*>(kp + q * 64 * V);
+            if constexpr (V == 2) {
+              m[q * V + 0] &= ballot(kv.x - t.klo <= t.kw);
+              m[q * V + 1] &= ballot(kv.y - t.klo <= t.kw);
+            } else {
+              m[q * V + 0] &= ballot(kv.x - t.klo <= t.kw);
+              m[q * V + 1] &= ballot(kv.y - t.klo <= t.kw);
+              m[q * V + 2] &= ballot(kv.z - t.klo <= t.kw);
+              m[q * V + 3] &= ballot(kv.w - t.klo <= t.kw);
+            }
+          }
+        };
+        bool dead = false;
+        uint32_t pi = 0;
+#pragma unroll 1
+        for (; pi + 1 < np; pi += 2) {
+          const TabPred t0 = load_pred(tp + pi), t1 = load_pred(tp + pi + 1);
+          apply(t0);
+          apply(t1);
+          if (pi + 2 < np) {
+            uint64_t any = 0;
+#pragma unroll
+            for (int g = 0; g < RG; ++g) any |= m[g];
+            if (any == 0) {
+              dead = true;
+              break;
+            }
+          }
+        }
+        if (dead) continue;
+        if (pi < np) apply(load_pred(tp + pi));
+        uint32_t c = 0;
+#pragma unroll
+        for (int g = 0; g < RG; ++g) c += __popcll(m[g]);
+        if (c != 0) {
+          if (lane == 0) atomicAdd(&s_cnt[qi], c);
+          if (kind != kBatchCount) {
+            uint64_t* words = bp.words + static_cast<uint64_t>(head >> 16) * bp.n_words + word0;
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+              if (m[g] != 0 && lane == 0) words[g] = m[g];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nq; i += W * 64) {
+      bp.tile_counts[static_cast<uint64_t>(q_beg + i) * bp.n_tiles + tile] = s_cnt[i];
+      s_cnt[i] = 0;
+    }
+    __syncthreads();
+  }
+}
+
 // Zero a range of 64-bit words (the bitmap scratch before a shared scan).
 __global__ void __launch_bounds__(256) zero_words_kernel(uint64_t* w, uint64_t n) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 256;
@@ -297,6 +461,17 @@ const void* pick_batch(int d, int w, int rg) {
   return w == 8 ? scan_fn<16, 8, 4>() : scan_fn<16, 4, 4>();
 }
 
+const void* pick_lds(int w, int rg) {
+  if (rg >= 8) return w == 8 ? reinterpret_cast<const void*>(&batch_lds_kernel<8, 8>)
+                             : reinterpret_cast<const void*>(&batch_lds_kernel<4, 8>);
+  if (rg == 4) return w == 8 ? reinterpret_cast<const void*>(&batch_lds_kernel<8, 4>)
+                             : reinterpret_cast<const void*>(&batch_lds_kernel<4, 4>);
+  return w == 8 ? reinterpret_cast<const void*>(&batch_lds_kernel<8, 2>)
+                : reinterpret_cast<const void*>(&batch_lds_kernel<4, 2>);
+}
+
+int lds_rows(int rg) { return rg >= 8 ? 8 : rg >= 4 ? 4 : 2; }
+
 }  // namespace
 
 uint32_t batch_key(float x) {
@@ -306,6 +481,10 @@ uint32_t batch_key(float x) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
+size_t batch_lds_key_bytes(int n_slots, int waves, int rg) {
+  return static_cast<size_t>(waves == 8 ? 8 : 4) * n_slots * lds_rows(rg) * 64 * 4;
+}
+
 int batch_rows_per_lane(int n_slots, int waves, int rg) {
   (void)n_slots;
   if (rg == 16 && waves == 8) rg = 8;
@@ -313,18 +492,18 @@ int batch_rows_per_lane(int n_slots, int waves, int rg) {
   return rg == 16 || rg == 8 ? rg : 4;
 }
 
-int batch_blocks_per_cu(int n_slots, int waves, int rg, size_t lds_bytes) {
+int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t lds_bytes) {
   int blocks = 0;
   const int w = waves == 8 ? 8 : 4;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &blocks, pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg)), w * 64,
-          lds_bytes) != hipSuccess)
+  const void* fn = lds_variant ? pick_lds(w, rg)
+                               : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg));
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, w * 64, lds_bytes) != hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;
 }
 
-hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, dim3 grid,
-                             size_t lds_bytes, hipStream_t stream) {
+hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, int lds_variant,
+                             dim3 grid, size_t lds_bytes, hipStream_t stream) {
   const int w = waves == 8 ? 8 : 4;
   const uint64_t n = bp.n_words * bp.n_out;
   if (n) {
@@ -334,8 +513,14 @@ hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int 
     if (e != hipSuccess) return e;
   }
   void* args[] = {const_cast<BatchParams*>(&bp)};
-  return hipLaunchKernel(pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg)), grid,
-                         dim3(w * 64), args, lds_bytes, stream);
+  const void* fn = lds_variant ? pick_lds(w, rg)
+                               : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg));
+  if (lds_bytes > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds_bytes));
+    if (e != hipSuccess) return e;
+  }
+  return hipLaunchKernel(fn, grid, dim3(w * 64), args, lds_bytes, stream);
 }
 
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream) {

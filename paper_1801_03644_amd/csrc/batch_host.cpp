@@ -66,7 +66,8 @@ uint64_t shape_key(uint64_t n_rows, size_t n_slots, size_t n_queries) {
   return (lr << 16) | (static_cast<uint64_t>(n_slots) << 8) | lq;
 }
 
-// Run one shared scan over `items` (all with k <= kMaxSlots, union <= kMaxSlots).
+// Run one shared scan over `items` (union of at most kMaxUnion columns; unions of more
+// than kMaxSlots columns take the LDS variant).
 // ms_out receives the device time of the scan and finish launches.
 int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
                const BatchConfig& cfg, hipStream_t stream, float* ms_out) {
@@ -217,10 +218,26 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   fin.counts_out = static_cast<uint64_t*>(ws.d_res);
   fin.kind_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws.d_res) + nq * 8);
 
-  const size_t lds = max_group_words * 4;
   const int waves = cfg.waves == 8 ? 8 : 4;
-  const int rg = batch_rows_per_lane(std::max(1, n_slots), waves, cfg.rows_per_lane);
-  const int per_cu = batch_blocks_per_cu(std::max(1, n_slots), waves, rg, lds);
+  const bool use_lds = cfg.lds || n_slots > kMaxSlots;
+  int rg;
+  size_t lds;
+  if (use_lds) {
+    uint64_t max_nq = 0;
+    for (uint32_t g = 0; g < n_groups; ++g)
+      max_nq = std::max<uint64_t>(max_nq, group_first[g + 1] - group_first[g]);
+    rg = cfg.rows_per_lane >= 8 ? 8 : cfg.rows_per_lane >= 4 ? 4 : 2;
+    auto need = [&](int r) {
+      return ((max_nq + 3) & ~uint64_t{3}) * 4 + batch_lds_key_bytes(std::max(1, n_slots), waves, r);
+    };
+    while (need(rg) > device().lds && rg > 2) rg /= 2;
+    lds = need(rg);
+    if (lds > device().lds) return fail(MDRQ_ENOTSUP, "shared scan: union keys do not fit LDS");
+  } else {
+    rg = batch_rows_per_lane(std::max(1, n_slots), waves, cfg.rows_per_lane);
+    lds = max_group_words * 4;
+  }
+  const int per_cu = batch_blocks_per_cu(std::max(1, n_slots), waves, rg, use_lds ? 1 : 0, lds);
   const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
   const uint64_t gx = std::max<uint64_t>(1, std::min<uint64_t>(n_tiles, resident / n_groups));
 
@@ -230,7 +247,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
            "copy query table");
   MDRQ_HIP(hipEventRecord(ws.ev0, stream), "hipEventRecord");
   if (n_tiles > 0)
-    MDRQ_HIP(launch_batch_scan(bp, std::max(1, n_slots), waves, rg,
+    MDRQ_HIP(launch_batch_scan(bp, std::max(1, n_slots), waves, rg, use_lds ? 1 : 0,
                                dim3(static_cast<uint32_t>(gx), n_groups), lds, stream),
              "shared scan launch");
   MDRQ_HIP(launch_batch_finish(fin, static_cast<uint32_t>(nq), stream), "batch finish launch");
@@ -274,7 +291,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
 }
 
 // Best-fit decreasing grouping of items into sets whose union of columns has at most
-// kMaxSlots columns and which hold at most MDRQ_MAX_BATCH items.  Each group lists item
+// kMaxUnion columns and which hold at most MDRQ_MAX_BATCH items.  Each group lists item
 // positions in ascending order.
 std::vector<std::vector<size_t>> group_by_columns(const std::vector<Item>& items, uint32_t n_dims) {
   struct Group {
@@ -291,12 +308,12 @@ std::vector<std::vector<size_t>> group_by_columns(const std::vector<Item>& items
   for (size_t i : order) {
     const std::vector<uint32_t>& dims = items[i].plan.dims;
     Group* best = nullptr;
-    int best_add = kMaxSlots + 1;
+    int best_add = kMaxUnion + 1;
     for (Group& g : groups) {
       if (g.members.size() >= MDRQ_MAX_BATCH) continue;
       int add = 0;
       for (uint32_t d : dims) add += g.in[d] ? 0 : 1;
-      if (g.used + add <= kMaxSlots && add < best_add) {
+      if (g.used + add <= kMaxUnion && add < best_add) {
         best = &g;
         best_add = add;
         if (add == 0) break;
@@ -323,28 +340,51 @@ std::vector<std::vector<size_t>> group_by_columns(const std::vector<Item>& items
 }
 
 // Candidate configurations the autotuner tries on a new batch shape.
-std::vector<BatchConfig> candidates(uint64_t nq, int n_slots) {
+std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
   std::vector<BatchConfig> c;
-  for (int rg : {16, 8, 4})
-    for (int w : {4, 8})
-      for (uint64_t g : {nq, (nq + 1) / 2, (nq + 3) / 4}) {
-        if (g < 16 && g != nq) continue;
-        BatchConfig b;
-        b.waves = w;
-        b.group = static_cast<uint32_t>(g);
-        b.rows_per_lane = batch_rows_per_lane(n_slots, w, rg);
-        bool dup = false;
-        for (const BatchConfig& o : c)
-          dup |= o.waves == b.waves && o.group == b.group && o.rows_per_lane == b.rows_per_lane;
-        if (!dup) c.push_back(b);
-      }
+  auto add = [&](const BatchConfig& b) {
+    for (const BatchConfig& o : c)
+      if (o.waves == b.waves && o.group == b.group && o.rows_per_lane == b.rows_per_lane && o.lds == b.lds)
+        return;
+    c.push_back(b);
+  };
+  for (uint64_t g : {nq, (nq + 1) / 2, (nq + 3) / 4}) {
+    if (g < 16 && g != nq) continue;
+    for (int w : {4, 8}) {
+      if (n_slots <= kMaxSlots && variant != 2)
+        for (int rg : {16, 8, 4}) {
+          BatchConfig b;
+          b.waves = w;
+          b.group = static_cast<uint32_t>(g);
+          b.rows_per_lane = batch_rows_per_lane(n_slots, w, rg);
+          add(b);
+        }
+      if (variant != 1 || n_slots > kMaxSlots)
+        for (int rg : {8, 4, 2}) {
+          if (((g + 3) & ~uint64_t{3}) * 4 + batch_lds_key_bytes(std::max(1, n_slots), w, rg) > device().lds)
+            continue;
+          BatchConfig b;
+          b.waves = w;
+          b.group = static_cast<uint32_t>(g);
+          b.rows_per_lane = rg;
+          b.lds = 1;
+          add(b);
+        }
+    }
+  }
+  if (c.empty()) {  // the smallest LDS configuration always fits
+    BatchConfig b;
+    b.rows_per_lane = 2;
+    b.lds = 1;
+    c.push_back(b);
+  }
   return c;
 }
 
 }  // namespace
 
 // Answer a batch: canonicalise each query, answer empty ones without a launch, run
-// queries that cannot share a scan (more than kMaxSlots predicates) alone, and group
+// queries that cannot share a scan (more than kMaxUnion predicates) alone, and group
 // the rest into shared scans whose union of columns fits the register slots.
 int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs,
               hipStream_t stream, BatchWorkspace* wsp, bool tune, BatchRunStats* st) {
@@ -371,7 +411,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
       if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
       continue;
     }
-    if (plan.preds.size() > static_cast<size_t>(kMaxSlots)) {
+    if (plan.preds.size() > static_cast<size_t>(kMaxUnion)) {
       alone.push_back(i);
       continue;
     }
@@ -398,7 +438,10 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     cfg.waves = ds->batch_waves ? ds->batch_waves : 4;
     cfg.group = ds->batch_group;
     cfg.rows_per_lane = ds->batch_rows ? ds->batch_rows : 16;
-    const bool fixed = ds->batch_waves || ds->batch_group || ds->batch_rows || !ds->autotune;
+    cfg.lds = ds->batch_variant == 2 ? 1 : 0;
+    if (used > kMaxSlots && !ds->batch_rows) cfg.rows_per_lane = 2;
+    const bool fixed = ds->batch_waves || ds->batch_group || ds->batch_rows || ds->batch_variant ||
+                       !ds->autotune;
     float ms = 0.f;
     if (fixed) {
       int rc = run_shared(ds, ws, batch, cfg, stream, &ms);
@@ -429,7 +472,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
         // Every candidate computes the same exact results; keep the fastest.
         BatchConfig best;
         float best_ms = std::numeric_limits<float>::infinity();
-        for (const BatchConfig& c : candidates(batch.size(), used)) {
+        for (const BatchConfig& c : candidates(batch.size(), used, ds->batch_variant)) {
           int rc = run_shared(ds, ws, batch, c, stream, &ms);
           if (rc) return rc;
           if (ms < best_ms) {
@@ -485,7 +528,7 @@ int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queri
   }
   // Query table: at most a 4-word header and 4 words per predicate per query, record
   // offsets and group arrays; then the output records.
-  const uint64_t blob = (nq * (8 + 4 * kMaxSlots) + 64) * 4 + nq * sizeof(BatchOut) + 16;
+  const uint64_t blob = (nq * (8 + 4 * kMaxUnion) + 64) * 4 + nq * sizeof(BatchOut) + 16;
   rc = grow_pinned(&ws.h_blob, &ws.h_blob_bytes, blob);
   if (rc) return rc;
   rc = grow_device(reinterpret_cast<uint8_t**>(&ws.d_blob), &ws.d_blob_bytes, blob, "batch table");

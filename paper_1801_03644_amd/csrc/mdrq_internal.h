@@ -84,7 +84,8 @@ hipError_t launch_probe(const ProbeParams& p, int unroll, int grid, hipStream_t 
 
 // ---------------------------------------------------------------- batched scan
 
-constexpr int kMaxSlots = 16;   // union columns one shared scan holds in registers
+constexpr int kMaxSlots = 16;   // union columns the register variant holds
+constexpr int kMaxUnion = 32;   // union columns of one shared scan (LDS variant)
 
 // Output kind of one query in a shared scan.
 enum BatchKind : uint32_t { kBatchCount = 0, kBatchBitmap = 1, kBatchIds = 2, kBatchAuto = 3 };
@@ -101,7 +102,7 @@ struct BatchParams {
   uint64_t* words;              // bitmap scratch, one row of n_words per output query
   uint64_t n_out;               // rows of the scratch in use (zeroed before the scan)
   uint32_t* tile_counts;        // [query][tile]
-  const float* slot_cols[kMaxSlots];
+  const float* slot_cols[kMaxUnion];
 };
 
 struct BatchOut {
@@ -123,9 +124,14 @@ struct BatchFinish {
 
 uint32_t batch_key(float x);
 int batch_rows_per_lane(int n_slots, int waves, int rg);
-int batch_blocks_per_cu(int n_slots, int waves, int rg, size_t lds_bytes);
-hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, dim3 grid,
-                             size_t lds_bytes, hipStream_t stream);
+int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t lds_bytes);
+// Shared-scan launch.  lds_variant 0: union keys in registers (n_slots <= kMaxSlots,
+// query table in LDS); 1: union keys staged in LDS (n_slots <= kMaxUnion, query table
+// read with scalar loads).  lds_bytes: the dynamic LDS of the launch.
+hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, int lds_variant,
+                             dim3 grid, size_t lds_bytes, hipStream_t stream);
+// LDS bytes the LDS variant stages keys in: waves x slots x rows per lane x 64 x 4.
+size_t batch_lds_key_bytes(int n_slots, int waves, int rg);
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream);
 
 // ---------------------------------------------------------------- learned estimator
@@ -298,7 +304,8 @@ struct BatchWorkspace {
 struct BatchConfig {
   int waves = 4;                 // waves per workgroup (4 or 8)
   uint32_t group = 0;            // queries per workgroup group (0 = all)
-  int rows_per_lane = 16;        // 64-row groups per lane per chunk: 4, 8 or 16
+  int rows_per_lane = 16;        // 64-row groups per lane per chunk: 2, 4, 8 or 16
+  int lds = 0;                   // 1: keys staged in LDS (any union up to kMaxUnion)
 };
 }  // namespace mdrq
 
@@ -340,7 +347,8 @@ struct mdrq_dataset {
   mdrq::BatchWorkspace batch;
   int batch_waves = 0;                   // 0: autotuned
   uint32_t batch_group = 0;              // 0: autotuned
-  int batch_rows = 0;                    // 64-row groups per lane (4, 8, 16); 0: autotuned
+  int batch_rows = 0;                    // 64-row groups per lane (2, 4, 8, 16); 0: autotuned
+  int batch_variant = 0;                 // 1: union keys in registers, 2: in LDS; 0: autotuned
   bool autotune = true;
   std::vector<std::pair<uint64_t, mdrq::BatchConfig>> tuned;  // shape key -> config
   uint64_t batch_launches = 0;

@@ -37,6 +37,7 @@ EST_BINS = 16
 EST_FEATS = EST_BINS + 3  # per dimension: H(lo), H(hi), histogram estimate, bins
 OPT_UNROLL, OPT_GRID, OPT_BLOCKS_PER_CU = 1, 2, 3
 OPT_BATCH_WAVES, OPT_BATCH_GROUP, OPT_AUTOTUNE, OPT_BATCH_ROWS = 4, 5, 6, 7
+OPT_BATCH_VARIANT = 8
 
 
 class MdrqError(RuntimeError):

@@ -166,6 +166,28 @@ def test_union_beyond_register_slots_and_long_queries():
         check_batch(ds, cols, qs, ["ids", "auto"] * 20, "union")
 
 
+@pytest.mark.parametrize("variant", [0, 2])
+def test_wide_unions_share_one_scan(variant):
+    """40 columns: unions of up to 32 columns share one LDS-staged scan; queries on more
+    than 32 columns run alone.  Ragged row count."""
+    n = 70_001
+    raw = [dg.column(44, j, dg.uniform() if j % 2 == 0 else dg.gmm(), n) for j in range(40)]
+    cols = oracle.prepare(raw)
+    rng = np.random.default_rng(9)
+    qs = []
+    for i in range(48):
+        k = 34 if i % 11 == 0 else int(rng.integers(1, 24))
+        dims = rng.permutation(40)[:k]
+        preds = []
+        for j in dims:
+            lo = float(rng.uniform(0, 0.3))
+            preds.append((int(j), lo, lo + float(rng.uniform(0.5, 0.7))))
+        qs.append(dg.make_query(preds))
+    with mdrq.Dataset.from_host(raw) as ds:
+        ds.set_option(mdrq.OPT_BATCH_VARIANT, variant)
+        check_batch(ds, cols, qs, ["ids", "bitmap", "count", "auto"] * 12, f"wide {variant}")
+
+
 def test_batch_overflow_and_host_outputs():
     w, raw = c3_like(120_000)
     cols = oracle.prepare(raw)
@@ -186,10 +208,15 @@ def test_launch_configurations_give_identical_results():
     qs = dg.workload_queries(w, 48, sampler=w.sampler(sample_rows=1 << 16))
     with mdrq.Dataset.from_host(raw) as ds:
         ref = None
-        for waves, group, tune in [(0, 0, 1), (4, 0, 0), (8, 0, 0), (4, 16, 0), (8, 24, 0), (0, 0, 1)]:
+        for waves, group, tune, variant, rows in [
+                (0, 0, 1, 0, 0), (4, 0, 0, 1, 0), (8, 0, 0, 1, 0), (4, 16, 0, 1, 0), (8, 24, 0, 1, 0),
+                (4, 0, 0, 2, 2), (4, 0, 0, 2, 4), (8, 0, 0, 2, 8), (4, 16, 0, 2, 8), (8, 24, 0, 2, 4),
+                (0, 0, 1, 0, 0)]:
             ds.set_option(mdrq.OPT_BATCH_WAVES, waves)
             ds.set_option(mdrq.OPT_BATCH_GROUP, group)
             ds.set_option(mdrq.OPT_AUTOTUNE, tune)
+            ds.set_option(mdrq.OPT_BATCH_VARIANT, variant)
+            ds.set_option(mdrq.OPT_BATCH_ROWS, rows)
             outs = make_outs(ds.n_rows, ["ids"] * len(qs))
             ans = ds.query_batch(qs, outs, "ids")
             got = [(a.count, payload(o, a, ds.n_rows).tobytes()) for a, o in zip(ans, outs)]
@@ -197,7 +224,7 @@ def test_launch_configurations_give_identical_results():
                 ref = got
                 for q, (c, _) in zip(qs, got):
                     assert c == oracle.count(cols, q)
-            assert got == ref, (waves, group, tune)
+            assert got == ref, (waves, group, tune, variant, rows)
 
 
 def test_full_size_c3_batch_sampled():
