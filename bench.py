@@ -63,7 +63,8 @@ def summarize(outdir: str, workload: str):
     for path in glob.glob(os.path.join(outdir, "**", "*kernel_stats.csv"), recursive=True):
         with open(path) as f:
             rows = list(csv.DictReader(f))
-        out = os.path.join(prof, f"scan_{workload}_kernel_stats.txt")
+        kind = {"c3": "batch", "c4": "learned", "c5": "serve"}.get(workload, "scan")
+        out = os.path.join(prof, f"{kind}_{workload}_kernel_stats.txt")
         with open(out, "w") as f:
             f.write("rocprofv3 --kernel-trace --stats summary\n")
             f.write(f"command: {cmd}\n\n")

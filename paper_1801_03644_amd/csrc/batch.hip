@@ -20,9 +20,10 @@
 //    its masks are zero.  RG rows per lane amortise the per-predicate table read.
 //  * The bitmap scratch is zeroed first; per (query, chunk) only non-zero masks are
 //    stored; per (query, 4096-row tile) the count is accumulated in LDS and stored.
-//  * A finishing launch takes one workgroup per query: it sums the query's tile
-//    counts and, for identifier output, scans them in LDS and compacts the query's
-//    bitmap into ascending identifiers (tiles without a hit are not read).
+//  * Finishing takes two launches: one workgroup per query sums its tile counts (the
+//    exact count), resolves AUTO and, for identifier output, turns the tile counts into
+//    output positions; then a grid of (tile range, query) workgroups copies bitmap
+//    words or compacts the tiles with a hit into ascending identifiers.
 #include <algorithm>
 #include <cstring>
 
@@ -349,40 +350,33 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t& excl, uint3
   return total;
 }
 
-// Workgroup q: exact count of query q, then its output: the bitmap copied to the
-// caller's buffer, or its ascending identifiers.  AUTO picks, from the exact count,
-// whichever of the two is smaller and fits the buffer.
-__global__ void __launch_bounds__(kFinThreads) batch_finish_kernel(BatchFinish f) {
-  __shared__ uint32_t s_off[kFinScan + 1];
+// Pass 1, workgroup q: the exact count of query q and its output kind (AUTO picks,
+// from the exact count, whichever of bitmap and identifiers is smaller and fits the
+// buffer); for identifier output the tile counts are replaced, in place, by their
+// exclusive prefix sums (each tile's first output position).
+__global__ void __launch_bounds__(kFinThreads) batch_count_kernel(BatchFinish f) {
   __shared__ uint32_t s_wave[kFinWaves];
   const uint32_t q = blockIdx.x;
   const BatchOut o = f.outs[q];
   const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & 63;
-  const uint32_t wave = tid / 64;
-  const uint32_t* counts = f.tile_counts + static_cast<uint64_t>(q) * f.n_tiles;
-  const uint64_t* words = f.words + static_cast<uint64_t>(o.out_index) * f.n_words;
-
+  uint32_t* counts = f.tile_counts + static_cast<uint64_t>(q) * f.n_tiles;
+  uint64_t part = 0;
+  for (uint64_t t = tid; t < f.n_tiles; t += kFinThreads) part += counts[t];
+  uint32_t ignore;
+  const uint64_t count = block_scan(static_cast<uint32_t>(part), ignore, s_wave);
   uint32_t kind = o.kind;
   if (kind == kBatchAuto) {
-    uint64_t part = 0;
-    for (uint64_t t = tid; t < f.n_tiles; t += kFinThreads) part += counts[t];
-    uint32_t ignore;
-    const uint64_t count = block_scan(static_cast<uint32_t>(part), ignore, s_wave);
     const uint64_t bitmap_bytes = 8 * f.n_words;
     const bool fits_bitmap = o.buf_bytes >= bitmap_bytes;
     kind = (fits_bitmap && (bitmap_bytes < 4 * count || o.buf_bytes < 4 * count)) ? kBatchBitmap
                                                                                  : kBatchIds;
   }
-  if (kind == kBatchBitmap) {
-    const uint64_t cap = o.buf_bytes / 8;
-    const uint64_t n = cap < f.n_words ? cap : f.n_words;
-    uint64_t* dst = static_cast<uint64_t*>(o.buf);
-    for (uint64_t i = tid; i < n; i += kFinThreads) dst[i] = words[i];
+  if (tid == 0) {
+    f.counts_out[q] = count;
+    f.kind_out[q] = kind;
   }
-  uint32_t* ids = static_cast<uint32_t*>(o.buf);
-  const uint64_t capacity = kind == kBatchIds ? o.buf_bytes / 4 : 0;
-  uint64_t carry = 0;
+  if (kind != kBatchIds || count == 0) return;
+  uint32_t carry = 0;
   for (uint64_t t0 = 0; t0 < f.n_tiles; t0 += kFinScan) {
     const uint32_t nt = static_cast<uint32_t>(f.n_tiles - t0 < kFinScan ? f.n_tiles - t0 : kFinScan);
     uint32_t v[8];
@@ -395,47 +389,70 @@ __global__ void __launch_bounds__(kFinThreads) batch_finish_kernel(BatchFinish f
     }
     uint32_t excl;
     const uint32_t total = block_scan(sum, excl, s_wave);
-    if (kind == kBatchIds && carry < capacity) {
+    excl += carry;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const uint32_t t = tid * 8 + i;
-        if (t < nt) s_off[t] = excl;
-        excl += v[i];
-      }
-      if (tid == 0) s_off[nt] = total;
-      __syncthreads();
-      // One tile = 64 words = one wave-wide load.
-      for (uint32_t t = wave; t < nt; t += kFinWaves) {
-        const uint32_t beg = s_off[t];
-        if (s_off[t + 1] == beg) continue;
-        const uint64_t off = carry + beg;
-        if (off >= capacity) continue;
-        const uint64_t w = (t0 + t) * 64 + lane;
-        const uint64_t word = w < f.n_words ? words[w] : 0;
-        const uint32_t k = __popcll(word);
-        uint32_t incl = k;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-          const uint32_t x = __shfl_up(incl, d);
-          if (lane >= static_cast<uint32_t>(d)) incl += x;
-        }
-        uint64_t r = off + incl - k;
-        uint64_t bits = word;
-        const uint32_t row = static_cast<uint32_t>(w * 64);
-        while (bits) {
-          const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(bits));
-          if (r < capacity) ids[r] = row + b;
-          ++r;
-          bits &= bits - 1;
-        }
-      }
-      __syncthreads();
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t t = tid * 8 + i;
+      if (t < nt) counts[t0 + t] = excl;
+      excl += v[i];
     }
     carry += total;
   }
-  if (tid == 0) {
-    f.counts_out[q] = carry;
-    f.kind_out[q] = kind;
+}
+
+// Pass 2, workgroup (c, q): tiles [c * kEmitTiles, (c + 1) * kEmitTiles) of query q.
+// Bitmap output copies the tiles' words; identifier output compacts each tile with a
+// hit (one wave per tile) at the tile's first output position, so the identifiers come
+// out ascending.  Nothing beyond the caller's capacity is written.
+constexpr uint32_t kEmitTiles = 128;
+
+__global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) {
+  const uint32_t q = blockIdx.y;
+  const uint32_t kind = f.kind_out[q];
+  const uint64_t count = f.counts_out[q];
+  if (kind == kBatchCount || (kind == kBatchIds && count == 0)) return;
+  const BatchOut o = f.outs[q];
+  const uint64_t t_beg = static_cast<uint64_t>(blockIdx.x) * kEmitTiles;
+  if (t_beg >= f.n_tiles) return;
+  const uint64_t t_end = t_beg + kEmitTiles < f.n_tiles ? t_beg + kEmitTiles : f.n_tiles;
+  const uint64_t* words = f.words + static_cast<uint64_t>(o.out_index) * f.n_words;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63;
+  const uint32_t wave = tid / 64;
+  if (kind == kBatchBitmap) {
+    const uint64_t cap = o.buf_bytes / 8;
+    const uint64_t lim = cap < f.n_words ? cap : f.n_words;
+    const uint64_t w_end = t_end * 64 < lim ? t_end * 64 : lim;
+    uint64_t* dst = static_cast<uint64_t*>(o.buf);
+    for (uint64_t i = t_beg * 64 + tid; i < w_end; i += kFinThreads) dst[i] = words[i];
+    return;
+  }
+  const uint32_t* offs = f.tile_counts + static_cast<uint64_t>(q) * f.n_tiles;
+  uint32_t* ids = static_cast<uint32_t*>(o.buf);
+  const uint64_t capacity = o.buf_bytes / 4;
+  for (uint64_t t = t_beg + wave; t < t_end; t += kFinWaves) {
+    const uint64_t beg = offs[t];
+    const uint64_t end = t + 1 < f.n_tiles ? offs[t + 1] : count;
+    if (end == beg || beg >= capacity) continue;
+    // One tile = 64 words = one wave-wide load.
+    const uint64_t w = t * 64 + lane;
+    const uint64_t word = w < f.n_words ? words[w] : 0;
+    const uint32_t k = __popcll(word);
+    uint32_t incl = k;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t x = __shfl_up(incl, d);
+      if (lane >= static_cast<uint32_t>(d)) incl += x;
+    }
+    uint64_t r = beg + incl - k;
+    uint64_t bits = word;
+    const uint32_t row = static_cast<uint32_t>(w * 64);
+    while (bits) {
+      const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(bits));
+      if (r < capacity) ids[r] = row + b;
+      ++r;
+      bits &= bits - 1;
+    }
   }
 }
 
@@ -525,9 +542,12 @@ hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int 
 
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream) {
   if (n_queries == 0) return hipSuccess;
-  void* args[] = {const_cast<BatchFinish*>(&f)};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&batch_finish_kernel), dim3(n_queries),
-                         dim3(kFinThreads), args, 0, stream);
+  batch_count_kernel<<<n_queries, kFinThreads, 0, stream>>>(f);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || f.n_tiles == 0) return e;
+  const uint32_t chunks = static_cast<uint32_t>((f.n_tiles + kEmitTiles - 1) / kEmitTiles);
+  batch_emit_kernel<<<dim3(chunks, n_queries), kFinThreads, 0, stream>>>(f);
+  return hipGetLastError();
 }
 
 }  // namespace mdrq

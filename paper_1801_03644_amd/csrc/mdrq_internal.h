@@ -116,7 +116,7 @@ struct BatchFinish {
   uint64_t n_tiles;
   uint64_t n_words;
   const uint64_t* words;
-  const uint32_t* tile_counts;
+  uint32_t* tile_counts;        // [query][tile]; becomes output positions for identifiers
   const BatchOut* outs;
   uint64_t* counts_out;         // [query] exact count
   uint32_t* kind_out;           // [query] kind used (kBatchAuto resolved)
