@@ -133,7 +133,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "syntuni"])
     ap.add_argument("--rows", type=int, default=None, help="override the row count")
     ap.add_argument("--queries", type=int, default=None)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -170,11 +170,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    if args.workload in ("c3", "c4", "c5"):
+    if args.workload in ("c3", "c4", "c5", "syntuni"):
         import bench_extra
 
         line = {"c3": bench_extra.batched, "c4": bench_extra.learned,
-                "c5": bench_extra.serving}[args.workload](args)
+                "c5": bench_extra.serving, "syntuni": bench_extra.paper}[args.workload](args)
         print(json.dumps(line), flush=True)
         return
     w = dg.workload(args.workload, args.rows)

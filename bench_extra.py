@@ -1,4 +1,5 @@
-"""The batched, learned and serving workloads of bench.py (--workload c3 / c4 / c5).
+"""The batched, learned, serving and paper-shaped workloads of bench.py
+(--workload c3 / c4 / c5 / syntuni).
 
 Each function returns one JSON-ready dict in the same form as bench.py's line: `value`
 is the configuration's headline throughput, with inputs already resident in HBM and
@@ -363,3 +364,52 @@ def serving(args):
     est.close()
     ds.close()
     return line
+
+
+def paper(args):
+    """SYNT-UNI in the paper's terms (section 7.2.1): queries/s of 1000 two-object
+    queries (complete match) per point, hot caches (one untimed pass first), for the
+    dimensionality sweep of Figure 5 (10^6 objects, 5..100 dims) and the size sweep of
+    Figure 7 (5 dims, 10^4..10^7 objects); one at a time and as shared scans."""
+    import torch
+
+    from paper_1801_03644_amd import datagen as dg
+    from paper_1801_03644_amd import mdrq
+
+    stream = mdrq._stream_handle(torch.cuda.current_stream())
+    n_q = 1000
+
+    def point(n, d):
+        w = dg.workload(f"syntuni{d}", n)
+        raw = w.columns()
+        qs = dg.two_object_queries(raw, n_q, seed=w.query_seed)
+        ds = mdrq.Dataset.from_host(raw)
+        out = torch.empty((1024, n), dtype=torch.int32, device="cuda:0")
+        run = Runner(ds, qs, out, stream)
+        run.plain()
+        c_plain, t_plain = _timed(run.plain)
+        run.batch()
+        c_batch, t_batch = _timed(run.batch)
+        if not np.array_equal(c_plain, c_batch):
+            raise RuntimeError("batched counts differ from single-query counts")
+        sel = c_plain / n
+        ds.close()
+        del out
+        r = {"n_rows": n, "dims": d, "plain_queries_per_s": n_q / t_plain,
+             "batched_queries_per_s": n_q / t_batch, "mean_selectivity_percent": 100 * float(sel.mean()),
+             "sigma_selectivity_percent": 100 * float(sel.std())}
+        log(f"N={n} d={d}: plain {r['plain_queries_per_s']:.0f} q/s, batched "
+            f"{r['batched_queries_per_s']:.0f} q/s, selectivity {r['mean_selectivity_percent']:.5f}%")
+        return r
+
+    fig5 = [point(1_000_000, d) for d in (5, 10, 20, 50, 100)]
+    fig7 = [point(n, 5) for n in (10_000, 100_000, 1_000_000, 10_000_000)]
+    best = max(p["batched_queries_per_s"] for p in fig5 if p["dims"] == 5)
+    return _line(best, "queries/s",
+                 {"workload": "syntuni: SYNT-UNI grid data, 1000 two-object queries per point; "
+                              "Figure 5 (10^6 x 5..100) and Figure 7 (10^4..10^7 x 5)",
+                  "n_queries": n_q},
+                 1, 1, n_q / best * 1e3,
+                 {"figure5_dimensionality": fig5, "figure7_dataset_size": fig7,
+                  "note": "value = batched queries/s at 10^6 x 5; the paper prints no numbers "
+                          "for these figures, so there is no vs_baseline"})

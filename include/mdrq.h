@@ -233,11 +233,11 @@ enum {
                                  union columns, batch size), time each candidate launch
                                  configuration and keep the fastest; 0: fixed defaults */
   MDRQ_OPT_BATCH_ROWS = 7,    /* shared scans: 64-row groups each lane holds per chunk,
-                                 2, 4, 8 or 16 (tile height 64 x value rows per wave);
+                                 1, 2, 4, 8 or 16 (tile height 64 x value rows per wave);
                                  0 = autotune */
   MDRQ_OPT_BATCH_VARIANT = 8  /* shared scans: 1 = the union's keys in registers (unions
                                  of up to 16 columns; wider ones use LDS), 2 = keys
-                                 staged in LDS (unions of up to 32 columns);
+                                 staged in LDS (any union, up to MDRQ_MAX_DIMS columns);
                                  0 = autotune (default) */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);

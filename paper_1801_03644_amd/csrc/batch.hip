@@ -171,6 +171,10 @@ __device__ __forceinline__ TabPred load_pred(ctabpred* p) {
 template <int RG>
 struct KeyVec;
 template <>
+struct KeyVec<1> {
+  typedef uint32_t type;
+};
+template <>
 struct KeyVec<2> {
   typedef uint2 type;
 };
@@ -191,7 +195,7 @@ struct KeyVec<8> {
 template <int W, int RG>
 __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
   static_assert(W * RG <= 64, "a tile must hold at least one chunk per wave");
-  constexpr int V = RG < 4 ? RG : 4;
+  constexpr int V = RG < 4 ? RG : 4;   // 1, 2 or 4
   constexpr int NQ = RG / V;
   typedef typename KeyVec<RG>::type vec;
   extern __shared__ uint32_t lds[];
@@ -230,7 +234,9 @@ __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
             k[v] = (full || r < bp.n_rows) ? dkey(col[r]) : 0xFFFFFFFFu;
           }
           vec kv;
-          if constexpr (V == 2) {
+          if constexpr (V == 1) {
+            kv = k[0];
+          } else if constexpr (V == 2) {
             kv = vec{k[0], k[1]};
           } else {
             kv = vec{k[0], k[1], k[2], k[3]};
@@ -262,7 +268,9 @@ __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
             const vec kv = *reinterpret_cast<const vec*>(kp + q * 64 * V);
-            if constexpr (V == 2) {
+            if constexpr (V == 1) {
+              m[q] &= ballot(kv - t.klo <= t.kw);
+            } else if constexpr (V == 2) {
               m[q * V + 0] &= ballot(kv.x - t.klo <= t.kw);
               m[q * V + 1] &= ballot(kv.y - t.klo <= t.kw);
             } else {
@@ -483,11 +491,13 @@ const void* pick_lds(int w, int rg) {
                              : reinterpret_cast<const void*>(&batch_lds_kernel<4, 8>);
   if (rg == 4) return w == 8 ? reinterpret_cast<const void*>(&batch_lds_kernel<8, 4>)
                              : reinterpret_cast<const void*>(&batch_lds_kernel<4, 4>);
-  return w == 8 ? reinterpret_cast<const void*>(&batch_lds_kernel<8, 2>)
-                : reinterpret_cast<const void*>(&batch_lds_kernel<4, 2>);
+  if (rg == 2) return w == 8 ? reinterpret_cast<const void*>(&batch_lds_kernel<8, 2>)
+                             : reinterpret_cast<const void*>(&batch_lds_kernel<4, 2>);
+  return w == 8 ? reinterpret_cast<const void*>(&batch_lds_kernel<8, 1>)
+                : reinterpret_cast<const void*>(&batch_lds_kernel<4, 1>);
 }
 
-int lds_rows(int rg) { return rg >= 8 ? 8 : rg >= 4 ? 4 : 2; }
+int lds_rows(int rg) { return rg >= 8 ? 8 : rg >= 4 ? 4 : rg >= 2 ? 2 : 1; }
 
 }  // namespace
 

@@ -218,7 +218,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   fin.counts_out = static_cast<uint64_t*>(ws.d_res);
   fin.kind_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws.d_res) + nq * 8);
 
-  const int waves = cfg.waves == 8 ? 8 : 4;
+  int waves = cfg.waves == 8 ? 8 : 4;
   const bool use_lds = cfg.lds || n_slots > kMaxSlots;
   int rg;
   size_t lds;
@@ -226,11 +226,15 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     uint64_t max_nq = 0;
     for (uint32_t g = 0; g < n_groups; ++g)
       max_nq = std::max<uint64_t>(max_nq, group_first[g + 1] - group_first[g]);
-    rg = cfg.rows_per_lane >= 8 ? 8 : cfg.rows_per_lane >= 4 ? 4 : 2;
+    rg = cfg.rows_per_lane >= 8 ? 8 : cfg.rows_per_lane >= 4 ? 4 : cfg.rows_per_lane >= 2 ? 2 : 1;
     auto need = [&](int r) {
       return ((max_nq + 3) & ~uint64_t{3}) * 4 + batch_lds_key_bytes(std::max(1, n_slots), waves, r);
     };
-    while (need(rg) > device().lds && rg > 2) rg /= 2;
+    while (need(rg) > device().lds && rg > 1) rg /= 2;
+    if (need(rg) > device().lds && waves == 8) {
+      waves = 4;
+      rg = 1;
+    }
     lds = need(rg);
     if (lds > device().lds) return fail(MDRQ_ENOTSUP, "shared scan: union keys do not fit LDS");
   } else {
@@ -290,8 +294,16 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   return MDRQ_OK;
 }
 
+// Widest union of columns one shared scan can stage in LDS (4 waves, one 64-row group
+// per lane, 1024-query counts), at most kMaxUnion.
+int max_union() {
+  const size_t per_slot = batch_lds_key_bytes(1, 4, 1);
+  const size_t room = device().lds > 4096 ? device().lds - 4096 : 0;
+  return static_cast<int>(std::min<size_t>(kMaxUnion, std::max<size_t>(kMaxSlots, room / per_slot)));
+}
+
 // Best-fit decreasing grouping of items into sets whose union of columns has at most
-// kMaxUnion columns and which hold at most MDRQ_MAX_BATCH items.  Each group lists item
+// max_union() columns and which hold at most MDRQ_MAX_BATCH items.  Each group lists item
 // positions in ascending order.
 std::vector<std::vector<size_t>> group_by_columns(const std::vector<Item>& items, uint32_t n_dims) {
   struct Group {
@@ -308,12 +320,13 @@ std::vector<std::vector<size_t>> group_by_columns(const std::vector<Item>& items
   for (size_t i : order) {
     const std::vector<uint32_t>& dims = items[i].plan.dims;
     Group* best = nullptr;
-    int best_add = kMaxUnion + 1;
+    const int limit = max_union();
+    int best_add = limit + 1;
     for (Group& g : groups) {
       if (g.members.size() >= MDRQ_MAX_BATCH) continue;
       int add = 0;
       for (uint32_t d : dims) add += g.in[d] ? 0 : 1;
-      if (g.used + add <= kMaxUnion && add < best_add) {
+      if (g.used + add <= limit && add < best_add) {
         best = &g;
         best_add = add;
         if (add == 0) break;
@@ -360,7 +373,7 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
           add(b);
         }
       if (variant != 1 || n_slots > kMaxSlots)
-        for (int rg : {8, 4, 2}) {
+        for (int rg : {8, 4, 2, 1}) {
           if (((g + 3) & ~uint64_t{3}) * 4 + batch_lds_key_bytes(std::max(1, n_slots), w, rg) > device().lds)
             continue;
           BatchConfig b;
@@ -372,9 +385,9 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
         }
     }
   }
-  if (c.empty()) {  // the smallest LDS configuration always fits
+  if (c.empty()) {  // the smallest LDS configuration: run_shared shrinks it to fit
     BatchConfig b;
-    b.rows_per_lane = 2;
+    b.rows_per_lane = 1;
     b.lds = 1;
     c.push_back(b);
   }
@@ -384,7 +397,7 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
 }  // namespace
 
 // Answer a batch: canonicalise each query, answer empty ones without a launch, run
-// queries that cannot share a scan (more than kMaxUnion predicates) alone, and group
+// queries that cannot share a scan (more than max_union() predicates) alone, and group
 // the rest into shared scans whose union of columns fits the register slots.
 int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs,
               hipStream_t stream, BatchWorkspace* wsp, bool tune, BatchRunStats* st) {
@@ -411,7 +424,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
       if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
       continue;
     }
-    if (plan.preds.size() > static_cast<size_t>(kMaxUnion)) {
+    if (plan.preds.size() > static_cast<size_t>(max_union())) {
       alone.push_back(i);
       continue;
     }
@@ -439,7 +452,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     cfg.group = ds->batch_group;
     cfg.rows_per_lane = ds->batch_rows ? ds->batch_rows : 16;
     cfg.lds = ds->batch_variant == 2 ? 1 : 0;
-    if (used > kMaxSlots && !ds->batch_rows) cfg.rows_per_lane = 2;
+    if (used > kMaxSlots && !ds->batch_rows) cfg.rows_per_lane = used > 32 ? 1 : 2;
     const bool fixed = ds->batch_waves || ds->batch_group || ds->batch_rows || ds->batch_variant ||
                        !ds->autotune;
     float ms = 0.f;

@@ -85,7 +85,7 @@ hipError_t launch_probe(const ProbeParams& p, int unroll, int grid, hipStream_t 
 // ---------------------------------------------------------------- batched scan
 
 constexpr int kMaxSlots = 16;   // union columns the register variant holds
-constexpr int kMaxUnion = 32;   // union columns of one shared scan (LDS variant)
+constexpr int kMaxUnion = MDRQ_MAX_DIMS;   // union columns of one shared scan (LDS variant)
 
 // Output kind of one query in a shared scan.
 enum BatchKind : uint32_t { kBatchCount = 0, kBatchBitmap = 1, kBatchIds = 2, kBatchAuto = 3 };

@@ -474,8 +474,8 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
       ds->batch_group = static_cast<uint32_t>(value);
       return MDRQ_OK;
     case MDRQ_OPT_BATCH_ROWS:
-      if (value != 0 && value != 2 && value != 4 && value != 8 && value != 16)
-        return fail(MDRQ_EINVAL, "batch rows per lane must be 0, 2, 4, 8 or 16");
+      if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+        return fail(MDRQ_EINVAL, "batch rows per lane must be 0, 1, 2, 4, 8 or 16");
       ds->batch_rows = static_cast<int>(value);
       return MDRQ_OK;
     case MDRQ_OPT_BATCH_VARIANT:

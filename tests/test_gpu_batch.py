@@ -168,8 +168,8 @@ def test_union_beyond_register_slots_and_long_queries():
 
 @pytest.mark.parametrize("variant", [0, 2])
 def test_wide_unions_share_one_scan(variant):
-    """40 columns: unions of up to 32 columns share one LDS-staged scan; queries on more
-    than 32 columns run alone.  Ragged row count."""
+    """40 columns: the union of all 40 is staged in LDS and the batch shares one scan
+    (forced LDS variant, or autotuned).  Ragged row count."""
     n = 70_001
     raw = [dg.column(44, j, dg.uniform() if j % 2 == 0 else dg.gmm(), n) for j in range(40)]
     cols = oracle.prepare(raw)
