@@ -99,25 +99,17 @@ __device__ __forceinline__ float log_scale(float s, float inv_rows, float inv_ln
   return -logf(s > inv_rows ? s : inv_rows) * inv_ln_rows;
 }
 
-// One thread per (query, dimension); qd holds (lo, hi, restricted) per (query, dimension).
-__global__ void features_kernel(FeatureArgs f) {
-  const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= static_cast<uint64_t>(f.n) * f.d) return;
-  const float* qd = f.qd + t * 3;
-  uint16_t* row = f.x + t * kFeatPerDim;
-  const uint32_t j = static_cast<uint32_t>(t % f.d);
-  const uint64_t q = t / f.d;
-  const float* b = f.bounds + j * (kBins + 1);
-  float* base = f.base + q * (f.d + 1) + j;
-  if (qd[2] == 0.0f) {
+// Features of one dimension of one query (kFeatPerDim bfloat16 values into row) and
+// its histogram estimate on the log scale (returned; 0 if not restricted).
+__device__ float dim_features(const float* b, float lo, float hi, bool restricted, uint16_t* row,
+                              float inv_rows, float inv_ln_rows) {
+  if (!restricted) {
     row[0] = to_bf16(-1.0f);
     row[1] = to_bf16(-1.0f);
     row[2] = 0;
     for (int i = 0; i < kBins; ++i) row[3 + i] = to_bf16(1.0f);
-    *base = 0.0f;
-    return;
+    return 0.0f;
   }
-  const float lo = qd[0], hi = qd[1];
   row[0] = to_bf16(hist_cdf(b, lo));
   row[1] = to_bf16(hist_cdf(b, hi));
   float sum = 0.0f;
@@ -135,9 +127,20 @@ __global__ void features_kernel(FeatureArgs f) {
     sum += c;
   }
   // Histogram estimate: the mean coverage (H(hi) - H(lo) without the cancellation).
-  const float y = log_scale(sum * (1.0f / kBins), f.inv_rows, f.inv_ln_rows);
+  const float y = log_scale(sum * (1.0f / kBins), inv_rows, inv_ln_rows);
   row[2] = to_bf16(y);
-  *base = y;
+  return y;
+}
+
+// One thread per (query, dimension); qd holds (lo, hi, restricted) per (query, dimension).
+__global__ void features_kernel(FeatureArgs f) {
+  const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<uint64_t>(f.n) * f.d) return;
+  const float* qd = f.qd + t * 3;
+  const uint32_t j = static_cast<uint32_t>(t % f.d);
+  const uint64_t q = t / f.d;
+  f.base[q * (f.d + 1) + j] = dim_features(f.bounds + j * (kBins + 1), qd[0], qd[1], qd[2] != 0.0f,
+                                           f.x + t * kFeatPerDim, f.inv_rows, f.inv_ln_rows);
 }
 
 // Joint base estimate of each query: min(1, sum of its per-dimension estimates), the
@@ -282,6 +285,112 @@ __global__ void gather_rows_kernel(const uint8_t* src, const uint32_t* idx, uint
       reinterpret_cast<const uint32_t*>(src)[static_cast<uint64_t>(idx[r]) * words + w];
 }
 
+// One query's evaluation order in one workgroup: features, the three layers (dot
+// products on the vector units -- a single row is no matrix product), the estimates,
+// and the rank of each of the plan's predicates by ascending estimated selectivity
+// (ties keep plan order): order[rank] = position in the plan.  The per-dimension
+// arrays are read through the kernel-argument segment pointer (indexed per lane).
+typedef __attribute__((address_space(4))) const OrderArgs korder;
+
+__device__ __forceinline__ float bf16_val(uint16_t v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
+__device__ __forceinline__ float in_val(float v) { return v; }
+__device__ __forceinline__ float in_val(uint16_t v) { return bf16_val(v); }
+
+// out[j] (for j < n_out, left in part[0][j]) = sum_i in[i] * W[i][j] over the 256
+// threads of the workgroup: thread t takes column j = j0 + t % 64 and every fourth
+// input row from t / 64; four independent partial sums keep several weight loads in
+// flight; the four row partitions are added in LDS.
+template <class T>
+__device__ void gemv(const T* in, uint32_t n_in, const uint16_t* W, uint32_t n_out, float (*part)[256]) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t c = t & 63, r0 = t >> 6;
+  for (uint32_t j0 = 0; j0 < n_out; j0 += 64) {
+    const uint32_t j = j0 + c;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (j < n_out) {
+      uint32_t i = r0;
+      for (; i + 12 < n_in; i += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          acc[u] += in_val(in[i + 4 * u]) * bf16_val(W[static_cast<uint64_t>(i + 4 * u) * n_out + j]);
+      }
+      for (; i < n_in; i += 4) acc[0] += in_val(in[i]) * bf16_val(W[static_cast<uint64_t>(i) * n_out + j]);
+    }
+    part[r0][j0 + c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  }
+  __syncthreads();
+  for (uint32_t j = t; j < n_out; j += 256) part[0][j] = (part[0][j] + part[1][j]) + (part[2][j] + part[3][j]);
+  __syncthreads();
+}
+
+// One query's evaluation order in one workgroup: features, the three layers (dot
+// products on the vector units -- a single row is no matrix product), the estimates,
+// and the rank of each of the plan's predicates by ascending estimated selectivity
+// (ties keep plan order): order[rank] = position in the plan.  The per-dimension
+// arrays are read through the kernel-argument segment pointer (indexed per lane).
+__global__ void __launch_bounds__(256) order_fused_kernel(OrderArgs a_) {
+  korder& a = *(korder*)__builtin_amdgcn_kernarg_segment_ptr();
+  __shared__ uint16_t s_x[MDRQ_MAX_DIMS * kFeatPerDim];
+  __shared__ float s_base[MDRQ_MAX_DIMS + 1];
+  __shared__ float s_h1[256];
+  __shared__ float s_h2[256];
+  __shared__ float s_part[4][256];
+  __shared__ float s_sel[MDRQ_MAX_DIMS + 1];
+  (void)a_;
+  const uint32_t t = threadIdx.x;
+  const uint32_t d = a.d, H = a.H, O = d + 1, F = d * kFeatPerDim;
+  if (t < d) {
+    const bool r = (a.restricted[t >> 5] >> (t & 31)) & 1u;
+    s_base[t] = dim_features(a.bounds + t * (kBins + 1), a.lo[t], a.hi[t], r, s_x + t * kFeatPerDim,
+                             a.inv_rows, a.inv_ln_rows);
+  }
+  __syncthreads();
+  if (t == 0) {
+    float sum = 0.0f;
+    for (uint32_t j = 0; j < d; ++j) sum += s_base[j];
+    s_base[d] = sum < 1.0f ? sum : 1.0f;
+  }
+  gemv(s_x, F, a.wb + a.oW1, H, s_part);
+  if (t < H) s_h1[t] = bf16_val(to_bf16(gelu(s_part[0][t] + a.params[a.ob1 + t])));
+  __syncthreads();
+  gemv(s_h1, H, a.wb + a.oW2, H, s_part);
+  if (t < H) s_h2[t] = bf16_val(to_bf16(gelu(s_part[0][t] + a.params[a.ob2 + t])));
+  __syncthreads();
+  gemv(s_h2, H, a.wb + a.oW3, O, s_part);
+  for (uint32_t o = t; o < O; o += 256) {
+    const float v = fminf(fmaxf(s_part[0][o] + a.params[a.ob3 + o] + s_base[o], 0.0f), 1.0f);
+    s_sel[o] = expf(-v * a.ln_rows);
+  }
+  __syncthreads();
+  if (t < a.k) {
+    const float si = s_sel[a.dims[t]];
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < a.k; ++j) {
+      const float sj = s_sel[a.dims[j]];
+      rank += (sj < si || (sj == si && j < t)) ? 1u : 0u;
+    }
+    a.order[rank] = t;
+  }
+}
+
+// Evaluation order from estimates: dims_k = (k, dims[0..k)) of a plan; thread i ranks
+// predicate i by its dimension's estimated selectivity (ties keep plan order) and
+// writes order[rank] = i.
+__global__ void __launch_bounds__(MDRQ_MAX_DIMS) order_kernel(const float* sel,
+                                                              const uint32_t* dims_k,
+                                                              uint32_t* order) {
+  const uint32_t k = dims_k[0];
+  const uint32_t i = threadIdx.x;
+  if (i >= k) return;
+  const float si = sel[dims_k[1 + i]];
+  uint32_t rank = 0;
+  for (uint32_t j = 0; j < k; ++j) {
+    const float sj = sel[dims_k[1 + j]];
+    rank += (sj < si || (sj == si && j < i)) ? 1u : 0u;
+  }
+  order[rank] = i;
+}
+
 inline uint32_t blocks_for(uint64_t n, uint32_t t) { return static_cast<uint32_t>((n + t - 1) / t); }
 
 }  // namespace
@@ -341,6 +450,16 @@ hipError_t launch_targets(const float* sel, uint32_t n, uint32_t o, uint64_t n_r
   const double rows = static_cast<double>(n_rows);
   targets_kernel<<<blocks_for(total, 256), 256, 0, s>>>(
       sel, total, static_cast<float>(1.0 / rows), static_cast<float>(1.0 / std::log(rows)), t, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_order_fused(const OrderArgs& a, hipStream_t s) {
+  order_fused_kernel<<<1, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const float* sel, const uint32_t* dims_k, uint32_t* order, hipStream_t s) {
+  order_kernel<<<1, MDRQ_MAX_DIMS, 0, s>>>(sel, dims_k, order);
   return hipGetLastError();
 }
 

@@ -82,6 +82,25 @@ struct mdrq_estimator {
   DevBuf losses;
   std::vector<float> h_qd;
 
+  // One-query prediction (the per-query path of estimated ordering) as a captured HIP
+  // graph on its own stream: query upload, features, the three layers, the estimates
+  // and their download replay as one launch.  Its buffers never move.
+  // A second graph ends in the evaluation order of a plan's predicates, left in device
+  // memory for the scan that follows on the same stream.
+  hipStream_t stream = nullptr;
+  DevBuf one_work;           // work buffers for one row
+  DevBuf one_dev;            // qd (d x 3 floats), estimates (O), (k, dims[128]), order[128]
+  float* one_host = nullptr; // pinned: qd, estimates, (k, dims[128])
+  hipGraph_t one_graph = nullptr, order_graph = nullptr;
+  hipGraphExec_t one_exec = nullptr, order_exec = nullptr;
+  uint64_t qd_floats() const { return static_cast<uint64_t>(d) * 3; }
+  float* dev_qd() const { return one_dev.as<float>(); }
+  float* dev_sel() const { return dev_qd() + qd_floats(); }
+  uint32_t* dev_dims() const { return reinterpret_cast<uint32_t*>(dev_sel() + O); }
+  uint32_t* dev_order() const { return dev_dims() + 1 + MDRQ_MAX_DIMS; }
+  float* host_sel() const { return one_host + qd_floats(); }
+  uint32_t* host_dims() const { return reinterpret_cast<uint32_t*>(host_sel() + O); }
+
   float* params() const { return state; }
   float* grads() const { return state + n_params; }
   float* adam_m() const { return state + 2 * n_params; }
@@ -158,7 +177,8 @@ void build_qd(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n) {
 }
 
 // Features and base estimates of n queries into X and base (device) from qd (device).
-int features(mdrq_estimator* e, const float* qd_dev, uint32_t n, uint16_t* X, float* base) {
+int features(mdrq_estimator* e, const float* qd_dev, uint32_t n, uint16_t* X, float* base,
+             hipStream_t stream = nullptr) {
   FeatureArgs f{};
   f.qd = qd_dev;
   f.bounds = e->bounds;
@@ -169,7 +189,7 @@ int features(mdrq_estimator* e, const float* qd_dev, uint32_t n, uint16_t* X, fl
   const double rows = static_cast<double>(e->n_rows);
   f.inv_rows = static_cast<float>(1.0 / rows);
   f.inv_ln_rows = static_cast<float>(1.0 / std::log(rows));
-  EST_CHECK(launch_features(f, nullptr), "estimator features");
+  EST_CHECK(launch_features(f, stream), "estimator features");
   return MDRQ_OK;
 }
 
@@ -190,28 +210,34 @@ GemmArgs gemm(const uint16_t* a, uint64_t a_m, uint64_t a_k, const uint16_t* b, 
 }
 
 // Forward pass of `rows` rows whose features and base estimates are in the work
-// buffer's X and Bs: the network's output corrects the base estimate.
-int forward(mdrq_estimator* e, uint32_t rows) {
-  const auto L = e->layout(e->work_rows);
+// buffer's X and Bs: the network's output corrects the base estimate.  `work` (laid out
+// for `cap` rows) defaults to the estimator's own work buffer.
+int forward(mdrq_estimator* e, uint32_t rows, const DevBuf* work = nullptr, uint32_t cap = 0,
+            hipStream_t stream = nullptr) {
+  if (!work) {
+    work = &e->work;
+    cap = e->work_rows;
+  }
+  const auto L = e->layout(cap);
   const uint32_t F = e->F, H = e->H, O = e->O;
-  uint16_t* X = e->work.as<uint16_t>(L.X);
+  uint16_t* X = work->as<uint16_t>(L.X);
   GemmArgs g = gemm(X, F, 1, e->wb + e->oW1, H, 1, rows, H, F);
   g.bias = e->params() + e->ob1;
-  g.c = e->work.as<float>(L.Z1);
-  g.act = e->work.as<uint16_t>(L.H1);
+  g.c = work->as<float>(L.Z1);
+  g.act = work->as<uint16_t>(L.H1);
   g.gelu = 1;
-  EST_CHECK(launch_gemm(g, nullptr), "estimator layer 1");
-  g = gemm(e->work.as<uint16_t>(L.H1), H, 1, e->wb + e->oW2, H, 1, rows, H, H);
+  EST_CHECK(launch_gemm(g, stream), "estimator layer 1");
+  g = gemm(work->as<uint16_t>(L.H1), H, 1, e->wb + e->oW2, H, 1, rows, H, H);
   g.bias = e->params() + e->ob2;
-  g.c = e->work.as<float>(L.Z2);
-  g.act = e->work.as<uint16_t>(L.H2);
+  g.c = work->as<float>(L.Z2);
+  g.act = work->as<uint16_t>(L.H2);
   g.gelu = 1;
-  EST_CHECK(launch_gemm(g, nullptr), "estimator layer 2");
-  g = gemm(e->work.as<uint16_t>(L.H2), H, 1, e->wb + e->oW3, O, 1, rows, O, H);
+  EST_CHECK(launch_gemm(g, stream), "estimator layer 2");
+  g = gemm(work->as<uint16_t>(L.H2), H, 1, e->wb + e->oW3, O, 1, rows, O, H);
   g.bias = e->params() + e->ob3;
-  g.add = e->work.as<float>(L.Bs);
-  g.c = e->work.as<float>(L.Y);
-  EST_CHECK(launch_gemm(g, nullptr), "estimator layer 3");
+  g.add = work->as<float>(L.Bs);
+  g.c = work->as<float>(L.Y);
+  EST_CHECK(launch_gemm(g, stream), "estimator layer 3");
   return MDRQ_OK;
 }
 
@@ -362,6 +388,75 @@ int predict_locked(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, float*
   return MDRQ_OK;
 }
 
+// Buffers of the one-query graphs (allocated once, never moved).
+int ensure_one(mdrq_estimator* e) {
+  if (e->one_host) return MDRQ_OK;
+  const uint64_t floats = e->qd_floats() + e->O;
+  const uint64_t words = 2 * (1 + MDRQ_MAX_DIMS);
+  int rc;
+  if ((rc = e->one_work.grow(e->layout(1).end)) || (rc = e->one_dev.grow((floats + words) * 4))) return rc;
+  if (hipHostMalloc(reinterpret_cast<void**>(&e->one_host), (floats + words) * 4, hipHostMallocDefault) !=
+      hipSuccess)
+    return fail(MDRQ_ENOMEM, "estimator: pinned allocation failed");
+  if (!e->stream) EST_CHECK(hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking), "estimator stream");
+  return MDRQ_OK;
+}
+
+// Capture the one-query graph: upload the query (and, for `order`, the plan's
+// dimensions), features, the three layers, the estimates; then either download the
+// estimates or rank the plan's predicates into the device order buffer.
+int capture_one(mdrq_estimator* e, bool order, hipGraphExec_t* exec_out, hipGraph_t* graph_out) {
+  const auto L = e->layout(1);
+  EST_CHECK(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal), "graph capture");
+  hipError_t ce = hipMemcpyAsync(e->dev_qd(), e->one_host, e->qd_floats() * 4, hipMemcpyHostToDevice, e->stream);
+  if (ce == hipSuccess && order)
+    ce = hipMemcpyAsync(e->dev_dims(), e->host_dims(), (1 + MDRQ_MAX_DIMS) * 4, hipMemcpyHostToDevice,
+                        e->stream);
+  int rc = ce == hipSuccess ? features(e, e->dev_qd(), 1, e->one_work.as<uint16_t>(L.X),
+                                       e->one_work.as<float>(L.Bs), e->stream)
+                            : MDRQ_EDEVICE;
+  if (rc == MDRQ_OK) rc = forward(e, 1, &e->one_work, 1, e->stream);
+  if (rc == MDRQ_OK)
+    ce = launch_to_selectivity(e->one_work.as<float>(L.Y), e->dev_qd(), 1, e->d, e->n_rows, e->dev_sel(),
+                               e->stream);
+  if (rc == MDRQ_OK && ce == hipSuccess)
+    ce = order ? launch_order(e->dev_sel(), e->dev_dims(), e->dev_order(), e->stream)
+               : hipMemcpyAsync(e->host_sel(), e->dev_sel(), e->O * 4, hipMemcpyDeviceToHost, e->stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(e->stream, &graph);
+  if (rc != MDRQ_OK || ce != hipSuccess || ee != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc != MDRQ_OK ? rc : fail_hip(ce != hipSuccess ? ce : ee, "estimator graph capture");
+  }
+  *graph_out = graph;
+  EST_CHECK(hipGraphInstantiate(exec_out, graph, nullptr, nullptr, 0), "estimator graph instantiate");
+  return MDRQ_OK;
+}
+
+void fill_one(mdrq_estimator* e, const mdrq_query_t* q) {
+  std::memset(e->one_host, 0, e->qd_floats() * 4);
+  for (uint32_t k = 0; k < q->n_preds; ++k) {
+    const mdrq_pred& p = q->preds[k];
+    if (!restricts(p)) continue;
+    float* t = e->one_host + static_cast<uint64_t>(p.dim) * 3;
+    t[0] = p.lo;
+    t[1] = p.hi;
+    t[2] = 1.0f;
+  }
+}
+
+// One query through the captured graph (captured on first use).
+int predict_one(mdrq_estimator* e, const mdrq_query_t* q, float* sel) {
+  int rc = ensure_one(e);
+  if (rc) return rc;
+  if (!e->one_exec && (rc = capture_one(e, false, &e->one_exec, &e->one_graph))) return rc;
+  fill_one(e, q);
+  EST_CHECK(hipGraphLaunch(e->one_exec, e->stream), "estimator graph launch");
+  EST_CHECK(hipStreamSynchronize(e->stream), "estimator graph completion");
+  std::memcpy(sel, e->host_sel(), e->O * 4);
+  return MDRQ_OK;
+}
+
 }  // namespace
 
 namespace mdrq {
@@ -375,7 +470,7 @@ int estimate_for_order(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, std
   if (!any) return MDRQ_OK;
   std::lock_guard<std::mutex> lock(e->mu);
   est.resize(static_cast<size_t>(n) * e->O);
-  return predict_locked(e, qs, n, est.data());
+  return n == 1 ? predict_one(e, qs, est.data()) : predict_locked(e, qs, n, est.data());
 }
 
 void order_plan(Plan& plan, const float* est_row) {
@@ -395,6 +490,44 @@ void order_plan(Plan& plan, const float* est_row) {
 }
 
 void detach_estimator(mdrq_dataset* ds) { ds->estimator = nullptr; }
+
+int order_on_device(mdrq_dataset* ds, const mdrq_query_t* q, Plan& plan, hipStream_t stream,
+                    std::unique_lock<std::mutex>& hold) {
+  mdrq_estimator* e = ds->estimator;
+  if (!e || plan.preds.size() < 2) return MDRQ_OK;
+  hold = std::unique_lock<std::mutex>(e->mu);
+  int rc = ensure_one(e);
+  if (rc) return rc;
+  OrderArgs a{};
+  a.bounds = e->bounds;
+  a.wb = e->wb;
+  a.params = e->params();
+  a.oW1 = e->oW1;
+  a.ob1 = e->ob1;
+  a.oW2 = e->oW2;
+  a.ob2 = e->ob2;
+  a.oW3 = e->oW3;
+  a.ob3 = e->ob3;
+  a.d = e->d;
+  a.H = e->H;
+  a.k = static_cast<uint32_t>(plan.dims.size());
+  const double rows = static_cast<double>(e->n_rows);
+  a.inv_rows = static_cast<float>(1.0 / rows);
+  a.inv_ln_rows = static_cast<float>(1.0 / std::log(rows));
+  a.ln_rows = static_cast<float>(std::log(rows));
+  a.order = e->dev_order();
+  for (uint32_t k = 0; k < q->n_preds; ++k) {
+    const mdrq_pred& p = q->preds[k];
+    if (!restricts(p)) continue;
+    a.restricted[p.dim >> 5] |= 1u << (p.dim & 31);
+    a.lo[p.dim] = p.lo;
+    a.hi[p.dim] = p.hi;
+  }
+  for (size_t i = 0; i < plan.dims.size(); ++i) a.dims[i] = plan.dims[i];
+  EST_CHECK(launch_order_fused(a, stream), "estimator order launch");
+  plan.order = e->dev_order();
+  return MDRQ_OK;
+}
 
 }  // namespace mdrq
 
@@ -475,6 +608,14 @@ void mdrq_estimator_free(mdrq_estimator* e) {
   e->work.release();
   e->data.release();
   e->losses.release();
+  if (e->one_exec) (void)hipGraphExecDestroy(e->one_exec);
+  if (e->one_graph) (void)hipGraphDestroy(e->one_graph);
+  if (e->order_exec) (void)hipGraphExecDestroy(e->order_exec);
+  if (e->order_graph) (void)hipGraphDestroy(e->order_graph);
+  e->one_work.release();
+  e->one_dev.release();
+  if (e->one_host) (void)hipHostFree(e->one_host);
+  if (e->stream) (void)hipStreamDestroy(e->stream);
   delete e;
 }
 
@@ -697,7 +838,7 @@ int mdrq_estimator_predict(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n
   int rc = check_queries(e, qs, n);
   if (rc) return rc;
   std::lock_guard<std::mutex> lock(e->mu);
-  return predict_locked(e, qs, n, sel);
+  return n == 1 ? predict_one(e, qs, sel) : predict_locked(e, qs, n, sel);
 }
 
 int mdrq_attach_estimator(mdrq_dataset* ds, mdrq_estimator* e) {

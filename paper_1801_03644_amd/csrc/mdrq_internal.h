@@ -48,6 +48,7 @@ struct ScanParams {
   uint32_t* tile_counts;  // kStage: qualifying rows per tile
   uint32_t* block_sums;   // kStage: qualifying rows per workgroup segment
   ScanState* state;
+  const uint32_t* order;  // device: evaluation order of preds (null: as given)
   DevPred preds[MDRQ_MAX_DIMS];
 };
 
@@ -221,6 +222,7 @@ struct Plan {
   uint32_t mode = kIds;
   uint64_t capacity = 0;
   bool early_out = true;
+  const uint32_t* order = nullptr;  // device evaluation order, written by the estimator
 };
 
 // Thread-local error reporting.
@@ -256,6 +258,28 @@ namespace mdrq {
 int estimate_for_order(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n,
                        std::vector<float>& est);
 void order_plan(Plan& plan, const float* est_row);
+// Queue, on `stream`, the estimator's prediction for one query and the permutation of
+// the plan's predicates by ascending estimated selectivity into a device buffer
+// (plan.order); no host round trip.  The estimator stays locked through `hold` until
+// the caller's launches that read plan.order have completed.
+int order_on_device(mdrq_dataset* ds, const mdrq_query_t* q, Plan& plan, hipStream_t stream,
+                    std::unique_lock<std::mutex>& hold);
+hipError_t launch_order(const float* sel, const uint32_t* dims_k, uint32_t* order, hipStream_t s);
+
+// One query's evaluation order computed in one launch (features, network, ranking).
+struct OrderArgs {
+  const float* bounds;         // [dim][kBins + 1]
+  const uint16_t* wb;          // bfloat16 weights (W1, W2, W3 at their parameter offsets)
+  const float* params;         // float32 parameters (biases)
+  uint64_t oW1, ob1, oW2, ob2, oW3, ob3;
+  uint32_t d, H, k, pad;
+  float inv_rows, inv_ln_rows, ln_rows, pad2;
+  uint32_t* order;             // out: order[rank] = position in the plan
+  uint32_t restricted[MDRQ_MAX_DIMS / 32];  // bit j: dimension j is restricted
+  float lo[MDRQ_MAX_DIMS], hi[MDRQ_MAX_DIMS];
+  uint32_t dims[MDRQ_MAX_DIMS];             // the plan's dimensions, in plan order
+};
+hipError_t launch_order_fused(const OrderArgs& a, hipStream_t s);
 void detach_estimator(mdrq_dataset* ds);
 }  // namespace mdrq
 

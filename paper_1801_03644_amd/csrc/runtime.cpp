@@ -223,6 +223,7 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
   p.tile_counts = ds->tile_counts;
   p.block_sums = ds->block_sums;
   p.state = ds->state;
+  p.order = plan.order;
   for (size_t i = 0; i < plan.preds.size(); ++i) p.preds[i] = plan.preds[i];
   CompactParams c{};
   c.n_tiles = n_tiles;
@@ -390,11 +391,13 @@ int mdrq_query(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r, void* 
   if (rc) return rc;
   std::lock_guard<std::mutex> lock(ds->mu);
   Plan plan = make_plan(ds, q, r);
-  if (q->flags & MDRQ_Q_ORDER_ESTIMATED) {
-    std::vector<float> est;
-    rc = estimate_for_order(ds, q, 1, est);
+  // Estimated order: the estimator's graph ranks the predicates on the device, ahead of
+  // the scan on the same stream (no host round trip); it stays locked until the scan
+  // has completed.
+  std::unique_lock<std::mutex> est_hold;
+  if ((q->flags & MDRQ_Q_ORDER_ESTIMATED) && !plan.empty) {
+    rc = order_on_device(ds, q, plan, static_cast<hipStream_t>(stream), est_hold);
     if (rc) return rc;
-    if (!est.empty()) order_plan(plan, est.data());
   }
   r->mode = plan.mode == kBitmap ? MDRQ_OUT_BITMAP : plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
   return run_query(ds, plan, r, static_cast<hipStream_t>(stream));

@@ -70,15 +70,17 @@ using LaneMask = typename std::conditional<(U > 8), uint64_t, uint32_t>::type;
 // Live-row mask of one wave tile (bit 4u+e <=> row row0 + 256u + 4*lane + e) after
 // all predicates, for a tile lying entirely below n_rows.
 template <int U>
-__device__ __forceinline__ LaneMask<U> eval_full(const ScanParams& p, uint64_t row0, uint32_t lane) {
+__device__ __forceinline__ LaneMask<U> eval_full(const ScanParams& p, const uint32_t* ord, uint64_t row0,
+                                                 uint32_t lane) {
   using M = LaneMask<U>;
   M m = static_cast<M>(~M{0}) >> (8 * sizeof(M) - 4 * U);
   const uint32_t k_end = p.n_preds;
   for (uint32_t k = 0; k < k_end; ++k) {
     if (k > 0 && p.early_out && ballot(m != 0) == 0) break;
-    const float* c = p.preds[k].col + row0 + 4 * lane;
-    const float lo = p.preds[k].lo;
-    const float hi = p.preds[k].hi;
+    const uint32_t kk = ord ? ord[k] : k;
+    const float* c = p.preds[kk].col + row0 + 4 * lane;
+    const float lo = p.preds[kk].lo;
+    const float hi = p.preds[kk].hi;
     float4 v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -94,7 +96,7 @@ __device__ __forceinline__ LaneMask<U> eval_full(const ScanParams& p, uint64_t r
 // Same for the last, partial tile: element-wise loads of rows below n_rows only.
 // (Runs once per query: kept as plain loops so it does not raise register pressure.)
 template <int U>
-__device__ LaneMask<U> eval_tail(const ScanParams& p, uint64_t row0, uint32_t lane) {
+__device__ LaneMask<U> eval_tail(const ScanParams& p, const uint32_t* ord, uint64_t row0, uint32_t lane) {
   using M = LaneMask<U>;
   M m = 0;
 #pragma unroll 1
@@ -102,9 +104,10 @@ __device__ LaneMask<U> eval_tail(const ScanParams& p, uint64_t row0, uint32_t la
     if (row0 + 256 * (b >> 2) + 4 * lane + (b & 3) < p.n_rows) m |= M{1} << b;
 #pragma unroll 1
   for (uint32_t k = 0; k < p.n_preds; ++k) {
-    const float* c = p.preds[k].col + row0 + 4 * lane;
-    const float lo = p.preds[k].lo;
-    const float hi = p.preds[k].hi;
+    const uint32_t kk = ord ? ord[k] : k;
+    const float* c = p.preds[kk].col + row0 + 4 * lane;
+    const float lo = p.preds[kk].lo;
+    const float hi = p.preds[kk].hi;
 #pragma unroll 1
     for (int b = 0; b < 4 * U; ++b) {
       const M bit = M{1} << b;
@@ -123,10 +126,14 @@ template <int MODE, int U>
 __global__ void __launch_bounds__(kBlock) scan_kernel(ScanParams p) {
   constexpr uint32_t kTileRows = 256 * U;
   __shared__ uint32_t s_block_total;
+  __shared__ uint32_t s_order[MDRQ_MAX_DIMS];  // evaluation order, when one is given
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = threadIdx.x / kWave;
   uint32_t wave_count = 0;  // uniform per wave
   if (threadIdx.x == 0) s_block_total = 0;
+  if (p.order)
+    for (uint32_t i = threadIdx.x; i < p.n_preds; i += kBlock) s_order[i] = p.order[i];
+  const uint32_t* ord = p.order ? s_order : nullptr;
   __syncthreads();
 
   const uint64_t n_words = (p.n_rows + 63) / 64;
@@ -137,7 +144,7 @@ __global__ void __launch_bounds__(kBlock) scan_kernel(ScanParams p) {
   for (uint64_t tile = seg_beg + wave; tile < seg_end; tile += kWavesPerBlock) {
     const uint64_t row0 = tile * kTileRows;
     const bool full = row0 + kTileRows <= p.n_rows;
-    const LaneMask<U> m = full ? eval_full<U>(p, row0, lane) : eval_tail<U>(p, row0, lane);
+    const LaneMask<U> m = full ? eval_full<U>(p, ord, row0, lane) : eval_tail<U>(p, ord, row0, lane);
     if constexpr (MODE != kCount) {
       // Word w holds rows 64w .. 64w+63; lanes 8g .. 8g+7 hold 32 consecutive rows.
 #pragma unroll

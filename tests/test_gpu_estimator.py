@@ -121,6 +121,56 @@ def test_forward_matches_reference():
     assert np.median(dy) < 1e-4
 
 
+def test_one_query_graph_replays_match_eager_prediction():
+    """A single query is predicted by replaying a captured HIP graph; every replay must
+    equal the eager (many-query) prediction of the same query, also after training has
+    changed the weights between replays."""
+    w, raw = c4_small(30_000)
+    qs = queries_with_edges(w, 40, seed=12)
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds, seed=2) as est:
+        p = random_params(est, 6)
+        est.set_params(p)
+        sel = ds.label_selectivities(qs)
+        for rep in range(3):
+            eager = est.predict(qs)
+            for i in range(12):
+                one = est.predict([qs[i]])
+                assert np.array_equal(one[0], eager[i]), (rep, i)
+            est.train(qs, sel, epochs=1, batch=16, lr=1e-2, seed=rep)
+
+
+def test_estimated_order_is_exact_on_every_query_shape():
+    """Single queries in estimated order (the order computed on the device, ahead of
+    the scan on the same stream): ids, bitmap and count equal the oracle's for empty,
+    one-predicate, partial-match and all-20-dimension queries; repeated calls replay
+    the estimator's graph."""
+    from tests.gpu_helpers import bitmap_to_ids
+
+    w, raw = c4_small(60_001)
+    cols = oracle.prepare(raw)
+    qs = queries_with_edges(w, 40, seed=13)
+    rng = np.random.default_rng(13)
+    for _ in range(6):
+        preds = []
+        for j in range(20):
+            lo = float(rng.uniform(0, 0.2))
+            preds.append((j, lo, lo + float(rng.uniform(0.6, 0.8))))
+        qs.append(dg.make_query(preds))
+    qs.append(dg.make_query([]))
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds, seed=4) as est:
+        est.set_params(random_params(est, 9))
+        ds.attach_estimator(est)
+        for rep in range(2):
+            for i, q in enumerate(qs):
+                st, cnt, want = oracle.query(cols, q)
+                a, ids = run(ds, q, flags=mdrq.Q_ORDER_ESTIMATED)
+                assert a.count == cnt and np.array_equal(ids, want), (rep, i)
+                a, words = run(ds, q, mode="bitmap", flags=mdrq.Q_ORDER_ESTIMATED)
+                assert np.array_equal(bitmap_to_ids(words, ds.n_rows)[0], want), (rep, i)
+                assert run(ds, q, mode="count", flags=mdrq.Q_ORDER_ESTIMATED)[0].count == cnt
+        ds.attach_estimator(None)
+
+
 def test_parameters_round_trip_and_invalid():
     w, raw = c4_small(10_000)
     with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds, hidden=32, seed=3) as est:
