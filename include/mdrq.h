@@ -64,7 +64,8 @@ enum {
   MDRQ_OUT_IDS = 0,     /* ascending uint32 identifiers */
   MDRQ_OUT_BITMAP = 1,  /* uint64 words: bit (i % 64) of word i / 64 <=> object i qualifies */
   MDRQ_OUT_COUNT = 2,   /* the count only */
-  MDRQ_OUT_AUTO = 3     /* IDS or BITMAP, chosen by the planner; the choice is reported */
+  MDRQ_OUT_AUTO = 3     /* IDS or BITMAP, whichever is smaller for the exact count and fits
+                           buf_bytes (decided on the device); the choice is reported */
 };
 
 /* Query flags. */

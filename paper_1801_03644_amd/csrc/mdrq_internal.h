@@ -34,7 +34,7 @@ struct ScanState {
   uint64_t total;      // finished workgroups (bits 40..63) and their count (bits 0..39)
   uint64_t count_out;  // exact result size, written at the end of a launch
   uint32_t error;      // nonzero: the launch detected an inconsistency
-  uint32_t pad;
+  uint32_t kind;       // output chosen for MDRQ_OUT_AUTO: 1 bitmap, 0 identifiers
 };
 
 struct ScanParams {
@@ -63,6 +63,10 @@ struct CompactParams {
   uint32_t* ids;
   uint64_t capacity;           // identifiers the output holds
   uint64_t* count_out;         // exact result size (written by the last workgroup)
+  uint32_t auto_mode;          // 1: bitmap or identifiers, whichever is smaller and fits
+  uint32_t pad;
+  uint64_t buf_bytes;          // output bytes (auto_mode)
+  uint32_t* kind_out;          // auto_mode: 1 bitmap, 0 identifiers
 };
 
 // Launch one single-query scan.  `unroll` selects the tile height (float4 loads per
@@ -222,6 +226,7 @@ struct Plan {
   uint32_t mode = kIds;
   uint64_t capacity = 0;
   bool early_out = true;
+  bool auto_mode = false;          // MDRQ_OUT_AUTO: identifiers or bitmap, decided on device
   const uint32_t* order = nullptr;  // device evaluation order, written by the estimator
 };
 

@@ -130,6 +130,7 @@ Plan make_plan(const mdrq_dataset* ds, const mdrq_query_t* q, const mdrq_result_
     plan.dims.push_back(p.dim);
   }
   plan.mode = r->mode == MDRQ_OUT_BITMAP ? kBitmap : r->mode == MDRQ_OUT_COUNT ? kCount : kIds;
+  plan.auto_mode = r->mode == MDRQ_OUT_AUTO;
   plan.capacity = plan.mode == kIds ? r->buf_bytes / 4 : plan.mode == kBitmap ? r->buf_bytes / 8 : 0;
   plan.early_out = !(q->flags & MDRQ_Q_NO_EARLYOUT);
   return plan;
@@ -235,6 +236,9 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
   c.ids = static_cast<uint32_t*>(out);
   c.capacity = plan.mode == kIds ? out_elems : 0;
   c.count_out = &ds->state->count_out;
+  c.auto_mode = plan.auto_mode ? 1u : 0u;
+  c.buf_bytes = r->buf_bytes;
+  c.kind_out = &ds->state->kind;
 
   if (ds->profiling) {
     if (!ds->ev0) MDRQ_HIP(hipEventCreate(&ds->ev0), "hipEventCreate");
@@ -270,6 +274,14 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
   }
   const uint64_t count = ds->host_state->count_out;
   r->count = count;
+  if (plan.auto_mode && ds->host_state->kind == 1) {  // AUTO chose the bitmap
+    r->mode = MDRQ_OUT_BITMAP;
+    r->written = n_words(ds);
+    r->status = MDRQ_OK;
+    if (host_out) MDRQ_HIP(hipMemcpy(r->buf, ds->staging, r->written * 8, hipMemcpyDeviceToHost),
+                           "copy result to host");
+    return r->status;
+  }
   if (plan.mode == kIds) {
     r->written = std::min(count, plan.capacity);
     r->status = count > plan.capacity ? MDRQ_EOVERFLOW : MDRQ_OK;
@@ -517,7 +529,7 @@ int mdrq_probe_bandwidth(mdrq_dataset* ds, const uint32_t* dims, uint32_t k, uin
     if (dims[i] >= ds->n_dims) return fail(MDRQ_EINVAL, "dimension out of range");
     p.cols[i] = ds->cols[dims[i]];
   }
-  p.sink = reinterpret_cast<uint32_t*>(ds->state) + offsetof(ScanState, pad) / 4;
+  p.sink = reinterpret_cast<uint32_t*>(ds->state) + offsetof(ScanState, kind) / 4;  // a sink no query reads before writing
   const Device& dev = device();
   const int grid = static_cast<int>(static_cast<uint64_t>(scan_blocks_per_cu(kCount, ds->unroll)) * dev.cus);
   hipEvent_t e0, e1;

@@ -237,6 +237,23 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(CompactParams c) {
 
   const uint64_t seg_beg = static_cast<uint64_t>(blockIdx.x) * c.seg_tiles;
   const uint64_t seg_end = seg_beg + c.seg_tiles < c.n_tiles ? seg_beg + c.seg_tiles : c.n_tiles;
+  if (c.auto_mode) {
+    // Every workgroup sums all segment counts and takes the same decision: the bitmap
+    // when it is smaller than the identifiers (or only it fits) and the buffer holds it.
+    uint32_t all = 0;
+    for (uint32_t j = tid; j < gridDim.x; j += kBlock) all += c.block_sums[j];
+    const uint64_t total = block_exclusive_scan(all, ignore, s_wave);
+    const uint64_t bitmap_bytes = 8 * c.n_words;
+    const bool bitmap = c.buf_bytes >= bitmap_bytes &&
+                        (bitmap_bytes < 4 * total || c.buf_bytes < 4 * total);
+    if (blockIdx.x == 0 && tid == 0) *c.kind_out = bitmap ? 1u : 0u;
+    if (bitmap) {
+      uint64_t* dst = reinterpret_cast<uint64_t*>(c.ids);
+      const uint64_t w_end = seg_end * (kTileRows / 64) < c.n_words ? seg_end * (kTileRows / 64) : c.n_words;
+      for (uint64_t w = seg_beg * (kTileRows / 64) + tid; w < w_end; w += kBlock) dst[w] = c.bitmap[w];
+      return;
+    }
+  }
   for (uint64_t t0 = seg_beg; t0 < seg_end; t0 += kScanTiles) {
     const uint32_t nt = static_cast<uint32_t>(seg_end - t0 < kScanTiles ? seg_end - t0 : kScanTiles);
     // Exclusive offsets of tiles t0 .. t0+nt-1 (and the end) into LDS.

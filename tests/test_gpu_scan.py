@@ -246,3 +246,39 @@ def test_gpu_invariants():
         mn_mx = [ds.column_range(j) for j in range(3)]
         full = run(ds, dg.make_query([(j, a, b) for j, (a, b) in enumerate(mn_mx)]), mode="count")[0]
         assert full.count == n
+
+
+@pytest.mark.parametrize("host", [False, True])
+def test_auto_output_picks_the_smaller_exact_result(host):
+    """MDRQ_OUT_AUTO on a single query: the bitmap when it is smaller than the ids
+    (selectivity above 1/32) and the buffer holds it, otherwise the ids; decided on the
+    device from the exact count.  Both decode to the oracle's ids."""
+    import torch
+
+    n = 300_001
+    raw = [dg.column(61, j, dg.uniform(), n) for j in range(3)]
+    cols = oracle.prepare(raw)
+    n_words = (n + 63) // 64
+    cases = [((0, 0.0, 0.5),), ((0, 0.0, 0.001),), ((1, 0.2, 0.9), (2, 0.0, 0.3)),
+             ((1, 0.5, 0.2),), ((0, 0.0, 1.0), (1, 0.0, 1.0))]
+    with mdrq.Dataset.from_host(raw) as ds:
+        for preds in cases:
+            q = dg.make_query(list(preds))
+            st, cnt, want = oracle.query(cols, q)
+            for n_bytes in (8 * n_words, 4 * n, 8 * n_words - 8):
+                if host:
+                    out = np.zeros(n_bytes // 4, dtype=np.uint32)
+                else:
+                    out = torch.full((n_bytes // 4,), -1, dtype=torch.int32, device=device())
+                a = ds.query(q, out, mode="auto")
+                buf = (out if host else out.cpu().numpy()).view(np.uint8)
+                assert a.count == cnt
+                bitmap_wins = 8 * n_words < 4 * cnt or n_bytes < 4 * cnt
+                if n_bytes >= 8 * n_words and bitmap_wins:
+                    assert a.mode == "bitmap" and a.written == n_words
+                    assert np.array_equal(bitmap_to_ids(buf[:8 * n_words].view(np.uint64), n)[0], want)
+                else:
+                    assert a.mode == "ids"
+                    got = buf[:4 * a.written].view(np.uint32)
+                    assert np.array_equal(got, want[:len(got)])
+                    assert a.status == (mdrq.EOVERFLOW if cnt > n_bytes // 4 else mdrq.OK)
