@@ -372,8 +372,11 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
           b.rows_per_lane = batch_rows_per_lane(n_slots, w, rg);
           add(b);
         }
-      if (variant != 1 || n_slots > kMaxSlots)
+      if (variant != 1 || n_slots > kMaxSlots) {
+        bool any = false;
         for (int rg : {8, 4, 2, 1}) {
+          // one 64-row group per lane only where nothing larger fits (it is slower)
+          if (rg == 1 && any) break;
           if (((g + 3) & ~uint64_t{3}) * 4 + batch_lds_key_bytes(std::max(1, n_slots), w, rg) > device().lds)
             continue;
           BatchConfig b;
@@ -382,7 +385,9 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
           b.rows_per_lane = rg;
           b.lds = 1;
           add(b);
+          any = true;
         }
+      }
     }
   }
   if (c.empty()) {  // the smallest LDS configuration: run_shared shrinks it to fit
