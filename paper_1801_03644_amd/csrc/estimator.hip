@@ -1,16 +1,19 @@
 // Learned selectivity estimator: kernels for gfx950.
 //
-// A small MLP (features -> 64 -> 64 -> d+1, GELU) estimates the selectivity of each
-// queried dimension and of the whole query.  The paper notes that evaluating the most
-// selective dimension first needs selectivity estimates (section 2.2.4) and leaves it
-// as future work (section 8); the estimator only orders dimensions and sizes result
-// buffers, so results never depend on it.
+// A small MLP (features -> 64 -> 64 -> d+1, GELU) corrects histogram estimates of the
+// selectivity of each queried dimension and of the whole query.  The paper notes that
+// evaluating the most selective dimension first needs selectivity estimates (section
+// 2.2.4) and leaves it as future work (section 8); the estimator only orders a query's
+// predicates, so results never depend on it.
 //
 // Kernels:
 //  * sample_sort_kernel: per column, a strided sample of up to 16384 rows sorted by a
 //    bitonic network in LDS; equi-depth boundaries are read off the sorted sample.
-//  * features_kernel: per (query, dimension) the histogram CDF of both bounds and the
-//    covered fraction of each bin, written as bfloat16 rows.
+//  * features_kernel: per (query, dimension) the histogram CDF of both bounds, the
+//    histogram estimate and the covered fraction of each bin, written as bfloat16 rows,
+//    and the base estimate the network corrects.
+//  * order_fused_kernel: one query's features, network and the ranking of its
+//    predicates in one workgroup, ahead of the scan on the same stream.
 //  * gemm_bf16_kernel: C = A * B with bfloat16 operands and float32 accumulation on the
 //    matrix cores (v_mfma_f32_16x16x16_bf16); one wave per 16x16 tile of C, operands
 //    read through strides so that transposed products need no copies.
@@ -373,24 +376,6 @@ __global__ void __launch_bounds__(256) order_fused_kernel(OrderArgs a_) {
   }
 }
 
-// Evaluation order from estimates: dims_k = (k, dims[0..k)) of a plan; thread i ranks
-// predicate i by its dimension's estimated selectivity (ties keep plan order) and
-// writes order[rank] = i.
-__global__ void __launch_bounds__(MDRQ_MAX_DIMS) order_kernel(const float* sel,
-                                                              const uint32_t* dims_k,
-                                                              uint32_t* order) {
-  const uint32_t k = dims_k[0];
-  const uint32_t i = threadIdx.x;
-  if (i >= k) return;
-  const float si = sel[dims_k[1 + i]];
-  uint32_t rank = 0;
-  for (uint32_t j = 0; j < k; ++j) {
-    const float sj = sel[dims_k[1 + j]];
-    rank += (sj < si || (sj == si && j < i)) ? 1u : 0u;
-  }
-  order[rank] = i;
-}
-
 inline uint32_t blocks_for(uint64_t n, uint32_t t) { return static_cast<uint32_t>((n + t - 1) / t); }
 
 }  // namespace
@@ -458,10 +443,6 @@ hipError_t launch_order_fused(const OrderArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_order(const float* sel, const uint32_t* dims_k, uint32_t* order, hipStream_t s) {
-  order_kernel<<<1, MDRQ_MAX_DIMS, 0, s>>>(sel, dims_k, order);
-  return hipGetLastError();
-}
 
 hipError_t launch_to_selectivity(const float* y, const float* qd, uint32_t n, uint32_t d,
                                  uint64_t n_rows, float* sel, hipStream_t s) {

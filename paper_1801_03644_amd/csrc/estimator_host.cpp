@@ -85,21 +85,19 @@ struct mdrq_estimator {
   // One-query prediction (the per-query path of estimated ordering) as a captured HIP
   // graph on its own stream: query upload, features, the three layers, the estimates
   // and their download replay as one launch.  Its buffers never move.
-  // A second graph ends in the evaluation order of a plan's predicates, left in device
+  // The evaluation order of a plan's predicates (order_fused_kernel) is left in device
   // memory for the scan that follows on the same stream.
   hipStream_t stream = nullptr;
   DevBuf one_work;           // work buffers for one row
-  DevBuf one_dev;            // qd (d x 3 floats), estimates (O), (k, dims[128]), order[128]
-  float* one_host = nullptr; // pinned: qd, estimates, (k, dims[128])
-  hipGraph_t one_graph = nullptr, order_graph = nullptr;
-  hipGraphExec_t one_exec = nullptr, order_exec = nullptr;
+  DevBuf one_dev;            // qd (d x 3 floats), estimates (O floats), order[128]
+  float* one_host = nullptr; // pinned: qd, estimates
+  hipGraph_t one_graph = nullptr;
+  hipGraphExec_t one_exec = nullptr;
   uint64_t qd_floats() const { return static_cast<uint64_t>(d) * 3; }
   float* dev_qd() const { return one_dev.as<float>(); }
   float* dev_sel() const { return dev_qd() + qd_floats(); }
-  uint32_t* dev_dims() const { return reinterpret_cast<uint32_t*>(dev_sel() + O); }
-  uint32_t* dev_order() const { return dev_dims() + 1 + MDRQ_MAX_DIMS; }
+  uint32_t* dev_order() const { return reinterpret_cast<uint32_t*>(dev_sel() + O); }
   float* host_sel() const { return one_host + qd_floats(); }
-  uint32_t* host_dims() const { return reinterpret_cast<uint32_t*>(host_sel() + O); }
 
   float* params() const { return state; }
   float* grads() const { return state + n_params; }
@@ -392,7 +390,7 @@ int predict_locked(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, float*
 int ensure_one(mdrq_estimator* e) {
   if (e->one_host) return MDRQ_OK;
   const uint64_t floats = e->qd_floats() + e->O;
-  const uint64_t words = 2 * (1 + MDRQ_MAX_DIMS);
+  const uint64_t words = MDRQ_MAX_DIMS;
   int rc;
   if ((rc = e->one_work.grow(e->layout(1).end)) || (rc = e->one_dev.grow((floats + words) * 4))) return rc;
   if (hipHostMalloc(reinterpret_cast<void**>(&e->one_host), (floats + words) * 4, hipHostMallocDefault) !=
@@ -402,16 +400,12 @@ int ensure_one(mdrq_estimator* e) {
   return MDRQ_OK;
 }
 
-// Capture the one-query graph: upload the query (and, for `order`, the plan's
-// dimensions), features, the three layers, the estimates; then either download the
-// estimates or rank the plan's predicates into the device order buffer.
-int capture_one(mdrq_estimator* e, bool order, hipGraphExec_t* exec_out, hipGraph_t* graph_out) {
+// Capture the one-query graph: upload the query, features, the three layers, the
+// estimates and their download.
+int capture_one(mdrq_estimator* e, hipGraphExec_t* exec_out, hipGraph_t* graph_out) {
   const auto L = e->layout(1);
   EST_CHECK(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal), "graph capture");
   hipError_t ce = hipMemcpyAsync(e->dev_qd(), e->one_host, e->qd_floats() * 4, hipMemcpyHostToDevice, e->stream);
-  if (ce == hipSuccess && order)
-    ce = hipMemcpyAsync(e->dev_dims(), e->host_dims(), (1 + MDRQ_MAX_DIMS) * 4, hipMemcpyHostToDevice,
-                        e->stream);
   int rc = ce == hipSuccess ? features(e, e->dev_qd(), 1, e->one_work.as<uint16_t>(L.X),
                                        e->one_work.as<float>(L.Bs), e->stream)
                             : MDRQ_EDEVICE;
@@ -420,8 +414,7 @@ int capture_one(mdrq_estimator* e, bool order, hipGraphExec_t* exec_out, hipGrap
     ce = launch_to_selectivity(e->one_work.as<float>(L.Y), e->dev_qd(), 1, e->d, e->n_rows, e->dev_sel(),
                                e->stream);
   if (rc == MDRQ_OK && ce == hipSuccess)
-    ce = order ? launch_order(e->dev_sel(), e->dev_dims(), e->dev_order(), e->stream)
-               : hipMemcpyAsync(e->host_sel(), e->dev_sel(), e->O * 4, hipMemcpyDeviceToHost, e->stream);
+    ce = hipMemcpyAsync(e->host_sel(), e->dev_sel(), e->O * 4, hipMemcpyDeviceToHost, e->stream);
   hipGraph_t graph = nullptr;
   const hipError_t ee = hipStreamEndCapture(e->stream, &graph);
   if (rc != MDRQ_OK || ce != hipSuccess || ee != hipSuccess) {
@@ -449,7 +442,7 @@ void fill_one(mdrq_estimator* e, const mdrq_query_t* q) {
 int predict_one(mdrq_estimator* e, const mdrq_query_t* q, float* sel) {
   int rc = ensure_one(e);
   if (rc) return rc;
-  if (!e->one_exec && (rc = capture_one(e, false, &e->one_exec, &e->one_graph))) return rc;
+  if (!e->one_exec && (rc = capture_one(e, &e->one_exec, &e->one_graph))) return rc;
   fill_one(e, q);
   EST_CHECK(hipGraphLaunch(e->one_exec, e->stream), "estimator graph launch");
   EST_CHECK(hipStreamSynchronize(e->stream), "estimator graph completion");
@@ -610,8 +603,6 @@ void mdrq_estimator_free(mdrq_estimator* e) {
   e->losses.release();
   if (e->one_exec) (void)hipGraphExecDestroy(e->one_exec);
   if (e->one_graph) (void)hipGraphDestroy(e->one_graph);
-  if (e->order_exec) (void)hipGraphExecDestroy(e->order_exec);
-  if (e->order_graph) (void)hipGraphDestroy(e->order_graph);
   e->one_work.release();
   e->one_dev.release();
   if (e->one_host) (void)hipHostFree(e->one_host);

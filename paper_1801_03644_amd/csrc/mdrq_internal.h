@@ -269,7 +269,6 @@ void order_plan(Plan& plan, const float* est_row);
 // the caller's launches that read plan.order have completed.
 int order_on_device(mdrq_dataset* ds, const mdrq_query_t* q, Plan& plan, hipStream_t stream,
                     std::unique_lock<std::mutex>& hold);
-hipError_t launch_order(const float* sel, const uint32_t* dims_k, uint32_t* order, hipStream_t s);
 
 // One query's evaluation order computed in one launch (features, network, ranking).
 struct OrderArgs {
