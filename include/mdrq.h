@@ -238,8 +238,9 @@ enum {
                                  0 = autotune */
   MDRQ_OPT_BATCH_VARIANT = 8  /* shared scans: 1 = the union's keys in registers (unions
                                  of up to 16 columns; wider ones use LDS), 2 = keys
-                                 staged in LDS (any union, up to MDRQ_MAX_DIMS columns);
-                                 0 = autotune (default) */
+                                 staged in LDS (any union, up to MDRQ_MAX_DIMS columns),
+                                 3 = keys in registers with each query's predicates
+                                 evaluated in column order; 0 = autotune (default) */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
 

@@ -15,9 +15,12 @@
 //    unsigned compare:  lo <= x <= hi  <=>  key(x) - key(lo) <= key(hi) - key(lo).
 //    The compare lands in a 64-bit wave mask, which is directly bitmap word g of the
 //    chunk (bit l <=> row 64g + l).
-//  * The union's keys sit in registers (D slots x RG); the query table sits in LDS.
-//    Per query, predicates run in the query's order and a query stops as soon as all
-//    its masks are zero.  RG rows per lane amortise the per-predicate table read.
+//  * The union's keys sit in registers (D slots x RG) and the query table in LDS; a
+//    predicate's register slot is found by uniform branches, either searched per
+//    predicate (the query's own order) or walked slot by slot with each query's
+//    predicates sorted by slot (fewer branches).  A query stops as soon as all its
+//    masks are zero.  RG rows per lane amortise the per-predicate work.  A second
+//    variant stages the keys in LDS instead, for unions wider than the registers hold.
 //  * The bitmap scratch is zeroed first; per (query, chunk) only non-zero masks are
 //    stored; per (query, 4096-row tile) the count is accumulated in LDS and stored.
 //  * Finishing takes two launches: one workgroup per query sums its tile counts (the
@@ -52,7 +55,11 @@ struct TabPred {
 // workgroup's group is evaluated; non-zero wave masks are stored as bitmap words
 // (the scratch was zeroed), and the chunk's count is added to the query's tile
 // count in LDS.
-template <int D, int W, int RG>
+//
+// WALK: the host has sorted each query's predicates by slot, and the slots are walked
+// in order (one uniform compare per slot and query) instead of searching each
+// predicate's slot (up to one compare per slot and predicate).
+template <int D, int W, int RG, bool WALK>
 __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
   static_assert(W * RG <= 64, "a tile must hold at least one chunk per wave");
   extern __shared__ uint32_t lds[];
@@ -78,6 +85,9 @@ __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
     for (uint32_t cw = 0; cw < kChunksPerWave; ++cw) {
       const uint64_t row0 = tile * 4096 + (wave * kChunksPerWave + cw) * kChunkRows;
       if (row0 >= bp.n_rows) break;
+      // Rows past the end get the key 0, below the key of every non-NaN float (bounds
+      // are never NaN: the smallest, key(-inf), is 0x007FFFFF), so the first predicate
+      // of every query rejects them.
       uint32_t x[D][RG];
       const bool full = row0 + kChunkRows <= bp.n_rows;
 #pragma unroll
@@ -99,9 +109,38 @@ __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
         const TabPred* tp = reinterpret_cast<const TabPred*>(rec + 4);
         rec += 4 + 4 * np;
         uint64_t m[RG];
+        if (np != 0) {
 #pragma unroll
-        for (int g = 0; g < RG; ++g) m[g] = ballot(row0 + 64 * g + lane < bp.n_rows);
+          for (int g = 0; g < RG; ++g) m[g] = ~uint64_t{0};
+        } else {  // no predicate: every row of the chunk that exists
+#pragma unroll
+          for (int g = 0; g < RG; ++g) m[g] = ballot(row0 + 64 * g + lane < bp.n_rows);
+        }
         bool dead = false;
+        if constexpr (WALK) {
+          uint32_t pi = 0;
+          uint32_t slot = np ? __builtin_amdgcn_readfirstlane(tp[0].slot) : static_cast<uint32_t>(D);
+#pragma unroll
+          for (int S = 0; S < D; ++S)
+            if (slot == static_cast<uint32_t>(S)) {
+              const uint32_t klo = __builtin_amdgcn_readfirstlane(tp[pi].klo);
+              const uint32_t kw = __builtin_amdgcn_readfirstlane(tp[pi].kw);
+#pragma unroll
+              for (int g = 0; g < RG; ++g) m[g] &= ballot(x[S][g] - klo <= kw);
+              ++pi;
+              slot = pi < np ? __builtin_amdgcn_readfirstlane(tp[pi].slot) : static_cast<uint32_t>(D);
+              // Early break of the whole chunk, tested after every second predicate.
+              if (!(pi & 1) && pi < np) {
+                uint64_t any = 0;
+#pragma unroll
+                for (int g = 0; g < RG; ++g) any |= m[g];
+                if (any == 0) {
+                  dead = true;
+                  slot = static_cast<uint32_t>(D);
+                }
+              }
+            }
+        } else {
 #pragma unroll 1
         for (uint32_t pi = 0; pi < np; ++pi) {
           const TabPred t = tp[pi];
@@ -126,6 +165,7 @@ __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
               break;
             }
           }
+        }
         }
         if (dead) continue;
         uint32_t c = 0;
@@ -465,25 +505,26 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
 }
 
 template <int D, int W, int RG>
-const void* scan_fn() {
-  return reinterpret_cast<const void*>(&batch_scan_kernel<D, W, RG>);
+const void* scan_fn(bool walk) {
+  return walk ? reinterpret_cast<const void*>(&batch_scan_kernel<D, W, RG, true>)
+              : reinterpret_cast<const void*>(&batch_scan_kernel<D, W, RG, false>);
 }
 
 // Register budget: D slots x RG rows per lane stays at or below 128 VGPRs.
-const void* pick_batch(int d, int w, int rg) {
+const void* pick_batch(int d, int w, int rg, bool walk) {
   const int dd = d <= 4 ? 4 : d <= 8 ? 8 : 16;
   if (dd == 4) {
-    if (rg == 16) return scan_fn<4, 4, 16>();
-    if (rg == 8) return w == 8 ? scan_fn<4, 8, 8>() : scan_fn<4, 4, 8>();
-    return w == 8 ? scan_fn<4, 8, 4>() : scan_fn<4, 4, 4>();
+    if (rg == 16) return scan_fn<4, 4, 16>(walk);
+    if (rg == 8) return w == 8 ? scan_fn<4, 8, 8>(walk) : scan_fn<4, 4, 8>(walk);
+    return w == 8 ? scan_fn<4, 8, 4>(walk) : scan_fn<4, 4, 4>(walk);
   }
   if (dd == 8) {
-    if (rg == 16) return scan_fn<8, 4, 16>();
-    if (rg == 8) return w == 8 ? scan_fn<8, 8, 8>() : scan_fn<8, 4, 8>();
-    return w == 8 ? scan_fn<8, 8, 4>() : scan_fn<8, 4, 4>();
+    if (rg == 16) return scan_fn<8, 4, 16>(walk);
+    if (rg == 8) return w == 8 ? scan_fn<8, 8, 8>(walk) : scan_fn<8, 4, 8>(walk);
+    return w == 8 ? scan_fn<8, 8, 4>(walk) : scan_fn<8, 4, 4>(walk);
   }
-  if (rg >= 8) return w == 8 ? scan_fn<16, 8, 8>() : scan_fn<16, 4, 8>();
-  return w == 8 ? scan_fn<16, 8, 4>() : scan_fn<16, 4, 4>();
+  if (rg >= 8) return w == 8 ? scan_fn<16, 8, 8>(walk) : scan_fn<16, 4, 8>(walk);
+  return w == 8 ? scan_fn<16, 8, 4>(walk) : scan_fn<16, 4, 4>(walk);
 }
 
 const void* pick_lds(int w, int rg) {
@@ -522,8 +563,8 @@ int batch_rows_per_lane(int n_slots, int waves, int rg) {
 int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t lds_bytes) {
   int blocks = 0;
   const int w = waves == 8 ? 8 : 4;
-  const void* fn = lds_variant ? pick_lds(w, rg)
-                               : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg));
+  const void* fn = lds_variant == 1 ? pick_lds(w, rg)
+                                    : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg), lds_variant == 2);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, w * 64, lds_bytes) != hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;
@@ -540,8 +581,8 @@ hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int 
     if (e != hipSuccess) return e;
   }
   void* args[] = {const_cast<BatchParams*>(&bp)};
-  const void* fn = lds_variant ? pick_lds(w, rg)
-                               : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg));
+  const void* fn = lds_variant == 1 ? pick_lds(w, rg)
+                                    : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg), lds_variant == 2);
   if (lds_bytes > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds_bytes));

@@ -76,17 +76,34 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   const uint64_t nw = n_words(ds);
   const uint64_t n_tiles = (n_rows + kTileRows - 1) / kTileRows;
 
-  // Union of the queried columns -> register slots.
+  // Union of the queried columns -> register slots, numbered by the columns' mean
+  // relative position in the queries' evaluation orders (given or estimated), so that
+  // a walk over the slots in order follows those orders as closely as one order can.
   std::vector<int> slot_of(ds->n_dims, -1);
   std::vector<uint32_t> slot_dim;
-  for (const Item& it : items)
-    for (uint32_t d : it.plan.dims)
+  std::vector<double> pos_sum(ds->n_dims, 0.0);
+  std::vector<uint32_t> uses(ds->n_dims, 0);
+  for (const Item& it : items) {
+    const size_t k = it.plan.dims.size();
+    for (size_t i = 0; i < k; ++i) {
+      const uint32_t d = it.plan.dims[i];
+      pos_sum[d] += (i + 0.5) / static_cast<double>(k);
+      uses[d] += 1;
       if (slot_of[d] < 0) {
-        slot_of[d] = static_cast<int>(slot_dim.size());
+        slot_of[d] = 0;
         slot_dim.push_back(d);
       }
+    }
+  }
+  std::stable_sort(slot_dim.begin(), slot_dim.end(), [&](uint32_t a, uint32_t b) {
+    return pos_sum[a] / uses[a] < pos_sum[b] / uses[b];
+  });
+  for (size_t i = 0; i < slot_dim.size(); ++i) slot_of[slot_dim[i]] = static_cast<int>(i);
   const int n_slots = static_cast<int>(slot_dim.size());
 
+  const bool use_lds = cfg.lds == 1 || n_slots > kMaxSlots;
+  const bool walk = cfg.lds == 2 && !use_lds;
+  const int variant = use_lds ? 1 : walk ? 2 : 0;
   // Queries per group: what the configuration asks for, and no more than fits LDS.
   uint64_t group = cfg.group ? cfg.group : nq;
   std::vector<uint32_t> group_first, group_table, table;
@@ -119,7 +136,13 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       table.push_back(0u);
       table.push_back(0u);
       table.push_back(0u);
-      for (size_t i = 0; i < pl.preds.size(); ++i) {
+      // The slot walk needs each query's predicates in ascending slot order.
+      std::vector<size_t> ord(pl.preds.size());
+      for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+      if (walk)
+        std::sort(ord.begin(), ord.end(),
+                  [&](size_t a, size_t b) { return slot_of[pl.dims[a]] < slot_of[pl.dims[b]]; });
+      for (size_t i : ord) {
         const uint32_t klo = batch_key(pl.preds[i].lo);
         const uint32_t khi = batch_key(pl.preds[i].hi);
         table.push_back(static_cast<uint32_t>(slot_of[pl.dims[i]]));
@@ -219,7 +242,6 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   fin.kind_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws.d_res) + nq * 8);
 
   int waves = cfg.waves == 8 ? 8 : 4;
-  const bool use_lds = cfg.lds || n_slots > kMaxSlots;
   int rg;
   size_t lds;
   if (use_lds) {
@@ -241,7 +263,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     rg = batch_rows_per_lane(std::max(1, n_slots), waves, cfg.rows_per_lane);
     lds = max_group_words * 4;
   }
-  const int per_cu = batch_blocks_per_cu(std::max(1, n_slots), waves, rg, use_lds ? 1 : 0, lds);
+  const int per_cu = batch_blocks_per_cu(std::max(1, n_slots), waves, rg, variant, lds);
   const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
   const uint64_t gx = std::max<uint64_t>(1, std::min<uint64_t>(n_tiles, resident / n_groups));
 
@@ -251,7 +273,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
            "copy query table");
   MDRQ_HIP(hipEventRecord(ws.ev0, stream), "hipEventRecord");
   if (n_tiles > 0)
-    MDRQ_HIP(launch_batch_scan(bp, std::max(1, n_slots), waves, rg, use_lds ? 1 : 0,
+    MDRQ_HIP(launch_batch_scan(bp, std::max(1, n_slots), waves, rg, variant,
                                dim3(static_cast<uint32_t>(gx), n_groups), lds, stream),
              "shared scan launch");
   MDRQ_HIP(launch_batch_finish(fin, static_cast<uint32_t>(nq), stream), "batch finish launch");
@@ -365,14 +387,17 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
     if (g < 16 && g != nq) continue;
     for (int w : {4, 8}) {
       if (n_slots <= kMaxSlots && variant != 2)
-        for (int rg : {16, 8, 4}) {
-          BatchConfig b;
-          b.waves = w;
-          b.group = static_cast<uint32_t>(g);
-          b.rows_per_lane = batch_rows_per_lane(n_slots, w, rg);
-          add(b);
-        }
-      if (variant != 1 || n_slots > kMaxSlots) {
+        for (int rg : {16, 8, 4})
+          for (int v : {0, 2}) {
+            if ((variant == 1 && v != 0) || (variant == 3 && v != 2)) continue;
+            BatchConfig b;
+            b.waves = w;
+            b.group = static_cast<uint32_t>(g);
+            b.rows_per_lane = batch_rows_per_lane(n_slots, w, rg);
+            b.lds = v;
+            add(b);
+          }
+      if (variant == 0 || variant == 2 || n_slots > kMaxSlots) {
         bool any = false;
         for (int rg : {8, 4, 2, 1}) {
           // one 64-row group per lane only where nothing larger fits (it is slower)
@@ -456,7 +481,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     cfg.waves = ds->batch_waves ? ds->batch_waves : 4;
     cfg.group = ds->batch_group;
     cfg.rows_per_lane = ds->batch_rows ? ds->batch_rows : 16;
-    cfg.lds = ds->batch_variant == 2 ? 1 : 0;
+    cfg.lds = ds->batch_variant == 2 ? 1 : ds->batch_variant == 3 ? 2 : 0;
     if (used > kMaxSlots && !ds->batch_rows) cfg.rows_per_lane = used > 32 ? 1 : 2;
     const bool fixed = ds->batch_waves || ds->batch_group || ds->batch_rows || ds->batch_variant ||
                        !ds->autotune;

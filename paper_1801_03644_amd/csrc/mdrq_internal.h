@@ -131,8 +131,10 @@ uint32_t batch_key(float x);
 int batch_rows_per_lane(int n_slots, int waves, int rg);
 int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t lds_bytes);
 // Shared-scan launch.  lds_variant 0: union keys in registers (n_slots <= kMaxSlots,
-// query table in LDS); 1: union keys staged in LDS (n_slots <= kMaxUnion, query table
-// read with scalar loads).  lds_bytes: the dynamic LDS of the launch.
+// query table in LDS), each predicate's slot searched; 2: the same with each query's
+// predicates sorted by slot and the slots walked in order; 1: union keys staged in LDS
+// (n_slots <= kMaxUnion, query table read with scalar loads).  lds_bytes: the dynamic
+// LDS of the launch.
 hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, int lds_variant,
                              dim3 grid, size_t lds_bytes, hipStream_t stream);
 // LDS bytes the LDS variant stages keys in: waves x slots x rows per lane x 64 x 4.
@@ -333,7 +335,8 @@ struct BatchConfig {
   int waves = 4;                 // waves per workgroup (4 or 8)
   uint32_t group = 0;            // queries per workgroup group (0 = all)
   int rows_per_lane = 16;        // 64-row groups per lane per chunk: 2, 4, 8 or 16
-  int lds = 0;                   // 1: keys staged in LDS (any union up to kMaxUnion)
+  int lds = 0;                   // 1: keys staged in LDS (any union up to kMaxUnion);
+                                 // 2: keys in registers, predicates walked in slot order
 };
 }  // namespace mdrq
 
@@ -376,7 +379,8 @@ struct mdrq_dataset {
   int batch_waves = 0;                   // 0: autotuned
   uint32_t batch_group = 0;              // 0: autotuned
   int batch_rows = 0;                    // 64-row groups per lane (2, 4, 8, 16); 0: autotuned
-  int batch_variant = 0;                 // 1: union keys in registers, 2: in LDS; 0: autotuned
+  int batch_variant = 0;                 // 1: keys in registers, 2: in LDS, 3: registers and
+                                         // slot-order walk; 0: autotuned
   bool autotune = true;
   std::vector<std::pair<uint64_t, mdrq::BatchConfig>> tuned;  // shape key -> config
   uint64_t batch_launches = 0;

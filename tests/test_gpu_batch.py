@@ -166,7 +166,7 @@ def test_union_beyond_register_slots_and_long_queries():
         check_batch(ds, cols, qs, ["ids", "auto"] * 20, "union")
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("variant", [0, 2, 3])
 def test_wide_unions_share_one_scan(variant):
     """40 columns: the union of all 40 is staged in LDS and the batch shares one scan
     (forced LDS variant, or autotuned).  Ragged row count."""
@@ -211,6 +211,7 @@ def test_launch_configurations_give_identical_results():
         for waves, group, tune, variant, rows in [
                 (0, 0, 1, 0, 0), (4, 0, 0, 1, 0), (8, 0, 0, 1, 0), (4, 16, 0, 1, 0), (8, 24, 0, 1, 0),
                 (4, 0, 0, 2, 2), (4, 0, 0, 2, 4), (8, 0, 0, 2, 8), (4, 16, 0, 2, 8), (8, 24, 0, 2, 4),
+                (4, 0, 0, 3, 8), (8, 0, 0, 3, 8), (4, 16, 0, 3, 16), (4, 0, 0, 2, 1),
                 (0, 0, 1, 0, 0)]:
             ds.set_option(mdrq.OPT_BATCH_WAVES, waves)
             ds.set_option(mdrq.OPT_BATCH_GROUP, group)
