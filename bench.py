@@ -156,7 +156,7 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(row sharding across GPUs is a design note, not code).", file=sys.stderr)
         sys.exit(2)
 
