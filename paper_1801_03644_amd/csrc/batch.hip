@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
 #pragma unroll
         for (int s = 0; s < D; ++s)
           x[s][g] = (s < static_cast<int>(bp.n_slots) && (full || r < bp.n_rows))
-                        ? dkey(bp.slot_cols[s][r]) : 0u;
+                        ? dkey(__builtin_nontemporal_load(&bp.slot_cols[s][r])) : 0u;
       }
       const uint64_t word0 = row0 / 64;
       // Records are contiguous: each is a 4-word header and 4 words per predicate.
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
 #pragma unroll
           for (int v = 0; v < V; ++v) {
             const uint64_t r = row0 + 64 * (q * V + v) + lane;
-            k[v] = (full || r < bp.n_rows) ? dkey(col[r]) : 0xFFFFFFFFu;
+            k[v] = (full || r < bp.n_rows) ? dkey(__builtin_nontemporal_load(&col[r])) : 0xFFFFFFFFu;
           }
           vec kv;
           if constexpr (V == 1) {

