@@ -240,7 +240,9 @@ enum {
                                  of up to 16 columns; wider ones use LDS), 2 = keys
                                  staged in LDS (any union, up to MDRQ_MAX_DIMS columns),
                                  3 = keys in registers with each query's predicates
-                                 evaluated in column order; 0 = autotune (default) */
+                                 evaluated in column order, 4 = keys in registers with
+                                 fixed-size query records (a slot mask and the bounds of
+                                 every slot); 0 = autotune (default) */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
 

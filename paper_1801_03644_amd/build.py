@@ -49,9 +49,15 @@ def build_datagen() -> str:
     return DATAGEN_LIB
 
 
+# Per-file additions.  The shared-scan kernels add to their LDS counts from one lane
+# with a wave-uniform value; the compiler's atomic optimizer would wrap each such add
+# in a wave reduction that does nothing here.
+FILE_FLAGS = {"batch.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *HIP_FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *HIP_FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     subprocess.check_call(cmd)

@@ -45,7 +45,8 @@ __device__ __forceinline__ uint32_t dkey(float x) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-// One query-table predicate, read from LDS as one 16-byte entry.
+// One query-table predicate, one 16-byte entry: the register slot, key(lo), and
+// key(hi) - key(lo) (register variants) or key(hi) (LDS variant).
 struct TabPred {
   uint32_t slot, klo, kw, pad;
 };
@@ -191,12 +192,159 @@ __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
   }
 }
 
-// ---------------------------------------------------------------- LDS-staged variant
-
 // The query table is read-only for the whole launch and every access to it is
 // wave-uniform: reading it through the constant address space gives scalar loads.
 typedef __attribute__((address_space(4))) const uint32_t cu32;
 typedef __attribute__((address_space(4))) const TabPred ctabpred;
+
+// ---------------------------------------------------------------- slot-mask variant
+
+// lo <= x <= hi on order-preserving keys  <=>  med3(x, lo, hi) == x.  The result is
+// folded into a per-lane word that stays zero while the row qualifies, so a range
+// test is two vector instructions (v_med3_u32, then v_bitop3_b32 for acc |= m ^ x)
+// and no scalar work.  gfx9 VOP3 reads at most one scalar operand, hence hi in a VGPR.
+__device__ __forceinline__ uint32_t med3u(uint32_t x, uint32_t lo, uint32_t hi) {
+  uint32_t r;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=&v"(r) : "v"(x), "s"(lo), "v"(hi));
+  return r;
+}
+
+// Order-preserving key from the raw bits of a non-NaN float (as dkey).
+__device__ __forceinline__ uint32_t bkey(uint32_t b) {
+  if (b == 0x80000000u) b = 0u;
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// As batch_scan_kernel, with fixed-size query records read by scalar loads: the
+// header, the query's slot mask (bit S: a predicate on slot S; bit 16 + S: test for
+// the early break after it), then (key(lo), key(hi)) for every slot S < D.  A query
+// walks the slots in order and tests those in its mask; the record of the next query
+// is loaded while the current one is tested.  A query without predicates carries
+// [key(-inf), key(+inf)] on slot 0, which every row passes except those past the end.
+template <int D>
+struct RegRecord {
+  static constexpr uint32_t kWords = 2 + 2 * D;
+};
+
+template <int D, int W, int RG>
+__global__ void __launch_bounds__(W * 64) batch_reg_kernel(BatchParams bp) {
+  static_assert(W * RG <= 64, "a tile must hold at least one chunk per wave");
+  constexpr uint32_t R = RegRecord<D>::kWords;
+  extern __shared__ uint32_t lds[];
+  const uint32_t group = blockIdx.y;
+  const uint32_t q_beg = bp.group_first[group];
+  const uint32_t nq = bp.group_first[group + 1] - q_beg;
+  cu32* recs = (cu32*)(bp.table) + bp.group_table[group];  // generic -> constant address space
+  uint32_t* s_cnt = lds;
+  for (uint32_t i = threadIdx.x; i < nq; i += W * 64) s_cnt[i] = 0;
+  __syncthreads();
+
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // wave-uniform
+  const uint32_t ns = bp.n_slots;
+  constexpr uint32_t kChunkRows = 64 * RG;
+  constexpr uint32_t kChunksPerWave = 4096 / kChunkRows / W;
+  for (uint64_t tile = blockIdx.x; tile < bp.n_tiles; tile += gridDim.x) {
+#pragma unroll 1
+    for (uint32_t cw = 0; cw < kChunksPerWave; ++cw) {
+      const uint64_t row0 = tile * 4096 + (wave * kChunksPerWave + cw) * kChunkRows;
+      if (row0 >= bp.n_rows) break;
+      const bool full = row0 + kChunkRows <= bp.n_rows;
+      // All loads of the chunk first (rows clamped into the column), keys after, so the
+      // loads are in flight together.  Rows past the end get the key 0, below
+      // key(-inf) = 0x007FFFFF, the smallest bound key: every predicate rejects them.
+      uint32_t x[D][RG];
+#pragma unroll
+      for (int g = 0; g < RG; ++g) {
+        const uint64_t r = row0 + 64 * g + lane;
+        const uint64_t rc = r < bp.n_rows ? r : bp.n_rows - 1;
+#pragma unroll
+        for (int s = 0; s < D; ++s)
+          x[s][g] = s < static_cast<int>(ns)
+                        ? __float_as_uint(__builtin_nontemporal_load(&bp.slot_cols[s][rc])) : 0u;
+      }
+#pragma unroll
+      for (int g = 0; g < RG; ++g) {
+        const bool valid = full || row0 + 64 * g + lane < bp.n_rows;
+#pragma unroll
+        for (int s = 0; s < D; ++s) x[s][g] = valid ? bkey(x[s][g]) : 0u;
+      }
+      const uint64_t word0 = row0 / 64;
+
+      auto load_rec = [&](uint32_t* rr, uint32_t qi) {
+        cu32* p = recs + qi * R;
+#pragma unroll
+        for (uint32_t i = 0; i < R; ++i) rr[i] = p[i];
+      };
+      // The query's predicates in slot order; true if the whole chunk is rejected (an
+      // early break clears the remaining mask, so the walk falls through its slots).
+      auto walk = [&](const uint32_t* rr, uint32_t* acc) -> bool {
+        uint32_t sm = rr[1];
+#pragma unroll
+        for (int S = 0; S < D; ++S) {
+          if (sm & (1u << S)) {
+            const uint32_t klo = rr[2 + 2 * S];
+            const uint32_t khi = rr[3 + 2 * S];
+            uint32_t t[RG];
+#pragma unroll
+            for (int g = 0; g < RG; ++g) t[g] = med3u(x[S][g], klo, khi);
+#pragma unroll
+            for (int g = 0; g < RG; ++g) acc[g] |= t[g] ^ x[S][g];
+            if (sm & (0x10000u << S)) {
+              uint32_t mn = acc[0];
+#pragma unroll
+              for (int g = 1; g < RG; ++g) mn = mn < acc[g] ? mn : acc[g];
+              if (ballot(mn == 0) == 0) sm = 0;
+            }
+          }
+        }
+        return sm == 0;
+      };
+      auto process = [&](const uint32_t* rr, uint32_t qi) {
+        uint32_t acc[RG];
+#pragma unroll
+        for (int g = 0; g < RG; ++g) acc[g] = 0;
+        if (walk(rr, acc)) return;
+        uint64_t m[RG];
+        uint32_t c = 0;
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+          m[g] = ballot(acc[g] == 0);
+          c += __popcll(m[g]);
+        }
+        if (c == 0) return;
+        const uint32_t head = rr[0];
+        if (lane == 0) atomicAdd(&s_cnt[qi], c);
+        if (((head >> 8) & 0x3u) != kBatchCount) {
+          uint64_t* words = bp.words + static_cast<uint64_t>(head >> 16) * bp.n_words + word0;
+#pragma unroll
+          for (int g = 0; g < RG; ++g)
+            if (m[g] != 0 && lane == 0) words[g] = m[g];
+        }
+      };
+      // Two record buffers in turn: the next record is loaded while one is tested.
+      uint32_t ra[R], rb[R];
+      load_rec(ra, 0);
+#pragma unroll 1
+      for (uint32_t qi = 0; qi < nq; qi += 2) {
+        load_rec(rb, qi + 1 < nq ? qi + 1 : qi);
+        process(ra, qi);
+        if (qi + 1 >= nq) break;
+        load_rec(ra, qi + 2 < nq ? qi + 2 : qi + 1);
+        process(rb, qi + 1);
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nq; i += W * 64) {
+      bp.tile_counts[static_cast<uint64_t>(q_beg + i) * bp.n_tiles + tile] = s_cnt[i];
+      s_cnt[i] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- LDS-staged variant
+
 
 __device__ __forceinline__ TabPred load_pred(ctabpred* p) {
   TabPred t;
@@ -289,38 +437,41 @@ __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
 #pragma unroll 1
       for (uint32_t qi = 0; qi < nq; ++qi) {
         const uint32_t head = rec[0];
-        const uint32_t np = head & 0xFFu;
+        const uint32_t np = head & 0xFFu;   // >= 1: the host gives an empty query an
+                                            // always-true predicate
         const uint32_t kind = (head >> 8) & 0x3u;
         ctabpred* tp = reinterpret_cast<ctabpred*>(rec + 4);
         rec += 4 + 4 * np;
-        uint64_t m[RG];
-        if (np != 0) {
+        // acc[g] stays zero in lanes whose row passes every predicate so far.
+        uint32_t acc[RG];
 #pragma unroll
-          for (int g = 0; g < RG; ++g) m[g] = ~uint64_t{0};
-        } else {  // no predicate: every row of the chunk that exists
-#pragma unroll
-          for (int g = 0; g < RG; ++g) m[g] = ballot(row0 + 64 * g + lane < bp.n_rows);
-        }
-        // Predicates in the query's order, two at a time; the early break of the
-        // whole chunk is tested after each pair.
+        for (int g = 0; g < RG; ++g) acc[g] = 0;
         auto apply = [&](const TabPred& t) {
           const uint32_t* kp = keys + t.slot * (NQ * 64 * V);
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
             const vec kv = *reinterpret_cast<const vec*>(kp + q * 64 * V);
+            uint32_t k[V];
             if constexpr (V == 1) {
-              m[q] &= ballot(kv - t.klo <= t.kw);
+              k[0] = kv;
             } else if constexpr (V == 2) {
-              m[q * V + 0] &= ballot(kv.x - t.klo <= t.kw);
-              m[q * V + 1] &= ballot(kv.y - t.klo <= t.kw);
+              k[0] = kv.x;
+              k[1] = kv.y;
             } else {
-              m[q * V + 0] &= ballot(kv.x - t.klo <= t.kw);
-              m[q * V + 1] &= ballot(kv.y - t.klo <= t.kw);
-              m[q * V + 2] &= ballot(kv.z - t.klo <= t.kw);
-              m[q * V + 3] &= ballot(kv.w - t.klo <= t.kw);
+              k[0] = kv.x;
+              k[1] = kv.y;
+              k[2] = kv.z;
+              k[3] = kv.w;
             }
+            uint32_t r[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) r[v] = med3u(k[v], t.klo, t.kw);  // kw holds key(hi) here
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[q * V + v] |= r[v] ^ k[v];
           }
         };
+        // Predicates in the query's order, two at a time; the early break of the
+        // whole chunk is tested after each pair.
         bool dead = false;
         uint32_t pi = 0;
 #pragma unroll 1
@@ -329,10 +480,10 @@ __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
           apply(t0);
           apply(t1);
           if (pi + 2 < np) {
-            uint64_t any = 0;
+            uint32_t mn = acc[0];
 #pragma unroll
-            for (int g = 0; g < RG; ++g) any |= m[g];
-            if (any == 0) {
+            for (int g = 1; g < RG; ++g) mn = mn < acc[g] ? mn : acc[g];
+            if (ballot(mn == 0) == 0) {
               dead = true;
               break;
             }
@@ -340,9 +491,13 @@ __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
         }
         if (dead) continue;
         if (pi < np) apply(load_pred(tp + pi));
+        uint64_t m[RG];
         uint32_t c = 0;
 #pragma unroll
-        for (int g = 0; g < RG; ++g) c += __popcll(m[g]);
+        for (int g = 0; g < RG; ++g) {
+          m[g] = ballot(acc[g] == 0);
+          c += __popcll(m[g]);
+        }
         if (c != 0) {
           if (lane == 0) atomicAdd(&s_cnt[qi], c);
           if (kind != kBatchCount) {
@@ -527,6 +682,27 @@ const void* pick_batch(int d, int w, int rg, bool walk) {
   return w == 8 ? scan_fn<16, 8, 4>(walk) : scan_fn<16, 4, 4>(walk);
 }
 
+template <int D, int W, int RG>
+const void* reg_fn() {
+  return reinterpret_cast<const void*>(&batch_reg_kernel<D, W, RG>);
+}
+
+const void* pick_reg(int d, int w, int rg) {
+  const int dd = d <= 4 ? 4 : d <= 8 ? 8 : 16;
+  if (dd == 4) {
+    if (rg == 16) return reg_fn<4, 4, 16>();
+    if (rg == 8) return w == 8 ? reg_fn<4, 8, 8>() : reg_fn<4, 4, 8>();
+    return w == 8 ? reg_fn<4, 8, 4>() : reg_fn<4, 4, 4>();
+  }
+  if (dd == 8) {
+    if (rg == 16) return reg_fn<8, 4, 16>();
+    if (rg == 8) return w == 8 ? reg_fn<8, 8, 8>() : reg_fn<8, 4, 8>();
+    return w == 8 ? reg_fn<8, 8, 4>() : reg_fn<8, 4, 4>();
+  }
+  if (rg >= 8) return w == 8 ? reg_fn<16, 8, 8>() : reg_fn<16, 4, 8>();
+  return w == 8 ? reg_fn<16, 8, 4>() : reg_fn<16, 4, 4>();
+}
+
 const void* pick_lds(int w, int rg) {
   if (rg >= 8) return w == 8 ? reinterpret_cast<const void*>(&batch_lds_kernel<8, 8>)
                              : reinterpret_cast<const void*>(&batch_lds_kernel<4, 8>);
@@ -549,6 +725,8 @@ uint32_t batch_key(float x) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
+int batch_reg_slots(int n_slots) { return n_slots <= 4 ? 4 : n_slots <= 8 ? 8 : 16; }
+
 size_t batch_lds_key_bytes(int n_slots, int waves, int rg) {
   return static_cast<size_t>(waves == 8 ? 8 : 4) * n_slots * lds_rows(rg) * 64 * 4;
 }
@@ -563,8 +741,9 @@ int batch_rows_per_lane(int n_slots, int waves, int rg) {
 int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t lds_bytes) {
   int blocks = 0;
   const int w = waves == 8 ? 8 : 4;
-  const void* fn = lds_variant == 1 ? pick_lds(w, rg)
-                                    : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg), lds_variant == 2);
+  const void* fn = lds_variant == 1   ? pick_lds(w, rg)
+                   : lds_variant == 3 ? pick_reg(n_slots, w, batch_rows_per_lane(n_slots, w, rg))
+                                      : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg), lds_variant == 2);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, w * 64, lds_bytes) != hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;
@@ -581,8 +760,9 @@ hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int 
     if (e != hipSuccess) return e;
   }
   void* args[] = {const_cast<BatchParams*>(&bp)};
-  const void* fn = lds_variant == 1 ? pick_lds(w, rg)
-                                    : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg), lds_variant == 2);
+  const void* fn = lds_variant == 1   ? pick_lds(w, rg)
+                   : lds_variant == 3 ? pick_reg(n_slots, w, batch_rows_per_lane(n_slots, w, rg))
+                                      : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg), lds_variant == 2);
   if (lds_bytes > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds_bytes));

@@ -19,6 +19,7 @@ namespace {
 
 constexpr uint64_t kTileRows = 4096;
 constexpr uint64_t kMaxLdsTable = 60 * 1024;   // bytes of query table per workgroup
+constexpr uint64_t kMaxRegGroup = 4096;         // queries per workgroup, slot-mask variant
 
 template <typename T>
 int grow_device(T** p, uint64_t* have, uint64_t need, const char* what) {
@@ -98,12 +99,17 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   std::stable_sort(slot_dim.begin(), slot_dim.end(), [&](uint32_t a, uint32_t b) {
     return pos_sum[a] / uses[a] < pos_sum[b] / uses[b];
   });
+  // The slot-mask and LDS variants give a query without predicates an always-true one
+  // on slot 0 (it rejects only the rows past the end), so the union has at least one
+  // column.
+  if ((cfg.lds == 1 || cfg.lds == 3) && slot_dim.empty()) slot_dim.push_back(0);
   for (size_t i = 0; i < slot_dim.size(); ++i) slot_of[slot_dim[i]] = static_cast<int>(i);
   const int n_slots = static_cast<int>(slot_dim.size());
 
   const bool use_lds = cfg.lds == 1 || n_slots > kMaxSlots;
   const bool walk = cfg.lds == 2 && !use_lds;
-  const int variant = use_lds ? 1 : walk ? 2 : 0;
+  const bool reg = cfg.lds == 3 && !use_lds;
+  const int variant = use_lds ? 1 : walk ? 2 : reg ? 3 : 0;
   // Queries per group: what the configuration asks for, and no more than fits LDS.
   uint64_t group = cfg.group ? cfg.group : nq;
   std::vector<uint32_t> group_first, group_table, table;
@@ -113,13 +119,49 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     outs[q].kind = items[q].kind;
     outs[q].out_index = items[q].kind == kBatchCount ? 0u : n_out++;
   }
+  // Slot-mask variant: fixed-size records (header, slot mask, then key(lo), key(hi)
+  // for every register slot), read by scalar loads, so a group is not limited by LDS.
+  const uint32_t reg_slots = static_cast<uint32_t>(batch_reg_slots(std::max(1, n_slots)));
+  for (uint64_t q0 = 0; reg && q0 < nq;) {
+    const uint64_t q1 = std::min<uint64_t>(nq, q0 + std::min<uint64_t>(group, kMaxRegGroup));
+    group_first.push_back(static_cast<uint32_t>(q0));
+    group_table.push_back(static_cast<uint32_t>(table.size()));
+    for (uint64_t q = q0; q < q1; ++q) {
+      const Plan& pl = items[q].plan;
+      const uint64_t base = table.size();
+      table.resize(base + 2 + 2 * reg_slots, 0u);
+      table[base] = static_cast<uint32_t>(pl.preds.size()) | (outs[q].kind << 8) |
+                    (outs[q].out_index << 16);
+      if (pl.preds.empty()) {
+        table[base + 1] = 1u;
+        table[base + 2] = batch_key(-std::numeric_limits<float>::infinity());
+        table[base + 3] = batch_key(std::numeric_limits<float>::infinity());
+      }
+      for (size_t i = 0; i < pl.preds.size(); ++i) {
+        const uint32_t s = static_cast<uint32_t>(slot_of[pl.dims[i]]);
+        table[base + 1] |= 1u << s;
+        table[base + 2 + 2 * s] = batch_key(pl.preds[i].lo);
+        table[base + 3 + 2 * s] = batch_key(pl.preds[i].hi);
+      }
+      // Early-break tests after every second predicate in slot order, but not after
+      // the last one.
+      uint32_t seen = 0;
+      for (uint32_t s = 0; s < reg_slots; ++s)
+        if ((table[base + 1] >> s) & 1u) {
+          ++seen;
+          if (seen % 2 == 0 && seen < pl.preds.size()) table[base + 1] |= 0x10000u << s;
+        }
+    }
+    q0 = q1;
+  }
   // Group table: record offsets (padded to 4 words), then per query a 4-word header
-  // and one 4-word entry (slot, key(lo), key(hi) - key(lo), 0) per predicate.
-  for (uint64_t q0 = 0; q0 < nq;) {
+  // and one 4-word entry (slot, key(lo), key(hi) - key(lo) or, for the LDS variant,
+  // key(hi), 0) per predicate.
+  for (uint64_t q0 = 0; !reg && q0 < nq;) {
     // Grow the group while its table and counts fit LDS.
     uint64_t words = 0, q1 = q0;
     while (q1 < nq && q1 - q0 < group) {
-      const uint64_t add = 4 + 4 * items[q1].plan.preds.size() + 2;  // record, offset, count
+      const uint64_t add = 8 + 4 * items[q1].plan.preds.size() + 2;  // record, offset, count
       if ((words + add + 8) * 4 > kMaxLdsTable && q1 > q0) break;
       words += add;
       ++q1;
@@ -131,11 +173,18 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     for (uint64_t q = q0; q < q1; ++q) {
       table[base + (q - q0)] = static_cast<uint32_t>(table.size() - base);
       const Plan& pl = items[q].plan;
-      table.push_back(static_cast<uint32_t>(pl.preds.size()) | (outs[q].kind << 8) |
+      const bool always = use_lds && pl.preds.empty();   // the always-true predicate
+      table.push_back(static_cast<uint32_t>(always ? 1 : pl.preds.size()) | (outs[q].kind << 8) |
                       (outs[q].out_index << 16));
       table.push_back(0u);
       table.push_back(0u);
       table.push_back(0u);
+      if (always) {
+        table.push_back(0u);
+        table.push_back(batch_key(-std::numeric_limits<float>::infinity()));
+        table.push_back(batch_key(std::numeric_limits<float>::infinity()));
+        table.push_back(0u);
+      }
       // The slot walk needs each query's predicates in ascending slot order.
       std::vector<size_t> ord(pl.preds.size());
       for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
@@ -147,7 +196,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
         const uint32_t khi = batch_key(pl.preds[i].hi);
         table.push_back(static_cast<uint32_t>(slot_of[pl.dims[i]]));
         table.push_back(klo);
-        table.push_back(khi - klo);
+        table.push_back(use_lds ? khi : khi - klo);   // the LDS variant takes key(hi)
         table.push_back(0u);
       }
     }
@@ -159,7 +208,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   uint64_t max_group_words = 0;
   for (uint32_t g = 0; g < n_groups; ++g)
     max_group_words = std::max<uint64_t>(
-        max_group_words, (group_table[g + 1] - group_table[g]) +
+        max_group_words, (reg ? 0 : group_table[g + 1] - group_table[g]) +
                              ((group_first[g + 1] - group_first[g] + 3) & ~uint64_t{3}));
 
   // Outputs: device buffers directly, host buffers through device staging.
@@ -388,8 +437,9 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
     for (int w : {4, 8}) {
       if (n_slots <= kMaxSlots && variant != 2)
         for (int rg : {16, 8, 4})
-          for (int v : {0, 2}) {
-            if ((variant == 1 && v != 0) || (variant == 3 && v != 2)) continue;
+          for (int v : {0, 2, 3}) {
+            if ((variant == 1 && v != 0) || (variant == 3 && v != 2) || (variant == 4 && v != 3))
+              continue;
             BatchConfig b;
             b.waves = w;
             b.group = static_cast<uint32_t>(g);
@@ -480,8 +530,9 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     BatchConfig cfg;
     cfg.waves = ds->batch_waves ? ds->batch_waves : 4;
     cfg.group = ds->batch_group;
-    cfg.rows_per_lane = ds->batch_rows ? ds->batch_rows : 16;
-    cfg.lds = ds->batch_variant == 2 ? 1 : ds->batch_variant == 3 ? 2 : 0;
+    cfg.rows_per_lane = ds->batch_rows ? ds->batch_rows : 8;
+    // Untuned default: the slot-mask register variant (fastest on every measured shape).
+    cfg.lds = ds->batch_variant == 1 ? 0 : ds->batch_variant == 2 ? 1 : ds->batch_variant == 3 ? 2 : 3;
     if (used > kMaxSlots && !ds->batch_rows) cfg.rows_per_lane = used > 32 ? 1 : 2;
     const bool fixed = ds->batch_waves || ds->batch_group || ds->batch_rows || ds->batch_variant ||
                        !ds->autotune;
