@@ -181,7 +181,7 @@ def batched(args):
                   "plain_queries_per_s": big["plain_queries_per_s"],
                   "roofline": {"bound": "alu", "achieved": ach, "peak": ALU_TESTS_PEAK,
                                "unit": "row-predicate tests/s", "frac": ach / ALU_TESTS_PEAK,
-                               "traffic": None, "kernel": "batch_scan_kernel (+ finish)",
+                               "traffic": None, "kernel": "shared scan, autotuned variant (+ finish)",
                                "note": "tests = sum over queries of (queried dims x rows), the "
                                        "work without early-out; peak = one 32-bit compare per "
                                        "lane and clock (256 CUs x 64 lanes x 2.4 GHz)"}})

@@ -442,10 +442,19 @@ __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
         const uint32_t kind = (head >> 8) & 0x3u;
         ctabpred* tp = reinterpret_cast<ctabpred*>(rec + 4);
         rec += 4 + 4 * np;
-        // acc[g] stays zero in lanes whose row passes every predicate so far.
+        // Two forms of the range test.  With four or more rows per lane: the median of
+        // three folded into acc[g], which stays zero in lanes whose row passes every
+        // predicate so far (vector work only).  With fewer: subtract and compare into
+        // the wave masks m[g] (one scalar AND per test, but no per-predicate setup to
+        // amortise over few rows).
+        constexpr bool kMed3 = RG >= 4;
         uint32_t acc[RG];
+        uint64_t m[RG];
 #pragma unroll
-        for (int g = 0; g < RG; ++g) acc[g] = 0;
+        for (int g = 0; g < RG; ++g) {
+          acc[g] = 0;
+          m[g] = ~uint64_t{0};
+        }
         auto apply = [&](const TabPred& t) {
           const uint32_t* kp = keys + t.slot * (NQ * 64 * V);
 #pragma unroll
@@ -463,11 +472,30 @@ __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
               k[2] = kv.z;
               k[3] = kv.w;
             }
-            uint32_t r[V];
+            if constexpr (kMed3) {
+              uint32_t r[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) r[v] = med3u(k[v], t.klo, t.kw);  // kw holds key(hi) here
+              for (int v = 0; v < V; ++v) r[v] = med3u(k[v], t.klo, t.kw);  // kw: key(hi)
 #pragma unroll
-            for (int v = 0; v < V; ++v) acc[q * V + v] |= r[v] ^ k[v];
+              for (int v = 0; v < V; ++v) acc[q * V + v] |= r[v] ^ k[v];
+            } else {
+              const uint32_t w = t.kw - t.klo;
+#pragma unroll
+              for (int v = 0; v < V; ++v) m[q * V + v] &= ballot(k[v] - t.klo <= w);
+            }
+          }
+        };
+        auto all_rejected = [&]() {
+          if constexpr (kMed3) {
+            uint32_t mn = acc[0];
+#pragma unroll
+            for (int g = 1; g < RG; ++g) mn = mn < acc[g] ? mn : acc[g];
+            return ballot(mn == 0) == 0;
+          } else {
+            uint64_t any = 0;
+#pragma unroll
+            for (int g = 0; g < RG; ++g) any |= m[g];
+            return any == 0;
           }
         };
         // Predicates in the query's order, two at a time; the early break of the
@@ -479,23 +507,17 @@ __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
           const TabPred t0 = load_pred(tp + pi), t1 = load_pred(tp + pi + 1);
           apply(t0);
           apply(t1);
-          if (pi + 2 < np) {
-            uint32_t mn = acc[0];
-#pragma unroll
-            for (int g = 1; g < RG; ++g) mn = mn < acc[g] ? mn : acc[g];
-            if (ballot(mn == 0) == 0) {
-              dead = true;
-              break;
-            }
+          if (pi + 2 < np && all_rejected()) {
+            dead = true;
+            break;
           }
         }
         if (dead) continue;
         if (pi < np) apply(load_pred(tp + pi));
-        uint64_t m[RG];
         uint32_t c = 0;
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
-          m[g] = ballot(acc[g] == 0);
+          if constexpr (kMed3) m[g] = ballot(acc[g] == 0);
           c += __popcll(m[g]);
         }
         if (c != 0) {

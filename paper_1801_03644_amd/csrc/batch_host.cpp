@@ -530,7 +530,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     BatchConfig cfg;
     cfg.waves = ds->batch_waves ? ds->batch_waves : 4;
     cfg.group = ds->batch_group;
-    cfg.rows_per_lane = ds->batch_rows ? ds->batch_rows : 8;
+    cfg.rows_per_lane = ds->batch_rows ? ds->batch_rows : used > 8 ? 4 : 8;
     // Untuned default: the slot-mask register variant (fastest on every measured shape).
     cfg.lds = ds->batch_variant == 1 ? 0 : ds->batch_variant == 2 ? 1 : ds->batch_variant == 3 ? 2 : 3;
     if (used > kMaxSlots && !ds->batch_rows) cfg.rows_per_lane = used > 32 ? 1 : 2;
