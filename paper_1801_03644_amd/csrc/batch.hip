@@ -710,7 +710,7 @@ const void* reg_fn() {
 }
 
 const void* pick_reg(int d, int w, int rg) {
-  const int dd = d <= 4 ? 4 : d <= 8 ? 8 : 16;
+  const int dd = batch_reg_slots(d);
   if (dd == 4) {
     if (rg == 16) return reg_fn<4, 4, 16>();
     if (rg == 8) return w == 8 ? reg_fn<4, 8, 8>() : reg_fn<4, 4, 8>();
@@ -720,6 +720,10 @@ const void* pick_reg(int d, int w, int rg) {
     if (rg == 16) return reg_fn<8, 4, 16>();
     if (rg == 8) return w == 8 ? reg_fn<8, 8, 8>() : reg_fn<8, 4, 8>();
     return w == 8 ? reg_fn<8, 8, 4>() : reg_fn<8, 4, 4>();
+  }
+  if (dd == 12) {
+    if (rg >= 8) return w == 8 ? reg_fn<12, 8, 8>() : reg_fn<12, 4, 8>();
+    return w == 8 ? reg_fn<12, 8, 4>() : reg_fn<12, 4, 4>();
   }
   if (rg >= 8) return w == 8 ? reg_fn<16, 8, 8>() : reg_fn<16, 4, 8>();
   return w == 8 ? reg_fn<16, 8, 4>() : reg_fn<16, 4, 4>();
@@ -747,7 +751,9 @@ uint32_t batch_key(float x) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-int batch_reg_slots(int n_slots) { return n_slots <= 4 ? 4 : n_slots <= 8 ? 8 : 16; }
+int batch_reg_slots(int n_slots) {
+  return n_slots <= 4 ? 4 : n_slots <= 8 ? 8 : n_slots <= 12 ? 12 : 16;
+}
 
 size_t batch_lds_key_bytes(int n_slots, int waves, int rg) {
   return static_cast<size_t>(waves == 8 ? 8 : 4) * n_slots * lds_rows(rg) * 64 * 4;

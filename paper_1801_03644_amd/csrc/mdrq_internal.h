@@ -138,7 +138,7 @@ int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t 
 // query table read with scalar loads).  lds_bytes: the dynamic LDS of the launch.
 hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, int lds_variant,
                              dim3 grid, size_t lds_bytes, hipStream_t stream);
-// Register slots of the slot-mask variant for a union of n_slots columns (4, 8 or 16):
+// Register slots of the slot-mask variant for a union of n_slots columns (4, 8, 12 or 16):
 // its query records hold 2 + 2 x that many words.
 int batch_reg_slots(int n_slots);
 // LDS bytes the LDS variant stages keys in: waves x slots x rows per lane x 64 x 4.
