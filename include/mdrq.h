@@ -158,7 +158,9 @@ typedef struct {
   uint32_t n_streams;       /* 1 .. 8 */
   uint32_t use_estimator;   /* 1: every request evaluates its predicates in estimated
                                order (needs an attached estimator) */
-  uint32_t reserved;
+  uint32_t max_queue;       /* live server: requests allowed to wait; a submission
+                               beyond it fails with MDRQ_EBUSY (admission control).
+                               0 = unbounded.  The replay ignores it. */
 } mdrq_serve_config_t;
 
 /* One request: the query, and its arrival time in ns after the start of the run. */
@@ -195,7 +197,44 @@ int mdrq_serve(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, const mdrq_requ
                uint32_t n_reqs, mdrq_result_t* rs, uint64_t* latency_ns,
                mdrq_serve_stats_t* stats);
 
-/* Release a dataset and everything the library allocated for it. */
+/*
+ * Live serving: the same workers and continuous batching as mdrq_serve, fed by
+ * submissions instead of a replayed arrival list.
+ *
+ * mdrq_serve_open starts a server on ds (workers, streams and each worker's share of
+ * result_budget_bytes are allocated here, nothing later).  The server does not hold
+ * the dataset's call lock: mdrq_query and mdrq_query_batch on the same dataset may run
+ * meanwhile from other threads; options must not be changed while it is open.
+ * mdrq_free closes any server still open on the dataset (its handle is invalid then).
+ *
+ * mdrq_serve_submit queues one request and returns its ticket (0, 1, 2, ... in
+ * submission order).  The query is copied; *r is the caller's: it must stay valid,
+ * with its device buffer, until the ticket is reported by mdrq_serve_poll, and the
+ * server writes the complete result into it (count, mode, written, status exactly as
+ * mdrq_query would) before reporting the ticket.  Results that are not count-only must
+ * be in device memory.  Latency counts from the submission.
+ * Errors: MDRQ_EINVAL (bad request, host-memory result, server closing), MDRQ_EBUSY
+ * (max_queue requests already waiting, or one bitmap row exceeds a stream's share),
+ * or a device error that stopped the server.
+ *
+ * mdrq_serve_poll writes up to max_tickets completed tickets (each reported once, in
+ * completion order) to tickets[] and their number to *n_out; with wait_ns > 0 it
+ * waits up to that long for at least one.  It returns the server's error, if a scan
+ * failed (the requests of that scan carry it in their status).
+ *
+ * mdrq_serve_close answers every request already submitted, stops the workers, frees
+ * the server and writes the summary over all its requests to *stats (optional).
+ * Returns MDRQ_EOVERFLOW if some result was truncated, a scan's error if one failed.
+ */
+typedef struct mdrq_server mdrq_server;   /* opaque */
+int mdrq_serve_open(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, mdrq_server** out);
+int mdrq_serve_submit(mdrq_server* s, const mdrq_query_t* q, mdrq_result_t* r, uint64_t* ticket);
+int mdrq_serve_poll(mdrq_server* s, uint64_t* tickets, uint32_t max_tickets, uint32_t* n_out,
+                    uint64_t wait_ns);
+int mdrq_serve_close(mdrq_server* s, mdrq_serve_stats_t* stats);
+
+/* Release a dataset and everything the library allocated for it (closing any server
+ * still open on it first). */
 void mdrq_free(mdrq_dataset* ds);
 
 /* Message of the calling thread's last failure ("" if none); valid until its next call. */

@@ -313,6 +313,8 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
 int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queries,
                   uint64_t max_rows);
 void free_batch(BatchWorkspace& ws);
+// Close every live server still open on the dataset (serve.cpp), before it is freed.
+void close_servers(mdrq_dataset* ds);
 }  // namespace mdrq
 
 namespace mdrq {
@@ -393,6 +395,7 @@ struct mdrq_dataset {
   double batch_ms = 0.0;
 
   mdrq_estimator* estimator = nullptr;   // attached estimator (MDRQ_Q_ORDER_ESTIMATED)
+  std::vector<mdrq_server*> servers;     // live servers open on the dataset (stat_mu)
 
   int64_t grid = 0;                      // workgroups per launch (0 = blocks_per_cu per CU)
   int blocks_per_cu = 3;                 // default launch width, capped by occupancy

@@ -417,6 +417,7 @@ int mdrq_query(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r, void* 
 
 void mdrq_free(mdrq_dataset* ds) {
   if (!ds) return;
+  close_servers(ds);
   (void)hipDeviceSynchronize();
   free_dataset(ds);
 }

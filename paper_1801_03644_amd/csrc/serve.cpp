@@ -1,16 +1,18 @@
-// Serving loop: replay arrival-stamped requests with continuous batching.
+// Serving loop with continuous batching: a live server (open / submit / poll / close)
+// and the replay of arrival-stamped requests built on it.
 //
-// Requests are queued as they arrive.  Each of n_streams workers owns a device stream
-// and a preallocated batch workspace holding an equal share of the result-memory
-// budget.  Whenever a worker is idle and requests are waiting, the dispatcher hands it
-// the oldest waiting requests, as many as max_batch allows and as fit in the worker's
-// share (a request that needs a bitmap reserves one full bitmap row: its result can
-// never need more), and the worker answers them with one call of the batched shared
-// scan.  Requests that arrive while scans run wait for the next idle worker, so scans
-// of different workers overlap on the device.  Every request's answer is exactly what
-// mdrq_query gives for it alone.
+// Requests wait in a queue in submission order.  Each of n_streams workers owns a
+// device stream and a preallocated batch workspace holding an equal share of the
+// result-memory budget.  Whenever a worker is idle and requests are waiting, the
+// dispatcher hands it the oldest waiting requests, as many as max_batch allows and as
+// fit in the worker's share (a request that needs a bitmap reserves one full bitmap
+// row: its result can never need more), and the worker answers them with one call of
+// the batched shared scan.  Requests that arrive while scans run wait for the next
+// idle worker, so scans of different workers overlap on the device.  Every request's
+// answer is exactly what mdrq_query gives for it alone.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -26,227 +28,383 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// One queued request: a private copy of the query, the caller's result record.
+struct Pending {
+  uint64_t ticket = 0;
+  mdrq_query_t q{};
+  std::vector<mdrq_pred> preds;
+  mdrq_result_t* r = nullptr;
+  Clock::time_point arrival;
+};
+
 struct Worker {
   hipStream_t stream = nullptr;
   BatchWorkspace ws;
   std::thread th;
-  std::vector<uint32_t> batch;  // request indices handed to this worker
+  std::vector<Pending*> batch;  // handed to this worker by the dispatcher
   bool busy = false;
-  uint64_t rows_cap = 0;        // bitmap rows the worker's share holds
 };
-
-struct Shared {
-  std::mutex mu;
-  std::condition_variable cv;
-  bool stop = false;
-  int error = MDRQ_OK;
-  std::string error_msg;
-  uint32_t done = 0;
-  BatchRunStats st;
-  uint64_t batches = 0;
-};
-
-uint64_t elapsed_ns(Clock::time_point t0) {
-  return static_cast<uint64_t>(
-      std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count());
-}
 
 bool needs_row(const mdrq_result_t& r) { return r.mode != MDRQ_OUT_COUNT; }
 
 }  // namespace
 
+struct mdrq_server {
+  mdrq_dataset* ds = nullptr;
+  mdrq_serve_config_t cfg{};
+  uint64_t rows_cap = 0;        // bitmap rows one worker's share holds
+  int dev = 0;
+  std::vector<Worker> workers;
+  std::thread dispatcher;
+
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Pending*> ready;
+  bool closing = false;         // no more submissions; drain, then stop
+  bool stop = false;            // workers exit
+  int error = MDRQ_OK;
+  std::string error_msg;
+  uint64_t next_ticket = 0;
+  uint64_t completed = 0;
+  std::vector<uint64_t> done;   // completed tickets not yet polled
+  std::vector<uint64_t> lat_ns; // per ticket: arrival -> completion
+  Clock::time_point first_arrival{}, last_done{};
+  BatchRunStats st;
+  uint64_t batches = 0;
+  bool overflow = false;
+};
+
+namespace {
+
+void worker_loop(mdrq_server* s, Worker* w) {
+  (void)hipSetDevice(s->dev);
+  std::vector<mdrq_query_t> qs;
+  std::vector<mdrq_result_t> out;
+  for (;;) {
+    std::vector<Pending*> batch;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [&] { return s->stop || !w->batch.empty(); });
+      if (w->batch.empty()) return;
+      batch.swap(w->batch);
+    }
+    qs.clear();
+    out.clear();
+    for (Pending* p : batch) {
+      qs.push_back(p->q);
+      out.push_back(*p->r);
+    }
+    BatchRunStats st;
+    int rc = run_batch(s->ds, qs.data(), static_cast<uint32_t>(qs.size()), out.data(), w->stream,
+                       &w->ws, false, &st);
+    const Clock::time_point t = Clock::now();
+    std::string msg = rc ? mdrq_last_error() : "";
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (rc && rc != MDRQ_EOVERFLOW && s->error == MDRQ_OK) {
+      s->error = rc;
+      s->error_msg = msg;
+    }
+    for (size_t k = 0; k < batch.size(); ++k) {
+      Pending* p = batch[k];
+      if (rc && rc != MDRQ_EOVERFLOW) out[k].status = rc;
+      *p->r = out[k];
+      s->overflow |= out[k].status == MDRQ_EOVERFLOW;
+      if (s->lat_ns.size() <= p->ticket) s->lat_ns.resize(p->ticket + 1, 0);
+      s->lat_ns[p->ticket] = static_cast<uint64_t>(
+          std::max<int64_t>(0, std::chrono::duration_cast<std::chrono::nanoseconds>(t - p->arrival).count()));
+      s->done.push_back(p->ticket);
+      delete p;
+    }
+    s->completed += batch.size();
+    s->last_done = t;
+    s->st.scans += st.scans;
+    s->st.column_bytes += st.column_bytes;
+    s->st.device_ms += st.device_ms;
+    s->batches += 1;
+    w->busy = false;
+    s->cv.notify_all();
+  }
+}
+
+void dispatch_loop(mdrq_server* s) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    Worker* idle = nullptr;
+    bool any_busy = false;
+    for (Worker& w : s->workers) {
+      if (!w.busy && !idle) idle = &w;
+      any_busy |= w.busy;
+    }
+    if (idle && !s->ready.empty()) {
+      uint64_t rows = 0;
+      while (!s->ready.empty() && idle->batch.size() < s->cfg.max_batch) {
+        Pending* p = s->ready.front();
+        const uint64_t need = needs_row(*p->r) ? 1 : 0;
+        if (rows + need > s->rows_cap) break;
+        rows += need;
+        idle->batch.push_back(p);
+        s->ready.pop_front();
+      }
+      idle->busy = true;
+      s->cv.notify_all();
+      continue;
+    }
+    if (s->closing && s->ready.empty() && !any_busy) break;
+    s->cv.wait(lk);
+  }
+  s->stop = true;
+  s->cv.notify_all();
+}
+
+// Validation shared by the live server and the replay.
+int check_config(const mdrq_dataset* ds, const mdrq_serve_config_t* cfg) {
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  if (!cfg) return fail(MDRQ_EINVAL, "NULL argument");
+  if (cfg->max_batch == 0 || cfg->max_batch > MDRQ_MAX_BATCH)
+    return fail(MDRQ_EINVAL, "max_batch must be in 1..MDRQ_MAX_BATCH");
+  if (cfg->n_streams == 0 || cfg->n_streams > 8) return fail(MDRQ_EINVAL, "n_streams must be in 1..8");
+  if (cfg->use_estimator && !ds->estimator)
+    return fail(MDRQ_EINVAL, "use_estimator needs an attached estimator");
+  return MDRQ_OK;
+}
+
+int check_request(const mdrq_server* s, const mdrq_query_t* q, const mdrq_result_t* r) {
+  int rc = check_query(s->ds, q);
+  if (rc) return rc;
+  rc = check_result(r);
+  if (rc) return rc;
+  if (needs_row(*r) && r->mem != MDRQ_MEM_DEVICE)
+    return fail(MDRQ_EINVAL, "serving writes results to device memory only (mem = MDRQ_MEM_DEVICE)");
+  if (needs_row(*r) && s->rows_cap == 0)
+    return fail(MDRQ_EBUSY, "a request's bitmap row does not fit in one stream's share of the result budget");
+  return MDRQ_OK;
+}
+
+void destroy(mdrq_server* s) {
+  for (Worker& w : s->workers) {
+    free_batch(w.ws);
+    if (w.stream) (void)hipStreamDestroy(w.stream);
+  }
+  for (Pending* p : s->ready) delete p;
+  delete s;
+}
+
+// Create the workers and the dispatcher.  `reserve_rows`: reserve bitmap rows up front.
+int create(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, bool reserve_rows, mdrq_server** out) {
+  mdrq_server* s = new mdrq_server();
+  s->ds = ds;
+  s->cfg = *cfg;
+  const uint64_t row_bytes = 8 * n_words(ds);
+  const uint64_t share = cfg->result_budget_bytes / cfg->n_streams;
+  s->rows_cap = std::min<uint64_t>(row_bytes ? share / row_bytes : cfg->max_batch, cfg->max_batch);
+  (void)hipGetDevice(&s->dev);
+  s->workers.resize(cfg->n_streams);
+  for (Worker& w : s->workers) {
+    hipError_t e = hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      destroy(s);
+      return fail_hip(e, "serving stream");
+    }
+    int rc = reserve_batch(ds, w.ws, cfg->max_batch, reserve_rows ? s->rows_cap : 0);
+    if (rc) {
+      destroy(s);
+      return rc;
+    }
+  }
+  for (Worker& w : s->workers) w.th = std::thread(worker_loop, s, &w);
+  s->dispatcher = std::thread(dispatch_loop, s);
+  *out = s;
+  return MDRQ_OK;
+}
+
+// Queue one request (caller holds no lock).  arrival: the time its latency counts from.
+int enqueue(mdrq_server* s, const mdrq_query_t* q, mdrq_result_t* r, Clock::time_point arrival,
+            bool bounded, uint64_t* ticket) {
+  Pending* p = new Pending();
+  p->q = *q;
+  p->preds.assign(q->preds, q->preds + q->n_preds);
+  p->q.preds = p->preds.data();
+  if (s->cfg.use_estimator) p->q.flags |= MDRQ_Q_ORDER_ESTIMATED;
+  p->r = r;
+  p->arrival = arrival;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->closing) {
+    delete p;
+    return fail(MDRQ_EINVAL, "server is closing");
+  }
+  if (s->error != MDRQ_OK) {
+    delete p;
+    return fail(s->error, "serving: " + s->error_msg);
+  }
+  if (bounded && s->cfg.max_queue && s->ready.size() >= s->cfg.max_queue) {
+    delete p;
+    return fail(MDRQ_EBUSY, "serving queue is full");
+  }
+  if (s->next_ticket == 0 || arrival < s->first_arrival) s->first_arrival = arrival;
+  p->ticket = s->next_ticket++;
+  if (ticket) *ticket = p->ticket;
+  s->ready.push_back(p);
+  s->cv.notify_all();
+  return MDRQ_OK;
+}
+
+// Drain and stop; summary statistics over every request answered.
+int shutdown(mdrq_server* s, mdrq_serve_stats_t* stats) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->closing = true;
+    s->cv.notify_all();
+  }
+  s->dispatcher.join();
+  for (Worker& w : s->workers) w.th.join();
+  const int err = s->error;
+  const std::string msg = s->error_msg;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    const uint64_t n = s->completed;
+    std::vector<uint64_t> sorted(s->lat_ns.begin(), s->lat_ns.begin() + std::min<uint64_t>(n, s->lat_ns.size()));
+    std::sort(sorted.begin(), sorted.end());
+    auto pct = [&](double p) {
+      const size_t k = static_cast<size_t>(std::min<double>(sorted.size() - 1, std::floor(p * (sorted.size() - 1) + 0.5)));
+      return sorted[k] * 1e-3;
+    };
+    stats->completed = n;
+    stats->scans = s->st.scans;
+    if (!sorted.empty()) {
+      double sum = 0.0;
+      for (uint64_t v : sorted) sum += static_cast<double>(v);
+      stats->wall_s = std::max(0.0, std::chrono::duration<double>(s->last_done - s->first_arrival).count());
+      stats->qps = stats->wall_s > 0 ? n / stats->wall_s : 0.0;
+      stats->p50_us = pct(0.50);
+      stats->p99_us = pct(0.99);
+      stats->mean_us = sum / sorted.size() * 1e-3;
+      stats->max_us = sorted.back() * 1e-3;
+    }
+    stats->mean_batch = s->batches ? static_cast<double>(n) / s->batches : 0.0;
+    stats->hbm_gbps = stats->wall_s > 0 ? s->st.column_bytes / stats->wall_s * 1e-9 : 0.0;
+    stats->overflow_reruns = 0;
+  }
+  const bool overflow = s->overflow;
+  {
+    std::lock_guard<std::mutex> lk(s->ds->stat_mu);
+    auto& v = s->ds->servers;
+    v.erase(std::remove(v.begin(), v.end(), s), v.end());
+  }
+  destroy(s);
+  if (err != MDRQ_OK) return fail(err, "serving: " + msg);
+  return overflow ? MDRQ_EOVERFLOW : MDRQ_OK;
+}
+
+}  // namespace
+
+namespace mdrq {
+void close_servers(mdrq_dataset* ds) {
+  for (;;) {
+    mdrq_server* s = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(ds->stat_mu);
+      if (ds->servers.empty()) return;
+      s = ds->servers.back();
+    }
+    (void)shutdown(s, nullptr);
+  }
+}
+}  // namespace mdrq
+
+extern "C" int mdrq_serve_open(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, mdrq_server** out) {
+  clear_error();
+  if (!out) return fail(MDRQ_EINVAL, "NULL argument");
+  *out = nullptr;
+  int rc = check_config(ds, cfg);
+  if (rc) return rc;
+  rc = create(ds, cfg, true, out);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ds->stat_mu);
+  ds->servers.push_back(*out);
+  return MDRQ_OK;
+}
+
+extern "C" int mdrq_serve_submit(mdrq_server* s, const mdrq_query_t* q, mdrq_result_t* r,
+                                 uint64_t* ticket) {
+  clear_error();
+  if (!s || !q || !r) return fail(MDRQ_EINVAL, "NULL argument");
+  int rc = check_request(s, q, r);
+  if (rc) return rc;
+  return enqueue(s, q, r, Clock::now(), true, ticket);
+}
+
+extern "C" int mdrq_serve_poll(mdrq_server* s, uint64_t* tickets, uint32_t max_tickets,
+                               uint32_t* n_out, uint64_t wait_ns) {
+  clear_error();
+  if (!s || !n_out || (max_tickets && !tickets)) return fail(MDRQ_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (wait_ns && s->done.empty() && s->error == MDRQ_OK)
+    s->cv.wait_for(lk, std::chrono::nanoseconds(wait_ns),
+                   [&] { return !s->done.empty() || s->error != MDRQ_OK; });
+  const size_t n = std::min<size_t>(max_tickets, s->done.size());
+  std::copy(s->done.begin(), s->done.begin() + n, tickets);
+  s->done.erase(s->done.begin(), s->done.begin() + n);
+  *n_out = static_cast<uint32_t>(n);
+  if (s->error != MDRQ_OK) return fail(s->error, "serving: " + s->error_msg);
+  return MDRQ_OK;
+}
+
+extern "C" int mdrq_serve_close(mdrq_server* s, mdrq_serve_stats_t* stats) {
+  clear_error();
+  if (!s) return fail(MDRQ_EINVAL, "server is NULL");
+  return shutdown(s, stats);
+}
+
 extern "C" int mdrq_serve(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, const mdrq_request_t* reqs,
                           uint32_t n_reqs, mdrq_result_t* rs, uint64_t* latency_ns,
                           mdrq_serve_stats_t* stats) {
   clear_error();
-  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
-  if (!cfg || !reqs || !rs) return fail(MDRQ_EINVAL, "NULL argument");
+  int rc = check_config(ds, cfg);
+  if (rc) return rc;
+  if (!reqs || !rs) return fail(MDRQ_EINVAL, "NULL argument");
   if (n_reqs == 0) return fail(MDRQ_EINVAL, "no requests");
-  if (cfg->max_batch == 0 || cfg->max_batch > MDRQ_MAX_BATCH)
-    return fail(MDRQ_EINVAL, "max_batch must be in 1..MDRQ_MAX_BATCH");
-  if (cfg->n_streams == 0 || cfg->n_streams > 8) return fail(MDRQ_EINVAL, "n_streams must be in 1..8");
-  for (uint32_t i = 0; i < n_reqs; ++i) {
-    int rc = check_query(ds, &reqs[i].query);
-    if (rc) return rc;
-    rc = check_result(&rs[i]);
-    if (rc) return rc;
-    if (needs_row(rs[i]) && rs[i].mem != MDRQ_MEM_DEVICE)
-      return fail(MDRQ_EINVAL, "serving writes results to device memory only (mem = MDRQ_MEM_DEVICE)");
-  }
   std::lock_guard<std::mutex> lock(ds->mu);
-  if (cfg->use_estimator && !ds->estimator)
-    return fail(MDRQ_EINVAL, "use_estimator needs an attached estimator");
-
-  const uint64_t row_bytes = 8 * n_words(ds);
-  const uint64_t share = cfg->result_budget_bytes / cfg->n_streams;
-  const uint64_t rows_cap = row_bytes ? share / row_bytes : cfg->max_batch;
   bool any_row = false;
   for (uint32_t i = 0; i < n_reqs; ++i) any_row |= needs_row(rs[i]);
-  if (any_row && rows_cap == 0)
-    return fail(MDRQ_EBUSY, "a request's bitmap row does not fit in one stream's share of the result budget");
+  mdrq_server* s = nullptr;
+  rc = create(ds, cfg, any_row, &s);
+  if (rc) return rc;
+  for (uint32_t i = 0; i < n_reqs; ++i) {
+    rc = check_request(s, &reqs[i].query, &rs[i]);
+    if (rc) {
+      std::string msg = mdrq_last_error();
+      (void)shutdown(s, nullptr);
+      return fail(rc, msg);
+    }
+  }
 
-  // Arrival order (stable for equal stamps).
+  // Replay: each request is queued when the clock reaches its arrival stamp (arrival
+  // order, stable for equal stamps); its latency counts from that stamp.
   std::vector<uint32_t> order(n_reqs);
   for (uint32_t i = 0; i < n_reqs; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](uint32_t a, uint32_t b) { return reqs[a].arrival_ns < reqs[b].arrival_ns; });
-
-  // Workers with their own stream and preallocated workspace.
-  std::vector<Worker> workers(cfg->n_streams);
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  auto cleanup = [&]() {
-    for (Worker& w : workers) {
-      free_batch(w.ws);
-      if (w.stream) (void)hipStreamDestroy(w.stream);
-    }
-  };
-  for (Worker& w : workers) {
-    w.rows_cap = std::min<uint64_t>(rows_cap, cfg->max_batch);
-    hipError_t e = hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-      cleanup();
-      return fail_hip(e, "serving stream");
-    }
-    int rc = reserve_batch(ds, w.ws, cfg->max_batch, any_row ? w.rows_cap : 0);
-    if (rc) {
-      cleanup();
-      return rc;
-    }
-  }
-
-  std::vector<uint64_t> done_ns(n_reqs, 0);
-  std::vector<mdrq_query_t> qcopy(n_reqs);
-  for (uint32_t i = 0; i < n_reqs; ++i) {
-    qcopy[i] = reqs[i].query;
-    if (cfg->use_estimator) qcopy[i].flags |= MDRQ_Q_ORDER_ESTIMATED;
-  }
-  Shared sh;
+  std::vector<uint32_t> index_of_ticket(n_reqs);
   const Clock::time_point t0 = Clock::now();
-
-  auto work = [&](Worker* w) {
-    (void)hipSetDevice(dev);
-    std::vector<mdrq_query_t> qs;
-    std::vector<mdrq_result_t> out;
-    for (;;) {
-      std::vector<uint32_t> batch;
-      {
-        std::unique_lock<std::mutex> lk(sh.mu);
-        sh.cv.wait(lk, [&] { return sh.stop || !w->batch.empty(); });
-        if (w->batch.empty()) return;
-        batch.swap(w->batch);
-      }
-      qs.clear();
-      out.clear();
-      for (uint32_t i : batch) {
-        qs.push_back(qcopy[i]);
-        out.push_back(rs[i]);
-      }
-      BatchRunStats st;
-      int rc = run_batch(ds, qs.data(), static_cast<uint32_t>(qs.size()), out.data(), w->stream,
-                         &w->ws, false, &st);
-      const uint64_t t = elapsed_ns(t0);
-      std::string msg = rc ? mdrq_last_error() : "";
-      std::lock_guard<std::mutex> lk(sh.mu);
-      if (rc && rc != MDRQ_EOVERFLOW && sh.error == MDRQ_OK) {
-        sh.error = rc;
-        sh.error_msg = msg;
-      }
-      for (size_t k = 0; k < batch.size(); ++k) {
-        rs[batch[k]] = out[k];
-        done_ns[batch[k]] = t;
-      }
-      sh.done += static_cast<uint32_t>(batch.size());
-      sh.st.scans += st.scans;
-      sh.st.column_bytes += st.column_bytes;
-      sh.st.device_ms += st.device_ms;
-      sh.batches += 1;
-      w->busy = false;
-      sh.cv.notify_all();
+  for (uint32_t k = 0; k < n_reqs; ++k) {
+    const uint32_t i = order[k];
+    const Clock::time_point at = t0 + std::chrono::nanoseconds(reqs[i].arrival_ns);
+    std::this_thread::sleep_until(at);
+    uint64_t ticket = 0;
+    rc = enqueue(s, &reqs[i].query, &rs[i], at, false, &ticket);
+    if (rc) break;
+    index_of_ticket[ticket] = i;
+  }
+  if (latency_ns) {
+    // Latencies are final once the server has drained; copy them before it is freed.
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [&] { return s->completed == s->next_ticket || s->error != MDRQ_OK; });
+      for (uint64_t t = 0; t < s->next_ticket && t < s->lat_ns.size(); ++t)
+        latency_ns[index_of_ticket[t]] = s->lat_ns[t];
     }
-  };
-  for (Worker& w : workers) w.th = std::thread(work, &w);
-
-  // Dispatcher.
-  {
-    std::deque<uint32_t> ready;
-    uint32_t next = 0;
-    std::unique_lock<std::mutex> lk(sh.mu);
-    while (sh.done < n_reqs && sh.error == MDRQ_OK) {
-      const uint64_t now = elapsed_ns(t0);
-      while (next < n_reqs && reqs[order[next]].arrival_ns <= now) ready.push_back(order[next++]);
-      Worker* idle = nullptr;
-      for (Worker& w : workers)
-        if (!w.busy) {
-          idle = &w;
-          break;
-        }
-      if (idle && !ready.empty()) {
-        uint64_t rows = 0;
-        while (!ready.empty() && idle->batch.size() < cfg->max_batch) {
-          const uint32_t i = ready.front();
-          const uint64_t need = needs_row(rs[i]) ? 1 : 0;
-          if (rows + need > idle->rows_cap) break;
-          rows += need;
-          idle->batch.push_back(i);
-          ready.pop_front();
-        }
-        idle->busy = true;
-        sh.cv.notify_all();
-        continue;
-      }
-      if (next < n_reqs && (idle || ready.empty())) {
-        const auto wake = t0 + std::chrono::nanoseconds(reqs[order[next]].arrival_ns);
-        sh.cv.wait_until(lk, wake);
-      } else {
-        sh.cv.wait(lk);
-      }
-    }
-    // Drain: let running batches finish, then stop the workers.
-    sh.cv.wait(lk, [&] {
-      for (Worker& w : workers)
-        if (w.busy) return false;
-      return true;
-    });
-    sh.stop = true;
-    sh.cv.notify_all();
   }
-  for (Worker& w : workers) w.th.join();
-  cleanup();
-  if (sh.error != MDRQ_OK) return fail(sh.error, "serving: " + sh.error_msg);
-
-  // Latencies and statistics.
-  std::vector<uint64_t> lat(n_reqs);
-  uint64_t first = UINT64_MAX, last = 0;
-  bool overflow = false;
-  for (uint32_t i = 0; i < n_reqs; ++i) {
-    lat[i] = done_ns[i] > reqs[i].arrival_ns ? done_ns[i] - reqs[i].arrival_ns : 0;
-    if (latency_ns) latency_ns[i] = lat[i];
-    first = std::min(first, reqs[i].arrival_ns);
-    last = std::max(last, done_ns[i]);
-    overflow |= rs[i].status == MDRQ_EOVERFLOW;
-  }
-  if (stats) {
-    std::vector<uint64_t> sorted = lat;
-    std::sort(sorted.begin(), sorted.end());
-    auto pct = [&](double p) {
-      const size_t k = static_cast<size_t>(std::min<double>(n_reqs - 1, std::floor(p * (n_reqs - 1) + 0.5)));
-      return sorted[k] * 1e-3;
-    };
-    double sum = 0.0;
-    for (uint64_t v : lat) sum += static_cast<double>(v);
-    std::memset(stats, 0, sizeof(*stats));
-    stats->completed = n_reqs;
-    stats->scans = sh.st.scans;
-    stats->wall_s = static_cast<double>(last > first ? last - first : 0) * 1e-9;
-    stats->qps = stats->wall_s > 0 ? n_reqs / stats->wall_s : 0.0;
-    stats->p50_us = pct(0.50);
-    stats->p99_us = pct(0.99);
-    stats->mean_us = sum / n_reqs * 1e-3;
-    stats->max_us = sorted.back() * 1e-3;
-    stats->mean_batch = sh.batches ? static_cast<double>(n_reqs) / sh.batches : 0.0;
-    stats->hbm_gbps = stats->wall_s > 0 ? sh.st.column_bytes / stats->wall_s * 1e-9 : 0.0;
-    stats->overflow_reruns = 0;
-  }
-  return overflow ? MDRQ_EOVERFLOW : MDRQ_OK;
+  const int rc_close = shutdown(s, stats);
+  if (rc) return rc;
+  return rc_close;
 }

@@ -32,7 +32,8 @@ EXPORTS = ["mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve", 
            "mdrq_estimator_create", "mdrq_estimator_free", "mdrq_estimator_histograms",
            "mdrq_estimator_features", "mdrq_estimator_param_count", "mdrq_estimator_get_params",
            "mdrq_estimator_set_params", "mdrq_label_selectivities", "mdrq_estimator_gradient",
-           "mdrq_estimator_train", "mdrq_estimator_predict", "mdrq_attach_estimator"]
+           "mdrq_estimator_train", "mdrq_estimator_predict", "mdrq_attach_estimator",
+           "mdrq_serve_open", "mdrq_serve_submit", "mdrq_serve_poll", "mdrq_serve_close"]
 EST_BINS = 16
 EST_FEATS = EST_BINS + 3  # per dimension: H(lo), H(hi), histogram estimate, bins
 OPT_UNROLL, OPT_GRID, OPT_BLOCKS_PER_CU = 1, 2, 3
@@ -65,7 +66,7 @@ class Result(ctypes.Structure):
 class ServeConfig(ctypes.Structure):
     _fields_ = [("result_budget_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32),
                 ("n_streams", ctypes.c_uint32), ("use_estimator", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("max_queue", ctypes.c_uint32)]
 
 
 class EstimatorConfig(ctypes.Structure):
@@ -126,6 +127,10 @@ def load_library(path: str = LIB_PATH):
     lib.mdrq_query.argtypes = [vp, P(Query), P(Result), vp]
     lib.mdrq_query_batch.argtypes = [vp, P(Query), u32, P(Result), vp]
     lib.mdrq_serve.argtypes = [vp, P(ServeConfig), P(Request), u32, P(Result), P(u64), P(ServeStats)]
+    lib.mdrq_serve_open.argtypes = [vp, P(ServeConfig), P(vp)]
+    lib.mdrq_serve_submit.argtypes = [vp, P(Query), P(Result), P(u64)]
+    lib.mdrq_serve_poll.argtypes = [vp, P(u64), u32, P(u32), u64]
+    lib.mdrq_serve_close.argtypes = [vp, P(ServeStats)]
     lib.mdrq_free.argtypes = [vp]
     lib.mdrq_free.restype = None
     lib.mdrq_last_error.restype = ctypes.c_char_p
@@ -230,6 +235,7 @@ class Dataset:
         self.n_dims = n_dims
         self._keep = keepalive
         self._estimators = weakref.WeakSet()  # released before the dataset
+        self._servers = weakref.WeakSet()     # closed before the dataset
 
     @classmethod
     def from_host(cls, cols, stream=None) -> "Dataset":
@@ -265,6 +271,8 @@ class Dataset:
 
     def close(self):
         if self._h and self._h.value:
+            for srv in list(self._servers):
+                srv.close()
             for est in list(self._estimators):
                 est.close()
             load_library().mdrq_free(self._h)
@@ -365,6 +373,11 @@ class Dataset:
         stats = {name: getattr(st, name) for name, _ in ServeStats._fields_}
         return answers, np.array(lat[:n], dtype=np.uint64), stats
 
+    def serve_open(self, max_batch: int = 256, n_streams: int = 2, budget_bytes: int = 1 << 30,
+                   use_estimator: bool = False, max_queue: int = 0) -> "Server":
+        """A live server on this dataset (submit / poll / close)."""
+        return Server(self, max_batch, n_streams, budget_bytes, use_estimator, max_queue)
+
     def label_selectivities(self, queries) -> np.ndarray:
         """Exact selectivities (n, n_dims + 1): each predicate alone, then the query;
         -1 where a query does not restrict a dimension."""
@@ -391,6 +404,75 @@ def _query_array(queries, flags: int):
 def _fptr(a: np.ndarray):
     assert a.dtype == np.float32 and a.flags.c_contiguous
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Server:
+    """Live serving loop (mdrq_serve_open): requests are submitted one at a time and
+    answered by continuous batching; poll() reports the completed ones."""
+
+    def __init__(self, ds: Dataset, max_batch: int, n_streams: int, budget_bytes: int,
+                 use_estimator: bool, max_queue: int):
+        cfg = ServeConfig(int(budget_bytes), max_batch, n_streams, 1 if use_estimator else 0,
+                          int(max_queue))
+        h = ctypes.c_void_p()
+        _check(load_library().mdrq_serve_open(ds.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.ds = ds
+        ds._servers.add(self)
+        self._pending = {}   # ticket -> (result record, output buffer): alive until polled
+
+    def submit(self, query, out=None, mode: str = "ids") -> int:
+        """Queue one request; returns its ticket.  Raises MdrqError (code EBUSY) when
+        the queue is full."""
+        q, keep = make_query(query, 0)
+        r = _result_for(out, mode)
+        t = ctypes.c_uint64()
+        _check(load_library().mdrq_serve_submit(self._h, ctypes.byref(q), ctypes.byref(r),
+                                                ctypes.byref(t)))
+        self._pending[t.value] = (r, out)
+        return t.value
+
+    def poll(self, max_tickets: int = 1024, wait_s: float = 0.0):
+        """Completed requests since the last poll: list of (ticket, Answer)."""
+        buf = (ctypes.c_uint64 * max(1, max_tickets))()
+        n = ctypes.c_uint32()
+        rc = load_library().mdrq_serve_poll(self._h, buf, max_tickets, ctypes.byref(n),
+                                            int(wait_s * 1e9))
+        done = []
+        for t in buf[:n.value]:
+            r, _ = self._pending.pop(t)
+            done.append((t, Answer(r.count, r.written, r.status, _MODE_NAMES[r.mode])))
+        _check(rc)
+        return done
+
+    def close(self):
+        """Answer everything submitted, stop, and return the summary statistics."""
+        if not (self._h and self._h.value):
+            return None
+        st = ServeStats()
+        rc = load_library().mdrq_serve_close(self._h, ctypes.byref(st))
+        self._h = ctypes.c_void_p()
+        _check(rc, (OK, EOVERFLOW))
+        return {name: getattr(st, name) for name, _ in ServeStats._fields_}
+
+    def results(self):
+        """Answers of requests completed but not yet polled (after close)."""
+        out = [(t, Answer(r.count, r.written, r.status, _MODE_NAMES[r.mode]))
+               for t, (r, _) in sorted(self._pending.items())]
+        self._pending.clear()
+        return out
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Estimator:

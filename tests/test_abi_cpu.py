@@ -104,3 +104,18 @@ def test_error_message_is_thread_local():
     t.join()
     assert seen == [""]
     assert mdrq.last_error() != ""
+
+
+def test_live_server_calls_reject_null_arguments():
+    lib = mdrq.load_library()
+    q, keep = mdrq.make_query([(0, 0.0, 1.0)])
+    r = mdrq.Result()
+    cfg = mdrq.ServeConfig(1 << 20, 16, 1, 0, 0)
+    h = ctypes.c_void_p()
+    t = ctypes.c_uint64()
+    n = ctypes.c_uint32()
+    tickets = (ctypes.c_uint64 * 4)()
+    assert lib.mdrq_serve_open(None, ctypes.byref(cfg), ctypes.byref(h)) == mdrq.EINVAL
+    assert lib.mdrq_serve_submit(None, ctypes.byref(q), ctypes.byref(r), ctypes.byref(t)) == mdrq.EINVAL
+    assert lib.mdrq_serve_poll(None, tickets, 4, ctypes.byref(n), 0) == mdrq.EINVAL
+    assert lib.mdrq_serve_close(None, None) == mdrq.EINVAL
