@@ -67,7 +67,12 @@ def summarize(outdir: str, workload: str):
         out = os.path.join(prof, f"{kind}_{workload}_kernel_stats.txt")
         with open(out, "w") as f:
             f.write("rocprofv3 --kernel-trace --stats summary\n")
-            f.write(f"command: {cmd}\n\n")
+            f.write(f"command: {cmd}\n")
+            if kind in ("batch", "learned", "serve"):
+                f.write("note: the first shared scan of each batch shape runs every autotuner "
+                        "candidate once; the shared-scan kernels with more calls than the "
+                        "others are the configurations it kept\n")
+            f.write("\n")
             f.write(f"{'kernel':72s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}\n")
             for r in rows:
                 f.write(f"{r.get('Name', '')[:72]:72s} {int(r.get('Calls', 0)):7d} "
