@@ -373,17 +373,18 @@ int max_union() {
   return static_cast<int>(std::min<size_t>(kMaxUnion, std::max<size_t>(kMaxSlots, room / per_slot)));
 }
 
-// Best-fit decreasing grouping of items into sets whose union of columns has at most
-// max_union() columns and which hold at most MDRQ_MAX_BATCH items.  Each group lists item
-// positions in ascending order.
-std::vector<std::vector<size_t>> group_by_columns(const std::vector<Item>& items, uint32_t n_dims) {
+// Best-fit decreasing grouping of the items listed in `which` into sets whose union of
+// columns has at most `limit` columns and which hold at most MDRQ_MAX_BATCH items.  Each
+// group lists item positions in ascending order.
+std::vector<std::vector<size_t>> group_by_columns(const std::vector<Item>& items,
+                                                  const std::vector<size_t>& which,
+                                                  uint32_t n_dims, int limit) {
   struct Group {
     std::vector<bool> in;
     int used = 0;
     std::vector<size_t> members;
   };
-  std::vector<size_t> order(items.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::vector<size_t> order(which);
   std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
     return items[a].plan.dims.size() > items[b].plan.dims.size();
   });
@@ -391,7 +392,6 @@ std::vector<std::vector<size_t>> group_by_columns(const std::vector<Item>& items
   for (size_t i : order) {
     const std::vector<uint32_t>& dims = items[i].plan.dims;
     Group* best = nullptr;
-    const int limit = max_union();
     int best_add = limit + 1;
     for (Group& g : groups) {
       if (g.members.size() >= MDRQ_MAX_BATCH) continue;
@@ -421,6 +421,50 @@ std::vector<std::vector<size_t>> group_by_columns(const std::vector<Item>& items
     out.push_back(std::move(g.members));
   }
   return out;
+}
+
+// Unions wider than the register slots take the LDS variant, which tests about half as
+// fast.  When a batch's queries would share such a union, also try grouping them into
+// register-sized unions (queries with more predicates than slots stay in wide groups)
+// and keep whichever grouping a simple cost model prefers: per scan, the larger of its
+// column bytes at streaming bandwidth and its row tests at the variant's rate.
+std::vector<std::vector<size_t>> plan_groups(const std::vector<Item>& items, uint32_t n_dims,
+                                             uint64_t n_rows) {
+  std::vector<size_t> all(items.size());
+  for (size_t i = 0; i < all.size(); ++i) all[i] = i;
+  std::vector<std::vector<size_t>> wide = group_by_columns(items, all, n_dims, max_union());
+  auto union_of = [&](const std::vector<size_t>& g) {
+    std::vector<bool> in(n_dims, false);
+    int u = 0;
+    for (size_t m : g)
+      for (uint32_t d : items[m].plan.dims)
+        if (!in[d]) {
+          in[d] = true;
+          ++u;
+        }
+    return u;
+  };
+  bool any_wide = false;
+  for (const auto& g : wide) any_wide |= union_of(g) > kMaxSlots;
+  if (!any_wide) return wide;
+  std::vector<size_t> narrow_items, wide_items;
+  for (size_t i = 0; i < items.size(); ++i)
+    (items[i].plan.dims.size() <= static_cast<size_t>(kMaxSlots) ? narrow_items : wide_items).push_back(i);
+  std::vector<std::vector<size_t>> split = group_by_columns(items, narrow_items, n_dims, kMaxSlots);
+  for (auto& g : group_by_columns(items, wide_items, n_dims, max_union())) split.push_back(std::move(g));
+  auto cost = [&](const std::vector<std::vector<size_t>>& groups) {
+    constexpr double kBytesPerS = 6e12, kRegTests = 8e12, kLdsTests = 4e12, kLaunchS = 30e-6;
+    double t = 0.0;
+    for (const auto& g : groups) {
+      const int u = union_of(g);
+      double tests = 0.0;
+      for (size_t m : g) tests += static_cast<double>(n_rows) * items[m].plan.dims.size();
+      t += std::max(4.0 * n_rows * u / kBytesPerS, tests / (u > kMaxSlots ? kLdsTests : kRegTests)) +
+           kLaunchS;
+    }
+    return t;
+  };
+  return cost(split) < cost(wide) ? split : wide;
 }
 
 // Candidate configurations the autotuner tries on a new batch shape.
@@ -514,7 +558,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
   // best-fit decreasing -- queries with the most columns first, each into the open
   // group it adds the fewest new columns to (a new group if none has room).  Queries
   // on overlapping columns share a scan, so each column is read by few scans.
-  std::vector<std::vector<size_t>> groups = group_by_columns(shared, ds->n_dims);
+  std::vector<std::vector<size_t>> groups = plan_groups(shared, ds->n_dims, ds->n_rows);
   for (const std::vector<size_t>& members : groups) {
     std::vector<Item> batch;
     std::vector<bool> in(ds->n_dims, false);
