@@ -115,7 +115,12 @@ def summarize(outdir: str, workload: str):
     log("wrote", out)
 
 
-def cpu_baseline(cols_raw, queries, n_rows, budget_s: float):
+def cpu_baseline(cols_raw, queries, n_rows, budget_s: float, all_cores: bool = True):
+    """The oracle on the host: single-threaded over the first queries for about
+    budget_s seconds; then (all_cores) the same unchanged single-threaded oracle on
+    one query per thread, all host threads (at most 16), for about half that."""
+    import threading
+
     import oracle
 
     cols = oracle.prepare(cols_raw)
@@ -127,10 +132,52 @@ def cpu_baseline(cols_raw, queries, n_rows, budget_s: float):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": n_rows * done / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+    line = {"value": n_rows * done / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
             "sample": f"first {done} of the {len(queries)} queries on the full {n_rows}-row data, "
                       f"single-threaded oracle scan ({dt:.1f} s)",
             "queries_per_s": done / dt}
+    if all_cores:
+        # The oracle's C scan runs outside the interpreter lock, so threads scale.
+        n_threads = max(1, min(16, os.cpu_count() or 1))
+        lock = threading.Lock()
+        state = {"next": 0, "done": 0}
+        stop_at = time.perf_counter() + budget_s / 2
+
+        def worker():
+            while time.perf_counter() < stop_at:
+                with lock:
+                    i = state["next"]
+                    state["next"] += 1
+                oracle.count(cols, queries[i % len(queries)])
+                with lock:
+                    state["done"] += 1
+
+        t1 = time.perf_counter()
+        threads = [threading.Thread(target=worker) for _ in range(n_threads)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        dt1 = time.perf_counter() - t1
+        line["all_cores"] = {"value": n_rows * state["done"] / dt1, "unit": "tuples/s",
+                             "cores": n_threads, "queries_per_s": state["done"] / dt1,
+                             "sample": f"{state['done']} queries, one per thread, "
+                                       f"{n_threads} threads ({dt1:.1f} s)"}
+    return line
+
+
+def device_info():
+    """The GPU the line was measured on (torch's view of it)."""
+    import torch
+
+    p = torch.cuda.get_device_properties(0)
+    info = {"name": p.name, "arch": getattr(p, "gcnArchName", ""),
+            "compute_units": p.multi_processor_count, "memory_gib": round(p.total_memory / 2**30, 1)}
+    for k in ("L2_cache_size", "shared_memory_per_block", "shared_memory_per_multiprocessor",
+              "clock_rate"):
+        if hasattr(p, k):
+            info[k] = getattr(p, k)
+    return info
 
 
 def main():
@@ -180,6 +227,7 @@ def main():
 
         line = {"c3": bench_extra.batched, "c4": bench_extra.learned,
                 "c5": bench_extra.serving, "syntuni": bench_extra.paper}[args.workload](args)
+        line["device"] = device_info()
         print(json.dumps(line), flush=True)
         return
     w = dg.workload(args.workload, args.rows)
@@ -318,6 +366,7 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(raw, queries, w.n_rows, args.cpu_budget)
+    line["device"] = device_info()
     ds.close()
     print(json.dumps(line), flush=True)
 
