@@ -44,6 +44,20 @@ int grow_pinned(void** p, uint64_t* have, uint64_t need) {
   return MDRQ_OK;
 }
 
+// Per-query counts (u64) and kinds (u32) of a batch, in mapped pinned memory that the
+// finish kernel writes directly (no copy back).
+int grow_results(BatchWorkspace& ws, uint64_t nq) {
+  if (nq <= ws.res_len) return MDRQ_OK;
+  if (ws.h_res) (void)hipHostFree(ws.h_res);
+  ws.h_res = ws.h_res_dev = nullptr;
+  ws.res_len = 0;
+  if (hipHostMalloc(&ws.h_res, nq * 12, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer(&ws.h_res_dev, ws.h_res, 0) != hipSuccess)
+    return fail(MDRQ_ENOMEM, "batch result buffers");
+  ws.res_len = nq;
+  return MDRQ_OK;
+}
+
 // One query of a shared scan.
 struct Item {
   uint32_t index;         // position in the caller's arrays
@@ -244,16 +258,8 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   if (rc) return rc;
   rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, nq * n_tiles + 1, "batch tile counts");
   if (rc) return rc;
-  if (nq > ws.res_len) {
-    if (ws.d_res) (void)hipFree(ws.d_res);
-    if (ws.h_res) (void)hipHostFree(ws.h_res);
-    ws.d_res = ws.h_res = nullptr;
-    ws.res_len = 0;
-    if (hipMalloc(&ws.d_res, nq * 12) != hipSuccess ||
-        hipHostMalloc(&ws.h_res, nq * 12, hipHostMallocDefault) != hipSuccess)
-      return fail(MDRQ_ENOMEM, "batch result buffers");
-    ws.res_len = nq;
-  }
+  rc = grow_results(ws, nq);
+  if (rc) return rc;
   // Blob: table, group_first, group_table (uint32), then BatchOut records (8-aligned).
   const uint64_t words_u32 = table.size() + group_first.size() + group_table.size();
   const uint64_t outs_off = (words_u32 * 4 + 15) / 16 * 16;
@@ -287,8 +293,8 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   fin.words = ws.d_words;
   fin.tile_counts = ws.d_tile_counts;
   fin.outs = reinterpret_cast<const BatchOut*>(static_cast<const uint8_t*>(ws.d_blob) + outs_off);
-  fin.counts_out = static_cast<uint64_t*>(ws.d_res);
-  fin.kind_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws.d_res) + nq * 8);
+  fin.counts_out = static_cast<uint64_t*>(ws.h_res_dev);
+  fin.kind_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws.h_res_dev) + nq * 8);
 
   int waves = cfg.waves == 8 ? 8 : 4;
   int rg;
@@ -327,15 +333,15 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
              "shared scan launch");
   MDRQ_HIP(launch_batch_finish(fin, static_cast<uint32_t>(nq), stream), "batch finish launch");
   MDRQ_HIP(hipEventRecord(ws.ev1, stream), "hipEventRecord");
-  MDRQ_HIP(hipMemcpyAsync(ws.h_res, ws.d_res, nq * 12, hipMemcpyDeviceToHost, stream),
-           "copy batch counts");
   MDRQ_HIP(hipStreamSynchronize(stream), "shared scan completion");
   float ms = 0.f;
   MDRQ_HIP(hipEventElapsedTime(&ms, ws.ev0, ws.ev1), "hipEventElapsedTime");
   if (ms_out) *ms_out = ms;
 
-  const uint64_t* counts = static_cast<const uint64_t*>(ws.h_res);
-  const uint32_t* kinds = reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(ws.h_res) + nq * 8);
+  // The finish kernel wrote the counts and kinds into the mapped pinned buffer.
+  const volatile uint64_t* counts = static_cast<const volatile uint64_t*>(ws.h_res);
+  const volatile uint32_t* kinds =
+      reinterpret_cast<const volatile uint32_t*>(static_cast<const uint8_t*>(ws.h_res) + nq * 8);
   for (uint64_t q = 0; q < nq; ++q) {
     mdrq_result_t* r = items[q].r;
     const uint64_t count = counts[q];
@@ -654,16 +660,8 @@ int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queri
   if (rc) return rc;
   rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, nq * n_tiles + 1, "batch tile counts");
   if (rc) return rc;
-  if (nq > ws.res_len) {
-    if (ws.d_res) (void)hipFree(ws.d_res);
-    if (ws.h_res) (void)hipHostFree(ws.h_res);
-    ws.d_res = ws.h_res = nullptr;
-    ws.res_len = 0;
-    if (hipMalloc(&ws.d_res, nq * 12) != hipSuccess ||
-        hipHostMalloc(&ws.h_res, nq * 12, hipHostMallocDefault) != hipSuccess)
-      return fail(MDRQ_ENOMEM, "batch result buffers");
-    ws.res_len = nq;
-  }
+  rc = grow_results(ws, nq);
+  if (rc) return rc;
   // Query table: at most a 4-word header and 4 words per predicate per query, record
   // offsets and group arrays; then the output records.
   const uint64_t blob = (nq * (8 + 4 * kMaxUnion) + 64) * 4 + nq * sizeof(BatchOut) + 16;
@@ -683,7 +681,6 @@ void free_batch(BatchWorkspace& ws) {
   if (ws.h_blob) (void)hipHostFree(ws.h_blob);
   if (ws.d_words) (void)hipFree(ws.d_words);
   if (ws.d_tile_counts) (void)hipFree(ws.d_tile_counts);
-  if (ws.d_res) (void)hipFree(ws.d_res);
   if (ws.h_res) (void)hipHostFree(ws.h_res);
   if (ws.d_stage) (void)hipFree(ws.d_stage);
   if (ws.ev0) (void)hipEventDestroy(ws.ev0);

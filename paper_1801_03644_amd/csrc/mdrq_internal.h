@@ -30,10 +30,12 @@ struct DevPred {
 
 // Cross-workgroup bookkeeping of one scan launch.  Zero between launches: the last
 // workgroup of a launch resets it, so launches on one stream need no memset.
+// The device copy holds `total`; the kernels write `count_out` and `kind` straight into
+// the pinned host copy, which the host reads after the stream has completed.
 struct ScanState {
   uint64_t total;      // finished workgroups (bits 40..63) and their count (bits 0..39)
   uint64_t count_out;  // exact result size, written at the end of a launch
-  uint32_t error;      // nonzero: the launch detected an inconsistency
+  uint32_t pad;
   uint32_t kind;       // output chosen for MDRQ_OUT_AUTO: 1 bitmap, 0 identifiers
 };
 
@@ -47,7 +49,8 @@ struct ScanParams {
   uint64_t seg_tiles;     // tiles per workgroup segment
   uint32_t* tile_counts;  // kStage: qualifying rows per tile
   uint32_t* block_sums;   // kStage: qualifying rows per workgroup segment
-  ScanState* state;
+  ScanState* state;       // device: the workgroups' running total
+  uint64_t* count_out;    // pinned host memory: exact result size (count, bitmap modes)
   const uint32_t* order;  // device: evaluation order of preds (null: as given)
   DevPred preds[MDRQ_MAX_DIMS];
 };
@@ -62,11 +65,12 @@ struct CompactParams {
   const uint32_t* block_sums;
   uint32_t* ids;
   uint64_t capacity;           // identifiers the output holds
-  uint64_t* count_out;         // exact result size (written by the last workgroup)
+  uint64_t* count_out;         // exact result size (written by the last workgroup;
+                               // pinned host memory)
   uint32_t auto_mode;          // 1: bitmap or identifiers, whichever is smaller and fits
   uint32_t pad;
   uint64_t buf_bytes;          // output bytes (auto_mode)
-  uint32_t* kind_out;          // auto_mode: 1 bitmap, 0 identifiers
+  uint32_t* kind_out;          // auto_mode: 1 bitmap, 0 identifiers (pinned host memory)
 };
 
 // Launch one single-query scan.  `unroll` selects the tile height (float4 loads per
@@ -328,8 +332,8 @@ struct BatchWorkspace {
   uint64_t d_words_len = 0;
   uint32_t* d_tile_counts = nullptr;
   uint64_t d_tile_counts_len = 0;
-  void* d_res = nullptr;         // counts (u64) and kinds (u32) per query
-  void* h_res = nullptr;         // pinned mirror
+  void* h_res = nullptr;         // counts (u64) and kinds (u32) per query: mapped pinned
+  void* h_res_dev = nullptr;     // its device address
   uint64_t res_len = 0;          // queries the two hold
   void* d_stage = nullptr;       // device staging for host-memory outputs
   uint64_t d_stage_bytes = 0;
@@ -370,7 +374,8 @@ struct mdrq_dataset {
   uint32_t* block_sums = nullptr;        // device, block_sums_len entries
   uint64_t block_sums_len = 0;
   uint64_t max_tiles = 0;
-  mdrq::ScanState* host_state = nullptr; // pinned mirror
+  mdrq::ScanState* host_state = nullptr; // pinned: results the kernels write for the host
+  mdrq::ScanState* host_state_dev = nullptr;  // its device address
   void* staging = nullptr;               // device staging for host-resident outputs
   uint64_t staging_bytes = 0;
 

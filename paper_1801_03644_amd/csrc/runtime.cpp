@@ -81,10 +81,13 @@ int alloc_workspace(mdrq_dataset* ds) {
   MDRQ_HIP(hipMemset(ds->state, 0, sizeof(ScanState)), "hipMemset(scan state)");
   MDRQ_HIP(hipMalloc(&ds->stage_bitmap, words * sizeof(uint64_t)), "hipMalloc(stage bitmap)");
   MDRQ_HIP(hipMalloc(&ds->tile_counts, ds->max_tiles * sizeof(uint32_t)), "hipMalloc(tile counts)");
+  // Mapped and coherent: the kernels' stores reach it without a copy.
   MDRQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&ds->host_state), sizeof(ScanState),
-                         hipHostMallocDefault),
+                         hipHostMallocMapped | hipHostMallocCoherent),
            "hipHostMalloc(scan state)");
   memset(ds->host_state, 0, sizeof(ScanState));
+  MDRQ_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&ds->host_state_dev), ds->host_state, 0),
+           "hipHostGetDevicePointer(scan state)");
   return MDRQ_OK;
 }
 
@@ -224,6 +227,7 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
   p.tile_counts = ds->tile_counts;
   p.block_sums = ds->block_sums;
   p.state = ds->state;
+  p.count_out = &ds->host_state_dev->count_out;
   p.order = plan.order;
   for (size_t i = 0; i < plan.preds.size(); ++i) p.preds[i] = plan.preds[i];
   CompactParams c{};
@@ -235,10 +239,10 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
   c.block_sums = ds->block_sums;
   c.ids = static_cast<uint32_t*>(out);
   c.capacity = plan.mode == kIds ? out_elems : 0;
-  c.count_out = &ds->state->count_out;
+  c.count_out = &ds->host_state_dev->count_out;
   c.auto_mode = plan.auto_mode ? 1u : 0u;
   c.buf_bytes = r->buf_bytes;
-  c.kind_out = &ds->state->kind;
+  c.kind_out = &ds->host_state_dev->kind;
 
   if (ds->profiling) {
     if (!ds->ev0) MDRQ_HIP(hipEventCreate(&ds->ev0), "hipEventCreate");
@@ -254,15 +258,11 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
     return fail_hip(e, "scan kernel launch");
   }
   if (ds->profiling) MDRQ_HIP(hipEventRecord(ds->ev2, stream), "hipEventRecord");
-  e = hipMemcpyAsync(ds->host_state, ds->state, sizeof(ScanState), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  // The last workgroup wrote the count (and AUTO's choice) into pinned host memory.
+  e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     recover_state(ds);
     return fail_hip(e, "scan completion");
-  }
-  if (ds->host_state->error) {
-    recover_state(ds);
-    return fail(MDRQ_EDEVICE, "tile look-back wait exceeded its bound; result discarded");
   }
   if (ds->profiling) {
     float ms1 = 0.f, ms2 = 0.f;
@@ -272,9 +272,10 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
     ds->prof_total_ms += ms2;
     ds->prof_launches += 1;
   }
-  const uint64_t count = ds->host_state->count_out;
+  const volatile ScanState* hs = ds->host_state;
+  const uint64_t count = hs->count_out;
   r->count = count;
-  if (plan.auto_mode && ds->host_state->kind == 1) {  // AUTO chose the bitmap
+  if (plan.auto_mode && hs->kind == 1) {  // AUTO chose the bitmap
     r->mode = MDRQ_OUT_BITMAP;
     r->written = n_words(ds);
     r->status = MDRQ_OK;

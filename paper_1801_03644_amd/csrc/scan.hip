@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kBlock) scan_kernel(ScanParams p) {
                                                    __HIP_MEMORY_SCOPE_AGENT);
       if ((prev >> 40) == gridDim.x - 1) {
         const uint64_t total = (prev & ((uint64_t{1} << 40) - 1)) + s_block_total;
-        __hip_atomic_store(&p.state->count_out, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(p.count_out, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(&p.state->total, uint64_t{0}, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
