@@ -355,3 +355,36 @@ def test_estimated_order_gives_identical_results_and_is_faster():
         for q, a in zip(qs, a1):
             assert a.count == oracle.count(cols, q)
         ds.attach_estimator(None)
+
+
+def test_full_size_c4_batched_estimated_order_sampled():
+    """The learned workload's shape at full size (10^8 x 20, correlated pairs), as the
+    bench runs its held-out set: shared scans with estimated order (an untrained
+    estimator: the histogram ranking), whose grouping splits the 20-column union into
+    register-sized scans.  Every count equals the query alone in given order, and a
+    sample of identifier lists equals the oracle's."""
+    import torch
+
+    from tests.gpu_helpers import device
+
+    w = dg.workload("c4")
+    _print("c4 full size: generating")
+    raw = w.columns()
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 64)   # held-out mix: k 3..10
+    with mdrq.Dataset.from_host(raw) as ds, mdrq.Estimator(ds) as est:
+        ds.attach_estimator(est)
+        outs = [torch.full((ds.n_rows,), -1, dtype=torch.int32, device=device()) if i in (0, 9, 33)
+                else None for i in range(len(qs))]
+        modes = ["ids" if o is not None else "count" for o in outs]
+        _print("c4 full size: batch of", len(qs))
+        ans = ds.query_batch(qs, outs, modes, flags=mdrq.Q_ORDER_ESTIMATED)
+        for i, q in enumerate(qs):
+            assert ans[i].count == ds.query(q, None, mode="count").count, i
+        for i in (0, 9, 33):
+            _print("c4 full size: oracle", i)
+            st, cnt, want = oracle.query(cols, qs[i])
+            assert ans[i].count == cnt
+            got = outs[i][:ans[i].written].cpu().numpy().view(np.uint32)
+            assert np.array_equal(got, want), i
+        ds.attach_estimator(None)

@@ -282,3 +282,22 @@ def test_auto_output_picks_the_smaller_exact_result(host):
                     got = buf[:4 * a.written].view(np.uint32)
                     assert np.array_equal(got, want[:len(got)])
                     assert a.status == (mdrq.EOVERFLOW if cnt > n_bytes // 4 else mdrq.OK)
+
+
+def test_full_size_c2_sampled():
+    """The headline shape at full size (10^8 x 17), in the bench's launch configuration
+    (ids output, default tile and grid): the first bench queries against the oracle,
+    identifier for identifier; two of them also without early break and as bitmaps."""
+    w = dg.workload("c2")
+    _print("c2 full size: generating")
+    raw = w.columns()
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 1000)[:5]
+    with mdrq.Dataset.from_host(raw) as ds:
+        for i, q in enumerate(qs):
+            _print("c2 full size: query", i, "k =", len(q[0]))
+            modes = ("ids", "bitmap") if i < 2 else ("ids",)
+            assert_same(ds, cols, q, modes=modes, label=f"c2 full {i}")
+            if i < 2:
+                assert_same(ds, cols, q, modes=("ids",), flags=mdrq.Q_NO_EARLYOUT,
+                            label=f"c2 full {i} no early break")

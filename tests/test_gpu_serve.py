@@ -155,3 +155,37 @@ def test_serve_with_estimated_order_is_exact():
                                        n_streams=3, budget_bytes=1 << 26, use_estimator=True)
         check(ds, cols, qs, modes, outs, answers, "estimated")
         ds.attach_estimator(None)
+
+
+def test_full_size_c5_served_sampled():
+    """The serving shape at full size (2*10^8 x 12 resident), as the bench runs it:
+    requests replayed through the serving loop with estimated order (an untrained
+    estimator: the histogram ranking) and AUTO outputs; every count equals the query
+    alone, and a sample of results equals the oracle's identifiers."""
+    from paper_1801_03644_amd.mdrq import Estimator
+
+    w = dg.workload("c5")
+    _print("c5 full size: generating")
+    raw = w.columns()
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 40)
+    modes = ["auto"] * len(qs)
+    with mdrq.Dataset.from_host(raw) as ds:
+        est = Estimator(ds)
+        ds.attach_estimator(est)
+        outs = outputs(ds.n_rows, modes, caps=[ds.n_rows] * len(qs))
+        _print("c5 full size: serve", len(qs))
+        answers, lat, stats = ds.serve(poisson(len(qs), 20_000, seed=5), qs, outs, modes,
+                                       max_batch=32, n_streams=2, budget_bytes=2 << 30,
+                                       use_estimator=True)
+        assert stats["completed"] == len(qs)
+        for i, q in enumerate(qs):
+            assert answers[i].count == ds.query(q, None, mode="count").count, i
+        for i in (0, 7, 19):
+            _print("c5 full size: oracle", i)
+            st, cnt, want = oracle.query(cols, qs[i])
+            assert answers[i].count == cnt
+            assert answers[i].status == mdrq.OK
+            assert np.array_equal(payload(outs[i], answers[i], ds.n_rows), want), i
+        ds.attach_estimator(None)
+        est.close()
