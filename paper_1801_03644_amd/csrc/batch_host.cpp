@@ -473,6 +473,27 @@ std::vector<std::vector<size_t>> plan_groups(const std::vector<Item>& items, uin
   return cost(split) < cost(wide) ? split : wide;
 }
 
+// A shared scan reads every column of its union in full and tests each query on every
+// row; one scan per query reads only that query's columns, and its early break skips
+// the groups of rows already rejected (about a quarter of the bytes on c2's mix).  For a
+// few queries the separate scans are cheaper.  Model: shared = max(column bytes at
+// 6 TB/s, row tests at 8e12/s in registers or 4e12/s in LDS) + 30 us; separate =
+// sum over queries of 3/4 of its column bytes at 6 TB/s + 25 us.
+bool plain_is_cheaper(const std::vector<Item>& items, const std::vector<size_t>& members, int used,
+                      uint64_t n_rows) {
+  constexpr double kBytesPerS = 6e12, kRegTests = 8e12, kLdsTests = 4e12;
+  const double n = static_cast<double>(n_rows);
+  double tests = 0.0, plain = 0.0;
+  for (size_t m : members) {
+    const double k = static_cast<double>(items[m].plan.dims.size());
+    tests += n * k;
+    plain += 0.75 * 4.0 * n * k / kBytesPerS + 25e-6;
+  }
+  const double shared =
+      std::max(4.0 * n * used / kBytesPerS, tests / (used > kMaxSlots ? kLdsTests : kRegTests)) + 30e-6;
+  return plain < shared;
+}
+
 // Candidate configurations the autotuner tries on a new batch shape.
 std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
   std::vector<BatchConfig> c;
@@ -565,18 +586,30 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
   // group it adds the fewest new columns to (a new group if none has room).  Queries
   // on overlapping columns share a scan, so each column is read by few scans.
   std::vector<std::vector<size_t>> groups = plan_groups(shared, ds->n_dims, ds->n_rows);
+  const bool fixed = ds->batch_waves || ds->batch_group || ds->batch_rows || ds->batch_variant ||
+                     !ds->autotune;
   for (const std::vector<size_t>& members : groups) {
     std::vector<Item> batch;
     std::vector<bool> in(ds->n_dims, false);
     int used = 0;
-    for (size_t m : members) {
+    for (size_t m : members)
       for (uint32_t d : shared[m].plan.dims)
         if (!in[d]) {
           in[d] = true;
           ++used;
         }
-      batch.push_back(std::move(shared[m]));
+    if (!fixed && plain_is_cheaper(shared, members, used, ds->n_rows)) {
+      for (size_t m : members) {
+        Item& it = shared[m];
+        it.r->mode = it.plan.mode == kBitmap ? MDRQ_OUT_BITMAP
+                     : it.plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
+        int rc = run_query(ds, it.plan, it.r, stream);
+        if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
+      }
+      if (st) st->alone += members.size();
+      continue;
     }
+    for (size_t m : members) batch.push_back(std::move(shared[m]));
     BatchConfig cfg;
     cfg.waves = ds->batch_waves ? ds->batch_waves : 4;
     cfg.group = ds->batch_group;
@@ -584,8 +617,6 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     // Untuned default: the slot-mask register variant (fastest on every measured shape).
     cfg.lds = ds->batch_variant == 1 ? 0 : ds->batch_variant == 2 ? 1 : ds->batch_variant == 3 ? 2 : 3;
     if (used > kMaxSlots && !ds->batch_rows) cfg.rows_per_lane = used > 32 ? 1 : 2;
-    const bool fixed = ds->batch_waves || ds->batch_group || ds->batch_rows || ds->batch_variant ||
-                       !ds->autotune;
     float ms = 0.f;
     if (fixed) {
       int rc = run_shared(ds, ws, batch, cfg, stream, &ms);

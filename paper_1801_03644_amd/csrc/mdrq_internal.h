@@ -305,6 +305,7 @@ struct BatchRunStats {
   uint64_t scans = 0;
   uint64_t column_bytes = 0;
   double device_ms = 0.0;
+  uint64_t alone = 0;          // queries answered by their own scan (cheaper for few)
 };
 // Batched path (batch_host.cpp).  ws: the workspace to use (null: the dataset's own);
 // tune: a new batch shape may be autotuned (otherwise a known or default configuration
