@@ -212,7 +212,8 @@ def test_host_outputs_and_borrowed_columns():
 @pytest.mark.parametrize("grid", [1, 2, 7, 64, 0])
 def test_launch_shapes_and_repeat_runs_are_deterministic(grid):
     """Any number of workgroups (down to one) gives the same ordered result; a tiny
-    grid makes every workgroup run many tiles and exercises the look-back chain."""
+    grid makes every workgroup run a long segment of tiles, whose offsets the
+    compaction's segment sums must carry."""
     n = 1_000_003
     raw = [dg.column(16, j, dg.uniform(), n) for j in range(2)]
     cols = oracle.prepare(raw)
