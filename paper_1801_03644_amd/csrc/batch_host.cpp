@@ -64,6 +64,7 @@ struct Item {
   Plan plan;
   uint32_t kind;          // BatchKind
   mdrq_result_t* r;
+  std::vector<float> sel; // estimated selectivity of each plan predicate alone
 };
 
 uint32_t kind_of(uint32_t mode) {
@@ -157,13 +158,26 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
         table[base + 2 + 2 * s] = batch_key(pl.preds[i].lo);
         table[base + 3 + 2 * s] = batch_key(pl.preds[i].hi);
       }
-      // Early-break tests after every second predicate in slot order, but not after
-      // the last one.
+      // Early-break tests, placed by the estimated chance that the whole chunk is
+      // rejected: with s the product of the selectivities so far (slot order), a chunk
+      // of R rows survives with probability about 1 - exp(-R s).  A test (five vector
+      // instructions) follows a predicate when that chance has grown by a third since
+      // the last test and predicates remain; none follows the last one.
+      std::vector<float> s_of(reg_slots, 1.0f);
+      for (size_t i = 0; i < pl.preds.size(); ++i)
+        s_of[slot_of[pl.dims[i]]] = items[q].sel[i];
+      const double chunk_rows = 64.0 * cfg.rows_per_lane;
+      double cum = 1.0, p_tested = 0.0;
       uint32_t seen = 0;
       for (uint32_t s = 0; s < reg_slots; ++s)
         if ((table[base + 1] >> s) & 1u) {
           ++seen;
-          if (seen % 2 == 0 && seen < pl.preds.size()) table[base + 1] |= 0x10000u << s;
+          cum *= std::max(0.0f, std::min(1.0f, s_of[s]));
+          const double p_dead = std::exp(-chunk_rows * cum);
+          if (seen < pl.preds.size() && p_dead - p_tested > 1.0 / 3.0) {
+            table[base + 1] |= 0x10000u << s;
+            p_tested = p_dead;
+          }
         }
     }
     q0 = q1;
@@ -579,7 +593,22 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
       alone.push_back(i);
       continue;
     }
-    shared.push_back(Item{i, std::move(plan), kind_of(rs[i].mode), &rs[i]});
+    // Per-predicate selectivities for placing the early-break tests: the estimator's,
+    // when the batch was estimated, else the interval's share of the column's range.
+    std::vector<float> sel(plan.preds.size());
+    const float* row = est.empty() ? nullptr : &est[static_cast<size_t>(i) * (ds->n_dims + 1)];
+    for (size_t j = 0; j < sel.size(); ++j) {
+      const uint32_t d = plan.dims[j];
+      if (row) {
+        sel[j] = row[d];
+      } else {
+        const double lo = std::max<double>(plan.preds[j].lo, ds->col_min[d]);
+        const double hi = std::min<double>(plan.preds[j].hi, ds->col_max[d]);
+        const double range = static_cast<double>(ds->col_max[d]) - ds->col_min[d];
+        sel[j] = range > 0 && std::isfinite(range) ? static_cast<float>(std::max(0.0, hi - lo) / range) : 1.0f;
+      }
+    }
+    shared.push_back(Item{i, std::move(plan), kind_of(rs[i].mode), &rs[i], std::move(sel)});
   }
   // Grouping into shared scans whose union of columns fits the register slots:
   // best-fit decreasing -- queries with the most columns first, each into the open
