@@ -11,9 +11,11 @@ CUS = 256
 CLOCK_GHZ = 2.4
 # Vector compares: 4 SIMDs x 16 lanes per CU retire one 32-bit compare per lane and clock
 # (a wave64 instruction every 4 clocks per SIMD): 256 * 64 * 2.4e9 = 3.93e13 per second.
-# A range test on one row needs at least one compare (unsigned range trick), so this is
-# the ALU ceiling of row-predicate tests.
-ALU_TESTS_PEAK = CUS * 64 * CLOCK_GHZ * 1e9
+# The work of one row-predicate test is two compares, lo <= x and x <= hi (no single
+# vector instruction decides a closed interval on this ISA: subtract then compare, or
+# median-of-three then compare), so the shared scans' ALU roofline counts compares.
+ALU_COMPARES_PEAK = CUS * 64 * CLOCK_GHZ * 1e9
+COMPARES_PER_TEST = 2
 
 
 def column_bytes(n_rows: int, n_dims: int) -> int:
