@@ -316,10 +316,17 @@ __global__ void __launch_bounds__(W * 64) batch_reg_kernel(BatchParams bp) {
         const uint32_t head = rr[0];
         if (lane == 0) atomicAdd(&s_cnt[qi], c);
         if (((head >> 8) & 0x3u) != kBatchCount) {
-          uint64_t* words = bp.words + static_cast<uint64_t>(head >> 16) * bp.n_words + word0;
+          // The non-zero words, and the chunk's mark: bit g <=> word g was stored.
+          const uint64_t out = head >> 16;
+          uint64_t* words = bp.words + out * bp.n_words + word0;
+          uint32_t stored = 0;
 #pragma unroll
           for (int g = 0; g < RG; ++g)
-            if (m[g] != 0 && lane == 0) words[g] = m[g];
+            if (m[g] != 0) {
+              stored |= 1u << g;
+              if (lane == 0) words[g] = m[g];
+            }
+          if (lane == 0) bp.flags[out * bp.n_chunks + row0 / kChunkRows] = static_cast<uint16_t>(stored);
         }
       };
       // Two record buffers in turn: the next record is loaded while one is tested.
@@ -631,6 +638,16 @@ __global__ void __launch_bounds__(kFinThreads) batch_count_kernel(BatchFinish f)
 // out ascending.  Nothing beyond the caller's capacity is written.
 constexpr uint32_t kEmitTiles = 128;
 
+// Word w of query q's scratch row: zero unless the scan marked it as stored.  The word
+// and its mark are loaded independently (both in bounds), then combined.
+__device__ __forceinline__ uint64_t scratch_word(const BatchFinish& f, const uint64_t* words,
+                                                 uint64_t out_index, uint64_t w) {
+  const uint64_t v = words[w];
+  if (!f.flags) return v;
+  const uint32_t mark = f.flags[out_index * f.n_chunks + (w >> f.chunk_shift)];
+  return (mark >> (w & ((1u << f.chunk_shift) - 1))) & 1u ? v : 0;
+}
+
 __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) {
   const uint32_t q = blockIdx.y;
   const uint32_t kind = f.kind_out[q];
@@ -649,7 +666,8 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
     const uint64_t lim = cap < f.n_words ? cap : f.n_words;
     const uint64_t w_end = t_end * 64 < lim ? t_end * 64 : lim;
     uint64_t* dst = static_cast<uint64_t*>(o.buf);
-    for (uint64_t i = t_beg * 64 + tid; i < w_end; i += kFinThreads) dst[i] = words[i];
+    for (uint64_t i = t_beg * 64 + tid; i < w_end; i += kFinThreads)
+      dst[i] = scratch_word(f, words, o.out_index, i);
     return;
   }
   const uint32_t* offs = f.tile_counts + static_cast<uint64_t>(q) * f.n_tiles;
@@ -661,7 +679,7 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
     if (end == beg || beg >= capacity) continue;
     // One tile = 64 words = one wave-wide load.
     const uint64_t w = t * 64 + lane;
-    const uint64_t word = w < f.n_words ? words[w] : 0;
+    const uint64_t word = w < f.n_words ? scratch_word(f, words, o.out_index, w) : 0;
     const uint32_t k = __popcll(word);
     uint32_t incl = k;
 #pragma unroll
@@ -780,10 +798,12 @@ int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t 
 hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, int lds_variant,
                              dim3 grid, size_t lds_bytes, hipStream_t stream) {
   const int w = waves == 8 ? 8 : 4;
-  const uint64_t n = bp.n_words * bp.n_out;
+  // Zero the scratch rows, or only their chunk marks (slot-mask variant).
+  const uint64_t n = bp.flags ? (bp.n_chunks * bp.n_out + 3) / 4 : bp.n_words * bp.n_out;
   if (n) {
     const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
-    zero_words_kernel<<<static_cast<uint32_t>(blocks), 256, 0, stream>>>(bp.words, n);
+    zero_words_kernel<<<static_cast<uint32_t>(blocks), 256, 0, stream>>>(
+        bp.flags ? reinterpret_cast<uint64_t*>(bp.flags) : bp.words, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -298,6 +298,8 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   bp.group_first = db + table.size();
   bp.group_table = db + table.size() + group_first.size();
   bp.words = ws.d_words;
+  bp.flags = nullptr;
+  bp.n_chunks = 0;
   bp.n_out = n_out;
   bp.tile_counts = ws.d_tile_counts;
   for (int s = 0; s < n_slots; ++s) bp.slot_cols[s] = ds->cols[slot_dim[s]];
@@ -305,6 +307,9 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   fin.n_tiles = n_tiles;
   fin.n_words = nw;
   fin.words = ws.d_words;
+  fin.flags = nullptr;
+  fin.n_chunks = 0;
+  fin.chunk_shift = 0;
   fin.tile_counts = ws.d_tile_counts;
   fin.outs = reinterpret_cast<const BatchOut*>(static_cast<const uint8_t*>(ws.d_blob) + outs_off);
   fin.counts_out = static_cast<uint64_t*>(ws.h_res_dev);
@@ -331,6 +336,17 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   } else {
     rg = batch_rows_per_lane(std::max(1, n_slots), waves, cfg.rows_per_lane);
     lds = max_group_words * 4;
+  }
+  if (reg && n_out) {  // chunk marks instead of zeroed rows
+    const uint64_t chunk_rows = 64 * static_cast<uint64_t>(rg);
+    const uint64_t n_chunks = (n_rows + chunk_rows - 1) / chunk_rows;
+    rc = grow_device(&ws.d_flags, &ws.d_flags_len, (n_chunks * n_out + 3) / 4 + 1, "batch chunk marks");
+    if (rc) return rc;
+    bp.flags = reinterpret_cast<uint16_t*>(ws.d_flags);
+    bp.n_chunks = n_chunks;
+    fin.flags = bp.flags;
+    fin.n_chunks = n_chunks;
+    fin.chunk_shift = static_cast<uint32_t>(__builtin_ctz(static_cast<unsigned>(rg)));
   }
   const int per_cu = batch_blocks_per_cu(std::max(1, n_slots), waves, rg, variant, lds);
   const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
@@ -718,6 +734,11 @@ int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queri
   const uint64_t nq = max_queries;
   int rc = grow_device(&ws.d_words, &ws.d_words_len, std::max<uint64_t>(1, max_rows) * nw + 1, "batch bitmaps");
   if (rc) return rc;
+  // Chunk marks of the slot-mask variant, for its smallest chunk (4 row groups of 64).
+  rc = grow_device(&ws.d_flags, &ws.d_flags_len,
+                   ((ds->n_rows + 255) / 256 * std::max<uint64_t>(1, max_rows) + 3) / 4 + 1,
+                   "batch chunk marks");
+  if (rc) return rc;
   rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, nq * n_tiles + 1, "batch tile counts");
   if (rc) return rc;
   rc = grow_results(ws, nq);
@@ -740,6 +761,7 @@ void free_batch(BatchWorkspace& ws) {
   if (ws.d_blob) (void)hipFree(ws.d_blob);
   if (ws.h_blob) (void)hipHostFree(ws.h_blob);
   if (ws.d_words) (void)hipFree(ws.d_words);
+  if (ws.d_flags) (void)hipFree(ws.d_flags);
   if (ws.d_tile_counts) (void)hipFree(ws.d_tile_counts);
   if (ws.h_res) (void)hipHostFree(ws.h_res);
   if (ws.d_stage) (void)hipFree(ws.d_stage);

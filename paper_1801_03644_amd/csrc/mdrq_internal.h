@@ -109,8 +109,15 @@ struct BatchParams {
   const uint32_t* group_first;  // first query of each group (+ end)
   const uint32_t* group_table;  // first table word of each group (+ end)
   uint64_t* words;              // bitmap scratch, one row of n_words per output query
-  uint64_t n_out;               // rows of the scratch in use (zeroed before the scan)
+  uint64_t n_out;               // rows of the scratch in use
   uint32_t* tile_counts;        // [query][tile]
+  // Null: the scratch rows are zeroed before the scan, which stores the non-zero words.
+  // Otherwise (slot-mask variant) one 16-bit mark per (output row, chunk of at most
+  // 16 words) is zeroed instead; the scan stores the
+  // non-zero words of a chunk and sets bit g of its mark for each stored word g, and the
+  // finish takes unmarked words as zero.
+  uint16_t* flags;
+  uint64_t n_chunks;            // chunks per output row
   const float* slot_cols[kMaxUnion];
 };
 
@@ -125,6 +132,10 @@ struct BatchFinish {
   uint64_t n_tiles;
   uint64_t n_words;
   const uint64_t* words;
+  const uint16_t* flags;        // as BatchParams::flags (null: every word is valid)
+  uint64_t n_chunks;
+  uint32_t chunk_shift;         // log2 of the bitmap words per chunk (4, 8 or 16 words)
+  uint32_t pad;
   uint32_t* tile_counts;        // [query][tile]; becomes output positions for identifiers
   const BatchOut* outs;
   uint64_t* counts_out;         // [query] exact count
@@ -331,6 +342,8 @@ struct BatchWorkspace {
   uint64_t h_blob_bytes = 0;
   uint64_t* d_words = nullptr;   // bitmap scratch
   uint64_t d_words_len = 0;
+  uint64_t* d_flags = nullptr;   // chunk marks of the slot-mask variant (as 64-bit words)
+  uint64_t d_flags_len = 0;
   uint32_t* d_tile_counts = nullptr;
   uint64_t d_tile_counts_len = 0;
   void* h_res = nullptr;         // counts (u64) and kinds (u32) per query: mapped pinned
