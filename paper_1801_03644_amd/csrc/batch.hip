@@ -230,6 +230,9 @@ template <int D, int W, int RG>
 __global__ void __launch_bounds__(W * 64) batch_reg_kernel(BatchParams bp) {
   static_assert(W * RG <= 64, "a tile must hold at least one chunk per wave");
   constexpr uint32_t R = RegRecord<D>::kWords;
+  // Chunk marks instead of zeroed scratch rows, where scalar registers allow: with 12
+  // or 16 slots the mark's address would push scalar spills into the query loop.
+  constexpr bool kMarks = batch_reg_uses_marks(D);
   extern __shared__ uint32_t lds[];
   const uint32_t group = blockIdx.y;
   const uint32_t q_beg = bp.group_first[group];
@@ -316,17 +319,23 @@ __global__ void __launch_bounds__(W * 64) batch_reg_kernel(BatchParams bp) {
         const uint32_t head = rr[0];
         if (lane == 0) atomicAdd(&s_cnt[qi], c);
         if (((head >> 8) & 0x3u) != kBatchCount) {
-          // The non-zero words, and the chunk's mark: bit g <=> word g was stored.
           const uint64_t out = head >> 16;
           uint64_t* words = bp.words + out * bp.n_words + word0;
-          uint32_t stored = 0;
+          if constexpr (kMarks) {
+            // The non-zero words, and the chunk's mark: bit g <=> word g was stored.
+            uint32_t stored = 0;
 #pragma unroll
-          for (int g = 0; g < RG; ++g)
-            if (m[g] != 0) {
-              stored |= 1u << g;
-              if (lane == 0) words[g] = m[g];
-            }
-          if (lane == 0) bp.flags[out * bp.n_chunks + row0 / kChunkRows] = static_cast<uint16_t>(stored);
+            for (int g = 0; g < RG; ++g)
+              if (m[g] != 0) {
+                stored |= 1u << g;
+                if (lane == 0) words[g] = m[g];
+              }
+            if (lane == 0) bp.flags[out * bp.n_chunks + row0 / kChunkRows] = static_cast<uint16_t>(stored);
+          } else {  // the rows were zeroed: the non-zero words only
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+              if (m[g] != 0 && lane == 0) words[g] = m[g];
+          }
         }
       };
       // Two record buffers in turn: the next record is loaded while one is tested.

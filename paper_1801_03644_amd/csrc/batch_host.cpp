@@ -337,7 +337,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     rg = batch_rows_per_lane(std::max(1, n_slots), waves, cfg.rows_per_lane);
     lds = max_group_words * 4;
   }
-  if (reg && n_out) {  // chunk marks instead of zeroed rows
+  if (reg && n_out && batch_reg_uses_marks(static_cast<int>(reg_slots))) {  // marks, not zeroing
     const uint64_t chunk_rows = 64 * static_cast<uint64_t>(rg);
     const uint64_t n_chunks = (n_rows + chunk_rows - 1) / chunk_rows;
     rc = grow_device(&ws.d_flags, &ws.d_flags_len, (n_chunks * n_out + 3) / 4 + 1, "batch chunk marks");

@@ -673,8 +673,7 @@ int mdrq_label_selectivities(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t 
   }
   const uint32_t O = ds->n_dims + 1;
   const double N = static_cast<double>(ds->n_rows);
-  // Expand: the whole queries first, then every restricting predicate alone, grouped
-  // by dimension so that a shared scan holds many predicates on few columns.
+  // Every restricting predicate alone: counted from sorted copies of the columns.
   std::vector<mdrq_pred> singles;
   std::vector<std::pair<uint32_t, uint32_t>> single_where;  // (query, dimension)
   for (uint32_t i = 0; i < n; ++i) {
@@ -686,33 +685,24 @@ int mdrq_label_selectivities(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t 
         single_where.emplace_back(i, qs[i].preds[k].dim);
       }
   }
-  std::vector<size_t> by_dim(singles.size());
-  for (size_t k = 0; k < by_dim.size(); ++k) by_dim[k] = k;
-  std::stable_sort(by_dim.begin(), by_dim.end(),
-                   [&](size_t a, size_t b) { return singles[a].dim < singles[b].dim; });
-  std::vector<mdrq_query_t> ex;
-  std::vector<std::pair<uint32_t, uint32_t>> where;  // (query, column of sel)
-  ex.reserve(n + singles.size());
-  where.reserve(n + singles.size());
-  for (uint32_t i = 0; i < n; ++i) {
-    ex.push_back(mdrq_query_t{qs[i].preds, qs[i].n_preds, 0});
-    where.emplace_back(i, ds->n_dims);
-  }
-  for (size_t k : by_dim) {
-    ex.push_back(mdrq_query_t{&singles[k], 1, 0});
-    where.push_back(single_where[k]);
-  }
   std::lock_guard<std::mutex> lock(ds->mu);
+  std::vector<uint64_t> single_counts;
+  int rc = count_single_predicates(ds, singles, single_counts);
+  if (rc != MDRQ_OK) return rc;
+  for (size_t k = 0; k < singles.size(); ++k)
+    sel[static_cast<size_t>(single_where[k].first) * O + single_where[k].second] =
+        static_cast<float>(static_cast<double>(single_counts[k]) / N);
+  // The whole queries: shared count-only scans.
+  std::vector<mdrq_query_t> ex(n);
+  for (uint32_t i = 0; i < n; ++i) ex[i] = mdrq_query_t{qs[i].preds, qs[i].n_preds, 0};
   std::vector<mdrq_result_t> rs(MDRQ_MAX_BATCH);
-  for (size_t at = 0; at < ex.size(); at += MDRQ_MAX_BATCH) {
-    const uint32_t m = static_cast<uint32_t>(std::min<size_t>(MDRQ_MAX_BATCH, ex.size() - at));
+  for (uint32_t at = 0; at < n; at += MDRQ_MAX_BATCH) {
+    const uint32_t m = std::min<uint32_t>(MDRQ_MAX_BATCH, n - at);
     for (uint32_t i = 0; i < m; ++i) rs[i] = mdrq_result_t{MDRQ_OUT_COUNT, MDRQ_MEM_HOST, nullptr, 0, 0, 0, 0, 0};
-    int rc = run_batch(ds, ex.data() + at, m, rs.data(), nullptr);
+    rc = run_batch(ds, ex.data() + at, m, rs.data(), nullptr);
     if (rc != MDRQ_OK) return rc;
-    for (uint32_t i = 0; i < m; ++i) {
-      const auto& w = where[at + i];
-      sel[static_cast<size_t>(w.first) * O + w.second] = static_cast<float>(static_cast<double>(rs[i].count) / N);
-    }
+    for (uint32_t i = 0; i < m; ++i)
+      sel[static_cast<size_t>(at + i) * O + ds->n_dims] = static_cast<float>(static_cast<double>(rs[i].count) / N);
   }
   return MDRQ_OK;
 }

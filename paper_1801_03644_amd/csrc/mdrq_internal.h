@@ -156,6 +156,9 @@ hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int 
 // Register slots of the slot-mask variant for a union of n_slots columns (4, 8, 12 or 16):
 // its query records hold 2 + 2 x that many words.
 int batch_reg_slots(int n_slots);
+// Whether the slot-mask variant with that many register slots marks stored chunks
+// (BatchParams::flags) instead of relying on zeroed scratch rows.
+constexpr bool batch_reg_uses_marks(int reg_slots) { return reg_slots <= 8; }
 // LDS bytes the LDS variant stages keys in: waves x slots x rows per lane x 64 x 4.
 size_t batch_lds_key_bytes(int n_slots, int waves, int rg);
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream);
@@ -331,6 +334,10 @@ int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queri
 void free_batch(BatchWorkspace& ws);
 // Close every live server still open on the dataset (serve.cpp), before it is freed.
 void close_servers(mdrq_dataset* ds);
+// Exact count of each single predicate (label.hip): one sort of each queried column's
+// keys, then two binary searches per predicate.
+int count_single_predicates(const mdrq_dataset* ds, const std::vector<mdrq_pred>& preds,
+                            std::vector<uint64_t>& counts);
 }  // namespace mdrq
 
 namespace mdrq {
