@@ -679,16 +679,35 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
       dst[i] = scratch_word(f, words, o.out_index, i);
     return;
   }
+  // The tiles' output positions (and the end of the last) into LDS in one pass.
+  __shared__ uint32_t s_pos[kEmitTiles + 1];
   const uint32_t* offs = f.tile_counts + static_cast<uint64_t>(q) * f.n_tiles;
+  for (uint64_t i = tid; i <= t_end - t_beg; i += kFinThreads) {
+    const uint64_t t = t_beg + i;
+    s_pos[i] = t < f.n_tiles ? offs[t] : static_cast<uint32_t>(count);
+  }
+  __syncthreads();
   uint32_t* ids = static_cast<uint32_t*>(o.buf);
   const uint64_t capacity = o.buf_bytes / 4;
-  for (uint64_t t = t_beg + wave; t < t_end; t += kFinWaves) {
-    const uint64_t beg = offs[t];
-    const uint64_t end = t + 1 < f.n_tiles ? offs[t + 1] : count;
-    if (end == beg || beg >= capacity) continue;
-    // One tile = 64 words = one wave-wide load.
+  auto hit = [&](uint64_t t) {
+    const uint32_t i = static_cast<uint32_t>(t - t_beg);
+    return s_pos[i + 1] != s_pos[i] && s_pos[i] < capacity;
+  };
+  // One tile = 64 words = one wave-wide load; the wave's next tile is loaded while the
+  // current one is written.
+  auto load = [&](uint64_t t) {
     const uint64_t w = t * 64 + lane;
-    const uint64_t word = w < f.n_words ? scratch_word(f, words, o.out_index, w) : 0;
+    return w < f.n_words ? scratch_word(f, words, o.out_index, w) : uint64_t{0};
+  };
+  uint64_t t = t_beg + wave;
+  uint64_t next = t < t_end && hit(t) ? load(t) : 0;
+  for (; t < t_end; t += kFinWaves) {
+    const uint64_t word = next;
+    const uint64_t tn = t + kFinWaves;
+    next = tn < t_end && hit(tn) ? load(tn) : 0;
+    if (!hit(t)) continue;
+    const uint64_t beg = s_pos[t - t_beg];
+    const uint64_t w = t * 64 + lane;
     const uint32_t k = __popcll(word);
     uint32_t incl = k;
 #pragma unroll
