@@ -281,7 +281,9 @@ enum {
                                  3 = keys in registers with each query's predicates
                                  evaluated in column order, 4 = keys in registers with
                                  fixed-size query records (a slot mask and the bounds of
-                                 every slot); 0 = autotune (default) */
+                                 every slot), 5 = per group of up to 128 queries, each
+                                 row's rank among the group's interval ends and per-rank
+                                 query bitsets; 0 = autotune (default) */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
 

@@ -359,6 +359,131 @@ __global__ void __launch_bounds__(W * 64) batch_reg_kernel(BatchParams bp) {
   }
 }
 
+// ---------------------------------------------------------------- rank variant
+
+// Per group of at most 32 * SW queries and per column of the union, the host sorts the
+// distinct interval ends of the group's predicates on that column (key(lo) and
+// key(hi) + 1) into boundaries B[0..M), and tabulates, for every rank r in [0, M], the
+// bitset of the group's queries that the column lets through when M' = r boundaries are
+// <= key(x): query q with predicate [lo, hi] passes iff idx(key(lo)) < r <=
+// idx(key(hi) + 1); a query without a predicate on the column always passes.  Each
+// row then costs, per column, one binary search for its rank and an AND of SW table
+// words -- shared by all the group's queries -- and each query one bit test per 64
+// rows.  Exact: the boundaries include every interval end, so each rank interval lies
+// wholly inside or outside every predicate.  Rows past the end get the key 0, below
+// every boundary (rank 0), where every predicate fails; a query without predicates
+// carries [key(-inf), key(+inf)] on slot 0.
+//
+// LDS layout of a group (words): per query, its kind and output row (kind | row << 8);
+// per slot, (offset of its boundaries, M); then per slot the boundaries followed, at a
+// 4-word aligned offset, by the table of (M + 1) x SW words.
+template <int W, int RG, int SW>
+__global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
+  static_assert(W * RG <= 64, "a tile must hold at least one chunk per wave");
+  extern __shared__ uint32_t lds[];
+  const uint32_t group = blockIdx.y;
+  const uint32_t q_beg = bp.group_first[group];
+  const uint32_t nq = bp.group_first[group + 1] - q_beg;
+  const uint32_t t_beg = bp.group_table[group];
+  const uint32_t t_len = bp.group_table[group + 1] - t_beg;
+  const uint32_t ns = bp.n_slots;
+  uint32_t* s_cnt = lds;
+  uint32_t* s_tab = lds + ((nq + 3) & ~3u);
+  for (uint32_t i = threadIdx.x; i < t_len; i += W * 64) s_tab[i] = bp.table[t_beg + i];
+  for (uint32_t i = threadIdx.x; i < nq; i += W * 64) s_cnt[i] = 0;
+  __syncthreads();
+  const uint32_t* info = s_tab;            // nq words
+  const uint32_t* hdr = s_tab + nq;        // 2 words per slot
+
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  constexpr uint32_t kChunkRows = 64 * RG;
+  constexpr uint32_t kChunksPerWave = 4096 / kChunkRows / W;
+  for (uint64_t tile = blockIdx.x; tile < bp.n_tiles; tile += gridDim.x) {
+#pragma unroll 1
+    for (uint32_t cw = 0; cw < kChunksPerWave; ++cw) {
+      const uint64_t row0 = tile * 4096 + (wave * kChunksPerWave + cw) * kChunkRows;
+      if (row0 >= bp.n_rows) break;
+      const bool full = row0 + kChunkRows <= bp.n_rows;
+      uint32_t acc[RG][SW];
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int w = 0; w < SW; ++w) acc[g][w] = ~0u;
+#pragma unroll 1
+      for (uint32_t s = 0; s < ns; ++s) {
+        const uint32_t M = hdr[2 * s + 1];
+        if (M == 0) continue;  // no predicate of the group on this column
+        const uint32_t* B = s_tab + hdr[2 * s];
+        const uint32_t* T = B + ((M + 3) & ~3u);
+        uint32_t x[RG];
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+          const uint64_t r = row0 + 64 * g + lane;
+          const uint64_t rc = r < bp.n_rows ? r : bp.n_rows - 1;
+          x[g] = __float_as_uint(__builtin_nontemporal_load(&bp.slot_cols[s][rc]));
+        }
+#pragma unroll
+        for (int g = 0; g < RG; ++g) x[g] = (full || row0 + 64 * g + lane < bp.n_rows) ? bkey(x[g]) : 0u;
+        // rank = number of boundaries <= key (branch-free binary search).
+        uint32_t top = 1;
+        while (top * 2 <= M) top *= 2;
+        uint32_t pos[RG];
+#pragma unroll
+        for (int g = 0; g < RG; ++g) pos[g] = 0;
+#pragma unroll 1
+        for (uint32_t step = top; step > 0; step >>= 1) {
+#pragma unroll
+          for (int g = 0; g < RG; ++g) {
+            const uint32_t i = pos[g] + step - 1 < M ? pos[g] + step - 1 : M - 1;
+            if (pos[g] + step <= M && B[i] <= x[g]) pos[g] += step;
+          }
+        }
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+          const uint32_t* t = T + pos[g] * SW;
+#pragma unroll
+          for (int w = 0; w < SW; ++w) acc[g][w] &= t[w];
+        }
+      }
+      // Per query: its 64-row words are ballots of its bit.
+      const uint64_t word0 = row0 / 64;
+#pragma unroll
+      for (int w = 0; w < SW; ++w) {
+        const uint32_t q0 = 32 * w;
+        if (q0 >= nq) break;
+        const uint32_t q1 = nq - q0 < 32 ? nq - q0 : 32;
+#pragma unroll 1
+        for (uint32_t b = 0; b < q1; ++b) {
+          uint64_t m[RG];
+          uint32_t c = 0;
+#pragma unroll
+          for (int g = 0; g < RG; ++g) {
+            m[g] = ballot((acc[g][w] >> b) & 1u);
+            c += __popcll(m[g]);
+          }
+          if (c == 0) continue;
+          const uint32_t qi = q0 + b;
+          if (lane == 0) atomicAdd(&s_cnt[qi], c);
+          const uint32_t inf = info[qi];
+          if ((inf & 0x3u) != kBatchCount) {
+            uint64_t* words = bp.words + static_cast<uint64_t>(inf >> 8) * bp.n_words + word0;
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+              if (m[g] != 0 && lane == 0) words[g] = m[g];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nq; i += W * 64) {
+      bp.tile_counts[static_cast<uint64_t>(q_beg + i) * bp.n_tiles + tile] = s_cnt[i];
+      s_cnt[i] = 0;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- LDS-staged variant
 
 
@@ -775,6 +900,16 @@ const void* pick_reg(int d, int w, int rg) {
   return w == 8 ? reg_fn<16, 8, 4>() : reg_fn<16, 4, 4>();
 }
 
+const void* pick_rank(int w, int rg, int sw) {
+#define MDRQ_RANK(W_, RG_)                                                                   \
+  (sw <= 1 ? reinterpret_cast<const void*>(&batch_rank_kernel<W_, RG_, 1>)                    \
+   : sw == 2 ? reinterpret_cast<const void*>(&batch_rank_kernel<W_, RG_, 2>)                  \
+             : reinterpret_cast<const void*>(&batch_rank_kernel<W_, RG_, 4>))
+  if (rg >= 8) return w == 8 ? MDRQ_RANK(8, 8) : MDRQ_RANK(4, 8);
+  return w == 8 ? MDRQ_RANK(8, 4) : MDRQ_RANK(4, 4);
+#undef MDRQ_RANK
+}
+
 const void* pick_lds(int w, int rg) {
   if (rg >= 8) return w == 8 ? reinterpret_cast<const void*>(&batch_lds_kernel<8, 8>)
                              : reinterpret_cast<const void*>(&batch_lds_kernel<4, 8>);
@@ -812,19 +947,26 @@ int batch_rows_per_lane(int n_slots, int waves, int rg) {
   return rg == 16 || rg == 8 ? rg : 4;
 }
 
-int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t lds_bytes) {
+namespace {
+const void* pick_scan(int n_slots, int w, int rg, int lds_variant, int sw) {
+  if (lds_variant == 1) return pick_lds(w, rg);
+  if (lds_variant == 4) return pick_rank(w, rg >= 8 ? 8 : 4, sw);
+  if (lds_variant == 3) return pick_reg(n_slots, w, batch_rows_per_lane(n_slots, w, rg));
+  return pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg), lds_variant == 2);
+}
+}  // namespace
+
+int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t lds_bytes, int sw) {
   int blocks = 0;
   const int w = waves == 8 ? 8 : 4;
-  const void* fn = lds_variant == 1   ? pick_lds(w, rg)
-                   : lds_variant == 3 ? pick_reg(n_slots, w, batch_rows_per_lane(n_slots, w, rg))
-                                      : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg), lds_variant == 2);
+  const void* fn = pick_scan(n_slots, w, rg, lds_variant, sw);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, w * 64, lds_bytes) != hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;
 }
 
 hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, int lds_variant,
-                             dim3 grid, size_t lds_bytes, hipStream_t stream) {
+                             dim3 grid, size_t lds_bytes, hipStream_t stream, int sw) {
   const int w = waves == 8 ? 8 : 4;
   // Zero the scratch rows, or only their chunk marks (slot-mask variant).
   const uint64_t n = bp.flags ? (bp.n_chunks * bp.n_out + 3) / 4 : bp.n_words * bp.n_out;
@@ -836,9 +978,7 @@ hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int 
     if (e != hipSuccess) return e;
   }
   void* args[] = {const_cast<BatchParams*>(&bp)};
-  const void* fn = lds_variant == 1   ? pick_lds(w, rg)
-                   : lds_variant == 3 ? pick_reg(n_slots, w, batch_rows_per_lane(n_slots, w, rg))
-                                      : pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg), lds_variant == 2);
+  const void* fn = pick_scan(n_slots, w, rg, lds_variant, sw);
   if (lds_bytes > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds_bytes));

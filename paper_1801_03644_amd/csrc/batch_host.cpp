@@ -114,17 +114,28 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   std::stable_sort(slot_dim.begin(), slot_dim.end(), [&](uint32_t a, uint32_t b) {
     return pos_sum[a] / uses[a] < pos_sum[b] / uses[b];
   });
-  // The slot-mask and LDS variants give a query without predicates an always-true one
-  // on slot 0 (it rejects only the rows past the end), so the union has at least one
+  // The slot-mask, rank and LDS variants give a query without predicates an always-true
+  // one on slot 0 (it rejects only the rows past the end), so the union has at least one
   // column.
-  if ((cfg.lds == 1 || cfg.lds == 3) && slot_dim.empty()) slot_dim.push_back(0);
+  if ((cfg.lds == 1 || cfg.lds == 3 || cfg.lds == 4) && slot_dim.empty()) slot_dim.push_back(0);
   for (size_t i = 0; i < slot_dim.size(); ++i) slot_of[slot_dim[i]] = static_cast<int>(i);
   const int n_slots = static_cast<int>(slot_dim.size());
 
-  const bool use_lds = cfg.lds == 1 || n_slots > kMaxSlots;
+  // Rank variant: queries per group (32 x sw) such that the worst-case tables fit LDS.
+  const size_t lds_room = device().lds > 4096 ? device().lds - 4096 : 0;
+  auto rank_words = [&](uint64_t S) {  // worst case: 2 S interval ends per slot
+    const uint64_t sw = S <= 32 ? 1 : S <= 64 ? 2 : 4;
+    return S + 4 + 2 * static_cast<uint64_t>(n_slots) +
+           static_cast<uint64_t>(n_slots) * (2 * S + 4 + (2 * S + 1) * sw);
+  };
+  uint64_t rank_group = std::min<uint64_t>(128, cfg.group ? cfg.group : nq);
+  while (rank_group > 32 && (rank_words(rank_group) + 4) * 4 > lds_room) rank_group /= 2;
+  const bool rank = cfg.lds == 4 && (rank_words(rank_group) + rank_group + 4) * 4 <= lds_room;
+  const int rank_sw = rank_group <= 32 ? 1 : rank_group <= 64 ? 2 : 4;
+  const bool use_lds = !rank && (cfg.lds == 1 || n_slots > kMaxSlots);
   const bool walk = cfg.lds == 2 && !use_lds;
   const bool reg = cfg.lds == 3 && !use_lds;
-  const int variant = use_lds ? 1 : walk ? 2 : reg ? 3 : 0;
+  const int variant = rank ? 4 : use_lds ? 1 : walk ? 2 : reg ? 3 : 0;
   // Queries per group: what the configuration asks for, and no more than fits LDS.
   uint64_t group = cfg.group ? cfg.group : nq;
   std::vector<uint32_t> group_first, group_table, table;
@@ -182,10 +193,81 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     }
     q0 = q1;
   }
+  // Rank variant: per group, per query (kind | output row << 8), per slot (offset, M),
+  // then per slot the M sorted interval ends and the (M + 1) x sw table of query
+  // bitsets by rank (offsets relative to the group's start, 4-word aligned).
+  for (uint64_t q0 = 0; rank && q0 < nq;) {
+    const uint64_t q1 = std::min<uint64_t>(nq, q0 + rank_group);
+    const uint32_t gq = static_cast<uint32_t>(q1 - q0);
+    group_first.push_back(static_cast<uint32_t>(q0));
+    const uint64_t base = table.size();
+    group_table.push_back(static_cast<uint32_t>(base));
+    table.resize(base + gq + 2 * static_cast<uint64_t>(n_slots), 0u);
+    while ((table.size() - base) % 4) table.push_back(0u);
+    for (uint64_t q = q0; q < q1; ++q)
+      table[base + (q - q0)] = outs[q].kind | (outs[q].out_index << 8);
+    // Per query and slot: (key(lo), key(hi)) of its predicate, if any.
+    std::vector<int> pred_at(gq * static_cast<size_t>(n_slots), -1);
+    for (uint64_t q = q0; q < q1; ++q) {
+      const Plan& pl = items[q].plan;
+      for (size_t i = 0; i < pl.preds.size(); ++i) pred_at[(q - q0) * n_slots + slot_of[pl.dims[i]]] = static_cast<int>(i);
+    }
+    for (int sl = 0; sl < n_slots; ++sl) {
+      std::vector<uint32_t> ends;
+      auto bounds_of = [&](uint64_t q, uint32_t& klo, uint32_t& khi) {
+        const Plan& pl = items[q].plan;
+        const int i = pred_at[(q - q0) * n_slots + sl];
+        if (i >= 0) {
+          klo = batch_key(pl.preds[i].lo);
+          khi = batch_key(pl.preds[i].hi);
+          return true;
+        }
+        if (pl.preds.empty() && sl == 0) {  // the always-true predicate
+          klo = batch_key(-std::numeric_limits<float>::infinity());
+          khi = batch_key(std::numeric_limits<float>::infinity());
+          return true;
+        }
+        return false;
+      };
+      for (uint64_t q = q0; q < q1; ++q) {
+        uint32_t klo, khi;
+        if (bounds_of(q, klo, khi)) {
+          ends.push_back(klo);
+          ends.push_back(khi + 1);  // keys of non-NaN floats stay below 0xFFFFFFFF
+        }
+      }
+      std::sort(ends.begin(), ends.end());
+      ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
+      const uint32_t M = static_cast<uint32_t>(ends.size());
+      while ((table.size() - base) % 4) table.push_back(0u);  // 16-byte aligned
+      const uint64_t off = table.size() - base;
+      table[base + gq + 2 * sl] = static_cast<uint32_t>(off);
+      table[base + gq + 2 * sl + 1] = M;
+      if (M == 0) continue;
+      table.insert(table.end(), ends.begin(), ends.end());
+      while ((table.size() - base) % 4) table.push_back(0u);
+      const uint64_t t0 = table.size();
+      table.resize(t0 + static_cast<uint64_t>(M + 1) * rank_sw, 0u);
+      for (uint64_t q = q0; q < q1; ++q) {
+        const uint32_t bit = static_cast<uint32_t>(q - q0);
+        uint32_t klo, khi, r_lo = 0, r_hi = M;  // the query passes for ranks in (r_lo, r_hi]
+        if (bounds_of(q, klo, khi)) {
+          r_lo = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), klo) - ends.begin());
+          r_hi = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), khi + 1) - ends.begin());
+        } else {
+          r_lo = 0;  // no predicate on this slot: every rank, 0 included
+          for (uint32_t r = 0; r <= M; ++r) table[t0 + r * rank_sw + bit / 32] |= 1u << (bit % 32);
+          continue;
+        }
+        for (uint32_t r = r_lo + 1; r <= r_hi; ++r) table[t0 + r * rank_sw + bit / 32] |= 1u << (bit % 32);
+      }
+    }
+    q0 = q1;
+  }
   // Group table: record offsets (padded to 4 words), then per query a 4-word header
   // and one 4-word entry (slot, key(lo), key(hi) - key(lo) or, for the LDS variant,
   // key(hi), 0) per predicate.
-  for (uint64_t q0 = 0; !reg && q0 < nq;) {
+  for (uint64_t q0 = 0; !reg && !rank && q0 < nq;) {
     // Grow the group while its table and counts fit LDS.
     uint64_t words = 0, q1 = q0;
     while (q1 < nq && q1 - q0 < group) {
@@ -238,6 +320,8 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     max_group_words = std::max<uint64_t>(
         max_group_words, (reg ? 0 : group_table[g + 1] - group_table[g]) +
                              ((group_first[g + 1] - group_first[g] + 3) & ~uint64_t{3}));
+  if (rank && max_group_words * 4 > lds_room)
+    return fail(MDRQ_ENOTSUP, "shared scan: rank tables do not fit LDS");
 
   // Outputs: device buffers directly, host buffers through device staging.
   uint64_t stage_need = 0;
@@ -333,6 +417,10 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     }
     lds = need(rg);
     if (lds > device().lds) return fail(MDRQ_ENOTSUP, "shared scan: union keys do not fit LDS");
+  } else if (rank) {
+    rg = cfg.rows_per_lane >= 8 ? 8 : 4;
+    if (waves == 8) rg = std::min(rg, 8);
+    lds = max_group_words * 4;
   } else {
     rg = batch_rows_per_lane(std::max(1, n_slots), waves, cfg.rows_per_lane);
     lds = max_group_words * 4;
@@ -348,7 +436,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     fin.n_chunks = n_chunks;
     fin.chunk_shift = static_cast<uint32_t>(__builtin_ctz(static_cast<unsigned>(rg)));
   }
-  const int per_cu = batch_blocks_per_cu(std::max(1, n_slots), waves, rg, variant, lds);
+  const int per_cu = batch_blocks_per_cu(std::max(1, n_slots), waves, rg, variant, lds, rank_sw);
   const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
   const uint64_t gx = std::max<uint64_t>(1, std::min<uint64_t>(n_tiles, resident / n_groups));
 
@@ -359,7 +447,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   MDRQ_HIP(hipEventRecord(ws.ev0, stream), "hipEventRecord");
   if (n_tiles > 0)
     MDRQ_HIP(launch_batch_scan(bp, std::max(1, n_slots), waves, rg, variant,
-                               dim3(static_cast<uint32_t>(gx), n_groups), lds, stream),
+                               dim3(static_cast<uint32_t>(gx), n_groups), lds, stream, rank_sw),
              "shared scan launch");
   MDRQ_HIP(launch_batch_finish(fin, static_cast<uint32_t>(nq), stream), "batch finish launch");
   MDRQ_HIP(hipEventRecord(ws.ev1, stream), "hipEventRecord");
@@ -536,7 +624,7 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
   for (uint64_t g : {nq, (nq + 1) / 2, (nq + 3) / 4}) {
     if (g < 16 && g != nq) continue;
     for (int w : {4, 8}) {
-      if (n_slots <= kMaxSlots && variant != 2)
+      if (n_slots <= kMaxSlots && variant != 2 && variant != 5)
         for (int rg : {16, 8, 4})
           for (int v : {0, 2, 3}) {
             if ((variant == 1 && v != 0) || (variant == 3 && v != 2) || (variant == 4 && v != 3))
@@ -548,6 +636,15 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
             b.lds = v;
             add(b);
           }
+      if (variant == 0 || variant == 5)
+        for (int rg : {8, 4}) {
+          BatchConfig b;
+          b.waves = w;
+          b.group = static_cast<uint32_t>(std::min<uint64_t>(g, 128));
+          b.rows_per_lane = rg;
+          b.lds = 4;
+          add(b);
+        }
       if (variant == 0 || variant == 2 || n_slots > kMaxSlots) {
         bool any = false;
         for (int rg : {8, 4, 2, 1}) {
@@ -659,8 +756,9 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     cfg.waves = ds->batch_waves ? ds->batch_waves : 4;
     cfg.group = ds->batch_group;
     cfg.rows_per_lane = ds->batch_rows ? ds->batch_rows : used > 8 ? 4 : 8;
-    // Untuned default: the slot-mask register variant (fastest on every measured shape).
-    cfg.lds = ds->batch_variant == 1 ? 0 : ds->batch_variant == 2 ? 1 : ds->batch_variant == 3 ? 2 : 3;
+    // Untuned default: the rank variant (fastest on every measured shape, c3 and c5).
+    cfg.lds = ds->batch_variant == 1 ? 0 : ds->batch_variant == 2 ? 1 : ds->batch_variant == 3 ? 2
+              : ds->batch_variant == 4 ? 3 : 4;
     if (used > kMaxSlots && !ds->batch_rows) cfg.rows_per_lane = used > 32 ? 1 : 2;
     float ms = 0.f;
     if (fixed) {

@@ -144,15 +144,17 @@ struct BatchFinish {
 
 uint32_t batch_key(float x);
 int batch_rows_per_lane(int n_slots, int waves, int rg);
-int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t lds_bytes);
+int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t lds_bytes, int sw = 1);
 // Shared-scan launch.  lds_variant 0: union keys in registers (n_slots <= kMaxSlots,
 // query table in LDS), each predicate's slot searched; 2: the same with each query's
 // predicates sorted by slot and the slots walked in order; 3: union keys in registers,
 // fixed-size query records (slot mask, bounds per slot) read with scalar loads and the
-// range test as a median of three; 1: union keys staged in LDS (n_slots <= kMaxUnion,
-// query table read with scalar loads).  lds_bytes: the dynamic LDS of the launch.
+// range test as a median of three; 4: per group of 32 * sw queries, each row's rank
+// among the group's interval ends and per-rank query bitsets (tables in LDS, any union
+// that fits); 1: union keys staged in LDS (n_slots <= kMaxUnion, query table read with
+// scalar loads).  lds_bytes: the dynamic LDS of the launch.
 hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, int lds_variant,
-                             dim3 grid, size_t lds_bytes, hipStream_t stream);
+                             dim3 grid, size_t lds_bytes, hipStream_t stream, int sw = 1);
 // Register slots of the slot-mask variant for a union of n_slots columns (4, 8, 12 or 16):
 // its query records hold 2 + 2 x that many words.
 int batch_reg_slots(int n_slots);
@@ -368,7 +370,8 @@ struct BatchConfig {
   int rows_per_lane = 16;        // 64-row groups per lane per chunk: 2, 4, 8 or 16
   int lds = 0;                   // 1: keys staged in LDS (any union up to kMaxUnion);
                                  // 2: keys in registers, predicates walked in slot order;
-                                 // 3: keys in registers, slot-mask records
+                                 // 3: keys in registers, slot-mask records;
+                                 // 4: ranks among interval ends, query bitsets
 };
 }  // namespace mdrq
 
@@ -414,7 +417,8 @@ struct mdrq_dataset {
   int batch_rows = 0;                    // 64-row groups per lane (2, 4, 8, 16); 0: autotuned
   int batch_variant = 0;                 // 1: keys in registers, 2: in LDS, 3: registers and
                                          // slot-order walk, 4: registers and slot-mask
-                                         // records; 0: autotuned
+                                         // records, 5: ranks and query bitsets;
+                                         // 0: autotuned
   bool autotune = true;
   std::vector<std::pair<uint64_t, mdrq::BatchConfig>> tuned;  // shape key -> config
   uint64_t batch_launches = 0;

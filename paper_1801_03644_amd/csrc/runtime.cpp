@@ -496,7 +496,7 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
       ds->batch_rows = static_cast<int>(value);
       return MDRQ_OK;
     case MDRQ_OPT_BATCH_VARIANT:
-      if (value < 0 || value > 4) return fail(MDRQ_EINVAL, "batch variant must be 0, 1, 2, 3 or 4");
+      if (value < 0 || value > 5) return fail(MDRQ_EINVAL, "batch variant must be 0 .. 5");
       ds->batch_variant = static_cast<int>(value);
       return MDRQ_OK;
     case MDRQ_OPT_AUTOTUNE:

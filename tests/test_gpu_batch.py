@@ -111,7 +111,7 @@ def test_batch_sizes_and_ragged_tails(n):
             preds.append((int(j), lo, lo + wdt))
         qs.append(dg.make_query(preds))
     with mdrq.Dataset.from_host(raw) as ds:
-        for variant in (0, 4):   # autotuned; slot-mask records
+        for variant in (0, 4, 5):   # autotuned; slot-mask records; ranks and bitsets
             ds.set_option(mdrq.OPT_BATCH_VARIANT, variant)
             for Q in (1, 7, 16):
                 modes = (["ids", "bitmap", "count", "auto"] * 4)[:Q]
@@ -139,7 +139,7 @@ def test_batch_special_values_degenerate_and_invalid():
                                   cands[rng.integers(len(cands))]) for j in dims]))
     modes = (["ids", "bitmap", "auto", "count"] * 16)
     with mdrq.Dataset.from_host(raw) as ds:
-        for variant in (4, 3, 2, 1, 0):
+        for variant in (5, 4, 3, 2, 1, 0):
             ds.set_option(mdrq.OPT_BATCH_VARIANT, variant)
             check_batch(ds, cols, qs, modes, f"special variant={variant}")
         with pytest.raises(mdrq.MdrqError) as e:
@@ -167,12 +167,12 @@ def test_union_beyond_register_slots_and_long_queries():
             preds.append((int(j), lo, lo + (0.6 if k > 10 else 0.4)))
         qs.append(dg.make_query(preds))
     with mdrq.Dataset.from_host(raw) as ds:
-        for variant in (0, 4):
+        for variant in (0, 4, 5):
             ds.set_option(mdrq.OPT_BATCH_VARIANT, variant)
             check_batch(ds, cols, qs, ["ids", "auto"] * 20, f"union variant={variant}")
 
 
-@pytest.mark.parametrize("variant", [0, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 2, 3, 4, 5])
 def test_wide_unions_share_one_scan(variant):
     """40 columns: the union of all 40 is staged in LDS and the batch shares one scan
     (forced LDS variant, or autotuned).  Ragged row count."""
@@ -219,7 +219,8 @@ def test_launch_configurations_give_identical_results():
                 (4, 0, 0, 2, 2), (4, 0, 0, 2, 4), (8, 0, 0, 2, 8), (4, 16, 0, 2, 8), (8, 24, 0, 2, 4),
                 (4, 0, 0, 3, 8), (8, 0, 0, 3, 8), (4, 16, 0, 3, 16), (4, 0, 0, 2, 1),
                 (4, 0, 0, 4, 8), (8, 0, 0, 4, 8), (4, 16, 0, 4, 16), (8, 24, 0, 4, 4),
-                (4, 0, 0, 4, 4), (0, 0, 1, 0, 0)]:
+                (4, 0, 0, 4, 4), (4, 0, 0, 5, 8), (8, 0, 0, 5, 4), (4, 20, 0, 5, 8),
+                (8, 40, 0, 5, 4), (4, 0, 0, 5, 16), (0, 0, 1, 0, 0)]:
             ds.set_option(mdrq.OPT_BATCH_WAVES, waves)
             ds.set_option(mdrq.OPT_BATCH_GROUP, group)
             ds.set_option(mdrq.OPT_AUTOTUNE, tune)
