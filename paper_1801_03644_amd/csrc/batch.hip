@@ -375,7 +375,8 @@ __global__ void __launch_bounds__(W * 64) batch_reg_kernel(BatchParams bp) {
 // carries [key(-inf), key(+inf)] on slot 0.
 //
 // LDS layout of a group (words): per query, its kind and output row (kind | row << 8);
-// per slot, (offset of its boundaries, M); then per slot the boundaries followed, at a
+// per slot, (offset of its boundaries, M); then per slot the M boundaries padded with
+// 0xFFFFFFFF to 2 top - 1 entries (top: the largest power of two <= M), followed, at a
 // 4-word aligned offset, by the table of (M + 1) x SW words.
 template <int W, int RG, int SW>
 __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
@@ -412,10 +413,11 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
         for (int w = 0; w < SW; ++w) acc[g][w] = ~0u;
 #pragma unroll 1
       for (uint32_t s = 0; s < ns; ++s) {
-        const uint32_t M = hdr[2 * s + 1];
+        const uint32_t M = __builtin_amdgcn_readfirstlane(hdr[2 * s + 1]);   // uniform
         if (M == 0) continue;  // no predicate of the group on this column
-        const uint32_t* B = s_tab + hdr[2 * s];
-        const uint32_t* T = B + ((M + 3) & ~3u);
+        const uint32_t* B = s_tab + __builtin_amdgcn_readfirstlane(hdr[2 * s]);
+        const uint32_t top = 1u << (31 - __builtin_clz(M));   // largest power of 2 <= M
+        const uint32_t* T = B + ((2 * top - 1 + 3) & ~3u);    // ends padded to 2 top - 1
         uint32_t x[RG];
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
@@ -425,20 +427,24 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
         }
 #pragma unroll
         for (int g = 0; g < RG; ++g) x[g] = (full || row0 + 64 * g + lane < bp.n_rows) ? bkey(x[g]) : 0u;
-        // rank = number of boundaries <= key (branch-free binary search).
-        uint32_t top = 1;
-        while (top * 2 <= M) top *= 2;
+        // rank = number of boundaries <= key: a branch-free binary search, the reads of
+        // all row groups of a step issued together.  The ends are padded with 0xFFFFFFFF
+        // up to 2 top - 1 entries, the farthest a search reaches, so a candidate past M
+        // is never taken by a key below 0xFFFFFFFF.
         uint32_t pos[RG];
 #pragma unroll
         for (int g = 0; g < RG; ++g) pos[g] = 0;
 #pragma unroll 1
         for (uint32_t step = top; step > 0; step >>= 1) {
+          uint32_t v[RG];
 #pragma unroll
-          for (int g = 0; g < RG; ++g) {
-            const uint32_t i = pos[g] + step - 1 < M ? pos[g] + step - 1 : M - 1;
-            if (pos[g] + step <= M && B[i] <= x[g]) pos[g] += step;
-          }
+          for (int g = 0; g < RG; ++g) v[g] = B[pos[g] + step - 1];
+#pragma unroll
+          for (int g = 0; g < RG; ++g) pos[g] = v[g] <= x[g] ? pos[g] + step : pos[g];
         }
+        // Only the NaN key 0xFFFFFFFF reaches the padding: its rank is M.
+#pragma unroll
+        for (int g = 0; g < RG; ++g) pos[g] = pos[g] < M ? pos[g] : M;
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
           const uint32_t* t = T + pos[g] * SW;
@@ -465,7 +471,7 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
           if (c == 0) continue;
           const uint32_t qi = q0 + b;
           if (lane == 0) atomicAdd(&s_cnt[qi], c);
-          const uint32_t inf = info[qi];
+          const uint32_t inf = __builtin_amdgcn_readfirstlane(info[qi]);
           if ((inf & 0x3u) != kBatchCount) {
             uint64_t* words = bp.words + static_cast<uint64_t>(inf >> 8) * bp.n_words + word0;
 #pragma unroll

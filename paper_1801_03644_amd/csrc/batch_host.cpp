@@ -123,10 +123,10 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
 
   // Rank variant: queries per group (32 x sw) such that the worst-case tables fit LDS.
   const size_t lds_room = device().lds > 4096 ? device().lds - 4096 : 0;
-  auto rank_words = [&](uint64_t S) {  // worst case: 2 S interval ends per slot
+  auto rank_words = [&](uint64_t S) {  // worst case: 2 S interval ends per slot (padded)
     const uint64_t sw = S <= 32 ? 1 : S <= 64 ? 2 : 4;
     return S + 4 + 2 * static_cast<uint64_t>(n_slots) +
-           static_cast<uint64_t>(n_slots) * (2 * S + 4 + (2 * S + 1) * sw);
+           static_cast<uint64_t>(n_slots) * (4 * S + 8 + (2 * S + 1) * sw);
   };
   uint64_t rank_group = std::min<uint64_t>(128, cfg.group ? cfg.group : nq);
   while (rank_group > 32 && (rank_words(rank_group) + 4) * 4 > lds_room) rank_group /= 2;
@@ -245,6 +245,9 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       table[base + gq + 2 * sl + 1] = M;
       if (M == 0) continue;
       table.insert(table.end(), ends.begin(), ends.end());
+      // Padding above every key, to the farthest entry a binary search reads.
+      const uint32_t top = 1u << (31 - __builtin_clz(M));
+      table.resize(table.size() + (2 * top - 1 - M), 0xFFFFFFFFu);
       while ((table.size() - base) % 4) table.push_back(0u);
       const uint64_t t0 = table.size();
       table.resize(t0 + static_cast<uint64_t>(M + 1) * rank_sw, 0u);
