@@ -361,6 +361,63 @@ __global__ void __launch_bounds__(W * 64) batch_reg_kernel(BatchParams bp) {
 
 // ---------------------------------------------------------------- rank variant
 
+// 32 x 32 bit transpose within each half of the wave: on return lane 32 h + c holds in
+// bit r what lane 32 h + r held in bit c.  One stage per index bit k (the stages
+// commute): lanes r and r ^ 2^k trade the bits whose index differs from the lane's in
+// bit k.  Stages 4 and 3 move whole bytes (one byte permute); stages 2..0 rotate the
+// partner's word by 2^k and insert the moved bits.  Partners are fetched with DPP
+// within a row of 16 lanes and with a swizzle across rows.
+struct HalfTranspose {
+  uint32_t m1, a1, m2, a2, m4, a4, s8, s16;
+};
+
+__device__ __forceinline__ HalfTranspose half_transpose_consts(uint32_t lane) {
+  HalfTranspose c;
+  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8, b4 = lane & 16;
+  c.m1 = b0 ? 0x55555555u : 0xAAAAAAAAu;
+  c.a1 = b0 ? 1 : 31;   // rotate right by 1, or left by 1
+  c.m2 = b1 ? 0x33333333u : 0xCCCCCCCCu;
+  c.a2 = b1 ? 2 : 30;
+  c.m4 = b2 ? 0x0F0F0F0Fu : 0xF0F0F0F0u;
+  c.a4 = b2 ? 4 : 28;
+  // Byte selectors over (partner, own): own bytes 0..3, partner bytes 4..7.
+  c.s8 = b3 ? 0x03070105u : 0x06020400u;
+  c.s16 = b4 ? 0x03020706u : 0x05040100u;
+  return c;
+}
+
+__device__ __forceinline__ uint32_t bit_stage(uint32_t a, uint32_t p, uint32_t mask, uint32_t amt) {
+  const uint32_t rot = __builtin_amdgcn_alignbit(p, p, amt);
+  uint32_t r;  // (mask & rot) | (~mask & a) in one instruction
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(mask), "v"(rot), "v"(a));
+  return r;
+}
+
+__device__ __forceinline__ uint32_t lane_xor16(uint32_t a) {  // swizzle: lane ^ 16 within 32
+  return static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(static_cast<int>(a), 0x401F));
+}
+__device__ __forceinline__ uint32_t lane_xor4(uint32_t a) {   // swizzle: lane ^ 4 within 32
+  return static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(static_cast<int>(a), 0x101F));
+}
+__device__ __forceinline__ uint32_t lane_xor8(uint32_t a) {    // DPP row_ror:8
+  return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(a), 0x128, 0xF, 0xF, false));
+}
+__device__ __forceinline__ uint32_t lane_xor2(uint32_t a) {    // DPP quad_perm [2, 3, 0, 1]
+  return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(a), 0x4E, 0xF, 0xF, false));
+}
+__device__ __forceinline__ uint32_t lane_xor1(uint32_t a) {    // DPP quad_perm [1, 0, 3, 2]
+  return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(a), 0xB1, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ uint32_t half_transpose(uint32_t a, const HalfTranspose& c) {
+  a = __builtin_amdgcn_perm(lane_xor16(a), a, c.s16);
+  a = __builtin_amdgcn_perm(lane_xor8(a), a, c.s8);
+  a = bit_stage(a, lane_xor4(a), c.m4, c.a4);
+  a = bit_stage(a, lane_xor2(a), c.m2, c.a2);
+  a = bit_stage(a, lane_xor1(a), c.m1, c.a1);
+  return a;
+}
+
 // Per group of at most 32 * SW queries and per column of the union, the host sorts the
 // distinct interval ends of the group's predicates on that column (key(lo) and
 // key(hi) + 1) into boundaries B[0..M), and tabulates, for every rank r in [0, M], the
@@ -368,8 +425,8 @@ __global__ void __launch_bounds__(W * 64) batch_reg_kernel(BatchParams bp) {
 // <= key(x): query q with predicate [lo, hi] passes iff idx(key(lo)) < r <=
 // idx(key(hi) + 1); a query without a predicate on the column always passes.  Each
 // row then costs, per column, one binary search for its rank and an AND of SW table
-// words -- shared by all the group's queries -- and each query one bit test per 64
-// rows.  Exact: the boundaries include every interval end, so each rank interval lies
+// words -- shared by all the group's queries -- and each 32 queries a bit transpose
+// per 64 rows.  Exact: the boundaries include every interval end, so each rank interval lies
 // wholly inside or outside every predicate.  Rows past the end get the key 0, below
 // every boundary (rank 0), where every predicate fails; a query without predicates
 // carries [key(-inf), key(+inf)] on slot 0.
@@ -398,6 +455,19 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
 
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const HalfTranspose tc = half_transpose_consts(lane);
+  // Lane 32 h + c writes half h of query 32 w + c's words: its output row, and a mask
+  // that drops the stores of count-only queries and of lanes past the group.
+  uint32_t* out[SW];
+  uint32_t keep[SW];
+#pragma unroll
+  for (int w = 0; w < SW; ++w) {
+    const uint32_t qi = 32 * w + (lane & 31);
+    const uint32_t inf = qi < nq ? info[qi] : kBatchCount;
+    keep[w] = (inf & 0x3u) != kBatchCount ? ~0u : 0u;
+    out[w] = reinterpret_cast<uint32_t*>(bp.words + static_cast<uint64_t>(keep[w] ? inf >> 8 : 0) * bp.n_words) +
+             (lane >> 5);
+  }
   constexpr uint32_t kChunkRows = 64 * RG;
   constexpr uint32_t kChunksPerWave = 4096 / kChunkRows / W;
   for (uint64_t tile = blockIdx.x; tile < bp.n_tiles; tile += gridDim.x) {
@@ -452,32 +522,26 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
           for (int w = 0; w < SW; ++w) acc[g][w] &= t[w];
         }
       }
-      // Per query: its 64-row words are ballots of its bit.
+      // Per word of 32 queries and row group: a bit transpose within each half-wave
+      // leaves in lane 32 h + c the 32 rows 64 g + 32 h + [0, 32) of query 32 w + c,
+      // that is one half of its 64-row output word.  Counts are lane popcounts; words
+      // are stored when not zero (the output was cleared before the scan).
       const uint64_t word0 = row0 / 64;
 #pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int w = 0; w < SW; ++w) acc[g][w] = half_transpose(acc[g][w], tc);
+#pragma unroll
       for (int w = 0; w < SW; ++w) {
-        const uint32_t q0 = 32 * w;
-        if (q0 >= nq) break;
-        const uint32_t q1 = nq - q0 < 32 ? nq - q0 : 32;
-#pragma unroll 1
-        for (uint32_t b = 0; b < q1; ++b) {
-          uint64_t m[RG];
-          uint32_t c = 0;
+        if (32 * w >= static_cast<int>(nq)) break;
+        uint32_t cnt = 0;
 #pragma unroll
-          for (int g = 0; g < RG; ++g) {
-            m[g] = ballot((acc[g][w] >> b) & 1u);
-            c += __popcll(m[g]);
-          }
-          if (c == 0) continue;
-          const uint32_t qi = q0 + b;
-          if (lane == 0) atomicAdd(&s_cnt[qi], c);
-          const uint32_t inf = __builtin_amdgcn_readfirstlane(info[qi]);
-          if ((inf & 0x3u) != kBatchCount) {
-            uint64_t* words = bp.words + static_cast<uint64_t>(inf >> 8) * bp.n_words + word0;
+        for (int g = 0; g < RG; ++g) cnt += __builtin_popcount(acc[g][w]);
+        if (cnt != 0) atomicAdd(&s_cnt[32 * w + (lane & 31)], cnt);
 #pragma unroll
-            for (int g = 0; g < RG; ++g)
-              if (m[g] != 0 && lane == 0) words[g] = m[g];
-          }
+        for (int g = 0; g < RG; ++g) {
+          const uint32_t st = acc[g][w] & keep[w];
+          if (st != 0) out[w][(word0 + g) * 2] = st;
         }
       }
     }
