@@ -431,10 +431,17 @@ __device__ __forceinline__ uint32_t half_transpose(uint32_t a, const HalfTranspo
 // every boundary (rank 0), where every predicate fails; a query without predicates
 // carries [key(-inf), key(+inf)] on slot 0.
 //
-// LDS layout of a group (words): per query, its kind and output row (kind | row << 8);
-// per slot, (offset of its boundaries, M); then per slot the M boundaries padded with
-// 0xFFFFFFFF to 2 top - 1 entries (top: the largest power of two <= M), followed, at a
-// 4-word aligned offset, by the table of (M + 1) x SW words.
+// The rank search is bucketed: the host splits the key range of a slot's boundaries
+// into nb buckets of 2^shift keys from the smallest boundary kmin (the last bucket
+// open above) and stores per bucket the number of boundaries in lower buckets; a row
+// then needs one bucket lookup and d binary-search steps, 2^d - 1 being at least the
+// fullest bucket's count.
+//
+// LDS layout of a group (words): per query, its kind and output row (kind | row << 8),
+// padded to 4 words; per slot a header (offset of its boundaries, M, kmin, shift |
+// d << 8 | (nb - 1) << 16); then per slot the nb 16-bit bucket starts, the M
+// boundaries padded with 2^d - 1 words 0xFFFFFFFF, and, at a 4-word aligned offset,
+// the table of (M + 1) x SW words.
 template <int W, int RG, int SW>
 __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
   static_assert(W * RG <= 64, "a tile must hold at least one chunk per wave");
@@ -450,8 +457,8 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
   for (uint32_t i = threadIdx.x; i < t_len; i += W * 64) s_tab[i] = bp.table[t_beg + i];
   for (uint32_t i = threadIdx.x; i < nq; i += W * 64) s_cnt[i] = 0;
   __syncthreads();
-  const uint32_t* info = s_tab;            // nq words
-  const uint32_t* hdr = s_tab + nq;        // 2 words per slot
+  const uint32_t* info = s_tab;                     // nq words
+  const uint32_t* hdr = s_tab + ((nq + 3) & ~3u);   // 4 words per slot
 
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
@@ -483,11 +490,15 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
         for (int w = 0; w < SW; ++w) acc[g][w] = ~0u;
 #pragma unroll 1
       for (uint32_t s = 0; s < ns; ++s) {
-        const uint32_t M = __builtin_amdgcn_readfirstlane(hdr[2 * s + 1]);   // uniform
+        const uint4 h = *reinterpret_cast<const uint4*>(hdr + 4 * s);
+        const uint32_t M = __builtin_amdgcn_readfirstlane(h.y);   // uniform
         if (M == 0) continue;  // no predicate of the group on this column
-        const uint32_t* B = s_tab + __builtin_amdgcn_readfirstlane(hdr[2 * s]);
-        const uint32_t top = 1u << (31 - __builtin_clz(M));   // largest power of 2 <= M
-        const uint32_t* T = B + ((2 * top - 1 + 3) & ~3u);    // ends padded to 2 top - 1
+        const uint32_t* B = s_tab + __builtin_amdgcn_readfirstlane(h.x);
+        const uint32_t kmin = __builtin_amdgcn_readfirstlane(h.z);
+        const uint32_t hw = __builtin_amdgcn_readfirstlane(h.w);
+        const uint32_t shift = hw & 31u, d = (hw >> 8) & 31u, nbm1 = hw >> 16;
+        const uint16_t* starts = reinterpret_cast<const uint16_t*>(B) - (nbm1 + 1);
+        const uint32_t* T = B + ((M + (1u << d) - 1 + 3) & ~3u);
         uint32_t x[RG];
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
@@ -497,15 +508,19 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
         }
 #pragma unroll
         for (int g = 0; g < RG; ++g) x[g] = (full || row0 + 64 * g + lane < bp.n_rows) ? bkey(x[g]) : 0u;
-        // rank = number of boundaries <= key: a branch-free binary search, the reads of
-        // all row groups of a step issued together.  The ends are padded with 0xFFFFFFFF
-        // up to 2 top - 1 entries, the farthest a search reaches, so a candidate past M
-        // is never taken by a key below 0xFFFFFFFF.
+        // rank = number of ends <= key: the ends in lower buckets, then a branch-free
+        // binary search of d steps within the key's bucket, the reads of all row groups
+        // of a step issued together.  The ends are padded with 0xFFFFFFFF so that a
+        // search window running past the last end reads only words above every key
+        // below 0xFFFFFFFF.
         uint32_t pos[RG];
 #pragma unroll
-        for (int g = 0; g < RG; ++g) pos[g] = 0;
+        for (int g = 0; g < RG; ++g) {
+          uint32_t b = (x[g] > kmin ? x[g] - kmin : 0u) >> shift;
+          pos[g] = starts[b < nbm1 ? b : nbm1];
+        }
 #pragma unroll 1
-        for (uint32_t step = top; step > 0; step >>= 1) {
+        for (uint32_t step = (1u << d) >> 1; step > 0; step >>= 1) {
           uint32_t v[RG];
 #pragma unroll
           for (int g = 0; g < RG; ++g) v[g] = B[pos[g] + step - 1];

@@ -20,6 +20,7 @@ namespace {
 constexpr uint64_t kTileRows = 4096;
 constexpr uint64_t kMaxLdsTable = 60 * 1024;   // bytes of query table per workgroup
 constexpr uint64_t kMaxRegGroup = 4096;         // queries per workgroup, slot-mask variant
+constexpr uint32_t kRankBuckets = 256;          // most buckets of a rank search
 
 template <typename T>
 int grow_device(T** p, uint64_t* have, uint64_t need, const char* what) {
@@ -85,6 +86,42 @@ uint64_t shape_key(uint64_t n_rows, size_t n_slots, size_t n_queries) {
 // Run one shared scan over `items` (union of at most kMaxUnion columns; unions of more
 // than kMaxSlots columns take the LDS variant).
 // ms_out receives the device time of the scan and finish launches.
+// Buckets of the rank search over sorted distinct interval ends: nb (a power of two,
+// at most kRankBuckets) buckets of 2^shift keys from the smallest end, the last
+// bucket open above; the starts count the ends in lower buckets, and d is the number
+// of binary-search steps that resolve the fullest bucket.  Of the bucket counts tried,
+// the one with the fewest steps wins, the smaller on a tie.
+struct RankBuckets {
+  uint32_t nb = 0, shift = 0, d = 0;
+  std::vector<uint16_t> starts;
+};
+
+RankBuckets rank_buckets(const std::vector<uint32_t>& ends) {
+  RankBuckets best;
+  const uint32_t kmin = ends.front(), span = ends.back() - kmin;
+  for (uint32_t nb = 8; nb <= kRankBuckets; nb *= 2) {
+    uint32_t shift = 0;
+    while ((span >> shift) > nb - 1) ++shift;
+    std::vector<uint16_t> starts(nb, 0);
+    std::vector<uint32_t> occ(nb, 0);
+    for (uint32_t e : ends) ++occ[std::min<uint32_t>((e - kmin) >> shift, nb - 1)];
+    uint32_t below = 0, fullest = 0;
+    for (uint32_t b = 0; b < nb; ++b) {
+      starts[b] = static_cast<uint16_t>(below);
+      below += occ[b];
+      fullest = std::max(fullest, occ[b]);
+    }
+    const uint32_t d = 32 - static_cast<uint32_t>(__builtin_clz(fullest));  // 2^d - 1 >= fullest
+    if (best.nb == 0 || d < best.d) {
+      best.nb = nb;
+      best.shift = shift;
+      best.d = d;
+      best.starts = std::move(starts);
+    }
+  }
+  return best;
+}
+
 int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
                const BatchConfig& cfg, hipStream_t stream, float* ms_out) {
   const uint64_t nq = items.size();
@@ -125,8 +162,8 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   const size_t lds_room = device().lds > 4096 ? device().lds - 4096 : 0;
   auto rank_words = [&](uint64_t S) {  // worst case: 2 S interval ends per slot (padded)
     const uint64_t sw = S <= 32 ? 1 : S <= 64 ? 2 : 4;
-    return S + 4 + 2 * static_cast<uint64_t>(n_slots) +
-           static_cast<uint64_t>(n_slots) * (4 * S + 8 + (2 * S + 1) * sw);
+    return S + 4 + 4 * static_cast<uint64_t>(n_slots) +
+           static_cast<uint64_t>(n_slots) * (kRankBuckets / 2 + 4 * S + 8 + (2 * S + 1) * sw);
   };
   uint64_t rank_group = std::min<uint64_t>(128, cfg.group ? cfg.group : nq);
   while (rank_group > 32 && (rank_words(rank_group) + 4) * 4 > lds_room) rank_group /= 2;
@@ -193,17 +230,21 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     }
     q0 = q1;
   }
-  // Rank variant: per group, per query (kind | output row << 8), per slot (offset, M),
-  // then per slot the M sorted interval ends and the (M + 1) x sw table of query
-  // bitsets by rank (offsets relative to the group's start, 4-word aligned).
+  // Rank variant: per group, per query (kind | output row << 8), per slot a header
+  // (offset of the ends, M, kmin, shift | d << 8 | (nb - 1) << 16), then per slot the
+  // bucket starts (nb 16-bit counts), the M sorted interval ends padded with 2^d - 1
+  // words 0xFFFFFFFF, and the (M + 1) x sw table of query bitsets by rank (offsets
+  // relative to the group's start, 4-word aligned).  A key x falls in bucket
+  // min((max(x, kmin) - kmin) >> shift, nb - 1); the bucket starts count the ends in
+  // lower buckets, and no bucket holds more than 2^d - 1 ends.
   for (uint64_t q0 = 0; rank && q0 < nq;) {
     const uint64_t q1 = std::min<uint64_t>(nq, q0 + rank_group);
     const uint32_t gq = static_cast<uint32_t>(q1 - q0);
     group_first.push_back(static_cast<uint32_t>(q0));
     const uint64_t base = table.size();
     group_table.push_back(static_cast<uint32_t>(base));
-    table.resize(base + gq + 2 * static_cast<uint64_t>(n_slots), 0u);
-    while ((table.size() - base) % 4) table.push_back(0u);
+    const uint32_t hq = (gq + 3) & ~3u;  // headers, 16-byte aligned
+    table.resize(base + hq + 4 * static_cast<uint64_t>(n_slots), 0u);
     for (uint64_t q = q0; q < q1; ++q)
       table[base + (q - q0)] = outs[q].kind | (outs[q].out_index << 8);
     // Per query and slot: (key(lo), key(hi)) of its predicate, if any.
@@ -239,15 +280,20 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       std::sort(ends.begin(), ends.end());
       ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
       const uint32_t M = static_cast<uint32_t>(ends.size());
-      while ((table.size() - base) % 4) table.push_back(0u);  // 16-byte aligned
-      const uint64_t off = table.size() - base;
-      table[base + gq + 2 * sl] = static_cast<uint32_t>(off);
-      table[base + gq + 2 * sl + 1] = M;
+      table[base + hq + 4 * sl + 1] = M;
       if (M == 0) continue;
+      const RankBuckets rb = rank_buckets(ends);
+      while ((table.size() - base) % 4) table.push_back(0u);  // 16-byte aligned
+      const uint64_t s0 = table.size();
+      table.resize(s0 + rb.nb / 2, 0u);
+      for (uint32_t b = 0; b < rb.nb; ++b)
+        table[s0 + b / 2] |= static_cast<uint32_t>(rb.starts[b]) << (16 * (b % 2));
+      table[base + hq + 4 * sl] = static_cast<uint32_t>(table.size() - base);
+      table[base + hq + 4 * sl + 2] = ends[0];
+      table[base + hq + 4 * sl + 3] = rb.shift | (rb.d << 8) | ((rb.nb - 1) << 16);
       table.insert(table.end(), ends.begin(), ends.end());
-      // Padding above every key, to the farthest entry a binary search reads.
-      const uint32_t top = 1u << (31 - __builtin_clz(M));
-      table.resize(table.size() + (2 * top - 1 - M), 0xFFFFFFFFu);
+      // Padding above every key, to the farthest entry a search within a bucket reads.
+      table.resize(table.size() + ((1u << rb.d) - 1), 0xFFFFFFFFu);
       while ((table.size() - base) % 4) table.push_back(0u);
       const uint64_t t0 = table.size();
       table.resize(t0 + static_cast<uint64_t>(M + 1) * rank_sw, 0u);
