@@ -55,7 +55,10 @@ class Runner:
                 arr[i] = qq
                 self.keep.append(k)
             self.q[flags] = arr
-        self.r = (mdrq.Result * self.n)()
+        # Result records as numpy fields, set and read per batch without a Python loop.
+        self.rrec = np.zeros(self.n, dtype=mdrq._RESULT_DT)
+        self.r = (mdrq.Result * self.n).from_buffer(self.rrec)
+        self.ptrs = np.array([out2d[s].data_ptr() for s in range(out2d.shape[0])], dtype=np.uint64)
         self.counts = np.zeros(self.n, dtype=np.int64)
 
     def _result(self, i, slot):
@@ -80,8 +83,11 @@ class Runner:
         hi = self.n if hi is None else hi
         for a in range(lo, hi, size):
             b = min(hi, a + size)
-            for i in range(a, b):
-                self._result(i, i - a)
+            rec = self.rrec[a:b]
+            rec["mode"] = self.mdrq.OUT_IDS
+            rec["mem"] = self.mdrq.MEM_DEVICE
+            rec["buf"] = self.ptrs[:b - a]
+            rec["buf_bytes"] = self.cap * 4
             qp = ctypes.cast(ctypes.byref(self.q[flags], a * ctypes.sizeof(self.mdrq.Query)),
                              ctypes.POINTER(self.mdrq.Query))
             rp = ctypes.cast(ctypes.byref(self.r, a * ctypes.sizeof(self.mdrq.Result)),
@@ -89,8 +95,7 @@ class Runner:
             rc = self.lib.mdrq_query_batch(self.ds.handle, qp, b - a, rp, self.stream)
             if rc not in (0, self.mdrq.EOVERFLOW):
                 raise self.mdrq.MdrqError(rc, self.mdrq.last_error())
-            for i in range(a, b):
-                self.counts[i] = self.r[i].count
+            self.counts[a:b] = rec["count"]
         return self.counts[lo:hi].copy()
 
 

@@ -189,6 +189,18 @@ def _stream_handle(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(int(stream) if stream else 0)
 
 
+# numpy views of the records above, for building whole batches without a Python loop
+# over predicates.
+_PRED_DT = np.dtype([("dim", "<u4"), ("lo", "<f4"), ("hi", "<f4")])
+_QUERY_DT = np.dtype([("preds", "<u8"), ("n_preds", "<u4"), ("flags", "<u4")])
+_RESULT_DT = np.dtype([("mode", "<u4"), ("mem", "<u4"), ("buf", "<u8"), ("buf_bytes", "<u8"),
+                       ("count", "<u8"), ("written", "<u8"), ("status", "<i4"),
+                       ("reserved", "<u4")])
+assert _PRED_DT.itemsize == ctypes.sizeof(Pred)
+assert _QUERY_DT.itemsize == ctypes.sizeof(Query)
+assert _RESULT_DT.itemsize == ctypes.sizeof(Result)
+
+
 def make_query(query, flags: int = 0):
     """(dims, lo, hi) arrays or [(dim, lo, hi), ...] -> (Query, keepalive)."""
     if isinstance(query, tuple) and len(query) == 3 and hasattr(query[0], "__len__") \
@@ -209,20 +221,24 @@ class Answer:
     mode: str
 
 
+def _out_spec(out):
+    """(memory kind, address, bytes) of an output buffer."""
+    if out is None:
+        return MEM_DEVICE, 0, 0
+    if isinstance(out, np.ndarray):
+        if not out.flags.c_contiguous:
+            raise ValueError("output array must be contiguous")
+        return MEM_HOST, out.ctypes.data, out.nbytes
+    if not out.is_contiguous():  # torch tensor
+        raise ValueError("output tensor must be contiguous")
+    return (MEM_DEVICE if out.is_cuda else MEM_HOST), out.data_ptr(), out.numel() * out.element_size()
+
+
 def _result_for(out, mode: str) -> Result:
     r = Result()
     r.mode = _MODES[mode]
-    if out is None:
-        r.mem, r.buf, r.buf_bytes = MEM_DEVICE, None, 0
-    elif isinstance(out, np.ndarray):
-        if not out.flags.c_contiguous:
-            raise ValueError("output array must be contiguous")
-        r.mem, r.buf, r.buf_bytes = MEM_HOST, out.ctypes.data, out.nbytes
-    else:  # torch tensor
-        if not out.is_contiguous():
-            raise ValueError("output tensor must be contiguous")
-        r.mem = MEM_DEVICE if out.is_cuda else MEM_HOST
-        r.buf, r.buf_bytes = out.data_ptr(), out.numel() * out.element_size()
+    r.mem, buf, r.buf_bytes = _out_spec(out)
+    r.buf = buf or None
     return r
 
 
@@ -313,13 +329,25 @@ class Dataset:
     def query_batch(self, queries, outs=None, modes="ids", flags: int = 0, stream=None):
         lib = load_library()
         n = len(queries)
-        outs = outs if outs is not None else [None] * n
-        modes = [modes] * n if isinstance(modes, str) else list(modes)
         qarr, keep = _query_array(queries, flags)
-        rarr = (Result * max(1, n))(*[_result_for(o, m) for o, m in zip(outs, modes)])
+        rec = np.zeros(max(1, n), dtype=_RESULT_DT)
+        if isinstance(modes, str):
+            rec["mode"][:n] = _MODES[modes]
+        else:
+            rec["mode"][:n] = [_MODES[m] for m in modes]
+        if outs is None:
+            rec["mem"][:n] = MEM_DEVICE
+        else:
+            spec = [_out_spec(o) for o in outs]
+            rec["mem"][:n] = [m for m, _, _ in spec]
+            rec["buf"][:n] = [a for _, a, _ in spec]
+            rec["buf_bytes"][:n] = [b for _, _, b in spec]
+        rarr = (Result * max(1, n)).from_buffer(rec)
         rc = lib.mdrq_query_batch(self._h, qarr, n, rarr, _stream_handle(stream))
         _check(rc, (OK, EOVERFLOW))
-        return [Answer(r.count, r.written, r.status, _MODE_NAMES[r.mode]) for r in rarr[:n]]
+        return [Answer(c, w, st, _MODE_NAMES[m]) for c, w, st, m in
+                zip(rec["count"][:n].tolist(), rec["written"][:n].tolist(),
+                    rec["status"][:n].tolist(), rec["mode"][:n].tolist())]
 
     def set_option(self, option: int, value: int):
         _check(load_library().mdrq_set_option(self._h, option, value))
@@ -391,14 +419,34 @@ class Dataset:
         _check(load_library().mdrq_attach_estimator(self._h, est.handle if est else None))
 
 
+def _query_parts(query):
+    """(dims, lo, hi) of a query given as three arrays or as [(dim, lo, hi), ...]."""
+    if isinstance(query, tuple) and len(query) == 3 and hasattr(query[0], "__len__") \
+            and not isinstance(query[0], tuple):
+        return query
+    q = list(query)
+    return [p[0] for p in q], [p[1] for p in q], [p[2] for p in q]
+
+
 def _query_array(queries, flags: int):
-    qarr = (Query * max(1, len(queries)))()
-    keep = []
-    for i, qq in enumerate(queries):
-        q, k = make_query(qq, flags)
-        qarr[i] = q
-        keep.append(k)
-    return qarr, keep
+    """ctypes array of mdrq_query over numpy records: all predicates in one array, each
+    query pointing at its run (NULL when it has none).  Returns (array, keepalive)."""
+    n = len(queries)
+    parts = [_query_parts(q) for q in queries]
+    counts = np.fromiter((len(p[0]) for p in parts), dtype=np.int64, count=n)
+    total = int(counts.sum())
+    preds = np.zeros(max(1, total), dtype=_PRED_DT)
+    if total:
+        preds["dim"][:total] = np.concatenate([p[0] for p in parts]).astype(np.int64).astype(np.uint32)
+        preds["lo"][:total] = np.concatenate([p[1] for p in parts]).astype(np.float32)
+        preds["hi"][:total] = np.concatenate([p[2] for p in parts]).astype(np.float32)
+    rec = np.zeros(max(1, n), dtype=_QUERY_DT)
+    if n:
+        offs = np.cumsum(counts) - counts
+        rec["preds"][:n] = np.where(counts > 0, preds.ctypes.data + offs * _PRED_DT.itemsize, 0)
+        rec["n_preds"][:n] = counts
+        rec["flags"][:n] = flags
+    return (Query * max(1, n)).from_buffer(rec), (preds, rec)
 
 
 def _fptr(a: np.ndarray):
