@@ -426,7 +426,8 @@ __device__ __forceinline__ uint32_t half_transpose(uint32_t a, const HalfTranspo
 // idx(key(hi) + 1); a query without a predicate on the column always passes.  Each
 // row then costs, per column, one binary search for its rank and an AND of SW table
 // words -- shared by all the group's queries -- and each 32 queries a bit transpose
-// per 64 rows.  Exact: the boundaries include every interval end, so each rank interval lies
+// per 64 rows.  Output words are stored with per-chunk marks (bp.flags), as in the
+// slot-mask variant, so the words need no clearing.  Exact: the boundaries include every interval end, so each rank interval lies
 // wholly inside or outside every predicate.  Rows past the end get the key 0, below
 // every boundary (rank 0), where every predicate fails; a query without predicates
 // carries [key(-inf), key(+inf)] on slot 0.
@@ -466,14 +467,14 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
   // Lane 32 h + c writes half h of query 32 w + c's words: its output row, and a mask
   // that drops the stores of count-only queries and of lanes past the group.
   uint32_t* out[SW];
-  uint32_t keep[SW];
+  uint32_t keep[SW], outi[SW];
 #pragma unroll
   for (int w = 0; w < SW; ++w) {
     const uint32_t qi = 32 * w + (lane & 31);
     const uint32_t inf = qi < nq ? info[qi] : kBatchCount;
     keep[w] = (inf & 0x3u) != kBatchCount ? ~0u : 0u;
-    out[w] = reinterpret_cast<uint32_t*>(bp.words + static_cast<uint64_t>(keep[w] ? inf >> 8 : 0) * bp.n_words) +
-             (lane >> 5);
+    outi[w] = keep[w] ? inf >> 8 : 0;
+    out[w] = reinterpret_cast<uint32_t*>(bp.words + static_cast<uint64_t>(outi[w]) * bp.n_words) + (lane >> 5);
   }
   constexpr uint32_t kChunkRows = 64 * RG;
   constexpr uint32_t kChunksPerWave = 4096 / kChunkRows / W;
@@ -549,15 +550,21 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
 #pragma unroll
       for (int w = 0; w < SW; ++w) {
         if (32 * w >= static_cast<int>(nq)) break;
-        uint32_t cnt = 0;
-#pragma unroll
-        for (int g = 0; g < RG; ++g) cnt += __builtin_popcount(acc[g][w]);
-        if (cnt != 0) atomicAdd(&s_cnt[32 * w + (lane & 31)], cnt);
+        uint32_t cnt = 0, nz = 0;   // nz bit g: word g of the query is not zero
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
-          const uint32_t st = acc[g][w] & keep[w];
-          if (st != 0) out[w][(word0 + g) * 2] = st;
+          cnt += __builtin_popcount(acc[g][w]);
+          nz |= (acc[g][w] != 0 ? 1u : 0u) << g;
         }
+        nz = (nz | __shfl_xor(nz, 32)) & keep[w];   // lanes c and 32 + c: the two halves
+        if (cnt != 0) atomicAdd(&s_cnt[32 * w + (lane & 31)], cnt);
+        // Both halves of every non-zero word, and the chunk's mark (bit g <=> word g
+        // was stored): the words themselves are not cleared before the scan.
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+          if ((nz >> g) & 1u) out[w][(word0 + g) * 2] = acc[g][w];
+        if (nz != 0 && lane < 32)
+          bp.flags[static_cast<uint64_t>(outi[w]) * bp.n_chunks + row0 / kChunkRows] = static_cast<uint16_t>(nz);
       }
     }
     __syncthreads();

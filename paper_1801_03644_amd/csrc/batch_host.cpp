@@ -474,7 +474,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     rg = batch_rows_per_lane(std::max(1, n_slots), waves, cfg.rows_per_lane);
     lds = max_group_words * 4;
   }
-  if (reg && n_out && batch_reg_uses_marks(static_cast<int>(reg_slots))) {  // marks, not zeroing
+  if (n_out && (rank || (reg && batch_reg_uses_marks(static_cast<int>(reg_slots))))) {  // marks, not zeroing
     const uint64_t chunk_rows = 64 * static_cast<uint64_t>(rg);
     const uint64_t n_chunks = (n_rows + chunk_rows - 1) / chunk_rows;
     rc = grow_device(&ws.d_flags, &ws.d_flags_len, (n_chunks * n_out + 3) / 4 + 1, "batch chunk marks");
@@ -881,7 +881,8 @@ int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queri
   const uint64_t nq = max_queries;
   int rc = grow_device(&ws.d_words, &ws.d_words_len, std::max<uint64_t>(1, max_rows) * nw + 1, "batch bitmaps");
   if (rc) return rc;
-  // Chunk marks of the slot-mask variant, for its smallest chunk (4 row groups of 64).
+  // Chunk marks of the slot-mask and rank variants, for the smallest chunk (4 row groups
+  // of 64).
   rc = grow_device(&ws.d_flags, &ws.d_flags_len,
                    ((ds->n_rows + 255) / 256 * std::max<uint64_t>(1, max_rows) + 3) / 4 + 1,
                    "batch chunk marks");

@@ -112,10 +112,10 @@ struct BatchParams {
   uint64_t n_out;               // rows of the scratch in use
   uint32_t* tile_counts;        // [query][tile]
   // Null: the scratch rows are zeroed before the scan, which stores the non-zero words.
-  // Otherwise (slot-mask variant) one 16-bit mark per (output row, chunk of at most
-  // 16 words) is zeroed instead; the scan stores the
-  // non-zero words of a chunk and sets bit g of its mark for each stored word g, and the
-  // finish takes unmarked words as zero.
+  // Otherwise (slot-mask variant with at most 8 register slots, rank variant) one
+  // 16-bit mark per (output row, chunk of at most 16 words) is zeroed instead; the scan
+  // stores the non-zero words of a chunk and sets bit g of its mark for each stored
+  // word g, and the finish takes unmarked words as zero.
   uint16_t* flags;
   uint64_t n_chunks;            // chunks per output row
   const float* slot_cols[kMaxUnion];
@@ -351,7 +351,7 @@ struct BatchWorkspace {
   uint64_t h_blob_bytes = 0;
   uint64_t* d_words = nullptr;   // bitmap scratch
   uint64_t d_words_len = 0;
-  uint64_t* d_flags = nullptr;   // chunk marks of the slot-mask variant (as 64-bit words)
+  uint64_t* d_flags = nullptr;   // chunk marks of the slot-mask and rank variants (as 64-bit words)
   uint64_t d_flags_len = 0;
   uint32_t* d_tile_counts = nullptr;
   uint64_t d_tile_counts_len = 0;
