@@ -432,17 +432,18 @@ __device__ __forceinline__ uint32_t half_transpose(uint32_t a, const HalfTranspo
 // every boundary (rank 0), where every predicate fails; a query without predicates
 // carries [key(-inf), key(+inf)] on slot 0.
 //
-// The rank search is bucketed: the host splits the key range of a slot's boundaries
-// into nb buckets of 2^shift keys from the smallest boundary kmin (the last bucket
-// open above) and stores per bucket the number of boundaries in lower buckets; a row
-// then needs one bucket lookup and d binary-search steps, 2^d - 1 being at least the
-// fullest bucket's count.
+// The rank search is bucketed: the host maps a slot's keys monotonically to nb
+// buckets, either by key (2^shift keys per bucket from the smallest boundary kmin) or
+// by value (float (v - vlo) * scale, truncated), whichever leaves the fewest
+// boundaries in the fullest bucket, and stores per bucket the number of boundaries in
+// lower buckets; a row then needs one bucket lookup and d binary-search steps, 2^d - 1
+// being at least the fullest bucket's count.
 //
 // LDS layout of a group (words): per query, its kind and output row (kind | row << 8),
-// padded to 4 words; per slot a header (offset of its boundaries, M, kmin, shift |
-// d << 8 | (nb - 1) << 16); then per slot the nb 16-bit bucket starts, the M
-// boundaries padded with 2^d - 1 words 0xFFFFFFFF, and, at a 4-word aligned offset,
-// the table of (M + 1) x SW words.
+// padded to 4 words; per slot a header (offset of its boundaries; M | d << 12 |
+// (nb - 1) << 16 | shift << 24 | by value << 31; kmin or vlo; scale); then per slot the
+// nb 16-bit bucket starts, the M boundaries padded with 2^d - 1 words 0xFFFFFFFF, and,
+// at a 4-word aligned offset, the table of (M + 1) x SW words.
 template <int W, int RG, int SW>
 __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
   static_assert(W * RG <= 64, "a tile must hold at least one chunk per wave");
@@ -492,12 +493,14 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
 #pragma unroll 1
       for (uint32_t s = 0; s < ns; ++s) {
         const uint4 h = *reinterpret_cast<const uint4*>(hdr + 4 * s);
-        const uint32_t M = __builtin_amdgcn_readfirstlane(h.y);   // uniform
-        if (M == 0) continue;  // no predicate of the group on this column
+        const uint32_t hw = __builtin_amdgcn_readfirstlane(h.y);   // uniform
+        if (hw == 0) continue;  // no predicate of the group on this column
+        const uint32_t M = hw & 0xFFFu, d = (hw >> 12) & 15u, nbm1 = (hw >> 16) & 0xFFu;
+        const uint32_t shift = (hw >> 24) & 31u;
+        const bool by_value = hw >> 31;
         const uint32_t* B = s_tab + __builtin_amdgcn_readfirstlane(h.x);
-        const uint32_t kmin = __builtin_amdgcn_readfirstlane(h.z);
-        const uint32_t hw = __builtin_amdgcn_readfirstlane(h.w);
-        const uint32_t shift = hw & 31u, d = (hw >> 8) & 31u, nbm1 = hw >> 16;
+        const uint32_t base = __builtin_amdgcn_readfirstlane(h.z);   // kmin, or vlo's bits
+        const float scale = __uint_as_float(__builtin_amdgcn_readfirstlane(h.w));
         const uint16_t* starts = reinterpret_cast<const uint16_t*>(B) - (nbm1 + 1);
         const uint32_t* T = B + ((M + (1u << d) - 1 + 3) & ~3u);
         uint32_t x[RG];
@@ -507,19 +510,39 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
           const uint64_t rc = r < bp.n_rows ? r : bp.n_rows - 1;
           x[g] = __float_as_uint(__builtin_nontemporal_load(&bp.slot_cols[s][rc]));
         }
+        // Bucket of each row: by key, min((max(key, kmin) - kmin) >> shift, nb - 1), or
+        // by value, trunc(clamp((v - vlo) * scale, 0, nb - 1)) in the host's float
+        // arithmetic; rows past the end take key 0 and bucket 0 (rank 0).
+        uint32_t bk[RG];
+        if (by_value) {
+          const float vlo = __uint_as_float(base), top = static_cast<float>(nbm1);
 #pragma unroll
-        for (int g = 0; g < RG; ++g) x[g] = (full || row0 + 64 * g + lane < bp.n_rows) ? bkey(x[g]) : 0u;
+          for (int g = 0; g < RG; ++g) {
+            const float t = (__uint_as_float(x[g]) - vlo) * scale;
+            bk[g] = static_cast<uint32_t>(fminf(fmaxf(t, 0.0f), top));
+          }
+#pragma unroll
+          for (int g = 0; g < RG; ++g) {
+            const bool in = full || row0 + 64 * g + lane < bp.n_rows;
+            x[g] = in ? bkey(x[g]) : 0u;
+            bk[g] = in ? bk[g] : 0u;
+          }
+        } else {
+#pragma unroll
+          for (int g = 0; g < RG; ++g) {
+            x[g] = (full || row0 + 64 * g + lane < bp.n_rows) ? bkey(x[g]) : 0u;
+            const uint32_t b = (x[g] > base ? x[g] - base : 0u) >> shift;
+            bk[g] = b < nbm1 ? b : nbm1;
+          }
+        }
         // rank = number of ends <= key: the ends in lower buckets, then a branch-free
-        // binary search of d steps within the key's bucket, the reads of all row groups
+        // binary search of d steps within the row's bucket, the reads of all row groups
         // of a step issued together.  The ends are padded with 0xFFFFFFFF so that a
         // search window running past the last end reads only words above every key
         // below 0xFFFFFFFF.
         uint32_t pos[RG];
 #pragma unroll
-        for (int g = 0; g < RG; ++g) {
-          uint32_t b = (x[g] > kmin ? x[g] - kmin : 0u) >> shift;
-          pos[g] = starts[b < nbm1 ? b : nbm1];
-        }
+        for (int g = 0; g < RG; ++g) pos[g] = starts[bk[g]];
 #pragma unroll 1
         for (uint32_t step = (1u << d) >> 1; step > 0; step >>= 1) {
           uint32_t v[RG];

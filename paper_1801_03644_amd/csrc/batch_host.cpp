@@ -83,28 +83,43 @@ uint64_t shape_key(uint64_t n_rows, size_t n_slots, size_t n_queries) {
   return (lr << 16) | (static_cast<uint64_t>(n_slots) << 8) | lq;
 }
 
-// Run one shared scan over `items` (union of at most kMaxUnion columns; unions of more
-// than kMaxSlots columns take the LDS variant).
-// ms_out receives the device time of the scan and finish launches.
-// Buckets of the rank search over sorted distinct interval ends: nb (a power of two,
-// at most kRankBuckets) buckets of 2^shift keys from the smallest end, the last
-// bucket open above; the starts count the ends in lower buckets, and d is the number
-// of binary-search steps that resolve the fullest bucket.  Of the bucket counts tried,
-// the one with the fewest steps wins, the smaller on a tie.
+// Buckets of the rank search over sorted distinct interval ends, either by key (nb
+// buckets of 2^shift keys from the smallest end, the last open above) or by value
+// (bucket min(trunc(clamp((v - vlo) * scale, 0, nb - 1))) of a float v, in float
+// arithmetic that the kernel repeats exactly; an end above key(+inf) goes to the last
+// bucket).  Both maps are monotone in the key order, so an end in a lower bucket is
+// below every key of a higher one.  The starts count the ends in lower buckets, and d
+// is the number of binary-search steps that resolve the fullest bucket.  Of the maps
+// and bucket counts (powers of two up to kRankBuckets) tried, the one with the fewest
+// steps wins, key before value and the fewer buckets on a tie.
 struct RankBuckets {
   uint32_t nb = 0, shift = 0, d = 0;
+  bool by_value = false;
+  float vlo = 0.0f, scale = 1.0f;
   std::vector<uint16_t> starts;
 };
 
+float key_value(uint32_t k) {  // the float of an order-preserving key (NaN above +inf)
+  const uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  float v;
+  std::memcpy(&v, &b, sizeof v);
+  return v;
+}
+
+uint32_t value_bucket(float v, float vlo, float scale, uint32_t nbm1) {
+  if (std::isnan(v)) return nbm1;
+  float t = (v - vlo) * scale;
+  t = std::fmin(std::fmax(t, 0.0f), static_cast<float>(nbm1));
+  return static_cast<uint32_t>(t);
+}
+
 RankBuckets rank_buckets(const std::vector<uint32_t>& ends) {
   RankBuckets best;
-  const uint32_t kmin = ends.front(), span = ends.back() - kmin;
-  for (uint32_t nb = 8; nb <= kRankBuckets; nb *= 2) {
-    uint32_t shift = 0;
-    while ((span >> shift) > nb - 1) ++shift;
+  auto consider = [&](uint32_t nb, bool by_value, uint32_t shift, float vlo, float scale,
+                      const std::vector<uint32_t>& bucket_of) {
     std::vector<uint16_t> starts(nb, 0);
     std::vector<uint32_t> occ(nb, 0);
-    for (uint32_t e : ends) ++occ[std::min<uint32_t>((e - kmin) >> shift, nb - 1)];
+    for (uint32_t b : bucket_of) ++occ[b];
     uint32_t below = 0, fullest = 0;
     for (uint32_t b = 0; b < nb; ++b) {
       starts[b] = static_cast<uint16_t>(below);
@@ -116,12 +131,41 @@ RankBuckets rank_buckets(const std::vector<uint32_t>& ends) {
       best.nb = nb;
       best.shift = shift;
       best.d = d;
+      best.by_value = by_value;
+      best.vlo = vlo;
+      best.scale = scale;
       best.starts = std::move(starts);
+    }
+  };
+  const uint32_t kmin = ends.front(), span = ends.back() - kmin;
+  std::vector<uint32_t> bucket_of(ends.size());
+  for (uint32_t nb = 8; nb <= kRankBuckets; nb *= 2) {
+    uint32_t shift = 0;
+    while ((span >> shift) > nb - 1) ++shift;
+    for (size_t i = 0; i < ends.size(); ++i) bucket_of[i] = std::min<uint32_t>((ends[i] - kmin) >> shift, nb - 1);
+    consider(nb, false, shift, 0.0f, 1.0f, bucket_of);
+  }
+  float vlo = std::numeric_limits<float>::infinity(), vhi = -vlo;
+  for (uint32_t e : ends) {
+    const float v = key_value(e);
+    if (std::isfinite(v)) {
+      vlo = std::min(vlo, v);
+      vhi = std::max(vhi, v);
+    }
+  }
+  if (vlo < vhi && std::isfinite(vhi - vlo)) {
+    for (uint32_t nb = 8; nb <= kRankBuckets; nb *= 2) {
+      const float scale = static_cast<float>(nb) / (vhi - vlo);
+      for (size_t i = 0; i < ends.size(); ++i) bucket_of[i] = value_bucket(key_value(ends[i]), vlo, scale, nb - 1);
+      consider(nb, true, 0, vlo, scale, bucket_of);
     }
   }
   return best;
 }
 
+// Run one shared scan over `items` (union of at most kMaxUnion columns; unions of more
+// than kMaxSlots columns take the LDS variant).
+// ms_out receives the device time of the scan and finish launches.
 int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
                const BatchConfig& cfg, hipStream_t stream, float* ms_out) {
   const uint64_t nq = items.size();
@@ -231,12 +275,13 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     q0 = q1;
   }
   // Rank variant: per group, per query (kind | output row << 8), per slot a header
-  // (offset of the ends, M, kmin, shift | d << 8 | (nb - 1) << 16), then per slot the
+  // (offset of the ends; M | d << 12 | (nb - 1) << 16 | shift << 24 | by value << 31;
+  // kmin or vlo; scale), then per slot the
   // bucket starts (nb 16-bit counts), the M sorted interval ends padded with 2^d - 1
   // words 0xFFFFFFFF, and the (M + 1) x sw table of query bitsets by rank (offsets
-  // relative to the group's start, 4-word aligned).  A key x falls in bucket
-  // min((max(x, kmin) - kmin) >> shift, nb - 1); the bucket starts count the ends in
-  // lower buckets, and no bucket holds more than 2^d - 1 ends.
+  // relative to the group's start, 4-word aligned).  The bucket starts count the ends
+  // in lower buckets, and no bucket holds more than 2^d - 1 ends (M <= 2 x 128 fits
+  // the header's 12 bits).
   for (uint64_t q0 = 0; rank && q0 < nq;) {
     const uint64_t q1 = std::min<uint64_t>(nq, q0 + rank_group);
     const uint32_t gq = static_cast<uint32_t>(q1 - q0);
@@ -280,17 +325,21 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       std::sort(ends.begin(), ends.end());
       ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
       const uint32_t M = static_cast<uint32_t>(ends.size());
-      table[base + hq + 4 * sl + 1] = M;
-      if (M == 0) continue;
+      if (M == 0) continue;  // header all zero
       const RankBuckets rb = rank_buckets(ends);
       while ((table.size() - base) % 4) table.push_back(0u);  // 16-byte aligned
       const uint64_t s0 = table.size();
       table.resize(s0 + rb.nb / 2, 0u);
       for (uint32_t b = 0; b < rb.nb; ++b)
         table[s0 + b / 2] |= static_cast<uint32_t>(rb.starts[b]) << (16 * (b % 2));
+      uint32_t vlo_bits, scale_bits;
+      std::memcpy(&vlo_bits, &rb.vlo, 4);
+      std::memcpy(&scale_bits, &rb.scale, 4);
       table[base + hq + 4 * sl] = static_cast<uint32_t>(table.size() - base);
-      table[base + hq + 4 * sl + 2] = ends[0];
-      table[base + hq + 4 * sl + 3] = rb.shift | (rb.d << 8) | ((rb.nb - 1) << 16);
+      table[base + hq + 4 * sl + 1] = M | (rb.d << 12) | ((rb.nb - 1) << 16) | (rb.shift << 24) |
+                                      (rb.by_value ? 0x80000000u : 0u);
+      table[base + hq + 4 * sl + 2] = rb.by_value ? vlo_bits : ends[0];
+      table[base + hq + 4 * sl + 3] = rb.by_value ? scale_bits : 0u;
       table.insert(table.end(), ends.begin(), ends.end());
       // Padding above every key, to the farthest entry a search within a bucket reads.
       table.resize(table.size() + ((1u << rb.d) - 1), 0xFFFFFFFFu);
