@@ -886,6 +886,7 @@ __global__ void __launch_bounds__(kFinThreads) batch_count_kernel(BatchFinish f)
 // hit (one wave per tile) at the tile's first output position, so the identifiers come
 // out ascending.  Nothing beyond the caller's capacity is written.
 constexpr uint32_t kEmitTiles = 128;
+constexpr uint32_t kEmitStage = 2048;   // ids per wave staged in LDS (tiles of up to 4096)
 
 // Word w of query q's scratch row: zero unless the scan marked it as stored.  The word
 // and its mark are loaded independently (both in bounds), then combined.
@@ -921,6 +922,7 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
   }
   // The tiles' output positions (and the end of the last) into LDS in one pass.
   __shared__ uint32_t s_pos[kEmitTiles + 1];
+  __shared__ uint16_t s_stage[kFinWaves][kEmitStage];
   const uint32_t* offs = f.tile_counts + static_cast<uint64_t>(q) * f.n_tiles;
   for (uint64_t i = tid; i <= t_end - t_beg; i += kFinThreads) {
     const uint64_t t = t_beg + i;
@@ -955,14 +957,47 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
       const uint32_t x = __shfl_up(incl, d);
       if (lane >= static_cast<uint32_t>(d)) incl += x;
     }
-    uint64_t r = beg + incl - k;
+    const uint32_t total = __shfl(incl, 63);   // ids of the tile
     uint64_t bits = word;
     const uint32_t row = static_cast<uint32_t>(w * 64);
-    while (bits) {
-      const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(bits));
-      if (r < capacity) ids[r] = row + b;
-      ++r;
-      bits &= bits - 1;
+    if (total <= kEmitStage) {
+      // Each lane's rows (16-bit offsets in the tile) into the wave's LDS buffer at
+      // their places in the tile's output, then out to HBM in consecutive 64-lane runs.
+      uint16_t* buf = s_stage[wave];
+      uint32_t r = incl - k;
+      const uint32_t off = lane * 64;
+      while (bits) {
+        buf[r++] = static_cast<uint16_t>(off + static_cast<uint32_t>(__builtin_ctzll(bits)));
+        bits &= bits - 1;
+      }
+      const uint32_t tile_row = static_cast<uint32_t>(t * 4096);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (uint32_t i0 = 0; i0 < total; i0 += 256) {   // four runs' reads in flight
+        uint32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t i = i0 + 64 * j + lane;
+          v[j] = i < total ? tile_row + buf[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t i = i0 + 64 * j + lane;
+          if (i < total && beg + i < capacity) ids[beg + i] = v[j];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {  // a dense tile: each lane writes its ids directly
+      uint64_t r = beg + incl - k;
+      while (bits) {
+        const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(bits));
+        if (r < capacity) ids[r] = row + b;
+        ++r;
+        bits &= bits - 1;
+      }
     }
   }
 }
