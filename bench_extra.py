@@ -176,6 +176,10 @@ def batched(args):
             raise RuntimeError("batched ids differ from single-query ids")
     big = res[1024]
     ach = COMPARES_PER_TEST * big["row_tests_per_s"]
+    # HBM view of the same batch: every column of the union read once, ids written.
+    union = len({int(d) for q in queries for d in q[0]})
+    hbm_bytes = 4.0 * w.n_rows * union + 4.0 * float(np.minimum(run.counts, cap).sum())
+    hbm_ach = hbm_bytes / (big["device_ms_per_batch"] / 1e3) / 1e9
     line = _line(big["batched_queries_per_s"], "queries/s",
                  {"workload": f"c3: {w.n_rows} rows x {w.n_dims} float32 columns, batches of "
                               f"64/256/1024 queries (k 1..8, s 1e-5..0.2), ids output",
@@ -190,7 +194,15 @@ def batched(args):
                                "note": "work = 2 compares (lo <= x, x <= hi) per row-predicate "
                                        "test, tests = sum over queries of (queried dims x rows), "
                                        "the work without early-out; peak = one 32-bit compare "
-                                       "per lane and clock (256 CUs x 64 lanes x 2.4 GHz)"}})
+                                       "per lane and clock (256 CUs x 64 lanes x 2.4 GHz). This "
+                                       "is the roof of the variants that test every (row, "
+                                       "predicate); the rank variant looks each row up once per "
+                                       "group of up to 128 queries and column, so its frac can "
+                                       "exceed 1"},
+                  "roofline_hbm": {"bound": "hbm", "achieved": hbm_ach, "peak": 8000.0,
+                                   "unit": "GB/s", "frac": hbm_ach / 8000.0, "traffic": None,
+                                   "note": "bytes = 4 N x union columns (each read once) + 4 x "
+                                           "ids written, over the device time of the batch"}})
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         line["cpu_baseline"] = _cpu(raw, queries, w.n_rows, args.cpu_budget)
