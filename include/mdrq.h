@@ -275,7 +275,7 @@ enum {
   MDRQ_OPT_BATCH_ROWS = 7,    /* shared scans: 64-row groups each lane holds per chunk,
                                  1, 2, 4, 8 or 16 (tile height 64 x value rows per wave);
                                  0 = autotune */
-  MDRQ_OPT_BATCH_VARIANT = 8  /* shared scans: 1 = the union's keys in registers (unions
+  MDRQ_OPT_BATCH_VARIANT = 8, /* shared scans: 1 = the union's keys in registers (unions
                                  of up to 16 columns; wider ones use LDS), 2 = keys
                                  staged in LDS (any union, up to MDRQ_MAX_DIMS columns),
                                  3 = keys in registers with each query's predicates
@@ -284,6 +284,11 @@ enum {
                                  every slot), 5 = per group of up to 128 queries, each
                                  row's rank among the group's interval ends and per-rank
                                  query bitsets; 0 = autotune (default) */
+  MDRQ_OPT_RANK_BUCKETS = 9   /* rank variant: how a column's keys map to the search's
+                                 buckets: 0 = per column the map that leaves the fewest
+                                 ends in the fullest bucket (default), 1 = by key,
+                                 2 = by float value (by key where the ends' finite values
+                                 do not span a finite range); results never depend on it */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
 

@@ -113,7 +113,8 @@ uint32_t value_bucket(float v, float vlo, float scale, uint32_t nbm1) {
   return static_cast<uint32_t>(t);
 }
 
-RankBuckets rank_buckets(const std::vector<uint32_t>& ends) {
+// mode: 0 either map, 1 by key only, 2 by value only (by key where that is impossible).
+RankBuckets rank_buckets(const std::vector<uint32_t>& ends, int mode) {
   RankBuckets best;
   auto consider = [&](uint32_t nb, bool by_value, uint32_t shift, float vlo, float scale,
                       const std::vector<uint32_t>& bucket_of) {
@@ -139,7 +140,7 @@ RankBuckets rank_buckets(const std::vector<uint32_t>& ends) {
   };
   const uint32_t kmin = ends.front(), span = ends.back() - kmin;
   std::vector<uint32_t> bucket_of(ends.size());
-  for (uint32_t nb = 8; nb <= kRankBuckets; nb *= 2) {
+  for (uint32_t nb = 8; mode != 2 && nb <= kRankBuckets; nb *= 2) {
     uint32_t shift = 0;
     while ((span >> shift) > nb - 1) ++shift;
     for (size_t i = 0; i < ends.size(); ++i) bucket_of[i] = std::min<uint32_t>((ends[i] - kmin) >> shift, nb - 1);
@@ -153,13 +154,14 @@ RankBuckets rank_buckets(const std::vector<uint32_t>& ends) {
       vhi = std::max(vhi, v);
     }
   }
-  if (vlo < vhi && std::isfinite(vhi - vlo)) {
+  if (mode != 1 && vlo < vhi && std::isfinite(vhi - vlo)) {
     for (uint32_t nb = 8; nb <= kRankBuckets; nb *= 2) {
       const float scale = static_cast<float>(nb) / (vhi - vlo);
       for (size_t i = 0; i < ends.size(); ++i) bucket_of[i] = value_bucket(key_value(ends[i]), vlo, scale, nb - 1);
       consider(nb, true, 0, vlo, scale, bucket_of);
     }
   }
+  if (best.nb == 0) return rank_buckets(ends, 1);  // by value was asked for and impossible
   return best;
 }
 
@@ -326,7 +328,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
       const uint32_t M = static_cast<uint32_t>(ends.size());
       if (M == 0) continue;  // header all zero
-      const RankBuckets rb = rank_buckets(ends);
+      const RankBuckets rb = rank_buckets(ends, ds->rank_buckets);
       while ((table.size() - base) % 4) table.push_back(0u);  // 16-byte aligned
       const uint64_t s0 = table.size();
       table.resize(s0 + rb.nb / 2, 0u);

@@ -419,6 +419,8 @@ struct mdrq_dataset {
                                          // slot-order walk, 4: registers and slot-mask
                                          // records, 5: ranks and query bitsets;
                                          // 0: autotuned
+  int rank_buckets = 0;                  // rank variant's bucket map: 0 fewest steps,
+                                         // 1 by key, 2 by value
   bool autotune = true;
   std::vector<std::pair<uint64_t, mdrq::BatchConfig>> tuned;  // shape key -> config
   uint64_t batch_launches = 0;

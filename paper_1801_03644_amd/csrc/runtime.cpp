@@ -499,6 +499,10 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
       if (value < 0 || value > 5) return fail(MDRQ_EINVAL, "batch variant must be 0 .. 5");
       ds->batch_variant = static_cast<int>(value);
       return MDRQ_OK;
+    case MDRQ_OPT_RANK_BUCKETS:
+      if (value < 0 || value > 2) return fail(MDRQ_EINVAL, "rank buckets must be 0, 1 or 2");
+      ds->rank_buckets = static_cast<int>(value);
+      return MDRQ_OK;
     case MDRQ_OPT_AUTOTUNE:
       ds->autotune = value != 0;
       if (!ds->autotune) ds->tuned.clear();

@@ -39,6 +39,7 @@ EST_FEATS = EST_BINS + 3  # per dimension: H(lo), H(hi), histogram estimate, bin
 OPT_UNROLL, OPT_GRID, OPT_BLOCKS_PER_CU = 1, 2, 3
 OPT_BATCH_WAVES, OPT_BATCH_GROUP, OPT_AUTOTUNE, OPT_BATCH_ROWS = 4, 5, 6, 7
 OPT_BATCH_VARIANT = 8
+OPT_RANK_BUCKETS = 9
 
 
 class MdrqError(RuntimeError):

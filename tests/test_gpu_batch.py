@@ -116,6 +116,11 @@ def test_batch_sizes_and_ragged_tails(n):
             for Q in (1, 7, 16):
                 modes = (["ids", "bitmap", "count", "auto"] * 4)[:Q]
                 check_batch(ds, cols, qs[:Q], modes, f"n={n} Q={Q} variant={variant}")
+        for buckets in (1, 2):      # rank variant, each bucket map forced
+            ds.set_option(mdrq.OPT_RANK_BUCKETS, buckets)
+            modes = ["ids", "bitmap", "count", "auto"] * 4
+            check_batch(ds, cols, qs, modes, f"n={n} rank buckets={buckets}")
+        ds.set_option(mdrq.OPT_RANK_BUCKETS, 0)
 
 
 def test_batch_special_values_degenerate_and_invalid():
@@ -142,6 +147,14 @@ def test_batch_special_values_degenerate_and_invalid():
         for variant in (5, 4, 3, 2, 1, 0):
             ds.set_option(mdrq.OPT_BATCH_VARIANT, variant)
             check_batch(ds, cols, qs, modes, f"special variant={variant}")
+        ds.set_option(mdrq.OPT_BATCH_VARIANT, 5)
+        for buckets in (1, 2):   # the rank search's buckets by key, then by float value
+            ds.set_option(mdrq.OPT_RANK_BUCKETS, buckets)
+            check_batch(ds, cols, qs, modes, f"special rank buckets={buckets}")
+        ds.set_option(mdrq.OPT_RANK_BUCKETS, 0)
+        with pytest.raises(mdrq.MdrqError) as e:
+            ds.set_option(mdrq.OPT_RANK_BUCKETS, 3)
+        assert e.value.code == mdrq.EINVAL
         with pytest.raises(mdrq.MdrqError) as e:
             ds.query_batch([qs[3], dg.make_query([(1, np.nan, 1.0)])], None, "count")
         assert e.value.code == mdrq.EINVAL
