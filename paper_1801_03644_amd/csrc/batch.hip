@@ -888,6 +888,19 @@ __global__ void __launch_bounds__(kFinThreads) batch_count_kernel(BatchFinish f)
 constexpr uint32_t kEmitTiles = 128;
 constexpr uint32_t kEmitStage = 2048;   // ids per wave staged in LDS (tiles of up to 4096)
 
+// Inclusive prefix sum over the wave's lanes by DPP: shifts by 1, 2, 4, 8 within each
+// row of 16 lanes, then row 0's and row 2's last lane added to rows 1 and 3, then lane
+// 31 to rows 2 and 3 (lanes with no source add 0).
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xA, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xC, 0xF, false));
+  return v;
+}
+
 // Word w of query q's scratch row: zero unless the scan marked it as stored.  The word
 // and its mark are loaded independently (both in bounds), then combined.
 __device__ __forceinline__ uint64_t scratch_word(const BatchFinish& f, const uint64_t* words,
@@ -951,13 +964,8 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
     const uint64_t beg = s_pos[t - t_beg];
     const uint64_t w = t * 64 + lane;
     const uint32_t k = __popcll(word);
-    uint32_t incl = k;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t x = __shfl_up(incl, d);
-      if (lane >= static_cast<uint32_t>(d)) incl += x;
-    }
-    const uint32_t total = __shfl(incl, 63);   // ids of the tile
+    const uint32_t incl = wave_incl_sum(k);
+    const uint32_t total = __builtin_amdgcn_readlane(incl, 63);   // ids of the tile
     uint64_t bits = word;
     const uint32_t row = static_cast<uint32_t>(w * 64);
     if (total <= kEmitStage) {
