@@ -441,7 +441,7 @@ __device__ __forceinline__ uint32_t half_transpose(uint32_t a, const HalfTranspo
 //
 // LDS layout of a group (words): per query, its kind and output row (kind | row << 8),
 // padded to 4 words; per slot a header (offset of its boundaries; M | d << 12 |
-// (nb - 1) << 16 | shift << 24 | by value << 31; kmin or vlo; scale); then per slot the
+// log2(nb) << 16 | shift << 24 | by value << 31; kmin or vlo; scale); then per slot the
 // nb 16-bit bucket starts, the M boundaries padded with 2^d - 1 words 0xFFFFFFFF, and,
 // at a 4-word aligned offset, the table of (M + 1) x SW words.
 template <int W, int RG, int SW>
@@ -495,7 +495,7 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
         const uint4 h = *reinterpret_cast<const uint4*>(hdr + 4 * s);
         const uint32_t hw = __builtin_amdgcn_readfirstlane(h.y);   // uniform
         if (hw == 0) continue;  // no predicate of the group on this column
-        const uint32_t M = hw & 0xFFFu, d = (hw >> 12) & 15u, nbm1 = (hw >> 16) & 0xFFu;
+        const uint32_t M = hw & 0xFFFu, d = (hw >> 12) & 15u, nbm1 = (1u << ((hw >> 16) & 15u)) - 1;
         const uint32_t shift = (hw >> 24) & 31u;
         const bool by_value = hw >> 31;
         const uint32_t* B = s_tab + __builtin_amdgcn_readfirstlane(h.x);

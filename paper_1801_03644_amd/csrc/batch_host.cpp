@@ -20,7 +20,8 @@ namespace {
 constexpr uint64_t kTileRows = 4096;
 constexpr uint64_t kMaxLdsTable = 60 * 1024;   // bytes of query table per workgroup
 constexpr uint64_t kMaxRegGroup = 4096;         // queries per workgroup, slot-mask variant
-constexpr uint32_t kRankBuckets = 256;          // most buckets of a rank search
+constexpr uint32_t kRankBuckets = 1024;         // most buckets of a rank search
+constexpr uint64_t kRankLdsWords = 72 * 256;    // group tables up to which it is tried
 
 template <typename T>
 int grow_device(T** p, uint64_t* have, uint64_t need, const char* what) {
@@ -113,8 +114,9 @@ uint32_t value_bucket(float v, float vlo, float scale, uint32_t nbm1) {
   return static_cast<uint32_t>(t);
 }
 
-// mode: 0 either map, 1 by key only, 2 by value only (by key where that is impossible).
-RankBuckets rank_buckets(const std::vector<uint32_t>& ends, int mode) {
+// mode: 0 either map, 1 by key only, 2 by value only (by key where that is impossible);
+// max_nb: the most buckets tried (a power of two, 8 .. kRankBuckets).
+RankBuckets rank_buckets(const std::vector<uint32_t>& ends, int mode, uint32_t max_nb) {
   RankBuckets best;
   auto consider = [&](uint32_t nb, bool by_value, uint32_t shift, float vlo, float scale,
                       const std::vector<uint32_t>& bucket_of) {
@@ -140,7 +142,7 @@ RankBuckets rank_buckets(const std::vector<uint32_t>& ends, int mode) {
   };
   const uint32_t kmin = ends.front(), span = ends.back() - kmin;
   std::vector<uint32_t> bucket_of(ends.size());
-  for (uint32_t nb = 8; mode != 2 && nb <= kRankBuckets; nb *= 2) {
+  for (uint32_t nb = 8; mode != 2 && nb <= max_nb; nb *= 2) {
     uint32_t shift = 0;
     while ((span >> shift) > nb - 1) ++shift;
     for (size_t i = 0; i < ends.size(); ++i) bucket_of[i] = std::min<uint32_t>((ends[i] - kmin) >> shift, nb - 1);
@@ -155,13 +157,13 @@ RankBuckets rank_buckets(const std::vector<uint32_t>& ends, int mode) {
     }
   }
   if (mode != 1 && vlo < vhi && std::isfinite(vhi - vlo)) {
-    for (uint32_t nb = 8; nb <= kRankBuckets; nb *= 2) {
+    for (uint32_t nb = 8; nb <= max_nb; nb *= 2) {
       const float scale = static_cast<float>(nb) / (vhi - vlo);
       for (size_t i = 0; i < ends.size(); ++i) bucket_of[i] = value_bucket(key_value(ends[i]), vlo, scale, nb - 1);
       consider(nb, true, 0, vlo, scale, bucket_of);
     }
   }
-  if (best.nb == 0) return rank_buckets(ends, 1);  // by value was asked for and impossible
+  if (best.nb == 0) return rank_buckets(ends, 1, max_nb);  // by value was asked for and impossible
   return best;
 }
 
@@ -209,7 +211,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   auto rank_words = [&](uint64_t S) {  // worst case: 2 S interval ends per slot (padded)
     const uint64_t sw = S <= 32 ? 1 : S <= 64 ? 2 : 4;
     return S + 4 + 4 * static_cast<uint64_t>(n_slots) +
-           static_cast<uint64_t>(n_slots) * (kRankBuckets / 2 + 4 * S + 8 + (2 * S + 1) * sw);
+           static_cast<uint64_t>(n_slots) * (256 / 2 + 4 * S + 8 + (2 * S + 1) * sw);
   };
   uint64_t rank_group = std::min<uint64_t>(128, cfg.group ? cfg.group : nq);
   while (rank_group > 32 && (rank_words(rank_group) + 4) * 4 > lds_room) rank_group /= 2;
@@ -277,7 +279,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     q0 = q1;
   }
   // Rank variant: per group, per query (kind | output row << 8), per slot a header
-  // (offset of the ends; M | d << 12 | (nb - 1) << 16 | shift << 24 | by value << 31;
+  // (offset of the ends; M | d << 12 | log2(nb) << 16 | shift << 24 | by value << 31;
   // kmin or vlo; scale), then per slot the
   // bucket starts (nb 16-bit counts), the M sorted interval ends padded with 2^d - 1
   // words 0xFFFFFFFF, and the (M + 1) x sw table of query bitsets by rank (offsets
@@ -300,35 +302,55 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       const Plan& pl = items[q].plan;
       for (size_t i = 0; i < pl.preds.size(); ++i) pred_at[(q - q0) * n_slots + slot_of[pl.dims[i]]] = static_cast<int>(i);
     }
+    auto bounds_of = [&](uint64_t q, int sl, uint32_t& klo, uint32_t& khi) {
+      const Plan& pl = items[q].plan;
+      const int i = pred_at[(q - q0) * n_slots + sl];
+      if (i >= 0) {
+        klo = batch_key(pl.preds[i].lo);
+        khi = batch_key(pl.preds[i].hi);
+        return true;
+      }
+      if (pl.preds.empty() && sl == 0) {  // the always-true predicate
+        klo = batch_key(-std::numeric_limits<float>::infinity());
+        khi = batch_key(std::numeric_limits<float>::infinity());
+        return true;
+      }
+      return false;
+    };
+    // Per slot the sorted distinct interval ends and their buckets: up to kRankBuckets
+    // buckets where the group's tables then stay within kRankLdsWords (two workgroups
+    // of 8 waves per CU, the most the kernel's registers allow), else up to 256.
+    std::vector<std::vector<uint32_t>> ends_of(n_slots);
+    std::vector<RankBuckets> buckets_of(n_slots);
     for (int sl = 0; sl < n_slots; ++sl) {
-      std::vector<uint32_t> ends;
-      auto bounds_of = [&](uint64_t q, uint32_t& klo, uint32_t& khi) {
-        const Plan& pl = items[q].plan;
-        const int i = pred_at[(q - q0) * n_slots + sl];
-        if (i >= 0) {
-          klo = batch_key(pl.preds[i].lo);
-          khi = batch_key(pl.preds[i].hi);
-          return true;
-        }
-        if (pl.preds.empty() && sl == 0) {  // the always-true predicate
-          klo = batch_key(-std::numeric_limits<float>::infinity());
-          khi = batch_key(std::numeric_limits<float>::infinity());
-          return true;
-        }
-        return false;
-      };
+      std::vector<uint32_t>& ends = ends_of[sl];
       for (uint64_t q = q0; q < q1; ++q) {
         uint32_t klo, khi;
-        if (bounds_of(q, klo, khi)) {
+        if (bounds_of(q, sl, klo, khi)) {
           ends.push_back(klo);
           ends.push_back(khi + 1);  // keys of non-NaN floats stay below 0xFFFFFFFF
         }
       }
       std::sort(ends.begin(), ends.end());
       ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
+    }
+    auto choose = [&](uint32_t max_nb) {
+      uint64_t words = hq + 4 * static_cast<uint64_t>(n_slots);
+      for (int sl = 0; sl < n_slots; ++sl) {
+        const uint32_t M = static_cast<uint32_t>(ends_of[sl].size());
+        if (M == 0) continue;
+        buckets_of[sl] = rank_buckets(ends_of[sl], ds->rank_buckets, max_nb);
+        const RankBuckets& rb = buckets_of[sl];
+        words += rb.nb / 2 + ((M + (1u << rb.d) - 1 + 3) & ~3u) + static_cast<uint64_t>(M + 1) * rank_sw + 3;
+      }
+      return words;
+    };
+    if (choose(kRankBuckets) + ((gq + 3) & ~3u) > kRankLdsWords) choose(256);
+    for (int sl = 0; sl < n_slots; ++sl) {
+      const std::vector<uint32_t>& ends = ends_of[sl];
       const uint32_t M = static_cast<uint32_t>(ends.size());
       if (M == 0) continue;  // header all zero
-      const RankBuckets rb = rank_buckets(ends, ds->rank_buckets);
+      const RankBuckets& rb = buckets_of[sl];
       while ((table.size() - base) % 4) table.push_back(0u);  // 16-byte aligned
       const uint64_t s0 = table.size();
       table.resize(s0 + rb.nb / 2, 0u);
@@ -338,7 +360,8 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       std::memcpy(&vlo_bits, &rb.vlo, 4);
       std::memcpy(&scale_bits, &rb.scale, 4);
       table[base + hq + 4 * sl] = static_cast<uint32_t>(table.size() - base);
-      table[base + hq + 4 * sl + 1] = M | (rb.d << 12) | ((rb.nb - 1) << 16) | (rb.shift << 24) |
+      table[base + hq + 4 * sl + 1] = M | (rb.d << 12) | (static_cast<uint32_t>(__builtin_ctz(rb.nb)) << 16) |
+                                      (rb.shift << 24) |
                                       (rb.by_value ? 0x80000000u : 0u);
       table[base + hq + 4 * sl + 2] = rb.by_value ? vlo_bits : ends[0];
       table[base + hq + 4 * sl + 3] = rb.by_value ? scale_bits : 0u;
@@ -351,7 +374,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       for (uint64_t q = q0; q < q1; ++q) {
         const uint32_t bit = static_cast<uint32_t>(q - q0);
         uint32_t klo, khi, r_lo = 0, r_hi = M;  // the query passes for ranks in (r_lo, r_hi]
-        if (bounds_of(q, klo, khi)) {
+        if (bounds_of(q, sl, klo, khi)) {
           r_lo = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), klo) - ends.begin());
           r_hi = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), khi + 1) - ends.begin());
         } else {
