@@ -156,7 +156,14 @@ RankBuckets rank_buckets(const std::vector<uint32_t>& ends, int mode, uint32_t m
       vhi = std::max(vhi, v);
     }
   }
-  if (mode != 1 && vlo < vhi && std::isfinite(vhi - vlo)) {
+  // The value map only where the host's float arithmetic on the ends cannot meet a
+  // subnormal that a flush-to-zero mode of the calling thread could change: a span of
+  // at least 2^-90 (scale at most 2^100) and a zero or normal lower end of at least
+  // 2^-100 in magnitude.  A subnormal end or key then lands in the bucket it would get
+  // exactly (the difference rounds to -vlo, or the product truncates to 0).
+  const bool value_ok = vlo < vhi && std::isfinite(vhi - vlo) && vhi - vlo >= 0x1p-90f &&
+                        (vlo == 0.0f || std::fabs(vlo) >= 0x1p-100f);
+  if (mode != 1 && value_ok) {
     for (uint32_t nb = 8; nb <= max_nb; nb *= 2) {
       const float scale = static_cast<float>(nb) / (vhi - vlo);
       for (size_t i = 0; i < ends.size(); ++i) bucket_of[i] = value_bucket(key_value(ends[i]), vlo, scale, nb - 1);
