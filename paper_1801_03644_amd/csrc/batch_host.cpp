@@ -7,6 +7,7 @@
 #include <limits>
 
 #include "mdrq_internal.h"
+#include "rank_buckets.h"
 
 namespace mdrq {
 namespace {
@@ -20,7 +21,6 @@ namespace {
 constexpr uint64_t kTileRows = 4096;
 constexpr uint64_t kMaxLdsTable = 60 * 1024;   // bytes of query table per workgroup
 constexpr uint64_t kMaxRegGroup = 4096;         // queries per workgroup, slot-mask variant
-constexpr uint32_t kRankBuckets = 1024;         // most buckets of a rank search
 constexpr uint64_t kRankLdsWords = 72 * 256;    // group tables up to which it is tried
 
 template <typename T>
@@ -84,95 +84,6 @@ uint64_t shape_key(uint64_t n_rows, size_t n_slots, size_t n_queries) {
   return (lr << 16) | (static_cast<uint64_t>(n_slots) << 8) | lq;
 }
 
-// Buckets of the rank search over sorted distinct interval ends, either by key (nb
-// buckets of 2^shift keys from the smallest end, the last open above) or by value
-// (bucket min(trunc(clamp((v - vlo) * scale, 0, nb - 1))) of a float v, in float
-// arithmetic that the kernel repeats exactly; an end above key(+inf) goes to the last
-// bucket).  Both maps are monotone in the key order, so an end in a lower bucket is
-// below every key of a higher one.  The starts count the ends in lower buckets, and d
-// is the number of binary-search steps that resolve the fullest bucket.  Of the maps
-// and bucket counts (powers of two up to kRankBuckets) tried, the one with the fewest
-// steps wins, key before value and the fewer buckets on a tie.
-struct RankBuckets {
-  uint32_t nb = 0, shift = 0, d = 0;
-  bool by_value = false;
-  float vlo = 0.0f, scale = 1.0f;
-  std::vector<uint16_t> starts;
-};
-
-float key_value(uint32_t k) {  // the float of an order-preserving key (NaN above +inf)
-  const uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
-  float v;
-  std::memcpy(&v, &b, sizeof v);
-  return v;
-}
-
-uint32_t value_bucket(float v, float vlo, float scale, uint32_t nbm1) {
-  if (std::isnan(v)) return nbm1;
-  float t = (v - vlo) * scale;
-  t = std::fmin(std::fmax(t, 0.0f), static_cast<float>(nbm1));
-  return static_cast<uint32_t>(t);
-}
-
-// mode: 0 either map, 1 by key only, 2 by value only (by key where that is impossible);
-// max_nb: the most buckets tried (a power of two, 8 .. kRankBuckets).
-RankBuckets rank_buckets(const std::vector<uint32_t>& ends, int mode, uint32_t max_nb) {
-  RankBuckets best;
-  auto consider = [&](uint32_t nb, bool by_value, uint32_t shift, float vlo, float scale,
-                      const std::vector<uint32_t>& bucket_of) {
-    std::vector<uint16_t> starts(nb, 0);
-    std::vector<uint32_t> occ(nb, 0);
-    for (uint32_t b : bucket_of) ++occ[b];
-    uint32_t below = 0, fullest = 0;
-    for (uint32_t b = 0; b < nb; ++b) {
-      starts[b] = static_cast<uint16_t>(below);
-      below += occ[b];
-      fullest = std::max(fullest, occ[b]);
-    }
-    const uint32_t d = 32 - static_cast<uint32_t>(__builtin_clz(fullest));  // 2^d - 1 >= fullest
-    if (best.nb == 0 || d < best.d) {
-      best.nb = nb;
-      best.shift = shift;
-      best.d = d;
-      best.by_value = by_value;
-      best.vlo = vlo;
-      best.scale = scale;
-      best.starts = std::move(starts);
-    }
-  };
-  const uint32_t kmin = ends.front(), span = ends.back() - kmin;
-  std::vector<uint32_t> bucket_of(ends.size());
-  for (uint32_t nb = 8; mode != 2 && nb <= max_nb; nb *= 2) {
-    uint32_t shift = 0;
-    while ((span >> shift) > nb - 1) ++shift;
-    for (size_t i = 0; i < ends.size(); ++i) bucket_of[i] = std::min<uint32_t>((ends[i] - kmin) >> shift, nb - 1);
-    consider(nb, false, shift, 0.0f, 1.0f, bucket_of);
-  }
-  float vlo = std::numeric_limits<float>::infinity(), vhi = -vlo;
-  for (uint32_t e : ends) {
-    const float v = key_value(e);
-    if (std::isfinite(v)) {
-      vlo = std::min(vlo, v);
-      vhi = std::max(vhi, v);
-    }
-  }
-  // The value map only where the host's float arithmetic on the ends cannot meet a
-  // subnormal that a flush-to-zero mode of the calling thread could change: a span of
-  // at least 2^-90 (scale at most 2^100) and a zero or normal lower end of at least
-  // 2^-100 in magnitude.  A subnormal end or key then lands in the bucket it would get
-  // exactly (the difference rounds to -vlo, or the product truncates to 0).
-  const bool value_ok = vlo < vhi && std::isfinite(vhi - vlo) && vhi - vlo >= 0x1p-90f &&
-                        (vlo == 0.0f || std::fabs(vlo) >= 0x1p-100f);
-  if (mode != 1 && value_ok) {
-    for (uint32_t nb = 8; nb <= max_nb; nb *= 2) {
-      const float scale = static_cast<float>(nb) / (vhi - vlo);
-      for (size_t i = 0; i < ends.size(); ++i) bucket_of[i] = value_bucket(key_value(ends[i]), vlo, scale, nb - 1);
-      consider(nb, true, 0, vlo, scale, bucket_of);
-    }
-  }
-  if (best.nb == 0) return rank_buckets(ends, 1, max_nb);  // by value was asked for and impossible
-  return best;
-}
 
 // Run one shared scan over `items` (union of at most kMaxUnion columns; unions of more
 // than kMaxSlots columns take the LDS variant).
@@ -341,18 +252,23 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       std::sort(ends.begin(), ends.end());
       ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
     }
+    std::vector<std::vector<RankBuckets>> cands(n_slots);
+    for (int sl = 0; sl < n_slots; ++sl)
+      if (!ends_of[sl].empty()) cands[sl] = bucket_candidates(ends_of[sl], ds->rank_buckets, kRankBuckets);
     auto choose = [&](uint32_t max_nb) {
       uint64_t words = hq + 4 * static_cast<uint64_t>(n_slots);
       for (int sl = 0; sl < n_slots; ++sl) {
         const uint32_t M = static_cast<uint32_t>(ends_of[sl].size());
         if (M == 0) continue;
-        buckets_of[sl] = rank_buckets(ends_of[sl], ds->rank_buckets, max_nb);
+        buckets_of[sl] = pick_buckets(cands[sl], max_nb);
         const RankBuckets& rb = buckets_of[sl];
         words += rb.nb / 2 + ((M + (1u << rb.d) - 1 + 3) & ~3u) + static_cast<uint64_t>(M + 1) * rank_sw + 3;
       }
       return words;
     };
     if (choose(kRankBuckets) + ((gq + 3) & ~3u) > kRankLdsWords) choose(256);
+    for (int sl = 0; sl < n_slots; ++sl)
+      if (!ends_of[sl].empty()) fill_starts(ends_of[sl], buckets_of[sl]);
     for (int sl = 0; sl < n_slots; ++sl) {
       const std::vector<uint32_t>& ends = ends_of[sl];
       const uint32_t M = static_cast<uint32_t>(ends.size());
@@ -378,18 +294,29 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       while ((table.size() - base) % 4) table.push_back(0u);
       const uint64_t t0 = table.size();
       table.resize(t0 + static_cast<uint64_t>(M + 1) * rank_sw, 0u);
+      // A query passes for ranks in (r_lo, r_hi]: its bit is toggled on at r_lo + 1 and
+      // off at r_hi + 1, and a running XOR over the ranks fills the rows; a query
+      // without a predicate on this slot passes at every rank, 0 included.
+      std::vector<uint32_t> toggle(static_cast<size_t>(M + 2) * rank_sw, 0u), always(rank_sw, 0u);
       for (uint64_t q = q0; q < q1; ++q) {
-        const uint32_t bit = static_cast<uint32_t>(q - q0);
-        uint32_t klo, khi, r_lo = 0, r_hi = M;  // the query passes for ranks in (r_lo, r_hi]
-        if (bounds_of(q, sl, klo, khi)) {
-          r_lo = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), klo) - ends.begin());
-          r_hi = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), khi + 1) - ends.begin());
-        } else {
-          r_lo = 0;  // no predicate on this slot: every rank, 0 included
-          for (uint32_t r = 0; r <= M; ++r) table[t0 + r * rank_sw + bit / 32] |= 1u << (bit % 32);
+        const uint32_t bit = static_cast<uint32_t>(q - q0), w = bit / 32, m = 1u << (bit % 32);
+        uint32_t klo, khi;
+        if (!bounds_of(q, sl, klo, khi)) {
+          always[w] |= m;
           continue;
         }
-        for (uint32_t r = r_lo + 1; r <= r_hi; ++r) table[t0 + r * rank_sw + bit / 32] |= 1u << (bit % 32);
+        const uint32_t r_lo = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), klo) - ends.begin());
+        const uint32_t r_hi = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), khi + 1) - ends.begin());
+        if (r_lo >= r_hi) continue;  // an empty interval passes nowhere
+        toggle[static_cast<size_t>(r_lo + 1) * rank_sw + w] ^= m;
+        toggle[static_cast<size_t>(r_hi + 1) * rank_sw + w] ^= m;
+      }
+      for (int w = 0; w < rank_sw; ++w) {
+        uint32_t cur = 0;
+        for (uint32_t r = 0; r <= M; ++r) {
+          cur ^= toggle[static_cast<size_t>(r) * rank_sw + w];
+          table[t0 + static_cast<uint64_t>(r) * rank_sw + w] = cur | always[w];
+        }
       }
     }
     q0 = q1;

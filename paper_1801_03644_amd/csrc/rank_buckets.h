@@ -1,0 +1,157 @@
+// Bucket maps of the rank variant's search (host side, plain C++: the kernel repeats
+// the value map's float arithmetic exactly, and a CPU test checks these functions
+// against brute force).
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+namespace mdrq {
+
+constexpr uint32_t kRankBuckets = 1024;  // most buckets of a rank search
+
+// Buckets of the rank search over sorted distinct interval ends, either by key (nb
+// buckets of 2^shift keys from the smallest end, the last open above) or by value
+// (bucket min(trunc(clamp((v - vlo) * scale, 0, nb - 1))) of a float v, in float
+// arithmetic that the kernel repeats exactly; an end above key(+inf) goes to the last
+// bucket).  Both maps are monotone in the key order, so an end in a lower bucket is
+// below every key of a higher one.  The starts count the ends in lower buckets, and d
+// is the number of binary-search steps that resolve the fullest bucket.  Of the maps
+// and bucket counts (powers of two up to kRankBuckets) tried, the one with the fewest
+// steps wins, key before value and the fewer buckets on a tie.
+struct RankBuckets {
+  uint32_t nb = 0, shift = 0, d = 0;
+  bool by_value = false;
+  float vlo = 0.0f, scale = 1.0f;
+  std::vector<uint16_t> starts;
+};
+
+inline float key_value(uint32_t k) {  // the float of an order-preserving key (NaN above +inf)
+  const uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  float v;
+  std::memcpy(&v, &b, sizeof v);
+  return v;
+}
+
+inline uint32_t value_bucket(float v, float vlo, float scale, uint32_t nbm1) {
+  if (v != v) return nbm1;  // NaN: an end above key(+inf)
+  const float t = (v - vlo) * scale;
+  // trunc(clamp(t, 0, nb - 1)); t is never NaN here (v, vlo finite or infinite, scale
+  // finite and positive, and v - vlo is not inf - inf as vlo is finite)
+  if (!(t > 0.0f)) return 0;
+  return t < static_cast<float>(nbm1) ? static_cast<uint32_t>(t) : nbm1;
+}
+
+// Candidate bucket maps of sorted distinct ends, each with its search steps d (starts
+// not built).  mode: 0 both maps, 1 by key only, 2 by value only (by key where that is
+// impossible); max_nb: the most buckets (a power of two, 8 .. kRankBuckets); no more
+// than about 4 per end are tried.  Because both maps are monotone and the ends sorted,
+// the ends of a bucket are consecutive, so the fullest bucket is the longest run of
+// equal bucket numbers: one pass per candidate, nothing allocated.  Halving the bucket
+// count merges buckets in pairs under either map (the key map's shift grows by one,
+// the value map's scale halves exactly), so d never falls as buckets are halved: each
+// map is walked down from its most buckets and left once d has grown past its value at
+// min(max_nb, 256) buckets -- every candidate a smaller cap could prefer is seen.
+inline std::vector<RankBuckets> bucket_candidates(const std::vector<uint32_t>& ends, int mode,
+                                                  uint32_t max_nb) {
+  const uint32_t M = static_cast<uint32_t>(ends.size());
+  const uint32_t kmin = ends.front(), span = ends.back() - kmin;
+  std::vector<RankBuckets> out;
+  uint32_t cap = 8;
+  while (cap < max_nb && cap < 4 * M) cap *= 2;
+  const uint32_t low_cap = std::min<uint32_t>(cap, 256);
+  auto steps = [](uint32_t fullest) { return 32 - static_cast<uint32_t>(__builtin_clz(fullest)); };
+  auto walk = [&](auto&& make, auto&& bucket_of) {
+    uint32_t d_low = 0;
+    for (uint32_t nb = cap; nb >= 8; nb /= 2) {
+      RankBuckets m = make(nb);
+      uint32_t fullest = 0, run = 0, prev = 0xFFFFFFFFu;
+      for (uint32_t i = 0; i < M; ++i) {
+        const uint32_t b = bucket_of(m, i);
+        run = b == prev ? run + 1 : 1;
+        prev = b;
+        fullest = std::max(fullest, run);
+      }
+      m.d = steps(fullest);
+      if (nb == low_cap) d_low = m.d;
+      if (nb < low_cap && m.d > d_low) break;
+      out.push_back(m);
+    }
+  };
+  if (mode != 2)
+    walk(
+        [&](uint32_t nb) {
+          RankBuckets m;
+          m.nb = nb;
+          while ((span >> m.shift) > nb - 1) ++m.shift;
+          return m;
+        },
+        [&](const RankBuckets& m, uint32_t i) { return std::min<uint32_t>((ends[i] - kmin) >> m.shift, m.nb - 1); });
+  if (mode == 1) return out;
+  std::vector<float> vals(M);
+  float vlo = std::numeric_limits<float>::infinity(), vhi = -vlo;
+  for (uint32_t i = 0; i < M; ++i) {
+    vals[i] = key_value(ends[i]);
+    if (std::isfinite(vals[i])) {
+      vlo = std::min(vlo, vals[i]);
+      vhi = std::max(vhi, vals[i]);
+    }
+  }
+  // The value map only where the host's float arithmetic on the ends cannot meet a
+  // subnormal that a flush-to-zero mode of the calling thread could change: a span of
+  // at least 2^-90 (scale at most 2^100) and a zero or normal lower end of at least
+  // 2^-100 in magnitude.  A subnormal end or key then lands in the bucket it would get
+  // exactly (the difference rounds to -vlo, or the product truncates to 0).
+  const bool value_ok = vlo < vhi && std::isfinite(vhi - vlo) && vhi - vlo >= 0x1p-90f &&
+                        (vlo == 0.0f || std::fabs(vlo) >= 0x1p-100f);
+  if (!value_ok) return mode == 2 ? bucket_candidates(ends, 1, max_nb) : out;
+  walk(
+      [&](uint32_t nb) {
+        RankBuckets m;
+        m.nb = nb;
+        m.by_value = true;
+        m.vlo = vlo;
+        m.scale = static_cast<float>(nb) / (vhi - vlo);
+        return m;
+      },
+      [&](const RankBuckets& m, uint32_t i) { return value_bucket(vals[i], m.vlo, m.scale, m.nb - 1); });
+  return out;
+}
+
+// The preferred candidate with at most cap buckets: the fewest steps, then the key map,
+// then the fewest buckets.
+inline RankBuckets pick_buckets(const std::vector<RankBuckets>& c, uint32_t cap) {
+  RankBuckets best;
+  for (const RankBuckets& m : c) {
+    if (m.nb > cap) continue;
+    if (best.nb == 0 || m.d < best.d ||
+        (m.d == best.d && (m.by_value < best.by_value || (m.by_value == best.by_value && m.nb < best.nb))))
+      best = m;
+  }
+  return best;
+}
+
+// The bucket starts of a chosen map: the number of ends in lower buckets.
+inline void fill_starts(const std::vector<uint32_t>& ends, RankBuckets& rb) {
+  const uint32_t M = static_cast<uint32_t>(ends.size());
+  rb.starts.assign(rb.nb, 0);
+  uint32_t next = 0;  // first bucket whose start is not yet set
+  for (uint32_t i = 0; i < M; ++i) {
+    const uint32_t b = rb.by_value ? value_bucket(key_value(ends[i]), rb.vlo, rb.scale, rb.nb - 1)
+                                   : std::min<uint32_t>((ends[i] - ends[0]) >> rb.shift, rb.nb - 1);
+    while (next <= b) rb.starts[next++] = static_cast<uint16_t>(i);
+  }
+  while (next < rb.nb) rb.starts[next++] = static_cast<uint16_t>(M);
+}
+
+inline RankBuckets rank_buckets(const std::vector<uint32_t>& ends, int mode, uint32_t max_nb) {
+  RankBuckets rb = pick_buckets(bucket_candidates(ends, mode, max_nb), max_nb);
+  fill_starts(ends, rb);
+  return rb;
+}
+
+}  // namespace mdrq

@@ -1,0 +1,119 @@
+// Brute-force check of the rank variant's bucket maps (host side).  For random sorted
+// sets of distinct interval ends -- uniform, log-spread of both signs, arbitrary bit
+// patterns, a grid, with key(-inf) and key(+inf) + 1 mixed in -- and every mode and
+// bucket cap: bucket numbers never decrease along the sorted ends (the map is
+// monotone), the starts equal the number of ends in lower buckets, 2^d - 1 holds the
+// fullest bucket and 2^(d-1) - 1 does not, the bucket count respects the cap, the
+// key-only mode never picks the value map, and the choice equals an exhaustive search.  The kernel's value map repeats the host's
+// float arithmetic, so a key between two ends lands in a bucket between theirs.
+#include <cstdio>
+#include <random>
+
+#include "rank_buckets.h"
+
+namespace {
+
+uint32_t order_key(float x) {
+  uint32_t b;
+  std::memcpy(&b, &x, 4);
+  if (b == 0x80000000u) b = 0;
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+}  // namespace
+
+int main() {
+  std::mt19937 rng(1);
+  int bad = 0, value_maps = 0, key_maps = 0;
+  for (int it = 0; it < 20000; ++it) {
+    const int n = 1 + static_cast<int>(rng() % 300);
+    std::vector<uint32_t> ends;
+    const int kind = it % 4;
+    for (int i = 0; i < n; ++i) {
+      float v;
+      if (kind == 0) {
+        v = std::uniform_real_distribution<float>(0.0f, 1.0f)(rng);
+      } else if (kind == 1) {
+        v = std::exp(std::uniform_real_distribution<float>(-20.0f, 5.0f)(rng)) * ((rng() & 1) ? 1.0f : -1.0f);
+      } else if (kind == 2) {
+        const uint32_t b = static_cast<uint32_t>(rng());
+        std::memcpy(&v, &b, 4);
+        if (std::isnan(v)) v = 1.0f;
+      } else {
+        v = static_cast<float>(rng() % 1000000) * 1e-6f;
+      }
+      const uint32_t k = order_key(v);
+      ends.push_back((rng() & 1) ? k : k + 1);  // key(lo) or key(hi) + 1
+    }
+    if (it % 7 == 0) ends.push_back(order_key(-INFINITY));
+    if (it % 11 == 0) ends.push_back(order_key(INFINITY) + 1);
+    std::sort(ends.begin(), ends.end());
+    ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
+    const uint32_t M = static_cast<uint32_t>(ends.size());
+    for (int mode = 0; mode < 3; ++mode)
+      for (uint32_t cap : {256u, 1024u}) {
+        const mdrq::RankBuckets rb = mdrq::rank_buckets(ends, mode, cap);
+        (rb.by_value ? value_maps : key_maps)++;
+        std::vector<uint32_t> bk(M);
+        for (uint32_t i = 0; i < M; ++i)
+          bk[i] = rb.by_value ? mdrq::value_bucket(mdrq::key_value(ends[i]), rb.vlo, rb.scale, rb.nb - 1)
+                              : std::min<uint32_t>((ends[i] - ends[0]) >> rb.shift, rb.nb - 1);
+        for (uint32_t i = 1; i < M; ++i)
+          if (bk[i] < bk[i - 1]) {
+            ++bad;
+            break;
+          }
+        std::vector<uint32_t> occ(rb.nb, 0);
+        for (uint32_t b : bk) ++occ[b];
+        uint32_t below = 0, fullest = 0;
+        for (uint32_t b = 0; b < rb.nb; ++b) {
+          if (rb.starts[b] != below) {
+            ++bad;
+            break;
+          }
+          below += occ[b];
+          fullest = std::max(fullest, occ[b]);
+        }
+        if (fullest > (1u << rb.d) - 1 || (rb.d > 1 && fullest <= (1u << (rb.d - 1)) - 1)) ++bad;
+        if (rb.nb > cap || rb.nb < 8 || (rb.nb & (rb.nb - 1))) ++bad;
+        if (mode == 1 && rb.by_value) ++bad;
+        // The choice equals an exhaustive search over both maps and all bucket counts
+        // up to the cap (and about 4 per end): fewest steps, then key, then fewest.
+        uint32_t lim = 8;
+        while (lim < cap && lim < 4 * M) lim *= 2;
+        uint32_t best_d = 99, best_v = 2, best_nb = 0;
+        float vlo = INFINITY, vhi = -INFINITY;
+        for (uint32_t e : ends) {
+          const float v = mdrq::key_value(e);
+          if (std::isfinite(v)) {
+            vlo = std::min(vlo, v);
+            vhi = std::max(vhi, v);
+          }
+        }
+        const bool value_ok = vlo < vhi && std::isfinite(vhi - vlo) && vhi - vlo >= 0x1p-90f &&
+                              (vlo == 0.0f || std::fabs(vlo) >= 0x1p-100f);
+        for (uint32_t v = 0; v < 2; ++v) {
+          if ((v == 0 && mode == 2 && value_ok) || (v == 1 && (mode == 1 || !value_ok))) continue;
+          for (uint32_t nb = 8; nb <= lim; nb *= 2) {
+            std::vector<uint32_t> o(nb, 0);
+            uint32_t shift = 0;
+            while (((ends.back() - ends[0]) >> shift) > nb - 1) ++shift;
+            const float scale = static_cast<float>(nb) / (vhi - vlo);
+            for (uint32_t e : ends)
+              ++o[v ? mdrq::value_bucket(mdrq::key_value(e), vlo, scale, nb - 1)
+                    : std::min<uint32_t>((e - ends[0]) >> shift, nb - 1)];
+            const uint32_t f = *std::max_element(o.begin(), o.end());
+            const uint32_t d = 32 - static_cast<uint32_t>(__builtin_clz(f));
+            if (d < best_d || (d == best_d && (v < best_v || (v == best_v && nb < best_nb)))) {
+              best_d = d;
+              best_v = v;
+              best_nb = nb;
+            }
+          }
+        }
+        if (rb.d != best_d || rb.by_value != (best_v == 1) || rb.nb != best_nb) ++bad;
+      }
+  }
+  std::printf("bad=%d key_maps=%d value_maps=%d\n", bad, key_maps, value_maps);
+  return bad != 0 || value_maps == 0 || key_maps == 0;
+}
