@@ -651,12 +651,15 @@ std::vector<std::vector<size_t>> plan_groups(const std::vector<Item>& items, uin
 // A shared scan reads every column of its union in full and tests each query on every
 // row; one scan per query reads only that query's columns, and its early break skips
 // the groups of rows already rejected (about a quarter of the bytes on c2's mix).  For a
-// few queries the separate scans are cheaper.  Model: shared = max(column bytes at
-// 6 TB/s, row tests at 8e12/s in registers or 4e12/s in LDS) + 30 us; separate =
-// sum over queries of 3/4 of its column bytes at 6 TB/s + 25 us.
+// few queries the separate scans are cheaper.  Model: shared = max(union column bytes
+// at 4.5 TB/s, row tests at 8e12/s in registers or 4e12/s in LDS) + 30 us; separate =
+// sum over queries of 3/4 of its column bytes at 6 TB/s + 25 us.  (Measured on 2·10^8
+// rows x 12 columns, batches of 1..32 queries: the shared scan, rank variant with its
+// finish, took 1.05 / 1.72 / 2.25 / 2.97 ms at 2 / 4 / 8 / 32 queries, separate scans
+// about 0.37 ms per query; the two meet at 4 to 5 queries.)
 bool plain_is_cheaper(const std::vector<Item>& items, const std::vector<size_t>& members, int used,
                       uint64_t n_rows) {
-  constexpr double kBytesPerS = 6e12, kRegTests = 8e12, kLdsTests = 4e12;
+  constexpr double kBytesPerS = 6e12, kSharedBytesPerS = 4.5e12, kRegTests = 8e12, kLdsTests = 4e12;
   const double n = static_cast<double>(n_rows);
   double tests = 0.0, plain = 0.0;
   for (size_t m : members) {
@@ -665,7 +668,7 @@ bool plain_is_cheaper(const std::vector<Item>& items, const std::vector<size_t>&
     plain += 0.75 * 4.0 * n * k / kBytesPerS + 25e-6;
   }
   const double shared =
-      std::max(4.0 * n * used / kBytesPerS, tests / (used > kMaxSlots ? kLdsTests : kRegTests)) + 30e-6;
+      std::max(4.0 * n * used / kSharedBytesPerS, tests / (used > kMaxSlots ? kLdsTests : kRegTests)) + 30e-6;
   return plain < shared;
 }
 
