@@ -2,6 +2,8 @@
 // grouping of queries into shared scans, the query table, the launch configuration
 // autotuner, and completion.
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -204,12 +206,18 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   // relative to the group's start, 4-word aligned).  The bucket starts count the ends
   // in lower buckets, and no bucket holds more than 2^d - 1 ends (M <= 2 x 128 fits
   // the header's 12 bits).
-  for (uint64_t q0 = 0; rank && q0 < nq;) {
+  // The groups' tables are independent: each is built into its own vector (offsets
+  // relative to its start), on several host threads when there are many slot tables,
+  // then appended in group order.
+  std::vector<uint64_t> rank_q0;
+  for (uint64_t q0 = 0; rank && q0 < nq; q0 += rank_group) rank_q0.push_back(q0);
+  std::vector<std::vector<uint32_t>> rank_tables(rank_q0.size());
+  auto build_rank_group = [&](size_t gi) {
+    const uint64_t q0 = rank_q0[gi];
     const uint64_t q1 = std::min<uint64_t>(nq, q0 + rank_group);
     const uint32_t gq = static_cast<uint32_t>(q1 - q0);
-    group_first.push_back(static_cast<uint32_t>(q0));
-    const uint64_t base = table.size();
-    group_table.push_back(static_cast<uint32_t>(base));
+    std::vector<uint32_t>& table = rank_tables[gi];
+    const uint64_t base = 0;
     const uint32_t hq = (gq + 3) & ~3u;  // headers, 16-byte aligned
     table.resize(base + hq + 4 * static_cast<uint64_t>(n_slots), 0u);
     for (uint64_t q = q0; q < q1; ++q)
@@ -319,7 +327,25 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
         }
       }
     }
-    q0 = q1;
+  };
+  const size_t slot_tables = rank_q0.size() * static_cast<size_t>(n_slots);
+  const unsigned hw_threads = std::max(1u, std::thread::hardware_concurrency());
+  const size_t n_threads = slot_tables >= 128 ? std::min<size_t>({rank_q0.size(), 8, hw_threads}) : 1;
+  if (n_threads > 1) {
+    std::atomic<size_t> next{0};
+    std::vector<std::thread> pool;
+    for (size_t t = 0; t < n_threads; ++t)
+      pool.emplace_back([&]() {
+        for (size_t gi = next++; gi < rank_q0.size(); gi = next++) build_rank_group(gi);
+      });
+    for (std::thread& th : pool) th.join();
+  } else {
+    for (size_t gi = 0; gi < rank_q0.size(); ++gi) build_rank_group(gi);
+  }
+  for (size_t gi = 0; gi < rank_q0.size(); ++gi) {
+    group_first.push_back(static_cast<uint32_t>(rank_q0[gi]));
+    group_table.push_back(static_cast<uint32_t>(table.size()));
+    table.insert(table.end(), rank_tables[gi].begin(), rank_tables[gi].end());
   }
   // Group table: record offsets (padded to 4 words), then per query a 4-word header
   // and one 4-word entry (slot, key(lo), key(hi) - key(lo) or, for the LDS variant,
