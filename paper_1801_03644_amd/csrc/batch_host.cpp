@@ -207,8 +207,8 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   // in lower buckets, and no bucket holds more than 2^d - 1 ends (M <= 2 x 128 fits
   // the header's 12 bits).
   // The groups' tables are independent: each is built into its own vector (offsets
-  // relative to its start), on several host threads when there are many slot tables,
-  // then appended in group order.
+  // relative to its start), on several host threads when there are 24 or more slot
+  // tables (about 10 us each), then appended in group order.
   std::vector<uint64_t> rank_q0;
   for (uint64_t q0 = 0; rank && q0 < nq; q0 += rank_group) rank_q0.push_back(q0);
   std::vector<std::vector<uint32_t>> rank_tables(rank_q0.size());
@@ -260,15 +260,12 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       std::sort(ends.begin(), ends.end());
       ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
     }
-    std::vector<std::vector<RankBuckets>> cands(n_slots);
-    for (int sl = 0; sl < n_slots; ++sl)
-      if (!ends_of[sl].empty()) cands[sl] = bucket_candidates(ends_of[sl], ds->rank_buckets, kRankBuckets);
     auto choose = [&](uint32_t max_nb) {
       uint64_t words = hq + 4 * static_cast<uint64_t>(n_slots);
       for (int sl = 0; sl < n_slots; ++sl) {
         const uint32_t M = static_cast<uint32_t>(ends_of[sl].size());
         if (M == 0) continue;
-        buckets_of[sl] = pick_buckets(cands[sl], max_nb);
+        buckets_of[sl] = pick_buckets(bucket_candidates(ends_of[sl], ds->rank_buckets, max_nb), max_nb);
         const RankBuckets& rb = buckets_of[sl];
         words += rb.nb / 2 + ((M + (1u << rb.d) - 1 + 3) & ~3u) + static_cast<uint64_t>(M + 1) * rank_sw + 3;
       }
@@ -330,7 +327,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   };
   const size_t slot_tables = rank_q0.size() * static_cast<size_t>(n_slots);
   const unsigned hw_threads = std::max(1u, std::thread::hardware_concurrency());
-  const size_t n_threads = slot_tables >= 128 ? std::min<size_t>({rank_q0.size(), 8, hw_threads}) : 1;
+  const size_t n_threads = slot_tables >= 24 ? std::min<size_t>({rank_q0.size(), 8, hw_threads}) : 1;
   if (n_threads > 1) {
     std::atomic<size_t> next{0};
     std::vector<std::thread> pool;

@@ -54,8 +54,8 @@ inline uint32_t value_bucket(float v, float vlo, float scale, uint32_t nbm1) {
 // equal bucket numbers: one pass per candidate, nothing allocated.  Halving the bucket
 // count merges buckets in pairs under either map (the key map's shift grows by one,
 // the value map's scale halves exactly), so d never falls as buckets are halved: each
-// map is walked down from its most buckets and left once d has grown past its value at
-// min(max_nb, 256) buckets -- every candidate a smaller cap could prefer is seen.
+// map is walked down from its most buckets and left once d has grown, and the last
+// candidate kept is that map's fewest buckets with its fewest steps.
 inline std::vector<RankBuckets> bucket_candidates(const std::vector<uint32_t>& ends, int mode,
                                                   uint32_t max_nb) {
   const uint32_t M = static_cast<uint32_t>(ends.size());
@@ -63,10 +63,9 @@ inline std::vector<RankBuckets> bucket_candidates(const std::vector<uint32_t>& e
   std::vector<RankBuckets> out;
   uint32_t cap = 8;
   while (cap < max_nb && cap < 4 * M) cap *= 2;
-  const uint32_t low_cap = std::min<uint32_t>(cap, 256);
   auto steps = [](uint32_t fullest) { return 32 - static_cast<uint32_t>(__builtin_clz(fullest)); };
   auto walk = [&](auto&& make, auto&& bucket_of) {
-    uint32_t d_low = 0;
+    uint32_t d_top = 0;
     for (uint32_t nb = cap; nb >= 8; nb /= 2) {
       RankBuckets m = make(nb);
       uint32_t fullest = 0, run = 0, prev = 0xFFFFFFFFu;
@@ -77,8 +76,8 @@ inline std::vector<RankBuckets> bucket_candidates(const std::vector<uint32_t>& e
         fullest = std::max(fullest, run);
       }
       m.d = steps(fullest);
-      if (nb == low_cap) d_low = m.d;
-      if (nb < low_cap && m.d > d_low) break;
+      if (nb == cap) d_top = m.d;
+      if (m.d > d_top) break;
       out.push_back(m);
     }
   };
