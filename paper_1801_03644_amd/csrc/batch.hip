@@ -427,10 +427,11 @@ __device__ __forceinline__ uint32_t half_transpose(uint32_t a, const HalfTranspo
 // row then costs, per column, one binary search for its rank and an AND of SW table
 // words -- shared by all the group's queries -- and each 32 queries a bit transpose
 // per 64 rows.  Output words are stored with per-chunk marks (bp.flags), as in the
-// slot-mask variant, so the words need no clearing.  Exact: the boundaries include every interval end, so each rank interval lies
-// wholly inside or outside every predicate.  Rows past the end get the key 0, below
-// every boundary (rank 0), where every predicate fails; a query without predicates
-// carries [key(-inf), key(+inf)] on slot 0.
+// slot-mask variant, so the words need no clearing.  Exact: the boundaries include
+// every interval end, so each rank interval lies wholly inside or outside every
+// predicate.  Rows past the end get the key 0, below every boundary (rank 0), where
+// every predicate fails; a query without predicates carries [key(-inf), key(+inf)]
+// on slot 0.
 //
 // The rank search is bucketed: the host maps a slot's keys monotonically to nb
 // buckets, either by key (2^shift keys per bucket from the smallest boundary kmin) or
