@@ -3,6 +3,7 @@
 // autotuner, and completion.
 #include <algorithm>
 #include <atomic>
+#include <system_error>
 #include <thread>
 #include <cmath>
 #include <cstring>
@@ -328,16 +329,20 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   const size_t slot_tables = rank_q0.size() * static_cast<size_t>(n_slots);
   const unsigned hw_threads = std::max(1u, std::thread::hardware_concurrency());
   const size_t n_threads = slot_tables >= 24 ? std::min<size_t>({rank_q0.size(), 8, hw_threads}) : 1;
-  if (n_threads > 1) {
+  {
+    // The calling thread takes part; if a helper thread cannot be started, the ones
+    // that did start and the calling thread share the groups.
     std::atomic<size_t> next{0};
+    auto work = [&]() {
+      for (size_t gi = next++; gi < rank_q0.size(); gi = next++) build_rank_group(gi);
+    };
     std::vector<std::thread> pool;
-    for (size_t t = 0; t < n_threads; ++t)
-      pool.emplace_back([&]() {
-        for (size_t gi = next++; gi < rank_q0.size(); gi = next++) build_rank_group(gi);
-      });
+    try {
+      for (size_t t = 1; t < n_threads; ++t) pool.emplace_back(work);
+    } catch (const std::system_error&) {
+    }
+    work();
     for (std::thread& th : pool) th.join();
-  } else {
-    for (size_t gi = 0; gi < rank_q0.size(); ++gi) build_rank_group(gi);
   }
   for (size_t gi = 0; gi < rank_q0.size(); ++gi) {
     group_first.push_back(static_cast<uint32_t>(rank_q0[gi]));
