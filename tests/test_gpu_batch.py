@@ -213,12 +213,15 @@ def test_batch_overflow_and_host_outputs():
     q = dg.make_query([(0, 0.1, 0.7), (5, 0.0, 0.9)])
     st, cnt, want = oracle.query(cols, q)
     with mdrq.Dataset.from_host(raw) as ds:
-        caps = [0, 1, cnt // 2, cnt - 1, cnt, None]
-        check_batch(ds, cols, [q] * len(caps), ["ids"] * len(caps), "overflow", caps=caps)
-        outs = [np.zeros(w.n_rows, dtype=np.uint32), np.zeros((w.n_rows + 63) // 64, dtype=np.uint64)]
-        a = ds.query_batch([q, q], outs, ["ids", "bitmap"])
-        assert a[0].count == cnt and np.array_equal(outs[0][:a[0].written], want)
-        assert np.array_equal(bitmap_to_ids(outs[1], w.n_rows)[0], want)
+        for variant in (0, 5):   # autotuned; ranks and bitsets
+            ds.set_option(mdrq.OPT_BATCH_VARIANT, variant)
+            caps = [0, 1, cnt // 2, cnt - 1, cnt, None]
+            check_batch(ds, cols, [q] * len(caps), ["ids"] * len(caps), f"overflow variant={variant}",
+                        caps=caps)
+            outs = [np.zeros(w.n_rows, dtype=np.uint32), np.zeros((w.n_rows + 63) // 64, dtype=np.uint64)]
+            a = ds.query_batch([q, q], outs, ["ids", "bitmap"])
+            assert a[0].count == cnt and np.array_equal(outs[0][:a[0].written], want)
+            assert np.array_equal(bitmap_to_ids(outs[1], w.n_rows)[0], want)
 
 
 def test_launch_configurations_give_identical_results():
