@@ -183,7 +183,9 @@ typedef struct {
 
 /*
  * Replay n_reqs arrival-stamped requests through the serving loop: request i is
- * queued when the run's clock reaches reqs[i].arrival_ns.  rs[i] receives request i's
+ * queued when the run's clock reaches reqs[i].arrival_ns.  The call first waits until
+ * the device is idle (work queued on any stream before the call is complete before
+ * the first scan).  rs[i] receives request i's
  * result exactly as mdrq_query would give it; results that are not count-only must be
  * in device memory.  latency_ns (optional, n_reqs entries) receives each request's
  * arrival-to-completion time; stats (optional) the summary.  The call returns when
@@ -212,7 +214,11 @@ int mdrq_serve(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, const mdrq_requ
  * with its device buffer, until the ticket is reported by mdrq_serve_poll, and the
  * server writes the complete result into it (count, mode, written, status exactly as
  * mdrq_query would) before reporting the ticket.  Results that are not count-only must
- * be in device memory.  Latency counts from the submission.
+ * be in device memory.  `stream` (a hipStream_t, NULL = the default stream) is the
+ * stream of the caller's work on the result buffer: the server records an event on it
+ * at submission and the request's scan runs only after that event, so writes the
+ * caller queued before submitting (a fill, a pending read of a reused buffer) complete
+ * first.  Latency counts from the submission.
  * Errors: MDRQ_EINVAL (bad request, host-memory result, server closing), MDRQ_EBUSY
  * (max_queue requests already waiting, or one bitmap row exceeds a stream's share),
  * or a device error that stopped the server.
@@ -228,7 +234,8 @@ int mdrq_serve(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, const mdrq_requ
  */
 typedef struct mdrq_server mdrq_server;   /* opaque */
 int mdrq_serve_open(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, mdrq_server** out);
-int mdrq_serve_submit(mdrq_server* s, const mdrq_query_t* q, mdrq_result_t* r, uint64_t* ticket);
+int mdrq_serve_submit(mdrq_server* s, const mdrq_query_t* q, mdrq_result_t* r, void* stream,
+                      uint64_t* ticket);
 int mdrq_serve_poll(mdrq_server* s, uint64_t* tickets, uint32_t max_tickets, uint32_t* n_out,
                     uint64_t wait_ns);
 int mdrq_serve_close(mdrq_server* s, mdrq_serve_stats_t* stats);

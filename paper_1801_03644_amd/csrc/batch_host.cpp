@@ -127,16 +127,22 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   for (size_t i = 0; i < slot_dim.size(); ++i) slot_of[slot_dim[i]] = static_cast<int>(i);
   const int n_slots = static_cast<int>(slot_dim.size());
 
-  // Rank variant: queries per group (32 x sw) such that the worst-case tables fit LDS.
+  // Rank variant: queries per group (32 x sw) such that the tables of any group fit LDS.
+  // A group's LDS words: its per-query counts and headers (4-word aligned), 4 header
+  // words per slot and each slot's tables.  Tables with up to kRankBuckets buckets are
+  // only built when the whole group stays within kRankLdsWords, else at most 256
+  // buckets, whose size slot_table_words_bound caps for any 2 S interval ends.
   const size_t lds_room = device().lds > 4096 ? device().lds - 4096 : 0;
-  auto rank_words = [&](uint64_t S) {  // worst case: 2 S interval ends per slot (padded)
-    const uint64_t sw = S <= 32 ? 1 : S <= 64 ? 2 : 4;
-    return S + 4 + 4 * static_cast<uint64_t>(n_slots) +
-           static_cast<uint64_t>(n_slots) * (256 / 2 + 4 * S + 8 + (2 * S + 1) * sw);
+  auto rank_words = [&](uint64_t S) {
+    const uint32_t sw = S <= 32 ? 1 : S <= 64 ? 2 : 4;
+    const uint64_t bound = 2 * align4(S) + 4 * static_cast<uint64_t>(n_slots) +
+                           static_cast<uint64_t>(n_slots) *
+                               slot_table_words_bound(static_cast<uint32_t>(2 * S), 256, sw);
+    return std::max<uint64_t>(bound, kRankLdsWords);
   };
   uint64_t rank_group = std::min<uint64_t>(128, cfg.group ? cfg.group : nq);
-  while (rank_group > 32 && (rank_words(rank_group) + 4) * 4 > lds_room) rank_group /= 2;
-  const bool rank = cfg.lds == 4 && (rank_words(rank_group) + rank_group + 4) * 4 <= lds_room;
+  while (rank_group > 32 && rank_words(rank_group) * 4 > lds_room) rank_group /= 2;
+  const bool rank = cfg.lds == 4 && rank_words(rank_group) * 4 <= lds_room;
   const int rank_sw = rank_group <= 32 ? 1 : rank_group <= 64 ? 2 : 4;
   const bool use_lds = !rank && (cfg.lds == 1 || n_slots > kMaxSlots);
   const bool walk = cfg.lds == 2 && !use_lds;
@@ -201,15 +207,13 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   }
   // Rank variant: per group, per query (kind | output row << 8), per slot a header
   // (offset of the ends; M | d << 12 | log2(nb) << 16 | shift << 24 | by value << 31;
-  // kmin or vlo; scale), then per slot the
-  // bucket starts (nb 16-bit counts), the M sorted interval ends padded with 2^d - 1
-  // words 0xFFFFFFFF, and the (M + 1) x sw table of query bitsets by rank (offsets
+  // kmin or vlo; scale), then per slot the tables of append_slot_tables (offsets
   // relative to the group's start, 4-word aligned).  The bucket starts count the ends
-  // in lower buckets, and no bucket holds more than 2^d - 1 ends (M <= 2 x 128 fits
-  // the header's 12 bits).
-  // The groups' tables are independent: each is built into its own vector (offsets
-  // relative to its start), on several host threads when there are 24 or more slot
-  // tables (about 10 us each), then appended in group order.
+  // in lower buckets, and no bucket holds more than 2^d - 1 ends (M <= 2 x 128 fits the
+  // header's 12 bits).
+  // The groups' tables are independent: each is built into its own vector, on several
+  // host threads when there are 24 or more slot tables (about 10 us each), then
+  // appended in group order.
   std::vector<uint64_t> rank_q0;
   for (uint64_t q0 = 0; rank && q0 < nq; q0 += rank_group) rank_q0.push_back(q0);
   std::vector<std::vector<uint32_t>> rank_tables(rank_q0.size());
@@ -218,32 +222,27 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     const uint64_t q1 = std::min<uint64_t>(nq, q0 + rank_group);
     const uint32_t gq = static_cast<uint32_t>(q1 - q0);
     std::vector<uint32_t>& table = rank_tables[gi];
-    const uint64_t base = 0;
-    const uint32_t hq = (gq + 3) & ~3u;  // headers, 16-byte aligned
-    table.resize(base + hq + 4 * static_cast<uint64_t>(n_slots), 0u);
-    for (uint64_t q = q0; q < q1; ++q)
-      table[base + (q - q0)] = outs[q].kind | (outs[q].out_index << 8);
-    // Per query and slot: (key(lo), key(hi)) of its predicate, if any.
-    std::vector<int> pred_at(gq * static_cast<size_t>(n_slots), -1);
+    const uint32_t hq = static_cast<uint32_t>(align4(gq));  // headers, 16-byte aligned
+    table.assign(hq + 4 * static_cast<uint64_t>(n_slots), 0u);
+    for (uint64_t q = q0; q < q1; ++q) table[q - q0] = outs[q].kind | (outs[q].out_index << 8);
+    // Per slot and query: (key(lo), key(hi)) of its predicate, if any; a query without
+    // predicates carries the always-true [key(-inf), key(+inf)] on slot 0.
+    std::vector<std::vector<KeyInterval>> iv(n_slots, std::vector<KeyInterval>(gq));
     for (uint64_t q = q0; q < q1; ++q) {
       const Plan& pl = items[q].plan;
-      for (size_t i = 0; i < pl.preds.size(); ++i) pred_at[(q - q0) * n_slots + slot_of[pl.dims[i]]] = static_cast<int>(i);
+      for (size_t i = 0; i < pl.preds.size(); ++i) {
+        KeyInterval& k = iv[slot_of[pl.dims[i]]][q - q0];
+        k.klo = batch_key(pl.preds[i].lo);
+        k.khi = batch_key(pl.preds[i].hi);
+        k.has = true;
+      }
+      if (pl.preds.empty()) {
+        KeyInterval& k = iv[0][q - q0];
+        k.klo = batch_key(-std::numeric_limits<float>::infinity());
+        k.khi = batch_key(std::numeric_limits<float>::infinity());
+        k.has = true;
+      }
     }
-    auto bounds_of = [&](uint64_t q, int sl, uint32_t& klo, uint32_t& khi) {
-      const Plan& pl = items[q].plan;
-      const int i = pred_at[(q - q0) * n_slots + sl];
-      if (i >= 0) {
-        klo = batch_key(pl.preds[i].lo);
-        khi = batch_key(pl.preds[i].hi);
-        return true;
-      }
-      if (pl.preds.empty() && sl == 0) {  // the always-true predicate
-        klo = batch_key(-std::numeric_limits<float>::infinity());
-        khi = batch_key(std::numeric_limits<float>::infinity());
-        return true;
-      }
-      return false;
-    };
     // Per slot the sorted distinct interval ends and their buckets: up to kRankBuckets
     // buckets where the group's tables then stay within kRankLdsWords (two workgroups
     // of 8 waves per CU, the most the kernel's registers allow), else up to 256.
@@ -251,13 +250,11 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     std::vector<RankBuckets> buckets_of(n_slots);
     for (int sl = 0; sl < n_slots; ++sl) {
       std::vector<uint32_t>& ends = ends_of[sl];
-      for (uint64_t q = q0; q < q1; ++q) {
-        uint32_t klo, khi;
-        if (bounds_of(q, sl, klo, khi)) {
-          ends.push_back(klo);
-          ends.push_back(khi + 1);  // keys of non-NaN floats stay below 0xFFFFFFFF
+      for (const KeyInterval& k : iv[sl])
+        if (k.has) {
+          ends.push_back(k.klo);
+          ends.push_back(k.khi + 1);  // keys of non-NaN floats stay below 0xFFFFFFFF
         }
-      }
       std::sort(ends.begin(), ends.end());
       ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
     }
@@ -267,63 +264,26 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
         const uint32_t M = static_cast<uint32_t>(ends_of[sl].size());
         if (M == 0) continue;
         buckets_of[sl] = pick_buckets(bucket_candidates(ends_of[sl], ds->rank_buckets, max_nb), max_nb);
-        const RankBuckets& rb = buckets_of[sl];
-        words += rb.nb / 2 + ((M + (1u << rb.d) - 1 + 3) & ~3u) + static_cast<uint64_t>(M + 1) * rank_sw + 3;
+        words += slot_table_words(M, buckets_of[sl], rank_sw);
       }
       return words;
     };
-    if (choose(kRankBuckets) + ((gq + 3) & ~3u) > kRankLdsWords) choose(256);
-    for (int sl = 0; sl < n_slots; ++sl)
-      if (!ends_of[sl].empty()) fill_starts(ends_of[sl], buckets_of[sl]);
+    if (choose(kRankBuckets) + hq > kRankLdsWords) choose(256);
     for (int sl = 0; sl < n_slots; ++sl) {
       const std::vector<uint32_t>& ends = ends_of[sl];
       const uint32_t M = static_cast<uint32_t>(ends.size());
       if (M == 0) continue;  // header all zero
-      const RankBuckets& rb = buckets_of[sl];
-      while ((table.size() - base) % 4) table.push_back(0u);  // 16-byte aligned
-      const uint64_t s0 = table.size();
-      table.resize(s0 + rb.nb / 2, 0u);
-      for (uint32_t b = 0; b < rb.nb; ++b)
-        table[s0 + b / 2] |= static_cast<uint32_t>(rb.starts[b]) << (16 * (b % 2));
+      RankBuckets& rb = buckets_of[sl];
+      fill_starts(ends, rb);
+      const uint32_t at = append_slot_tables(table, ends, rb, iv[sl], rank_sw);
       uint32_t vlo_bits, scale_bits;
       std::memcpy(&vlo_bits, &rb.vlo, 4);
       std::memcpy(&scale_bits, &rb.scale, 4);
-      table[base + hq + 4 * sl] = static_cast<uint32_t>(table.size() - base);
-      table[base + hq + 4 * sl + 1] = M | (rb.d << 12) | (static_cast<uint32_t>(__builtin_ctz(rb.nb)) << 16) |
-                                      (rb.shift << 24) |
-                                      (rb.by_value ? 0x80000000u : 0u);
-      table[base + hq + 4 * sl + 2] = rb.by_value ? vlo_bits : ends[0];
-      table[base + hq + 4 * sl + 3] = rb.by_value ? scale_bits : 0u;
-      table.insert(table.end(), ends.begin(), ends.end());
-      // Padding above every key, to the farthest entry a search within a bucket reads.
-      table.resize(table.size() + ((1u << rb.d) - 1), 0xFFFFFFFFu);
-      while ((table.size() - base) % 4) table.push_back(0u);
-      const uint64_t t0 = table.size();
-      table.resize(t0 + static_cast<uint64_t>(M + 1) * rank_sw, 0u);
-      // A query passes for ranks in (r_lo, r_hi]: its bit is toggled on at r_lo + 1 and
-      // off at r_hi + 1, and a running XOR over the ranks fills the rows; a query
-      // without a predicate on this slot passes at every rank, 0 included.
-      std::vector<uint32_t> toggle(static_cast<size_t>(M + 2) * rank_sw, 0u), always(rank_sw, 0u);
-      for (uint64_t q = q0; q < q1; ++q) {
-        const uint32_t bit = static_cast<uint32_t>(q - q0), w = bit / 32, m = 1u << (bit % 32);
-        uint32_t klo, khi;
-        if (!bounds_of(q, sl, klo, khi)) {
-          always[w] |= m;
-          continue;
-        }
-        const uint32_t r_lo = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), klo) - ends.begin());
-        const uint32_t r_hi = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), khi + 1) - ends.begin());
-        if (r_lo >= r_hi) continue;  // an empty interval passes nowhere
-        toggle[static_cast<size_t>(r_lo + 1) * rank_sw + w] ^= m;
-        toggle[static_cast<size_t>(r_hi + 1) * rank_sw + w] ^= m;
-      }
-      for (int w = 0; w < rank_sw; ++w) {
-        uint32_t cur = 0;
-        for (uint32_t r = 0; r <= M; ++r) {
-          cur ^= toggle[static_cast<size_t>(r) * rank_sw + w];
-          table[t0 + static_cast<uint64_t>(r) * rank_sw + w] = cur | always[w];
-        }
-      }
+      table[hq + 4 * sl] = at;
+      table[hq + 4 * sl + 1] = M | (rb.d << 12) | (static_cast<uint32_t>(__builtin_ctz(rb.nb)) << 16) |
+                               (rb.shift << 24) | (rb.by_value ? 0x80000000u : 0u);
+      table[hq + 4 * sl + 2] = rb.by_value ? vlo_bits : ends[0];
+      table[hq + 4 * sl + 3] = rb.by_value ? scale_bits : 0u;
     }
   };
   const size_t slot_tables = rank_q0.size() * static_cast<size_t>(n_slots);
@@ -331,18 +291,25 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   const size_t n_threads = slot_tables >= 24 ? std::min<size_t>({rank_q0.size(), 8, hw_threads}) : 1;
   {
     // The calling thread takes part; if a helper thread cannot be started, the ones
-    // that did start and the calling thread share the groups.
+    // that did start and the calling thread share the groups.  An exception inside a
+    // builder (an allocation failure) is recorded and reported after the join.
     std::atomic<size_t> next{0};
+    std::atomic<bool> failed{false};
     auto work = [&]() {
-      for (size_t gi = next++; gi < rank_q0.size(); gi = next++) build_rank_group(gi);
+      try {
+        for (size_t gi = next++; gi < rank_q0.size() && !failed; gi = next++) build_rank_group(gi);
+      } catch (...) {
+        failed = true;
+      }
     };
     std::vector<std::thread> pool;
     try {
       for (size_t t = 1; t < n_threads; ++t) pool.emplace_back(work);
-    } catch (const std::system_error&) {
+    } catch (...) {
     }
     work();
     for (std::thread& th : pool) th.join();
+    if (failed) return fail(MDRQ_ENOMEM, "shared scan: host memory for the rank tables");
   }
   for (size_t gi = 0; gi < rank_q0.size(); ++gi) {
     group_first.push_back(static_cast<uint32_t>(rank_q0[gi]));
@@ -405,8 +372,13 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     max_group_words = std::max<uint64_t>(
         max_group_words, (reg ? 0 : group_table[g + 1] - group_table[g]) +
                              ((group_first[g + 1] - group_first[g] + 3) & ~uint64_t{3}));
-  if (rank && max_group_words * 4 > lds_room)
-    return fail(MDRQ_ENOTSUP, "shared scan: rank tables do not fit LDS");
+  if (rank && max_group_words > rank_words(rank_group)) {
+    // Cannot happen (rank_words bounds every group's tables); answered by the
+    // LDS-staged variant rather than failing if it ever did.
+    BatchConfig other = cfg;
+    other.lds = 1;
+    return run_shared(ds, ws, items, other, stream, ms_out);
+  }
 
   // Outputs: device buffers directly, host buffers through device staging.
   uint64_t stage_need = 0;

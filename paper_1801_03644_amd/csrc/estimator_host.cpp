@@ -527,65 +527,67 @@ int order_on_device(mdrq_dataset* ds, const mdrq_query_t* q, Plan& plan, hipStre
 extern "C" {
 
 int mdrq_estimator_create(mdrq_dataset* ds, const mdrq_estimator_config_t* cfg, mdrq_estimator** out) {
-  clear_error();
-  if (!ds || !cfg || !out) return fail(MDRQ_EINVAL, "NULL argument");
-  *out = nullptr;
-  const uint32_t H = cfg->hidden ? cfg->hidden : 64;
-  if (H < 16 || H > 256 || H % 16) return fail(MDRQ_EINVAL, "hidden width must be a multiple of 16 in 16..256");
-  if (ds->n_rows < 2) return fail(MDRQ_EINVAL, "the estimator needs at least 2 rows");
-  uint32_t m = cfg->sample_rows ? cfg->sample_rows
-                                : static_cast<uint32_t>(std::min<uint64_t>(kSampleMax, ds->n_rows));
-  if (m < 2 || m > kSampleMax || m > ds->n_rows) return fail(MDRQ_EINVAL, "sample_rows out of range");
+  return guarded([&]() -> int {
+    clear_error();
+    if (!ds || !cfg || !out) return fail(MDRQ_EINVAL, "NULL argument");
+    *out = nullptr;
+    const uint32_t H = cfg->hidden ? cfg->hidden : 64;
+    if (H < 16 || H > 256 || H % 16) return fail(MDRQ_EINVAL, "hidden width must be a multiple of 16 in 16..256");
+    if (ds->n_rows < 2) return fail(MDRQ_EINVAL, "the estimator needs at least 2 rows");
+    uint32_t m = cfg->sample_rows ? cfg->sample_rows
+                                  : static_cast<uint32_t>(std::min<uint64_t>(kSampleMax, ds->n_rows));
+    if (m < 2 || m > kSampleMax || m > ds->n_rows) return fail(MDRQ_EINVAL, "sample_rows out of range");
 
-  auto* e = new mdrq_estimator();
-  e->ds = ds;
-  e->d = ds->n_dims;
-  e->F = ds->n_dims * kFeatPerDim;
-  e->H = H;
-  e->O = ds->n_dims + 1;
-  e->n_rows = ds->n_rows;
-  uint64_t o = 0;
-  e->oW1 = o; o += static_cast<uint64_t>(e->F) * H;
-  e->ob1 = o; o += H;
-  e->oW2 = o; o += static_cast<uint64_t>(H) * H;
-  e->ob2 = o; o += H;
-  e->oW3 = o; o += static_cast<uint64_t>(H) * e->O;
-  e->ob3 = o; o += e->O;
-  e->n_params = o;
-  auto cleanup = [&](int rc) {
-    mdrq_estimator_free(e);
-    return rc;
-  };
-  if (hipMalloc(&e->bounds, static_cast<uint64_t>(e->d) * (kBins + 1) * 4) != hipSuccess ||
-      hipMalloc(&e->state, 4 * e->n_params * 4) != hipSuccess ||
-      hipMalloc(&e->wb, e->n_params * 2) != hipSuccess)
-    return cleanup(fail(MDRQ_ENOMEM, "estimator: device allocation failed"));
+    auto* e = new mdrq_estimator();
+    e->ds = ds;
+    e->d = ds->n_dims;
+    e->F = ds->n_dims * kFeatPerDim;
+    e->H = H;
+    e->O = ds->n_dims + 1;
+    e->n_rows = ds->n_rows;
+    uint64_t o = 0;
+    e->oW1 = o; o += static_cast<uint64_t>(e->F) * H;
+    e->ob1 = o; o += H;
+    e->oW2 = o; o += static_cast<uint64_t>(H) * H;
+    e->ob2 = o; o += H;
+    e->oW3 = o; o += static_cast<uint64_t>(H) * e->O;
+    e->ob3 = o; o += e->O;
+    e->n_params = o;
+    auto cleanup = [&](int rc) {
+      mdrq_estimator_free(e);
+      return rc;
+    };
+    if (hipMalloc(&e->bounds, static_cast<uint64_t>(e->d) * (kBins + 1) * 4) != hipSuccess ||
+        hipMalloc(&e->state, 4 * e->n_params * 4) != hipSuccess ||
+        hipMalloc(&e->wb, e->n_params * 2) != hipSuccess)
+      return cleanup(fail(MDRQ_ENOMEM, "estimator: device allocation failed"));
 
-  // Histograms: a strided sample of each column, sorted on the device.
-  HistArgs ha{};
-  ha.n_rows = ds->n_rows;
-  ha.m = m;
-  ha.m_pow2 = 1;
-  while (ha.m_pow2 < m) ha.m_pow2 <<= 1;
-  ha.bounds = e->bounds;
-  for (uint32_t j = 0; j < e->d; ++j) ha.cols[j] = ds->cols[j];
-  hipError_t he = launch_sample_sort(ha, e->d, nullptr);
-  if (he != hipSuccess) return cleanup(fail_hip(he, "estimator histograms"));
+    // Histograms: a strided sample of each column, sorted on the device.
+    HistArgs ha{};
+    ha.n_rows = ds->n_rows;
+    ha.m = m;
+    ha.m_pow2 = 1;
+    while (ha.m_pow2 < m) ha.m_pow2 <<= 1;
+    ha.bounds = e->bounds;
+    for (uint32_t j = 0; j < e->d; ++j) ha.cols[j] = ds->cols[j];
+    hipError_t he = launch_sample_sort(ha, e->d, nullptr);
+    if (he != hipSuccess) return cleanup(fail_hip(he, "estimator histograms"));
 
-  // Glorot-uniform hidden weights; zero output layer, so that an untrained network
-  // returns the base (histogram independence) estimate; zero biases and moments.
-  std::vector<float> p(e->n_params, 0.0f);
-  auto fill = [&](uint64_t off, uint32_t fan_in, uint32_t fan_out, uint64_t stream) {
-    const double a = std::sqrt(6.0 / (fan_in + fan_out));
-    for (uint64_t i = 0; i < static_cast<uint64_t>(fan_in) * fan_out; ++i)
-      p[off + i] = static_cast<float>((2.0 * unit(cfg->seed + stream, i) - 1.0) * a);
-  };
-  fill(e->oW1, e->F, H, 1);
-  fill(e->oW2, H, H, 2);
-  int rc = mdrq_estimator_set_params(e, p.data());
-  if (rc) return cleanup(rc);
-  *out = e;
-  return MDRQ_OK;
+    // Glorot-uniform hidden weights; zero output layer, so that an untrained network
+    // returns the base (histogram independence) estimate; zero biases and moments.
+    std::vector<float> p(e->n_params, 0.0f);
+    auto fill = [&](uint64_t off, uint32_t fan_in, uint32_t fan_out, uint64_t stream) {
+      const double a = std::sqrt(6.0 / (fan_in + fan_out));
+      for (uint64_t i = 0; i < static_cast<uint64_t>(fan_in) * fan_out; ++i)
+        p[off + i] = static_cast<float>((2.0 * unit(cfg->seed + stream, i) - 1.0) * a);
+    };
+    fill(e->oW1, e->F, H, 1);
+    fill(e->oW2, H, H, 2);
+    int rc = mdrq_estimator_set_params(e, p.data());
+    if (rc) return cleanup(rc);
+    *out = e;
+    return MDRQ_OK;
+  });
 }
 
 void mdrq_estimator_free(mdrq_estimator* e) {
@@ -619,19 +621,21 @@ int mdrq_estimator_histograms(const mdrq_estimator* e, float* bounds) {
 }
 
 int mdrq_estimator_features(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, uint16_t* out) {
-  clear_error();
-  if (!e || !out) return fail(MDRQ_EINVAL, "NULL argument");
-  int rc = check_queries(e, qs, n);
-  if (rc) return rc;
-  std::lock_guard<std::mutex> lock(e->mu);
-  const DataLayout dl = data_layout(e, n, false);
-  rc = e->data.grow(dl.end);
-  if (rc) return rc;
-  rc = upload_queries(e, qs, n, dl);
-  if (rc) return rc;
-  EST_CHECK(hipMemcpy(out, e->data.as<uint16_t>(dl.X), static_cast<uint64_t>(n) * e->F * 2, hipMemcpyDeviceToHost),
-            "estimator feature download");
-  return MDRQ_OK;
+  return guarded([&]() -> int {
+    clear_error();
+    if (!e || !out) return fail(MDRQ_EINVAL, "NULL argument");
+    int rc = check_queries(e, qs, n);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(e->mu);
+    const DataLayout dl = data_layout(e, n, false);
+    rc = e->data.grow(dl.end);
+    if (rc) return rc;
+    rc = upload_queries(e, qs, n, dl);
+    if (rc) return rc;
+    EST_CHECK(hipMemcpy(out, e->data.as<uint16_t>(dl.X), static_cast<uint64_t>(n) * e->F * 2, hipMemcpyDeviceToHost),
+              "estimator feature download");
+    return MDRQ_OK;
+  });
 }
 
 int mdrq_estimator_param_count(const mdrq_estimator* e, uint64_t* count) {
@@ -664,162 +668,170 @@ int mdrq_estimator_set_params(mdrq_estimator* e, const float* in) {
 }
 
 int mdrq_label_selectivities(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, float* sel) {
-  clear_error();
-  if (!ds || !qs || !sel) return fail(MDRQ_EINVAL, "NULL argument");
-  if (n == 0 || n > MDRQ_EST_MAX_QUERIES) return fail(MDRQ_EINVAL, "query count out of range");
-  for (uint32_t i = 0; i < n; ++i) {
-    int rc = check_query(ds, &qs[i]);
-    if (rc) return rc;
-  }
-  const uint32_t O = ds->n_dims + 1;
-  const double N = static_cast<double>(ds->n_rows);
-  // Every restricting predicate alone: counted from sorted copies of the columns.
-  std::vector<mdrq_pred> singles;
-  std::vector<std::pair<uint32_t, uint32_t>> single_where;  // (query, dimension)
-  for (uint32_t i = 0; i < n; ++i) {
-    float* row = sel + static_cast<size_t>(i) * O;
-    for (uint32_t j = 0; j < O; ++j) row[j] = -1.0f;
-    for (uint32_t k = 0; k < qs[i].n_preds; ++k)
-      if (restricts(qs[i].preds[k])) {
-        singles.push_back(qs[i].preds[k]);
-        single_where.emplace_back(i, qs[i].preds[k].dim);
-      }
-  }
-  std::lock_guard<std::mutex> lock(ds->mu);
-  std::vector<uint64_t> single_counts;
-  int rc = count_single_predicates(ds, singles, single_counts);
-  if (rc != MDRQ_OK) return rc;
-  for (size_t k = 0; k < singles.size(); ++k)
-    sel[static_cast<size_t>(single_where[k].first) * O + single_where[k].second] =
-        static_cast<float>(static_cast<double>(single_counts[k]) / N);
-  // The whole queries: shared count-only scans.
-  std::vector<mdrq_query_t> ex(n);
-  for (uint32_t i = 0; i < n; ++i) ex[i] = mdrq_query_t{qs[i].preds, qs[i].n_preds, 0};
-  std::vector<mdrq_result_t> rs(MDRQ_MAX_BATCH);
-  for (uint32_t at = 0; at < n; at += MDRQ_MAX_BATCH) {
-    const uint32_t m = std::min<uint32_t>(MDRQ_MAX_BATCH, n - at);
-    for (uint32_t i = 0; i < m; ++i) rs[i] = mdrq_result_t{MDRQ_OUT_COUNT, MDRQ_MEM_HOST, nullptr, 0, 0, 0, 0, 0};
-    rc = run_batch(ds, ex.data() + at, m, rs.data(), nullptr);
+  return guarded([&]() -> int {
+    clear_error();
+    if (!ds || !qs || !sel) return fail(MDRQ_EINVAL, "NULL argument");
+    if (n == 0 || n > MDRQ_EST_MAX_QUERIES) return fail(MDRQ_EINVAL, "query count out of range");
+    for (uint32_t i = 0; i < n; ++i) {
+      int rc = check_query(ds, &qs[i]);
+      if (rc) return rc;
+    }
+    const uint32_t O = ds->n_dims + 1;
+    const double N = static_cast<double>(ds->n_rows);
+    // Every restricting predicate alone: counted from sorted copies of the columns.
+    std::vector<mdrq_pred> singles;
+    std::vector<std::pair<uint32_t, uint32_t>> single_where;  // (query, dimension)
+    for (uint32_t i = 0; i < n; ++i) {
+      float* row = sel + static_cast<size_t>(i) * O;
+      for (uint32_t j = 0; j < O; ++j) row[j] = -1.0f;
+      for (uint32_t k = 0; k < qs[i].n_preds; ++k)
+        if (restricts(qs[i].preds[k])) {
+          singles.push_back(qs[i].preds[k]);
+          single_where.emplace_back(i, qs[i].preds[k].dim);
+        }
+    }
+    std::lock_guard<std::mutex> lock(ds->mu);
+    std::vector<uint64_t> single_counts;
+    int rc = count_single_predicates(ds, singles, single_counts);
     if (rc != MDRQ_OK) return rc;
-    for (uint32_t i = 0; i < m; ++i)
-      sel[static_cast<size_t>(at + i) * O + ds->n_dims] = static_cast<float>(static_cast<double>(rs[i].count) / N);
-  }
-  return MDRQ_OK;
+    for (size_t k = 0; k < singles.size(); ++k)
+      sel[static_cast<size_t>(single_where[k].first) * O + single_where[k].second] =
+          static_cast<float>(static_cast<double>(single_counts[k]) / N);
+    // The whole queries: shared count-only scans.
+    std::vector<mdrq_query_t> ex(n);
+    for (uint32_t i = 0; i < n; ++i) ex[i] = mdrq_query_t{qs[i].preds, qs[i].n_preds, 0};
+    std::vector<mdrq_result_t> rs(MDRQ_MAX_BATCH);
+    for (uint32_t at = 0; at < n; at += MDRQ_MAX_BATCH) {
+      const uint32_t m = std::min<uint32_t>(MDRQ_MAX_BATCH, n - at);
+      for (uint32_t i = 0; i < m; ++i) rs[i] = mdrq_result_t{MDRQ_OUT_COUNT, MDRQ_MEM_HOST, nullptr, 0, 0, 0, 0, 0};
+      rc = run_batch(ds, ex.data() + at, m, rs.data(), nullptr);
+      if (rc != MDRQ_OK) return rc;
+      for (uint32_t i = 0; i < m; ++i)
+        sel[static_cast<size_t>(at + i) * O + ds->n_dims] = static_cast<float>(static_cast<double>(rs[i].count) / N);
+    }
+    return MDRQ_OK;
+  });
 }
 
 int mdrq_estimator_gradient(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, const float* sel,
                             float* loss, float* grad) {
-  clear_error();
-  if (!e || !loss || !grad) return fail(MDRQ_EINVAL, "NULL argument");
-  if (n > kMaxTrainBatch) return fail(MDRQ_EINVAL, "at most 65536 queries per gradient");
-  int rc = check_queries(e, qs, n);
-  if (rc) return rc;
-  std::vector<uint32_t> present;
-  rc = check_labels(e, sel, n, present);
-  if (rc) return rc;
-  std::lock_guard<std::mutex> lock(e->mu);
-  const DataLayout dl = data_layout(e, n, true);
-  if ((rc = e->data.grow(dl.end)) || (rc = e->ensure_work(n)) || (rc = e->losses.grow(4))) return rc;
-  rc = upload_queries(e, qs, n, dl);
-  if (rc) return rc;
-  rc = upload_targets(e, sel, n, dl);
-  if (rc) return rc;
-  const auto L = e->layout(e->work_rows);
-  EST_CHECK(hipMemcpy(e->work.as<char>(L.X), e->data.as<char>(dl.X), static_cast<uint64_t>(n) * e->F * 2,
-                      hipMemcpyDeviceToDevice), "estimator copy");
-  EST_CHECK(hipMemcpy(e->work.as<char>(L.Bs), e->data.as<char>(dl.base), static_cast<uint64_t>(n) * e->O * 4,
-                      hipMemcpyDeviceToDevice), "estimator copy");
-  EST_CHECK(hipMemcpy(e->work.as<char>(L.T), e->data.as<char>(dl.T), static_cast<uint64_t>(n) * e->O * 4,
-                      hipMemcpyDeviceToDevice), "estimator copy");
-  EST_CHECK(hipMemcpy(e->work.as<char>(L.M), e->data.as<char>(dl.M), static_cast<uint64_t>(n) * e->O * 4,
-                      hipMemcpyDeviceToDevice), "estimator copy");
-  EST_CHECK(hipMemset(e->losses.p, 0, 4), "estimator loss clear");
-  uint64_t cnt = 0;
-  for (uint32_t c : present) cnt += c;
-  rc = forward(e, n);
-  if (rc) return rc;
-  rc = backward(e, n, static_cast<float>(1.0 / static_cast<double>(cnt)), e->losses.as<float>());
-  if (rc) return rc;
-  EST_CHECK(hipMemcpy(grad, e->grads(), e->n_params * 4, hipMemcpyDeviceToHost), "estimator gradient download");
-  EST_CHECK(hipMemcpy(loss, e->losses.p, 4, hipMemcpyDeviceToHost), "estimator loss download");
-  return MDRQ_OK;
+  return guarded([&]() -> int {
+    clear_error();
+    if (!e || !loss || !grad) return fail(MDRQ_EINVAL, "NULL argument");
+    if (n > kMaxTrainBatch) return fail(MDRQ_EINVAL, "at most 65536 queries per gradient");
+    int rc = check_queries(e, qs, n);
+    if (rc) return rc;
+    std::vector<uint32_t> present;
+    rc = check_labels(e, sel, n, present);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(e->mu);
+    const DataLayout dl = data_layout(e, n, true);
+    if ((rc = e->data.grow(dl.end)) || (rc = e->ensure_work(n)) || (rc = e->losses.grow(4))) return rc;
+    rc = upload_queries(e, qs, n, dl);
+    if (rc) return rc;
+    rc = upload_targets(e, sel, n, dl);
+    if (rc) return rc;
+    const auto L = e->layout(e->work_rows);
+    EST_CHECK(hipMemcpy(e->work.as<char>(L.X), e->data.as<char>(dl.X), static_cast<uint64_t>(n) * e->F * 2,
+                        hipMemcpyDeviceToDevice), "estimator copy");
+    EST_CHECK(hipMemcpy(e->work.as<char>(L.Bs), e->data.as<char>(dl.base), static_cast<uint64_t>(n) * e->O * 4,
+                        hipMemcpyDeviceToDevice), "estimator copy");
+    EST_CHECK(hipMemcpy(e->work.as<char>(L.T), e->data.as<char>(dl.T), static_cast<uint64_t>(n) * e->O * 4,
+                        hipMemcpyDeviceToDevice), "estimator copy");
+    EST_CHECK(hipMemcpy(e->work.as<char>(L.M), e->data.as<char>(dl.M), static_cast<uint64_t>(n) * e->O * 4,
+                        hipMemcpyDeviceToDevice), "estimator copy");
+    EST_CHECK(hipMemset(e->losses.p, 0, 4), "estimator loss clear");
+    uint64_t cnt = 0;
+    for (uint32_t c : present) cnt += c;
+    rc = forward(e, n);
+    if (rc) return rc;
+    rc = backward(e, n, static_cast<float>(1.0 / static_cast<double>(cnt)), e->losses.as<float>());
+    if (rc) return rc;
+    EST_CHECK(hipMemcpy(grad, e->grads(), e->n_params * 4, hipMemcpyDeviceToHost), "estimator gradient download");
+    EST_CHECK(hipMemcpy(loss, e->losses.p, 4, hipMemcpyDeviceToHost), "estimator loss download");
+    return MDRQ_OK;
+  });
 }
 
 int mdrq_estimator_train(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, const float* sel,
                          const mdrq_train_config_t* cfg, float* epoch_loss) {
-  clear_error();
-  if (!e || !cfg) return fail(MDRQ_EINVAL, "NULL argument");
-  if (cfg->epochs == 0 || cfg->epochs > 100000) return fail(MDRQ_EINVAL, "epochs out of range");
-  if (cfg->batch == 0 || cfg->batch > kMaxTrainBatch) return fail(MDRQ_EINVAL, "batch out of range");
-  if (!(cfg->lr > 0.0f) || !std::isfinite(cfg->lr)) return fail(MDRQ_EINVAL, "learning rate must be positive");
-  int rc = check_queries(e, qs, n);
-  if (rc) return rc;
-  std::vector<uint32_t> present;
-  rc = check_labels(e, sel, n, present);
-  if (rc) return rc;
-  std::lock_guard<std::mutex> lock(e->mu);
-  const uint32_t B = std::min(cfg->batch, n);
-  const DataLayout dl = data_layout(e, n, true);
-  if ((rc = e->data.grow(dl.end)) || (rc = e->ensure_work(B)) ||
-      (rc = e->losses.grow(static_cast<uint64_t>(cfg->epochs) * 4)))
-    return rc;
-  rc = upload_queries(e, qs, n, dl);
-  if (rc) return rc;
-  rc = upload_targets(e, sel, n, dl);
-  if (rc) return rc;
-  EST_CHECK(hipMemset(e->losses.p, 0, static_cast<uint64_t>(cfg->epochs) * 4), "estimator loss clear");
-  const auto L = e->layout(e->work_rows);
-  std::vector<uint32_t> perm(n);
-  const uint32_t steps = (n + B - 1) / B;
-  for (uint32_t ep = 0; ep < cfg->epochs; ++ep) {
-    // Fisher-Yates shuffle from the counter-based generator.
-    for (uint32_t i = 0; i < n; ++i) perm[i] = i;
-    for (uint32_t i = n; i > 1; --i) {
-      const uint64_t r = splitmix(cfg->seed ^ splitmix((static_cast<uint64_t>(ep) << 32) | i));
-      const uint32_t j = static_cast<uint32_t>(r % i);
-      std::swap(perm[i - 1], perm[j]);
+  return guarded([&]() -> int {
+    clear_error();
+    if (!e || !cfg) return fail(MDRQ_EINVAL, "NULL argument");
+    if (cfg->epochs == 0 || cfg->epochs > 100000) return fail(MDRQ_EINVAL, "epochs out of range");
+    if (cfg->batch == 0 || cfg->batch > kMaxTrainBatch) return fail(MDRQ_EINVAL, "batch out of range");
+    if (!(cfg->lr > 0.0f) || !std::isfinite(cfg->lr)) return fail(MDRQ_EINVAL, "learning rate must be positive");
+    int rc = check_queries(e, qs, n);
+    if (rc) return rc;
+    std::vector<uint32_t> present;
+    rc = check_labels(e, sel, n, present);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(e->mu);
+    const uint32_t B = std::min(cfg->batch, n);
+    const DataLayout dl = data_layout(e, n, true);
+    if ((rc = e->data.grow(dl.end)) || (rc = e->ensure_work(B)) ||
+        (rc = e->losses.grow(static_cast<uint64_t>(cfg->epochs) * 4)))
+      return rc;
+    rc = upload_queries(e, qs, n, dl);
+    if (rc) return rc;
+    rc = upload_targets(e, sel, n, dl);
+    if (rc) return rc;
+    EST_CHECK(hipMemset(e->losses.p, 0, static_cast<uint64_t>(cfg->epochs) * 4), "estimator loss clear");
+    const auto L = e->layout(e->work_rows);
+    std::vector<uint32_t> perm(n);
+    const uint32_t steps = (n + B - 1) / B;
+    for (uint32_t ep = 0; ep < cfg->epochs; ++ep) {
+      // Fisher-Yates shuffle from the counter-based generator.
+      for (uint32_t i = 0; i < n; ++i) perm[i] = i;
+      for (uint32_t i = n; i > 1; --i) {
+        const uint64_t r = splitmix(cfg->seed ^ splitmix((static_cast<uint64_t>(ep) << 32) | i));
+        const uint32_t j = static_cast<uint32_t>(r % i);
+        std::swap(perm[i - 1], perm[j]);
+      }
+      EST_CHECK(hipMemcpy(e->data.as<uint32_t>(dl.perm), perm.data(), static_cast<uint64_t>(n) * 4,
+                          hipMemcpyHostToDevice), "estimator permutation upload");
+      for (uint32_t s = 0; s < steps; ++s) {
+        const uint32_t at = s * B;
+        const uint32_t rows = std::min(B, n - at);
+        const uint32_t* idx = e->data.as<uint32_t>(dl.perm) + at;
+        uint64_t cnt = 0;
+        for (uint32_t i = 0; i < rows; ++i) cnt += present[perm[at + i]];
+        EST_CHECK(launch_gather_rows(e->data.as<void>(dl.X), idx, rows, e->F * 2, e->work.as<void>(L.X), nullptr),
+                  "estimator gather");
+        EST_CHECK(launch_gather_rows(e->data.as<void>(dl.base), idx, rows, e->O * 4, e->work.as<void>(L.Bs), nullptr),
+                  "estimator gather");
+        EST_CHECK(launch_gather_rows(e->data.as<void>(dl.T), idx, rows, e->O * 4, e->work.as<void>(L.T), nullptr),
+                  "estimator gather");
+        EST_CHECK(launch_gather_rows(e->data.as<void>(dl.M), idx, rows, e->O * 4, e->work.as<void>(L.M), nullptr),
+                  "estimator gather");
+        rc = forward(e, rows);
+        if (rc) return rc;
+        rc = backward(e, rows, static_cast<float>(1.0 / static_cast<double>(cnt)), e->losses.as<float>() + ep);
+        if (rc) return rc;
+        e->step += 1;
+        EST_CHECK(launch_adam(e->params(), e->grads(), e->adam_m(), e->adam_v(), e->n_params, cfg->lr, e->step,
+                              nullptr), "estimator Adam");
+        rc = refresh_bf16(e);
+        if (rc) return rc;
+      }
     }
-    EST_CHECK(hipMemcpy(e->data.as<uint32_t>(dl.perm), perm.data(), static_cast<uint64_t>(n) * 4,
-                        hipMemcpyHostToDevice), "estimator permutation upload");
-    for (uint32_t s = 0; s < steps; ++s) {
-      const uint32_t at = s * B;
-      const uint32_t rows = std::min(B, n - at);
-      const uint32_t* idx = e->data.as<uint32_t>(dl.perm) + at;
-      uint64_t cnt = 0;
-      for (uint32_t i = 0; i < rows; ++i) cnt += present[perm[at + i]];
-      EST_CHECK(launch_gather_rows(e->data.as<void>(dl.X), idx, rows, e->F * 2, e->work.as<void>(L.X), nullptr),
-                "estimator gather");
-      EST_CHECK(launch_gather_rows(e->data.as<void>(dl.base), idx, rows, e->O * 4, e->work.as<void>(L.Bs), nullptr),
-                "estimator gather");
-      EST_CHECK(launch_gather_rows(e->data.as<void>(dl.T), idx, rows, e->O * 4, e->work.as<void>(L.T), nullptr),
-                "estimator gather");
-      EST_CHECK(launch_gather_rows(e->data.as<void>(dl.M), idx, rows, e->O * 4, e->work.as<void>(L.M), nullptr),
-                "estimator gather");
-      rc = forward(e, rows);
-      if (rc) return rc;
-      rc = backward(e, rows, static_cast<float>(1.0 / static_cast<double>(cnt)), e->losses.as<float>() + ep);
-      if (rc) return rc;
-      e->step += 1;
-      EST_CHECK(launch_adam(e->params(), e->grads(), e->adam_m(), e->adam_v(), e->n_params, cfg->lr, e->step,
-                            nullptr), "estimator Adam");
-      rc = refresh_bf16(e);
-      if (rc) return rc;
-    }
-  }
-  std::vector<float> sums(cfg->epochs);
-  EST_CHECK(hipMemcpy(sums.data(), e->losses.p, sums.size() * 4, hipMemcpyDeviceToHost), "estimator loss download");
-  if (epoch_loss)
-    for (uint32_t ep = 0; ep < cfg->epochs; ++ep) epoch_loss[ep] = sums[ep] / static_cast<float>(steps);
-  return MDRQ_OK;
+    std::vector<float> sums(cfg->epochs);
+    EST_CHECK(hipMemcpy(sums.data(), e->losses.p, sums.size() * 4, hipMemcpyDeviceToHost), "estimator loss download");
+    if (epoch_loss)
+      for (uint32_t ep = 0; ep < cfg->epochs; ++ep) epoch_loss[ep] = sums[ep] / static_cast<float>(steps);
+    return MDRQ_OK;
+  });
 }
 
 int mdrq_estimator_predict(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, float* sel) {
-  clear_error();
-  if (!e || !sel) return fail(MDRQ_EINVAL, "NULL argument");
-  int rc = check_queries(e, qs, n);
-  if (rc) return rc;
-  std::lock_guard<std::mutex> lock(e->mu);
-  return n == 1 ? predict_one(e, qs, sel) : predict_locked(e, qs, n, sel);
+  return guarded([&]() -> int {
+    clear_error();
+    if (!e || !sel) return fail(MDRQ_EINVAL, "NULL argument");
+    int rc = check_queries(e, qs, n);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(e->mu);
+    return n == 1 ? predict_one(e, qs, sel) : predict_locked(e, qs, n, sel);
+  });
 }
 
 int mdrq_attach_estimator(mdrq_dataset* ds, mdrq_estimator* e) {

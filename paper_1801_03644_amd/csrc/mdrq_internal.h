@@ -5,6 +5,8 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <exception>
+#include <new>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -260,6 +262,21 @@ struct Plan {
 int fail(int code, const std::string& msg);
 int fail_hip(hipError_t e, const char* what);
 void clear_error();
+
+// Body of a C entry point: a C++ exception (a failed host allocation) becomes a status
+// instead of crossing the C boundary.
+template <typename F>
+int guarded(F&& body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail(MDRQ_ENOMEM, "host memory allocation failed");
+  } catch (const std::exception& e) {
+    return fail(MDRQ_EDEVICE, std::string("unexpected host error: ") + e.what());
+  } catch (...) {
+    return fail(MDRQ_EDEVICE, "unexpected host error");
+  }
+}
 
 struct Device {
   int id = 0;

@@ -153,4 +153,70 @@ inline RankBuckets rank_buckets(const std::vector<uint32_t>& ends, int mode, uin
   return rb;
 }
 
+inline uint64_t align4(uint64_t x) { return (x + 3) & ~uint64_t{3}; }
+
+// Words one column's tables take in a group's LDS image (see append_slot_tables).
+inline uint64_t slot_table_words(uint32_t M, const RankBuckets& rb, uint32_t sw) {
+  return rb.nb / 2 + align4(M + (uint64_t{1} << rb.d) - 1) + align4(uint64_t{M + 1} * sw);
+}
+
+// Upper bound of slot_table_words over every set of at most max_ends distinct ends and
+// every bucket map of at most nb buckets.  A map's steps d are the fewest with
+// 2^d - 1 >= its fullest bucket, so 2^(d-1) <= fullest <= max_ends and the padding
+// 2^d - 1 is below 2 max_ends: ends and padding take less than 3 max_ends words.
+inline uint64_t slot_table_words_bound(uint32_t max_ends, uint32_t nb, uint32_t sw) {
+  return nb / 2 + align4(3 * uint64_t{max_ends}) + align4(uint64_t{max_ends + 1} * sw);
+}
+
+// One query's interval on a column as order-preserving keys; has = false: the query
+// does not restrict the column and passes at every rank.
+struct KeyInterval {
+  uint32_t klo = 0, khi = 0;
+  bool has = false;
+};
+
+// Append one column's tables to a group's words g (whose size is 4-word aligned on
+// entry and stays so): the nb 16-bit bucket starts, the M sorted distinct ends padded
+// with 2^d - 1 words 0xFFFFFFFF (the farthest entry a search within a bucket reads),
+// then the (M + 1) x sw table of query bitsets by rank.  Query q of qs passes at rank r
+// (r ends <= the row's key) iff idx(klo) < r <= idx(khi + 1); its bit is toggled on at
+// idx(klo) + 1 and off at idx(khi + 1) + 1, and a running XOR over the ranks fills the
+// rows.  Returns the offset of the ends in g (the column header's first word).
+inline uint32_t append_slot_tables(std::vector<uint32_t>& g, const std::vector<uint32_t>& ends,
+                                   const RankBuckets& rb, const std::vector<KeyInterval>& qs,
+                                   uint32_t sw) {
+  const uint32_t M = static_cast<uint32_t>(ends.size());
+  const size_t s0 = g.size();
+  g.resize(s0 + rb.nb / 2, 0u);
+  for (uint32_t b = 0; b < rb.nb; ++b) g[s0 + b / 2] |= static_cast<uint32_t>(rb.starts[b]) << (16 * (b % 2));
+  const uint32_t at = static_cast<uint32_t>(g.size());
+  g.insert(g.end(), ends.begin(), ends.end());
+  g.resize(g.size() + ((size_t{1} << rb.d) - 1), 0xFFFFFFFFu);
+  g.resize(align4(g.size()), 0u);
+  const size_t t0 = g.size();
+  g.resize(t0 + static_cast<size_t>(M + 1) * sw, 0u);
+  std::vector<uint32_t> toggle(static_cast<size_t>(M + 2) * sw, 0u), always(sw, 0u);
+  for (size_t q = 0; q < qs.size(); ++q) {
+    const uint32_t w = static_cast<uint32_t>(q / 32), m = 1u << (q % 32);
+    if (!qs[q].has) {
+      always[w] |= m;
+      continue;
+    }
+    const uint32_t r_lo = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), qs[q].klo) - ends.begin());
+    const uint32_t r_hi = static_cast<uint32_t>(std::lower_bound(ends.begin(), ends.end(), qs[q].khi + 1) - ends.begin());
+    if (r_lo >= r_hi) continue;  // an empty interval passes nowhere
+    toggle[static_cast<size_t>(r_lo + 1) * sw + w] ^= m;
+    toggle[static_cast<size_t>(r_hi + 1) * sw + w] ^= m;
+  }
+  for (uint32_t w = 0; w < sw; ++w) {
+    uint32_t cur = 0;
+    for (uint32_t r = 0; r <= M; ++r) {
+      cur ^= toggle[static_cast<size_t>(r) * sw + w];
+      g[t0 + static_cast<size_t>(r) * sw + w] = cur | always[w];
+    }
+  }
+  g.resize(align4(g.size()), 0u);
+  return at;
+}
+
 }  // namespace mdrq

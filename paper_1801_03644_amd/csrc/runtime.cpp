@@ -305,115 +305,119 @@ extern "C" {
 
 int mdrq_load_columns(const float* const* cols, uint32_t n_dims, uint64_t n_rows, uint32_t flags,
                       void* stream_, mdrq_dataset** out) {
-  clear_error();
-  if (!out) return fail(MDRQ_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!cols) return fail(MDRQ_EINVAL, "cols is NULL");
-  if (n_dims == 0 || n_dims > MDRQ_MAX_DIMS) return fail(MDRQ_EINVAL, "n_dims must be 1..128");
-  if (n_rows > kMaxRows) return fail(MDRQ_EINVAL, "n_rows exceeds 2^32 - 1");
-  const bool dev_in = flags & MDRQ_MEM_DEVICE;
-  const bool borrow = flags & MDRQ_BORROW;
-  if (flags & ~static_cast<uint32_t>(MDRQ_MEM_DEVICE | MDRQ_BORROW))
-    return fail(MDRQ_EINVAL, "unknown load flags");
-  if (borrow && !dev_in) return fail(MDRQ_EINVAL, "MDRQ_BORROW requires MDRQ_MEM_DEVICE");
-  for (uint32_t j = 0; j < n_dims; ++j) {
-    if (!cols[j] && n_rows > 0) return fail(MDRQ_EINVAL, "column pointer is NULL");
-    if (borrow && (reinterpret_cast<uintptr_t>(cols[j]) & 15u))
-      return fail(MDRQ_EINVAL, "borrowed column is not 16-byte aligned");
-  }
-  hipStream_t stream = static_cast<hipStream_t>(stream_);
-  mdrq_dataset* ds = new mdrq_dataset();
-  ds->n_rows = n_rows;
-  ds->n_dims = n_dims;
-  ds->owned = !borrow;
-  ds->cols.resize(n_dims);
-  int rc = MDRQ_OK;
-  ColumnStats* st_dev = nullptr;
-  ColumnStats st_host{};
-  if (borrow) {
-    for (uint32_t j = 0; j < n_dims; ++j) ds->cols[j] = cols[j];
-  } else {
-    ds->stride = (n_rows + 63) / 64 * 64;
-    const uint64_t bytes = std::max<uint64_t>(1, ds->stride * n_dims * sizeof(float));
-    if (hipMalloc(reinterpret_cast<void**>(&ds->base), bytes) != hipSuccess) {
-      free_dataset(ds);
-      return fail(MDRQ_ENOMEM, "device allocation of the columns failed");
-    }
+  return guarded([&]() -> int {
+    clear_error();
+    if (!out) return fail(MDRQ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cols) return fail(MDRQ_EINVAL, "cols is NULL");
+    if (n_dims == 0 || n_dims > MDRQ_MAX_DIMS) return fail(MDRQ_EINVAL, "n_dims must be 1..128");
+    if (n_rows > kMaxRows) return fail(MDRQ_EINVAL, "n_rows exceeds 2^32 - 1");
+    const bool dev_in = flags & MDRQ_MEM_DEVICE;
+    const bool borrow = flags & MDRQ_BORROW;
+    if (flags & ~static_cast<uint32_t>(MDRQ_MEM_DEVICE | MDRQ_BORROW))
+      return fail(MDRQ_EINVAL, "unknown load flags");
+    if (borrow && !dev_in) return fail(MDRQ_EINVAL, "MDRQ_BORROW requires MDRQ_MEM_DEVICE");
     for (uint32_t j = 0; j < n_dims; ++j) {
-      float* dst = ds->base + ds->stride * j;
-      ds->cols[j] = dst;
-      if (n_rows) {
-        hipError_t e = hipMemcpyAsync(dst, cols[j], n_rows * sizeof(float),
-                                      dev_in ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                                      stream);
-        if (e != hipSuccess) {
-          free_dataset(ds);
-          return fail_hip(e, "column copy");
+      if (!cols[j] && n_rows > 0) return fail(MDRQ_EINVAL, "column pointer is NULL");
+      if (borrow && (reinterpret_cast<uintptr_t>(cols[j]) & 15u))
+        return fail(MDRQ_EINVAL, "borrowed column is not 16-byte aligned");
+    }
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    mdrq_dataset* ds = new mdrq_dataset();
+    ds->n_rows = n_rows;
+    ds->n_dims = n_dims;
+    ds->owned = !borrow;
+    ds->cols.resize(n_dims);
+    int rc = MDRQ_OK;
+    ColumnStats* st_dev = nullptr;
+    ColumnStats st_host{};
+    if (borrow) {
+      for (uint32_t j = 0; j < n_dims; ++j) ds->cols[j] = cols[j];
+    } else {
+      ds->stride = (n_rows + 63) / 64 * 64;
+      const uint64_t bytes = std::max<uint64_t>(1, ds->stride * n_dims * sizeof(float));
+      if (hipMalloc(reinterpret_cast<void**>(&ds->base), bytes) != hipSuccess) {
+        free_dataset(ds);
+        return fail(MDRQ_ENOMEM, "device allocation of the columns failed");
+      }
+      for (uint32_t j = 0; j < n_dims; ++j) {
+        float* dst = ds->base + ds->stride * j;
+        ds->cols[j] = dst;
+        if (n_rows) {
+          hipError_t e = hipMemcpyAsync(dst, cols[j], n_rows * sizeof(float),
+                                        dev_in ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                        stream);
+          if (e != hipSuccess) {
+            free_dataset(ds);
+            return fail_hip(e, "column copy");
+          }
         }
       }
     }
-  }
-  rc = alloc_workspace(ds);
-  if (rc) {
-    free_dataset(ds);
-    return rc;
-  }
-  // Validation on the device: NaN check, min and max per column.
-  st_host.nan_count = 0;
-  for (uint32_t j = 0; j < MDRQ_MAX_DIMS; ++j) {
-    st_host.min_key[j] = 0xFFFFFFFFu;
-    st_host.max_key[j] = 0u;
-  }
-  hipError_t e = hipMalloc(&st_dev, sizeof(ColumnStats));
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(st_dev, &st_host, sizeof(ColumnStats), hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess && n_rows) e = launch_validate(ds->cols.data(), n_dims, n_rows, st_dev, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(&st_host, st_dev, sizeof(ColumnStats), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (st_dev) (void)hipFree(st_dev);
-  if (e != hipSuccess) {
-    free_dataset(ds);
-    return fail_hip(e, "column validation");
-  }
-  if (st_host.nan_count) {
-    free_dataset(ds);
-    return fail(MDRQ_EINVAL, "NaN in the data");
-  }
-  ds->col_min.resize(n_dims);
-  ds->col_max.resize(n_dims);
-  for (uint32_t j = 0; j < n_dims; ++j) {
-    if (n_rows) {
-      ds->col_min[j] = key_to_float(st_host.min_key[j]);
-      ds->col_max[j] = key_to_float(st_host.max_key[j]);
-    } else {
-      ds->col_min[j] = std::numeric_limits<float>::infinity();
-      ds->col_max[j] = -std::numeric_limits<float>::infinity();
+    rc = alloc_workspace(ds);
+    if (rc) {
+      free_dataset(ds);
+      return rc;
     }
-  }
-  *out = ds;
-  return MDRQ_OK;
+    // Validation on the device: NaN check, min and max per column.
+    st_host.nan_count = 0;
+    for (uint32_t j = 0; j < MDRQ_MAX_DIMS; ++j) {
+      st_host.min_key[j] = 0xFFFFFFFFu;
+      st_host.max_key[j] = 0u;
+    }
+    hipError_t e = hipMalloc(&st_dev, sizeof(ColumnStats));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(st_dev, &st_host, sizeof(ColumnStats), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && n_rows) e = launch_validate(ds->cols.data(), n_dims, n_rows, st_dev, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&st_host, st_dev, sizeof(ColumnStats), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (st_dev) (void)hipFree(st_dev);
+    if (e != hipSuccess) {
+      free_dataset(ds);
+      return fail_hip(e, "column validation");
+    }
+    if (st_host.nan_count) {
+      free_dataset(ds);
+      return fail(MDRQ_EINVAL, "NaN in the data");
+    }
+    ds->col_min.resize(n_dims);
+    ds->col_max.resize(n_dims);
+    for (uint32_t j = 0; j < n_dims; ++j) {
+      if (n_rows) {
+        ds->col_min[j] = key_to_float(st_host.min_key[j]);
+        ds->col_max[j] = key_to_float(st_host.max_key[j]);
+      } else {
+        ds->col_min[j] = std::numeric_limits<float>::infinity();
+        ds->col_max[j] = -std::numeric_limits<float>::infinity();
+      }
+    }
+    *out = ds;
+    return MDRQ_OK;
+  });
 }
 
 int mdrq_query(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r, void* stream) {
-  clear_error();
-  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
-  int rc = check_query(ds, q);
-  if (rc) return rc;
-  rc = check_result(r);
-  if (rc) return rc;
-  std::lock_guard<std::mutex> lock(ds->mu);
-  Plan plan = make_plan(ds, q, r);
-  // Estimated order: the estimator's graph ranks the predicates on the device, ahead of
-  // the scan on the same stream (no host round trip); it stays locked until the scan
-  // has completed.
-  std::unique_lock<std::mutex> est_hold;
-  if ((q->flags & MDRQ_Q_ORDER_ESTIMATED) && !plan.empty) {
-    rc = order_on_device(ds, q, plan, static_cast<hipStream_t>(stream), est_hold);
+  return guarded([&]() -> int {
+    clear_error();
+    if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+    int rc = check_query(ds, q);
     if (rc) return rc;
-  }
-  r->mode = plan.mode == kBitmap ? MDRQ_OUT_BITMAP : plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
-  return run_query(ds, plan, r, static_cast<hipStream_t>(stream));
+    rc = check_result(r);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(ds->mu);
+    Plan plan = make_plan(ds, q, r);
+    // Estimated order: the estimator's graph ranks the predicates on the device, ahead of
+    // the scan on the same stream (no host round trip); it stays locked until the scan
+    // has completed.
+    std::unique_lock<std::mutex> est_hold;
+    if ((q->flags & MDRQ_Q_ORDER_ESTIMATED) && !plan.empty) {
+      rc = order_on_device(ds, q, plan, static_cast<hipStream_t>(stream), est_hold);
+      if (rc) return rc;
+    }
+    r->mode = plan.mode == kBitmap ? MDRQ_OUT_BITMAP : plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
+    return run_query(ds, plan, r, static_cast<hipStream_t>(stream));
+  });
 }
 
 void mdrq_free(mdrq_dataset* ds) {
@@ -559,22 +563,24 @@ const char* mdrq_version(void) { return "0.1.0"; }
 
 int mdrq_query_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n_queries,
                      mdrq_result_t* rs, void* stream) {
-  clear_error();
-  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
-  if (!qs || !rs) return fail(MDRQ_EINVAL, "queries or results is NULL");
-  if (n_queries == 0 || n_queries > MDRQ_MAX_BATCH)
-    return fail(MDRQ_EINVAL, "n_queries must be 1..MDRQ_MAX_BATCH");
-  for (uint32_t i = 0; i < n_queries; ++i) {
-    int rc = check_query(ds, &qs[i]);
-    if (!rc) rc = check_result(&rs[i]);
-    if (rc) return fail(rc, "query " + std::to_string(i) + ": " + mdrq_last_error());
-  }
-  std::lock_guard<std::mutex> lock(ds->mu);
-  int rc = run_batch(ds, qs, n_queries, rs, static_cast<hipStream_t>(stream));
-  if (rc) return rc;
-  for (uint32_t i = 0; i < n_queries; ++i)
-    if (rs[i].status == MDRQ_EOVERFLOW) return MDRQ_EOVERFLOW;
-  return MDRQ_OK;
+  return guarded([&]() -> int {
+    clear_error();
+    if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+    if (!qs || !rs) return fail(MDRQ_EINVAL, "queries or results is NULL");
+    if (n_queries == 0 || n_queries > MDRQ_MAX_BATCH)
+      return fail(MDRQ_EINVAL, "n_queries must be 1..MDRQ_MAX_BATCH");
+    for (uint32_t i = 0; i < n_queries; ++i) {
+      int rc = check_query(ds, &qs[i]);
+      if (!rc) rc = check_result(&rs[i]);
+      if (rc) return fail(rc, "query " + std::to_string(i) + ": " + mdrq_last_error());
+    }
+    std::lock_guard<std::mutex> lock(ds->mu);
+    int rc = run_batch(ds, qs, n_queries, rs, static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+    for (uint32_t i = 0; i < n_queries; ++i)
+      if (rs[i].status == MDRQ_EOVERFLOW) return MDRQ_EOVERFLOW;
+    return MDRQ_OK;
+  });
 }
 
 int mdrq_get_batch_profile(const mdrq_dataset* ds, uint64_t* scans, double* ms) {

@@ -28,13 +28,17 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// One queued request: a private copy of the query, the caller's result record.
+// One queued request: a private copy of the query, the caller's result record, and an
+// event recorded on the caller's stream at submission (null for the replay): the
+// worker's stream waits for it, so the scan writes the result buffer only after the
+// work the caller queued before submitting.
 struct Pending {
   uint64_t ticket = 0;
   mdrq_query_t q{};
   std::vector<mdrq_pred> preds;
   mdrq_result_t* r = nullptr;
   Clock::time_point arrival;
+  hipEvent_t ready = nullptr;
 };
 
 struct Worker {
@@ -72,6 +76,7 @@ struct mdrq_server {
   BatchRunStats st;
   uint64_t batches = 0;
   bool overflow = false;
+  std::vector<hipEvent_t> free_events;  // submission events for reuse (mu)
 };
 
 namespace {
@@ -90,13 +95,24 @@ void worker_loop(mdrq_server* s, Worker* w) {
     }
     qs.clear();
     out.clear();
+    int rc = MDRQ_OK;
     for (Pending* p : batch) {
       qs.push_back(p->q);
       out.push_back(*p->r);
+      if (p->ready && rc == MDRQ_OK) {
+        const hipError_t e = hipStreamWaitEvent(w->stream, p->ready, 0);
+        if (e != hipSuccess) rc = fail_hip(e, "serving: wait for the submitting stream");
+      }
     }
     BatchRunStats st;
-    int rc = run_batch(s->ds, qs.data(), static_cast<uint32_t>(qs.size()), out.data(), w->stream,
+    if (rc == MDRQ_OK) {
+      try {
+        rc = run_batch(s->ds, qs.data(), static_cast<uint32_t>(qs.size()), out.data(), w->stream,
                        &w->ws, false, &st);
+      } catch (...) {
+        rc = fail(MDRQ_ENOMEM, "serving: host memory");
+      }
+    }
     const Clock::time_point t = Clock::now();
     std::string msg = rc ? mdrq_last_error() : "";
     std::lock_guard<std::mutex> lk(s->mu);
@@ -113,6 +129,7 @@ void worker_loop(mdrq_server* s, Worker* w) {
       s->lat_ns[p->ticket] = static_cast<uint64_t>(
           std::max<int64_t>(0, std::chrono::duration_cast<std::chrono::nanoseconds>(t - p->arrival).count()));
       s->done.push_back(p->ticket);
+      if (p->ready) s->free_events.push_back(p->ready);
       delete p;
     }
     s->completed += batch.size();
@@ -185,7 +202,11 @@ void destroy(mdrq_server* s) {
     free_batch(w.ws);
     if (w.stream) (void)hipStreamDestroy(w.stream);
   }
-  for (Pending* p : s->ready) delete p;
+  for (Pending* p : s->ready) {
+    if (p->ready) (void)hipEventDestroy(p->ready);
+    delete p;
+  }
+  for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
   delete s;
 }
 
@@ -218,8 +239,9 @@ int create(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, bool reserve_rows, 
 }
 
 // Queue one request (caller holds no lock).  arrival: the time its latency counts from.
+// order: record an event on `stream` that the request's scan waits for.
 int enqueue(mdrq_server* s, const mdrq_query_t* q, mdrq_result_t* r, Clock::time_point arrival,
-            bool bounded, uint64_t* ticket) {
+            bool bounded, bool order, hipStream_t stream, uint64_t* ticket) {
   Pending* p = new Pending();
   p->q = *q;
   p->preds.assign(q->preds, q->preds + q->n_preds);
@@ -227,19 +249,32 @@ int enqueue(mdrq_server* s, const mdrq_query_t* q, mdrq_result_t* r, Clock::time
   if (s->cfg.use_estimator) p->q.flags |= MDRQ_Q_ORDER_ESTIMATED;
   p->r = r;
   p->arrival = arrival;
+  if (order) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (!s->free_events.empty()) {
+        p->ready = s->free_events.back();
+        s->free_events.pop_back();
+      }
+    }
+    hipError_t e = p->ready ? hipSuccess : hipEventCreateWithFlags(&p->ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(p->ready, stream);
+    if (e != hipSuccess) {
+      if (p->ready) (void)hipEventDestroy(p->ready);
+      delete p;
+      return fail_hip(e, "serving: event on the submitting stream");
+    }
+  }
   std::lock_guard<std::mutex> lk(s->mu);
-  if (s->closing) {
+  auto reject = [&](int code, const std::string& msg) {
+    if (p->ready) s->free_events.push_back(p->ready);
     delete p;
-    return fail(MDRQ_EINVAL, "server is closing");
-  }
-  if (s->error != MDRQ_OK) {
-    delete p;
-    return fail(s->error, "serving: " + s->error_msg);
-  }
-  if (bounded && s->cfg.max_queue && s->ready.size() >= s->cfg.max_queue) {
-    delete p;
-    return fail(MDRQ_EBUSY, "serving queue is full");
-  }
+    return fail(code, msg);
+  };
+  if (s->closing) return reject(MDRQ_EINVAL, "server is closing");
+  if (s->error != MDRQ_OK) return reject(s->error, "serving: " + s->error_msg);
+  if (bounded && s->cfg.max_queue && s->ready.size() >= s->cfg.max_queue)
+    return reject(MDRQ_EBUSY, "serving queue is full");
   if (s->next_ticket == 0 || arrival < s->first_arrival) s->first_arrival = arrival;
   p->ticket = s->next_ticket++;
   if (ticket) *ticket = p->ticket;
@@ -312,25 +347,29 @@ void close_servers(mdrq_dataset* ds) {
 }  // namespace mdrq
 
 extern "C" int mdrq_serve_open(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, mdrq_server** out) {
-  clear_error();
-  if (!out) return fail(MDRQ_EINVAL, "NULL argument");
-  *out = nullptr;
-  int rc = check_config(ds, cfg);
-  if (rc) return rc;
-  rc = create(ds, cfg, true, out);
-  if (rc) return rc;
-  std::lock_guard<std::mutex> lk(ds->stat_mu);
-  ds->servers.push_back(*out);
-  return MDRQ_OK;
+  return guarded([&]() -> int {
+    clear_error();
+    if (!out) return fail(MDRQ_EINVAL, "NULL argument");
+    *out = nullptr;
+    int rc = check_config(ds, cfg);
+    if (rc) return rc;
+    rc = create(ds, cfg, true, out);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ds->stat_mu);
+    ds->servers.push_back(*out);
+    return MDRQ_OK;
+  });
 }
 
 extern "C" int mdrq_serve_submit(mdrq_server* s, const mdrq_query_t* q, mdrq_result_t* r,
-                                 uint64_t* ticket) {
-  clear_error();
-  if (!s || !q || !r) return fail(MDRQ_EINVAL, "NULL argument");
-  int rc = check_request(s, q, r);
-  if (rc) return rc;
-  return enqueue(s, q, r, Clock::now(), true, ticket);
+                                 void* stream, uint64_t* ticket) {
+  return guarded([&]() -> int {
+    clear_error();
+    if (!s || !q || !r) return fail(MDRQ_EINVAL, "NULL argument");
+    int rc = check_request(s, q, r);
+    if (rc) return rc;
+    return enqueue(s, q, r, Clock::now(), true, true, static_cast<hipStream_t>(stream), ticket);
+  });
 }
 
 extern "C" int mdrq_serve_poll(mdrq_server* s, uint64_t* tickets, uint32_t max_tickets,
@@ -358,53 +397,59 @@ extern "C" int mdrq_serve_close(mdrq_server* s, mdrq_serve_stats_t* stats) {
 extern "C" int mdrq_serve(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, const mdrq_request_t* reqs,
                           uint32_t n_reqs, mdrq_result_t* rs, uint64_t* latency_ns,
                           mdrq_serve_stats_t* stats) {
-  clear_error();
-  int rc = check_config(ds, cfg);
-  if (rc) return rc;
-  if (!reqs || !rs) return fail(MDRQ_EINVAL, "NULL argument");
-  if (n_reqs == 0) return fail(MDRQ_EINVAL, "no requests");
-  std::lock_guard<std::mutex> lock(ds->mu);
-  bool any_row = false;
-  for (uint32_t i = 0; i < n_reqs; ++i) any_row |= needs_row(rs[i]);
-  mdrq_server* s = nullptr;
-  rc = create(ds, cfg, any_row, &s);
-  if (rc) return rc;
-  for (uint32_t i = 0; i < n_reqs; ++i) {
-    rc = check_request(s, &reqs[i].query, &rs[i]);
-    if (rc) {
-      std::string msg = mdrq_last_error();
-      (void)shutdown(s, nullptr);
-      return fail(rc, msg);
+  return guarded([&]() -> int {
+    clear_error();
+    int rc = check_config(ds, cfg);
+    if (rc) return rc;
+    if (!reqs || !rs) return fail(MDRQ_EINVAL, "NULL argument");
+    if (n_reqs == 0) return fail(MDRQ_EINVAL, "no requests");
+    std::lock_guard<std::mutex> lock(ds->mu);
+    // The result buffers may have been prepared by work still queued on any stream: the
+    // replay starts once the device is idle (its requests then need no events).
+    const hipError_t idle = hipDeviceSynchronize();
+    if (idle != hipSuccess) return fail_hip(idle, "serving: device synchronisation");
+    bool any_row = false;
+    for (uint32_t i = 0; i < n_reqs; ++i) any_row |= needs_row(rs[i]);
+    mdrq_server* s = nullptr;
+    rc = create(ds, cfg, any_row, &s);
+    if (rc) return rc;
+    for (uint32_t i = 0; i < n_reqs; ++i) {
+      rc = check_request(s, &reqs[i].query, &rs[i]);
+      if (rc) {
+        std::string msg = mdrq_last_error();
+        (void)shutdown(s, nullptr);
+        return fail(rc, msg);
+      }
     }
-  }
 
-  // Replay: each request is queued when the clock reaches its arrival stamp (arrival
-  // order, stable for equal stamps); its latency counts from that stamp.
-  std::vector<uint32_t> order(n_reqs);
-  for (uint32_t i = 0; i < n_reqs; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](uint32_t a, uint32_t b) { return reqs[a].arrival_ns < reqs[b].arrival_ns; });
-  std::vector<uint32_t> index_of_ticket(n_reqs);
-  const Clock::time_point t0 = Clock::now();
-  for (uint32_t k = 0; k < n_reqs; ++k) {
-    const uint32_t i = order[k];
-    const Clock::time_point at = t0 + std::chrono::nanoseconds(reqs[i].arrival_ns);
-    std::this_thread::sleep_until(at);
-    uint64_t ticket = 0;
-    rc = enqueue(s, &reqs[i].query, &rs[i], at, false, &ticket);
-    if (rc) break;
-    index_of_ticket[ticket] = i;
-  }
-  if (latency_ns) {
-    // Latencies are final once the server has drained; copy them before it is freed.
-    {
-      std::unique_lock<std::mutex> lk(s->mu);
-      s->cv.wait(lk, [&] { return s->completed == s->next_ticket || s->error != MDRQ_OK; });
-      for (uint64_t t = 0; t < s->next_ticket && t < s->lat_ns.size(); ++t)
-        latency_ns[index_of_ticket[t]] = s->lat_ns[t];
+    // Replay: each request is queued when the clock reaches its arrival stamp (arrival
+    // order, stable for equal stamps); its latency counts from that stamp.
+    std::vector<uint32_t> order(n_reqs);
+    for (uint32_t i = 0; i < n_reqs; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return reqs[a].arrival_ns < reqs[b].arrival_ns; });
+    std::vector<uint32_t> index_of_ticket(n_reqs);
+    const Clock::time_point t0 = Clock::now();
+    for (uint32_t k = 0; k < n_reqs; ++k) {
+      const uint32_t i = order[k];
+      const Clock::time_point at = t0 + std::chrono::nanoseconds(reqs[i].arrival_ns);
+      std::this_thread::sleep_until(at);
+      uint64_t ticket = 0;
+      rc = enqueue(s, &reqs[i].query, &rs[i], at, false, false, nullptr, &ticket);
+      if (rc) break;
+      index_of_ticket[ticket] = i;
     }
-  }
-  const int rc_close = shutdown(s, stats);
-  if (rc) return rc;
-  return rc_close;
+    if (latency_ns) {
+      // Latencies are final once the server has drained; copy them before it is freed.
+      {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv.wait(lk, [&] { return s->completed == s->next_ticket || s->error != MDRQ_OK; });
+        for (uint64_t t = 0; t < s->next_ticket && t < s->lat_ns.size(); ++t)
+          latency_ns[index_of_ticket[t]] = s->lat_ns[t];
+      }
+    }
+    const int rc_close = shutdown(s, stats);
+    if (rc) return rc;
+    return rc_close;
+  });
 }

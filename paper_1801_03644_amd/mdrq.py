@@ -129,7 +129,7 @@ def load_library(path: str = LIB_PATH):
     lib.mdrq_query_batch.argtypes = [vp, P(Query), u32, P(Result), vp]
     lib.mdrq_serve.argtypes = [vp, P(ServeConfig), P(Request), u32, P(Result), P(u64), P(ServeStats)]
     lib.mdrq_serve_open.argtypes = [vp, P(ServeConfig), P(vp)]
-    lib.mdrq_serve_submit.argtypes = [vp, P(Query), P(Result), P(u64)]
+    lib.mdrq_serve_submit.argtypes = [vp, P(Query), P(Result), vp, P(u64)]
     lib.mdrq_serve_poll.argtypes = [vp, P(u64), u32, P(u32), u64]
     lib.mdrq_serve_close.argtypes = [vp, P(ServeStats)]
     lib.mdrq_free.argtypes = [vp]
@@ -470,14 +470,15 @@ class Server:
         ds._servers.add(self)
         self._pending = {}   # ticket -> (result record, output buffer): alive until polled
 
-    def submit(self, query, out=None, mode: str = "ids") -> int:
-        """Queue one request; returns its ticket.  Raises MdrqError (code EBUSY) when
-        the queue is full."""
+    def submit(self, query, out=None, mode: str = "ids", stream=None) -> int:
+        """Queue one request; returns its ticket.  The request's scan runs after the work
+        queued so far on `stream` (default: torch's current stream), e.g. a fill of
+        `out`.  Raises MdrqError (code EBUSY) when the queue is full."""
         q, keep = make_query(query, 0)
         r = _result_for(out, mode)
         t = ctypes.c_uint64()
         _check(load_library().mdrq_serve_submit(self._h, ctypes.byref(q), ctypes.byref(r),
-                                                ctypes.byref(t)))
+                                                _stream_handle(stream), ctypes.byref(t)))
         self._pending[t.value] = (r, out)
         return t.value
 

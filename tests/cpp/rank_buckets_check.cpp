@@ -6,6 +6,8 @@
 // fullest bucket and 2^(d-1) - 1 does not, the bucket count respects the cap, the
 // key-only mode never picks the value map, and the choice equals an exhaustive search.  The kernel's value map repeats the host's
 // float arithmetic, so a key between two ends lands in a bucket between theirs.
+// The slot tables appended for the kernel are checked too: their size against the
+// bound the host plans LDS with, the padding, and every query bitset row.
 #include <cstdio>
 #include <random>
 
@@ -114,6 +116,80 @@ int main() {
         if (rb.d != best_d || rb.by_value != (best_v == 1) || rb.nb != best_nb) ++bad;
       }
   }
-  std::printf("bad=%d key_maps=%d value_maps=%d\n", bad, key_maps, value_maps);
+  // Slot tables of S queries (32 x sw per group, any S up to 128): the appended words
+  // equal slot_table_words and stay within slot_table_words_bound(2 S) for adversarial
+  // end sets (all but one end crowded into one bucket, so the padding 2^d - 1 is as
+  // large as it gets), and every bitset row says exactly which queries pass at that
+  // rank.
+  int tables = 0;
+  for (int it = 0; it < 4000; ++it) {
+    const uint32_t S = 1 + static_cast<uint32_t>(rng() % 128);
+    const uint32_t sw = S <= 32 ? 1 : S <= 64 ? 2 : 4;
+    const int kind = it % 3;
+    std::vector<mdrq::KeyInterval> qs(S);
+    const uint32_t base = order_key(0.5f);
+    for (uint32_t q = 0; q < S; ++q) {
+      if (rng() % 5 == 0) continue;  // no predicate on this column
+      uint32_t a, b;
+      if (kind == 0) {        // crowded: consecutive keys, one far outlier below
+        a = base + static_cast<uint32_t>(rng() % (2 * S + 2));
+        b = base + static_cast<uint32_t>(rng() % (2 * S + 2));
+      } else if (kind == 1) { // spread
+        a = order_key(std::uniform_real_distribution<float>(0.0f, 1.0f)(rng));
+        b = order_key(std::uniform_real_distribution<float>(0.0f, 1.0f)(rng));
+      } else {                // arbitrary keys below key(NaN)
+        a = static_cast<uint32_t>(rng()) % 0xFF800000u;
+        b = static_cast<uint32_t>(rng()) % 0xFF800000u;
+      }
+      if (rng() % 4) {
+        if (a > b) std::swap(a, b);
+      }
+      qs[q] = mdrq::KeyInterval{a, b, true};
+    }
+    if (kind == 0) qs[0] = mdrq::KeyInterval{order_key(-1e30f), order_key(-1e30f), true};
+    std::vector<uint32_t> ends;
+    for (const auto& k : qs)
+      if (k.has) {
+        ends.push_back(k.klo);
+        ends.push_back(k.khi + 1);
+      }
+    if (ends.empty()) continue;
+    std::sort(ends.begin(), ends.end());
+    ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
+    const uint32_t M = static_cast<uint32_t>(ends.size());
+    for (uint32_t cap : {256u, 1024u}) {
+      mdrq::RankBuckets rb = mdrq::rank_buckets(ends, it % 3, cap);
+      std::vector<uint32_t> g(8, 0u);
+      const uint32_t at = mdrq::append_slot_tables(g, ends, rb, qs, sw);
+      const uint64_t words = g.size() - 8;
+      ++tables;
+      if (words != mdrq::slot_table_words(M, rb, sw) || g.size() % 4 ||
+          (cap == 256 && words > mdrq::slot_table_words_bound(2 * S, 256, sw)) || at != 8 + rb.nb / 2) {
+        std::printf("size S=%u M=%u d=%u nb=%u words=%llu\n", S, M, rb.d, rb.nb,
+                    static_cast<unsigned long long>(words));
+        ++bad;
+        continue;
+      }
+      for (uint32_t i = 0; i < M; ++i)
+        if (g[at + i] != ends[i]) ++bad;
+      for (uint32_t i = M; i < M + (1u << rb.d) - 1; ++i)
+        if (g[at + i] != 0xFFFFFFFFu) ++bad;
+      const size_t t0 = at + mdrq::align4(M + (1u << rb.d) - 1);
+      for (uint32_t r = 0; r <= M; ++r)
+        for (uint32_t q = 0; q < S; ++q) {
+          // rank r: the ends[0..r) are <= the key; the query passes iff
+          // klo <= key <= khi, i.e. klo is among them and khi + 1 is not.
+          bool pass = true;
+          if (qs[q].has) {
+            const uint32_t lo_idx = static_cast<uint32_t>(std::find(ends.begin(), ends.end(), qs[q].klo) - ends.begin());
+            const uint32_t hi_idx = static_cast<uint32_t>(std::find(ends.begin(), ends.end(), qs[q].khi + 1) - ends.begin());
+            pass = lo_idx < r && r <= hi_idx;
+          }
+          const bool got = (g[t0 + static_cast<size_t>(r) * sw + q / 32] >> (q % 32)) & 1u;
+          if (got != pass) ++bad;
+        }
+    }
+  }
+  std::printf("bad=%d key_maps=%d value_maps=%d slot_tables=%d\n", bad, key_maps, value_maps, tables);
   return bad != 0 || value_maps == 0 || key_maps == 0;
 }

@@ -116,6 +116,6 @@ def test_live_server_calls_reject_null_arguments():
     n = ctypes.c_uint32()
     tickets = (ctypes.c_uint64 * 4)()
     assert lib.mdrq_serve_open(None, ctypes.byref(cfg), ctypes.byref(h)) == mdrq.EINVAL
-    assert lib.mdrq_serve_submit(None, ctypes.byref(q), ctypes.byref(r), ctypes.byref(t)) == mdrq.EINVAL
+    assert lib.mdrq_serve_submit(None, ctypes.byref(q), ctypes.byref(r), None, ctypes.byref(t)) == mdrq.EINVAL
     assert lib.mdrq_serve_poll(None, tickets, 4, ctypes.byref(n), 0) == mdrq.EINVAL
     assert lib.mdrq_serve_close(None, None) == mdrq.EINVAL
