@@ -33,9 +33,13 @@ def _line(value, unit, config, steps, warmup, ms_per_step, extra):
 
 class Runner:
     """Prepared single-query and batch calls through the C ABI (no per-call Python
-    marshalling in the timed loops)."""
+    marshalling in the timed loops).  Query i writes its ids into its own region of one
+    device buffer, caps[i] ids long; the regions of each window of `window` consecutive
+    queries (a batch) are disjoint, and windows reuse the buffer."""
 
-    def __init__(self, ds, queries, out2d, stream):
+    def __init__(self, ds, queries, caps, stream, window=1024):
+        import torch
+
         from paper_1801_03644_amd import mdrq
 
         self.mdrq = mdrq
@@ -43,12 +47,21 @@ class Runner:
         self.ds = ds
         self.stream = stream
         self.n = len(queries)
-        self.out2d = out2d
-        cap = out2d.shape[1]
-        self.cap = cap
+        self.window = window
+        self.caps = np.maximum(np.asarray(caps, dtype=np.int64), 1)
+        off = np.zeros(self.n, dtype=np.int64)
+        need = 1
+        for a in range(0, self.n, window):
+            c = self.caps[a:a + window]
+            off[a:a + window] = np.concatenate([[0], np.cumsum(c)[:-1]])
+            need = max(need, int(c.sum()))
+        self.buf = torch.empty(need, dtype=torch.int32, device="cuda:0")
+        self.off = off
+        self.ptrs = (self.buf.data_ptr() + 4 * off).astype(np.uint64)
+        self.bytes = (4 * self.caps).astype(np.uint64)
         self.keep = []
         self.q = {}
-        for flags in (0, mdrq.Q_ORDER_ESTIMATED):
+        for flags in (0, mdrq.Q_ORDER_ESTIMATED, mdrq.Q_ORDER_ESTIMATED | mdrq.Q_SIZE_ESTIMATED):
             arr = (mdrq.Query * self.n)()
             for i, q in enumerate(queries):
                 qq, k = mdrq.make_query(q, flags)
@@ -58,25 +71,30 @@ class Runner:
         # Result records as numpy fields, set and read per batch without a Python loop.
         self.rrec = np.zeros(self.n, dtype=mdrq._RESULT_DT)
         self.r = (mdrq.Result * self.n).from_buffer(self.rrec)
-        self.ptrs = np.array([out2d[s].data_ptr() for s in range(out2d.shape[0])], dtype=np.uint64)
         self.counts = np.zeros(self.n, dtype=np.int64)
+        self.written = np.zeros(self.n, dtype=np.int64)
 
-    def _result(self, i, slot):
-        r = self.r[i]
-        r.mode, r.mem = self.mdrq.OUT_IDS, self.mdrq.MEM_DEVICE
-        r.buf = self.out2d[slot].data_ptr()
-        r.buf_bytes = self.cap * 4
-        return r
+    def ids(self, i):
+        """The ids query i wrote in the last call that answered it."""
+        return self.buf[self.off[i]:self.off[i] + int(self.written[i])]
+
+    def check_complete(self):
+        if (self.written != self.counts).any():
+            raise RuntimeError("an output buffer was too small: work would be skipped")
 
     def plain(self, flags=0, lo=0, hi=None):
         hi = self.n if hi is None else hi
         for i in range(lo, hi):
-            r = self._result(i, i % self.out2d.shape[0])
+            r = self.r[i]
+            r.mode, r.mem = self.mdrq.OUT_IDS, self.mdrq.MEM_DEVICE
+            r.buf = int(self.ptrs[i])
+            r.buf_bytes = int(self.bytes[i])
             rc = self.lib.mdrq_query(self.ds.handle, ctypes.byref(self.q[flags][i]), ctypes.byref(r),
                                      self.stream)
             if rc not in (0, self.mdrq.EOVERFLOW):
                 raise self.mdrq.MdrqError(rc, self.mdrq.last_error())
             self.counts[i] = r.count
+            self.written[i] = r.written
         return self.counts[lo:hi].copy()
 
     def batch(self, flags=0, lo=0, hi=None, size=1024):
@@ -86,8 +104,8 @@ class Runner:
             rec = self.rrec[a:b]
             rec["mode"] = self.mdrq.OUT_IDS
             rec["mem"] = self.mdrq.MEM_DEVICE
-            rec["buf"] = self.ptrs[:b - a]
-            rec["buf_bytes"] = self.cap * 4
+            rec["buf"] = self.ptrs[a:b]
+            rec["buf_bytes"] = self.bytes[a:b]
             qp = ctypes.cast(ctypes.byref(self.q[flags], a * ctypes.sizeof(self.mdrq.Query)),
                              ctypes.POINTER(self.mdrq.Query))
             rp = ctypes.cast(ctypes.byref(self.r, a * ctypes.sizeof(self.mdrq.Result)),
@@ -96,10 +114,19 @@ class Runner:
             if rc not in (0, self.mdrq.EOVERFLOW):
                 raise self.mdrq.MdrqError(rc, self.mdrq.last_error())
             self.counts[a:b] = rec["count"]
+            self.written[a:b] = rec["written"]
         return self.counts[lo:hi].copy()
 
 
-def _setup(name, rows):
+def _exact_counts(ds, queries):
+    """Exact result sizes (count-only shared scans), to size the output buffers."""
+    out = []
+    for a in range(0, len(queries), 1024):
+        out += [x.count for x in ds.query_batch(queries[a:a + 1024], None, "count")]
+    return np.array(out, dtype=np.int64)
+
+
+def _setup(name, rows, graphs=None):
     import torch
 
     from paper_1801_03644_amd import datagen as dg
@@ -111,6 +138,8 @@ def _setup(name, rows):
     raw = w.columns()
     log(f"generated in {time.perf_counter() - t0:.1f}s; loading into HBM")
     ds = mdrq.Dataset.from_host(raw)
+    if graphs is not None:
+        ds.set_option(mdrq.OPT_GRAPHS, graphs)
     stream = mdrq._stream_handle(torch.cuda.current_stream())
     return w, raw, ds, stream
 
@@ -138,15 +167,14 @@ def batched(args):
     import torch
 
     from paper_1801_03644_amd import datagen as dg
-    from paper_1801_03644_amd.metrics import ALU_COMPARES_PEAK, COMPARES_PER_TEST
+    from paper_1801_03644_amd.metrics import (ALU_COMPARES_PEAK, COMPARES_PER_TEST, LDS_PEAK_GBPS,
+                                              RANK_LDS_BYTES_PER_LOOKUP)
 
-    w, raw, ds, stream = _setup("c3", args.rows)
+    w, raw, ds, stream = _setup("c3", args.rows, args.graphs)
     n_q = 1024
     queries = dg.workload_queries(w, n_q)
     ks = np.array([len(q[0]) for q in queries])
-    cap = min(w.n_rows, 12_000_000)
-    out = torch.empty((n_q, cap), dtype=torch.int32, device="cuda:0")
-    run = Runner(ds, queries, out, stream)
+    run = Runner(ds, queries, _exact_counts(ds, queries), stream)
     reps = max(1, args.steps)
     res = {}
     for Q in (64, 256, 1024):
@@ -158,27 +186,32 @@ def batched(args):
         ds.reset_profile()
         c_batch, t_batch = _timed(lambda: run.batch(0, 0, Q, Q), reps)
         scans, dev_ms = ds.batch_profile()
+        lookups, col_bytes, scan_ms = ds.batch_work()
         if not np.array_equal(c_plain, c_batch):
             raise RuntimeError("batched counts differ from single-query counts")
         tests = float(ks[:Q].sum()) * w.n_rows
         res[Q] = {"plain_queries_per_s": Q / t_plain, "batched_queries_per_s": Q / t_batch,
                   "speedup": t_plain / t_batch, "batch_ms": t_batch * 1e3,
                   "shared_scans_per_batch": scans / reps, "device_ms_per_batch": dev_ms / reps,
-                  "row_tests_per_s": tests / (dev_ms / reps / 1e3)}
+                  "row_tests_per_s": tests / (dev_ms / reps / 1e3),
+                  "scan_kernel_ms_per_batch": scan_ms / reps, "rank_lookups_per_batch": lookups / reps,
+                  "column_bytes_per_batch": col_bytes / reps}
         log(f"Q={Q}: plain {Q / t_plain:.0f} q/s, batched {Q / t_batch:.0f} q/s")
     # ids of a few queries of the largest batch against their single-query ids
     run.batch(0, 0, n_q, n_q)
+    run.check_complete()
     check = [0, 17, 511, 1023]
-    got = [out[i, :min(cap, int(run.counts[i]))].clone() for i in check]
+    got = [run.ids(i).clone() for i in check]
     for j, i in enumerate(check):
         run.plain(0, i, i + 1)
-        if not torch.equal(got[j], out[i % out.shape[0], :min(cap, int(run.counts[i]))]):
+        if not torch.equal(got[j], run.ids(i)):
             raise RuntimeError("batched ids differ from single-query ids")
     big = res[1024]
     ach = COMPARES_PER_TEST * big["row_tests_per_s"]
+    lds_ach = big["rank_lookups_per_batch"] * RANK_LDS_BYTES_PER_LOOKUP / (big["scan_kernel_ms_per_batch"] / 1e3) / 1e9
     # HBM view of the same batch: every column of the union read once, ids written.
     union = len({int(d) for q in queries for d in q[0]})
-    hbm_bytes = 4.0 * w.n_rows * union + 4.0 * float(np.minimum(run.counts, cap).sum())
+    hbm_bytes = 4.0 * w.n_rows * union + 4.0 * float(run.counts.sum())
     hbm_ach = hbm_bytes / (big["device_ms_per_batch"] / 1e3) / 1e9
     line = _line(big["batched_queries_per_s"], "queries/s",
                  {"workload": f"c3: {w.n_rows} rows x {w.n_dims} float32 columns, batches of "
@@ -188,7 +221,16 @@ def batched(args):
                  reps, 1, big["batch_ms"],
                  {"batches": {str(k): v for k, v in res.items()},
                   "plain_queries_per_s": big["plain_queries_per_s"],
-                  "roofline": {"bound": "alu", "achieved": ach, "peak": ALU_COMPARES_PEAK,
+                  "roofline": {"bound": "lds", "achieved": lds_ach, "peak": LDS_PEAK_GBPS, "unit": "GB/s",
+                               "frac": lds_ach / LDS_PEAK_GBPS, "traffic": None,
+                               "kernel": "batch_rank_kernel (the shared scan alone, without the finish)",
+                               "avg_kernel_ms": big["scan_kernel_ms_per_batch"],
+                               "note": "work = per row and (group of up to 128 queries, column) one "
+                                       "4-byte bucket word and one 16-byte row of query bitsets read "
+                                       "from LDS (the search probes inside a bucket are data-dependent "
+                                       "and not counted); peak = 128 B per clock per CU x 256 CUs x "
+                                       "2.4 GHz"},
+                  "roofline_alu": {"bound": "alu", "achieved": ach, "peak": ALU_COMPARES_PEAK,
                                "unit": "compares/s", "frac": ach / ALU_COMPARES_PEAK,
                                "traffic": None, "kernel": "shared scan, autotuned variant (+ finish)",
                                "note": "work = 2 compares (lo <= x, x <= hi) per row-predicate "
@@ -223,87 +265,106 @@ def _qstats(q):
 
 
 def learned(args):
-    """c4: the estimator trained on scan-labelled queries; q-error against the
-    histogram independence product (the untrained estimator returns exactly that); and
-    queries/s of the held-out queries in given and in estimated predicate order, one at
-    a time and in shared scans of 1024."""
-    import torch
-
+    """c4: the estimator trained on scan-labelled queries and gated on a held-out
+    validation split (an output keeps its learned correction only where it lowers the
+    validation error); q-error against the histogram estimates and their independence
+    product (the untrained estimator returns exactly those); and queries/s of the
+    held-out queries one at a time in given order, in the untrained estimator's
+    (histogram) order and in the trained one's, and in shared scans of 1024 in given
+    order and with the trained estimator's order and scratch sizing.  Every query's
+    output buffer holds its whole result (no work skipped)."""
     from paper_1801_03644_amd import datagen as dg
     from paper_1801_03644_amd import mdrq
 
-    w, raw, ds, stream = _setup("c4", args.rows)
+    w, raw, ds, stream = _setup("c4", args.rows, args.graphs)
     samp = w.sampler()
     n_tr, n_te = args.train_queries, args.test_queries
+    n_va = max(1000, n_te // 2)
     train_q = dg.quantile_queries(samp, n_tr, (1, 10), (1e-5, 0.2), w.split_seed)
+    val_q = dg.quantile_queries(samp, n_va, (1, 10), (1e-5, 0.2), w.split_seed + 1)
     test_q = dg.quantile_queries(samp, n_te, (3, 10), (1e-5, 0.2), w.query_seed)
-    log(f"labelling {n_tr} + {n_te} queries with shared count scans")
+    log(f"labelling {n_tr} + {n_va} + {n_te} queries with shared count scans")
     t0 = time.perf_counter()
     parts = []
     for a in range(0, n_tr, 20_000):
         parts.append(ds.label_selectivities(train_q[a:a + 20_000]))
         log(f"labelled {min(n_tr, a + 20_000)} training queries ({time.perf_counter() - t0:.1f}s)")
     s_train = np.concatenate(parts)
+    s_val = ds.label_selectivities(val_q)
     s_test = ds.label_selectivities(test_q)
     t_label = time.perf_counter() - t0
+    hist_est = mdrq.Estimator(ds, seed=1)              # untrained: histogram estimates
     est = mdrq.Estimator(ds, seed=1)
-    base = est.predict(test_q)                         # untrained: the independence product
+    base = hist_est.predict(test_q)
     log(f"training {args.epochs} epochs")
     t0 = time.perf_counter()
     losses = est.train(train_q, s_train, epochs=args.epochs, batch=256, lr=1e-3,
                        seed=w.split_seed)
     t_train = time.perf_counter() - t0
+    ungated = est.predict(test_q)
+    kept = est.gate(val_q, s_val)
     pred = est.predict(test_q)
     n = w.n_rows
     mask = s_test[:, :-1] >= 0
     qerr = {"joint_learned": _qstats(_qerror(pred[:, -1], s_test[:, -1], n)),
             "joint_independence": _qstats(_qerror(base[:, -1], s_test[:, -1], n)),
             "per_dim_learned": _qstats(_qerror(pred[:, :-1][mask], s_test[:, :-1][mask], n)),
-            "per_dim_histogram": _qstats(_qerror(base[:, :-1][mask], s_test[:, :-1][mask], n))}
-    ds.attach_estimator(est)
-    cap = min(n, 12_000_000)
-    out = torch.empty((1024, cap), dtype=torch.int32, device="cuda:0")
-    run = Runner(ds, test_q, out, stream)
+            "per_dim_learned_before_gating": _qstats(_qerror(ungated[:, :-1][mask], s_test[:, :-1][mask], n)),
+            "per_dim_histogram": _qstats(_qerror(base[:, :-1][mask], s_test[:, :-1][mask], n)),
+            "outputs_kept": [int(j) for j in np.flatnonzero(kept)]}
+    counts = _exact_counts(ds, test_q)
+    run = Runner(ds, test_q, counts, stream)
     G, E = 0, mdrq.Q_ORDER_ESTIMATED
+    ES = mdrq.Q_ORDER_ESTIMATED | mdrq.Q_SIZE_ESTIMATED
     variants = {}
     log("warm-up (the first shared scan of each batch shape autotunes its launch)")
+    ds.attach_estimator(est)
     run.plain(G, 0, 200)
     run.plain(E, 0, 200)
     run.batch(G)
-    run.batch(E)
+    run.batch(ES)
     ds.set_profiling(True)
-    for name, fn in (("plain_given_order", lambda: run.plain(G)),
-                     ("plain_estimated_order", lambda: run.plain(E)),
-                     ("batched_given_order", lambda: run.batch(G)),
-                     ("batched_estimated_order", lambda: run.batch(E))):
+    for name, fn, e in (("plain_given_order", lambda: run.plain(G), est),
+                        ("plain_histogram_order", lambda: run.plain(E), hist_est),
+                        ("plain_learned_order", lambda: run.plain(E), est),
+                        ("batched_given_order", lambda: run.batch(G), est),
+                        ("batched_learned_order_and_sizing", lambda: run.batch(ES), est)):
         log(name)
+        ds.attach_estimator(e)
         ds.reset_profile()
         c, t = _timed(fn)
+        run.check_complete()
         launches, scan_ms, total_ms = ds.profile()
         variants[name] = {"queries_per_s": n_te / t, "seconds": t, "counts": c}
         if launches:
             variants[name]["scan_kernel_us_per_query"] = scan_ms / launches * 1e3
+        sized, reruns = ds.sizing_profile()
+        if sized:
+            variants[name]["sized_by_estimate"] = sized
+            variants[name]["answered_again"] = reruns
         log(f"{name}: {n_te / t:.0f} queries/s")
     ds.set_profiling(False)
     ref = variants["plain_given_order"]["counts"]
     for name, v in variants.items():
         if not np.array_equal(v.pop("counts"), ref):
             raise RuntimeError(f"{name}: counts differ")
-    if not np.array_equal(ref, np.round(s_test[:, -1].astype(np.float64) * n).astype(np.int64)):
-        # labels are float32 count / N: allow the float32 rounding of the label
-        lab = s_test[:, -1].astype(np.float64) * n
-        if np.abs(lab - ref).max() > 1e-6 * n + 1:
-            raise RuntimeError("labels disagree with the scan counts")
-    best = variants["batched_estimated_order"]["queries_per_s"]
+    if not np.array_equal(ref, counts):
+        raise RuntimeError("counts differ from the count-only scans")
+    lab = s_test[:, -1].astype(np.float64) * n
+    if np.abs(lab - ref).max() > 1e-6 * n + 1:   # labels are float32 count / N
+        raise RuntimeError("labels disagree with the scan counts")
+    best = variants["batched_learned_order_and_sizing"]["queries_per_s"]
     line = _line(best, "queries/s",
                  {"workload": f"c4: {n} rows x {w.n_dims} float32 columns (10 correlated pairs), "
-                              f"{n_tr} training / {n_te} held-out queries, ids output",
-                  "n_rows": n, "n_dims": w.n_dims, "train_queries": n_tr, "test_queries": n_te,
-                  "hidden": 64, "epochs": args.epochs, "data_seed": w.data_seed,
+                              f"{n_tr} training / {n_va} validation / {n_te} held-out queries, ids output",
+                  "n_rows": n, "n_dims": w.n_dims, "train_queries": n_tr, "validation_queries": n_va,
+                  "test_queries": n_te, "hidden": 64, "epochs": args.epochs, "data_seed": w.data_seed,
                   "query_seed": w.query_seed, "split_seed": w.split_seed},
-                 1, 0, variants["batched_estimated_order"]["seconds"] * 1e3,
+                 1, 0, variants["batched_learned_order_and_sizing"]["seconds"] * 1e3,
                  {"variants": variants, "q_error": qerr,
                   "speedup_vs_plain_given_order": best / variants["plain_given_order"]["queries_per_s"],
+                  "learned_vs_histogram_order_plain": variants["plain_learned_order"]["queries_per_s"]
+                  / variants["plain_histogram_order"]["queries_per_s"],
                   "label_seconds": t_label, "train_seconds": t_train,
                   "epoch_loss_first_last": [float(losses[0]), float(losses[-1])]})
     if not args.no_cpu_baseline:
@@ -311,6 +372,7 @@ def learned(args):
         line["cpu_baseline"] = _cpu(raw, test_q, n, args.cpu_budget)
     ds.attach_estimator(None)
     est.close()
+    hist_est.close()
     ds.close()
     return line
 
@@ -323,13 +385,15 @@ def serving(args):
     from paper_1801_03644_amd import datagen as dg
     from paper_1801_03644_amd import mdrq
 
-    w, raw, ds, stream = _setup("c5", args.rows)
+    w, raw, ds, stream = _setup("c5", args.rows, args.graphs)
     samp = w.sampler()
     pool = dg.workload_queries(w, 4096, sampler=samp)
     train_q = dg.quantile_queries(samp, 20_000, (1, 6), (1e-6, 0.1), w.split_seed)
-    log("labelling and training the estimator")
+    val_q = dg.quantile_queries(samp, 4_000, (1, 6), (1e-6, 0.1), w.split_seed + 1)
+    log("labelling, training and gating the estimator")
     est = mdrq.Estimator(ds, seed=1)
     est.train(train_q, ds.label_selectivities(train_q), epochs=args.epochs, batch=256, lr=1e-3)
+    kept = est.gate(val_q, ds.label_selectivities(val_q))
     ds.attach_estimator(est)
     log("pool counts (single queries)")
     pool_counts = np.array([ds.query(q, None, mode="count").count for q in pool])
@@ -363,7 +427,7 @@ def serving(args):
         st = serve(rate, args.serve_seconds, 100 + i)
         per_rate[str(int(rate))] = {k: st[k] for k in ("completed", "scans", "wall_s", "qps", "p50_us",
                                                        "p99_us", "mean_us", "max_us", "mean_batch",
-                                                       "hbm_gbps")}
+                                                       "hbm_gbps", "sized_by_estimate", "overflow_reruns")}
         log(f"rate {rate:.0f}: {st['qps']:.0f} q/s, p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us")
     top = per_rate[str(int(rates[-1]))]
     line = _line(top["qps"], "queries/s",
@@ -374,7 +438,8 @@ def serving(args):
                   "result_budget_bytes": budget, "data_seed": w.data_seed,
                   "query_seed": w.query_seed},
                  1, 0, top["wall_s"] * 1e3,
-                 {"rates": per_rate, "p50_us": top["p50_us"], "p99_us": top["p99_us"]})
+                 {"rates": per_rate, "p50_us": top["p50_us"], "p99_us": top["p99_us"],
+                  "estimator_outputs_kept": [int(j) for j in np.flatnonzero(kept)]})
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         line["cpu_baseline"] = _cpu(raw, pool, w.n_rows, args.cpu_budget)

@@ -72,7 +72,16 @@ enum {
 enum {
   MDRQ_Q_ORDER_GIVEN = 0,      /* evaluate predicates in the order given */
   MDRQ_Q_ORDER_ESTIMATED = 1,  /* most selective first, by the attached estimator */
-  MDRQ_Q_NO_EARLYOUT = 2       /* read every queried column in full (measurement) */
+  MDRQ_Q_NO_EARLYOUT = 2,      /* read every queried column in full (measurement) */
+  MDRQ_Q_SIZE_ESTIMATED = 4    /* batches and serving: size this query's share of the
+                                  shared scan's scratch by the attached estimator's joint
+                                  estimate instead of the worst case (a bitmap row of
+                                  ceil(n_rows / 64) words): only the chunks of rows with a
+                                  hit are kept, in room for about MDRQ_OPT_RESERVE_FACTOR
+                                  times the estimated count; when the estimate was too
+                                  low the query is answered again by the single-query
+                                  scan.  Needs an attached estimator (else the worst case
+                                  is reserved); results never depend on it */
 };
 
 typedef struct mdrq_dataset mdrq_dataset;  /* opaque, owned by the library */
@@ -145,19 +154,23 @@ int mdrq_query_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n_querie
                      mdrq_result_t* rs, void* stream);
 
 /* Serving configuration.  n_streams workers each own a device stream and an equal share
- * of result_budget_bytes of device memory for the scans' bitmap rows: a request whose
- * result needs identifiers or a bitmap reserves one row of ceil(n_rows / 64) words (its
- * result can never need more), a count-only request reserves none.  A worker that is
- * idle takes the oldest waiting requests, at most max_batch and as many as its share
- * holds, and answers them with one batched shared scan (as mdrq_query_batch); requests
- * that arrive meanwhile wait for the next idle worker (continuous batching), and the
- * workers' scans overlap on the device. */
+ * of result_budget_bytes of device memory for the scans' scratch: a request whose result
+ * needs identifiers or a bitmap reserves one bitmap row of ceil(n_rows / 64) words and
+ * its chunk marks (its result can never need more), or, with use_estimator, the room its
+ * estimated result needs in the scan's sparse scratch (MDRQ_Q_SIZE_ESTIMATED; about four
+ * times the estimate, and never more than the row); a count-only request reserves none.
+ * A worker that is idle takes the oldest waiting requests, at most max_batch and as many
+ * as its share holds, and answers them with one batched shared scan (as
+ * mdrq_query_batch); requests that arrive meanwhile wait for the next idle worker
+ * (continuous batching), and the workers' scans overlap on the device. */
 typedef struct {
   uint64_t result_budget_bytes;
   uint32_t max_batch;       /* 1 .. MDRQ_MAX_BATCH */
   uint32_t n_streams;       /* 1 .. 8 */
   uint32_t use_estimator;   /* 1: every request evaluates its predicates in estimated
-                               order (needs an attached estimator) */
+                               order and has its scratch sized by its estimate
+                               (MDRQ_Q_ORDER_ESTIMATED | MDRQ_Q_SIZE_ESTIMATED; needs an
+                               attached estimator) */
   uint32_t max_queue;       /* live server: requests allowed to wait; a submission
                                beyond it fails with MDRQ_EBUSY (admission control).
                                0 = unbounded.  The replay ignores it. */
@@ -178,7 +191,9 @@ typedef struct {
   double mean_batch;        /* requests per worker batch */
   double hbm_gbps;          /* column bytes covered by the scans (each union column in
                                full) / wall_s */
-  uint64_t overflow_reruns; /* always 0: reservations are upper bounds, never re-run */
+  uint64_t overflow_reruns; /* requests answered again by the single-query scan because
+                               their estimate-sized scratch was too small */
+  uint64_t sized_by_estimate; /* requests whose scratch was sized by their estimate */
 } mdrq_serve_stats_t;
 
 /*
@@ -265,6 +280,17 @@ int mdrq_reset_profile(mdrq_dataset* ds);
 /* Shared scans run by mdrq_query_batch and mdrq_serve since the last reset, and their
  * summed device time (scan and finishing launches) in milliseconds. */
 int mdrq_get_batch_profile(const mdrq_dataset* ds, uint64_t* scans, double* ms);
+/* Work of the shared scans since the last reset: rank lookups (rows times the (group of
+ * up to 128 queries, column) pairs with a predicate, each one bucket word, a search
+ * within the bucket and one row of query bitsets read from LDS; 0 for the other
+ * variants), the column bytes read (4 per row and (group, column) pair of the rank
+ * variant, per row and union column otherwise), and the device time of the scan kernels
+ * alone in milliseconds (without the finishing launches). */
+int mdrq_get_batch_work(const mdrq_dataset* ds, uint64_t* lookups, uint64_t* column_bytes, double* scan_ms);
+/* Queries of mdrq_query_batch and mdrq_serve since the last reset whose scratch was
+ * sized by their estimate (MDRQ_Q_SIZE_ESTIMATED), and how many of them were answered
+ * again by the single-query scan because their result outgrew it. */
+int mdrq_get_sizing_profile(const mdrq_dataset* ds, uint64_t* sized, uint64_t* reruns);
 
 /* Tuning options of a dataset's scans (results never depend on them). */
 enum {
@@ -291,11 +317,21 @@ enum {
                                  every slot), 5 = per group of up to 128 queries, each
                                  row's rank among the group's interval ends and per-rank
                                  query bitsets; 0 = autotune (default) */
-  MDRQ_OPT_RANK_BUCKETS = 9   /* rank variant: how a column's keys map to the search's
+  MDRQ_OPT_RANK_BUCKETS = 9,  /* rank variant: how a column's keys map to the search's
                                  buckets: 0 = per column the map that leaves the fewest
                                  ends in the fullest bucket (default), 1 = by key,
                                  2 = by float value (by key where the ends' finite values
                                  do not span a finite range); results never depend on it */
+  MDRQ_OPT_GRAPHS = 10,       /* bit 0: the launch sequence of a single query (scan,
+                                 compaction), bit 1: that of a shared scan (query-table
+                                 copy, zeroing, scan, finish), is built once per launch
+                                 shape as a HIP graph and replayed with each call's
+                                 arguments; a clear bit launches each kernel directly.
+                                 Default 0 */
+  MDRQ_OPT_RESERVE_FACTOR = 11 /* MDRQ_Q_SIZE_ESTIMATED: room reserved per estimated
+                                 result row, in millionths (default 4000000: four times
+                                 the estimate, plus 64 chunks); 1..10^9.  Small values
+                                 force the fallback (tests) */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
 
@@ -306,6 +342,18 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
  * Errors: MDRQ_EINVAL (NULL pointers, k == 0, dim out of range), MDRQ_EDEVICE. */
 int mdrq_probe_bandwidth(mdrq_dataset* ds, const uint32_t* dims, uint32_t k, uint32_t iters,
                          void* stream, double* ms);
+
+/* Column bytes the scan of query q must read from HBM (a measurement of the method's
+ * own traffic, for rooflines; q is not answered).  With the early break (section 2.2.4)
+ * a later predicate needs only the rows that every earlier one accepted; memory is read
+ * in 128-byte lines (32 rows of a column), so the figure is 128 times the number of
+ * (predicate, line) pairs where the line holds such a row, predicates taken in the
+ * query's evaluation order (given, or estimated with MDRQ_Q_ORDER_ESTIMATED); with
+ * MDRQ_Q_NO_EARLYOUT every queried column is read in full.  Lines are counted from each
+ * column's first row (library-owned columns start on 256-byte boundaries).  Writes of
+ * the result are not included.  An empty query reads nothing.
+ * Errors: as mdrq_query for q; MDRQ_EDEVICE. */
+int mdrq_query_read_bytes(mdrq_dataset* ds, const mdrq_query_t* q, uint64_t* bytes, void* stream);
 
 /* ---------------------------------------------------------------- learned estimator
  *
@@ -392,6 +440,27 @@ int mdrq_estimator_train(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n,
 /* Estimated selectivities of n queries (same layout as sel; 1 for a dimension the
  * query does not restrict). */
 int mdrq_estimator_predict(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, float* sel);
+
+/* The network's intermediate values for n queries (1 .. 65536), as the prediction computes
+ * them: h1 and h2 receive the two hidden layers' bfloat16 activations (n rows of `hidden`
+ * bit patterns each), y the output layer (n rows of n_dims + 1 floats: the network's
+ * correction plus the base estimate, on the log scale y(s), before clamping to [0, 1]).
+ * Any of the three may be NULL.  For checking the matrix products against a reference
+ * fed the same bfloat16 operands.  Errors: as mdrq_estimator_predict. */
+int mdrq_estimator_activations(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, uint16_t* h1,
+                               uint16_t* h2, float* y);
+
+/* Keep each output's learned correction only where it helps: on n labelled queries
+ * (1 .. MDRQ_EST_MAX_QUERIES; a held-out split, not the training queries) compare, for
+ * every output, the squared error on the log scale of the network's estimate and of the
+ * base estimate alone (the histogram estimate of a dimension's predicate, or the
+ * independence product for the whole query), over the targets present.  An output the
+ * network does not improve gets its correction removed (its column of W3 and its entry
+ * of b3 set to zero, with their Adam moments), so it returns the base estimate from then
+ * on.  kept (optional, n_dims + 1 entries) receives 1 for each output kept, 0 for each
+ * removed.  Errors: as mdrq_estimator_gradient. */
+int mdrq_estimator_gate(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, const float* sel,
+                        uint32_t* kept);
 
 /* Let queries flagged MDRQ_Q_ORDER_ESTIMATED on ds evaluate their predicates in order of
  * ascending estimated selectivity (e = NULL detaches; such queries then keep the order

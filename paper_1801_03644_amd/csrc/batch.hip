@@ -436,16 +436,17 @@ __device__ __forceinline__ uint32_t half_transpose(uint32_t a, const HalfTranspo
 // The rank search is bucketed: the host maps a slot's keys monotonically to nb
 // buckets, either by key (2^shift keys per bucket from the smallest boundary kmin) or
 // by value (float (v - vlo) * scale, truncated), whichever leaves the fewest
-// boundaries in the fullest bucket, and stores per bucket the number of boundaries in
-// lower buckets; a row then needs one bucket lookup and d binary-search steps, 2^d - 1
-// being at least the fullest bucket's count.
+// boundaries in the fullest bucket, and stores per bucket the range of its boundaries;
+// a row then needs one bucket lookup and at most d binary-search steps (2^d - 1 being at
+// least the fullest bucket's count), of which it reads only those inside its bucket.
 //
-// LDS layout of a group (words): per query, its kind and output row (kind | row << 8),
-// padded to 4 words; per slot a header (offset of its boundaries; M | d << 12 |
-// log2(nb) << 16 | shift << 24 | by value << 31; kmin or vlo; scale); then per slot the
-// nb 16-bit bucket starts, the M boundaries padded with 2^d - 1 words 0xFFFFFFFF, and,
-// at a 4-word aligned offset, the table of (M + 1) x SW words.
-template <int W, int RG, int SW>
+// LDS layout of a group (words): per query, its kind and output row (kind | sparse << 2
+// | row << 8), padded to 4 words; per slot a header (offset of its boundaries; M | d <<
+// 12 | log2(nb) << 16 | shift << 24 | by value << 31; kmin or vlo; scale); then per slot
+// the nb bucket words (index of the bucket's first end | index past its last << 16), the
+// M boundaries and a word 0xFFFFFFFF, and, at a 4-word aligned offset, the table of
+// (M + 1) x SW words.
+template <int W, int RG, int SW, bool SPARSE>
 __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
   static_assert(W * RG <= 64, "a tile must hold at least one chunk per wave");
   extern __shared__ uint32_t lds[];
@@ -468,15 +469,20 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
   const HalfTranspose tc = half_transpose_consts(lane);
   // Lane 32 h + c writes half h of query 32 w + c's words: its output row, and a mask
   // that drops the stores of count-only queries and of lanes past the group.
+  // A sparse query (bit 2) stores its chunks with a hit in slots of its pool region.
   uint32_t* out[SW];
   uint32_t keep[SW], outi[SW];
+  uint32_t sp = 0;   // bit w: the lane's query of word w has sparse scratch
 #pragma unroll
   for (int w = 0; w < SW; ++w) {
     const uint32_t qi = 32 * w + (lane & 31);
     const uint32_t inf = qi < nq ? info[qi] : kBatchCount;
     keep[w] = (inf & 0x3u) != kBatchCount ? ~0u : 0u;
     outi[w] = keep[w] ? inf >> 8 : 0;
-    out[w] = reinterpret_cast<uint32_t*>(bp.words + static_cast<uint64_t>(outi[w]) * bp.n_words) + (lane >> 5);
+    const uint32_t sparse = SPARSE && keep[w] ? (inf >> 2) & 1u : 0u;
+    sp |= sparse << w;
+    out[w] = reinterpret_cast<uint32_t*>(bp.words + static_cast<uint64_t>(sparse ? 0u : outi[w]) * bp.n_words) +
+             (lane >> 5);
   }
   constexpr uint32_t kChunkRows = 64 * RG;
   constexpr uint32_t kChunksPerWave = 4096 / kChunkRows / W;
@@ -502,8 +508,8 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
         const uint32_t* B = s_tab + __builtin_amdgcn_readfirstlane(h.x);
         const uint32_t base = __builtin_amdgcn_readfirstlane(h.z);   // kmin, or vlo's bits
         const float scale = __uint_as_float(__builtin_amdgcn_readfirstlane(h.w));
-        const uint16_t* starts = reinterpret_cast<const uint16_t*>(B) - (nbm1 + 1);
-        const uint32_t* T = B + ((M + (1u << d) - 1 + 3) & ~3u);
+        const uint32_t* bucket = B - (nbm1 + 1);   // per bucket: first end | past-last << 16
+        const uint32_t* T = B + ((M + 1 + 3) & ~3u);
         uint32_t x[RG];
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
@@ -536,30 +542,45 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
             bk[g] = b < nbm1 ? b : nbm1;
           }
         }
-        // rank = number of ends <= key: the ends in lower buckets, then a branch-free
-        // binary search of d steps within the row's bucket, the reads of all row groups
-        // of a step issued together.  The ends are padded with 0xFFFFFFFF so that a
-        // search window running past the last end reads only words above every key
-        // below 0xFFFFFFFF.
-        uint32_t pos[RG];
+        // rank = number of ends <= key: the ends in lower buckets, then a binary search
+        // of d steps within the row's bucket, the reads of all row groups of a step
+        // issued together.  A probe past the bucket's last end would read an end of a
+        // higher bucket, above every key of this one: such a probe reads the word
+        // 0xFFFFFFFF after the ends instead, the same word for every lane (one broadcast,
+        // no bank conflict), so a row in an empty bucket costs no conflicting reads.
+        uint32_t pos[RG], lim[RG];
 #pragma unroll
-        for (int g = 0; g < RG; ++g) pos[g] = starts[bk[g]];
+        for (int g = 0; g < RG; ++g) {
+          const uint32_t e = bucket[bk[g]];
+          pos[g] = e & 0xFFFFu;
+          lim[g] = e >> 16;
+        }
 #pragma unroll 1
         for (uint32_t step = (1u << d) >> 1; step > 0; step >>= 1) {
           uint32_t v[RG];
 #pragma unroll
-          for (int g = 0; g < RG; ++g) v[g] = B[pos[g] + step - 1];
+          for (int g = 0; g < RG; ++g) v[g] = B[pos[g] + step <= lim[g] ? pos[g] + step - 1 : M];
 #pragma unroll
           for (int g = 0; g < RG; ++g) pos[g] = v[g] <= x[g] ? pos[g] + step : pos[g];
         }
-        // Only the NaN key 0xFFFFFFFF reaches the padding: its rank is M.
-#pragma unroll
-        for (int g = 0; g < RG; ++g) pos[g] = pos[g] < M ? pos[g] : M;
+        // One table row per row group: SW words, 4 * SW-byte aligned, in one LDS read.
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
           const uint32_t* t = T + pos[g] * SW;
+          if constexpr (SW == 4) {
+            const uint4 r = *reinterpret_cast<const uint4*>(t);
+            acc[g][0] &= r.x;
+            acc[g][1] &= r.y;
+            acc[g][2] &= r.z;
+            acc[g][3] &= r.w;
+          } else if constexpr (SW == 2) {
+            const uint2 r = *reinterpret_cast<const uint2*>(t);
+            acc[g][0] &= r.x;
+            acc[g][1] &= r.y;
+          } else {
 #pragma unroll
-          for (int w = 0; w < SW; ++w) acc[g][w] &= t[w];
+            for (int w = 0; w < SW; ++w) acc[g][w] &= t[w];
+          }
         }
       }
       // Per word of 32 queries and row group: a bit transpose within each half-wave
@@ -582,13 +603,32 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
         }
         nz = (nz | __shfl_xor(nz, 32)) & keep[w];   // lanes c and 32 + c: the two halves
         if (cnt != 0) atomicAdd(&s_cnt[32 * w + (lane & 31)], cnt);
-        // Both halves of every non-zero word, and the chunk's mark (bit g <=> word g
-        // was stored): the words themselves are not cleared before the scan.
+        // Sparse query with a hit in this chunk: lane c takes a slot, lane 32 + c gets
+        // it, both store their halves of all RG words there; no room: nothing stored.
+        const bool sparse = SPARSE && ((sp >> w) & 1u);
+        const bool take = sparse && nz != 0;
+        uint32_t slot = 0;
+        if constexpr (SPARSE) {
+          if (take && lane < 32) slot = atomicAdd(&bp.slot_next[outi[w]], 1u);
+          slot = __shfl(slot, lane & 31);
+        }
+        if (take) {
+          if (slot < bp.sparse_cap[outi[w]]) {
+            const uint64_t at = static_cast<uint64_t>(bp.sparse_base[outi[w]]) + slot;
+            uint32_t* dst = reinterpret_cast<uint32_t*>(bp.pool + at * RG) + (lane >> 5);
 #pragma unroll
-        for (int g = 0; g < RG; ++g)
-          if ((nz >> g) & 1u) out[w][(word0 + g) * 2] = acc[g][w];
-        if (nz != 0 && lane < 32)
-          bp.flags[static_cast<uint64_t>(outi[w]) * bp.n_chunks + row0 / kChunkRows] = static_cast<uint16_t>(nz);
+            for (int g = 0; g < RG; ++g) dst[2 * g] = acc[g][w];
+            if (lane < 32) bp.slots[static_cast<uint64_t>(outi[w]) * bp.n_chunks + row0 / kChunkRows] = slot + 1;
+          }
+        } else if (!sparse) {
+          // Both halves of every non-zero word, and the chunk's mark (bit g <=> word g
+          // was stored): the words themselves are not cleared before the scan.
+#pragma unroll
+          for (int g = 0; g < RG; ++g)
+            if ((nz >> g) & 1u) out[w][(word0 + g) * 2] = acc[g][w];
+          if (nz != 0 && lane < 32)
+            bp.flags[static_cast<uint64_t>(outi[w]) * bp.n_chunks + row0 / kChunkRows] = static_cast<uint16_t>(nz);
+        }
       }
     }
     __syncthreads();
@@ -853,11 +893,13 @@ __global__ void __launch_bounds__(kFinThreads) batch_count_kernel(BatchFinish f)
     kind = (fits_bitmap && (bitmap_bytes < 4 * count || o.buf_bytes < 4 * count)) ? kBatchBitmap
                                                                                  : kBatchIds;
   }
+  const bool over = o.sparse && f.slot_next[o.out_index] > f.sparse_cap[o.out_index];
   if (tid == 0) {
     f.counts_out[q] = count;
     f.kind_out[q] = kind;
+    if (f.over_out) f.over_out[q] = over ? 1u : 0u;
   }
-  if (kind != kBatchIds || count == 0) return;
+  if (kind != kBatchIds || count == 0 || over) return;
   uint32_t carry = 0;
   for (uint64_t t0 = 0; t0 < f.n_tiles; t0 += kFinScan) {
     const uint32_t nt = static_cast<uint32_t>(f.n_tiles - t0 < kFinScan ? f.n_tiles - t0 : kFinScan);
@@ -912,16 +954,28 @@ __device__ __forceinline__ uint64_t scratch_word(const BatchFinish& f, const uin
   return (mark >> (w & ((1u << f.chunk_shift) - 1))) & 1u ? v : 0;
 }
 
+// Word w of a sparse query's scratch: in its chunk's slot if the chunk was stored, else
+// zero.
+__device__ __forceinline__ uint64_t sparse_word(const BatchFinish& f, uint32_t si, uint64_t w) {
+  const uint32_t slot = f.slots[static_cast<uint64_t>(si) * f.n_chunks + (w >> f.chunk_shift)];
+  if (slot == 0) return 0;
+  const uint64_t at = (static_cast<uint64_t>(f.sparse_base[si]) + slot - 1) << f.chunk_shift;
+  return f.pool[at + (w & ((1u << f.chunk_shift) - 1))];
+}
+
 __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) {
   const uint32_t q = blockIdx.y;
   const uint32_t kind = f.kind_out[q];
   const uint64_t count = f.counts_out[q];
   if (kind == kBatchCount || (kind == kBatchIds && count == 0)) return;
   const BatchOut o = f.outs[q];
+  // A sparse query whose slots ran out is answered again by the host.
+  if (o.sparse && f.slot_next[o.out_index] > f.sparse_cap[o.out_index]) return;
   const uint64_t t_beg = static_cast<uint64_t>(blockIdx.x) * kEmitTiles;
   if (t_beg >= f.n_tiles) return;
   const uint64_t t_end = t_beg + kEmitTiles < f.n_tiles ? t_beg + kEmitTiles : f.n_tiles;
-  const uint64_t* words = f.words + static_cast<uint64_t>(o.out_index) * f.n_words;
+  const uint64_t* words = f.words + static_cast<uint64_t>(o.sparse ? 0u : o.out_index) * f.n_words;
+  const bool sparse = o.sparse != 0;
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63;
   const uint32_t wave = tid / 64;
@@ -931,7 +985,7 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
     const uint64_t w_end = t_end * 64 < lim ? t_end * 64 : lim;
     uint64_t* dst = static_cast<uint64_t*>(o.buf);
     for (uint64_t i = t_beg * 64 + tid; i < w_end; i += kFinThreads)
-      dst[i] = scratch_word(f, words, o.out_index, i);
+      dst[i] = sparse ? sparse_word(f, o.out_index, i) : scratch_word(f, words, o.out_index, i);
     return;
   }
   // The tiles' output positions (and the end of the last) into LDS in one pass.
@@ -953,7 +1007,8 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
   // current one is written.
   auto load = [&](uint64_t t) {
     const uint64_t w = t * 64 + lane;
-    return w < f.n_words ? scratch_word(f, words, o.out_index, w) : uint64_t{0};
+    if (w >= f.n_words) return uint64_t{0};
+    return sparse ? sparse_word(f, o.out_index, w) : scratch_word(f, words, o.out_index, w);
   };
   uint64_t t = t_beg + wave;
   uint64_t next = t < t_end && hit(t) ? load(t) : 0;
@@ -1059,13 +1114,15 @@ const void* pick_reg(int d, int w, int rg) {
   return w == 8 ? reg_fn<16, 8, 4>() : reg_fn<16, 4, 4>();
 }
 
-const void* pick_rank(int w, int rg, int sw) {
-#define MDRQ_RANK(W_, RG_)                                                                   \
-  (sw <= 1 ? reinterpret_cast<const void*>(&batch_rank_kernel<W_, RG_, 1>)                    \
-   : sw == 2 ? reinterpret_cast<const void*>(&batch_rank_kernel<W_, RG_, 2>)                  \
-             : reinterpret_cast<const void*>(&batch_rank_kernel<W_, RG_, 4>))
-  if (rg >= 8) return w == 8 ? MDRQ_RANK(8, 8) : MDRQ_RANK(4, 8);
-  return w == 8 ? MDRQ_RANK(8, 4) : MDRQ_RANK(4, 4);
+const void* pick_rank(int w, int rg, int sw, bool sparse) {
+#define MDRQ_RANK(W_, RG_, SP_)                                                              \
+  (sw <= 1 ? reinterpret_cast<const void*>(&batch_rank_kernel<W_, RG_, 1, SP_>)               \
+   : sw == 2 ? reinterpret_cast<const void*>(&batch_rank_kernel<W_, RG_, 2, SP_>)             \
+             : reinterpret_cast<const void*>(&batch_rank_kernel<W_, RG_, 4, SP_>))
+  // Sparse scratch only with 8 row groups per lane (512-row chunks).
+  if (sparse) return w == 8 ? MDRQ_RANK(8, 8, true) : MDRQ_RANK(4, 8, true);
+  if (rg >= 8) return w == 8 ? MDRQ_RANK(8, 8, false) : MDRQ_RANK(4, 8, false);
+  return w == 8 ? MDRQ_RANK(8, 4, false) : MDRQ_RANK(4, 4, false);
 #undef MDRQ_RANK
 }
 
@@ -1109,7 +1166,8 @@ int batch_rows_per_lane(int n_slots, int waves, int rg) {
 namespace {
 const void* pick_scan(int n_slots, int w, int rg, int lds_variant, int sw) {
   if (lds_variant == 1) return pick_lds(w, rg);
-  if (lds_variant == 4) return pick_rank(w, rg >= 8 ? 8 : 4, sw);
+  if (lds_variant == 4) return pick_rank(w, rg >= 8 ? 8 : 4, sw, false);
+  if (lds_variant == 5) return pick_rank(w, 8, sw, true);
   if (lds_variant == 3) return pick_reg(n_slots, w, batch_rows_per_lane(n_slots, w, rg));
   return pick_batch(n_slots, w, batch_rows_per_lane(n_slots, w, rg), lds_variant == 2);
 }
@@ -1128,7 +1186,7 @@ hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int 
                              dim3 grid, size_t lds_bytes, hipStream_t stream, int sw) {
   const int w = waves == 8 ? 8 : 4;
   // Zero the scratch rows, or only their chunk marks (slot-mask variant).
-  const uint64_t n = bp.flags ? (bp.n_chunks * bp.n_out + 3) / 4 : bp.n_words * bp.n_out;
+  const uint64_t n = bp.flags ? bp.n_zero : bp.n_words * bp.n_out;
   if (n) {
     const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
     zero_words_kernel<<<static_cast<uint32_t>(blocks), 256, 0, stream>>>(
@@ -1144,6 +1202,43 @@ hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int 
     if (e != hipSuccess) return e;
   }
   return hipLaunchKernel(fn, grid, dim3(w * 64), args, lds_bytes, stream);
+}
+
+hipError_t batch_launches(const BatchParams& bp, const BatchFinish& f, uint32_t n_queries, int n_slots, int waves,
+                          int rg, int lds_variant, dim3 grid, size_t lds_bytes, int sw, BatchLaunches* L) {
+  const int w = waves == 8 ? 8 : 4;
+  L->bp = bp;
+  L->fin = f;
+  L->zero_ptr = bp.flags ? reinterpret_cast<uint64_t*>(bp.flags) : bp.words;
+  L->zero_n = bp.flags ? bp.n_zero : bp.n_words * bp.n_out;
+  L->zero_args[0] = &L->zero_ptr;
+  L->zero_args[1] = &L->zero_n;
+  L->scan_args[0] = &L->bp;
+  L->fin_args[0] = &L->fin;
+  auto node = [](const void* fn, dim3 g, uint32_t threads, size_t shmem, void** args) {
+    hipKernelNodeParams k{};
+    k.func = const_cast<void*>(fn);
+    k.gridDim = g;
+    k.blockDim = dim3(threads);
+    k.sharedMemBytes = static_cast<unsigned int>(shmem);
+    k.kernelParams = args;
+    k.extra = nullptr;
+    return k;
+  };
+  const uint64_t zb = std::max<uint64_t>(1, std::min<uint64_t>((L->zero_n + 255) / 256, 65536));
+  L->zero = node(reinterpret_cast<const void*>(&zero_words_kernel), dim3(static_cast<uint32_t>(zb)), 256, 0,
+                 L->zero_args);
+  const void* fn = pick_scan(n_slots, w, rg, lds_variant, sw);
+  if (lds_bytes > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+    if (e != hipSuccess) return e;
+  }
+  L->scan = node(fn, grid, static_cast<uint32_t>(w * 64), lds_bytes, L->scan_args);
+  L->count = node(reinterpret_cast<const void*>(&batch_count_kernel), dim3(n_queries), kFinThreads, 0, L->fin_args);
+  const uint32_t chunks = static_cast<uint32_t>(std::max<uint64_t>(1, (f.n_tiles + kEmitTiles - 1) / kEmitTiles));
+  L->emit = node(reinterpret_cast<const void*>(&batch_emit_kernel), dim3(chunks, n_queries), kFinThreads, 0,
+                 L->fin_args);
+  return hipSuccess;
 }
 
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream) {

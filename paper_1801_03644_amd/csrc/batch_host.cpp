@@ -49,14 +49,14 @@ int grow_pinned(void** p, uint64_t* have, uint64_t need) {
   return MDRQ_OK;
 }
 
-// Per-query counts (u64) and kinds (u32) of a batch, in mapped pinned memory that the
-// finish kernel writes directly (no copy back).
+// Per-query counts (u64), kinds (u32) and sparse-scratch overflow marks (u32) of a
+// batch, in mapped pinned memory that the finish kernel writes directly (no copy back).
 int grow_results(BatchWorkspace& ws, uint64_t nq) {
   if (nq <= ws.res_len) return MDRQ_OK;
   if (ws.h_res) (void)hipHostFree(ws.h_res);
   ws.h_res = ws.h_res_dev = nullptr;
   ws.res_len = 0;
-  if (hipHostMalloc(&ws.h_res, nq * 12, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+  if (hipHostMalloc(&ws.h_res, nq * 16, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer(&ws.h_res_dev, ws.h_res, 0) != hipSuccess)
     return fail(MDRQ_ENOMEM, "batch result buffers");
   ws.res_len = nq;
@@ -70,7 +70,11 @@ struct Item {
   uint32_t kind;          // BatchKind
   mdrq_result_t* r;
   std::vector<float> sel; // estimated selectivity of each plan predicate alone
+  double est_rows = -1.0; // MDRQ_Q_SIZE_ESTIMATED: estimated result rows (< 0: none)
 };
+
+// Rows per chunk of the rank variant when some query's scratch is sized by estimate.
+constexpr uint64_t kSparseChunkRows = 512;
 
 uint32_t kind_of(uint32_t mode) {
   switch (mode) {
@@ -88,12 +92,84 @@ uint64_t shape_key(uint64_t n_rows, size_t n_slots, size_t n_queries) {
 }
 
 
+void destroy_graph(BatchWorkspace::Graph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g = BatchWorkspace::Graph{};
+}
+
+// Queue one shared scan by replaying the workspace's graph for its scan kernel (built on
+// first use): the query-table copy, the zeroing, the scan and the finish, with the
+// workspace's events after the copy, after the scan and at the end, every node updated
+// with this batch's arguments, grid and buffers.
+hipError_t launch_shared_graph(BatchWorkspace& ws, const BatchParams& bp, const BatchFinish& fin, uint32_t nq,
+                               int n_slots, int waves, int rg, int variant, dim3 grid, size_t lds, int sw,
+                               uint64_t blob, hipStream_t stream) {
+  BatchLaunches L;
+  hipError_t e = batch_launches(bp, fin, nq, n_slots, waves, rg, variant, grid, lds, sw, &L);
+  if (e != hipSuccess) return e;
+  BatchWorkspace::Graph* g = nullptr;
+  for (BatchWorkspace::Graph& c : ws.graphs)
+    if (c.scan_fn == L.scan.func) g = &c;
+  if (g) {
+    e = hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy, ws.d_blob, ws.h_blob, blob, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->zero, &L.zero);
+    if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->scan, &L.scan);
+    if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->count, &L.count);
+    if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->emit, &L.emit);
+    if (e == hipSuccess) return hipGraphLaunch(g->exec, stream);
+    // An update the instantiated graph does not take: build it anew below.
+    destroy_graph(*g);
+    ws.graphs.erase(ws.graphs.begin() + (g - ws.graphs.data()));
+  }
+  if (ws.graphs.size() >= 8) {
+    destroy_graph(ws.graphs.front());
+    ws.graphs.erase(ws.graphs.begin());
+  }
+  BatchWorkspace::Graph n;
+  n.scan_fn = L.scan.func;
+  hipGraphNode_t prev = nullptr, ev = nullptr;
+  e = hipGraphCreate(&n.graph, 0);
+  if (e == hipSuccess)
+    e = hipGraphAddMemcpyNode1D(&n.copy, n.graph, nullptr, 0, ws.d_blob, ws.h_blob, blob, hipMemcpyHostToDevice);
+  prev = n.copy;
+  if (e == hipSuccess) e = hipGraphAddEventRecordNode(&ev, n.graph, &prev, 1, ws.ev0);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n.zero, n.graph, &ev, 1, &L.zero);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n.scan, n.graph, &n.zero, 1, &L.scan);
+  if (e == hipSuccess) e = hipGraphAddEventRecordNode(&ev, n.graph, &n.scan, 1, ws.ev2);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n.count, n.graph, &ev, 1, &L.count);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n.emit, n.graph, &n.count, 1, &L.emit);
+  if (e == hipSuccess) e = hipGraphAddEventRecordNode(&ev, n.graph, &n.emit, 1, ws.ev1);
+  if (e == hipSuccess) e = hipGraphInstantiate(&n.exec, n.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    destroy_graph(n);
+    return e;
+  }
+  ws.graphs.push_back(n);
+  return hipGraphLaunch(ws.graphs.back().exec, stream);
+}
+
 // Run one shared scan over `items` (union of at most kMaxUnion columns; unions of more
 // than kMaxSlots columns take the LDS variant).
 // ms_out receives the device time of the scan and finish launches.
 int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
-               const BatchConfig& cfg, hipStream_t stream, float* ms_out) {
+               const BatchConfig& cfg_in, hipStream_t stream, float* ms_out, BatchRunStats* st = nullptr) {
   const uint64_t nq = items.size();
+  // Scratch sized by estimate: pool slots per query (0: a full bitmap row).  Any such
+  // query makes the scan a rank-variant scan of 512-row chunks, the layout the serving
+  // loop's admission reserves for.
+  std::vector<uint64_t> cap_of(nq, 0);
+  bool any_sparse = false;
+  for (uint64_t q = 0; q < nq; ++q)
+    if (items[q].kind != kBatchCount && items[q].est_rows >= 0.0) {
+      cap_of[q] = sparse_slots(ds, items[q].est_rows, kSparseChunkRows);
+      any_sparse |= cap_of[q] > 0;
+    }
+  BatchConfig cfg = cfg_in;
+  if (any_sparse) {
+    cfg.lds = 4;
+    cfg.rows_per_lane = 8;
+  }
   const uint64_t n_rows = ds->n_rows;
   const uint64_t nw = n_words(ds);
   const uint64_t n_tiles = (n_rows + kTileRows - 1) / kTileRows;
@@ -147,15 +223,29 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   const bool use_lds = !rank && (cfg.lds == 1 || n_slots > kMaxSlots);
   const bool walk = cfg.lds == 2 && !use_lds;
   const bool reg = cfg.lds == 3 && !use_lds;
-  const int variant = rank ? 4 : use_lds ? 1 : walk ? 2 : reg ? 3 : 0;
+  int variant = rank ? 4 : use_lds ? 1 : walk ? 2 : reg ? 3 : 0;
   // Queries per group: what the configuration asks for, and no more than fits LDS.
   uint64_t group = cfg.group ? cfg.group : nq;
   std::vector<uint32_t> group_first, group_table, table;
   std::vector<BatchOut> outs(nq);
-  uint32_t n_out = 0;
+  uint32_t n_out = 0, n_sparse = 0;
+  if (rank && any_sparse) variant = 5;   // the rank kernel with sparse scratch (512-row chunks)
+  std::vector<uint32_t> sparse_base, sparse_cap;
+  uint64_t pool_slots = 0;
   for (uint64_t q = 0; q < nq; ++q) {
     outs[q].kind = items[q].kind;
-    outs[q].out_index = items[q].kind == kBatchCount ? 0u : n_out++;
+    outs[q].sparse = 0;
+    if (items[q].kind == kBatchCount) {
+      outs[q].out_index = 0;
+    } else if (rank && cap_of[q] > 0) {
+      outs[q].sparse = 1;
+      outs[q].out_index = n_sparse++;
+      sparse_base.push_back(static_cast<uint32_t>(pool_slots));
+      sparse_cap.push_back(static_cast<uint32_t>(cap_of[q]));
+      pool_slots += cap_of[q];
+    } else {
+      outs[q].out_index = n_out++;
+    }
   }
   // Slot-mask variant: fixed-size records (header, slot mask, then key(lo), key(hi)
   // for every register slot), read by scalar loads, so a group is not limited by LDS.
@@ -205,18 +295,19 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     }
     q0 = q1;
   }
-  // Rank variant: per group, per query (kind | output row << 8), per slot a header
-  // (offset of the ends; M | d << 12 | log2(nb) << 16 | shift << 24 | by value << 31;
-  // kmin or vlo; scale), then per slot the tables of append_slot_tables (offsets
-  // relative to the group's start, 4-word aligned).  The bucket starts count the ends
-  // in lower buckets, and no bucket holds more than 2^d - 1 ends (M <= 2 x 128 fits the
-  // header's 12 bits).
+  // Rank variant: per group, per query (kind | sparse << 2 | output row << 8), per slot
+  // a header (offset of the ends; M | d << 12 | log2(nb) << 16 | shift << 24 | by value
+  // << 31; kmin or vlo; scale), then per slot the tables of append_slot_tables (offsets
+  // relative to the group's start, 4-word aligned).  The bucket words hold the range of
+  // each bucket's ends, and no bucket holds more than 2^d - 1 ends (M <= 2 x 128 fits
+  // the header's 12 bits and the bucket words' 16).
   // The groups' tables are independent: each is built into its own vector, on several
   // host threads when there are 24 or more slot tables (about 10 us each), then
   // appended in group order.
   std::vector<uint64_t> rank_q0;
   for (uint64_t q0 = 0; rank && q0 < nq; q0 += rank_group) rank_q0.push_back(q0);
   std::vector<std::vector<uint32_t>> rank_tables(rank_q0.size());
+  std::atomic<uint64_t> used_pairs{0};   // (group, column) pairs with a predicate
   auto build_rank_group = [&](size_t gi) {
     const uint64_t q0 = rank_q0[gi];
     const uint64_t q1 = std::min<uint64_t>(nq, q0 + rank_group);
@@ -224,7 +315,8 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     std::vector<uint32_t>& table = rank_tables[gi];
     const uint32_t hq = static_cast<uint32_t>(align4(gq));  // headers, 16-byte aligned
     table.assign(hq + 4 * static_cast<uint64_t>(n_slots), 0u);
-    for (uint64_t q = q0; q < q1; ++q) table[q - q0] = outs[q].kind | (outs[q].out_index << 8);
+    for (uint64_t q = q0; q < q1; ++q)
+      table[q - q0] = outs[q].kind | (outs[q].out_index << 8) | (outs[q].sparse ? 4u : 0u);
     // Per slot and query: (key(lo), key(hi)) of its predicate, if any; a query without
     // predicates carries the always-true [key(-inf), key(+inf)] on slot 0.
     std::vector<std::vector<KeyInterval>> iv(n_slots, std::vector<KeyInterval>(gq));
@@ -269,6 +361,9 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       return words;
     };
     if (choose(kRankBuckets) + hq > kRankLdsWords) choose(256);
+    uint64_t used = 0;
+    for (int sl = 0; sl < n_slots; ++sl) used += ends_of[sl].empty() ? 0 : 1;
+    used_pairs += used;
     for (int sl = 0; sl < n_slots; ++sl) {
       const std::vector<uint32_t>& ends = ends_of[sl];
       const uint32_t M = static_cast<uint32_t>(ends.size());
@@ -377,7 +472,8 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     // LDS-staged variant rather than failing if it ever did.
     BatchConfig other = cfg;
     other.lds = 1;
-    return run_shared(ds, ws, items, other, stream, ms_out);
+    for (Item& it : items) it.est_rows = -1.0;
+    return run_shared(ds, ws, items, other, stream, ms_out, st);
   }
 
   // Outputs: device buffers directly, host buffers through device staging.
@@ -408,15 +504,14 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     }
   }
 
-  // Device buffers.
-  rc = grow_device(&ws.d_words, &ws.d_words_len, std::max<uint64_t>(1, n_out) * nw + 1, "batch bitmaps");
-  if (rc) return rc;
+  // Device buffers (the bitmap scratch is laid out below, once the chunk size is known).
+  const int rank_rg = cfg.rows_per_lane >= 8 ? 8 : 4;
   rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, nq * n_tiles + 1, "batch tile counts");
   if (rc) return rc;
   rc = grow_results(ws, nq);
   if (rc) return rc;
   // Blob: table, group_first, group_table (uint32), then BatchOut records (8-aligned).
-  const uint64_t words_u32 = table.size() + group_first.size() + group_table.size();
+  const uint64_t words_u32 = table.size() + group_first.size() + group_table.size() + 2 * n_sparse;
   const uint64_t outs_off = (words_u32 * 4 + 15) / 16 * 16;
   const uint64_t blob = outs_off + nq * sizeof(BatchOut);
   rc = grow_pinned(&ws.h_blob, &ws.h_blob_bytes, blob);
@@ -427,6 +522,11 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   std::memcpy(hb, table.data(), table.size() * 4);
   std::memcpy(hb + table.size(), group_first.data(), group_first.size() * 4);
   std::memcpy(hb + table.size() + group_first.size(), group_table.data(), group_table.size() * 4);
+  uint32_t* hsp = hb + table.size() + group_first.size() + group_table.size();
+  if (n_sparse) {
+    std::memcpy(hsp, sparse_base.data(), n_sparse * 4);
+    std::memcpy(hsp + n_sparse, sparse_cap.data(), n_sparse * 4);
+  }
   std::memcpy(static_cast<uint8_t*>(ws.h_blob) + outs_off, outs.data(), nq * sizeof(BatchOut));
   const uint32_t* db = static_cast<const uint32_t*>(ws.d_blob);
 
@@ -443,6 +543,9 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   bp.n_chunks = 0;
   bp.n_out = n_out;
   bp.tile_counts = ws.d_tile_counts;
+  const uint32_t* dsp = db + table.size() + group_first.size() + group_table.size();
+  bp.sparse_base = dsp;
+  bp.sparse_cap = dsp + n_sparse;
   for (int s = 0; s < n_slots; ++s) bp.slot_cols[s] = ds->cols[slot_dim[s]];
   BatchFinish fin{};
   fin.n_tiles = n_tiles;
@@ -455,6 +558,9 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   fin.outs = reinterpret_cast<const BatchOut*>(static_cast<const uint8_t*>(ws.d_blob) + outs_off);
   fin.counts_out = static_cast<uint64_t*>(ws.h_res_dev);
   fin.kind_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws.h_res_dev) + nq * 8);
+  fin.over_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws.h_res_dev) + nq * 12);
+  fin.sparse_base = bp.sparse_base;
+  fin.sparse_cap = bp.sparse_cap;
 
   int waves = cfg.waves == 8 ? 8 : 4;
   int rg;
@@ -475,23 +581,42 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     lds = need(rg);
     if (lds > device().lds) return fail(MDRQ_ENOTSUP, "shared scan: union keys do not fit LDS");
   } else if (rank) {
-    rg = cfg.rows_per_lane >= 8 ? 8 : 4;
-    if (waves == 8) rg = std::min(rg, 8);
+    rg = rank_rg;
     lds = max_group_words * 4;
   } else {
     rg = batch_rows_per_lane(std::max(1, n_slots), waves, cfg.rows_per_lane);
     lds = max_group_words * 4;
   }
-  if (n_out && (rank || (reg && batch_reg_uses_marks(static_cast<int>(reg_slots))))) {  // marks, not zeroing
-    const uint64_t chunk_rows = 64 * static_cast<uint64_t>(rg);
-    const uint64_t n_chunks = (n_rows + chunk_rows - 1) / chunk_rows;
-    rc = grow_device(&ws.d_flags, &ws.d_flags_len, (n_chunks * n_out + 3) / 4 + 1, "batch chunk marks");
-    if (rc) return rc;
-    bp.flags = reinterpret_cast<uint16_t*>(ws.d_flags);
+  // Bitmap scratch, one allocation: the dense queries' rows, the sparse queries' pool
+  // slots, then (variants with marks) the dense rows' chunk marks, the sparse queries'
+  // slot tables and slot counters, which are zeroed before the scan.  The serving loop
+  // admits requests by these sizes (request_scratch_bytes bounds each query's part).
+  const bool marks = rank || (reg && batch_reg_uses_marks(static_cast<int>(reg_slots)));
+  const uint64_t rows_words = static_cast<uint64_t>(n_out) * nw + pool_slots * static_cast<uint64_t>(rg);
+  const uint64_t chunk_rows = 64 * static_cast<uint64_t>(rg);
+  const uint64_t n_chunks = (n_rows + chunk_rows - 1) / chunk_rows;
+  const uint64_t marks_words = marks ? (n_chunks * n_out + 3) / 4 : 0;
+  const uint64_t slots_words = (n_chunks * n_sparse + 1) / 2;
+  const uint64_t next_words = (static_cast<uint64_t>(n_sparse) + 1) / 2;
+  rc = grow_device(&ws.d_words, &ws.d_words_len, rows_words + marks_words + slots_words + next_words + 1,
+                   "batch bitmaps");
+  if (rc) return rc;
+  bp.words = ws.d_words;
+  fin.words = ws.d_words;
+  bp.pool = ws.d_words + static_cast<uint64_t>(n_out) * nw;
+  fin.pool = bp.pool;
+  if ((n_out || n_sparse) && marks) {
+    uint64_t* fl = ws.d_words + rows_words;
+    bp.flags = reinterpret_cast<uint16_t*>(fl);
     bp.n_chunks = n_chunks;
+    bp.slots = reinterpret_cast<uint32_t*>(fl + marks_words);
+    bp.slot_next = reinterpret_cast<uint32_t*>(fl + marks_words + slots_words);
+    bp.n_zero = marks_words + slots_words + next_words;
     fin.flags = bp.flags;
     fin.n_chunks = n_chunks;
     fin.chunk_shift = static_cast<uint32_t>(__builtin_ctz(static_cast<unsigned>(rg)));
+    fin.slots = bp.slots;
+    fin.slot_next = bp.slot_next;
   }
   const int per_cu = batch_blocks_per_cu(std::max(1, n_slots), waves, rg, variant, lds, rank_sw);
   const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
@@ -499,19 +624,37 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
 
   if (!ws.ev0) MDRQ_HIP(hipEventCreate(&ws.ev0), "hipEventCreate");
   if (!ws.ev1) MDRQ_HIP(hipEventCreate(&ws.ev1), "hipEventCreate");
-  MDRQ_HIP(hipMemcpyAsync(ws.d_blob, ws.h_blob, blob, hipMemcpyHostToDevice, stream),
-           "copy query table");
-  MDRQ_HIP(hipEventRecord(ws.ev0, stream), "hipEventRecord");
-  if (n_tiles > 0)
-    MDRQ_HIP(launch_batch_scan(bp, std::max(1, n_slots), waves, rg, variant,
-                               dim3(static_cast<uint32_t>(gx), n_groups), lds, stream, rank_sw),
-             "shared scan launch");
-  MDRQ_HIP(launch_batch_finish(fin, static_cast<uint32_t>(nq), stream), "batch finish launch");
-  MDRQ_HIP(hipEventRecord(ws.ev1, stream), "hipEventRecord");
+  if (!ws.ev2) MDRQ_HIP(hipEventCreate(&ws.ev2), "hipEventCreate");
+  if (ds->graph_batch && n_tiles > 0) {
+    MDRQ_HIP(launch_shared_graph(ws, bp, fin, static_cast<uint32_t>(nq), std::max(1, n_slots), waves, rg, variant,
+                                 dim3(static_cast<uint32_t>(gx), n_groups), lds, rank_sw, blob, stream),
+             "shared scan graph");
+  } else {
+    MDRQ_HIP(hipMemcpyAsync(ws.d_blob, ws.h_blob, blob, hipMemcpyHostToDevice, stream),
+             "copy query table");
+    MDRQ_HIP(hipEventRecord(ws.ev0, stream), "hipEventRecord");
+    if (n_tiles > 0)
+      MDRQ_HIP(launch_batch_scan(bp, std::max(1, n_slots), waves, rg, variant,
+                                 dim3(static_cast<uint32_t>(gx), n_groups), lds, stream, rank_sw),
+               "shared scan launch");
+    MDRQ_HIP(hipEventRecord(ws.ev2, stream), "hipEventRecord");
+    MDRQ_HIP(launch_batch_finish(fin, static_cast<uint32_t>(nq), stream), "batch finish launch");
+    MDRQ_HIP(hipEventRecord(ws.ev1, stream), "hipEventRecord");
+  }
   MDRQ_HIP(hipStreamSynchronize(stream), "shared scan completion");
-  float ms = 0.f;
+  float ms = 0.f, scan_ms = 0.f;
   MDRQ_HIP(hipEventElapsedTime(&ms, ws.ev0, ws.ev1), "hipEventElapsedTime");
+  MDRQ_HIP(hipEventElapsedTime(&scan_ms, ws.ev0, ws.ev2), "hipEventElapsedTime");
   if (ms_out) *ms_out = ms;
+  {
+    // Work of the scan: rows looked up per (group, column) in the rank variant, column
+    // bytes read (each group reads its own columns in the rank variant).
+    std::lock_guard<std::mutex> lock(ds->stat_mu);
+    const uint64_t pairs = rank ? used_pairs.load() : static_cast<uint64_t>(n_slots);
+    ds->batch_lookups += rank ? n_rows * pairs : 0;
+    ds->batch_column_bytes += 4 * n_rows * pairs;
+    ds->batch_scan_ms += scan_ms;
+  }
 
   // The finish kernel wrote the counts and kinds into the mapped pinned buffer.
   const volatile uint64_t* counts = static_cast<const volatile uint64_t*>(ws.h_res);
@@ -542,6 +685,28 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     }
     if (kind != kBatchCount && r->mem == MDRQ_MEM_HOST && bytes)
       MDRQ_HIP(hipMemcpy(r->buf, outs[q].buf, bytes, hipMemcpyDeviceToHost), "copy result to host");
+  }
+  // Queries whose estimate was too low for their scratch: answered again alone (the
+  // count above was exact already; the scan repeats it).
+  const volatile uint32_t* over =
+      reinterpret_cast<const volatile uint32_t*>(static_cast<const uint8_t*>(ws.h_res) + nq * 12);
+  uint64_t n_reruns = 0;
+  for (uint64_t q = 0; q < nq; ++q) {
+    if (!outs[q].sparse || !over[q]) continue;
+    Item& it = items[q];
+    it.r->mode = it.plan.mode == kBitmap ? MDRQ_OUT_BITMAP : it.plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
+    rc = run_query(ds, it.plan, it.r, stream);
+    if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
+    ++n_reruns;
+  }
+  if (st) {
+    st->sparse += n_sparse;
+    st->reruns += n_reruns;
+  }
+  if (n_sparse) {
+    std::lock_guard<std::mutex> lock(ds->stat_mu);
+    ds->sized_queries += n_sparse;
+    ds->sized_reruns += n_reruns;
   }
   return MDRQ_OK;
 }
@@ -734,15 +899,40 @@ std::vector<BatchConfig> candidates(uint64_t nq, int n_slots, int variant) {
 
 }  // namespace
 
+uint64_t sparse_slots(const mdrq_dataset* ds, double est_rows, uint64_t chunk_rows) {
+  if (!(est_rows >= 0.0)) return 0;
+  const uint64_t n_chunks = (ds->n_rows + chunk_rows - 1) / chunk_rows;
+  // A chunk with a hit holds at least one result row: chunks <= rows.
+  const double want = std::ceil(est_rows * static_cast<double>(ds->reserve_ppm) * 1e-6) + 64.0;
+  const uint64_t slots = want >= static_cast<double>(n_chunks) ? n_chunks : static_cast<uint64_t>(want);
+  const uint64_t sparse_bytes = n_chunks * 4 + slots * (chunk_rows / 64) * 8;
+  const uint64_t dense_bytes = n_words(ds) * 8 + n_chunks * 2;
+  return sparse_bytes < dense_bytes ? slots : 0;
+}
+
+uint64_t request_scratch_bytes(const mdrq_dataset* ds, const mdrq_result_t& r, double est_rows) {
+  if (r.mode == MDRQ_OUT_COUNT) return 0;
+  const uint64_t slots = sparse_slots(ds, est_rows, kSparseChunkRows);
+  const uint64_t n_chunks = (ds->n_rows + kSparseChunkRows - 1) / kSparseChunkRows;
+  if (slots) return n_chunks * 4 + slots * (kSparseChunkRows / 64) * 8 + 16;
+  // A bitmap row and its chunk marks at the smallest chunk (256 rows).
+  return n_words(ds) * 8 + ((ds->n_rows + 255) / 256) * 2 + 16;
+}
+
 // Answer a batch: canonicalise each query, answer empty ones without a launch, run
 // queries that cannot share a scan (more than max_union() predicates) alone, and group
 // the rest into shared scans whose union of columns fits the register slots.
 int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs,
-              hipStream_t stream, BatchWorkspace* wsp, bool tune, BatchRunStats* st) {
+              hipStream_t stream, BatchWorkspace* wsp, bool tune, BatchRunStats* st, const float* est_in) {
   BatchWorkspace& ws = wsp ? *wsp : ds->batch;
-  std::vector<float> est;  // estimated selectivities, for MDRQ_Q_ORDER_ESTIMATED
-  int erc = estimate_for_order(ds, qs, n, est);
-  if (erc) return erc;
+  // Estimated selectivities, for MDRQ_Q_ORDER_ESTIMATED and MDRQ_Q_SIZE_ESTIMATED.
+  std::vector<float> est;
+  if (est_in) {
+    est.assign(est_in, est_in + static_cast<size_t>(n) * (ds->n_dims + 1));
+  } else {
+    int erc = estimate_for_order(ds, qs, n, est);
+    if (erc) return erc;
+  }
   auto plan_of = [&](uint32_t i) {
     Plan plan = make_plan(ds, &qs[i], &rs[i]);
     if (!est.empty() && (qs[i].flags & MDRQ_Q_ORDER_ESTIMATED))
@@ -782,6 +972,8 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
       }
     }
     shared.push_back(Item{i, std::move(plan), kind_of(rs[i].mode), &rs[i], std::move(sel)});
+    if (row && (qs[i].flags & MDRQ_Q_SIZE_ESTIMATED))
+      shared.back().est_rows = static_cast<double>(row[ds->n_dims]) * static_cast<double>(ds->n_rows);
   }
   // Grouping into shared scans whose union of columns fits the register slots:
   // best-fit decreasing -- queries with the most columns first, each into the open
@@ -822,7 +1014,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     if (used > kMaxSlots && !ds->batch_rows) cfg.rows_per_lane = used > 32 ? 1 : 2;
     float ms = 0.f;
     if (fixed) {
-      int rc = run_shared(ds, ws, batch, cfg, stream, &ms);
+      int rc = run_shared(ds, ws, batch, cfg, stream, &ms, st);
       if (rc) return rc;
     } else {
       const uint64_t key = shape_key(ds->n_rows, static_cast<size_t>(used), batch.size());
@@ -844,7 +1036,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
             }
       }
       if (known || !tune) {
-        int rc = run_shared(ds, ws, batch, known ? known_cfg : cfg, stream, &ms);
+        int rc = run_shared(ds, ws, batch, known ? known_cfg : cfg, stream, &ms, st);
         if (rc) return rc;
       } else {
         // Every candidate computes the same exact results; keep the fastest.
@@ -886,17 +1078,12 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
   return MDRQ_OK;
 }
 
-int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queries, uint64_t max_rows) {
-  const uint64_t nw = n_words(ds);
+int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queries, uint64_t scratch_bytes) {
   const uint64_t n_tiles = (ds->n_rows + kTileRows - 1) / kTileRows;
   const uint64_t nq = max_queries;
-  int rc = grow_device(&ws.d_words, &ws.d_words_len, std::max<uint64_t>(1, max_rows) * nw + 1, "batch bitmaps");
-  if (rc) return rc;
-  // Chunk marks of the slot-mask and rank variants, for the smallest chunk (4 row groups
-  // of 64).
-  rc = grow_device(&ws.d_flags, &ws.d_flags_len,
-                   ((ds->n_rows + 255) / 256 * std::max<uint64_t>(1, max_rows) + 3) / 4 + 1,
-                   "batch chunk marks");
+  // The bitmap scratch: dense rows, sparse pools, marks and slot tables of a batch whose
+  // requests' request_scratch_bytes sum to at most scratch_bytes.
+  int rc = grow_device(&ws.d_words, &ws.d_words_len, (scratch_bytes + 7) / 8 + 8, "batch bitmaps");
   if (rc) return rc;
   rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, nq * n_tiles + 1, "batch tile counts");
   if (rc) return rc;
@@ -920,12 +1107,13 @@ void free_batch(BatchWorkspace& ws) {
   if (ws.d_blob) (void)hipFree(ws.d_blob);
   if (ws.h_blob) (void)hipHostFree(ws.h_blob);
   if (ws.d_words) (void)hipFree(ws.d_words);
-  if (ws.d_flags) (void)hipFree(ws.d_flags);
   if (ws.d_tile_counts) (void)hipFree(ws.d_tile_counts);
   if (ws.h_res) (void)hipHostFree(ws.h_res);
   if (ws.d_stage) (void)hipFree(ws.d_stage);
   if (ws.ev0) (void)hipEventDestroy(ws.ev0);
   if (ws.ev1) (void)hipEventDestroy(ws.ev1);
+  if (ws.ev2) (void)hipEventDestroy(ws.ev2);
+  for (BatchWorkspace::Graph& g : ws.graphs) destroy_graph(g);
   ws = BatchWorkspace{};
 }
 

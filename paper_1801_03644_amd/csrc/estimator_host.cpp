@@ -459,7 +459,8 @@ int estimate_for_order(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, std
   mdrq_estimator* e = ds->estimator;
   if (!e) return MDRQ_OK;
   bool any = false;
-  for (uint32_t i = 0; i < n && !any; ++i) any = (qs[i].flags & MDRQ_Q_ORDER_ESTIMATED) != 0;
+  for (uint32_t i = 0; i < n && !any; ++i)
+    any = (qs[i].flags & (MDRQ_Q_ORDER_ESTIMATED | MDRQ_Q_SIZE_ESTIMATED)) != 0;
   if (!any) return MDRQ_OK;
   std::lock_guard<std::mutex> lock(e->mu);
   est.resize(static_cast<size_t>(n) * e->O);
@@ -831,6 +832,115 @@ int mdrq_estimator_predict(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n
     if (rc) return rc;
     std::lock_guard<std::mutex> lock(e->mu);
     return n == 1 ? predict_one(e, qs, sel) : predict_locked(e, qs, n, sel);
+  });
+}
+
+int mdrq_estimator_activations(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, uint16_t* h1,
+                               uint16_t* h2, float* y) {
+  return guarded([&]() -> int {
+    clear_error();
+    if (!e) return fail(MDRQ_EINVAL, "estimator is NULL");
+    if (n > kPredictChunk) return fail(MDRQ_EINVAL, "at most 65536 queries per activation call");
+    int rc = check_queries(e, qs, n);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(e->mu);
+    const DataLayout dl = data_layout(e, n, false);
+    if ((rc = e->data.grow(dl.end)) || (rc = e->ensure_work(n))) return rc;
+    const auto L = e->layout(e->work_rows);
+    build_qd(e, qs, n);
+    EST_CHECK(hipMemcpy(e->data.as<float>(dl.qd), e->h_qd.data(), e->h_qd.size() * 4, hipMemcpyHostToDevice),
+              "estimator query upload");
+    rc = features(e, e->data.as<float>(dl.qd), n, e->work.as<uint16_t>(L.X), e->work.as<float>(L.Bs));
+    if (rc) return rc;
+    rc = forward(e, n);
+    if (rc) return rc;
+    const uint64_t nh = static_cast<uint64_t>(n) * e->H;
+    if (h1) EST_CHECK(hipMemcpy(h1, e->work.as<uint16_t>(L.H1), nh * 2, hipMemcpyDeviceToHost), "activation download");
+    if (h2) EST_CHECK(hipMemcpy(h2, e->work.as<uint16_t>(L.H2), nh * 2, hipMemcpyDeviceToHost), "activation download");
+    if (y)
+      EST_CHECK(hipMemcpy(y, e->work.as<float>(L.Y), static_cast<uint64_t>(n) * e->O * 4, hipMemcpyDeviceToHost),
+                "output download");
+    return MDRQ_OK;
+  });
+}
+
+int mdrq_estimator_gate(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, const float* sel, uint32_t* kept) {
+  return guarded([&]() -> int {
+    clear_error();
+    if (!e) return fail(MDRQ_EINVAL, "estimator is NULL");
+    int rc = check_queries(e, qs, n);
+    if (rc) return rc;
+    std::vector<uint32_t> present;
+    rc = check_labels(e, sel, n, present);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(e->mu);
+    const uint32_t O = e->O;
+    const double ln_rows = std::log(static_cast<double>(e->n_rows));
+    const double floor = 1.0 / static_cast<double>(e->n_rows);
+    // Per output: squared errors on the log scale of the network's estimate and of the
+    // base estimate alone, over the targets present.
+    std::vector<double> err_net(O, 0.0), err_base(O, 0.0);
+    std::vector<float> y, base;
+    for (uint32_t at = 0; at < n; at += kPredictChunk) {
+      const uint32_t rows = std::min(kPredictChunk, n - at);
+      const DataLayout dl = data_layout(e, rows, false);
+      if ((rc = e->data.grow(dl.end)) || (rc = e->ensure_work(rows))) return rc;
+      const auto L = e->layout(e->work_rows);
+      build_qd(e, qs + at, rows);
+      EST_CHECK(hipMemcpy(e->data.as<float>(dl.qd), e->h_qd.data(), e->h_qd.size() * 4, hipMemcpyHostToDevice),
+                "estimator query upload");
+      rc = features(e, e->data.as<float>(dl.qd), rows, e->work.as<uint16_t>(L.X), e->work.as<float>(L.Bs));
+      if (rc) return rc;
+      rc = forward(e, rows);
+      if (rc) return rc;
+      y.resize(static_cast<size_t>(rows) * O);
+      base.resize(static_cast<size_t>(rows) * O);
+      EST_CHECK(hipMemcpy(y.data(), e->work.as<float>(L.Y), y.size() * 4, hipMemcpyDeviceToHost), "output download");
+      EST_CHECK(hipMemcpy(base.data(), e->work.as<float>(L.Bs), base.size() * 4, hipMemcpyDeviceToHost),
+                "base download");
+      for (uint32_t i = 0; i < rows; ++i)
+        for (uint32_t j = 0; j < O; ++j) {
+          const double s = sel[static_cast<size_t>(at + i) * O + j];
+          if (s < 0.0) continue;
+          const double t = -std::log(std::max(s, floor)) / ln_rows;
+          // Estimates are clamped to [0, 1] on the log scale, as predictions are.
+          const double yn = std::min(1.0, std::max(0.0, static_cast<double>(y[static_cast<size_t>(i) * O + j])));
+          const double yb = std::min(1.0, std::max(0.0, static_cast<double>(base[static_cast<size_t>(i) * O + j])));
+          err_net[j] += (yn - t) * (yn - t);
+          err_base[j] += (yb - t) * (yb - t);
+        }
+    }
+    // Remove the correction of every output it does not improve: its column of W3 and
+    // its entry of b3 become zero (and their Adam moments with them).
+    std::vector<float> w3(static_cast<size_t>(e->H) * O), b3(O);
+    EST_CHECK(hipMemcpy(w3.data(), e->params() + e->oW3, w3.size() * 4, hipMemcpyDeviceToHost), "parameter download");
+    EST_CHECK(hipMemcpy(b3.data(), e->params() + e->ob3, b3.size() * 4, hipMemcpyDeviceToHost), "parameter download");
+    std::vector<float> zeros_w(w3.size(), 0.0f), zeros_b(O, 0.0f);
+    for (uint32_t j = 0; j < O; ++j) {
+      const bool keep = err_net[j] < err_base[j];
+      if (kept) kept[j] = keep ? 1u : 0u;
+      if (keep) continue;
+      for (uint32_t h = 0; h < e->H; ++h) w3[static_cast<size_t>(h) * O + j] = 0.0f;
+      b3[j] = 0.0f;
+    }
+    for (float* m : {e->adam_m(), e->adam_v()}) {
+      std::vector<float> mw(w3.size()), mb(O);
+      EST_CHECK(hipMemcpy(mw.data(), m + e->oW3, mw.size() * 4, hipMemcpyDeviceToHost), "moment download");
+      EST_CHECK(hipMemcpy(mb.data(), m + e->ob3, mb.size() * 4, hipMemcpyDeviceToHost), "moment download");
+      for (uint32_t j = 0; j < O; ++j) {
+        if (err_net[j] < err_base[j]) continue;
+        for (uint32_t h = 0; h < e->H; ++h) mw[static_cast<size_t>(h) * O + j] = 0.0f;
+        mb[j] = 0.0f;
+      }
+      EST_CHECK(hipMemcpy(m + e->oW3, mw.data(), mw.size() * 4, hipMemcpyHostToDevice), "moment upload");
+      EST_CHECK(hipMemcpy(m + e->ob3, mb.data(), mb.size() * 4, hipMemcpyHostToDevice), "moment upload");
+    }
+    EST_CHECK(hipMemcpy(e->params() + e->oW3, w3.data(), w3.size() * 4, hipMemcpyHostToDevice), "parameter upload");
+    EST_CHECK(hipMemcpy(e->params() + e->ob3, b3.data(), b3.size() * 4, hipMemcpyHostToDevice), "parameter upload");
+    rc = refresh_bf16(e);
+    if (rc) return rc;
+    EST_CHECK(hipDeviceSynchronize(), "estimator gate");
+    return MDRQ_OK;
   });
 }
 

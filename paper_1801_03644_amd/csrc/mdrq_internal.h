@@ -81,6 +81,9 @@ hipError_t launch_scan(const ScanParams& p, uint32_t mode, int unroll, int grid,
                        hipStream_t stream);
 hipError_t launch_compact(const CompactParams& c, int unroll, int grid, hipStream_t stream);
 int scan_tile_rows(int unroll);
+// The kernels behind launch_scan / launch_compact (for graph kernel nodes).
+const void* scan_kernel_fn(uint32_t mode, int unroll);
+const void* compact_kernel_fn(int unroll);
 // Workgroups per CU the scan kernel can keep resident (occupancy).
 int scan_blocks_per_cu(uint32_t mode, int unroll);
 
@@ -92,6 +95,17 @@ struct ProbeParams {
   const float* cols[MDRQ_MAX_DIMS];
 };
 hipError_t launch_probe(const ProbeParams& p, int unroll, int grid, hipStream_t stream);
+
+// Early-break read measurement: 128-byte column lines one query's scan must read.
+struct LinesParams {
+  uint64_t n_rows;
+  uint32_t n_preds;
+  uint32_t early_out;
+  const uint32_t* order;        // device evaluation order (null: as given)
+  unsigned long long* lines;    // device: incremented by the line count
+  DevPred preds[MDRQ_MAX_DIMS];
+};
+hipError_t launch_lines(const LinesParams& p, int grid, hipStream_t stream);
 
 // ---------------------------------------------------------------- batched scan
 
@@ -120,14 +134,29 @@ struct BatchParams {
   // word g, and the finish takes unmarked words as zero.
   uint16_t* flags;
   uint64_t n_chunks;            // chunks per output row
+  uint64_t n_zero;              // with flags: 64-bit words zeroed from flags on (marks,
+                                // then slot tables and slot counters)
+  // Sparse scratch (rank variant): a query whose table word has bit 2 set stores only
+  // its chunks with a hit, each in a slot of 64-row words taken from its own region of
+  // the pool; output row r of such a query is its sparse index.  slot_next[r] counts
+  // the slots taken (zeroed before the scan); slots[r * n_chunks + chunk] is the slot
+  // + 1 of a stored chunk, 0 otherwise (zeroed); a chunk past sparse_cap[r] slots is
+  // not stored, and the query is answered again by the single-query scan.
+  uint64_t* pool;               // sparse words, sparse_base[r] + slot slots of RG words
+  uint32_t* slots;
+  uint32_t* slot_next;
+  const uint32_t* sparse_base;  // first pool slot of each sparse query
+  const uint32_t* sparse_cap;   // pool slots of each sparse query
   const float* slot_cols[kMaxUnion];
 };
 
 struct BatchOut {
   uint32_t kind;                // BatchKind; kBatchAuto is resolved on the device
-  uint32_t out_index;           // row of the bitmap scratch
+  uint32_t out_index;           // row of the bitmap scratch, or the sparse index
   void* buf;                    // ids or bitmap words (device)
   uint64_t buf_bytes;
+  uint32_t sparse;              // 1: the scratch of this query is sparse (BatchParams)
+  uint32_t pad;
 };
 
 struct BatchFinish {
@@ -142,6 +171,14 @@ struct BatchFinish {
   const BatchOut* outs;
   uint64_t* counts_out;         // [query] exact count
   uint32_t* kind_out;           // [query] kind used (kBatchAuto resolved)
+  // Sparse scratch (see BatchParams); over_out[query] = 1 when its slots ran out (its
+  // output is then not written: the host answers it again).
+  const uint64_t* pool;
+  const uint32_t* slots;
+  const uint32_t* slot_next;
+  const uint32_t* sparse_base;
+  const uint32_t* sparse_cap;
+  uint32_t* over_out;
 };
 
 uint32_t batch_key(float x);
@@ -153,8 +190,9 @@ int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t 
 // fixed-size query records (slot mask, bounds per slot) read with scalar loads and the
 // range test as a median of three; 4: per group of 32 * sw queries, each row's rank
 // among the group's interval ends and per-rank query bitsets (tables in LDS, any union
-// that fits); 1: union keys staged in LDS (n_slots <= kMaxUnion, query table read with
-// scalar loads).  lds_bytes: the dynamic LDS of the launch.
+// that fits); 5: the same with sparse scratch for the queries flagged so (rg 8); 1: union
+// keys staged in LDS (n_slots <= kMaxUnion, query table read with scalar loads).
+// lds_bytes: the dynamic LDS of the launch.
 hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, int lds_variant,
                              dim3 grid, size_t lds_bytes, hipStream_t stream, int sw = 1);
 // Register slots of the slot-mask variant for a union of n_slots columns (4, 8, 12 or 16):
@@ -166,6 +204,21 @@ constexpr bool batch_reg_uses_marks(int reg_slots) { return reg_slots <= 8; }
 // LDS bytes the LDS variant stages keys in: waves x slots x rows per lane x 64 x 4.
 size_t batch_lds_key_bytes(int n_slots, int waves, int rg);
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream);
+// The kernel launches of one shared scan (zeroing, scan, count, emit) as graph kernel
+// node parameters, whose arguments point into *L (kept alive while they are used).
+struct BatchLaunches {
+  uint64_t* zero_ptr;
+  uint64_t zero_n;
+  BatchParams bp;
+  BatchFinish fin;
+  void* zero_args[2];
+  void* scan_args[1];
+  void* fin_args[1];
+  hipKernelNodeParams zero, scan, count, emit;
+};
+hipError_t batch_launches(const BatchParams& bp, const BatchFinish& f, uint32_t n_queries, int n_slots, int waves,
+                          int rg, int lds_variant, dim3 grid, size_t lds_bytes, int sw, BatchLaunches* L);
+
 
 // ---------------------------------------------------------------- learned estimator
 
@@ -339,17 +392,30 @@ struct BatchRunStats {
   uint64_t column_bytes = 0;
   double device_ms = 0.0;
   uint64_t alone = 0;          // queries answered by their own scan (cheaper for few)
+  uint64_t sparse = 0;         // queries whose scratch was sized by their estimate
+  uint64_t reruns = 0;         // of those, answered again (the estimate was too low)
 };
+// Scratch of one query in a shared scan with estimated sizing: pool slots (chunks with a
+// hit) reserved for an estimated result of est_rows rows, 0 when the worst case (a full
+// bitmap row) is no larger.  chunk_rows: rows per chunk.
+uint64_t sparse_slots(const mdrq_dataset* ds, double est_rows, uint64_t chunk_rows);
+// Bytes of scratch a request reserves in serving (an upper bound on what the shared
+// scan lays out for it): a bitmap row and its chunk marks, or, sized by an estimate,
+// the slot table and pool slots; 0 for count-only requests.
+uint64_t request_scratch_bytes(const mdrq_dataset* ds, const mdrq_result_t& r, double est_rows);
 // Batched path (batch_host.cpp).  ws: the workspace to use (null: the dataset's own);
 // tune: a new batch shape may be autotuned (otherwise a known or default configuration
 // is used).  Calls with different workspaces may run concurrently.
+// est_in (optional): the attached estimator's estimates of the n queries (rows of
+// n_dims + 1), computed by the caller; otherwise they are computed here when a query
+// asks for estimated order or sizing.
 int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs,
               hipStream_t stream, BatchWorkspace* ws = nullptr, bool tune = true,
-              BatchRunStats* st = nullptr);
-// Grow a workspace so that batches of up to max_queries queries, max_rows of them with
-// bitmap rows, run without allocating.
+              BatchRunStats* st = nullptr, const float* est_in = nullptr);
+// Grow a workspace so that batches of up to max_queries queries whose requests'
+// request_scratch_bytes sum to at most scratch_bytes run without allocating.
 int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queries,
-                  uint64_t max_rows);
+                  uint64_t scratch_bytes);
 void free_batch(BatchWorkspace& ws);
 // Close every live server still open on the dataset (serve.cpp), before it is freed.
 void close_servers(mdrq_dataset* ds);
@@ -366,10 +432,8 @@ struct BatchWorkspace {
   uint64_t d_blob_bytes = 0;
   void* h_blob = nullptr;        // pinned staging of the same
   uint64_t h_blob_bytes = 0;
-  uint64_t* d_words = nullptr;   // bitmap scratch
+  uint64_t* d_words = nullptr;   // bitmap scratch: rows, sparse pools, marks, slot tables
   uint64_t d_words_len = 0;
-  uint64_t* d_flags = nullptr;   // chunk marks of the slot-mask and rank variants (as 64-bit words)
-  uint64_t d_flags_len = 0;
   uint32_t* d_tile_counts = nullptr;
   uint64_t d_tile_counts_len = 0;
   void* h_res = nullptr;         // counts (u64) and kinds (u32) per query: mapped pinned
@@ -377,7 +441,29 @@ struct BatchWorkspace {
   uint64_t res_len = 0;          // queries the two hold
   void* d_stage = nullptr;       // device staging for host-memory outputs
   uint64_t d_stage_bytes = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  // Shared scans replayed from graphs (query-table copy, zeroing, scan, finish, and the
+  // events around them), one per scan kernel, arguments updated per batch.
+  struct Graph {
+    const void* scan_fn = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy = nullptr, zero = nullptr, scan = nullptr, count = nullptr, emit = nullptr;
+  };
+  std::vector<Graph> graphs;
+};
+
+// A single-query launch sequence (scan, compaction for identifiers, and the profiling
+// events when enabled) instantiated once per launch shape and replayed with each
+// query's kernel arguments.
+struct QueryGraph {
+  uint32_t mode = 0;
+  int unroll = 0;
+  uint64_t grid = 0;
+  bool profiling = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t scan = nullptr, compact = nullptr;
 };
 
 // Launch configuration of a shared scan.
@@ -427,6 +513,13 @@ struct mdrq_dataset {
   double prof_scan_ms = 0.0;
   double prof_total_ms = 0.0;
   int unroll = 8;                        // tile height of single-query scans (x 256 rows)
+  // Launch sequences replayed from graphs (MDRQ_OPT_GRAPHS): single queries (one graph
+  // per launch shape) and shared scans (one per scan kernel and workspace), arguments
+  // updated per call.
+  bool graph_single = false;
+  bool graph_batch = false;
+  int64_t reserve_ppm = 4000000;         // MDRQ_Q_SIZE_ESTIMATED: reserved rows per estimate (1e-6)
+  std::vector<mdrq::QueryGraph> graphs;
   // Batched path.
   mdrq::BatchWorkspace batch;
   int batch_waves = 0;                   // 0: autotuned
@@ -442,6 +535,11 @@ struct mdrq_dataset {
   std::vector<std::pair<uint64_t, mdrq::BatchConfig>> tuned;  // shape key -> config
   uint64_t batch_launches = 0;
   double batch_ms = 0.0;
+  uint64_t batch_lookups = 0;            // rank variant: rows x (group, column) pairs looked up
+  uint64_t batch_column_bytes = 0;       // column bytes the shared scans read
+  double batch_scan_ms = 0.0;            // device time of the shared-scan kernels alone
+  uint64_t sized_queries = 0;            // MDRQ_Q_SIZE_ESTIMATED queries with sparse scratch
+  uint64_t sized_reruns = 0;             // of those, answered again (estimate too low)
 
   mdrq_estimator* estimator = nullptr;   // attached estimator (MDRQ_Q_ORDER_ESTIMATED)
   std::vector<mdrq_server*> servers;     // live servers open on the dataset (stat_mu)

@@ -157,15 +157,13 @@ inline uint64_t align4(uint64_t x) { return (x + 3) & ~uint64_t{3}; }
 
 // Words one column's tables take in a group's LDS image (see append_slot_tables).
 inline uint64_t slot_table_words(uint32_t M, const RankBuckets& rb, uint32_t sw) {
-  return rb.nb / 2 + align4(M + (uint64_t{1} << rb.d) - 1) + align4(uint64_t{M + 1} * sw);
+  return rb.nb + align4(uint64_t{M} + 1) + align4(uint64_t{M + 1} * sw);
 }
 
 // Upper bound of slot_table_words over every set of at most max_ends distinct ends and
-// every bucket map of at most nb buckets.  A map's steps d are the fewest with
-// 2^d - 1 >= its fullest bucket, so 2^(d-1) <= fullest <= max_ends and the padding
-// 2^d - 1 is below 2 max_ends: ends and padding take less than 3 max_ends words.
+// every bucket map of at most nb buckets.
 inline uint64_t slot_table_words_bound(uint32_t max_ends, uint32_t nb, uint32_t sw) {
-  return nb / 2 + align4(3 * uint64_t{max_ends}) + align4(uint64_t{max_ends + 1} * sw);
+  return nb + align4(uint64_t{max_ends} + 1) + align4(uint64_t{max_ends + 1} * sw);
 }
 
 // One query's interval on a column as order-preserving keys; has = false: the query
@@ -176,9 +174,12 @@ struct KeyInterval {
 };
 
 // Append one column's tables to a group's words g (whose size is 4-word aligned on
-// entry and stays so): the nb 16-bit bucket starts, the M sorted distinct ends padded
-// with 2^d - 1 words 0xFFFFFFFF (the farthest entry a search within a bucket reads),
-// then the (M + 1) x sw table of query bitsets by rank.  Query q of qs passes at rank r
+// entry and stays so): per bucket one word holding the index of its first end (the
+// number of ends in lower buckets) in the low 16 bits and the index past its last end
+// in the high 16 bits, the M sorted distinct ends and one word 0xFFFFFFFF after them
+// (4-word aligned), then the (M + 1) x sw table of query bitsets by rank.  A search
+// within a bucket reads only the bucket's own ends; a probe it does not need reads the
+// word after the ends instead, the same word for every lane.  Query q of qs passes at rank r
 // (r ends <= the row's key) iff idx(klo) < r <= idx(khi + 1); its bit is toggled on at
 // idx(klo) + 1 and off at idx(khi + 1) + 1, and a running XOR over the ranks fills the
 // rows.  Returns the offset of the ends in g (the column header's first word).
@@ -187,11 +188,14 @@ inline uint32_t append_slot_tables(std::vector<uint32_t>& g, const std::vector<u
                                    uint32_t sw) {
   const uint32_t M = static_cast<uint32_t>(ends.size());
   const size_t s0 = g.size();
-  g.resize(s0 + rb.nb / 2, 0u);
-  for (uint32_t b = 0; b < rb.nb; ++b) g[s0 + b / 2] |= static_cast<uint32_t>(rb.starts[b]) << (16 * (b % 2));
+  g.resize(s0 + rb.nb, 0u);
+  for (uint32_t b = 0; b < rb.nb; ++b) {
+    const uint32_t end = b + 1 < rb.nb ? rb.starts[b + 1] : M;
+    g[s0 + b] = static_cast<uint32_t>(rb.starts[b]) | (end << 16);
+  }
   const uint32_t at = static_cast<uint32_t>(g.size());
   g.insert(g.end(), ends.begin(), ends.end());
-  g.resize(g.size() + ((size_t{1} << rb.d) - 1), 0xFFFFFFFFu);
+  g.push_back(0xFFFFFFFFu);
   g.resize(align4(g.size()), 0u);
   const size_t t0 = g.size();
   g.resize(t0 + static_cast<size_t>(M + 1) * sw, 0u);

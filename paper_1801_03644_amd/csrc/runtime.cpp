@@ -57,6 +57,13 @@ constexpr uint64_t kMaxRows = 0xFFFFFFFFull;
     if (e_ != hipSuccess) return fail_hip(e_, what); \
   } while (0)
 
+void destroy_graph(QueryGraph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+}
+
 void free_dataset(mdrq_dataset* ds) {
   if (!ds) return;
   if (ds->owned && ds->base) (void)hipFree(ds->base);
@@ -66,6 +73,7 @@ void free_dataset(mdrq_dataset* ds) {
   if (ds->block_sums) (void)hipFree(ds->block_sums);
   if (ds->host_state) (void)hipHostFree(ds->host_state);
   if (ds->staging) (void)hipFree(ds->staging);
+  for (QueryGraph& g : ds->graphs) destroy_graph(g);
   if (ds->ev0) (void)hipEventDestroy(ds->ev0);
   if (ds->ev1) (void)hipEventDestroy(ds->ev1);
   if (ds->ev2) (void)hipEventDestroy(ds->ev2);
@@ -99,7 +107,7 @@ int check_query(const mdrq_dataset* ds, const mdrq_query_t* q) {
   if (!q) return fail(MDRQ_EINVAL, "query is NULL");
   if (q->n_preds > 0 && !q->preds) return fail(MDRQ_EINVAL, "query has predicates but preds is NULL");
   if (q->n_preds > ds->n_dims) return fail(MDRQ_EINVAL, "more predicates than dimensions");
-  if (q->flags & ~static_cast<uint32_t>(MDRQ_Q_ORDER_ESTIMATED | MDRQ_Q_NO_EARLYOUT))
+  if (q->flags & ~static_cast<uint32_t>(MDRQ_Q_ORDER_ESTIMATED | MDRQ_Q_NO_EARLYOUT | MDRQ_Q_SIZE_ESTIMATED))
     return fail(MDRQ_EINVAL, "unknown query flags");
   uint64_t seen[MDRQ_MAX_DIMS / 64] = {0, 0};
   for (uint32_t i = 0; i < q->n_preds; ++i) {
@@ -172,71 +180,150 @@ int ensure_staging(mdrq_dataset* ds, uint64_t bytes) {
   return MDRQ_OK;
 }
 
-int recover_state(mdrq_dataset* ds) {
+int recover_state(ScanState* state) {
   (void)hipDeviceSynchronize();
-  (void)hipMemset(ds->state, 0, sizeof(ScanState));
+  (void)hipMemset(state, 0, sizeof(ScanState));
   (void)hipDeviceSynchronize();
   return MDRQ_OK;
 }
 
-int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream) {
-  if (plan.empty || ds->n_rows == 0) return finish_empty(ds, plan, r, stream);
-  std::lock_guard<std::mutex> single(ds->single_mu);
-  const bool host_out = r->mem == MDRQ_MEM_HOST && plan.mode != kCount;
-  const uint64_t elem = plan.mode == kIds ? 4 : 8;
-  const uint64_t out_elems = plan.mode == kBitmap ? std::min(plan.capacity, n_words(ds)) : plan.capacity;
-  void* out = r->buf;
-  if (host_out) {
-    if (out_elems) {
-      int rc = ensure_staging(ds, out_elems * elem);
-      if (rc) return rc;
-    }
-    out = ds->staging;
-  }
+// Device buffers of one single-query scan.
+struct ScanWork {
+  ScanState* state;        // zero between launches
+  uint64_t* stage_bitmap;  // ceil(n_rows / 64) words
+  uint32_t* tile_counts;   // one per wave tile
+  uint32_t* block_sums;    // one per workgroup
+};
+
+// Launch shape of a single-query scan: grid and tiles per workgroup segment.
+void scan_shape(const mdrq_dataset* ds, uint32_t kmode, uint64_t n_tiles, uint64_t max_grid, uint64_t* grid_out,
+                uint64_t* seg_out) {
   const int U = ds->unroll;
   const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(U));
-  const uint32_t kmode = plan.mode == kIds ? kStage : plan.mode;
-  const uint64_t n_tiles = (ds->n_rows + tile - 1) / tile;
   const Device& dev = device();
   const uint64_t per_cu = std::min<uint64_t>(scan_blocks_per_cu(kmode, U), ds->blocks_per_cu);
   const uint64_t resident = per_cu * dev.cus;
   uint64_t want = ds->grid > 0 ? static_cast<uint64_t>(ds->grid) : resident;
+  want = std::min(want, max_grid);
   const uint64_t blocks_needed = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   uint64_t grid = std::min<uint64_t>(blocks_needed, want);
   // Segments of whole 4096-row compaction chunks.
   const uint64_t align = std::max<uint64_t>(1, 4096 / tile);
   const uint64_t seg = ((n_tiles + grid - 1) / grid + align - 1) / align * align;
-  grid = (n_tiles + seg - 1) / seg;
-  if (plan.mode == kIds && grid > ds->block_sums_len) {
-    if (ds->block_sums) (void)hipFree(ds->block_sums);
-    ds->block_sums = nullptr;
-    ds->block_sums_len = 0;
-    if (hipMalloc(&ds->block_sums, grid * sizeof(uint32_t)) != hipSuccess)
-      return fail(MDRQ_ENOMEM, "workgroup count buffer");
-    ds->block_sums_len = grid;
+  *grid_out = (n_tiles + seg - 1) / seg;
+  *seg_out = seg;
+}
+
+constexpr size_t kMaxQueryGraphs = 16;
+
+// Launch a single query's scan (and compaction) by replaying the dataset's graph for
+// this launch shape, built on first use; each replay carries this query's arguments.
+// With profiling on, the graph records the dataset's three events around the kernels.
+hipError_t launch_query_graph(mdrq_dataset* ds, const ScanParams& p, const CompactParams& c, uint32_t kmode,
+                              uint64_t grid, bool compact, hipStream_t stream) {
+  const int U = ds->unroll;
+  void* sargs[] = {const_cast<ScanParams*>(&p)};
+  void* cargs[] = {const_cast<CompactParams*>(&c)};
+  hipKernelNodeParams ks{};
+  ks.func = const_cast<void*>(scan_kernel_fn(kmode, U));
+  ks.gridDim = dim3(static_cast<uint32_t>(grid));
+  ks.blockDim = dim3(kBlock);
+  ks.sharedMemBytes = 0;
+  ks.kernelParams = sargs;
+  ks.extra = nullptr;
+  hipKernelNodeParams kc = ks;
+  kc.func = const_cast<void*>(compact_kernel_fn(U));
+  kc.kernelParams = cargs;
+  if (!ks.func || !kc.func) return hipErrorInvalidValue;
+  QueryGraph* qg = nullptr;
+  for (QueryGraph& g : ds->graphs)
+    if (g.mode == kmode && g.unroll == U && g.grid == grid && g.profiling == ds->profiling) qg = &g;
+  hipError_t e = hipSuccess;
+  if (qg) {
+    e = hipGraphExecKernelNodeSetParams(qg->exec, qg->scan, &ks);
+    if (e == hipSuccess && compact) e = hipGraphExecKernelNodeSetParams(qg->exec, qg->compact, &kc);
+    if (e == hipSuccess) return hipGraphLaunch(qg->exec, stream);
+    // An update the instantiated graph does not take: build it anew below.
+    destroy_graph(*qg);
+    ds->graphs.erase(ds->graphs.begin() + (qg - ds->graphs.data()));
   }
+  if (ds->graphs.size() >= kMaxQueryGraphs) {
+    destroy_graph(ds->graphs.front());
+    ds->graphs.erase(ds->graphs.begin());
+  }
+  QueryGraph g;
+  g.mode = kmode;
+  g.unroll = U;
+  g.grid = grid;
+  g.profiling = ds->profiling;
+  e = hipGraphCreate(&g.graph, 0);
+  hipGraphNode_t last = nullptr;
+  auto chain = [&](hipGraphNode_t n) { last = n; };
+  if (e == hipSuccess && g.profiling) {
+    hipGraphNode_t n = nullptr;
+    e = hipGraphAddEventRecordNode(&n, g.graph, nullptr, 0, ds->ev0);
+    chain(n);
+  }
+  if (e == hipSuccess) {
+    e = hipGraphAddKernelNode(&g.scan, g.graph, last ? &last : nullptr, last ? 1 : 0, &ks);
+    chain(g.scan);
+  }
+  if (e == hipSuccess && g.profiling) {
+    hipGraphNode_t n = nullptr;
+    e = hipGraphAddEventRecordNode(&n, g.graph, &last, 1, ds->ev1);
+    chain(n);
+  }
+  if (e == hipSuccess && compact) {
+    e = hipGraphAddKernelNode(&g.compact, g.graph, &last, 1, &kc);
+    chain(g.compact);
+  }
+  if (e == hipSuccess && g.profiling) {
+    hipGraphNode_t n = nullptr;
+    e = hipGraphAddEventRecordNode(&n, g.graph, &last, 1, ds->ev2);
+    chain(n);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    destroy_graph(g);
+    return e;
+  }
+  ds->graphs.push_back(g);
+  return hipGraphLaunch(ds->graphs.back().exec, stream);
+}
+
+// Scan (and compaction) of one planned query, whose predicates are preds[0 .. n_preds),
+// into `out` (device memory, out_elems elements) with the workspace `w`; waits for
+// completion.  With host_out, `out` is device staging copied to r->buf at the end.
+int scan_query(mdrq_dataset* ds, const Plan& plan, const DevPred* preds, uint32_t n_preds, mdrq_result_t* r,
+               hipStream_t stream, const ScanWork& w, void* out, uint64_t out_elems, uint64_t grid, uint64_t seg,
+               bool host_out) {
+  const int U = ds->unroll;
+  const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(U));
+  const uint32_t kmode = plan.mode == kIds ? kStage : plan.mode;
+  const uint64_t n_tiles = (ds->n_rows + tile - 1) / tile;
+  const uint64_t elem = plan.mode == kIds ? 4 : 8;
   ScanParams p{};
   p.n_rows = ds->n_rows;
   p.n_tiles = n_tiles;
-  p.n_preds = static_cast<uint32_t>(plan.preds.size());
+  p.n_preds = n_preds;
   p.early_out = plan.early_out ? 1u : 0u;
-  p.bitmap = plan.mode == kIds ? ds->stage_bitmap
+  p.bitmap = plan.mode == kIds ? w.stage_bitmap
              : plan.mode == kBitmap ? static_cast<uint64_t*>(out) : nullptr;
   p.capacity = plan.mode == kIds ? n_words(ds) : plan.mode == kBitmap ? out_elems : 0;
   p.seg_tiles = seg;
-  p.tile_counts = ds->tile_counts;
-  p.block_sums = ds->block_sums;
-  p.state = ds->state;
+  p.tile_counts = w.tile_counts;
+  p.block_sums = w.block_sums;
+  p.state = w.state;
   p.count_out = &ds->host_state_dev->count_out;
   p.order = plan.order;
-  for (size_t i = 0; i < plan.preds.size(); ++i) p.preds[i] = plan.preds[i];
+  for (uint32_t i = 0; i < n_preds; ++i) p.preds[i] = preds[i];
   CompactParams c{};
   c.n_tiles = n_tiles;
   c.n_words = n_words(ds);
   c.seg_tiles = seg;
-  c.bitmap = ds->stage_bitmap;
-  c.tile_counts = ds->tile_counts;
-  c.block_sums = ds->block_sums;
+  c.bitmap = w.stage_bitmap;
+  c.tile_counts = w.tile_counts;
+  c.block_sums = w.block_sums;
   c.ids = static_cast<uint32_t*>(out);
   c.capacity = plan.mode == kIds ? out_elems : 0;
   c.count_out = &ds->host_state_dev->count_out;
@@ -248,20 +335,25 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
     if (!ds->ev0) MDRQ_HIP(hipEventCreate(&ds->ev0), "hipEventCreate");
     if (!ds->ev1) MDRQ_HIP(hipEventCreate(&ds->ev1), "hipEventCreate");
     if (!ds->ev2) MDRQ_HIP(hipEventCreate(&ds->ev2), "hipEventCreate");
-    MDRQ_HIP(hipEventRecord(ds->ev0, stream), "hipEventRecord");
   }
-  hipError_t e = launch_scan(p, kmode, U, static_cast<int>(grid), stream);
-  if (e == hipSuccess && ds->profiling) e = hipEventRecord(ds->ev1, stream);
-  if (e == hipSuccess && plan.mode == kIds) e = launch_compact(c, U, static_cast<int>(grid), stream);
+  hipError_t e = hipSuccess;
+  if (ds->graph_single && w.state == ds->state) {
+    e = launch_query_graph(ds, p, c, kmode, grid, plan.mode == kIds, stream);
+  } else {
+    if (ds->profiling) e = hipEventRecord(ds->ev0, stream);
+    if (e == hipSuccess) e = launch_scan(p, kmode, U, static_cast<int>(grid), stream);
+    if (e == hipSuccess && ds->profiling) e = hipEventRecord(ds->ev1, stream);
+    if (e == hipSuccess && plan.mode == kIds) e = launch_compact(c, U, static_cast<int>(grid), stream);
+    if (e == hipSuccess && ds->profiling) e = hipEventRecord(ds->ev2, stream);
+  }
   if (e != hipSuccess) {
-    recover_state(ds);
+    recover_state(w.state);
     return fail_hip(e, "scan kernel launch");
   }
-  if (ds->profiling) MDRQ_HIP(hipEventRecord(ds->ev2, stream), "hipEventRecord");
   // The last workgroup wrote the count (and AUTO's choice) into pinned host memory.
   e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
-    recover_state(ds);
+    recover_state(w.state);
     return fail_hip(e, "scan completion");
   }
   if (ds->profiling) {
@@ -279,7 +371,7 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
     r->mode = MDRQ_OUT_BITMAP;
     r->written = n_words(ds);
     r->status = MDRQ_OK;
-    if (host_out) MDRQ_HIP(hipMemcpy(r->buf, ds->staging, r->written * 8, hipMemcpyDeviceToHost),
+    if (host_out) MDRQ_HIP(hipMemcpy(r->buf, out, r->written * 8, hipMemcpyDeviceToHost),
                            "copy result to host");
     return r->status;
   }
@@ -294,9 +386,40 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
     r->status = MDRQ_OK;
   }
   if (host_out && r->written)
-    MDRQ_HIP(hipMemcpy(r->buf, ds->staging, r->written * elem, hipMemcpyDeviceToHost),
-             "copy result to host");
+    MDRQ_HIP(hipMemcpy(r->buf, out, r->written * elem, hipMemcpyDeviceToHost), "copy result to host");
   return r->status;
+}
+
+int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream) {
+  if (plan.empty || ds->n_rows == 0) return finish_empty(ds, plan, r, stream);
+  std::lock_guard<std::mutex> single(ds->single_mu);
+  const bool host_out = r->mem == MDRQ_MEM_HOST && plan.mode != kCount;
+  const uint64_t elem = plan.mode == kIds ? 4 : 8;
+  const uint64_t out_elems = plan.mode == kBitmap ? std::min(plan.capacity, n_words(ds)) : plan.capacity;
+  void* out = r->buf;
+  if (host_out) {
+    if (out_elems) {
+      int rc = ensure_staging(ds, out_elems * elem);
+      if (rc) return rc;
+    }
+    out = ds->staging;
+  }
+  const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(ds->unroll));
+  const uint32_t kmode = plan.mode == kIds ? kStage : plan.mode;
+  const uint64_t n_tiles = (ds->n_rows + tile - 1) / tile;
+  uint64_t grid = 0, seg = 0;
+  scan_shape(ds, kmode, n_tiles, UINT64_MAX, &grid, &seg);
+  if (plan.mode == kIds && grid > ds->block_sums_len) {
+    if (ds->block_sums) (void)hipFree(ds->block_sums);
+    ds->block_sums = nullptr;
+    ds->block_sums_len = 0;
+    if (hipMalloc(&ds->block_sums, grid * sizeof(uint32_t)) != hipSuccess)
+      return fail(MDRQ_ENOMEM, "workgroup count buffer");
+    ds->block_sums_len = grid;
+  }
+  const ScanWork w{ds->state, ds->stage_bitmap, ds->tile_counts, ds->block_sums};
+  return scan_query(ds, plan, plan.preds.data(), static_cast<uint32_t>(plan.preds.size()), r, stream, w, out,
+                    out_elems, grid, seg, host_out);
 }
 
 }  // namespace mdrq
@@ -473,6 +596,11 @@ int mdrq_reset_profile(mdrq_dataset* ds) {
   ds->prof_total_ms = 0.0;
   ds->batch_launches = 0;
   ds->batch_ms = 0.0;
+  ds->sized_queries = 0;
+  ds->sized_reruns = 0;
+  ds->batch_lookups = 0;
+  ds->batch_column_bytes = 0;
+  ds->batch_scan_ms = 0.0;
   return MDRQ_OK;
 }
 
@@ -481,6 +609,15 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
   if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
   std::lock_guard<std::mutex> lock(ds->mu);
   switch (option) {
+    case MDRQ_OPT_RESERVE_FACTOR:
+      if (value < 1 || value > 1000000000) return fail(MDRQ_EINVAL, "reserve factor must be 1..10^9 millionths");
+      ds->reserve_ppm = value;
+      return MDRQ_OK;
+    case MDRQ_OPT_GRAPHS:
+      if (value < 0 || value > 3) return fail(MDRQ_EINVAL, "graphs must be 0..3");
+      ds->graph_single = (value & 1) != 0;
+      ds->graph_batch = (value & 2) != 0;
+      return MDRQ_OK;
     case MDRQ_OPT_UNROLL:
       if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
         return fail(MDRQ_EINVAL, "unroll must be 1, 2, 4, 8 or 16");
@@ -559,6 +696,49 @@ int mdrq_probe_bandwidth(mdrq_dataset* ds, const uint32_t* dims, uint32_t k, uin
   return MDRQ_OK;
 }
 
+int mdrq_query_read_bytes(mdrq_dataset* ds, const mdrq_query_t* q, uint64_t* bytes, void* stream_) {
+  return guarded([&]() -> int {
+    clear_error();
+    if (!ds || !bytes) return fail(MDRQ_EINVAL, "NULL argument");
+    int rc = check_query(ds, q);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(ds->mu);
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const mdrq_result_t count_only{MDRQ_OUT_COUNT, MDRQ_MEM_HOST, nullptr, 0, 0, 0, 0, 0};
+    Plan plan = make_plan(ds, q, &count_only);
+    *bytes = 0;
+    if (plan.empty || ds->n_rows == 0 || plan.preds.empty()) return MDRQ_OK;
+    std::unique_lock<std::mutex> est_hold;
+    if (q->flags & MDRQ_Q_ORDER_ESTIMATED) {
+      rc = order_on_device(ds, q, plan, stream, est_hold);
+      if (rc) return rc;
+    }
+    std::lock_guard<std::mutex> single(ds->single_mu);
+    LinesParams p{};
+    p.n_rows = ds->n_rows;
+    p.n_preds = static_cast<uint32_t>(plan.preds.size());
+    p.early_out = plan.early_out ? 1u : 0u;
+    p.order = plan.order;
+    for (size_t i = 0; i < plan.preds.size(); ++i) p.preds[i] = plan.preds[i];
+    // The running sum lives in the dataset's scan state word, which is zero between
+    // scans and is set back to zero here.
+    p.lines = reinterpret_cast<unsigned long long*>(&ds->state->total);
+    const int grid = static_cast<int>(std::min<uint64_t>((ds->n_rows + kBlock - 1) / kBlock,
+                                                         static_cast<uint64_t>(device().cus) * 8));
+    unsigned long long lines = 0;
+    hipError_t e = launch_lines(p, grid, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&lines, p.lines, sizeof lines, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(p.lines, 0, sizeof lines, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      recover_state(ds->state);
+      return fail_hip(e, "read-bytes measurement");
+    }
+    *bytes = static_cast<uint64_t>(lines) * 128;
+    return MDRQ_OK;
+  });
+}
+
 const char* mdrq_version(void) { return "0.1.0"; }
 
 int mdrq_query_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n_queries,
@@ -588,6 +768,23 @@ int mdrq_get_batch_profile(const mdrq_dataset* ds, uint64_t* scans, double* ms) 
   if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
   if (scans) *scans = ds->batch_launches;
   if (ms) *ms = ds->batch_ms;
+  return MDRQ_OK;
+}
+
+int mdrq_get_batch_work(const mdrq_dataset* ds, uint64_t* lookups, uint64_t* column_bytes, double* scan_ms) {
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  if (lookups) *lookups = ds->batch_lookups;
+  if (column_bytes) *column_bytes = ds->batch_column_bytes;
+  if (scan_ms) *scan_ms = ds->batch_scan_ms;
+  return MDRQ_OK;
+}
+
+int mdrq_get_sizing_profile(const mdrq_dataset* ds, uint64_t* sized, uint64_t* reruns) {
+  clear_error();
+  if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+  if (sized) *sized = ds->sized_queries;
+  if (reruns) *reruns = ds->sized_reruns;
   return MDRQ_OK;
 }
 

@@ -366,6 +366,43 @@ __global__ void __launch_bounds__(kBlock) probe_kernel(ProbeParams p) {
   if (acc == 0x9E3779B9u) p.sink[0] = acc;
 }
 
+// ---------------------------------------------------------------- early-break read bytes
+
+// The column lines the early break must read for one query: for each predicate in
+// evaluation order, the 128-byte lines (32 rows) of its column that hold a row every
+// earlier predicate accepted (all lines for the first predicate, or for every predicate
+// without early-out).  A measurement of the method's own bytes, not part of answering
+// the query: one lane per row, each wave covering two lines, grid-stride over the rows.
+__global__ void __launch_bounds__(kBlock) lines_kernel(LinesParams p) {
+  __shared__ uint32_t s_order[MDRQ_MAX_DIMS];
+  __shared__ unsigned long long s_sum;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t wave = threadIdx.x / kWave;
+  if (threadIdx.x == 0) s_sum = 0;
+  if (p.order)
+    for (uint32_t i = threadIdx.x; i < p.n_preds; i += kBlock) s_order[i] = p.order[i];
+  __syncthreads();
+  uint64_t lines = 0;  // uniform per wave
+  for (uint64_t row0 = (static_cast<uint64_t>(blockIdx.x) * kWavesPerBlock + wave) * kWave;
+       row0 < p.n_rows; row0 += static_cast<uint64_t>(gridDim.x) * kBlock) {
+    const uint64_t row = row0 + lane;
+    bool alive = row < p.n_rows;
+    for (uint32_t k = 0; k < p.n_preds; ++k) {
+      const uint64_t b = ballot(alive || (!p.early_out && row < p.n_rows));
+      if (b == 0) break;
+      lines += (static_cast<uint32_t>(b) != 0u) + ((b >> 32) != 0u);
+      const uint32_t kk = p.order ? s_order[k] : k;
+      if (alive) {
+        const float x = p.preds[kk].col[row];
+        alive = p.preds[kk].lo <= x && x <= p.preds[kk].hi;
+      }
+    }
+  }
+  if (lane == 0) atomicAdd(&s_sum, static_cast<unsigned long long>(lines));
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(p.lines, s_sum);
+}
+
 // ---------------------------------------------------------------- load validation
 
 __device__ __forceinline__ uint32_t order_key(float x) {
@@ -422,6 +459,19 @@ int scan_blocks_per_cu(uint32_t mode, int unroll) {
   return blocks > 0 ? blocks : 1;
 }
 
+const void* scan_kernel_fn(uint32_t mode, int unroll) { return pick(mode, unroll); }
+
+const void* compact_kernel_fn(int unroll) {
+  switch (unroll) {
+    case 1: return reinterpret_cast<const void*>(&compact_kernel<1>);
+    case 2: return reinterpret_cast<const void*>(&compact_kernel<2>);
+    case 4: return reinterpret_cast<const void*>(&compact_kernel<4>);
+    case 8: return reinterpret_cast<const void*>(&compact_kernel<8>);
+    case 16: return reinterpret_cast<const void*>(&compact_kernel<16>);
+    default: return nullptr;
+  }
+}
+
 hipError_t launch_scan(const ScanParams& p, uint32_t mode, int unroll, int grid,
                        hipStream_t stream) {
   void* f = pick(mode, unroll);
@@ -458,6 +508,12 @@ hipError_t launch_probe(const ProbeParams& p, int unroll, int grid, hipStream_t 
     default: return hipErrorInvalidValue;
   }
   return hipLaunchKernel(f, dim3(grid), dim3(kBlock), args, 0, stream);
+}
+
+hipError_t launch_lines(const LinesParams& p, int grid, hipStream_t stream) {
+  void* args[] = {const_cast<LinesParams*>(&p)};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&lines_kernel), dim3(grid), dim3(kBlock), args, 0,
+                         stream);
 }
 
 hipError_t launch_validate(const float* const* cols_dev, uint32_t n_dims, uint64_t n_rows,

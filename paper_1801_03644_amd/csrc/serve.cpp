@@ -5,9 +5,12 @@
 // device stream and a preallocated batch workspace holding an equal share of the
 // result-memory budget.  Whenever a worker is idle and requests are waiting, the
 // dispatcher hands it the oldest waiting requests, as many as max_batch allows and as
-// fit in the worker's share (a request that needs a bitmap reserves one full bitmap
-// row: its result can never need more), and the worker answers them with one call of
-// the batched shared scan.  Requests that arrive while scans run wait for the next
+// fit in the worker's share of scratch memory, and the worker answers them with one
+// call of the batched shared scan.  A request that needs identifiers or a bitmap
+// reserves a full bitmap row (its result can never need more), or, with the estimator
+// (use_estimator), room for about four times its estimated result in the scan's sparse
+// scratch: the dispatcher estimates waiting requests in bulk before admitting them, and
+// a request whose result outgrows its room is answered again by the single-query scan.  Requests that arrive while scans run wait for the next
 // idle worker, so scans of different workers overlap on the device.  Every request's
 // answer is exactly what mdrq_query gives for it alone.
 #include <algorithm>
@@ -39,6 +42,8 @@ struct Pending {
   mdrq_result_t* r = nullptr;
   Clock::time_point arrival;
   hipEvent_t ready = nullptr;
+  std::vector<float> est;       // the estimator's estimates (n_dims + 1), when used
+  bool estimated = false;
 };
 
 struct Worker {
@@ -56,7 +61,7 @@ bool needs_row(const mdrq_result_t& r) { return r.mode != MDRQ_OUT_COUNT; }
 struct mdrq_server {
   mdrq_dataset* ds = nullptr;
   mdrq_serve_config_t cfg{};
-  uint64_t rows_cap = 0;        // bitmap rows one worker's share holds
+  uint64_t share = 0;           // scratch bytes of one worker's share of the budget
   int dev = 0;
   std::vector<Worker> workers;
   std::thread dispatcher;
@@ -85,6 +90,7 @@ void worker_loop(mdrq_server* s, Worker* w) {
   (void)hipSetDevice(s->dev);
   std::vector<mdrq_query_t> qs;
   std::vector<mdrq_result_t> out;
+  std::vector<float> est;
   for (;;) {
     std::vector<Pending*> batch;
     {
@@ -95,10 +101,14 @@ void worker_loop(mdrq_server* s, Worker* w) {
     }
     qs.clear();
     out.clear();
+    est.clear();
     int rc = MDRQ_OK;
+    bool all_est = true;
+    for (Pending* p : batch) all_est &= !p->est.empty();
     for (Pending* p : batch) {
       qs.push_back(p->q);
       out.push_back(*p->r);
+      if (all_est) est.insert(est.end(), p->est.begin(), p->est.end());
       if (p->ready && rc == MDRQ_OK) {
         const hipError_t e = hipStreamWaitEvent(w->stream, p->ready, 0);
         if (e != hipSuccess) rc = fail_hip(e, "serving: wait for the submitting stream");
@@ -108,7 +118,7 @@ void worker_loop(mdrq_server* s, Worker* w) {
     if (rc == MDRQ_OK) {
       try {
         rc = run_batch(s->ds, qs.data(), static_cast<uint32_t>(qs.size()), out.data(), w->stream,
-                       &w->ws, false, &st);
+                       &w->ws, false, &st, est.empty() ? nullptr : est.data());
       } catch (...) {
         rc = fail(MDRQ_ENOMEM, "serving: host memory");
       }
@@ -137,14 +147,38 @@ void worker_loop(mdrq_server* s, Worker* w) {
     s->st.scans += st.scans;
     s->st.column_bytes += st.column_bytes;
     s->st.device_ms += st.device_ms;
+    s->st.sparse += st.sparse;
+    s->st.reruns += st.reruns;
     s->batches += 1;
     w->busy = false;
     s->cv.notify_all();
   }
 }
 
+// Estimates of the waiting requests not yet estimated, in one call (the server's lock is
+// released meanwhile; only the dispatcher takes requests off the queue).
+void estimate_waiting(mdrq_server* s, std::unique_lock<std::mutex>& lk) {
+  std::vector<Pending*> todo;
+  for (Pending* p : s->ready)
+    if (!p->estimated) todo.push_back(p);
+  if (todo.empty()) return;
+  std::vector<mdrq_query_t> qs;
+  for (Pending* p : todo) qs.push_back(p->q);
+  lk.unlock();
+  std::vector<float> est;
+  const int rc = estimate_for_order(s->ds, qs.data(), static_cast<uint32_t>(qs.size()), est);
+  lk.lock();
+  const size_t o = s->ds->n_dims + 1;
+  for (size_t i = 0; i < todo.size(); ++i) {
+    todo[i]->estimated = true;
+    if (rc == MDRQ_OK && est.size() == todo.size() * o)
+      todo[i]->est.assign(est.begin() + i * o, est.begin() + (i + 1) * o);
+  }
+}
+
 void dispatch_loop(mdrq_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
+  const double n_rows = static_cast<double>(s->ds->n_rows);
   for (;;) {
     Worker* idle = nullptr;
     bool any_busy = false;
@@ -153,12 +187,14 @@ void dispatch_loop(mdrq_server* s) {
       any_busy |= w.busy;
     }
     if (idle && !s->ready.empty()) {
-      uint64_t rows = 0;
+      if (s->cfg.use_estimator) estimate_waiting(s, lk);
+      uint64_t bytes = 0;
       while (!s->ready.empty() && idle->batch.size() < s->cfg.max_batch) {
         Pending* p = s->ready.front();
-        const uint64_t need = needs_row(*p->r) ? 1 : 0;
-        if (rows + need > s->rows_cap) break;
-        rows += need;
+        const double est_rows = p->est.empty() ? -1.0 : p->est[s->ds->n_dims] * n_rows;
+        const uint64_t need = request_scratch_bytes(s->ds, *p->r, est_rows);
+        if (bytes + need > s->share) break;
+        bytes += need;
         idle->batch.push_back(p);
         s->ready.pop_front();
       }
@@ -192,7 +228,7 @@ int check_request(const mdrq_server* s, const mdrq_query_t* q, const mdrq_result
   if (rc) return rc;
   if (needs_row(*r) && r->mem != MDRQ_MEM_DEVICE)
     return fail(MDRQ_EINVAL, "serving writes results to device memory only (mem = MDRQ_MEM_DEVICE)");
-  if (needs_row(*r) && s->rows_cap == 0)
+  if (request_scratch_bytes(s->ds, *r, -1.0) > s->share)
     return fail(MDRQ_EBUSY, "a request's bitmap row does not fit in one stream's share of the result budget");
   return MDRQ_OK;
 }
@@ -210,14 +246,12 @@ void destroy(mdrq_server* s) {
   delete s;
 }
 
-// Create the workers and the dispatcher.  `reserve_rows`: reserve bitmap rows up front.
+// Create the workers and the dispatcher.  `reserve_rows`: reserve the scratch up front.
 int create(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, bool reserve_rows, mdrq_server** out) {
   mdrq_server* s = new mdrq_server();
   s->ds = ds;
   s->cfg = *cfg;
-  const uint64_t row_bytes = 8 * n_words(ds);
-  const uint64_t share = cfg->result_budget_bytes / cfg->n_streams;
-  s->rows_cap = std::min<uint64_t>(row_bytes ? share / row_bytes : cfg->max_batch, cfg->max_batch);
+  s->share = cfg->result_budget_bytes / cfg->n_streams;
   (void)hipGetDevice(&s->dev);
   s->workers.resize(cfg->n_streams);
   for (Worker& w : s->workers) {
@@ -226,7 +260,10 @@ int create(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, bool reserve_rows, 
       destroy(s);
       return fail_hip(e, "serving stream");
     }
-    int rc = reserve_batch(ds, w.ws, cfg->max_batch, reserve_rows ? s->rows_cap : 0);
+    // At most max_batch bitmap rows are ever used by one batch.
+    const uint64_t row = request_scratch_bytes(ds, mdrq_result_t{MDRQ_OUT_IDS, 0, nullptr, 0, 0, 0, 0, 0}, -1.0);
+    const uint64_t bytes = std::min<uint64_t>(s->share, row * cfg->max_batch);
+    int rc = reserve_batch(ds, w.ws, cfg->max_batch, reserve_rows ? bytes : 0);
     if (rc) {
       destroy(s);
       return rc;
@@ -246,7 +283,7 @@ int enqueue(mdrq_server* s, const mdrq_query_t* q, mdrq_result_t* r, Clock::time
   p->q = *q;
   p->preds.assign(q->preds, q->preds + q->n_preds);
   p->q.preds = p->preds.data();
-  if (s->cfg.use_estimator) p->q.flags |= MDRQ_Q_ORDER_ESTIMATED;
+  if (s->cfg.use_estimator) p->q.flags |= MDRQ_Q_ORDER_ESTIMATED | MDRQ_Q_SIZE_ESTIMATED;
   p->r = r;
   p->arrival = arrival;
   if (order) {
@@ -317,7 +354,8 @@ int shutdown(mdrq_server* s, mdrq_serve_stats_t* stats) {
     }
     stats->mean_batch = s->batches ? static_cast<double>(n) / s->batches : 0.0;
     stats->hbm_gbps = stats->wall_s > 0 ? s->st.column_bytes / stats->wall_s * 1e-9 : 0.0;
-    stats->overflow_reruns = 0;
+    stats->overflow_reruns = s->st.reruns;
+    stats->sized_by_estimate = s->st.sparse;
   }
   const bool overflow = s->overflow;
   {

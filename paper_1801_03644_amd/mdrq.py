@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libmdrq.so")
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 MEM_HOST, MEM_DEVICE, BORROW = 0, 1, 2
 OUT_IDS, OUT_BITMAP, OUT_COUNT, OUT_AUTO = 0, 1, 2, 3
-Q_ORDER_GIVEN, Q_ORDER_ESTIMATED, Q_NO_EARLYOUT = 0, 1, 2
+Q_ORDER_GIVEN, Q_ORDER_ESTIMATED, Q_NO_EARLYOUT, Q_SIZE_ESTIMATED = 0, 1, 2, 4
 MAX_DIMS, MAX_BATCH = 128, 1024
 _MODES = {"ids": OUT_IDS, "bitmap": OUT_BITMAP, "count": OUT_COUNT, "auto": OUT_AUTO}
 _MODE_NAMES = {v: k for k, v in _MODES.items()}
@@ -33,6 +33,8 @@ EXPORTS = ["mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve", 
            "mdrq_estimator_features", "mdrq_estimator_param_count", "mdrq_estimator_get_params",
            "mdrq_estimator_set_params", "mdrq_label_selectivities", "mdrq_estimator_gradient",
            "mdrq_estimator_train", "mdrq_estimator_predict", "mdrq_attach_estimator",
+           "mdrq_estimator_activations", "mdrq_query_read_bytes", "mdrq_estimator_gate",
+           "mdrq_get_sizing_profile", "mdrq_get_batch_work",
            "mdrq_serve_open", "mdrq_serve_submit", "mdrq_serve_poll", "mdrq_serve_close"]
 EST_BINS = 16
 EST_FEATS = EST_BINS + 3  # per dimension: H(lo), H(hi), histogram estimate, bins
@@ -40,6 +42,8 @@ OPT_UNROLL, OPT_GRID, OPT_BLOCKS_PER_CU = 1, 2, 3
 OPT_BATCH_WAVES, OPT_BATCH_GROUP, OPT_AUTOTUNE, OPT_BATCH_ROWS = 4, 5, 6, 7
 OPT_BATCH_VARIANT = 8
 OPT_RANK_BUCKETS = 9
+OPT_GRAPHS = 10
+OPT_RESERVE_FACTOR = 11
 
 
 class MdrqError(RuntimeError):
@@ -90,7 +94,7 @@ class ServeStats(ctypes.Structure):
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
                 ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
                 ("mean_batch", ctypes.c_double), ("hbm_gbps", ctypes.c_double),
-                ("overflow_reruns", ctypes.c_uint64)]
+                ("overflow_reruns", ctypes.c_uint64), ("sized_by_estimate", ctypes.c_uint64)]
 
 
 _lib = None
@@ -158,13 +162,20 @@ def load_library(path: str = LIB_PATH):
     lib.mdrq_estimator_train.argtypes = [vp, P(Query), u32, fp, P(TrainConfig), fp]
     lib.mdrq_estimator_predict.argtypes = [vp, P(Query), u32, fp]
     lib.mdrq_attach_estimator.argtypes = [vp, vp]
+    lib.mdrq_estimator_activations.argtypes = [vp, P(Query), u32, u16p, u16p, fp]
+    lib.mdrq_query_read_bytes.argtypes = [vp, P(Query), P(u64), vp]
+    lib.mdrq_estimator_gate.argtypes = [vp, P(Query), u32, fp, P(u32)]
+    lib.mdrq_get_sizing_profile.argtypes = [vp, P(u64), P(u64)]
+    lib.mdrq_get_batch_work.argtypes = [vp, P(u64), P(u64), P(ctypes.c_double)]
     for f in ("mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve",
               "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
               "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth",
               "mdrq_get_batch_profile", "mdrq_estimator_create", "mdrq_estimator_histograms",
               "mdrq_estimator_features", "mdrq_estimator_param_count", "mdrq_estimator_get_params",
               "mdrq_estimator_set_params", "mdrq_label_selectivities", "mdrq_estimator_gradient",
-              "mdrq_estimator_train", "mdrq_estimator_predict", "mdrq_attach_estimator"):
+              "mdrq_estimator_train", "mdrq_estimator_predict", "mdrq_attach_estimator",
+              "mdrq_estimator_activations", "mdrq_query_read_bytes", "mdrq_estimator_gate",
+              "mdrq_get_sizing_profile", "mdrq_get_batch_work"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -327,6 +338,15 @@ class Dataset:
         _check(rc, (OK, EOVERFLOW))
         return Answer(r.count, r.written, r.status, _MODE_NAMES[r.mode])
 
+    def read_bytes(self, query, flags: int = 0, stream=None) -> int:
+        """Column bytes the scan of `query` must read (128-byte lines that hold a row
+        every earlier predicate accepted)."""
+        q, keep = make_query(query, flags)
+        b = ctypes.c_uint64()
+        _check(load_library().mdrq_query_read_bytes(self._h, ctypes.byref(q), ctypes.byref(b),
+                                                    _stream_handle(stream)))
+        return b.value
+
     def query_batch(self, queries, outs=None, modes="ids", flags: int = 0, stream=None):
         lib = load_library()
         n = len(queries)
@@ -376,6 +396,20 @@ class Dataset:
         n, ms = ctypes.c_uint64(), ctypes.c_double()
         _check(load_library().mdrq_get_batch_profile(self._h, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+    def batch_work(self):
+        """(rank lookups, column bytes, scan-kernel ms) of the shared scans since the last
+        reset."""
+        a, b, ms = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
+        _check(load_library().mdrq_get_batch_work(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(ms)))
+        return a.value, b.value, ms.value
+
+    def sizing_profile(self):
+        """(queries whose scratch was sized by estimate, of those answered again) since the
+        last reset."""
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load_library().mdrq_get_sizing_profile(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def reset_profile(self):
         _check(load_library().mdrq_reset_profile(self._h))
@@ -621,6 +655,29 @@ class Estimator:
         _check(load_library().mdrq_estimator_train(self._h, qarr, len(queries), _fptr(sel),
                                                     ctypes.byref(cfg), _fptr(losses)))
         return losses
+
+    def gate(self, queries, sel) -> np.ndarray:
+        """Remove the learned correction of every output that does not lower the held-out
+        error on these labelled queries; returns the kept mask (n_dims + 1,)."""
+        qarr, keep = _query_array(queries, 0)
+        sel = np.ascontiguousarray(sel, dtype=np.float32)
+        kept = np.zeros(self.n_dims + 1, dtype=np.uint32)
+        _check(load_library().mdrq_estimator_gate(
+            self._h, qarr, len(queries), _fptr(sel), kept.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+        return kept.astype(bool)
+
+    def activations(self, queries):
+        """(h1, h2, y): the hidden layers' bfloat16 bit patterns (n, hidden) as uint16 and
+        the output layer (n, n_dims + 1) as float32, before clamping."""
+        qarr, keep = _query_array(queries, 0)
+        n = len(queries)
+        h1 = np.empty((n, self.hidden), dtype=np.uint16)
+        h2 = np.empty((n, self.hidden), dtype=np.uint16)
+        y = np.empty((n, self.n_dims + 1), dtype=np.float32)
+        u16 = ctypes.POINTER(ctypes.c_uint16)
+        _check(load_library().mdrq_estimator_activations(
+            self._h, qarr, n, h1.ctypes.data_as(u16), h2.ctypes.data_as(u16), _fptr(y)))
+        return h1, h2, y
 
     def predict(self, queries) -> np.ndarray:
         qarr, keep = _query_array(queries, 0)

@@ -16,6 +16,14 @@ CLOCK_GHZ = 2.4
 # median-of-three then compare), so the shared scans' ALU roofline counts compares.
 ALU_COMPARES_PEAK = CUS * 64 * CLOCK_GHZ * 1e9
 COMPARES_PER_TEST = 2
+# LDS: 128 bytes per clock per CU (32 banks of 4 bytes), the CDNA figure for wave-wide
+# reads; 256 * 128 * 2.4e9 = 78.6 TB/s over the chip.
+LDS_BYTES_PER_CLK = 128
+LDS_PEAK_GBPS = CUS * LDS_BYTES_PER_CLK * CLOCK_GHZ
+# Rank variant, per row and (group of up to 128 queries, column): one 4-byte bucket word
+# and one row of query bitsets (4 words for a group of 128) read from LDS, plus the
+# search probes inside the row's bucket (data-dependent, not counted).
+RANK_LDS_BYTES_PER_LOOKUP = 4 + 16
 
 
 def column_bytes(n_rows: int, n_dims: int) -> int:

@@ -118,9 +118,9 @@ int main() {
   }
   // Slot tables of S queries (32 x sw per group, any S up to 128): the appended words
   // equal slot_table_words and stay within slot_table_words_bound(2 S) for adversarial
-  // end sets (all but one end crowded into one bucket, so the padding 2^d - 1 is as
-  // large as it gets), and every bitset row says exactly which queries pass at that
-  // rank.
+  // end sets (all but one end crowded into one bucket), each bucket word holds the
+  // first and one-past-last index of the bucket's ends, and every bitset row says
+  // exactly which queries pass at that rank.
   int tables = 0;
   for (int it = 0; it < 4000; ++it) {
     const uint32_t S = 1 + static_cast<uint32_t>(rng() % 128);
@@ -137,9 +137,9 @@ int main() {
       } else if (kind == 1) { // spread
         a = order_key(std::uniform_real_distribution<float>(0.0f, 1.0f)(rng));
         b = order_key(std::uniform_real_distribution<float>(0.0f, 1.0f)(rng));
-      } else {                // arbitrary keys below key(NaN)
-        a = static_cast<uint32_t>(rng()) % 0xFF800000u;
-        b = static_cast<uint32_t>(rng()) % 0xFF800000u;
+      } else {                // arbitrary keys of non-NaN floats, key(-inf) .. key(+inf)
+        a = 0x007FFFFFu + static_cast<uint32_t>(rng()) % (0xFF800000u - 0x007FFFFFu);
+        b = 0x007FFFFFu + static_cast<uint32_t>(rng()) % (0xFF800000u - 0x007FFFFFu);
       }
       if (rng() % 4) {
         if (a > b) std::swap(a, b);
@@ -164,7 +164,7 @@ int main() {
       const uint64_t words = g.size() - 8;
       ++tables;
       if (words != mdrq::slot_table_words(M, rb, sw) || g.size() % 4 ||
-          (cap == 256 && words > mdrq::slot_table_words_bound(2 * S, 256, sw)) || at != 8 + rb.nb / 2) {
+          (cap == 256 && words > mdrq::slot_table_words_bound(2 * S, 256, sw)) || at != 8 + rb.nb) {
         std::printf("size S=%u M=%u d=%u nb=%u words=%llu\n", S, M, rb.d, rb.nb,
                     static_cast<unsigned long long>(words));
         ++bad;
@@ -172,9 +172,36 @@ int main() {
       }
       for (uint32_t i = 0; i < M; ++i)
         if (g[at + i] != ends[i]) ++bad;
-      for (uint32_t i = M; i < M + (1u << rb.d) - 1; ++i)
-        if (g[at + i] != 0xFFFFFFFFu) ++bad;
-      const size_t t0 = at + mdrq::align4(M + (1u << rb.d) - 1);
+      if (g[at + M] != 0xFFFFFFFFu) ++bad;
+      // bucket words: [first, past-last) of the ends the map puts in that bucket, and
+      // a search of d steps within it stays inside it
+      for (uint32_t b = 0; b < rb.nb; ++b) {
+        uint32_t first = M, past = 0, n_in = 0;
+        for (uint32_t i = 0; i < M; ++i) {
+          const uint32_t bi = rb.by_value ? mdrq::value_bucket(mdrq::key_value(ends[i]), rb.vlo, rb.scale, rb.nb - 1)
+                                          : std::min<uint32_t>((ends[i] - ends[0]) >> rb.shift, rb.nb - 1);
+          if (bi == b) {
+            first = std::min(first, i);
+            past = std::max(past, i + 1);
+            ++n_in;
+          }
+        }
+        uint32_t below = 0;
+        for (uint32_t i = 0; i < M; ++i) {
+          const uint32_t bi = rb.by_value ? mdrq::value_bucket(mdrq::key_value(ends[i]), rb.vlo, rb.scale, rb.nb - 1)
+                                          : std::min<uint32_t>((ends[i] - ends[0]) >> rb.shift, rb.nb - 1);
+          below += bi < b ? 1u : 0u;
+        }
+        const uint32_t w = g[8 + b];
+        if ((w & 0xFFFFu) != below || (w >> 16) != below + n_in || (n_in && (first != below || past != below + n_in)) ||
+            n_in > (1u << rb.d) - 1) {
+          if (bad < 5)
+            std::printf("bucket b=%u nb=%u words %u/%u below=%u n_in=%u d=%u M=%u\n", b, rb.nb, w & 0xFFFFu,
+                        w >> 16, below, n_in, rb.d, M);
+          ++bad;
+        }
+      }
+      const size_t t0 = at + mdrq::align4(M + 1);
       for (uint32_t r = 0; r <= M; ++r)
         for (uint32_t q = 0; q < S; ++q) {
           // rank r: the ends[0..r) are <= the key; the query passes iff

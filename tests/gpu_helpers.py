@@ -40,3 +40,30 @@ def run(ds, q, mode="ids", cap=None, flags=0, host=False):
 def bitmap_to_ids(words, n_rows):
     bits = np.unpackbits(np.ascontiguousarray(words).view(np.uint8), bitorder="little")
     return np.flatnonzero(bits[:n_rows]).astype(np.uint32), bits[n_rows:]
+
+
+def oracle_counts(cols, queries, threads=None):
+    """Oracle counts of many queries on host threads (each call is the unchanged
+    single-threaded oracle; ctypes releases the interpreter lock during it)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    oracle._load()  # once, before the threads
+    threads = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(lambda q: oracle.count(cols, q), queries))
+
+
+def oracle_queries(cols, queries, threads=None):
+    """(status, count, ids) of each query from the oracle, on host threads."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    oracle._load()
+    threads = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(lambda q: oracle.query(cols, q), queries))

@@ -155,3 +155,69 @@ def test_targets_and_qerror():
     assert abs(er.selectivity_from_output(y[4:5], 1000)[0] - 1e-3) < 1e-12
     q = er.qerror([0.1, 0.01, 1e-9], [0.01, 0.1, 1e-12], 1000)
     assert np.allclose(q, [10, 10, 1])
+
+
+def test_rounded_paths_on_a_hand_computed_network():
+    """Where the bfloat16 roundings sit, pinned by a one-unit network worked out by hand.
+
+    Every pre-activation is above 8, where erf(z / sqrt 2) is 1 in float64, so GELU is
+    the identity and its derivative 1; the only changes to the numbers are the
+    roundings.  bfloat16 keeps 8 significant bits: the spacing is 2^-7 on [1, 2),
+    2^-9 on [0.25, 0.5), 2^-4 on [8, 16).
+
+    Forward (operands rounded, biases and base not):
+      x  = 1 + 3*2^-9  -> 1 + 2^-7 = 1.0078125        (3/4 of a unit: up)
+      W1 = 10.03       -> 10.0                        (0.03 < half of 2^-4)
+      z1 = 1.0078125 * 10 + 0.001 = 10.079125 -> h1 = 10.0625
+      W2 = 1.5 + 2^-9  -> 1.5
+      z2 = 10.0625 * 1.5 + 0.003 = 15.09675  -> h2 = 15.125  (0.03425 > 2^-5: up)
+      W3 = 0.2509      -> 0.25
+      y  = 15.125 * 0.25 + 0.0007 + 0.5 (base) = 4.28195
+    Backward (product operands rounded, bias gradients from the unrounded values):
+      dy = 1 + 3*2^-9 -> 1.0078125
+      dW3 = 15.125 * 1.0078125 = 15.2431640625;  db3 = 1.005859375
+      dz2 = 1.0078125 * 0.25 = 0.251953125 (on the grid)
+      dW2 = 10.0625 * 0.251953125 = 2.5352783203125;  db2 = 0.251953125
+      dz1 = 0.251953125 * 1.5 = 0.3779296875 = 193.5 units of 2^-9: a tie, to even
+            -> 194 * 2^-9 = 0.37890625
+      dW1 = 1.0078125 * 0.37890625 = 0.381866455078125;  db1 = 0.3779296875
+    """
+    p = {"W1": np.array([[10.03]]), "b1": np.array([0.001]),
+         "W2": np.array([[1.5 + 2 ** -9]]), "b2": np.array([0.003]),
+         "W3": np.array([[0.2509]]), "b3": np.array([0.0007])}
+    X = np.array([[1 + 3 * 2 ** -9]])
+    Y, cache = er.forward(p, X, np.array([[0.5]]))
+    assert cache["X"][0, 0] == 1.0078125 and cache["W1"][0, 0] == 10.0
+    assert cache["H1"][0, 0] == 10.0625 and cache["H2"][0, 0] == 15.125
+    assert abs(Y[0, 0] - 4.28195) < 1e-12
+    g = er.backward(cache, np.array([[1 + 3 * 2 ** -9]]))
+    assert g["W3"][0, 0] == 15.2431640625 and g["b3"][0] == 1.005859375
+    assert g["W2"][0, 0] == 2.5352783203125 and g["b2"][0] == 0.251953125
+    assert g["W1"][0, 0] == 0.381866455078125 and g["b1"][0] == 0.3779296875
+    # the unrounded path gives other numbers (so the roundings above are exercised)
+    Yu, cu = er.forward(p, X, np.array([[0.5]]), rounding=False)
+    assert abs(Yu[0, 0] - 4.28195) > 1e-3
+    gu = er.backward(cu, np.array([[1 + 3 * 2 ** -9]]), round_like_gpu=False)
+    assert gu["W1"][0, 0] != g["W1"][0, 0]
+
+
+def test_rounded_paths_equal_unrounded_on_grid_values():
+    """Operands that bfloat16 holds exactly (small integers, powers of two), with every
+    pre-activation an integer in [12, 256) so that GELU is the identity and keeps
+    activations on the grid: the rounded forward and backward equal the unrounded ones
+    bit for bit."""
+    rng = np.random.default_rng(7)
+    K, H, O, n = 3, 4, 2, 5
+    p = {"W1": rng.integers(2, 5, (K, H)).astype(np.float64), "b1": np.zeros(H),
+         "W2": rng.integers(1, 3, (H, H)).astype(np.float64), "b2": np.zeros(H),
+         "W3": 2.0 ** -rng.integers(1, 6, (H, O)), "b3": np.zeros(O)}
+    X = rng.integers(2, 5, (n, K)).astype(np.float64)
+    Yr, cr = er.forward(p, X)
+    Yu, cu = er.forward(p, X, rounding=False)
+    assert (cr["H1"] >= 12).all() and (cr["H2"] < 256).all()
+    assert np.array_equal(Yr, Yu)
+    dY = 2.0 ** -rng.integers(1, 6, (n, O))
+    gr = er.backward(cr, dY)
+    gu = er.backward(cu, dY, round_like_gpu=False)
+    for k in gr:
+        assert np.array_equal(gr[k], gu[k]), k

@@ -253,8 +253,10 @@ def test_launch_configurations_give_identical_results():
 
 
 def test_full_size_c3_batch_sampled():
-    """The c3 shape at full size (5*10^7 x 8): one batch of 256 queries; every count
-    and the ids of a sample of queries against the oracle."""
+    """The c3 shape at full size (5*10^7 x 8): one batch of 256 queries in AUTO mode;
+    every count and the results of a sample of queries against the oracle."""
+    from tests.gpu_helpers import oracle_counts, oracle_queries
+
     w = dg.workload("c3")
     _print("c3 full size: generating")
     raw = w.columns()
@@ -266,14 +268,109 @@ def test_full_size_c3_batch_sampled():
         _print("c3 full size: batch")
         ans = ds.query_batch(qs, outs, modes)
         rng = np.random.default_rng(0)
-        for i in rng.choice(256, size=6, replace=False):
-            st, cnt, want = oracle.query(cols, qs[i])
+        pick = rng.choice(256, size=8, replace=False)
+        for i, (st, cnt, want) in zip(pick, oracle_queries(cols, [qs[i] for i in pick])):
             assert ans[i].count == cnt
             got = payload(outs[i], ans[i], ds.n_rows)
             if ans[i].status == mdrq.OK:
                 assert np.array_equal(got, want)
             else:
                 assert np.array_equal(got, want[:len(got)])
-        # counts of all 256 against the single-query path
-        for i, q in enumerate(qs):
-            assert ds.query(q, None, mode="count").count == ans[i].count
+        _print("c3 full size: oracle counts of all 256")
+        assert [a.count for a in ans] == oracle_counts(cols, qs)
+
+
+def test_full_size_c3_headline_batch():
+    """The c3 headline batch as the bench runs it: 5*10^7 x 8, 1024 queries in one call
+    (eight rank groups of 128 under the autotuned launch), ids output into 12 M-id
+    buffers.  The autotuning call and a repeat both give every count equal to the
+    oracle's (host threads, one query each), and 16 sampled id lists equal the
+    oracle's."""
+    import torch
+
+    from tests.gpu_helpers import oracle_counts, oracle_queries
+
+    w = dg.workload("c3")
+    _print("c3 headline: generating")
+    raw = w.columns()
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 1024)
+    cap = 12_000_000
+    with mdrq.Dataset.from_host(raw) as ds:
+        out = torch.full((1024, cap), -1, dtype=torch.int32, device=device())
+        outs = [out[i] for i in range(1024)]
+        _print("c3 headline: oracle counts (host threads)")
+        want_counts = oracle_counts(cols, qs)
+        assert max(want_counts) <= cap  # no overflow: the bench's outputs hold every id
+        for rep in range(2):
+            _print("c3 headline: batch", rep)
+            ans = ds.query_batch(qs, outs, "ids")
+            assert [a.count for a in ans] == want_counts, rep
+            assert all(a.status == mdrq.OK and a.mode == "ids" for a in ans)
+        rng = np.random.default_rng(1)
+        pick = sorted(set(rng.choice(1024, size=14, replace=False).tolist()) | {0, 1023})
+        _print("c3 headline: oracle ids of", len(pick), "queries")
+        for i, (st, cnt, want) in zip(pick, oracle_queries(cols, [qs[i] for i in pick])):
+            got = out[i, :ans[i].written].cpu().numpy().view(np.uint32)
+            assert ans[i].written == cnt and np.array_equal(got, want), i
+
+
+@pytest.mark.parametrize("factor", [4_000_000, 1])
+def test_estimate_sized_scratch_is_exact_and_falls_back(factor):
+    """Batches with MDRQ_Q_SIZE_ESTIMATED: queries predicted to have small results keep
+    only their chunks with a hit, in room for the reserve factor times the estimate
+    (default four times); at a factor of 10^-6 nearly every such query outgrows its room
+    and is answered again by the single-query scan.  Either way every count, id list
+    and bitmap equals the oracle's, in every output mode and on a ragged row count."""
+    from paper_1801_03644_amd.mdrq import Estimator
+
+    w = dg.workload("c5", 1_000_003)
+    raw = w.columns()
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 96, sampler=w.sampler(sample_rows=1 << 15), seed=4)
+    qs[0] = dg.make_query([(0, 0.5, 0.4)])            # empty
+    qs[1] = dg.make_query([])                          # every row
+    qs[2] = dg.make_query([(1, 0.3, 0.3000001)])       # (nearly) a point
+    modes = [("ids", "bitmap", "auto", "count")[i % 4] for i in range(len(qs))]
+    with mdrq.Dataset.from_host(raw) as ds, Estimator(ds) as est:
+        ds.attach_estimator(est)
+        ds.set_option(mdrq.OPT_RESERVE_FACTOR, factor)
+        ds.reset_profile()
+        outs = make_outs(ds.n_rows, modes)
+        ans = ds.query_batch(qs, outs, modes, flags=mdrq.Q_SIZE_ESTIMATED | mdrq.Q_ORDER_ESTIMATED)
+        sized, reruns = ds.sizing_profile()
+        _print("factor", factor, "sized by estimate", sized, "answered again", reruns)
+        assert sized > 0
+        if factor == 1:
+            assert reruns > 0
+        for i, (q, m, a, o) in enumerate(zip(qs, modes, ans, outs)):
+            st, cnt, want = oracle.query(cols, q)
+            assert a.count == cnt, (i, m)
+            if m == "count":
+                continue
+            got = payload(o, a, ds.n_rows)
+            assert np.array_equal(got, want), (i, m, a.mode)
+        ds.attach_estimator(None)
+
+
+def test_batch_graph_replays_match_direct_launches():
+    """Shared scans replay a graph per scan kernel with each batch's arguments, grid and
+    buffers: batches of different sizes, unions and modes alternate through the graphs,
+    with other device work between them, then the same batches with direct launches;
+    every result equals the oracle's."""
+    import torch
+
+    w = dg.workload("c3", 400_009)
+    raw = w.columns()
+    cols = oracle.prepare(raw)
+    samp = w.sampler(sample_rows=1 << 14)
+    batches = [dg.workload_queries(w, n, sampler=samp, seed=s) for n, s in ((40, 1), (7, 2), (130, 3), (40, 4))]
+    with mdrq.Dataset.from_host(raw) as ds:
+        for graphs in (2, 0):
+            ds.set_option(mdrq.OPT_GRAPHS, graphs)   # bit 1: shared scans
+            for rep in range(2):
+                for b, qs in enumerate(batches):
+                    x = torch.randn(1 << 16, device=device())
+                    _ = (x * 3).sum().item()
+                    modes = [("ids", "bitmap", "auto", "count")[(i + rep + b) % 4] for i in range(len(qs))]
+                    check_batch(ds, cols, qs, modes, label=f"graphs={graphs} rep={rep} batch={b}")

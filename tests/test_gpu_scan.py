@@ -302,3 +302,76 @@ def test_full_size_c2_sampled():
             if i < 2:
                 assert_same(ds, cols, q, modes=("ids",), flags=mdrq.Q_NO_EARLYOUT,
                             label=f"c2 full {i} no early break")
+
+
+def _lines_reference(raw, query, early_out=True):
+    """128-byte lines (32 rows) per predicate, in the given order, holding a row that
+    every earlier predicate accepted (numpy, from the definition of the early break)."""
+    n = len(raw[0])
+    n_lines = (n + 31) // 32
+    alive = np.ones(n, dtype=bool)
+    total = 0
+    for j, lo, hi in zip(*query):
+        if lo == -np.inf and hi == np.inf:
+            continue
+        if lo > hi:
+            return 0
+        pad = np.zeros(n_lines * 32, dtype=bool)
+        pad[:n] = alive if early_out else True
+        total += int(pad.reshape(n_lines, 32).any(axis=1).sum())
+        x = raw[j]
+        alive &= (np.float32(lo) <= x) & (x <= np.float32(hi))
+    return 128 * total
+
+
+def test_read_bytes_measurement():
+    """mdrq_query_read_bytes (the early break's own column bytes, for the roofline)
+    equals the line count taken from the definition, with and without early-out, on
+    ragged row counts and over wide and narrow predicates."""
+    for n in (1, 31, 33, 200_017):
+        w = dg.workload("c2", n)
+        raw = w.columns()
+        qs = dg.workload_queries(w, 12, sampler=w.sampler(sample_rows=min(n, 1 << 14)))
+        qs.append(dg.make_query([(0, -np.inf, np.inf), (3, 0.2, 0.9), (5, 0.1, 0.15)]))
+        qs.append(dg.make_query([(2, 0.5, 0.4)]))
+        qs.append(dg.make_query([]))
+        with mdrq.Dataset.from_host(raw) as ds:
+            for q in qs:
+                assert ds.read_bytes(q) == _lines_reference(raw, q), (n, q)
+                assert ds.read_bytes(q, flags=mdrq.Q_NO_EARLYOUT) == _lines_reference(raw, q, False)
+
+
+def test_graph_replays_match_direct_launches():
+    """Single queries replay a captured graph per launch shape with each query's
+    arguments: different queries and modes alternate through the same graphs, with
+    other device work and synchronisations between replays, with profiling events on
+    and off; every replay equals the oracle and the directly launched kernels."""
+    import torch
+
+    w = dg.workload("c2", 300_007)
+    raw = w.columns()
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 10, sampler=w.sampler(sample_rows=1 << 14))
+    want = [oracle.query(cols, q) for q in qs]
+    with mdrq.Dataset.from_host(raw) as ds:
+        results = {}
+        for graphs in (1, 0):
+            ds.set_option(mdrq.OPT_GRAPHS, graphs)   # bit 0: single queries
+            for rep in range(3):
+                ds.set_profiling(rep == 1)
+                for i, q in enumerate(qs):
+                    x = torch.randn(1 << 16, device=device())
+                    _ = (x * 2).sum().item()            # unrelated work between replays
+                    a, ids = run(ds, q)
+                    st, cnt, ref = want[i]
+                    assert a.count == cnt and np.array_equal(ids, ref), (graphs, rep, i)
+                    b, words = run(ds, q, mode="bitmap")
+                    assert np.array_equal(bitmap_to_ids(words, ds.n_rows)[0], ref), (graphs, rep, i)
+                    c, _ = run(ds, q, mode="count")
+                    assert c.count == cnt
+                    results[(graphs, rep, i)] = (a.count, ids.tobytes(), words.tobytes())
+            ds.set_profiling(False)
+        for key, val in results.items():
+            assert val == results[(0, key[1], key[2])], key
+        launches, scan_ms, total_ms = ds.profile()
+        assert launches > 0 and 0 < scan_ms <= total_ms

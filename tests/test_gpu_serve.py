@@ -160,9 +160,10 @@ def test_serve_with_estimated_order_is_exact():
 def test_full_size_c5_served_sampled():
     """The serving shape at full size (2*10^8 x 12 resident), as the bench runs it:
     requests replayed through the serving loop with estimated order (an untrained
-    estimator: the histogram ranking) and AUTO outputs; every count equals the query
-    alone, and a sample of results equals the oracle's identifiers."""
+    estimator: the histogram ranking) and AUTO outputs; every count and a sample of
+    results equal the oracle's."""
     from paper_1801_03644_amd.mdrq import Estimator
+    from tests.gpu_helpers import oracle_counts
 
     w = dg.workload("c5")
     _print("c5 full size: generating")
@@ -179,13 +180,54 @@ def test_full_size_c5_served_sampled():
                                        max_batch=32, n_streams=2, budget_bytes=2 << 30,
                                        use_estimator=True)
         assert stats["completed"] == len(qs)
-        for i, q in enumerate(qs):
-            assert answers[i].count == ds.query(q, None, mode="count").count, i
+        _print("c5 full size: oracle counts of all", len(qs))
+        assert [a.count for a in answers] == oracle_counts(cols, qs)
         for i in (0, 7, 19):
             _print("c5 full size: oracle", i)
             st, cnt, want = oracle.query(cols, qs[i])
             assert answers[i].count == cnt
             assert answers[i].status == mdrq.OK
             assert np.array_equal(payload(outs[i], answers[i], ds.n_rows), want), i
+        ds.attach_estimator(None)
+        est.close()
+
+
+def test_serving_with_estimate_sized_scratch():
+    """Serving with the estimator: requests are admitted by the scratch their estimate
+    needs (smaller than a bitmap row for small results), so more of them share a scan;
+    with the reserve factor forced to 10^-6 most of them outgrow their room and are
+    answered again.  Every result equals the oracle's."""
+    from paper_1801_03644_amd.mdrq import Estimator
+
+    w = dg.workload("c5", 2_000_003)
+    raw = w.columns()
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 120, sampler=w.sampler(sample_rows=1 << 15), seed=9)
+    modes = [("ids", "auto", "bitmap")[i % 3] for i in range(len(qs))]
+    want = [oracle.query(cols, q) for q in qs]
+    with mdrq.Dataset.from_host(raw) as ds:
+        est = Estimator(ds)
+        ds.attach_estimator(est)
+        row_bytes = 8 * ((ds.n_rows + 63) // 64)
+        for factor in (4_000_000, 1):
+            ds.set_option(mdrq.OPT_RESERVE_FACTOR, factor)
+            outs = outputs(ds.n_rows, modes)
+            # a burst: every request waits at once, so batches are bounded by memory
+            answers, lat, stats = ds.serve(poisson(len(qs), 100_000_000, seed=3), qs, outs, modes,
+                                           max_batch=64, n_streams=2, budget_bytes=8 * row_bytes,
+                                           use_estimator=True)
+            _print("factor", factor, "mean batch", stats["mean_batch"], "sized", stats["sized_by_estimate"],
+                   "reruns", stats["overflow_reruns"])
+            assert stats["completed"] == len(qs) and stats["sized_by_estimate"] > 0
+            if factor == 1:
+                assert stats["overflow_reruns"] > 0
+            else:
+                # a stream's share holds three bitmap rows with their marks; estimates
+                # admit more requests per scan
+                assert stats["mean_batch"] > 3
+            for i, (a, o) in enumerate(zip(answers, outs)):
+                st, cnt, ids = want[i]
+                assert a.count == cnt and a.status == mdrq.OK, i
+                assert np.array_equal(payload(o, a, ds.n_rows), ids), (factor, i)
         ds.attach_estimator(None)
         est.close()
