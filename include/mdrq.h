@@ -153,6 +153,23 @@ int mdrq_query(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r, void* 
 int mdrq_query_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n_queries,
                      mdrq_result_t* rs, void* stream);
 
+/*
+ * mdrq_query without allocation, for callers that cannot allocate device memory during
+ * a call (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, results and errors as mdrq_query, but the scan's
+ * workspace (staged bitmap, per-tile and per-workgroup counts, scan state) is a fixed
+ * 32 MiB array compiled into the library, one per GPU, held until the process ends;
+ * the call allocates no device memory (no hipMalloc or hipFree) and builds its launch
+ * parameters without the host heap.  Calls on one GPU share
+ * that array and are serialised by a process-wide lock per device; the array keeps the
+ * last call's contents, and each call clears what must start at zero.  Limits:
+ * results must be count-only or in device memory (host buf: MDRQ_EINVAL), predicates
+ * are evaluated in the order given (MDRQ_Q_ORDER_ESTIMATED: MDRQ_ENOTSUP), and the
+ * dataset must fit the array (about n_rows / 8 + n_rows / 512 bytes at the default tile
+ * height, i.e. up to about 2.6e8 rows; larger: MDRQ_ENOTSUP).
+ */
+int mdrq_query_noalloc(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r, void* stream);
+
 /* Serving configuration.  n_streams workers each own a device stream and an equal share
  * of result_budget_bytes of device memory for the scans' scratch: a request whose result
  * needs identifiers or a bitmap reserves one bitmap row of ceil(n_rows / 64) words and

@@ -1182,6 +1182,13 @@ int batch_blocks_per_cu(int n_slots, int waves, int rg, int lds_variant, size_t 
   return blocks > 0 ? blocks : 1;
 }
 
+hipError_t launch_zero_words(uint64_t* w, uint64_t n, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
+  zero_words_kernel<<<static_cast<uint32_t>(blocks), 256, 0, stream>>>(w, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_scan(const BatchParams& bp, int n_slots, int waves, int rg, int lds_variant,
                              dim3 grid, size_t lds_bytes, hipStream_t stream, int sw) {
   const int w = waves == 8 ? 8 : 4;

@@ -204,6 +204,8 @@ constexpr bool batch_reg_uses_marks(int reg_slots) { return reg_slots <= 8; }
 // LDS bytes the LDS variant stages keys in: waves x slots x rows per lane x 64 x 4.
 size_t batch_lds_key_bytes(int n_slots, int waves, int rg);
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream);
+// Zero n 64-bit words with a fill kernel (no memset node, so capturable).
+hipError_t launch_zero_words(uint64_t* w, uint64_t n, hipStream_t stream);
 // The kernel launches of one shared scan (zeroing, scan, count, emit) as graph kernel
 // node parameters, whose arguments point into *L (kept alive while they are used).
 struct BatchLaunches {

@@ -422,6 +422,47 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
                     out_elems, grid, seg, host_out);
 }
 
+// ---------------------------------------------------------------- fixed scratch
+
+// mdrq_query_noalloc's workspace: one array per GPU, part of the library's code object
+// (so nothing is allocated at call time), kept until the process ends.  Host code never
+// passes `scratch` itself to a kernel (on the host it names a host-side stand-in): it
+// uses the device address that hipGetSymbolAddress returns for the current device.
+constexpr uint64_t kScratchBytes = uint64_t{32} << 20;
+constexpr uint64_t kScratchMaxGrid = 4096;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];   // one call at a time per GPU
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+struct ScratchLayout {
+  uint64_t state, block_sums, tile_counts, bitmap, end;
+};
+ScratchLayout scratch_layout(uint64_t n_rows, uint64_t n_tiles, uint64_t grid) {
+  auto up = [](uint64_t x) { return (x + 255) / 256 * 256; };
+  ScratchLayout l{};
+  l.state = 0;
+  l.block_sums = up(sizeof(ScanState));
+  l.tile_counts = l.block_sums + up(grid * 4);
+  l.bitmap = l.tile_counts + up(n_tiles * 4);
+  l.end = l.bitmap + ((n_rows + 63) / 64 + 1) * 8;
+  return l;
+}
+
+// Device address of this GPU's scratch, looked up once per device (the current one).
+int scratch_address(int dev, unsigned char** out) {
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(MDRQ_EDEVICE, "scratch has no device address");
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return MDRQ_OK;
+}
+
 }  // namespace mdrq
 
 extern "C" {
@@ -573,6 +614,13 @@ int mdrq_set_profiling(mdrq_dataset* ds, int enable) {
   clear_error();
   if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
   std::lock_guard<std::mutex> lock(ds->mu);
+  // The events are created here, so that timed calls (mdrq_query_noalloc too) allocate
+  // nothing.
+  if (enable) {
+    if (!ds->ev0) MDRQ_HIP(hipEventCreate(&ds->ev0), "hipEventCreate");
+    if (!ds->ev1) MDRQ_HIP(hipEventCreate(&ds->ev1), "hipEventCreate");
+    if (!ds->ev2) MDRQ_HIP(hipEventCreate(&ds->ev2), "hipEventCreate");
+  }
   ds->profiling = enable != 0;
   return MDRQ_OK;
 }
@@ -740,6 +788,82 @@ int mdrq_query_read_bytes(mdrq_dataset* ds, const mdrq_query_t* q, uint64_t* byt
 }
 
 const char* mdrq_version(void) { return "0.1.0"; }
+
+int mdrq_query_noalloc(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r, void* stream_) {
+  return guarded([&]() -> int {
+    clear_error();
+    if (!ds) return fail(MDRQ_EINVAL, "dataset is NULL");
+    int rc = check_query(ds, q);
+    if (rc) return rc;
+    rc = check_result(r);
+    if (rc) return rc;
+    if (q->flags & MDRQ_Q_ORDER_ESTIMATED)
+      return fail(MDRQ_ENOTSUP, "mdrq_query_noalloc evaluates predicates in the order given");
+    if (r->mem == MDRQ_MEM_HOST && r->mode != MDRQ_OUT_COUNT)
+      return fail(MDRQ_EINVAL, "mdrq_query_noalloc writes results to device memory only");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MDRQ_ENOTSUP, "device index beyond the scratch table");
+    // No heap use from here on: the plan is built in the launch parameters directly.
+    std::lock_guard<std::mutex> lock(ds->mu);
+    std::lock_guard<std::mutex> single(ds->single_mu);
+    std::lock_guard<std::mutex> gpu(g_scratch_mu[dev]);
+    unsigned char* base = nullptr;
+    rc = scratch_address(dev, &base);
+    if (rc) return rc;
+    Plan plan;  // empty vectors: no allocation
+    const float inf = std::numeric_limits<float>::infinity();
+    plan.mode = r->mode == MDRQ_OUT_BITMAP ? kBitmap : r->mode == MDRQ_OUT_COUNT ? kCount : kIds;
+    plan.auto_mode = r->mode == MDRQ_OUT_AUTO;
+    plan.capacity = plan.mode == kIds ? r->buf_bytes / 4 : plan.mode == kBitmap ? r->buf_bytes / 8 : 0;
+    plan.early_out = !(q->flags & MDRQ_Q_NO_EARLYOUT);
+    r->mode = plan.mode == kBitmap ? MDRQ_OUT_BITMAP : plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
+    for (uint32_t i = 0; i < q->n_preds; ++i) plan.empty |= q->preds[i].lo > q->preds[i].hi;
+    if (plan.empty || ds->n_rows == 0) {
+      r->count = 0;
+      r->written = 0;
+      r->status = MDRQ_OK;
+      if (plan.mode == kBitmap) {
+        const uint64_t words = std::min(plan.capacity, n_words(ds));
+        if (words) {
+          e = launch_zero_words(static_cast<uint64_t*>(r->buf), words, stream);
+          if (e == hipSuccess) e = hipStreamSynchronize(stream);
+          if (e != hipSuccess) return fail_hip(e, "clearing the bitmap");
+        }
+        r->written = words;
+        if (plan.capacity < n_words(ds)) r->status = MDRQ_EOVERFLOW;
+      }
+      return r->status;
+    }
+    const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(ds->unroll));
+    const uint32_t kmode = plan.mode == kIds ? kStage : plan.mode;
+    const uint64_t n_tiles = (ds->n_rows + tile - 1) / tile;
+    uint64_t grid = 0, seg = 0;
+    scan_shape(ds, kmode, n_tiles, kScratchMaxGrid, &grid, &seg);
+    const ScratchLayout L = scratch_layout(ds->n_rows, n_tiles, grid);
+    if (L.end > kScratchBytes)
+      return fail(MDRQ_ENOTSUP, "dataset too large for mdrq_query_noalloc's fixed 32 MiB scratch "
+                                "(bitmap of n_rows / 8 bytes plus tile counts; about 2.6e8 rows at "
+                                "the default tile height)");
+    // The scan state must start at zero; the last call may have been cut short.
+    ScanWork w{reinterpret_cast<ScanState*>(base + L.state), reinterpret_cast<uint64_t*>(base + L.bitmap),
+               reinterpret_cast<uint32_t*>(base + L.tile_counts), reinterpret_cast<uint32_t*>(base + L.block_sums)};
+    e = launch_zero_words(reinterpret_cast<uint64_t*>(w.state), sizeof(ScanState) / 8, stream);
+    if (e != hipSuccess) return fail_hip(e, "clearing the scan state");
+    // Predicates that can change the result, in the order given.
+    DevPred preds[MDRQ_MAX_DIMS];
+    uint32_t k = 0;
+    for (uint32_t i = 0; i < q->n_preds; ++i) {
+      const mdrq_pred& pr = q->preds[i];
+      if (pr.lo == -inf && pr.hi == inf) continue;
+      preds[k++] = DevPred{ds->cols[pr.dim], pr.lo, pr.hi};
+    }
+    const uint64_t out_elems = plan.mode == kBitmap ? std::min(plan.capacity, n_words(ds)) : plan.capacity;
+    return scan_query(ds, plan, preds, k, r, stream, w, r->buf, out_elems, grid, seg, false);
+  });
+}
 
 int mdrq_query_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n_queries,
                      mdrq_result_t* rs, void* stream) {

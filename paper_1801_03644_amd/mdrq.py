@@ -34,7 +34,7 @@ EXPORTS = ["mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve", 
            "mdrq_estimator_set_params", "mdrq_label_selectivities", "mdrq_estimator_gradient",
            "mdrq_estimator_train", "mdrq_estimator_predict", "mdrq_attach_estimator",
            "mdrq_estimator_activations", "mdrq_query_read_bytes", "mdrq_estimator_gate",
-           "mdrq_get_sizing_profile", "mdrq_get_batch_work",
+           "mdrq_get_sizing_profile", "mdrq_get_batch_work", "mdrq_query_noalloc",
            "mdrq_serve_open", "mdrq_serve_submit", "mdrq_serve_poll", "mdrq_serve_close"]
 EST_BINS = 16
 EST_FEATS = EST_BINS + 3  # per dimension: H(lo), H(hi), histogram estimate, bins
@@ -167,6 +167,7 @@ def load_library(path: str = LIB_PATH):
     lib.mdrq_estimator_gate.argtypes = [vp, P(Query), u32, fp, P(u32)]
     lib.mdrq_get_sizing_profile.argtypes = [vp, P(u64), P(u64)]
     lib.mdrq_get_batch_work.argtypes = [vp, P(u64), P(u64), P(ctypes.c_double)]
+    lib.mdrq_query_noalloc.argtypes = [vp, P(Query), P(Result), vp]
     for f in ("mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve",
               "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
               "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth",
@@ -175,7 +176,7 @@ def load_library(path: str = LIB_PATH):
               "mdrq_estimator_set_params", "mdrq_label_selectivities", "mdrq_estimator_gradient",
               "mdrq_estimator_train", "mdrq_estimator_predict", "mdrq_attach_estimator",
               "mdrq_estimator_activations", "mdrq_query_read_bytes", "mdrq_estimator_gate",
-              "mdrq_get_sizing_profile", "mdrq_get_batch_work"):
+              "mdrq_get_sizing_profile", "mdrq_get_batch_work", "mdrq_query_noalloc"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -335,6 +336,16 @@ class Dataset:
         q, keep = make_query(query, flags)
         r = _result_for(out, mode)
         rc = lib.mdrq_query(self._h, ctypes.byref(q), ctypes.byref(r), _stream_handle(stream))
+        _check(rc, (OK, EOVERFLOW))
+        return Answer(r.count, r.written, r.status, _MODE_NAMES[r.mode])
+
+    def query_noalloc(self, query, out=None, mode: str = "ids", flags: int = 0, stream=None) -> Answer:
+        """As query(), through mdrq_query_noalloc: the library's fixed per-GPU scratch
+        instead of the dataset's workspace (device outputs, given order)."""
+        lib = load_library()
+        q, keep = make_query(query, flags)
+        r = _result_for(out, mode)
+        rc = lib.mdrq_query_noalloc(self._h, ctypes.byref(q), ctypes.byref(r), _stream_handle(stream))
         _check(rc, (OK, EOVERFLOW))
         return Answer(r.count, r.written, r.status, _MODE_NAMES[r.mode])
 
