@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-earlyout", action="store_true")
     ap.add_argument("--unroll", type=int, default=None)
+    ap.add_argument("--blocks-per-cu", type=int, default=None,
+                    help="single-query scans: workgroups per CU (MDRQ_OPT_BLOCKS_PER_CU)")
     ap.add_argument("--graphs", type=int, default=None,
                     help="MDRQ_OPT_GRAPHS: bit 0 single queries, bit 1 shared scans replayed from graphs")
     ap.add_argument("--counters", type=int, default=0, metavar="Q",
@@ -245,6 +247,8 @@ def main():
         ds.set_option(mdrq.OPT_UNROLL, args.unroll)
     if args.graphs is not None:
         ds.set_option(mdrq.OPT_GRAPHS, args.graphs)
+    if args.blocks_per_cu:
+        ds.set_option(mdrq.OPT_BLOCKS_PER_CU, args.blocks_per_cu)
     flags = mdrq.Q_NO_EARLYOUT if args.no_earlyout else 0
     out = torch.empty(w.n_rows, dtype=torch.int32, device="cuda:0")
     prepared = [mdrq.make_query(q, flags) for q in queries]
@@ -359,6 +363,7 @@ def main():
                    "n_rows": w.n_rows, "n_dims": w.n_dims, "queries_per_step": n_q,
                    "mean_queried_dims": float(ks.mean()), "mean_selectivity": float(sel.mean()),
                    "early_out": not args.no_earlyout, "graphs": args.graphs or 0,
+                   "unroll": args.unroll or 8, "blocks_per_cu": args.blocks_per_cu or 3,
                    "data_seed": w.data_seed,
                    "query_seed": w.query_seed},
         "queries_per_s": total_q / elapsed,

@@ -209,6 +209,12 @@ __device__ __forceinline__ uint32_t med3u(uint32_t x, uint32_t lo, uint32_t hi) 
   return r;
 }
 
+// Order-preserving key from the raw bits of a float, -0 one below +0 (the rank
+// variant's keys: three instructions).
+__device__ __forceinline__ uint32_t rkey(uint32_t b) {
+  return b ^ (static_cast<uint32_t>(static_cast<int32_t>(b) >> 31) | 0x80000000u);
+}
+
 // Order-preserving key from the raw bits of a non-NaN float (as dkey).
 __device__ __forceinline__ uint32_t bkey(uint32_t b) {
   if (b == 0x80000000u) b = 0u;
@@ -510,36 +516,49 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
         const float scale = __uint_as_float(__builtin_amdgcn_readfirstlane(h.w));
         const uint32_t* bucket = B - (nbm1 + 1);   // per bucket: first end | past-last << 16
         const uint32_t* T = B + ((M + 1 + 3) & ~3u);
-        uint32_t x[RG];
+        // Keys are the raw order-preserving keys (-0 just below +0): the host places an
+        // interval end at zero so that both zeros fall on the same side of it.  Bucket
+        // of each row: by key, min((max(key, kmin) - kmin) >> shift, nb - 1), or by value,
+        // trunc(clamp((v - vlo) * scale, 0, nb - 1)) in the host's float arithmetic.  A
+        // chunk inside the data loads from one uniform base with lane offsets; in the
+        // last chunk rows past the end take key 0 and bucket 0 (rank 0).
+        uint32_t x[RG], bk[RG];
+        const float vlo = __uint_as_float(base), top = static_cast<float>(nbm1);
+        if (full) {
+          const float* c = bp.slot_cols[s] + row0 + lane;
 #pragma unroll
-        for (int g = 0; g < RG; ++g) {
-          const uint64_t r = row0 + 64 * g + lane;
-          const uint64_t rc = r < bp.n_rows ? r : bp.n_rows - 1;
-          x[g] = __float_as_uint(__builtin_nontemporal_load(&bp.slot_cols[s][rc]));
-        }
-        // Bucket of each row: by key, min((max(key, kmin) - kmin) >> shift, nb - 1), or
-        // by value, trunc(clamp((v - vlo) * scale, 0, nb - 1)) in the host's float
-        // arithmetic; rows past the end take key 0 and bucket 0 (rank 0).
-        uint32_t bk[RG];
-        if (by_value) {
-          const float vlo = __uint_as_float(base), top = static_cast<float>(nbm1);
+          for (int g = 0; g < RG; ++g) x[g] = __float_as_uint(__builtin_nontemporal_load(c + 64 * g));
+          if (by_value) {
 #pragma unroll
-          for (int g = 0; g < RG; ++g) {
-            const float t = (__uint_as_float(x[g]) - vlo) * scale;
-            bk[g] = static_cast<uint32_t>(fminf(fmaxf(t, 0.0f), top));
-          }
+            for (int g = 0; g < RG; ++g) {
+              const float t = (__uint_as_float(x[g]) - vlo) * scale;
+              bk[g] = static_cast<uint32_t>(__builtin_amdgcn_fmed3f(t, 0.0f, top));
+            }
 #pragma unroll
-          for (int g = 0; g < RG; ++g) {
-            const bool in = full || row0 + 64 * g + lane < bp.n_rows;
-            x[g] = in ? bkey(x[g]) : 0u;
-            bk[g] = in ? bk[g] : 0u;
+            for (int g = 0; g < RG; ++g) x[g] = rkey(x[g]);
+          } else {
+#pragma unroll
+            for (int g = 0; g < RG; ++g) {
+              x[g] = rkey(x[g]);
+              const uint32_t b = (x[g] > base ? x[g] - base : 0u) >> shift;
+              bk[g] = b < nbm1 ? b : nbm1;
+            }
           }
         } else {
 #pragma unroll
           for (int g = 0; g < RG; ++g) {
-            x[g] = (full || row0 + 64 * g + lane < bp.n_rows) ? bkey(x[g]) : 0u;
+            const uint64_t r = row0 + 64 * g + lane;
+            const uint64_t rc = r < bp.n_rows ? r : bp.n_rows - 1;
+            x[g] = __float_as_uint(__builtin_nontemporal_load(&bp.slot_cols[s][rc]));
+          }
+#pragma unroll
+          for (int g = 0; g < RG; ++g) {
+            const bool in = row0 + 64 * g + lane < bp.n_rows;
+            const float t = (__uint_as_float(x[g]) - vlo) * scale;
+            const uint32_t bv = static_cast<uint32_t>(__builtin_amdgcn_fmed3f(t, 0.0f, top));
+            x[g] = in ? rkey(x[g]) : 0u;
             const uint32_t b = (x[g] > base ? x[g] - base : 0u) >> shift;
-            bk[g] = b < nbm1 ? b : nbm1;
+            bk[g] = !in ? 0u : by_value ? bv : b < nbm1 ? b : nbm1;
           }
         }
         // rank = number of ends <= key: the ends in lower buckets, then a binary search

@@ -322,18 +322,10 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     std::vector<std::vector<KeyInterval>> iv(n_slots, std::vector<KeyInterval>(gq));
     for (uint64_t q = q0; q < q1; ++q) {
       const Plan& pl = items[q].plan;
-      for (size_t i = 0; i < pl.preds.size(); ++i) {
-        KeyInterval& k = iv[slot_of[pl.dims[i]]][q - q0];
-        k.klo = batch_key(pl.preds[i].lo);
-        k.khi = batch_key(pl.preds[i].hi);
-        k.has = true;
-      }
-      if (pl.preds.empty()) {
-        KeyInterval& k = iv[0][q - q0];
-        k.klo = batch_key(-std::numeric_limits<float>::infinity());
-        k.khi = batch_key(std::numeric_limits<float>::infinity());
-        k.has = true;
-      }
+      for (size_t i = 0; i < pl.preds.size(); ++i)
+        iv[slot_of[pl.dims[i]]][q - q0] = rank_interval(pl.preds[i].lo, pl.preds[i].hi);
+      if (pl.preds.empty())
+        iv[0][q - q0] = rank_interval(-std::numeric_limits<float>::infinity(), std::numeric_limits<float>::infinity());
     }
     // Per slot the sorted distinct interval ends and their buckets: up to kRankBuckets
     // buckets where the group's tables then stay within kRankLdsWords (two workgroups

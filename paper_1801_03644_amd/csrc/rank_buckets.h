@@ -173,6 +173,23 @@ struct KeyInterval {
   bool has = false;
 };
 
+// The rank variant's keys: order-preserving keys of the raw bits, -0 (0x7FFFFFFF) one
+// below +0 (0x80000000), so the kernel needs no zero test.  An interval [lo, hi] takes
+// the key of -0 for a lower end at zero and the key of +0 for an upper end at zero, so
+// both zeros fall inside exactly when zero does (-0 == +0).
+inline uint32_t rank_key(float x) {
+  uint32_t b;
+  std::memcpy(&b, &x, sizeof b);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+inline KeyInterval rank_interval(float lo, float hi) {
+  KeyInterval k;
+  k.klo = lo == 0.0f ? 0x7FFFFFFFu : rank_key(lo);
+  k.khi = hi == 0.0f ? 0x80000000u : rank_key(hi);
+  k.has = true;
+  return k;
+}
+
 // Append one column's tables to a group's words g (whose size is 4-word aligned on
 // entry and stays so): per bucket one word holding the index of its first end (the
 // number of ends in lower buckets) in the low 16 bits and the index past its last end

@@ -217,6 +217,35 @@ int main() {
         }
     }
   }
+  // The rank variant's interval keys: for every interval [lo, hi] and value x of a set
+  // with both zeros, infinities, subnormals and their neighbours, lo <= x <= hi exactly
+  // when klo <= rank_key(x) < khi + 1.
+  {
+    std::vector<float> vals = {0.0f, -0.0f, INFINITY, -INFINITY, 1e-45f, -1e-45f, 1.17549435e-38f,
+                               -1.17549435e-38f, 1.0f, -1.0f, 0.5f, -2.5f, 3.4e38f, -3.4e38f};
+    const size_t base_n = vals.size();
+    for (size_t i = 0; i < base_n; ++i) {
+      vals.push_back(std::nextafter(vals[i], INFINITY));
+      vals.push_back(std::nextafter(vals[i], -INFINITY));
+    }
+    int checked = 0;
+    for (float lo : vals)
+      for (float hi : vals) {
+        if (!(lo <= hi)) continue;
+        const mdrq::KeyInterval k = mdrq::rank_interval(lo, hi);
+        for (float x : vals) {
+          const bool want = lo <= x && x <= hi;
+          const uint32_t kx = mdrq::rank_key(x);
+          const bool got = k.klo <= kx && kx < k.khi + 1;
+          if (want != got) {
+            if (bad < 5) std::printf("rank key: lo=%g hi=%g x=%g\n", lo, hi, x);
+            ++bad;
+          }
+          ++checked;
+        }
+      }
+    std::printf("rank interval checks %d\n", checked);
+  }
   std::printf("bad=%d key_maps=%d value_maps=%d slot_tables=%d\n", bad, key_maps, value_maps, tables);
   return bad != 0 || value_maps == 0 || key_maps == 0;
 }
