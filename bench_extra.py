@@ -328,6 +328,7 @@ def learned(args):
                         ("plain_histogram_order", lambda: run.plain(E), hist_est),
                         ("plain_learned_order", lambda: run.plain(E), est),
                         ("batched_given_order", lambda: run.batch(G), est),
+                        ("batched_learned_order", lambda: run.batch(E), est),
                         ("batched_learned_order_and_sizing", lambda: run.batch(ES), est)):
         log(name)
         ds.attach_estimator(e)
@@ -353,15 +354,29 @@ def learned(args):
     lab = s_test[:, -1].astype(np.float64) * n
     if np.abs(lab - ref).max() > 1e-6 * n + 1:   # labels are float32 count / N
         raise RuntimeError("labels disagree with the scan counts")
-    best = variants["batched_learned_order_and_sizing"]["queries_per_s"]
+    best = max(variants["batched_learned_order"]["queries_per_s"],
+               variants["batched_learned_order_and_sizing"]["queries_per_s"])
+    # Scratch the shared scans reserve for the held-out queries: a bitmap row and its
+    # chunk marks each (worst case), against the estimate-sized room where it is smaller
+    # (the serving loop's admission sizes).
+    nw = (n + 63) // 64
+    dense_b = nw * 8 + ((n + 255) // 256) * 2
+    nch = (n + 511) // 512
+    est_rows = pred[:, -1].astype(np.float64) * n
+    want = np.minimum(nch, np.ceil(4.0 * est_rows) + 64)
+    sparse_b = nch * 4 + want * 64
+    sized_b = np.where(sparse_b < nw * 8 + nch * 2, sparse_b, dense_b)
+    scratch = {"worst_case_bytes_per_query": float(dense_b), "estimate_sized_mean_bytes": float(sized_b.mean()),
+               "estimate_sized_median_bytes": float(np.median(sized_b)),
+               "queries_sized": int((sparse_b < nw * 8 + nch * 2).sum())}
     line = _line(best, "queries/s",
                  {"workload": f"c4: {n} rows x {w.n_dims} float32 columns (10 correlated pairs), "
                               f"{n_tr} training / {n_va} validation / {n_te} held-out queries, ids output",
                   "n_rows": n, "n_dims": w.n_dims, "train_queries": n_tr, "validation_queries": n_va,
                   "test_queries": n_te, "hidden": 64, "epochs": args.epochs, "data_seed": w.data_seed,
                   "query_seed": w.query_seed, "split_seed": w.split_seed},
-                 1, 0, variants["batched_learned_order_and_sizing"]["seconds"] * 1e3,
-                 {"variants": variants, "q_error": qerr,
+                 1, 0, n_te / best * 1e3,
+                 {"variants": variants, "q_error": qerr, "scratch_reservation": scratch,
                   "speedup_vs_plain_given_order": best / variants["plain_given_order"]["queries_per_s"],
                   "learned_vs_histogram_order_plain": variants["plain_learned_order"]["queries_per_s"]
                   / variants["plain_histogram_order"]["queries_per_s"],
@@ -379,7 +394,9 @@ def learned(args):
 
 def serving(args):
     """c5: Poisson arrivals at each rate replayed through mdrq_serve (2 streams, shared
-    scans of up to 256, estimated predicate order), results in device memory."""
+    scans of up to 256), results in device memory; with the estimator's order and
+    estimate-sized admission, and, for comparison, its order with worst-case
+    reservations."""
     import torch
 
     from paper_1801_03644_amd import datagen as dg
@@ -404,7 +421,7 @@ def serving(args):
     rates = [float(r) for r in args.rates.split(",")]
     budget = 8 << 30
 
-    def serve(rate, seconds, seed):
+    def serve(rate, seconds, seed, use_estimator=3):
         n = max(1, int(rate * seconds))
         r = np.random.default_rng(seed)
         arrivals = np.cumsum(r.exponential(1e9 / rate, size=n)).astype(np.uint64)
@@ -413,7 +430,7 @@ def serving(args):
         # output buffers are reused cyclically; only counts are checked here
         outs = [bufs[i % n_buf] for i in range(n)]
         answers, lat, st = ds.serve(arrivals, qs, outs, "auto", max_batch=256, n_streams=2,
-                                    budget_bytes=budget, use_estimator=True)
+                                    budget_bytes=budget, use_estimator=use_estimator)
         counts = np.array([a.count for a in answers])
         if not np.array_equal(counts, pool_counts[pick]):
             raise RuntimeError("served counts differ from single-query counts")
@@ -422,13 +439,18 @@ def serving(args):
     log("warm-up")
     serve(rates[0], 0.2, 1)
     per_rate = {}
+    keys = ("completed", "scans", "wall_s", "qps", "p50_us", "p99_us", "mean_us", "max_us", "mean_batch",
+            "hbm_gbps", "sized_by_estimate", "overflow_reruns")
     for i, rate in enumerate(rates):
-        log(f"rate {rate:.0f}/s for {args.serve_seconds}s")
-        st = serve(rate, args.serve_seconds, 100 + i)
-        per_rate[str(int(rate))] = {k: st[k] for k in ("completed", "scans", "wall_s", "qps", "p50_us",
-                                                       "p99_us", "mean_us", "max_us", "mean_batch",
-                                                       "hbm_gbps", "sized_by_estimate", "overflow_reruns")}
+        log(f"rate {rate:.0f}/s for {args.serve_seconds}s: learned order and sizing")
+        st = serve(rate, args.serve_seconds, 100 + i, 3)
+        per_rate[str(int(rate))] = {k: st[k] for k in keys}
         log(f"rate {rate:.0f}: {st['qps']:.0f} q/s, p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us")
+        log(f"rate {rate:.0f}/s: learned order, worst-case reservations")
+        st1 = serve(rate, args.serve_seconds, 100 + i, 1)
+        per_rate[str(int(rate))]["order_only"] = {k: st1[k] for k in keys}
+        log(f"rate {rate:.0f} (order only): {st1['qps']:.0f} q/s, p50 {st1['p50_us']:.0f} us, "
+            f"p99 {st1['p99_us']:.0f} us")
     top = per_rate[str(int(rates[-1]))]
     line = _line(top["qps"], "queries/s",
                  {"workload": f"c5: {w.n_rows} rows x {w.n_dims} float32 columns resident, Poisson "
@@ -467,17 +489,17 @@ def paper(args):
         raw = w.columns()
         qs = dg.two_object_queries(raw, n_q, seed=w.query_seed)
         ds = mdrq.Dataset.from_host(raw)
-        out = torch.empty((1024, n), dtype=torch.int32, device="cuda:0")
-        run = Runner(ds, qs, out, stream)
+        run = Runner(ds, qs, _exact_counts(ds, qs), stream)
         run.plain()
         c_plain, t_plain = _timed(run.plain)
         run.batch()
         c_batch, t_batch = _timed(run.batch)
         if not np.array_equal(c_plain, c_batch):
             raise RuntimeError("batched counts differ from single-query counts")
+        run.check_complete()
         sel = c_plain / n
         ds.close()
-        del out
+        del run
         r = {"n_rows": n, "dims": d, "plain_queries_per_s": n_q / t_plain,
              "batched_queries_per_s": n_q / t_batch, "mean_selectivity_percent": 100 * float(sel.mean()),
              "sigma_selectivity_percent": 100 * float(sel.std())}

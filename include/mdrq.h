@@ -173,9 +173,10 @@ int mdrq_query_noalloc(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r
 /* Serving configuration.  n_streams workers each own a device stream and an equal share
  * of result_budget_bytes of device memory for the scans' scratch: a request whose result
  * needs identifiers or a bitmap reserves one bitmap row of ceil(n_rows / 64) words and
- * its chunk marks (its result can never need more), or, with use_estimator, the room its
- * estimated result needs in the scan's sparse scratch (MDRQ_Q_SIZE_ESTIMATED; about four
- * times the estimate, and never more than the row); a count-only request reserves none.
+ * its chunk marks (its result can never need more), or, with use_estimator bit 1, the
+ * room its estimated result needs in the scan's sparse scratch (MDRQ_Q_SIZE_ESTIMATED;
+ * about four times the estimate, and never more than the row); a count-only request
+ * reserves none.
  * A worker that is idle takes the oldest waiting requests, at most max_batch and as many
  * as its share holds, and answers them with one batched shared scan (as
  * mdrq_query_batch); requests that arrive meanwhile wait for the next idle worker
@@ -184,10 +185,11 @@ typedef struct {
   uint64_t result_budget_bytes;
   uint32_t max_batch;       /* 1 .. MDRQ_MAX_BATCH */
   uint32_t n_streams;       /* 1 .. 8 */
-  uint32_t use_estimator;   /* 1: every request evaluates its predicates in estimated
-                               order and has its scratch sized by its estimate
-                               (MDRQ_Q_ORDER_ESTIMATED | MDRQ_Q_SIZE_ESTIMATED; needs an
-                               attached estimator) */
+  uint32_t use_estimator;   /* bit 0: every request evaluates its predicates in
+                               estimated order (MDRQ_Q_ORDER_ESTIMATED); bit 1: every
+                               request has its scratch sized by its estimate and is
+                               admitted by that size (MDRQ_Q_SIZE_ESTIMATED); either
+                               needs an attached estimator */
   uint32_t max_queue;       /* live server: requests allowed to wait; a submission
                                beyond it fails with MDRQ_EBUSY (admission control).
                                0 = unbounded.  The replay ignores it. */

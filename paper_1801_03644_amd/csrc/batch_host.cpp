@@ -153,7 +153,8 @@ hipError_t launch_shared_graph(BatchWorkspace& ws, const BatchParams& bp, const 
 // than kMaxSlots columns take the LDS variant).
 // ms_out receives the device time of the scan and finish launches.
 int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
-               const BatchConfig& cfg_in, hipStream_t stream, float* ms_out, BatchRunStats* st = nullptr) {
+               const BatchConfig& cfg_in, hipStream_t stream, float* ms_out, BatchRunStats* st = nullptr,
+               std::vector<uint32_t>* redo = nullptr) {
   const uint64_t nq = items.size();
   // Scratch sized by estimate: pool slots per query (0: a full bitmap row).  Any such
   // query makes the scan a rank-variant scan of 512-row chunks, the layout the serving
@@ -465,7 +466,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     BatchConfig other = cfg;
     other.lds = 1;
     for (Item& it : items) it.est_rows = -1.0;
-    return run_shared(ds, ws, items, other, stream, ms_out, st);
+    return run_shared(ds, ws, items, other, stream, ms_out, st, redo);
   }
 
   // Outputs: device buffers directly, host buffers through device staging.
@@ -678,18 +679,23 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     if (kind != kBatchCount && r->mem == MDRQ_MEM_HOST && bytes)
       MDRQ_HIP(hipMemcpy(r->buf, outs[q].buf, bytes, hipMemcpyDeviceToHost), "copy result to host");
   }
-  // Queries whose estimate was too low for their scratch: answered again alone (the
-  // count above was exact already; the scan repeats it).
+  // Queries whose estimate was too low for their scratch: handed back in `redo` (the
+  // caller answers them again together, with worst-case scratch), or without it
+  // answered again here, each alone (the count above was exact already).
   const volatile uint32_t* over =
       reinterpret_cast<const volatile uint32_t*>(static_cast<const uint8_t*>(ws.h_res) + nq * 12);
   uint64_t n_reruns = 0;
   for (uint64_t q = 0; q < nq; ++q) {
     if (!outs[q].sparse || !over[q]) continue;
     Item& it = items[q];
+    ++n_reruns;
+    if (redo) {
+      redo->push_back(it.index);
+      continue;
+    }
     it.r->mode = it.plan.mode == kBitmap ? MDRQ_OUT_BITMAP : it.plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
     rc = run_query(ds, it.plan, it.r, stream);
     if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
-    ++n_reruns;
   }
   if (st) {
     st->sparse += n_sparse;
@@ -933,6 +939,9 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
   };
   std::vector<Item> shared;
   std::vector<uint32_t> alone;
+  std::vector<uint32_t> redo;   // queries whose estimate-sized scratch was too small
+  std::vector<uint32_t> asked(n);
+  for (uint32_t i = 0; i < n; ++i) asked[i] = rs[i].mode;
   for (uint32_t i = 0; i < n; ++i) {
     Plan plan = plan_of(i);
     if (plan.empty || ds->n_rows == 0) {
@@ -1006,7 +1015,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     if (used > kMaxSlots && !ds->batch_rows) cfg.rows_per_lane = used > 32 ? 1 : 2;
     float ms = 0.f;
     if (fixed) {
-      int rc = run_shared(ds, ws, batch, cfg, stream, &ms, st);
+      int rc = run_shared(ds, ws, batch, cfg, stream, &ms, st, &redo);
       if (rc) return rc;
     } else {
       const uint64_t key = shape_key(ds->n_rows, static_cast<size_t>(used), batch.size());
@@ -1028,7 +1037,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
             }
       }
       if (known || !tune) {
-        int rc = run_shared(ds, ws, batch, known ? known_cfg : cfg, stream, &ms, st);
+        int rc = run_shared(ds, ws, batch, known ? known_cfg : cfg, stream, &ms, st, &redo);
         if (rc) return rc;
       } else {
         // Every candidate computes the same exact results; keep the fastest.
@@ -1066,6 +1075,28 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
     }
     int rc = run_query(ds, plan, &rs[i], stream);
     if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
+  }
+  if (!redo.empty()) {
+    // Answered again together, with worst-case scratch: one shared scan for many, the
+    // single-query scan for a few (as any batch).
+    std::sort(redo.begin(), redo.end());
+    std::vector<mdrq_query_t> q2(redo.size());
+    std::vector<mdrq_result_t> r2(redo.size());
+    std::vector<float> e2;
+    for (size_t k = 0; k < redo.size(); ++k) {
+      const uint32_t i = redo[k];
+      q2[k] = qs[i];
+      q2[k].flags &= ~static_cast<uint32_t>(MDRQ_Q_SIZE_ESTIMATED);
+      r2[k] = rs[i];
+      r2[k].mode = asked[i];
+      if (!est.empty())
+        e2.insert(e2.end(), est.begin() + static_cast<size_t>(i) * (ds->n_dims + 1),
+                  est.begin() + static_cast<size_t>(i + 1) * (ds->n_dims + 1));
+    }
+    int rc = run_batch(ds, q2.data(), static_cast<uint32_t>(q2.size()), r2.data(), stream, wsp, tune, st,
+                       e2.empty() ? nullptr : e2.data());
+    if (rc != MDRQ_OK) return rc;
+    for (size_t k = 0; k < redo.size(); ++k) rs[redo[k]] = r2[k];
   }
   return MDRQ_OK;
 }

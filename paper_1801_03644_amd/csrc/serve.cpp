@@ -7,8 +7,8 @@
 // dispatcher hands it the oldest waiting requests, as many as max_batch allows and as
 // fit in the worker's share of scratch memory, and the worker answers them with one
 // call of the batched shared scan.  A request that needs identifiers or a bitmap
-// reserves a full bitmap row (its result can never need more), or, with the estimator
-// (use_estimator), room for about four times its estimated result in the scan's sparse
+// reserves a full bitmap row (its result can never need more), or, with estimated sizing
+// (use_estimator bit 1), room for about four times its estimated result in the scan's sparse
 // scratch: the dispatcher estimates waiting requests in bulk before admitting them, and
 // a request whose result outgrows its room is answered again by the single-query scan.  Requests that arrive while scans run wait for the next
 // idle worker, so scans of different workers overlap on the device.  Every request's
@@ -187,7 +187,7 @@ void dispatch_loop(mdrq_server* s) {
       any_busy |= w.busy;
     }
     if (idle && !s->ready.empty()) {
-      if (s->cfg.use_estimator) estimate_waiting(s, lk);
+      if (s->cfg.use_estimator & 2u) estimate_waiting(s, lk);
       uint64_t bytes = 0;
       while (!s->ready.empty() && idle->batch.size() < s->cfg.max_batch) {
         Pending* p = s->ready.front();
@@ -216,6 +216,7 @@ int check_config(const mdrq_dataset* ds, const mdrq_serve_config_t* cfg) {
   if (cfg->max_batch == 0 || cfg->max_batch > MDRQ_MAX_BATCH)
     return fail(MDRQ_EINVAL, "max_batch must be in 1..MDRQ_MAX_BATCH");
   if (cfg->n_streams == 0 || cfg->n_streams > 8) return fail(MDRQ_EINVAL, "n_streams must be in 1..8");
+  if (cfg->use_estimator > 3) return fail(MDRQ_EINVAL, "use_estimator must be 0..3");
   if (cfg->use_estimator && !ds->estimator)
     return fail(MDRQ_EINVAL, "use_estimator needs an attached estimator");
   return MDRQ_OK;
@@ -283,7 +284,8 @@ int enqueue(mdrq_server* s, const mdrq_query_t* q, mdrq_result_t* r, Clock::time
   p->q = *q;
   p->preds.assign(q->preds, q->preds + q->n_preds);
   p->q.preds = p->preds.data();
-  if (s->cfg.use_estimator) p->q.flags |= MDRQ_Q_ORDER_ESTIMATED | MDRQ_Q_SIZE_ESTIMATED;
+  if (s->cfg.use_estimator & 1u) p->q.flags |= MDRQ_Q_ORDER_ESTIMATED;
+  if (s->cfg.use_estimator & 2u) p->q.flags |= MDRQ_Q_SIZE_ESTIMATED;
   p->r = r;
   p->arrival = arrival;
   if (order) {

@@ -426,7 +426,7 @@ class Dataset:
         _check(load_library().mdrq_reset_profile(self._h))
 
     def serve(self, arrivals_ns, queries, outs, modes="ids", max_batch: int = 256,
-              n_streams: int = 2, budget_bytes: int = 1 << 30, use_estimator: bool = False):
+              n_streams: int = 2, budget_bytes: int = 1 << 30, use_estimator: int = 0):
         """Replay requests (arrival time in ns, query) through the serving loop.
         Returns (answers, latencies in ns, stats dict)."""
         lib = load_library()
@@ -440,7 +440,7 @@ class Dataset:
         rarr = (Result * max(1, n))(*[_result_for(o, m) for o, m in zip(outs, modes)])
         lat = (ctypes.c_uint64 * max(1, n))()
         st = ServeStats()
-        cfg = ServeConfig(int(budget_bytes), max_batch, n_streams, 1 if use_estimator else 0, 0)
+        cfg = ServeConfig(int(budget_bytes), max_batch, n_streams, int(use_estimator), 0)
         rc = lib.mdrq_serve(self._h, ctypes.byref(cfg), reqs, n, rarr, lat, ctypes.byref(st))
         _check(rc, (OK, EOVERFLOW))
         answers = [Answer(r.count, r.written, r.status, _MODE_NAMES[r.mode]) for r in rarr[:n]]
@@ -448,7 +448,7 @@ class Dataset:
         return answers, np.array(lat[:n], dtype=np.uint64), stats
 
     def serve_open(self, max_batch: int = 256, n_streams: int = 2, budget_bytes: int = 1 << 30,
-                   use_estimator: bool = False, max_queue: int = 0) -> "Server":
+                   use_estimator: int = 0, max_queue: int = 0) -> "Server":
         """A live server on this dataset (submit / poll / close)."""
         return Server(self, max_batch, n_streams, budget_bytes, use_estimator, max_queue)
 
@@ -505,8 +505,8 @@ class Server:
     answered by continuous batching; poll() reports the completed ones."""
 
     def __init__(self, ds: Dataset, max_batch: int, n_streams: int, budget_bytes: int,
-                 use_estimator: bool, max_queue: int):
-        cfg = ServeConfig(int(budget_bytes), max_batch, n_streams, 1 if use_estimator else 0,
+                 use_estimator: int, max_queue: int):
+        cfg = ServeConfig(int(budget_bytes), max_batch, n_streams, int(use_estimator),
                           int(max_queue))
         h = ctypes.c_void_p()
         _check(load_library().mdrq_serve_open(ds.handle, ctypes.byref(cfg), ctypes.byref(h)))

@@ -193,7 +193,8 @@ def test_full_size_c5_served_sampled():
 
 
 def test_serving_with_estimate_sized_scratch():
-    """Serving with the estimator: requests are admitted by the scratch their estimate
+    """Serving with estimated order and sizing (use_estimator = 3): requests are
+    admitted by the scratch their estimate
     needs (smaller than a bitmap row for small results), so more of them share a scan;
     with the reserve factor forced to 10^-6 most of them outgrow their room and are
     answered again.  Every result equals the oracle's."""
@@ -215,7 +216,7 @@ def test_serving_with_estimate_sized_scratch():
             # a burst: every request waits at once, so batches are bounded by memory
             answers, lat, stats = ds.serve(poisson(len(qs), 100_000_000, seed=3), qs, outs, modes,
                                            max_batch=64, n_streams=2, budget_bytes=8 * row_bytes,
-                                           use_estimator=True)
+                                           use_estimator=3)
             _print("factor", factor, "mean batch", stats["mean_batch"], "sized", stats["sized_by_estimate"],
                    "reruns", stats["overflow_reruns"])
             assert stats["completed"] == len(qs) and stats["sized_by_estimate"] > 0
