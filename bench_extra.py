@@ -421,7 +421,7 @@ def serving(args):
     rates = [float(r) for r in args.rates.split(",")]
     budget = 8 << 30
 
-    def serve(rate, seconds, seed, use_estimator=3):
+    def serve(rate, seconds, seed, use_estimator=3, segments=0):
         n = max(1, int(rate * seconds))
         r = np.random.default_rng(seed)
         arrivals = np.cumsum(r.exponential(1e9 / rate, size=n)).astype(np.uint64)
@@ -430,7 +430,7 @@ def serving(args):
         # output buffers are reused cyclically; only counts are checked here
         outs = [bufs[i % n_buf] for i in range(n)]
         answers, lat, st = ds.serve(arrivals, qs, outs, "auto", max_batch=256, n_streams=2,
-                                    budget_bytes=budget, use_estimator=use_estimator)
+                                    budget_bytes=budget, use_estimator=use_estimator, segments=segments)
         counts = np.array([a.count for a in answers])
         if not np.array_equal(counts, pool_counts[pick]):
             raise RuntimeError("served counts differ from single-query counts")
@@ -451,6 +451,12 @@ def serving(args):
         per_rate[str(int(rate))]["order_only"] = {k: st1[k] for k in keys}
         log(f"rate {rate:.0f} (order only): {st1['qps']:.0f} q/s, p50 {st1['p50_us']:.0f} us, "
             f"p99 {st1['p99_us']:.0f} us")
+        for seg in [int(x) for x in args.segments.split(",") if x]:
+            log(f"rate {rate:.0f}/s: circular scan, {seg} parts per pass")
+            st2 = serve(rate, args.serve_seconds, 100 + i, 0, seg)
+            per_rate[str(int(rate))][f"circular_{seg}"] = {k: st2[k] for k in keys}
+            log(f"rate {rate:.0f} (circular {seg}): {st2['qps']:.0f} q/s, p50 {st2['p50_us']:.0f} us, "
+                f"p99 {st2['p99_us']:.0f} us, {st2['mean_batch']:.1f} active per step")
     top = per_rate[str(int(rates[-1]))]
     line = _line(top["qps"], "queries/s",
                  {"workload": f"c5: {w.n_rows} rows x {w.n_dims} float32 columns resident, Poisson "

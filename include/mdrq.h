@@ -180,7 +180,17 @@ int mdrq_query_noalloc(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r
  * A worker that is idle takes the oldest waiting requests, at most max_batch and as many
  * as its share holds, and answers them with one batched shared scan (as
  * mdrq_query_batch); requests that arrive meanwhile wait for the next idle worker
- * (continuous batching), and the workers' scans overlap on the device. */
+ * (continuous batching), and the workers' scans overlap on the device.
+ * With segments > 0 each worker runs a circular shared scan instead (the shared scan of
+ * section 3.2 kept running over the data, which late arrivals join): the rows are cut
+ * into `segments` parts of whole 4096-row tiles (at most one per tile), and the worker
+ * scans one part per step, in order and wrapping around, for all its active requests.
+ * Between steps it admits waiting requests, oldest first, into free query slots (as many
+ * as its share holds, at most max_batch; each slot is a bitmap row, its chunk marks and
+ * a row of tile counts, whatever the output mode) while the union of their columns fits
+ * one scan; a request is complete, and finished exactly as in a shared scan, once it has
+ * seen every part.  So a request waits at most one step before its scan starts, instead
+ * of a whole scan.  Its results are the same as in the other mode. */
 typedef struct {
   uint64_t result_budget_bytes;
   uint32_t max_batch;       /* 1 .. MDRQ_MAX_BATCH */
@@ -193,6 +203,10 @@ typedef struct {
   uint32_t max_queue;       /* live server: requests allowed to wait; a submission
                                beyond it fails with MDRQ_EBUSY (admission control).
                                0 = unbounded.  The replay ignores it. */
+  uint32_t segments;        /* 0: continuous batching; 1 .. 4096: circular scan with
+                               this many parts per pass (use_estimator bit 1 is then
+                               MDRQ_EINVAL; bit 0 changes nothing: the circular scan
+                               evaluates every predicate of every row) */
 } mdrq_serve_config_t;
 
 /* One request: the query, and its arrival time in ns after the start of the run. */
@@ -207,7 +221,8 @@ typedef struct {
   double wall_s;            /* first arrival to last completion */
   double qps;               /* completed / wall_s */
   double p50_us, p99_us, mean_us, max_us;  /* arrival -> result complete in device memory */
-  double mean_batch;        /* requests per worker batch */
+  double mean_batch;        /* requests per worker batch (circular scan: active
+                               requests per step) */
   double hbm_gbps;          /* column bytes covered by the scans (each union column in
                                full) / wall_s */
   uint64_t overflow_reruns; /* requests answered again by the single-query scan because
@@ -471,10 +486,10 @@ int mdrq_estimator_activations(mdrq_estimator* e, const mdrq_query_t* qs, uint32
 
 /* Keep each output's learned correction only where it helps: on n labelled queries
  * (1 .. MDRQ_EST_MAX_QUERIES; a held-out split, not the training queries) compare, for
- * every output, the squared error on the log scale of the network's estimate and of the
- * base estimate alone (the histogram estimate of a dimension's predicate, or the
- * independence product for the whole query), over the targets present.  An output the
- * network does not improve gets its correction removed (its column of W3 and its entry
+ * every output, the mean squared and the mean absolute error on the log scale of the
+ * network's estimate and of the base estimate alone (the histogram estimate of a
+ * dimension's predicate, or the independence product for the whole query), over the
+ * targets present.  An output whose correction does not lower both gets its correction removed (its column of W3 and its entry
  * of b3 set to zero, with their Adam moments), so it returns the base estimate from then
  * on.  kept (optional, n_dims + 1 entries) receives 1 for each output kept, 0 for each
  * removed.  Errors: as mdrq_estimator_gradient. */

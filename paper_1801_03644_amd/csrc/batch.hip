@@ -51,7 +51,12 @@ struct TabPred {
   uint32_t slot, klo, kw, pad;
 };
 
-// Workgroups stride over 4096-row tiles; within a tile, each wave takes chunks of
+// Row of tile_counts that query q of the batch writes.
+__device__ __forceinline__ uint64_t count_row(const BatchParams& bp, uint32_t q) {
+  return bp.count_row ? bp.count_row[q] : q;
+}
+
+// Workgroups stride over the 4096-row tiles of [tile_begin, tile_end); within a tile, each wave takes chunks of
 // 64*RG rows (lane l holds rows 64g + l, g < RG).  For each chunk every query of the
 // workgroup's group is evaluated; non-zero wave masks are stored as bitmap words
 // (the scratch was zeroed), and the chunk's count is added to the query's tile
@@ -81,7 +86,7 @@ __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
   const uint32_t wave = threadIdx.x / 64;
   constexpr uint32_t kChunkRows = 64 * RG;
   constexpr uint32_t kChunksPerWave = 4096 / kChunkRows / W;
-  for (uint64_t tile = blockIdx.x; tile < bp.n_tiles; tile += gridDim.x) {
+  for (uint64_t tile = bp.tile_begin + blockIdx.x; tile < bp.tile_end; tile += gridDim.x) {
 #pragma unroll 1
     for (uint32_t cw = 0; cw < kChunksPerWave; ++cw) {
       const uint64_t row0 = tile * 4096 + (wave * kChunksPerWave + cw) * kChunkRows;
@@ -185,7 +190,7 @@ __global__ void __launch_bounds__(W * 64) batch_scan_kernel(BatchParams bp) {
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nq; i += W * 64) {
-      bp.tile_counts[static_cast<uint64_t>(q_beg + i) * bp.n_tiles + tile] = s_cnt[i];
+      bp.tile_counts[count_row(bp, q_beg + i) * bp.n_tiles + tile] = s_cnt[i];
       s_cnt[i] = 0;
     }
     __syncthreads();
@@ -253,7 +258,7 @@ __global__ void __launch_bounds__(W * 64) batch_reg_kernel(BatchParams bp) {
   const uint32_t ns = bp.n_slots;
   constexpr uint32_t kChunkRows = 64 * RG;
   constexpr uint32_t kChunksPerWave = 4096 / kChunkRows / W;
-  for (uint64_t tile = blockIdx.x; tile < bp.n_tiles; tile += gridDim.x) {
+  for (uint64_t tile = bp.tile_begin + blockIdx.x; tile < bp.tile_end; tile += gridDim.x) {
 #pragma unroll 1
     for (uint32_t cw = 0; cw < kChunksPerWave; ++cw) {
       const uint64_t row0 = tile * 4096 + (wave * kChunksPerWave + cw) * kChunkRows;
@@ -358,7 +363,7 @@ __global__ void __launch_bounds__(W * 64) batch_reg_kernel(BatchParams bp) {
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nq; i += W * 64) {
-      bp.tile_counts[static_cast<uint64_t>(q_beg + i) * bp.n_tiles + tile] = s_cnt[i];
+      bp.tile_counts[count_row(bp, q_beg + i) * bp.n_tiles + tile] = s_cnt[i];
       s_cnt[i] = 0;
     }
     __syncthreads();
@@ -492,7 +497,7 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
   }
   constexpr uint32_t kChunkRows = 64 * RG;
   constexpr uint32_t kChunksPerWave = 4096 / kChunkRows / W;
-  for (uint64_t tile = blockIdx.x; tile < bp.n_tiles; tile += gridDim.x) {
+  for (uint64_t tile = bp.tile_begin + blockIdx.x; tile < bp.tile_end; tile += gridDim.x) {
 #pragma unroll 1
     for (uint32_t cw = 0; cw < kChunksPerWave; ++cw) {
       const uint64_t row0 = tile * 4096 + (wave * kChunksPerWave + cw) * kChunkRows;
@@ -652,7 +657,7 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nq; i += W * 64) {
-      bp.tile_counts[static_cast<uint64_t>(q_beg + i) * bp.n_tiles + tile] = s_cnt[i];
+      bp.tile_counts[count_row(bp, q_beg + i) * bp.n_tiles + tile] = s_cnt[i];
       s_cnt[i] = 0;
     }
     __syncthreads();
@@ -718,7 +723,7 @@ __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
 
   constexpr uint32_t kChunkRows = 64 * RG;
   constexpr uint32_t kChunksPerWave = 4096 / kChunkRows / W;
-  for (uint64_t tile = blockIdx.x; tile < bp.n_tiles; tile += gridDim.x) {
+  for (uint64_t tile = bp.tile_begin + blockIdx.x; tile < bp.tile_end; tile += gridDim.x) {
 #pragma unroll 1
     for (uint32_t cw = 0; cw < kChunksPerWave; ++cw) {
       const uint64_t row0 = tile * 4096 + (wave * kChunksPerWave + cw) * kChunkRows;
@@ -849,7 +854,7 @@ __global__ void __launch_bounds__(W * 64) batch_lds_kernel(BatchParams bp) {
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nq; i += W * 64) {
-      bp.tile_counts[static_cast<uint64_t>(q_beg + i) * bp.n_tiles + tile] = s_cnt[i];
+      bp.tile_counts[count_row(bp, q_beg + i) * bp.n_tiles + tile] = s_cnt[i];
       s_cnt[i] = 0;
     }
     __syncthreads();
@@ -861,6 +866,13 @@ __global__ void __launch_bounds__(256) zero_words_kernel(uint64_t* w, uint64_t n
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 256;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride)
     w[i] = 0;
+}
+
+// Zero rows rows[y] of row_words 64-bit words each (workgroup row y of the grid).
+__global__ void __launch_bounds__(256) zero_rows_kernel(uint64_t* base, uint64_t row_words, const uint32_t* rows) {
+  uint64_t* w = base + static_cast<uint64_t>(rows[blockIdx.y]) * row_words;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 256;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x; i < row_words; i += stride) w[i] = 0;
 }
 
 // ---------------------------------------------------------------- per-query finish
@@ -900,7 +912,7 @@ __global__ void __launch_bounds__(kFinThreads) batch_count_kernel(BatchFinish f)
   const uint32_t q = blockIdx.x;
   const BatchOut o = f.outs[q];
   const uint32_t tid = threadIdx.x;
-  uint32_t* counts = f.tile_counts + static_cast<uint64_t>(q) * f.n_tiles;
+  uint32_t* counts = f.tile_counts + static_cast<uint64_t>(f.count_row ? f.count_row[q] : q) * f.n_tiles;
   uint64_t part = 0;
   for (uint64_t t = tid; t < f.n_tiles; t += kFinThreads) part += counts[t];
   uint32_t ignore;
@@ -1010,7 +1022,7 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
   // The tiles' output positions (and the end of the last) into LDS in one pass.
   __shared__ uint32_t s_pos[kEmitTiles + 1];
   __shared__ uint16_t s_stage[kFinWaves][kEmitStage];
-  const uint32_t* offs = f.tile_counts + static_cast<uint64_t>(q) * f.n_tiles;
+  const uint32_t* offs = f.tile_counts + static_cast<uint64_t>(f.count_row ? f.count_row[q] : q) * f.n_tiles;
   for (uint64_t i = tid; i <= t_end - t_beg; i += kFinThreads) {
     const uint64_t t = t_beg + i;
     s_pos[i] = t < f.n_tiles ? offs[t] : static_cast<uint32_t>(count);
@@ -1205,6 +1217,14 @@ hipError_t launch_zero_words(uint64_t* w, uint64_t n, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
   zero_words_kernel<<<static_cast<uint32_t>(blocks), 256, 0, stream>>>(w, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_rows(uint64_t* base, uint64_t row_words, const uint32_t* rows, uint32_t n_rows,
+                            hipStream_t stream) {
+  if (n_rows == 0 || row_words == 0) return hipSuccess;
+  const uint64_t blocks = std::min<uint64_t>((row_words + 255) / 256, 256);
+  zero_rows_kernel<<<dim3(static_cast<uint32_t>(blocks), n_rows), 256, 0, stream>>>(base, row_words, rows);
   return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <memory>
 
 #include "mdrq_internal.h"
 #include "rank_buckets.h"
@@ -152,34 +153,12 @@ hipError_t launch_shared_graph(BatchWorkspace& ws, const BatchParams& bp, const 
 // Run one shared scan over `items` (union of at most kMaxUnion columns; unions of more
 // than kMaxSlots columns take the LDS variant).
 // ms_out receives the device time of the scan and finish launches.
-int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
-               const BatchConfig& cfg_in, hipStream_t stream, float* ms_out, BatchRunStats* st = nullptr,
-               std::vector<uint32_t>* redo = nullptr) {
-  const uint64_t nq = items.size();
-  // Scratch sized by estimate: pool slots per query (0: a full bitmap row).  Any such
-  // query makes the scan a rank-variant scan of 512-row chunks, the layout the serving
-  // loop's admission reserves for.
-  std::vector<uint64_t> cap_of(nq, 0);
-  bool any_sparse = false;
-  for (uint64_t q = 0; q < nq; ++q)
-    if (items[q].kind != kBatchCount && items[q].est_rows >= 0.0) {
-      cap_of[q] = sparse_slots(ds, items[q].est_rows, kSparseChunkRows);
-      any_sparse |= cap_of[q] > 0;
-    }
-  BatchConfig cfg = cfg_in;
-  if (any_sparse) {
-    cfg.lds = 4;
-    cfg.rows_per_lane = 8;
-  }
-  const uint64_t n_rows = ds->n_rows;
-  const uint64_t nw = n_words(ds);
-  const uint64_t n_tiles = (n_rows + kTileRows - 1) / kTileRows;
-
-  // Union of the queried columns -> register slots, numbered by the columns' mean
-  // relative position in the queries' evaluation orders (given or estimated), so that
-  // a walk over the slots in order follows those orders as closely as one order can.
-  std::vector<int> slot_of(ds->n_dims, -1);
+// Union of the items' queried columns in register-slot order: numbered by the columns'
+// mean relative position in the queries' evaluation orders (given or estimated), so that
+// a walk over the slots in order follows those orders as closely as one order can.
+std::vector<uint32_t> union_columns(const mdrq_dataset* ds, const std::vector<Item>& items) {
   std::vector<uint32_t> slot_dim;
+  std::vector<bool> seen(ds->n_dims, false);
   std::vector<double> pos_sum(ds->n_dims, 0.0);
   std::vector<uint32_t> uses(ds->n_dims, 0);
   for (const Item& it : items) {
@@ -188,8 +167,8 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
       const uint32_t d = it.plan.dims[i];
       pos_sum[d] += (i + 0.5) / static_cast<double>(k);
       uses[d] += 1;
-      if (slot_of[d] < 0) {
-        slot_of[d] = 0;
+      if (!seen[d]) {
+        seen[d] = true;
         slot_dim.push_back(d);
       }
     }
@@ -197,116 +176,43 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   std::stable_sort(slot_dim.begin(), slot_dim.end(), [&](uint32_t a, uint32_t b) {
     return pos_sum[a] / uses[a] < pos_sum[b] / uses[b];
   });
-  // The slot-mask, rank and LDS variants give a query without predicates an always-true
-  // one on slot 0 (it rejects only the rows past the end), so the union has at least one
-  // column.
-  if ((cfg.lds == 1 || cfg.lds == 3 || cfg.lds == 4) && slot_dim.empty()) slot_dim.push_back(0);
-  for (size_t i = 0; i < slot_dim.size(); ++i) slot_of[slot_dim[i]] = static_cast<int>(i);
-  const int n_slots = static_cast<int>(slot_dim.size());
+  return slot_dim;
+}
 
-  // Rank variant: queries per group (32 x sw) such that the tables of any group fit LDS.
-  // A group's LDS words: its per-query counts and headers (4-word aligned), 4 header
-  // words per slot and each slot's tables.  Tables with up to kRankBuckets buckets are
-  // only built when the whole group stays within kRankLdsWords, else at most 256
-  // buckets, whose size slot_table_words_bound caps for any 2 S interval ends.
-  const size_t lds_room = device().lds > 4096 ? device().lds - 4096 : 0;
-  auto rank_words = [&](uint64_t S) {
-    const uint32_t sw = S <= 32 ? 1 : S <= 64 ? 2 : 4;
-    const uint64_t bound = 2 * align4(S) + 4 * static_cast<uint64_t>(n_slots) +
-                           static_cast<uint64_t>(n_slots) *
-                               slot_table_words_bound(static_cast<uint32_t>(2 * S), 256, sw);
-    return std::max<uint64_t>(bound, kRankLdsWords);
-  };
-  uint64_t rank_group = std::min<uint64_t>(128, cfg.group ? cfg.group : nq);
-  while (rank_group > 32 && rank_words(rank_group) * 4 > lds_room) rank_group /= 2;
-  const bool rank = cfg.lds == 4 && rank_words(rank_group) * 4 <= lds_room;
-  const int rank_sw = rank_group <= 32 ? 1 : rank_group <= 64 ? 2 : 4;
-  const bool use_lds = !rank && (cfg.lds == 1 || n_slots > kMaxSlots);
-  const bool walk = cfg.lds == 2 && !use_lds;
-  const bool reg = cfg.lds == 3 && !use_lds;
-  int variant = rank ? 4 : use_lds ? 1 : walk ? 2 : reg ? 3 : 0;
-  // Queries per group: what the configuration asks for, and no more than fits LDS.
-  uint64_t group = cfg.group ? cfg.group : nq;
-  std::vector<uint32_t> group_first, group_table, table;
-  std::vector<BatchOut> outs(nq);
-  uint32_t n_out = 0, n_sparse = 0;
-  if (rank && any_sparse) variant = 5;   // the rank kernel with sparse scratch (512-row chunks)
-  std::vector<uint32_t> sparse_base, sparse_cap;
-  uint64_t pool_slots = 0;
-  for (uint64_t q = 0; q < nq; ++q) {
-    outs[q].kind = items[q].kind;
-    outs[q].sparse = 0;
-    if (items[q].kind == kBatchCount) {
-      outs[q].out_index = 0;
-    } else if (rank && cap_of[q] > 0) {
-      outs[q].sparse = 1;
-      outs[q].out_index = n_sparse++;
-      sparse_base.push_back(static_cast<uint32_t>(pool_slots));
-      sparse_cap.push_back(static_cast<uint32_t>(cap_of[q]));
-      pool_slots += cap_of[q];
-    } else {
-      outs[q].out_index = n_out++;
-    }
-  }
-  // Slot-mask variant: fixed-size records (header, slot mask, then key(lo), key(hi)
-  // for every register slot), read by scalar loads, so a group is not limited by LDS.
-  const uint32_t reg_slots = static_cast<uint32_t>(batch_reg_slots(std::max(1, n_slots)));
-  for (uint64_t q0 = 0; reg && q0 < nq;) {
-    const uint64_t q1 = std::min<uint64_t>(nq, q0 + std::min<uint64_t>(group, kMaxRegGroup));
-    group_first.push_back(static_cast<uint32_t>(q0));
-    group_table.push_back(static_cast<uint32_t>(table.size()));
-    for (uint64_t q = q0; q < q1; ++q) {
-      const Plan& pl = items[q].plan;
-      const uint64_t base = table.size();
-      table.resize(base + 2 + 2 * reg_slots, 0u);
-      table[base] = static_cast<uint32_t>(pl.preds.size()) | (outs[q].kind << 8) |
-                    (outs[q].out_index << 16);
-      if (pl.preds.empty()) {
-        table[base + 1] = 1u;
-        table[base + 2] = batch_key(-std::numeric_limits<float>::infinity());
-        table[base + 3] = batch_key(std::numeric_limits<float>::infinity());
-      }
-      for (size_t i = 0; i < pl.preds.size(); ++i) {
-        const uint32_t s = static_cast<uint32_t>(slot_of[pl.dims[i]]);
-        table[base + 1] |= 1u << s;
-        table[base + 2 + 2 * s] = batch_key(pl.preds[i].lo);
-        table[base + 3 + 2 * s] = batch_key(pl.preds[i].hi);
-      }
-      // Early-break tests, placed by the estimated chance that the whole chunk is
-      // rejected: with s the product of the selectivities so far (slot order), a chunk
-      // of R rows survives with probability about 1 - exp(-R s).  A test (five vector
-      // instructions) follows a predicate when that chance has grown by a third since
-      // the last test and predicates remain; none follows the last one.
-      std::vector<float> s_of(reg_slots, 1.0f);
-      for (size_t i = 0; i < pl.preds.size(); ++i)
-        s_of[slot_of[pl.dims[i]]] = items[q].sel[i];
-      const double chunk_rows = 64.0 * cfg.rows_per_lane;
-      double cum = 1.0, p_tested = 0.0;
-      uint32_t seen = 0;
-      for (uint32_t s = 0; s < reg_slots; ++s)
-        if ((table[base + 1] >> s) & 1u) {
-          ++seen;
-          cum *= std::max(0.0f, std::min(1.0f, s_of[s]));
-          const double p_dead = std::exp(-chunk_rows * cum);
-          if (seen < pl.preds.size() && p_dead - p_tested > 1.0 / 3.0) {
-            table[base + 1] |= 0x10000u << s;
-            p_tested = p_dead;
-          }
-        }
-    }
-    q0 = q1;
-  }
-  // Rank variant: per group, per query (kind | sparse << 2 | output row << 8), per slot
-  // a header (offset of the ends; M | d << 12 | log2(nb) << 16 | shift << 24 | by value
-  // << 31; kmin or vlo; scale), then per slot the tables of append_slot_tables (offsets
-  // relative to the group's start, 4-word aligned).  The bucket words hold the range of
-  // each bucket's ends, and no bucket holds more than 2^d - 1 ends (M <= 2 x 128 fits
-  // the header's 12 bits and the bucket words' 16).
-  // The groups' tables are independent: each is built into its own vector, on several
-  // host threads when there are 24 or more slot tables (about 10 us each), then
-  // appended in group order.
+// LDS words that bound the rank tables of a group of S queries over n_slots columns:
+// its per-query counts and headers (4-word aligned), 4 header words per slot and each
+// slot's tables.  Tables with up to kRankBuckets buckets are only built when the whole
+// group stays within kRankLdsWords, else at most 256 buckets, whose size
+// slot_table_words_bound caps for any 2 S interval ends.
+uint64_t rank_group_words(uint64_t S, int n_slots) {
+  const uint32_t sw = S <= 32 ? 1 : S <= 64 ? 2 : 4;
+  const uint64_t bound = 2 * align4(S) + 4 * static_cast<uint64_t>(n_slots) +
+                         static_cast<uint64_t>(n_slots) *
+                             slot_table_words_bound(static_cast<uint32_t>(2 * S), 256, sw);
+  return std::max<uint64_t>(bound, kRankLdsWords);
+}
+
+// Dynamic LDS a rank group may use (the rest is the kernel's own).
+size_t rank_lds_room() { return device().lds > 4096 ? device().lds - 4096 : 0; }
+
+// Rank-variant tables of the items, in groups of rank_group consecutive queries: per
+// group, per query (kind | sparse << 2 | output row << 8), per slot a header (offset of
+// the ends; M | d << 12 | log2(nb) << 16 | shift << 24 | by value << 31; kmin or vlo;
+// scale), then per slot the tables of append_slot_tables (offsets relative to the
+// group's start, 4-word aligned).  The bucket words hold the range of each bucket's
+// ends, and no bucket holds more than 2^d - 1 ends (M <= 2 x 128 fits the header's 12
+// bits and the bucket words' 16).  Appends to table, group_first and group_table;
+// pairs_out: the (group, column) pairs with a predicate.
+// The groups' tables are independent: each is built into its own vector, on several
+// host threads when there are 24 or more slot tables (about 10 us each), then appended
+// in group order.
+int build_rank_tables(const mdrq_dataset* ds, const std::vector<Item>& items, const std::vector<BatchOut>& outs,
+                      const std::vector<int>& slot_of, int n_slots, uint64_t rank_group, int rank_sw,
+                      std::vector<uint32_t>& table, std::vector<uint32_t>& group_first,
+                      std::vector<uint32_t>& group_table, uint64_t* pairs_out) {
+  const uint64_t nq = items.size();
   std::vector<uint64_t> rank_q0;
-  for (uint64_t q0 = 0; rank && q0 < nq; q0 += rank_group) rank_q0.push_back(q0);
+  for (uint64_t q0 = 0; q0 < nq; q0 += rank_group) rank_q0.push_back(q0);
   std::vector<std::vector<uint32_t>> rank_tables(rank_q0.size());
   std::atomic<uint64_t> used_pairs{0};   // (group, column) pairs with a predicate
   auto build_rank_group = [&](size_t gi) {
@@ -399,10 +305,137 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     for (std::thread& th : pool) th.join();
     if (failed) return fail(MDRQ_ENOMEM, "shared scan: host memory for the rank tables");
   }
+  if (pairs_out) *pairs_out = used_pairs.load();
   for (size_t gi = 0; gi < rank_q0.size(); ++gi) {
     group_first.push_back(static_cast<uint32_t>(rank_q0[gi]));
     group_table.push_back(static_cast<uint32_t>(table.size()));
     table.insert(table.end(), rank_tables[gi].begin(), rank_tables[gi].end());
+  }
+  return MDRQ_OK;
+}
+
+int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
+               const BatchConfig& cfg_in, hipStream_t stream, float* ms_out, BatchRunStats* st = nullptr,
+               std::vector<uint32_t>* redo = nullptr) {
+  const uint64_t nq = items.size();
+  // Scratch sized by estimate: pool slots per query (0: a full bitmap row).  Any such
+  // query makes the scan a rank-variant scan of 512-row chunks, the layout the serving
+  // loop's admission reserves for.
+  std::vector<uint64_t> cap_of(nq, 0);
+  bool any_sparse = false;
+  for (uint64_t q = 0; q < nq; ++q)
+    if (items[q].kind != kBatchCount && items[q].est_rows >= 0.0) {
+      cap_of[q] = sparse_slots(ds, items[q].est_rows, kSparseChunkRows);
+      any_sparse |= cap_of[q] > 0;
+    }
+  BatchConfig cfg = cfg_in;
+  if (any_sparse) {
+    cfg.lds = 4;
+    cfg.rows_per_lane = 8;
+  }
+  const uint64_t n_rows = ds->n_rows;
+  const uint64_t nw = n_words(ds);
+  const uint64_t n_tiles = (n_rows + kTileRows - 1) / kTileRows;
+
+  std::vector<uint32_t> slot_dim = union_columns(ds, items);
+  // The slot-mask, rank and LDS variants give a query without predicates an always-true
+  // one on slot 0 (it rejects only the rows past the end), so the union has at least one
+  // column.
+  if ((cfg.lds == 1 || cfg.lds == 3 || cfg.lds == 4) && slot_dim.empty()) slot_dim.push_back(0);
+  std::vector<int> slot_of(ds->n_dims, -1);
+  for (size_t i = 0; i < slot_dim.size(); ++i) slot_of[slot_dim[i]] = static_cast<int>(i);
+  const int n_slots = static_cast<int>(slot_dim.size());
+
+  // Rank variant: queries per group (32 x sw) such that the tables of any group fit LDS.
+  const size_t lds_room = rank_lds_room();
+  auto rank_words = [&](uint64_t S) { return rank_group_words(S, n_slots); };
+  uint64_t rank_group = std::min<uint64_t>(128, cfg.group ? cfg.group : nq);
+  while (rank_group > 32 && rank_words(rank_group) * 4 > lds_room) rank_group /= 2;
+  const bool rank = cfg.lds == 4 && rank_words(rank_group) * 4 <= lds_room;
+  const int rank_sw = rank_group <= 32 ? 1 : rank_group <= 64 ? 2 : 4;
+  const bool use_lds = !rank && (cfg.lds == 1 || n_slots > kMaxSlots);
+  const bool walk = cfg.lds == 2 && !use_lds;
+  const bool reg = cfg.lds == 3 && !use_lds;
+  int variant = rank ? 4 : use_lds ? 1 : walk ? 2 : reg ? 3 : 0;
+  // Queries per group: what the configuration asks for, and no more than fits LDS.
+  uint64_t group = cfg.group ? cfg.group : nq;
+  std::vector<uint32_t> group_first, group_table, table;
+  std::vector<BatchOut> outs(nq);
+  uint32_t n_out = 0, n_sparse = 0;
+  if (rank && any_sparse) variant = 5;   // the rank kernel with sparse scratch (512-row chunks)
+  std::vector<uint32_t> sparse_base, sparse_cap;
+  uint64_t pool_slots = 0;
+  for (uint64_t q = 0; q < nq; ++q) {
+    outs[q].kind = items[q].kind;
+    outs[q].sparse = 0;
+    if (items[q].kind == kBatchCount) {
+      outs[q].out_index = 0;
+    } else if (rank && cap_of[q] > 0) {
+      outs[q].sparse = 1;
+      outs[q].out_index = n_sparse++;
+      sparse_base.push_back(static_cast<uint32_t>(pool_slots));
+      sparse_cap.push_back(static_cast<uint32_t>(cap_of[q]));
+      pool_slots += cap_of[q];
+    } else {
+      outs[q].out_index = n_out++;
+    }
+  }
+  // Slot-mask variant: fixed-size records (header, slot mask, then key(lo), key(hi)
+  // for every register slot), read by scalar loads, so a group is not limited by LDS.
+  const uint32_t reg_slots = static_cast<uint32_t>(batch_reg_slots(std::max(1, n_slots)));
+  for (uint64_t q0 = 0; reg && q0 < nq;) {
+    const uint64_t q1 = std::min<uint64_t>(nq, q0 + std::min<uint64_t>(group, kMaxRegGroup));
+    group_first.push_back(static_cast<uint32_t>(q0));
+    group_table.push_back(static_cast<uint32_t>(table.size()));
+    for (uint64_t q = q0; q < q1; ++q) {
+      const Plan& pl = items[q].plan;
+      const uint64_t base = table.size();
+      table.resize(base + 2 + 2 * reg_slots, 0u);
+      table[base] = static_cast<uint32_t>(pl.preds.size()) | (outs[q].kind << 8) |
+                    (outs[q].out_index << 16);
+      if (pl.preds.empty()) {
+        table[base + 1] = 1u;
+        table[base + 2] = batch_key(-std::numeric_limits<float>::infinity());
+        table[base + 3] = batch_key(std::numeric_limits<float>::infinity());
+      }
+      for (size_t i = 0; i < pl.preds.size(); ++i) {
+        const uint32_t s = static_cast<uint32_t>(slot_of[pl.dims[i]]);
+        table[base + 1] |= 1u << s;
+        table[base + 2 + 2 * s] = batch_key(pl.preds[i].lo);
+        table[base + 3 + 2 * s] = batch_key(pl.preds[i].hi);
+      }
+      // Early-break tests, placed by the estimated chance that the whole chunk is
+      // rejected: with s the product of the selectivities so far (slot order), a chunk
+      // of R rows survives with probability about 1 - exp(-R s).  A test (five vector
+      // instructions) follows a predicate when that chance has grown by a third since
+      // the last test and predicates remain; none follows the last one.
+      std::vector<float> s_of(reg_slots, 1.0f);
+      for (size_t i = 0; i < pl.preds.size(); ++i)
+        s_of[slot_of[pl.dims[i]]] = items[q].sel[i];
+      const double chunk_rows = 64.0 * cfg.rows_per_lane;
+      double cum = 1.0, p_tested = 0.0;
+      uint32_t seen = 0;
+      for (uint32_t s = 0; s < reg_slots; ++s)
+        if ((table[base + 1] >> s) & 1u) {
+          ++seen;
+          cum *= std::max(0.0f, std::min(1.0f, s_of[s]));
+          const double p_dead = std::exp(-chunk_rows * cum);
+          if (seen < pl.preds.size() && p_dead - p_tested > 1.0 / 3.0) {
+            table[base + 1] |= 0x10000u << s;
+            p_tested = p_dead;
+          }
+        }
+    }
+    q0 = q1;
+  }
+  // Rank variant: the groups' tables (build_rank_tables).
+  uint64_t used_pairs = 0;
+  if (rank) {
+    uint64_t pairs = 0;
+    const int rc_tables = build_rank_tables(ds, items, outs, slot_of, n_slots, rank_group, rank_sw, table, group_first,
+                                  group_table, &pairs);
+    if (rc_tables) return rc_tables;
+    used_pairs = pairs;
   }
   // Group table: record offsets (padded to 4 words), then per query a 4-word header
   // and one 4-word entry (slot, key(lo), key(hi) - key(lo) or, for the LDS variant,
@@ -526,6 +559,9 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   BatchParams bp{};
   bp.n_rows = n_rows;
   bp.n_tiles = n_tiles;
+  bp.tile_begin = 0;
+  bp.tile_end = n_tiles;
+  bp.count_row = nullptr;
   bp.n_words = nw;
   bp.n_slots = static_cast<uint32_t>(n_slots);
   bp.table = db;
@@ -548,6 +584,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   fin.n_chunks = 0;
   fin.chunk_shift = 0;
   fin.tile_counts = ws.d_tile_counts;
+  fin.count_row = nullptr;
   fin.outs = reinterpret_cast<const BatchOut*>(static_cast<const uint8_t*>(ws.d_blob) + outs_off);
   fin.counts_out = static_cast<uint64_t*>(ws.h_res_dev);
   fin.kind_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws.h_res_dev) + nq * 8);
@@ -643,7 +680,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
     // Work of the scan: rows looked up per (group, column) in the rank variant, column
     // bytes read (each group reads its own columns in the rank variant).
     std::lock_guard<std::mutex> lock(ds->stat_mu);
-    const uint64_t pairs = rank ? used_pairs.load() : static_cast<uint64_t>(n_slots);
+    const uint64_t pairs = rank ? used_pairs : static_cast<uint64_t>(n_slots);
     ds->batch_lookups += rank ? n_rows * pairs : 0;
     ds->batch_column_bytes += 4 * n_rows * pairs;
     ds->batch_scan_ms += scan_ms;
@@ -1138,6 +1175,335 @@ void free_batch(BatchWorkspace& ws) {
   if (ws.ev2) (void)hipEventDestroy(ws.ev2);
   for (BatchWorkspace::Graph& g : ws.graphs) destroy_graph(g);
   ws = BatchWorkspace{};
+}
+
+
+// ---------------------------------------------------------------- circular scan
+
+namespace {
+constexpr int kCircRg = 8;                          // rows per lane: 512-row chunks
+constexpr uint64_t kCircChunkRows = 64 * kCircRg;
+}  // namespace
+
+struct CircularScan {
+  mdrq_dataset* ds = nullptr;
+  BatchWorkspace ws;
+  uint32_t n_slots = 0;              // query slots
+  uint32_t max_union = 0;            // widest union of columns a step may scan
+  uint64_t n_tiles = 0, seg_tiles = 0, n_segs = 0;
+  uint64_t marks_stride = 0;         // marks per slot: the row's chunks, 4-aligned
+  uint64_t cur = 0;                  // segment of the next step
+  // Active queries, in admission order, and per query its slot, the steps it still
+  // needs, whether its marks still have to be cleared, and the caller's tag.
+  std::vector<Item> items;
+  struct Meta {
+    uint32_t slot;
+    uint64_t left;
+    bool fresh;
+    void* tag;
+  };
+  std::vector<Meta> meta;
+  std::vector<uint32_t> free_slots;
+  std::vector<uint32_t> dim_uses;    // per dimension: active queries restricting it
+  uint32_t union_size = 0;
+};
+
+uint64_t circular_slot_bytes(const mdrq_dataset* ds) {
+  const uint64_t n_chunks = (ds->n_rows + kCircChunkRows - 1) / kCircChunkRows;
+  const uint64_t n_tiles = (ds->n_rows + kTileRows - 1) / kTileRows;
+  return n_words(ds) * 8 + align4(n_chunks) * 2 + n_tiles * 4;
+}
+
+int circular_create(mdrq_dataset* ds, uint32_t slots, uint32_t segments, CircularScan** out) {
+  *out = nullptr;
+  if (slots == 0 || segments == 0) return fail(MDRQ_EINVAL, "circular scan: no slots or no segments");
+  std::unique_ptr<CircularScan> c(new CircularScan());
+  c->ds = ds;
+  c->n_slots = slots;
+  c->n_tiles = (ds->n_rows + kTileRows - 1) / kTileRows;
+  const uint64_t segs = std::max<uint64_t>(1, std::min<uint64_t>(segments, c->n_tiles));
+  c->seg_tiles = std::max<uint64_t>(1, (c->n_tiles + segs - 1) / segs);
+  c->n_segs = c->n_tiles ? (c->n_tiles + c->seg_tiles - 1) / c->seg_tiles : 1;
+  const uint64_t n_chunks = (ds->n_rows + kCircChunkRows - 1) / kCircChunkRows;
+  c->marks_stride = align4(n_chunks);
+  // The widest union whose smallest rank group (32 queries) fits LDS.
+  uint32_t mu = 0;
+  while (mu < static_cast<uint32_t>(kMaxUnion) && rank_group_words(32, static_cast<int>(mu) + 1) * 4 <= rank_lds_room())
+    ++mu;
+  if (mu == 0) return fail(MDRQ_ENOTSUP, "circular scan: no rank group fits LDS");
+  c->max_union = mu;
+  c->dim_uses.assign(ds->n_dims, 0);
+  for (uint32_t i = slots; i-- > 0;) c->free_slots.push_back(i);
+  const uint64_t nw = n_words(ds);
+  BatchWorkspace& ws = c->ws;
+  int rc = grow_device(&ws.d_words, &ws.d_words_len, slots * nw + slots * c->marks_stride / 4 + 1,
+                       "circular scan rows");
+  if (rc) return rc;
+  rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, slots * std::max<uint64_t>(1, c->n_tiles),
+                   "circular scan tile counts");
+  if (rc) return rc;
+  rc = grow_results(ws, slots);
+  if (rc) return rc;
+  // Query tables of all groups (at most one per 32 slots), the per-query arrays and two
+  // sets of output records.
+  const uint64_t groups = (slots + 31) / 32;
+  const uint64_t blob = groups * rank_group_words(128, static_cast<int>(mu)) * 4 + slots * (16 + 2 * sizeof(BatchOut)) +
+                        (2 * groups + 16) * 4 + 64;
+  rc = grow_pinned(&ws.h_blob, &ws.h_blob_bytes, blob);
+  if (rc) return rc;
+  rc = grow_device(reinterpret_cast<uint8_t**>(&ws.d_blob), &ws.d_blob_bytes, blob, "circular scan table");
+  if (rc) return rc;
+  MDRQ_HIP(hipEventCreate(&ws.ev0), "hipEventCreate");
+  MDRQ_HIP(hipEventCreate(&ws.ev1), "hipEventCreate");
+  *out = c.release();
+  return MDRQ_OK;
+}
+
+void circular_destroy(CircularScan* c) {
+  if (!c) return;
+  free_batch(c->ws);
+  delete c;
+}
+
+uint32_t circular_free_slots(const CircularScan* c) { return static_cast<uint32_t>(c->free_slots.size()); }
+uint32_t circular_active(const CircularScan* c) { return static_cast<uint32_t>(c->items.size()); }
+
+int circular_admit(CircularScan* c, const mdrq_query_t* q, mdrq_result_t* r, void* tag, hipStream_t stream,
+                   bool* answered) {
+  *answered = false;
+  mdrq_dataset* ds = c->ds;
+  // The rank scan has no early break: the evaluation order does not matter.
+  Plan plan = make_plan(ds, q, r);
+  const bool no_scan = plan.empty || ds->n_rows == 0;
+  if (no_scan || plan.preds.size() > c->max_union) {
+    if (r->mode == MDRQ_OUT_AUTO) {
+      plan.mode = kIds;
+      r->mode = MDRQ_OUT_IDS;
+    }
+    const int rc = no_scan ? finish_empty(ds, plan, r, stream) : run_query(ds, plan, r, stream);
+    if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
+    *answered = true;
+    return MDRQ_OK;
+  }
+  uint32_t added = 0;
+  for (uint32_t d : plan.dims) added += c->dim_uses[d] == 0 ? 1 : 0;
+  if (c->free_slots.empty() || c->union_size + std::max<uint32_t>(added, c->union_size ? 0 : 1) > c->max_union)
+    return MDRQ_EBUSY;
+  for (uint32_t d : plan.dims) c->dim_uses[d] += 1;
+  c->union_size += added;
+  const uint32_t slot = c->free_slots.back();
+  c->free_slots.pop_back();
+  c->items.push_back(Item{0, std::move(plan), kind_of(r->mode), r, {}});
+  c->meta.push_back(CircularScan::Meta{slot, c->n_segs, true, tag});
+  return MDRQ_OK;
+}
+
+namespace {
+// Drop the active query at position i: its slot is free again.
+void circular_drop(CircularScan* c, size_t i) {
+  for (uint32_t d : c->items[i].plan.dims)
+    if (--c->dim_uses[d] == 0) c->union_size -= 1;
+  c->free_slots.push_back(c->meta[i].slot);
+  c->items.erase(c->items.begin() + static_cast<std::ptrdiff_t>(i));
+  c->meta.erase(c->meta.begin() + static_cast<std::ptrdiff_t>(i));
+}
+
+int circular_step_inner(CircularScan* c, hipStream_t stream, std::vector<void*>& done, BatchRunStats* st) {
+  mdrq_dataset* ds = c->ds;
+  BatchWorkspace& ws = c->ws;
+  const uint64_t nq = c->items.size();
+  const uint64_t nw = n_words(ds);
+  const uint64_t t0 = c->cur * c->seg_tiles;
+  const uint64_t t1 = std::min<uint64_t>(c->n_tiles, t0 + c->seg_tiles);
+
+  std::vector<uint32_t> slot_dim = union_columns(ds, c->items);
+  if (slot_dim.empty()) slot_dim.push_back(0);   // only queries without predicates
+  std::vector<int> slot_of(ds->n_dims, -1);
+  for (size_t i = 0; i < slot_dim.size(); ++i) slot_of[slot_dim[i]] = static_cast<int>(i);
+  const int n_cols = static_cast<int>(slot_dim.size());
+  uint64_t rank_group = std::min<uint64_t>(128, std::max<uint64_t>(nq, 1));
+  while (rank_group > 32 && rank_group_words(rank_group, n_cols) * 4 > rank_lds_room()) rank_group /= 2;
+  if (rank_group_words(rank_group, n_cols) * 4 > rank_lds_room())
+    return fail(MDRQ_ENOTSUP, "circular scan: the union of columns does not fit LDS");
+  const int rank_sw = rank_group <= 32 ? 1 : rank_group <= 64 ? 2 : 4;
+
+  // Output records: every query writes its own slot's row, marks and tile counts.
+  std::vector<BatchOut> outs(nq);
+  std::vector<uint32_t> count_row(nq), fresh, fin_q;
+  for (uint64_t q = 0; q < nq; ++q) {
+    const CircularScan::Meta& m = c->meta[q];
+    outs[q].kind = c->items[q].kind;
+    outs[q].out_index = m.slot;
+    outs[q].sparse = 0;
+    outs[q].pad = 0;
+    outs[q].buf = c->items[q].kind == kBatchCount ? nullptr : c->items[q].r->buf;
+    outs[q].buf_bytes = c->items[q].kind == kBatchCount ? 0 : c->items[q].r->buf_bytes;
+    count_row[q] = m.slot;
+    if (m.fresh) fresh.push_back(m.slot);
+    if (m.left == 1) fin_q.push_back(static_cast<uint32_t>(q));
+  }
+  std::vector<uint32_t> table, group_first, group_table;
+  uint64_t pairs = 0;
+  int rc = build_rank_tables(ds, c->items, outs, slot_of, n_cols, rank_group, rank_sw, table, group_first,
+                             group_table, &pairs);
+  if (rc) return rc;
+  const uint32_t n_groups = static_cast<uint32_t>(group_first.size());
+  group_first.push_back(static_cast<uint32_t>(nq));
+  group_table.push_back(static_cast<uint32_t>(table.size()));
+  uint64_t max_group_words = 0;
+  for (uint32_t g = 0; g < n_groups; ++g)
+    max_group_words = std::max<uint64_t>(max_group_words, (group_table[g + 1] - group_table[g]) +
+                                                              align4(group_first[g + 1] - group_first[g]));
+  const uint32_t n_fin = static_cast<uint32_t>(fin_q.size());
+  std::vector<uint32_t> fin_row(n_fin);
+  std::vector<BatchOut> fin_outs(n_fin);
+  for (uint32_t k = 0; k < n_fin; ++k) {
+    fin_row[k] = count_row[fin_q[k]];
+    fin_outs[k] = outs[fin_q[k]];
+  }
+
+  // Blob: table, group_first, group_table, count rows, fresh slots, finishing count
+  // rows (uint32), then the output records of the scan and of the finish (16-aligned).
+  const uint64_t o_gf = table.size(), o_gt = o_gf + group_first.size(), o_cr = o_gt + group_table.size();
+  const uint64_t o_fr = o_cr + nq, o_fn = o_fr + fresh.size(), words_u32 = o_fn + n_fin;
+  const uint64_t outs_off = (words_u32 * 4 + 15) / 16 * 16;
+  const uint64_t fin_off = outs_off + nq * sizeof(BatchOut);
+  const uint64_t blob = fin_off + n_fin * sizeof(BatchOut);
+  rc = grow_pinned(&ws.h_blob, &ws.h_blob_bytes, blob);
+  if (rc) return rc;
+  rc = grow_device(reinterpret_cast<uint8_t**>(&ws.d_blob), &ws.d_blob_bytes, blob, "circular scan table");
+  if (rc) return rc;
+  uint32_t* hb = static_cast<uint32_t*>(ws.h_blob);
+  std::memcpy(hb, table.data(), table.size() * 4);
+  std::memcpy(hb + o_gf, group_first.data(), group_first.size() * 4);
+  std::memcpy(hb + o_gt, group_table.data(), group_table.size() * 4);
+  std::memcpy(hb + o_cr, count_row.data(), nq * 4);
+  if (!fresh.empty()) std::memcpy(hb + o_fr, fresh.data(), fresh.size() * 4);
+  if (n_fin) std::memcpy(hb + o_fn, fin_row.data(), n_fin * 4);
+  std::memcpy(static_cast<uint8_t*>(ws.h_blob) + outs_off, outs.data(), nq * sizeof(BatchOut));
+  if (n_fin) std::memcpy(static_cast<uint8_t*>(ws.h_blob) + fin_off, fin_outs.data(), n_fin * sizeof(BatchOut));
+  const uint32_t* db = static_cast<const uint32_t*>(ws.d_blob);
+  const uint8_t* dbb = static_cast<const uint8_t*>(ws.d_blob);
+
+  uint64_t* marks = ws.d_words + static_cast<uint64_t>(c->n_slots) * nw;
+  BatchParams bp{};
+  bp.n_rows = ds->n_rows;
+  bp.n_tiles = c->n_tiles;
+  bp.tile_begin = t0;
+  bp.tile_end = t1;
+  bp.count_row = db + o_cr;
+  bp.n_words = nw;
+  bp.n_slots = static_cast<uint32_t>(n_cols);
+  bp.table = db;
+  bp.group_first = db + o_gf;
+  bp.group_table = db + o_gt;
+  bp.words = ws.d_words;
+  bp.n_out = c->n_slots;
+  bp.tile_counts = ws.d_tile_counts;
+  bp.flags = reinterpret_cast<uint16_t*>(marks);
+  bp.n_chunks = c->marks_stride;
+  bp.n_zero = 0;   // each slot's marks are cleared once, before its first step
+  for (int sl = 0; sl < n_cols; ++sl) bp.slot_cols[sl] = ds->cols[slot_dim[sl]];
+  BatchFinish fin{};
+  fin.n_tiles = c->n_tiles;
+  fin.n_words = nw;
+  fin.words = ws.d_words;
+  fin.flags = bp.flags;
+  fin.n_chunks = c->marks_stride;
+  fin.chunk_shift = static_cast<uint32_t>(__builtin_ctz(static_cast<unsigned>(kCircRg)));
+  fin.tile_counts = ws.d_tile_counts;
+  fin.count_row = db + o_fn;
+  fin.outs = reinterpret_cast<const BatchOut*>(dbb + fin_off);
+  fin.counts_out = static_cast<uint64_t*>(ws.h_res_dev);
+  fin.kind_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws.h_res_dev) + static_cast<uint64_t>(c->n_slots) * 8);
+  fin.over_out = nullptr;
+
+  const size_t lds = max_group_words * 4;
+  const int per_cu = batch_blocks_per_cu(n_cols, 4, kCircRg, 4, lds, rank_sw);
+  const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
+  const uint64_t gx = std::max<uint64_t>(1, std::min<uint64_t>(t1 - t0, resident / n_groups));
+  MDRQ_HIP(hipMemcpyAsync(ws.d_blob, ws.h_blob, blob, hipMemcpyHostToDevice, stream), "copy query table");
+  MDRQ_HIP(hipEventRecord(ws.ev0, stream), "hipEventRecord");
+  if (!fresh.empty())
+    MDRQ_HIP(launch_zero_rows(marks, c->marks_stride / 4, db + o_fr, static_cast<uint32_t>(fresh.size()), stream),
+             "clear chunk marks");
+  if (t1 > t0)
+    MDRQ_HIP(launch_batch_scan(bp, n_cols, 4, kCircRg, 4, dim3(static_cast<uint32_t>(gx), n_groups), lds, stream,
+                               rank_sw),
+             "circular scan launch");
+  if (n_fin) MDRQ_HIP(launch_batch_finish(fin, n_fin, stream), "circular scan finish");
+  MDRQ_HIP(hipEventRecord(ws.ev1, stream), "hipEventRecord");
+  MDRQ_HIP(hipStreamSynchronize(stream), "circular scan step");
+  float ms = 0.f;
+  MDRQ_HIP(hipEventElapsedTime(&ms, ws.ev0, ws.ev1), "hipEventElapsedTime");
+  const uint64_t seg_rows = std::min<uint64_t>(ds->n_rows, t1 * kTileRows) - std::min<uint64_t>(ds->n_rows, t0 * kTileRows);
+  {
+    std::lock_guard<std::mutex> lock(ds->stat_mu);
+    ds->batch_lookups += seg_rows * pairs;
+    ds->batch_column_bytes += 4 * seg_rows * pairs;
+    ds->batch_scan_ms += ms;
+  }
+  if (st) {
+    st->scans += 1;
+    st->column_bytes += 4 * seg_rows * pairs;
+    st->device_ms += ms;
+  }
+  // Results of the finished queries, then their slots are free.
+  const volatile uint64_t* counts = static_cast<const volatile uint64_t*>(ws.h_res);
+  const volatile uint32_t* kinds = reinterpret_cast<const volatile uint32_t*>(
+      static_cast<const uint8_t*>(ws.h_res) + static_cast<uint64_t>(c->n_slots) * 8);
+  for (uint32_t k = 0; k < n_fin; ++k) {
+    mdrq_result_t* r = c->items[fin_q[k]].r;
+    const uint64_t count = counts[k];
+    const uint32_t kind = kinds[k];
+    r->count = count;
+    r->status = MDRQ_OK;
+    r->written = 0;
+    if (kind == kBatchCount) {
+      r->mode = MDRQ_OUT_COUNT;
+    } else if (kind == kBatchBitmap) {
+      r->mode = MDRQ_OUT_BITMAP;
+      const uint64_t cap = r->buf_bytes / 8;
+      r->written = std::min(cap, nw);
+      if (cap < nw) r->status = MDRQ_EOVERFLOW;
+    } else {
+      r->mode = MDRQ_OUT_IDS;
+      const uint64_t cap = r->buf_bytes / 4;
+      r->written = std::min(cap, count);
+      if (count > cap) r->status = MDRQ_EOVERFLOW;
+    }
+    done.push_back(c->meta[fin_q[k]].tag);
+  }
+  for (uint32_t k = n_fin; k-- > 0;) circular_drop(c, fin_q[k]);
+  for (CircularScan::Meta& m : c->meta) {
+    m.left -= 1;
+    m.fresh = false;
+  }
+  c->cur = (c->cur + 1) % c->n_segs;
+  return MDRQ_OK;
+}
+}  // namespace
+
+int circular_step(CircularScan* c, hipStream_t stream, std::vector<void*>& done, BatchRunStats* st,
+                  uint64_t* active_out) {
+  if (active_out) *active_out = c->items.size();
+  if (c->items.empty()) return MDRQ_OK;
+  int rc = MDRQ_OK;
+  try {
+    rc = circular_step_inner(c, stream, done, st);
+  } catch (...) {
+    rc = fail(MDRQ_ENOMEM, "circular scan: host memory");
+  }
+  if (rc != MDRQ_OK) {
+    // The active queries' slots are in an unknown state: every one is dropped, with the
+    // error in its result record.
+    for (size_t i = 0; i < c->items.size(); ++i) {
+      c->items[i].r->status = rc;
+      done.push_back(c->meta[i].tag);
+    }
+    while (!c->items.empty()) circular_drop(c, c->items.size() - 1);
+  }
+  return rc;
 }
 
 }  // namespace mdrq

@@ -877,9 +877,12 @@ int mdrq_estimator_gate(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, c
     const uint32_t O = e->O;
     const double ln_rows = std::log(static_cast<double>(e->n_rows));
     const double floor = 1.0 / static_cast<double>(e->n_rows);
-    // Per output: squared errors on the log scale of the network's estimate and of the
-    // base estimate alone, over the targets present.
-    std::vector<double> err_net(O, 0.0), err_base(O, 0.0);
+    // Per output: squared and absolute errors on the log scale of the network's estimate
+    // and of the base estimate alone, over the targets present.  The squared error is
+    // dominated by the few queries with the largest errors, the absolute one (the log of
+    // the geometric-mean q-error) by the typical query; a correction is kept only if it
+    // lowers both.
+    std::vector<double> err_net(O, 0.0), err_base(O, 0.0), abs_net(O, 0.0), abs_base(O, 0.0);
     std::vector<float> y, base;
     for (uint32_t at = 0; at < n; at += kPredictChunk) {
       const uint32_t rows = std::min(kPredictChunk, n - at);
@@ -908,6 +911,8 @@ int mdrq_estimator_gate(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, c
           const double yb = std::min(1.0, std::max(0.0, static_cast<double>(base[static_cast<size_t>(i) * O + j])));
           err_net[j] += (yn - t) * (yn - t);
           err_base[j] += (yb - t) * (yb - t);
+          abs_net[j] += std::fabs(yn - t);
+          abs_base[j] += std::fabs(yb - t);
         }
     }
     // Remove the correction of every output it does not improve: its column of W3 and
@@ -915,9 +920,10 @@ int mdrq_estimator_gate(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, c
     std::vector<float> w3(static_cast<size_t>(e->H) * O), b3(O);
     EST_CHECK(hipMemcpy(w3.data(), e->params() + e->oW3, w3.size() * 4, hipMemcpyDeviceToHost), "parameter download");
     EST_CHECK(hipMemcpy(b3.data(), e->params() + e->ob3, b3.size() * 4, hipMemcpyDeviceToHost), "parameter download");
-    std::vector<float> zeros_w(w3.size(), 0.0f), zeros_b(O, 0.0f);
+    std::vector<bool> keep_out(O);
+    for (uint32_t j = 0; j < O; ++j) keep_out[j] = err_net[j] < err_base[j] && abs_net[j] < abs_base[j];
     for (uint32_t j = 0; j < O; ++j) {
-      const bool keep = err_net[j] < err_base[j];
+      const bool keep = keep_out[j];
       if (kept) kept[j] = keep ? 1u : 0u;
       if (keep) continue;
       for (uint32_t h = 0; h < e->H; ++h) w3[static_cast<size_t>(h) * O + j] = 0.0f;
@@ -928,7 +934,7 @@ int mdrq_estimator_gate(mdrq_estimator* e, const mdrq_query_t* qs, uint32_t n, c
       EST_CHECK(hipMemcpy(mw.data(), m + e->oW3, mw.size() * 4, hipMemcpyDeviceToHost), "moment download");
       EST_CHECK(hipMemcpy(mb.data(), m + e->ob3, mb.size() * 4, hipMemcpyDeviceToHost), "moment download");
       for (uint32_t j = 0; j < O; ++j) {
-        if (err_net[j] < err_base[j]) continue;
+        if (keep_out[j]) continue;
         for (uint32_t h = 0; h < e->H; ++h) mw[static_cast<size_t>(h) * O + j] = 0.0f;
         mb[j] = 0.0f;
       }

@@ -126,7 +126,12 @@ struct BatchParams {
   const uint32_t* group_table;  // first table word of each group (+ end)
   uint64_t* words;              // bitmap scratch, one row of n_words per output query
   uint64_t n_out;               // rows of the scratch in use
-  uint32_t* tile_counts;        // [query][tile]
+  uint32_t* tile_counts;        // [count row][tile]
+  // Tiles [tile_begin, tile_end) are scanned (all of them: 0 and n_tiles).  count_row
+  // maps a query of the batch to its row of tile_counts (null: the query's own index),
+  // so that a query can keep its rows over several scans of different tile ranges.
+  uint64_t tile_begin, tile_end;
+  const uint32_t* count_row;
   // Null: the scratch rows are zeroed before the scan, which stores the non-zero words.
   // Otherwise (slot-mask variant with at most 8 register slots, rank variant) one
   // 16-bit mark per (output row, chunk of at most 16 words) is zeroed instead; the scan
@@ -167,7 +172,8 @@ struct BatchFinish {
   uint64_t n_chunks;
   uint32_t chunk_shift;         // log2 of the bitmap words per chunk (4, 8 or 16 words)
   uint32_t pad;
-  uint32_t* tile_counts;        // [query][tile]; becomes output positions for identifiers
+  uint32_t* tile_counts;        // [count row][tile]; becomes output positions for identifiers
+  const uint32_t* count_row;    // per query its row of tile_counts (null: its index)
   const BatchOut* outs;
   uint64_t* counts_out;         // [query] exact count
   uint32_t* kind_out;           // [query] kind used (kBatchAuto resolved)
@@ -206,6 +212,10 @@ size_t batch_lds_key_bytes(int n_slots, int waves, int rg);
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream);
 // Zero n 64-bit words with a fill kernel (no memset node, so capturable).
 hipError_t launch_zero_words(uint64_t* w, uint64_t n, hipStream_t stream);
+// Zero n_rows rows of row_words 64-bit words: row rows[i] (device array) at
+// base + rows[i] * row_words.
+hipError_t launch_zero_rows(uint64_t* base, uint64_t row_words, const uint32_t* rows, uint32_t n_rows,
+                            hipStream_t stream);
 // The kernel launches of one shared scan (zeroing, scan, count, emit) as graph kernel
 // node parameters, whose arguments point into *L (kept alive while they are used).
 struct BatchLaunches {
@@ -414,6 +424,34 @@ uint64_t request_scratch_bytes(const mdrq_dataset* ds, const mdrq_result_t& r, d
 int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs,
               hipStream_t stream, BatchWorkspace* ws = nullptr, bool tune = true,
               BatchRunStats* st = nullptr, const float* est_in = nullptr);
+// Circular shared scan (batch_host.cpp).  The rows are cut into segments of whole
+// tiles; each step scans the next segment, wrapping around, for every active query, so
+// a query joins at whatever segment comes next and is complete once it has seen each
+// segment once.  Each active query holds a slot (a bitmap row, its chunk marks and a row
+// of tile counts) from its first step to its last.
+struct CircularScan;
+// Bytes of device memory one query slot takes.
+uint64_t circular_slot_bytes(const mdrq_dataset* ds);
+// A circular scan with `slots` query slots and `segments` segments per circle (at most
+// one per tile).
+int circular_create(mdrq_dataset* ds, uint32_t slots, uint32_t segments, CircularScan** out);
+void circular_destroy(CircularScan* c);
+uint32_t circular_free_slots(const CircularScan* c);
+uint32_t circular_active(const CircularScan* c);
+// Admit a query whose result goes to *r (count-only or device memory; checked by the
+// caller).  *answered = true: it needed no shared scan (an empty result, or more
+// predicates than a scan's union may hold) and was answered on `stream` (complete once
+// the stream is); otherwise it joins at the next step.  MDRQ_EBUSY: no free slot, or its
+// columns would make the active queries' union too wide for one scan; nothing was done.
+int circular_admit(CircularScan* c, const mdrq_query_t* q, mdrq_result_t* r, void* tag, hipStream_t stream,
+                   bool* answered);
+// One step on `stream` (returns when it is complete): the next segment for every active
+// query; the queries that have now seen every segment are finished and their results
+// written, and their tags appended to `done`.  `active_out`: the queries the step
+// scanned.  On an error every active query is dropped and its tag appended to `done`
+// (its result record then holds the error status).
+int circular_step(CircularScan* c, hipStream_t stream, std::vector<void*>& done, BatchRunStats* st,
+                  uint64_t* active_out);
 // Grow a workspace so that batches of up to max_queries queries whose requests'
 // request_scratch_bytes sum to at most scratch_bytes run without allocating.
 int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queries,

@@ -10,9 +10,12 @@
 // reserves a full bitmap row (its result can never need more), or, with estimated sizing
 // (use_estimator bit 1), room for about four times its estimated result in the scan's sparse
 // scratch: the dispatcher estimates waiting requests in bulk before admitting them, and
-// a request whose result outgrows its room is answered again by the single-query scan.  Requests that arrive while scans run wait for the next
-// idle worker, so scans of different workers overlap on the device.  Every request's
-// answer is exactly what mdrq_query gives for it alone.
+// a request whose result outgrows its room is answered again by the single-query scan.
+// Requests that arrive while scans run wait for the next idle worker, so scans of
+// different workers overlap on the device.  In circular-scan mode each worker instead
+// keeps one shared scan running over the data, a segment of rows per step, and admits
+// waiting requests between steps (circular_worker_loop).  Every request's answer is
+// exactly what mdrq_query gives for it alone.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -44,6 +47,7 @@ struct Pending {
   hipEvent_t ready = nullptr;
   std::vector<float> est;       // the estimator's estimates (n_dims + 1), when used
   bool estimated = false;
+  mdrq_result_t res{};          // circular scan: the result, copied to *r when complete
 };
 
 struct Worker {
@@ -52,6 +56,7 @@ struct Worker {
   std::thread th;
   std::vector<Pending*> batch;  // handed to this worker by the dispatcher
   bool busy = false;
+  CircularScan* circ = nullptr; // circular-scan mode: this worker's scan
 };
 
 bool needs_row(const mdrq_result_t& r) { return r.mode != MDRQ_OUT_COUNT; }
@@ -80,11 +85,33 @@ struct mdrq_server {
   Clock::time_point first_arrival{}, last_done{};
   BatchRunStats st;
   uint64_t batches = 0;
+  uint64_t active_sum = 0;      // circular scan: active requests summed over steps
   bool overflow = false;
   std::vector<hipEvent_t> free_events;  // submission events for reuse (mu)
 };
 
 namespace {
+
+// Under the server's lock: the first error is kept for the callers.
+void record_error(mdrq_server* s, int rc, const std::string& msg) {
+  if (s->error != MDRQ_OK) return;
+  s->error = rc;
+  s->error_msg = msg;
+}
+
+// Under the server's lock: request p is answered with `res` at time t.
+void complete(mdrq_server* s, Pending* p, const mdrq_result_t& res, Clock::time_point t) {
+  *p->r = res;
+  s->overflow |= res.status == MDRQ_EOVERFLOW;
+  if (s->lat_ns.size() <= p->ticket) s->lat_ns.resize(p->ticket + 1, 0);
+  s->lat_ns[p->ticket] = static_cast<uint64_t>(
+      std::max<int64_t>(0, std::chrono::duration_cast<std::chrono::nanoseconds>(t - p->arrival).count()));
+  s->done.push_back(p->ticket);
+  if (p->ready) s->free_events.push_back(p->ready);
+  delete p;
+  s->completed += 1;
+  s->last_done = t;
+}
 
 void worker_loop(mdrq_server* s, Worker* w) {
   (void)hipSetDevice(s->dev);
@@ -126,24 +153,11 @@ void worker_loop(mdrq_server* s, Worker* w) {
     const Clock::time_point t = Clock::now();
     std::string msg = rc ? mdrq_last_error() : "";
     std::lock_guard<std::mutex> lk(s->mu);
-    if (rc && rc != MDRQ_EOVERFLOW && s->error == MDRQ_OK) {
-      s->error = rc;
-      s->error_msg = msg;
-    }
+    if (rc && rc != MDRQ_EOVERFLOW) record_error(s, rc, msg);
     for (size_t k = 0; k < batch.size(); ++k) {
-      Pending* p = batch[k];
       if (rc && rc != MDRQ_EOVERFLOW) out[k].status = rc;
-      *p->r = out[k];
-      s->overflow |= out[k].status == MDRQ_EOVERFLOW;
-      if (s->lat_ns.size() <= p->ticket) s->lat_ns.resize(p->ticket + 1, 0);
-      s->lat_ns[p->ticket] = static_cast<uint64_t>(
-          std::max<int64_t>(0, std::chrono::duration_cast<std::chrono::nanoseconds>(t - p->arrival).count()));
-      s->done.push_back(p->ticket);
-      if (p->ready) s->free_events.push_back(p->ready);
-      delete p;
+      complete(s, batch[k], out[k], t);
     }
-    s->completed += batch.size();
-    s->last_done = t;
     s->st.scans += st.scans;
     s->st.column_bytes += st.column_bytes;
     s->st.device_ms += st.device_ms;
@@ -151,6 +165,89 @@ void worker_loop(mdrq_server* s, Worker* w) {
     s->st.reruns += st.reruns;
     s->batches += 1;
     w->busy = false;
+    s->cv.notify_all();
+  }
+}
+
+// Circular-scan worker: between steps it admits waiting requests (oldest first, as many
+// as it has free slots and as keep the union of columns within one scan), then runs one
+// step and completes the requests whose circle has closed.  A request waits at most one
+// step before its scan starts, and its scan takes one circle.  The worker ends once the
+// server is closing and nothing waits or is active.
+void circular_worker_loop(mdrq_server* s, Worker* w) {
+  (void)hipSetDevice(s->dev);
+  CircularScan* c = w->circ;
+  std::vector<Pending*> take, answered;
+  std::vector<void*> done;
+  for (;;) {
+    take.clear();
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (circular_active(c) == 0) {
+        s->cv.wait(lk, [&] { return s->closing || !s->ready.empty(); });
+        if (s->ready.empty()) return;
+      }
+      const uint32_t room = circular_free_slots(c);
+      while (!s->ready.empty() && take.size() < room) {
+        take.push_back(s->ready.front());
+        s->ready.pop_front();
+      }
+    }
+    answered.clear();
+    size_t k = 0;
+    for (; k < take.size(); ++k) {
+      Pending* p = take[k];
+      int rc = MDRQ_OK;
+      if (p->ready) {
+        const hipError_t e = hipStreamWaitEvent(w->stream, p->ready, 0);
+        if (e != hipSuccess) rc = fail_hip(e, "serving: wait for the submitting stream");
+      }
+      bool now = false;
+      if (rc == MDRQ_OK) {
+        try {
+          rc = circular_admit(c, &p->q, &p->res, p, w->stream, &now);
+        } catch (...) {
+          rc = fail(MDRQ_ENOMEM, "serving: host memory");
+        }
+        if (rc == MDRQ_EBUSY) break;   // its columns would widen the union too far: it waits
+      }
+      if (rc != MDRQ_OK) {
+        const std::string msg = mdrq_last_error();
+        p->res.status = rc;
+        std::lock_guard<std::mutex> lk(s->mu);
+        record_error(s, rc, msg);
+      }
+      if (rc != MDRQ_OK || now) answered.push_back(p);
+    }
+    if (k < take.size()) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (size_t j = take.size(); j-- > k;) s->ready.push_front(take[j]);
+    }
+    done.clear();
+    uint64_t active = 0;
+    BatchRunStats st;
+    const int rc = circular_step(c, w->stream, done, &st, &active);
+    const std::string msg = rc ? mdrq_last_error() : "";
+    if (!answered.empty() && active == 0) {
+      const hipError_t e = hipStreamSynchronize(w->stream);
+      if (e != hipSuccess)
+        for (Pending* p : answered) p->res.status = fail_hip(e, "serving: stream synchronisation");
+    }
+    const Clock::time_point t = Clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (rc) record_error(s, rc, msg);
+    for (Pending* p : answered) complete(s, p, p->res, t);
+    for (void* tag : done) {
+      Pending* p = static_cast<Pending*>(tag);
+      complete(s, p, p->res, t);
+    }
+    s->st.scans += st.scans;
+    s->st.column_bytes += st.column_bytes;
+    s->st.device_ms += st.device_ms;
+    if (active) {
+      s->batches += 1;
+      s->active_sum += active;
+    }
     s->cv.notify_all();
   }
 }
@@ -217,6 +314,9 @@ int check_config(const mdrq_dataset* ds, const mdrq_serve_config_t* cfg) {
     return fail(MDRQ_EINVAL, "max_batch must be in 1..MDRQ_MAX_BATCH");
   if (cfg->n_streams == 0 || cfg->n_streams > 8) return fail(MDRQ_EINVAL, "n_streams must be in 1..8");
   if (cfg->use_estimator > 3) return fail(MDRQ_EINVAL, "use_estimator must be 0..3");
+  if (cfg->segments > 4096) return fail(MDRQ_EINVAL, "segments must be 0..4096");
+  if (cfg->segments && (cfg->use_estimator & 2u))
+    return fail(MDRQ_EINVAL, "the circular scan keeps full bitmap rows: use_estimator bit 1 does not apply");
   if (cfg->use_estimator && !ds->estimator)
     return fail(MDRQ_EINVAL, "use_estimator needs an attached estimator");
   return MDRQ_OK;
@@ -237,6 +337,7 @@ int check_request(const mdrq_server* s, const mdrq_query_t* q, const mdrq_result
 void destroy(mdrq_server* s) {
   for (Worker& w : s->workers) {
     free_batch(w.ws);
+    circular_destroy(w.circ);
     if (w.stream) (void)hipStreamDestroy(w.stream);
   }
   for (Pending* p : s->ready) {
@@ -261,17 +362,25 @@ int create(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, bool reserve_rows, 
       destroy(s);
       return fail_hip(e, "serving stream");
     }
-    // At most max_batch bitmap rows are ever used by one batch.
-    const uint64_t row = request_scratch_bytes(ds, mdrq_result_t{MDRQ_OUT_IDS, 0, nullptr, 0, 0, 0, 0, 0}, -1.0);
-    const uint64_t bytes = std::min<uint64_t>(s->share, row * cfg->max_batch);
-    int rc = reserve_batch(ds, w.ws, cfg->max_batch, reserve_rows ? bytes : 0);
+    int rc = MDRQ_OK;
+    if (cfg->segments) {
+      // Circular scan: as many query slots as the share holds, at most max_batch.
+      const uint64_t slots = std::min<uint64_t>(cfg->max_batch, s->share / circular_slot_bytes(ds));
+      rc = slots ? circular_create(ds, static_cast<uint32_t>(slots), cfg->segments, &w.circ)
+                 : fail(MDRQ_EBUSY, "one query slot of the circular scan does not fit in one stream's share of the result budget");
+    } else {
+      // At most max_batch bitmap rows are ever used by one batch.
+      const uint64_t row = request_scratch_bytes(ds, mdrq_result_t{MDRQ_OUT_IDS, 0, nullptr, 0, 0, 0, 0, 0}, -1.0);
+      const uint64_t bytes = std::min<uint64_t>(s->share, row * cfg->max_batch);
+      rc = reserve_batch(ds, w.ws, cfg->max_batch, reserve_rows ? bytes : 0);
+    }
     if (rc) {
       destroy(s);
       return rc;
     }
   }
-  for (Worker& w : s->workers) w.th = std::thread(worker_loop, s, &w);
-  s->dispatcher = std::thread(dispatch_loop, s);
+  for (Worker& w : s->workers) w.th = std::thread(cfg->segments ? circular_worker_loop : worker_loop, s, &w);
+  if (!cfg->segments) s->dispatcher = std::thread(dispatch_loop, s);
   *out = s;
   return MDRQ_OK;
 }
@@ -287,6 +396,7 @@ int enqueue(mdrq_server* s, const mdrq_query_t* q, mdrq_result_t* r, Clock::time
   if (s->cfg.use_estimator & 1u) p->q.flags |= MDRQ_Q_ORDER_ESTIMATED;
   if (s->cfg.use_estimator & 2u) p->q.flags |= MDRQ_Q_SIZE_ESTIMATED;
   p->r = r;
+  p->res = *r;
   p->arrival = arrival;
   if (order) {
     {
@@ -329,7 +439,7 @@ int shutdown(mdrq_server* s, mdrq_serve_stats_t* stats) {
     s->closing = true;
     s->cv.notify_all();
   }
-  s->dispatcher.join();
+  if (s->dispatcher.joinable()) s->dispatcher.join();
   for (Worker& w : s->workers) w.th.join();
   const int err = s->error;
   const std::string msg = s->error_msg;
@@ -354,7 +464,9 @@ int shutdown(mdrq_server* s, mdrq_serve_stats_t* stats) {
       stats->mean_us = sum / sorted.size() * 1e-3;
       stats->max_us = sorted.back() * 1e-3;
     }
-    stats->mean_batch = s->batches ? static_cast<double>(n) / s->batches : 0.0;
+    stats->mean_batch = !s->batches ? 0.0
+                        : s->cfg.segments ? static_cast<double>(s->active_sum) / s->batches
+                                          : static_cast<double>(n) / s->batches;
     stats->hbm_gbps = stats->wall_s > 0 ? s->st.column_bytes / stats->wall_s * 1e-9 : 0.0;
     stats->overflow_reruns = s->st.reruns;
     stats->sized_by_estimate = s->st.sparse;

@@ -71,7 +71,7 @@ class Result(ctypes.Structure):
 class ServeConfig(ctypes.Structure):
     _fields_ = [("result_budget_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32),
                 ("n_streams", ctypes.c_uint32), ("use_estimator", ctypes.c_uint32),
-                ("max_queue", ctypes.c_uint32)]
+                ("max_queue", ctypes.c_uint32), ("segments", ctypes.c_uint32)]
 
 
 class EstimatorConfig(ctypes.Structure):
@@ -426,8 +426,10 @@ class Dataset:
         _check(load_library().mdrq_reset_profile(self._h))
 
     def serve(self, arrivals_ns, queries, outs, modes="ids", max_batch: int = 256,
-              n_streams: int = 2, budget_bytes: int = 1 << 30, use_estimator: int = 0):
-        """Replay requests (arrival time in ns, query) through the serving loop.
+              n_streams: int = 2, budget_bytes: int = 1 << 30, use_estimator: int = 0,
+              segments: int = 0):
+        """Replay requests (arrival time in ns, query) through the serving loop
+        (segments > 0: the circular scan with that many parts per pass).
         Returns (answers, latencies in ns, stats dict)."""
         lib = load_library()
         n = len(queries)
@@ -440,7 +442,7 @@ class Dataset:
         rarr = (Result * max(1, n))(*[_result_for(o, m) for o, m in zip(outs, modes)])
         lat = (ctypes.c_uint64 * max(1, n))()
         st = ServeStats()
-        cfg = ServeConfig(int(budget_bytes), max_batch, n_streams, int(use_estimator), 0)
+        cfg = ServeConfig(int(budget_bytes), max_batch, n_streams, int(use_estimator), 0, int(segments))
         rc = lib.mdrq_serve(self._h, ctypes.byref(cfg), reqs, n, rarr, lat, ctypes.byref(st))
         _check(rc, (OK, EOVERFLOW))
         answers = [Answer(r.count, r.written, r.status, _MODE_NAMES[r.mode]) for r in rarr[:n]]
@@ -448,9 +450,9 @@ class Dataset:
         return answers, np.array(lat[:n], dtype=np.uint64), stats
 
     def serve_open(self, max_batch: int = 256, n_streams: int = 2, budget_bytes: int = 1 << 30,
-                   use_estimator: int = 0, max_queue: int = 0) -> "Server":
+                   use_estimator: int = 0, max_queue: int = 0, segments: int = 0) -> "Server":
         """A live server on this dataset (submit / poll / close)."""
-        return Server(self, max_batch, n_streams, budget_bytes, use_estimator, max_queue)
+        return Server(self, max_batch, n_streams, budget_bytes, use_estimator, max_queue, segments)
 
     def label_selectivities(self, queries) -> np.ndarray:
         """Exact selectivities (n, n_dims + 1): each predicate alone, then the query;
@@ -505,9 +507,9 @@ class Server:
     answered by continuous batching; poll() reports the completed ones."""
 
     def __init__(self, ds: Dataset, max_batch: int, n_streams: int, budget_bytes: int,
-                 use_estimator: int, max_queue: int):
+                 use_estimator: int, max_queue: int, segments: int = 0):
         cfg = ServeConfig(int(budget_bytes), max_batch, n_streams, int(use_estimator),
-                          int(max_queue))
+                          int(max_queue), int(segments))
         h = ctypes.c_void_p()
         _check(load_library().mdrq_serve_open(ds.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -20,7 +20,10 @@ def _print(*a):
     print(*a, flush=True)
 
 
-def test_live_server_results_match_oracle():
+@pytest.mark.parametrize("segments", [0, 5])
+def test_live_server_results_match_oracle(segments):
+    """Continuous batching (segments 0) and the circular scan (5 parts per pass), with
+    submissions in bursts while earlier requests are being scanned."""
     w, raw = c5_small(300_007)
     cols = oracle.prepare(raw)
     pool = dg.workload_queries(w, 48, sampler=w.sampler(sample_rows=1 << 16))
@@ -33,8 +36,8 @@ def test_live_server_results_match_oracle():
     with mdrq.Dataset.from_host(raw) as ds:
         outs = outputs(ds.n_rows, modes)
         answers = [None] * n
-        with ds.serve_open(max_batch=32, n_streams=2, budget_bytes=1 << 26) as srv:
-            _print("live: submitting", n)
+        with ds.serve_open(max_batch=32, n_streams=2, budget_bytes=1 << 26, segments=segments) as srv:
+            _print("live: submitting", n, "segments", segments)
             tickets = {}
             for i in range(n):
                 tickets[srv.submit(qs[i], outs[i], modes[i])] = i

@@ -93,6 +93,88 @@ def test_serve_results_match_oracle_and_alone():
             assert np.array_equal(ids1, payload(outs[i], answers[i], ds.n_rows))
 
 
+@pytest.mark.parametrize("segments", [1, 3, 8, 200])
+def test_circular_scan_results_match_oracle_and_alone(segments):
+    """The circular scan: requests join the running scan at whatever part of the rows
+    comes next and finish after one pass; every result is the oracle's and the query's
+    alone (mixed output modes, every row, an empty interval, an unrestricted query, a
+    ragged last tile; 200 parts are more than the 74 tiles: one per tile)."""
+    w, raw = c5_small(300_007)
+    cols = oracle.prepare(raw)
+    pool = dg.workload_queries(w, 64, sampler=w.sampler(sample_rows=1 << 16))
+    pool[0] = dg.make_query([])                       # every row
+    pool[1] = dg.make_query([(2, 0.6, 0.1)])          # empty interval
+    pool[2] = dg.make_query([(j, -np.inf, np.inf) for j in range(12)])
+    rng = np.random.default_rng(4)
+    n = 300
+    qs = [pool[i] for i in rng.integers(0, len(pool), size=n)]
+    modes = [["ids", "bitmap", "count", "auto"][i % 4] for i in range(n)]
+    arrivals = poisson(n, 40_000, seed=5)
+    with mdrq.Dataset.from_host(raw) as ds:
+        outs = outputs(ds.n_rows, modes)
+        _print("circular serve", n, "requests, segments", segments)
+        answers, lat, stats = ds.serve(arrivals, qs, outs, modes, max_batch=64, n_streams=2,
+                                       budget_bytes=1 << 26, segments=segments)
+        _print(stats)
+        check(ds, cols, qs, modes, outs, answers, "circular")
+        assert stats["completed"] == n and stats["scans"] >= 1
+        assert stats["mean_batch"] >= 1.0
+        assert stats["p50_us"] <= stats["p99_us"] <= stats["max_us"]
+        for i in range(0, n, 23):
+            if modes[i] != "ids":
+                continue
+            a1, ids1 = run(ds, qs[i])
+            assert a1.count == answers[i].count
+            assert np.array_equal(ids1, payload(outs[i], answers[i], ds.n_rows))
+
+
+def test_circular_scan_slots_and_union_limit():
+    """Circular-scan admission: with a share of two query slots per stream no step scans
+    more than two requests per worker; on 128 columns, requests restricting 50 columns
+    each wait while their union would not fit one scan, and a request on 110 columns is
+    answered by its own scan; all results are the oracle's."""
+    w, raw = c5_small(100_000)
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 40, sampler=w.sampler(sample_rows=1 << 16))
+    row = 8 * ((100_000 + 63) // 64)
+    with mdrq.Dataset.from_host(raw) as ds:
+        modes = ["ids", "auto"] * 20
+        outs = outputs(ds.n_rows, modes)
+        answers, lat, stats = ds.serve(np.zeros(40, dtype=np.uint64), qs, outs, modes, max_batch=64,
+                                       n_streams=2, budget_bytes=2 * 3 * row, segments=4)
+        _print(stats)
+        check(ds, cols, qs, modes, outs, answers, "slots")
+        assert 1.0 <= stats["mean_batch"] <= 2.0
+        with pytest.raises(mdrq.MdrqError) as e:
+            ds.serve([0], qs[:1], outputs(ds.n_rows, ["ids"]), "ids", n_streams=1,
+                     budget_bytes=row, segments=4)
+        assert e.value.code == mdrq.EBUSY
+        for kwargs in ({"segments": 4097}, {"segments": 2, "use_estimator": 2}):
+            with pytest.raises(mdrq.MdrqError) as e:
+                ds.serve([0], qs[:1], outputs(ds.n_rows, ["ids"]), "ids", **kwargs)
+            assert e.value.code == mdrq.EINVAL
+
+    n, d = 20_000, 128
+    raw = [dg.column(41, j, dg.uniform(), n) for j in range(d)]
+    cols = oracle.prepare(raw)
+    rng = np.random.default_rng(6)
+    qs = []
+    for i in range(24):
+        k = 110 if i == 7 else 50
+        dims = rng.choice(d, size=k, replace=False)
+        qs.append(dg.make_query([(int(j), 0.0, 0.995) for j in dims]))
+    modes = ["ids", "count", "bitmap"] * 8
+    with mdrq.Dataset.from_host(raw) as ds:
+        outs = outputs(ds.n_rows, modes)
+        answers, lat, stats = ds.serve(np.zeros(24, dtype=np.uint64), qs, outs, modes, max_batch=64,
+                                       n_streams=1, budget_bytes=1 << 26, segments=3)
+        _print(stats)
+        check(ds, cols, qs, modes, outs, answers, "union limit")
+        # at most two 50-column requests fit one scan's union (three cover about 99 of
+        # 128 columns, over the limit most of the time): steps carry few of the 24
+        assert stats["mean_batch"] < 6
+
+
 def test_admission_by_result_memory():
     """Each stream's share holds exactly 3 bitmap rows: no worker batch carries more
     than 3 requests that need one, count-only requests need none."""
