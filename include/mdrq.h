@@ -189,8 +189,12 @@ int mdrq_query_noalloc(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r
  * as its share holds, at most max_batch; each slot is a bitmap row, its chunk marks and
  * a row of tile counts, whatever the output mode) while the union of their columns fits
  * one scan; a request is complete, and finished exactly as in a shared scan, once it has
- * seen every part.  So a request waits at most one step before its scan starts, instead
- * of a whole scan.  Its results are the same as in the other mode. */
+ * seen every part.  So a request waits at most about one step before its scan starts,
+ * instead of a whole scan (two with pipelined steps, MDRQ_OPT_CIRCULAR).  Optionally
+ * (MDRQ_OPT_CIRCULAR) a worker with no pass running whose waiting requests are few
+ * enough that separate single-query scans cost less than a pass (the batched path's
+ * cost model) answers them that way instead.  Results are the same as in the other
+ * mode. */
 typedef struct {
   uint64_t result_budget_bytes;
   uint32_t max_batch;       /* 1 .. MDRQ_MAX_BATCH */
@@ -362,10 +366,16 @@ enum {
                                  shape as a HIP graph and replayed with each call's
                                  arguments; a clear bit launches each kernel directly.
                                  Default 0 */
-  MDRQ_OPT_RESERVE_FACTOR = 11 /* MDRQ_Q_SIZE_ESTIMATED: room reserved per estimated
+  MDRQ_OPT_RESERVE_FACTOR = 11, /* MDRQ_Q_SIZE_ESTIMATED: room reserved per estimated
                                  result row, in millionths (default 4000000: four times
                                  the estimate, plus 64 chunks); 1..10^9.  Small values
                                  force the fallback (tests) */
+  MDRQ_OPT_CIRCULAR = 12      /* circular-scan servers opened from now on (segments > 0):
+                                 bit 0: steps pipelined (the host prepares the next step
+                                 while the device runs one; a request then joins up to
+                                 two steps later), bit 1: an idle worker answers few
+                                 waiting requests by separate single-query scans when
+                                 those cost less than a pass.  Default 0 */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
 

@@ -1185,9 +1185,18 @@ constexpr int kCircRg = 8;                          // rows per lane: 512-row ch
 constexpr uint64_t kCircChunkRows = 64 * kCircRg;
 }  // namespace
 
+// Steps may be pipelined: the host builds and enqueues step k + 1 while the device runs
+// step k, then waits for step k and reads its results.  Two step buffers alternate
+// (query table, result records, events); a buffer is refilled only after its step is
+// complete, and a slot freed by a step can be taken at the next one because the stream
+// runs the next step's clearing and scan after this step's finish.  Otherwise each step
+// is waited for before the next is built, so requests admitted meanwhile join it.
 struct CircularScan {
   mdrq_dataset* ds = nullptr;
-  BatchWorkspace ws;
+  uint64_t* rows = nullptr;          // slot rows, then the slots' chunk marks
+  uint64_t rows_len = 0;
+  uint32_t* tile_counts = nullptr;   // per slot a row of tile counts
+  uint64_t tile_counts_len = 0;
   uint32_t n_slots = 0;              // query slots
   uint32_t max_union = 0;            // widest union of columns a step may scan
   uint64_t n_tiles = 0, seg_tiles = 0, n_segs = 0;
@@ -1206,6 +1215,23 @@ struct CircularScan {
   std::vector<uint32_t> free_slots;
   std::vector<uint32_t> dim_uses;    // per dimension: active queries restricting it
   uint32_t union_size = 0;
+  std::vector<void*> answered;       // answered at admission: complete with the next step
+  struct Step {
+    void* h_blob = nullptr;
+    uint64_t h_blob_bytes = 0;
+    void* d_blob = nullptr;
+    uint64_t d_blob_bytes = 0;
+    void* h_res = nullptr;           // counts (u64), then kinds (u32): mapped pinned
+    void* h_res_dev = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool inflight = false;
+    std::vector<std::pair<mdrq_result_t*, void*>> fin;   // finished by this step, in order
+    std::vector<void*> extra;        // answered at admission before this step
+    uint64_t seg_rows = 0, pairs = 0;
+  };
+  Step steps[2];
+  int next = 0;                      // buffer of the next step
+  bool pipelined = false;            // else each step is waited for before the next
 };
 
 uint64_t circular_slot_bytes(const mdrq_dataset* ds) {
@@ -1214,12 +1240,27 @@ uint64_t circular_slot_bytes(const mdrq_dataset* ds) {
   return n_words(ds) * 8 + align4(n_chunks) * 2 + n_tiles * 4;
 }
 
+void circular_destroy(CircularScan* c) {
+  if (!c) return;
+  if (c->rows) (void)hipFree(c->rows);
+  if (c->tile_counts) (void)hipFree(c->tile_counts);
+  for (CircularScan::Step& s : c->steps) {
+    if (s.h_blob) (void)hipHostFree(s.h_blob);
+    if (s.d_blob) (void)hipFree(s.d_blob);
+    if (s.h_res) (void)hipHostFree(s.h_res);
+    if (s.ev0) (void)hipEventDestroy(s.ev0);
+    if (s.ev1) (void)hipEventDestroy(s.ev1);
+  }
+  delete c;
+}
+
 int circular_create(mdrq_dataset* ds, uint32_t slots, uint32_t segments, CircularScan** out) {
   *out = nullptr;
   if (slots == 0 || segments == 0) return fail(MDRQ_EINVAL, "circular scan: no slots or no segments");
-  std::unique_ptr<CircularScan> c(new CircularScan());
+  std::unique_ptr<CircularScan, void (*)(CircularScan*)> c(new CircularScan(), circular_destroy);
   c->ds = ds;
   c->n_slots = slots;
+  c->pipelined = (ds->circular_mode & 1) != 0;
   c->n_tiles = (ds->n_rows + kTileRows - 1) / kTileRows;
   const uint64_t segs = std::max<uint64_t>(1, std::min<uint64_t>(segments, c->n_tiles));
   c->seg_tiles = std::max<uint64_t>(1, (c->n_tiles + segs - 1) / segs);
@@ -1235,38 +1276,37 @@ int circular_create(mdrq_dataset* ds, uint32_t slots, uint32_t segments, Circula
   c->dim_uses.assign(ds->n_dims, 0);
   for (uint32_t i = slots; i-- > 0;) c->free_slots.push_back(i);
   const uint64_t nw = n_words(ds);
-  BatchWorkspace& ws = c->ws;
-  int rc = grow_device(&ws.d_words, &ws.d_words_len, slots * nw + slots * c->marks_stride / 4 + 1,
-                       "circular scan rows");
+  int rc = grow_device(&c->rows, &c->rows_len, slots * nw + slots * c->marks_stride / 4 + 1, "circular scan rows");
   if (rc) return rc;
-  rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, slots * std::max<uint64_t>(1, c->n_tiles),
+  rc = grow_device(&c->tile_counts, &c->tile_counts_len, slots * std::max<uint64_t>(1, c->n_tiles),
                    "circular scan tile counts");
   if (rc) return rc;
-  rc = grow_results(ws, slots);
-  if (rc) return rc;
-  // Query tables of all groups (at most one per 32 slots), the per-query arrays and two
-  // sets of output records.
+  // Per step buffer: the query tables of all groups (at most one per 32 slots), the
+  // per-query arrays, two sets of output records, and the result records.
   const uint64_t groups = (slots + 31) / 32;
   const uint64_t blob = groups * rank_group_words(128, static_cast<int>(mu)) * 4 + slots * (16 + 2 * sizeof(BatchOut)) +
                         (2 * groups + 16) * 4 + 64;
-  rc = grow_pinned(&ws.h_blob, &ws.h_blob_bytes, blob);
-  if (rc) return rc;
-  rc = grow_device(reinterpret_cast<uint8_t**>(&ws.d_blob), &ws.d_blob_bytes, blob, "circular scan table");
-  if (rc) return rc;
-  MDRQ_HIP(hipEventCreate(&ws.ev0), "hipEventCreate");
-  MDRQ_HIP(hipEventCreate(&ws.ev1), "hipEventCreate");
+  for (CircularScan::Step& s : c->steps) {
+    rc = grow_pinned(&s.h_blob, &s.h_blob_bytes, blob);
+    if (rc) return rc;
+    rc = grow_device(reinterpret_cast<uint8_t**>(&s.d_blob), &s.d_blob_bytes, blob, "circular scan table");
+    if (rc) return rc;
+    if (hipHostMalloc(&s.h_res, static_cast<uint64_t>(slots) * 16, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer(&s.h_res_dev, s.h_res, 0) != hipSuccess)
+      return fail(MDRQ_ENOMEM, "circular scan result records");
+    MDRQ_HIP(hipEventCreate(&s.ev0), "hipEventCreate");
+    MDRQ_HIP(hipEventCreate(&s.ev1), "hipEventCreate");
+  }
   *out = c.release();
   return MDRQ_OK;
 }
 
-void circular_destroy(CircularScan* c) {
-  if (!c) return;
-  free_batch(c->ws);
-  delete c;
-}
-
 uint32_t circular_free_slots(const CircularScan* c) { return static_cast<uint32_t>(c->free_slots.size()); }
 uint32_t circular_active(const CircularScan* c) { return static_cast<uint32_t>(c->items.size()); }
+bool circular_busy(const CircularScan* c) {
+  return !c->items.empty() || c->steps[0].inflight || c->steps[1].inflight || !c->answered.empty();
+}
 
 int circular_admit(CircularScan* c, const mdrq_query_t* q, mdrq_result_t* r, void* tag, hipStream_t stream,
                    bool* answered) {
@@ -1282,6 +1322,7 @@ int circular_admit(CircularScan* c, const mdrq_query_t* q, mdrq_result_t* r, voi
     }
     const int rc = no_scan ? finish_empty(ds, plan, r, stream) : run_query(ds, plan, r, stream);
     if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
+    c->answered.push_back(tag);
     *answered = true;
     return MDRQ_OK;
   }
@@ -1308,9 +1349,11 @@ void circular_drop(CircularScan* c, size_t i) {
   c->meta.erase(c->meta.begin() + static_cast<std::ptrdiff_t>(i));
 }
 
-int circular_step_inner(CircularScan* c, hipStream_t stream, std::vector<void*>& done, BatchRunStats* st) {
+// Build and enqueue the next step into its buffer (not waited for).  The queries that
+// see their last segment in it leave the active list now; their results are read when
+// the step is complete.
+int circular_enqueue(CircularScan* c, CircularScan::Step& sb, hipStream_t stream) {
   mdrq_dataset* ds = c->ds;
-  BatchWorkspace& ws = c->ws;
   const uint64_t nq = c->items.size();
   const uint64_t nw = n_words(ds);
   const uint64_t t0 = c->cur * c->seg_tiles;
@@ -1332,12 +1375,13 @@ int circular_step_inner(CircularScan* c, hipStream_t stream, std::vector<void*>&
   std::vector<uint32_t> count_row(nq), fresh, fin_q;
   for (uint64_t q = 0; q < nq; ++q) {
     const CircularScan::Meta& m = c->meta[q];
-    outs[q].kind = c->items[q].kind;
+    const Item& it = c->items[q];
+    outs[q].kind = it.kind;
     outs[q].out_index = m.slot;
     outs[q].sparse = 0;
     outs[q].pad = 0;
-    outs[q].buf = c->items[q].kind == kBatchCount ? nullptr : c->items[q].r->buf;
-    outs[q].buf_bytes = c->items[q].kind == kBatchCount ? 0 : c->items[q].r->buf_bytes;
+    outs[q].buf = it.kind == kBatchCount ? nullptr : it.r->buf;
+    outs[q].buf_bytes = it.kind == kBatchCount ? 0 : it.r->buf_bytes;
     count_row[q] = m.slot;
     if (m.fresh) fresh.push_back(m.slot);
     if (m.left == 1) fin_q.push_back(static_cast<uint32_t>(q));
@@ -1369,23 +1413,23 @@ int circular_step_inner(CircularScan* c, hipStream_t stream, std::vector<void*>&
   const uint64_t outs_off = (words_u32 * 4 + 15) / 16 * 16;
   const uint64_t fin_off = outs_off + nq * sizeof(BatchOut);
   const uint64_t blob = fin_off + n_fin * sizeof(BatchOut);
-  rc = grow_pinned(&ws.h_blob, &ws.h_blob_bytes, blob);
+  rc = grow_pinned(&sb.h_blob, &sb.h_blob_bytes, blob);
   if (rc) return rc;
-  rc = grow_device(reinterpret_cast<uint8_t**>(&ws.d_blob), &ws.d_blob_bytes, blob, "circular scan table");
+  rc = grow_device(reinterpret_cast<uint8_t**>(&sb.d_blob), &sb.d_blob_bytes, blob, "circular scan table");
   if (rc) return rc;
-  uint32_t* hb = static_cast<uint32_t*>(ws.h_blob);
+  uint32_t* hb = static_cast<uint32_t*>(sb.h_blob);
   std::memcpy(hb, table.data(), table.size() * 4);
   std::memcpy(hb + o_gf, group_first.data(), group_first.size() * 4);
   std::memcpy(hb + o_gt, group_table.data(), group_table.size() * 4);
   std::memcpy(hb + o_cr, count_row.data(), nq * 4);
   if (!fresh.empty()) std::memcpy(hb + o_fr, fresh.data(), fresh.size() * 4);
   if (n_fin) std::memcpy(hb + o_fn, fin_row.data(), n_fin * 4);
-  std::memcpy(static_cast<uint8_t*>(ws.h_blob) + outs_off, outs.data(), nq * sizeof(BatchOut));
-  if (n_fin) std::memcpy(static_cast<uint8_t*>(ws.h_blob) + fin_off, fin_outs.data(), n_fin * sizeof(BatchOut));
-  const uint32_t* db = static_cast<const uint32_t*>(ws.d_blob);
-  const uint8_t* dbb = static_cast<const uint8_t*>(ws.d_blob);
+  std::memcpy(static_cast<uint8_t*>(sb.h_blob) + outs_off, outs.data(), nq * sizeof(BatchOut));
+  if (n_fin) std::memcpy(static_cast<uint8_t*>(sb.h_blob) + fin_off, fin_outs.data(), n_fin * sizeof(BatchOut));
+  const uint32_t* db = static_cast<const uint32_t*>(sb.d_blob);
+  const uint8_t* dbb = static_cast<const uint8_t*>(sb.d_blob);
 
-  uint64_t* marks = ws.d_words + static_cast<uint64_t>(c->n_slots) * nw;
+  uint64_t* marks = c->rows + static_cast<uint64_t>(c->n_slots) * nw;
   BatchParams bp{};
   bp.n_rows = ds->n_rows;
   bp.n_tiles = c->n_tiles;
@@ -1397,9 +1441,9 @@ int circular_step_inner(CircularScan* c, hipStream_t stream, std::vector<void*>&
   bp.table = db;
   bp.group_first = db + o_gf;
   bp.group_table = db + o_gt;
-  bp.words = ws.d_words;
+  bp.words = c->rows;
   bp.n_out = c->n_slots;
-  bp.tile_counts = ws.d_tile_counts;
+  bp.tile_counts = c->tile_counts;
   bp.flags = reinterpret_cast<uint16_t*>(marks);
   bp.n_chunks = c->marks_stride;
   bp.n_zero = 0;   // each slot's marks are cleared once, before its first step
@@ -1407,23 +1451,23 @@ int circular_step_inner(CircularScan* c, hipStream_t stream, std::vector<void*>&
   BatchFinish fin{};
   fin.n_tiles = c->n_tiles;
   fin.n_words = nw;
-  fin.words = ws.d_words;
+  fin.words = c->rows;
   fin.flags = bp.flags;
   fin.n_chunks = c->marks_stride;
   fin.chunk_shift = static_cast<uint32_t>(__builtin_ctz(static_cast<unsigned>(kCircRg)));
-  fin.tile_counts = ws.d_tile_counts;
+  fin.tile_counts = c->tile_counts;
   fin.count_row = db + o_fn;
   fin.outs = reinterpret_cast<const BatchOut*>(dbb + fin_off);
-  fin.counts_out = static_cast<uint64_t*>(ws.h_res_dev);
-  fin.kind_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(ws.h_res_dev) + static_cast<uint64_t>(c->n_slots) * 8);
+  fin.counts_out = static_cast<uint64_t*>(sb.h_res_dev);
+  fin.kind_out = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(sb.h_res_dev) + static_cast<uint64_t>(c->n_slots) * 8);
   fin.over_out = nullptr;
 
   const size_t lds = max_group_words * 4;
   const int per_cu = batch_blocks_per_cu(n_cols, 4, kCircRg, 4, lds, rank_sw);
   const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
   const uint64_t gx = std::max<uint64_t>(1, std::min<uint64_t>(t1 - t0, resident / n_groups));
-  MDRQ_HIP(hipMemcpyAsync(ws.d_blob, ws.h_blob, blob, hipMemcpyHostToDevice, stream), "copy query table");
-  MDRQ_HIP(hipEventRecord(ws.ev0, stream), "hipEventRecord");
+  MDRQ_HIP(hipMemcpyAsync(sb.d_blob, sb.h_blob, blob, hipMemcpyHostToDevice, stream), "copy query table");
+  MDRQ_HIP(hipEventRecord(sb.ev0, stream), "hipEventRecord");
   if (!fresh.empty())
     MDRQ_HIP(launch_zero_rows(marks, c->marks_stride / 4, db + o_fr, static_cast<uint32_t>(fresh.size()), stream),
              "clear chunk marks");
@@ -1432,28 +1476,48 @@ int circular_step_inner(CircularScan* c, hipStream_t stream, std::vector<void*>&
                                rank_sw),
              "circular scan launch");
   if (n_fin) MDRQ_HIP(launch_batch_finish(fin, n_fin, stream), "circular scan finish");
-  MDRQ_HIP(hipEventRecord(ws.ev1, stream), "hipEventRecord");
-  MDRQ_HIP(hipStreamSynchronize(stream), "circular scan step");
+  MDRQ_HIP(hipEventRecord(sb.ev1, stream), "hipEventRecord");
+
+  sb.inflight = true;
+  sb.seg_rows = std::min<uint64_t>(ds->n_rows, t1 * kTileRows) - std::min<uint64_t>(ds->n_rows, t0 * kTileRows);
+  sb.pairs = pairs;
+  sb.fin.clear();
+  for (uint32_t k = 0; k < n_fin; ++k) sb.fin.emplace_back(c->items[fin_q[k]].r, c->meta[fin_q[k]].tag);
+  sb.extra.swap(c->answered);
+  c->answered.clear();
+  for (uint32_t k = n_fin; k-- > 0;) circular_drop(c, fin_q[k]);
+  for (CircularScan::Meta& m : c->meta) {
+    m.left -= 1;
+    m.fresh = false;
+  }
+  c->cur = (c->cur + 1) % c->n_segs;
+  return MDRQ_OK;
+}
+
+// Wait for an enqueued step and read the results of the queries it finished.
+int circular_collect(CircularScan* c, CircularScan::Step& sb, std::vector<void*>& done, BatchRunStats* st) {
+  mdrq_dataset* ds = c->ds;
+  MDRQ_HIP(hipEventSynchronize(sb.ev1), "circular scan step");
+  sb.inflight = false;
   float ms = 0.f;
-  MDRQ_HIP(hipEventElapsedTime(&ms, ws.ev0, ws.ev1), "hipEventElapsedTime");
-  const uint64_t seg_rows = std::min<uint64_t>(ds->n_rows, t1 * kTileRows) - std::min<uint64_t>(ds->n_rows, t0 * kTileRows);
+  MDRQ_HIP(hipEventElapsedTime(&ms, sb.ev0, sb.ev1), "hipEventElapsedTime");
   {
     std::lock_guard<std::mutex> lock(ds->stat_mu);
-    ds->batch_lookups += seg_rows * pairs;
-    ds->batch_column_bytes += 4 * seg_rows * pairs;
+    ds->batch_lookups += sb.seg_rows * sb.pairs;
+    ds->batch_column_bytes += 4 * sb.seg_rows * sb.pairs;
     ds->batch_scan_ms += ms;
   }
   if (st) {
     st->scans += 1;
-    st->column_bytes += 4 * seg_rows * pairs;
+    st->column_bytes += 4 * sb.seg_rows * sb.pairs;
     st->device_ms += ms;
   }
-  // Results of the finished queries, then their slots are free.
-  const volatile uint64_t* counts = static_cast<const volatile uint64_t*>(ws.h_res);
+  const uint64_t nw = n_words(ds);
+  const volatile uint64_t* counts = static_cast<const volatile uint64_t*>(sb.h_res);
   const volatile uint32_t* kinds = reinterpret_cast<const volatile uint32_t*>(
-      static_cast<const uint8_t*>(ws.h_res) + static_cast<uint64_t>(c->n_slots) * 8);
-  for (uint32_t k = 0; k < n_fin; ++k) {
-    mdrq_result_t* r = c->items[fin_q[k]].r;
+      static_cast<const uint8_t*>(sb.h_res) + static_cast<uint64_t>(c->n_slots) * 8);
+  for (size_t k = 0; k < sb.fin.size(); ++k) {
+    mdrq_result_t* r = sb.fin[k].first;
     const uint64_t count = counts[k];
     const uint32_t kind = kinds[k];
     r->count = count;
@@ -1472,14 +1536,11 @@ int circular_step_inner(CircularScan* c, hipStream_t stream, std::vector<void*>&
       r->written = std::min(cap, count);
       if (count > cap) r->status = MDRQ_EOVERFLOW;
     }
-    done.push_back(c->meta[fin_q[k]].tag);
+    done.push_back(sb.fin[k].second);
   }
-  for (uint32_t k = n_fin; k-- > 0;) circular_drop(c, fin_q[k]);
-  for (CircularScan::Meta& m : c->meta) {
-    m.left -= 1;
-    m.fresh = false;
-  }
-  c->cur = (c->cur + 1) % c->n_segs;
+  for (void* t : sb.extra) done.push_back(t);
+  sb.fin.clear();
+  sb.extra.clear();
   return MDRQ_OK;
 }
 }  // namespace
@@ -1487,16 +1548,50 @@ int circular_step_inner(CircularScan* c, hipStream_t stream, std::vector<void*>&
 int circular_step(CircularScan* c, hipStream_t stream, std::vector<void*>& done, BatchRunStats* st,
                   uint64_t* active_out) {
   if (active_out) *active_out = c->items.size();
-  if (c->items.empty()) return MDRQ_OK;
   int rc = MDRQ_OK;
+  bool enqueued = false;
   try {
-    rc = circular_step_inner(c, stream, done, st);
+    CircularScan::Step& mine = c->steps[c->next];
+    CircularScan::Step& prev = c->steps[c->next ^ 1];
+    if (!c->items.empty()) {
+      rc = circular_enqueue(c, mine, stream);
+      enqueued = rc == MDRQ_OK;
+    }
+    if (rc == MDRQ_OK && prev.inflight) rc = circular_collect(c, prev, done, st);
+    if (rc == MDRQ_OK && enqueued && !c->pipelined) {
+      rc = circular_collect(c, mine, done, st);
+      enqueued = false;   // complete: the same buffer serves the next step
+    }
+    if (rc == MDRQ_OK && !enqueued && !c->answered.empty()) {
+      // Answered at admission with no step to complete them: wait for the stream.
+      const hipError_t e = hipStreamSynchronize(stream);
+      if (e != hipSuccess) {
+        rc = fail_hip(e, "circular scan: stream synchronisation");
+      } else {
+        for (void* t : c->answered) done.push_back(t);
+        c->answered.clear();
+      }
+    }
+    if (enqueued) c->next ^= 1;
   } catch (...) {
     rc = fail(MDRQ_ENOMEM, "circular scan: host memory");
   }
   if (rc != MDRQ_OK) {
-    // The active queries' slots are in an unknown state: every one is dropped, with the
-    // error in its result record.
+    // The slots are in an unknown state: wait for what was enqueued, then every query
+    // in flight or active is dropped with the error in its result record.
+    (void)hipStreamSynchronize(stream);
+    for (CircularScan::Step& sb : c->steps) {
+      for (auto& f : sb.fin) {
+        f.first->status = rc;
+        done.push_back(f.second);
+      }
+      for (void* t : sb.extra) done.push_back(t);
+      sb.fin.clear();
+      sb.extra.clear();
+      sb.inflight = false;
+    }
+    for (void* t : c->answered) done.push_back(t);
+    c->answered.clear();
     for (size_t i = 0; i < c->items.size(); ++i) {
       c->items[i].r->status = rc;
       done.push_back(c->meta[i].tag);
@@ -1504,6 +1599,27 @@ int circular_step(CircularScan* c, hipStream_t stream, std::vector<void*>& done,
     while (!c->items.empty()) circular_drop(c, c->items.size() - 1);
   }
   return rc;
+}
+
+// Whether separate single-query scans answer these queries sooner than one shared scan
+// (the model run_batch chooses by).
+bool separate_scans_cheaper(const mdrq_dataset* ds, const mdrq_query_t* qs, const mdrq_result_t* rs, uint32_t n) {
+  std::vector<Item> items;
+  std::vector<size_t> members;
+  std::vector<bool> in(ds->n_dims, false);
+  int used = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    Plan plan = make_plan(ds, &qs[i], &rs[i]);
+    if (plan.empty) continue;
+    for (uint32_t d : plan.dims)
+      if (!in[d]) {
+        in[d] = true;
+        ++used;
+      }
+    members.push_back(items.size());
+    items.push_back(Item{i, std::move(plan), kind_of(rs[i].mode), nullptr, {}});
+  }
+  return members.empty() || plain_is_cheaper(items, members, std::max(used, 1), ds->n_rows);
 }
 
 }  // namespace mdrq

@@ -438,20 +438,27 @@ int circular_create(mdrq_dataset* ds, uint32_t slots, uint32_t segments, Circula
 void circular_destroy(CircularScan* c);
 uint32_t circular_free_slots(const CircularScan* c);
 uint32_t circular_active(const CircularScan* c);
+// Active queries, a step in flight, or requests answered at admission not yet reported.
+bool circular_busy(const CircularScan* c);
 // Admit a query whose result goes to *r (count-only or device memory; checked by the
 // caller).  *answered = true: it needed no shared scan (an empty result, or more
-// predicates than a scan's union may hold) and was answered on `stream` (complete once
-// the stream is); otherwise it joins at the next step.  MDRQ_EBUSY: no free slot, or its
-// columns would make the active queries' union too wide for one scan; nothing was done.
+// predicates than a scan's union may hold) and was answered on `stream`; its tag is
+// reported by a later circular_step, once the stream has done that work.  Otherwise it
+// joins at the next step.  MDRQ_EBUSY: no free slot, or its columns would make the
+// active queries' union too wide for one scan; nothing was done.
 int circular_admit(CircularScan* c, const mdrq_query_t* q, mdrq_result_t* r, void* tag, hipStream_t stream,
                    bool* answered);
-// One step on `stream` (returns when it is complete): the next segment for every active
-// query; the queries that have now seen every segment are finished and their results
-// written, and their tags appended to `done`.  `active_out`: the queries the step
-// scanned.  On an error every active query is dropped and its tag appended to `done`
-// (its result record then holds the error status).
+// One call: enqueue the next step (the next segment for every active query) on `stream`,
+// then wait for the step enqueued by the previous call (pipelined steps) or for this one
+// and report the queries it completed (their results written, their tags appended to
+// `done`).  Call while circular_busy.  `active_out`: the
+// queries the enqueued step scans.  On an error every query in flight or active is
+// dropped, its tag appended to `done` and the error put in its result record.
 int circular_step(CircularScan* c, hipStream_t stream, std::vector<void*>& done, BatchRunStats* st,
                   uint64_t* active_out);
+// Whether separate single-query scans answer these queries sooner than one shared scan
+// (the cost model of the batched path).
+bool separate_scans_cheaper(const mdrq_dataset* ds, const mdrq_query_t* qs, const mdrq_result_t* rs, uint32_t n);
 // Grow a workspace so that batches of up to max_queries queries whose requests'
 // request_scratch_bytes sum to at most scratch_bytes run without allocating.
 int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queries,
@@ -558,6 +565,7 @@ struct mdrq_dataset {
   // updated per call.
   bool graph_single = false;
   bool graph_batch = false;
+  int circular_mode = 0;                 // MDRQ_OPT_CIRCULAR bits
   int64_t reserve_ppm = 4000000;         // MDRQ_Q_SIZE_ESTIMATED: reserved rows per estimate (1e-6)
   std::vector<mdrq::QueryGraph> graphs;
   // Batched path.

@@ -661,6 +661,10 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
       if (value < 1 || value > 1000000000) return fail(MDRQ_EINVAL, "reserve factor must be 1..10^9 millionths");
       ds->reserve_ppm = value;
       return MDRQ_OK;
+    case MDRQ_OPT_CIRCULAR:
+      if (value < 0 || value > 3) return fail(MDRQ_EINVAL, "circular mode must be 0..3");
+      ds->circular_mode = static_cast<int>(value);
+      return MDRQ_OK;
     case MDRQ_OPT_GRAPHS:
       if (value < 0 || value > 3) return fail(MDRQ_EINVAL, "graphs must be 0..3");
       ds->graph_single = (value & 1) != 0;

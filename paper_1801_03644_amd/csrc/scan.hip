@@ -222,17 +222,35 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& e
   return total;
 }
 
+// Inclusive prefix sum over the wave's lanes by DPP: shifts by 1, 2, 4, 8 within each
+// row of 16 lanes, then row 0's and row 2's last lane added to rows 1 and 3, then lane
+// 31 to rows 2 and 3 (lanes with no source add 0).
+__device__ __forceinline__ uint32_t compact_wave_sum(uint32_t v) {
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xA, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xC, 0xF, false));
+  return v;
+}
+
+constexpr uint32_t kCompactStage = 2048;   // ids per wave staged in LDS
+
 // Workgroup b turns the bitmap of its scan segment into ascending identifiers.  Its
 // global offset is the sum of the earlier segments' counts; offsets of its tiles come
 // from a scan of their counts in LDS; then each wave takes 64-word chunks (4096 rows):
-// one coalesced load, a wave scan of the words' popcounts, and every lane writes the
-// identifiers of its word.  Chunks without a hit are skipped without being read.
+// one coalesced load and a wave scan of the words' popcounts; a chunk of up to 2048 ids
+// is staged in LDS as 16-bit row offsets at their output places and written out in
+// consecutive 64-lane runs, a denser one is written by each lane for its word.  Chunks
+// without a hit are skipped without being read.
 template <int U>
 __global__ void __launch_bounds__(kBlock) compact_kernel(CompactParams c) {
   constexpr uint32_t kTileRows = 256 * U;
   constexpr uint32_t kTilesPerChunk = kChunkWords * 64 / kTileRows;
   __shared__ uint32_t s_off[kScanTiles + 1];
   __shared__ uint32_t s_wave[kWavesPerBlock];
+  __shared__ uint16_t s_stage[kWavesPerBlock][kCompactStage];
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & (kWave - 1);
   const uint32_t wave = tid / kWave;
@@ -294,23 +312,52 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(CompactParams c) {
       if (s_off[lt] == beg) continue;
       const uint64_t off = carry + beg;
       if (off >= c.capacity) continue;
-      const uint64_t w = (t0 + ft) * (kTileRows / 64) + lane;
+      const uint64_t w0 = (t0 + ft) * (kTileRows / 64);
+      const uint64_t w = w0 + lane;
       const uint64_t word = w < c.n_words && w < (t0 + lt) * (kTileRows / 64) ? c.bitmap[w] : 0;
       const uint32_t k = __popcll(word);
-      uint32_t incl = k;
-#pragma unroll
-      for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t o = __shfl_up(incl, d);
-        if (lane >= static_cast<uint32_t>(d)) incl += o;
-      }
-      uint64_t r = off + incl - k;
+      const uint32_t incl = compact_wave_sum(k);
+      const uint32_t total = __builtin_amdgcn_readlane(incl, 63);   // ids of the chunk
       uint64_t bits = word;
-      const uint32_t row = static_cast<uint32_t>(w * 64);
-      while (bits) {
-        const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(bits));
-        if (r < c.capacity) c.ids[r] = row + b;
-        ++r;
-        bits &= bits - 1;
+      if (total <= kCompactStage) {
+        // The chunk's rows (16-bit offsets) into the wave's LDS buffer at their output
+        // places, then out in consecutive 64-lane runs.
+        uint16_t* buf = s_stage[wave];
+        uint32_t at = incl - k;
+        const uint32_t lane_row = lane * 64;
+        while (bits) {
+          buf[at++] = static_cast<uint16_t>(lane_row + static_cast<uint32_t>(__builtin_ctzll(bits)));
+          bits &= bits - 1;
+        }
+        const uint32_t row0 = static_cast<uint32_t>(w0 * 64);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t i0 = 0; i0 < total; i0 += 4 * kWave) {
+          uint32_t v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t i = i0 + kWave * j + lane;
+            v[j] = i < total ? row0 + buf[i] : 0u;
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t i = i0 + kWave * j + lane;
+            if (i < total && off + i < c.capacity) c.ids[off + i] = v[j];
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else {   // a dense chunk: each lane writes its word's ids directly
+        uint64_t r = off + incl - k;
+        const uint32_t row = static_cast<uint32_t>(w * 64);
+        while (bits) {
+          const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(bits));
+          if (r < c.capacity) c.ids[r] = row + b;
+          ++r;
+          bits &= bits - 1;
+        }
       }
     }
     carry += chunk_total;

@@ -86,6 +86,7 @@ struct mdrq_server {
   BatchRunStats st;
   uint64_t batches = 0;
   uint64_t active_sum = 0;      // circular scan: active requests summed over steps
+  bool separate_when_idle = false;  // circular scan: MDRQ_OPT_CIRCULAR bit 1
   bool overflow = false;
   std::vector<hipEvent_t> free_events;  // submission events for reuse (mu)
 };
@@ -170,28 +171,81 @@ void worker_loop(mdrq_server* s, Worker* w) {
 }
 
 // Circular-scan worker: between steps it admits waiting requests (oldest first, as many
-// as it has free slots and as keep the union of columns within one scan), then runs one
-// step and completes the requests whose circle has closed.  A request waits at most one
-// step before its scan starts, and its scan takes one circle.  The worker ends once the
-// server is closing and nothing waits or is active.
+// as it has free slots and as keep the union of columns within one scan), then runs the
+// next step and completes the requests whose pass it closed (with pipelined steps: those
+// of the step before).  A request waits about one step (two) before its scan starts, and
+// its scan takes one pass.  Optionally (MDRQ_OPT_CIRCULAR bit 1), when the worker is idle
+// and the waiting requests are few enough that separate single-query scans are cheaper
+// than a pass (the batched path's cost model), it answers them that way instead of
+// starting a pass.  The worker ends once the server is closing and nothing waits or is
+// in flight.
 void circular_worker_loop(mdrq_server* s, Worker* w) {
   (void)hipSetDevice(s->dev);
   CircularScan* c = w->circ;
   std::vector<Pending*> take, answered;
   std::vector<void*> done;
+  std::vector<mdrq_query_t> qs;
+  std::vector<mdrq_result_t> rs;
   for (;;) {
     take.clear();
+    bool separate = false;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      if (circular_active(c) == 0) {
+      if (!circular_busy(c)) {
         s->cv.wait(lk, [&] { return s->closing || !s->ready.empty(); });
         if (s->ready.empty()) return;
+        // Idle: the oldest waiting requests (up to max_batch) by separate scans if that
+        // is cheaper than a pass for them.
+        const size_t n = s->separate_when_idle ? std::min<size_t>(s->ready.size(), s->cfg.max_batch) : 0;
+        qs.clear();
+        rs.clear();
+        for (size_t i = 0; i < n; ++i) {
+          qs.push_back(s->ready[i]->q);
+          rs.push_back(s->ready[i]->res);
+        }
+        try {
+          separate = n && separate_scans_cheaper(s->ds, qs.data(), rs.data(), static_cast<uint32_t>(n));
+        } catch (...) {
+        }
+        if (separate)
+          for (size_t i = 0; i < n; ++i) {
+            take.push_back(s->ready.front());
+            s->ready.pop_front();
+          }
       }
-      const uint32_t room = circular_free_slots(c);
+      const uint32_t room = separate ? 0 : circular_free_slots(c);
       while (!s->ready.empty() && take.size() < room) {
         take.push_back(s->ready.front());
         s->ready.pop_front();
       }
+    }
+    if (separate) {
+      int rc = MDRQ_OK;
+      for (Pending* p : take)
+        if (p->ready && rc == MDRQ_OK) {
+          const hipError_t e = hipStreamWaitEvent(w->stream, p->ready, 0);
+          if (e != hipSuccess) rc = fail_hip(e, "serving: wait for the submitting stream");
+        }
+      BatchRunStats st;
+      if (rc == MDRQ_OK) {
+        try {
+          rc = run_batch(s->ds, qs.data(), static_cast<uint32_t>(qs.size()), rs.data(), w->stream, &w->ws,
+                         false, &st);
+        } catch (...) {
+          rc = fail(MDRQ_ENOMEM, "serving: host memory");
+        }
+      }
+      const Clock::time_point t = Clock::now();
+      const std::string msg = rc ? mdrq_last_error() : "";
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (rc && rc != MDRQ_EOVERFLOW) record_error(s, rc, msg);
+      for (size_t k = 0; k < take.size(); ++k) {
+        if (rc && rc != MDRQ_EOVERFLOW) rs[k].status = rc;
+        complete(s, take[k], rs[k], t);
+      }
+      s->st.alone += st.alone;
+      s->cv.notify_all();
+      continue;
     }
     answered.clear();
     size_t k = 0;
@@ -217,7 +271,8 @@ void circular_worker_loop(mdrq_server* s, Worker* w) {
         std::lock_guard<std::mutex> lk(s->mu);
         record_error(s, rc, msg);
       }
-      if (rc != MDRQ_OK || now) answered.push_back(p);
+      // (one answered at admission is reported by a later step, with the stream's work)
+      if (rc != MDRQ_OK) answered.push_back(p);
     }
     if (k < take.size()) {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -228,11 +283,6 @@ void circular_worker_loop(mdrq_server* s, Worker* w) {
     BatchRunStats st;
     const int rc = circular_step(c, w->stream, done, &st, &active);
     const std::string msg = rc ? mdrq_last_error() : "";
-    if (!answered.empty() && active == 0) {
-      const hipError_t e = hipStreamSynchronize(w->stream);
-      if (e != hipSuccess)
-        for (Pending* p : answered) p->res.status = fail_hip(e, "serving: stream synchronisation");
-    }
     const Clock::time_point t = Clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
     if (rc) record_error(s, rc, msg);
@@ -354,6 +404,7 @@ int create(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, bool reserve_rows, 
   s->ds = ds;
   s->cfg = *cfg;
   s->share = cfg->result_budget_bytes / cfg->n_streams;
+  s->separate_when_idle = (ds->circular_mode & 2) != 0;
   (void)hipGetDevice(&s->dev);
   s->workers.resize(cfg->n_streams);
   for (Worker& w : s->workers) {

@@ -44,6 +44,7 @@ OPT_BATCH_VARIANT = 8
 OPT_RANK_BUCKETS = 9
 OPT_GRAPHS = 10
 OPT_RESERVE_FACTOR = 11
+OPT_CIRCULAR = 12
 
 
 class MdrqError(RuntimeError):

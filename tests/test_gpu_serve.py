@@ -93,12 +93,13 @@ def test_serve_results_match_oracle_and_alone():
             assert np.array_equal(ids1, payload(outs[i], answers[i], ds.n_rows))
 
 
-@pytest.mark.parametrize("segments", [1, 3, 8, 200])
-def test_circular_scan_results_match_oracle_and_alone(segments):
+@pytest.mark.parametrize("segments,mode", [(1, 0), (3, 0), (8, 0), (200, 0), (3, 3), (8, 1), (8, 2)])
+def test_circular_scan_results_match_oracle_and_alone(segments, mode):
     """The circular scan: requests join the running scan at whatever part of the rows
     comes next and finish after one pass; every result is the oracle's and the query's
     alone (mixed output modes, every row, an empty interval, an unrestricted query, a
-    ragged last tile; 200 parts are more than the 74 tiles: one per tile)."""
+    ragged last tile; 200 parts are more than the 74 tiles: one per tile), with steps
+    pipelined or not and with or without separate scans for few requests (mode bits)."""
     w, raw = c5_small(300_007)
     cols = oracle.prepare(raw)
     pool = dg.workload_queries(w, 64, sampler=w.sampler(sample_rows=1 << 16))
@@ -109,10 +110,15 @@ def test_circular_scan_results_match_oracle_and_alone(segments):
     n = 300
     qs = [pool[i] for i in rng.integers(0, len(pool), size=n)]
     modes = [["ids", "bitmap", "count", "auto"][i % 4] for i in range(n)]
-    arrivals = poisson(n, 40_000, seed=5)
+    # bursts of 1..24 requests (the first of 24) at Poisson times: bursts start passes,
+    # later ones join them, lone requests may be answered by their own scans
+    sizes = np.concatenate([[24], rng.integers(1, 25, size=n)])
+    burst_of = np.repeat(np.arange(len(sizes)), sizes)[:n]
+    arrivals = poisson(len(sizes), 3_000, seed=5)[burst_of] - poisson(len(sizes), 3_000, seed=5)[0]
     with mdrq.Dataset.from_host(raw) as ds:
+        ds.set_option(mdrq.OPT_CIRCULAR, mode)
         outs = outputs(ds.n_rows, modes)
-        _print("circular serve", n, "requests, segments", segments)
+        _print("circular serve", n, "requests, segments", segments, "mode", mode)
         answers, lat, stats = ds.serve(arrivals, qs, outs, modes, max_batch=64, n_streams=2,
                                        budget_bytes=1 << 26, segments=segments)
         _print(stats)
@@ -130,9 +136,10 @@ def test_circular_scan_results_match_oracle_and_alone(segments):
 
 def test_circular_scan_slots_and_union_limit():
     """Circular-scan admission: with a share of two query slots per stream no step scans
-    more than two requests per worker; on 128 columns, requests restricting 50 columns
-    each wait while their union would not fit one scan, and a request on 110 columns is
-    answered by its own scan; all results are the oracle's."""
+    more than two requests per worker; lone requests on an idle server get their own
+    scans; on 128 columns, requests restricting 50 columns each wait while their union
+    would not fit one scan, and a request on 110 columns is answered by its own scan;
+    all results are the oracle's."""
     w, raw = c5_small(100_000)
     cols = oracle.prepare(raw)
     qs = dg.workload_queries(w, 40, sampler=w.sampler(sample_rows=1 << 16))
@@ -145,6 +152,15 @@ def test_circular_scan_slots_and_union_limit():
         _print(stats)
         check(ds, cols, qs, modes, outs, answers, "slots")
         assert 1.0 <= stats["mean_batch"] <= 2.0
+        # requests arriving one at a time with idle gaps, separate scans allowed: each
+        # answered by its own scan (cheaper than a pass), no pass started
+        ds.set_option(mdrq.OPT_CIRCULAR, 2)
+        answers, lat, stats = ds.serve(np.arange(8, dtype=np.uint64) * 3_000_000, qs[:8], outs[:8], modes[:8],
+                                       max_batch=64, n_streams=1, budget_bytes=1 << 26, segments=4)
+        _print(stats)
+        check(ds, cols, qs[:8], modes[:8], outs[:8], answers, "separate")
+        assert stats["scans"] == 0
+        ds.set_option(mdrq.OPT_CIRCULAR, 0)
         with pytest.raises(mdrq.MdrqError) as e:
             ds.serve([0], qs[:1], outputs(ds.n_rows, ["ids"]), "ids", n_streams=1,
                      budget_bytes=row, segments=4)
