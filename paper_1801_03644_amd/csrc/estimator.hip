@@ -160,21 +160,26 @@ __global__ void base_joint_kernel(float* base, uint32_t n, uint32_t d) {
 // ---------------------------------------------------------------- matrix products
 
 // C[m][n] = sum_k A(m, k) * B(k, n) (+ bias[n]) (+ add[m][n]); A(m,k) = a[m*a_m + k*a_k] and
-// B(k,n) = b[k*b_k + n*b_n] are bfloat16, out of range reads are zero.  One wave
-// computes a 16x16 tile of C with 16x16x16 matrix-core steps.  (Loading four steps'
-// operands before their products measured slower: 13.4 against 8.0 us per call.)
-__global__ void __launch_bounds__(64) gemm_bf16_kernel(GemmArgs g) {
-  const uint32_t lane = threadIdx.x;
+// B(k,n) = b[k*b_k + n*b_n] are bfloat16, out of range reads are zero.  A workgroup
+// computes a 16x16 tile of C with 16x16x16 matrix-core steps; its kGemmWaves waves take
+// every kGemmWaves-th step (wave w: steps w, w + kGemmWaves, ...), so the chains of
+// dependent operand loads are that many times shorter, and wave 0 adds the waves'
+// partial tiles in wave order.  (The products are small and the operands are read
+// through strides: the loads' latency, not the matrix cores, sets the time.)
+constexpr uint32_t kGemmWaves = 4;
+__global__ void __launch_bounds__(64 * kGemmWaves) gemm_bf16_kernel(GemmArgs g) {
+  __shared__ floatx4 part[kGemmWaves - 1][64];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t m0 = blockIdx.y * 16, n0 = blockIdx.x * 16;
   const uint32_t r = lane % 16;        // row of A / column of B and C held by this lane
   const uint32_t kq = (lane / 16) * 4; // first of the 4 k values held by this lane
+  const uint32_t am = m0 + r, bn = n0 + r;
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (uint32_t k0 = 0; k0 < g.K; k0 += 16) {
+  for (uint32_t k0 = 16 * wave; k0 < g.K; k0 += 16 * kGemmWaves) {
     bf16x4 av, bv;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t k = k0 + kq + i;
-      const uint32_t am = m0 + r, bn = n0 + r;
       av[i] = (am < g.M && k < g.K)
                   ? static_cast<short>(g.a[static_cast<uint64_t>(am) * g.a_m + static_cast<uint64_t>(k) * g.a_k])
                   : static_cast<short>(0);
@@ -183,6 +188,15 @@ __global__ void __launch_bounds__(64) gemm_bf16_kernel(GemmArgs g) {
                   : static_cast<short>(0);
     }
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+  }
+  if (wave > 0) part[wave - 1][lane] = acc;
+  __syncthreads();
+  if (wave > 0) return;
+#pragma unroll
+  for (uint32_t w = 0; w + 1 < kGemmWaves; ++w) {
+    const floatx4 o = part[w][lane];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += o[i];
   }
   // acc[i] holds C[m0 + 4*(lane/16) + i][n0 + lane%16].
 #pragma unroll
@@ -417,7 +431,7 @@ hipError_t launch_features(const FeatureArgs& f, hipStream_t s) {
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  gemm_bf16_kernel<<<dim3((g.N + 15) / 16, (g.M + 15) / 16), 64, 0, s>>>(g);
+  gemm_bf16_kernel<<<dim3((g.N + 15) / 16, (g.M + 15) / 16), 64 * kGemmWaves, 0, s>>>(g);
   return hipGetLastError();
 }
 
