@@ -513,6 +513,19 @@ __global__ void __launch_bounds__(W * 64) batch_rank_kernel(BatchParams bp) {
         const uint4 h = *reinterpret_cast<const uint4*>(hdr + 4 * s);
         const uint32_t hw = __builtin_amdgcn_readfirstlane(h.y);   // uniform
         if (hw == 0) continue;  // no predicate of the group on this column
+        if constexpr (SW <= 2) {
+          // Early break per chunk and group (section 2.2.4): once no query of the group
+          // accepts a row of the chunk, the remaining columns are not read.  (acc starts
+          // all ones; each applied column clears the bits of queries beyond the group.)
+          // Checked for groups of up to 64 queries, where a chunk can die: in larger
+          // groups it hardly does and the test would only cost vector instructions.
+          uint32_t any = 0;
+#pragma unroll
+          for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int w = 0; w < SW; ++w) any |= acc[g][w];
+          if (__builtin_amdgcn_ballot_w64(any != 0) == 0) break;
+        }
         const uint32_t M = hw & 0xFFFu, d = (hw >> 12) & 15u, nbm1 = (1u << ((hw >> 16) & 15u)) - 1;
         const uint32_t shift = (hw >> 24) & 31u;
         const bool by_value = hw >> 31;
