@@ -209,9 +209,8 @@ typedef struct {
                                0 = unbounded.  The replay ignores it. */
   uint32_t segments;        /* 0: continuous batching; 1 .. 4096: circular scan with
                                this many parts per pass (use_estimator bit 1 is then
-                               MDRQ_EINVAL; bit 0 orders the columns a step walks, and
-                               a chunk of rows that no request of a group of up to 64
-                               still accepts reads no further column) */
+                               MDRQ_EINVAL; bit 0 changes nothing: predicates are
+                               walked in the given order) */
 } mdrq_serve_config_t;
 
 /* One request: the query, and its arrival time in ns after the start of the run. */

@@ -1309,13 +1309,13 @@ bool circular_busy(const CircularScan* c) {
 }
 
 int circular_admit(CircularScan* c, const mdrq_query_t* q, mdrq_result_t* r, void* tag, hipStream_t stream,
-                   bool* answered, const float* est) {
+                   bool* answered) {
   *answered = false;
   mdrq_dataset* ds = c->ds;
-  // The evaluation order only decides which columns a step reads first (the union is
-  // walked in the queries' mean order; a chunk no query accepts any more reads no more).
+  // Predicates in the given order: a step's early break needs a whole 512-row chunk to
+  // die for every query of a group, which estimated order was not measured to bring
+  // about any sooner (its estimates cost a host round trip per step).
   Plan plan = make_plan(ds, q, r);
-  if (est && (q->flags & MDRQ_Q_ORDER_ESTIMATED)) order_plan(plan, est);
   const bool no_scan = plan.empty || ds->n_rows == 0;
   if (no_scan || plan.preds.size() > c->max_union) {
     if (r->mode == MDRQ_OUT_AUTO) {

@@ -445,11 +445,9 @@ bool circular_busy(const CircularScan* c);
 // predicates than a scan's union may hold) and was answered on `stream`; its tag is
 // reported by a later circular_step, once the stream has done that work.  Otherwise it
 // joins at the next step.  MDRQ_EBUSY: no free slot, or its columns would make the
-// active queries' union too wide for one scan; nothing was done.  est (optional): the
-// query's estimated selectivities (n_dims + 1), which order its predicates when it asks
-// for estimated order.
+// active queries' union too wide for one scan; nothing was done.
 int circular_admit(CircularScan* c, const mdrq_query_t* q, mdrq_result_t* r, void* tag, hipStream_t stream,
-                   bool* answered, const float* est = nullptr);
+                   bool* answered);
 // One call: enqueue the next step (the next segment for every active query) on `stream`,
 // then wait for the step enqueued by the previous call (pipelined steps) or for this one
 // and report the queries it completed (their results written, their tags appended to

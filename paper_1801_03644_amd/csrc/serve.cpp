@@ -248,18 +248,6 @@ void circular_worker_loop(mdrq_server* s, Worker* w) {
       continue;
     }
     answered.clear();
-    // Estimated order (use_estimator bit 0): the new requests' estimates in one call.
-    std::vector<float> est;
-    if ((s->cfg.use_estimator & 1u) && !take.empty()) {
-      qs.clear();
-      for (Pending* p : take) qs.push_back(p->q);
-      try {
-        if (estimate_for_order(s->ds, qs.data(), static_cast<uint32_t>(qs.size()), est) != MDRQ_OK) est.clear();
-      } catch (...) {
-        est.clear();
-      }
-    }
-    const size_t est_row = s->ds->n_dims + 1;
     size_t k = 0;
     for (; k < take.size(); ++k) {
       Pending* p = take[k];
@@ -271,8 +259,7 @@ void circular_worker_loop(mdrq_server* s, Worker* w) {
       bool now = false;
       if (rc == MDRQ_OK) {
         try {
-          rc = circular_admit(c, &p->q, &p->res, p, w->stream, &now,
-                              est.size() == take.size() * est_row ? &est[k * est_row] : nullptr);
+          rc = circular_admit(c, &p->q, &p->res, p, w->stream, &now);
         } catch (...) {
           rc = fail(MDRQ_ENOMEM, "serving: host memory");
         }
