@@ -373,9 +373,9 @@ enum {
   MDRQ_OPT_CIRCULAR = 12      /* circular-scan servers opened from now on (segments > 0):
                                  bit 0: steps pipelined (the host prepares the next step
                                  while the device runs one; a request then joins up to
-                                 two steps later), bit 1: an idle worker answers few
-                                 waiting requests by separate single-query scans when
-                                 those cost less than a pass.  Default 0 */
+                                 two steps later), bit 1: an idle worker answers up to
+                                 four waiting requests by separate single-query scans
+                                 when those cost less than a pass.  Default 0 */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
 

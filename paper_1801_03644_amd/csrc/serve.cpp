@@ -61,6 +61,9 @@ struct Worker {
 
 bool needs_row(const mdrq_result_t& r) { return r.mode != MDRQ_OUT_COUNT; }
 
+// Circular scan: most waiting requests an idle worker answers by separate scans.
+constexpr size_t kSeparateMax = 4;
+
 }  // namespace
 
 struct mdrq_server {
@@ -194,9 +197,10 @@ void circular_worker_loop(mdrq_server* s, Worker* w) {
       if (!circular_busy(c)) {
         s->cv.wait(lk, [&] { return s->closing || !s->ready.empty(); });
         if (s->ready.empty()) return;
-        // Idle: the oldest waiting requests (up to max_batch) by separate scans if that
-        // is cheaper than a pass for them.
-        const size_t n = s->separate_when_idle ? std::min<size_t>(s->ready.size(), s->cfg.max_batch) : 0;
+        // Idle: up to kSeparateMax waiting requests by separate scans if that is cheaper
+        // than a pass for them.  (The cost model prices a scan's column bytes, not its
+        // output; capped so, a run of large-result scans cannot hold the others long.)
+        const size_t n = s->separate_when_idle && s->ready.size() <= kSeparateMax ? s->ready.size() : 0;
         qs.clear();
         rs.clear();
         for (size_t i = 0; i < n; ++i) {

@@ -191,6 +191,43 @@ def test_circular_scan_slots_and_union_limit():
         assert stats["mean_batch"] < 6
 
 
+def test_circular_scan_edge_datasets():
+    """The circular scan on a dataset of one ragged tile (more parts asked than tiles),
+    on special values (+-0, +-inf, subnormals, bounds at them) and on an empty dataset
+    (every request answered at admission)."""
+    special = np.array([-np.inf, -2.5, -1.0, -1e-45, -0.0, 0.0, 1e-45, 1.1754942e-38,
+                        0.25, 0.5, 1.0, 3.0e38, np.inf], dtype=np.float32)
+    rng = np.random.default_rng(8)
+    cases = [
+        ("one tile", [rng.random(1000, dtype=np.float32) for _ in range(4)],
+         [(j, lo, hi) for j in range(4) for lo, hi in ((0.1, 0.7), (0.0, 0.05), (0.5, 1.0))]),
+        ("special", [special[rng.integers(0, len(special), size=30_000)] for _ in range(3)],
+         [(j, lo, hi) for j in range(3) for lo, hi in ((-0.0, 0.0), (0.0, np.inf), (-np.inf, -0.0),
+                                                        (1e-45, 1.0), (-1e-45, 1e-45), (-2.5, 0.25))]),
+    ]
+    for label, raw, preds in cases:
+        cols = oracle.prepare(raw)
+        qs = [dg.make_query([preds[i], preds[(3 * i + 1) % len(preds)]])
+              if preds[i][0] != preds[(3 * i + 1) % len(preds)][0] else dg.make_query([preds[i]])
+              for i in range(len(preds))]
+        qs.append(dg.make_query([]))
+        modes = [["ids", "bitmap", "count", "auto"][i % 4] for i in range(len(qs))]
+        with mdrq.Dataset.from_host(raw) as ds:
+            outs = outputs(ds.n_rows, modes)
+            answers, lat, stats = ds.serve(np.zeros(len(qs), dtype=np.uint64), qs, outs, modes,
+                                           max_batch=64, n_streams=1, budget_bytes=1 << 26, segments=4)
+            _print(label, stats)
+            check(ds, cols, qs, modes, outs, answers, label)
+    raw = [np.empty(0, dtype=np.float32)] * 2
+    with mdrq.Dataset.from_host(raw) as ds:
+        modes = ["ids", "bitmap", "count", "auto"]
+        qs = [dg.make_query([(0, 0.0, 1.0)])] * 4
+        answers, lat, stats = ds.serve(np.zeros(4, dtype=np.uint64), qs, [None] * 4, modes,
+                                       max_batch=8, n_streams=1, budget_bytes=1 << 20, segments=3)
+        assert all(a.count == 0 and a.status == mdrq.OK for a in answers)
+        assert stats["completed"] == 4 and stats["scans"] == 0
+
+
 def test_admission_by_result_memory():
     """Each stream's share holds exactly 3 bitmap rows: no worker batch carries more
     than 3 requests that need one, count-only requests need none."""
