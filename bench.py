@@ -208,7 +208,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="c5: seconds per rate")
     ap.add_argument("--segments", default="4",
                     help="c5: circular-scan parts per pass to serve each rate with as well (comma list)")
-    ap.add_argument("--circular-modes", default="0,2",
+    ap.add_argument("--circular-modes", default="4,0",
                     help="c5: MDRQ_OPT_CIRCULAR values to serve the circular scan with (comma list)")
     args = ap.parse_args()
     if args.summarize:

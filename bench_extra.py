@@ -454,13 +454,13 @@ def serving(args):
         for seg in [int(x) for x in args.segments.split(",") if x]:
             for cm in [int(x) for x in args.circular_modes.split(",") if x]:
                 ds.set_option(mdrq.OPT_CIRCULAR, cm)
-                name = f"circular_{seg}" if cm == 0 else f"circular_{seg}_mode{cm}"
+                name = f"circular_{seg}" if cm == 4 else f"circular_{seg}_mode{cm}"
                 log(f"rate {rate:.0f}/s: circular scan, {seg} parts per pass, mode {cm}")
                 st2 = serve(rate, args.serve_seconds, 100 + i, 0, seg)
                 per_rate[str(int(rate))][name] = {k: st2[k] for k in keys}
                 log(f"rate {rate:.0f} ({name}): {st2['qps']:.0f} q/s, p50 {st2['p50_us']:.0f} us, "
                     f"p99 {st2['p99_us']:.0f} us, {st2['mean_batch']:.1f} active per step")
-            ds.set_option(mdrq.OPT_CIRCULAR, 0)
+            ds.set_option(mdrq.OPT_CIRCULAR, 4)
     top = per_rate[str(int(rates[-1]))]
     line = _line(top["qps"], "queries/s",
                  {"workload": f"c5: {w.n_rows} rows x {w.n_dims} float32 columns resident, Poisson "

@@ -375,7 +375,11 @@ enum {
                                  while the device runs one; a request then joins up to
                                  two steps later), bit 1: an idle worker answers up to
                                  four waiting requests by separate single-query scans
-                                 when those cost less than a pass.  Default 0 */
+                                 when those cost less than a pass, bit 2: a step whose
+                                 requests are few enough that single-query scans of its
+                                 rows cost less than the shared scan (the batched path's
+                                 cost model) runs those instead, into the same slots.
+                                 Default 4 */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
 

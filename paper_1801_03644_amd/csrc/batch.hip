@@ -881,6 +881,12 @@ __global__ void __launch_bounds__(256) zero_words_kernel(uint64_t* w, uint64_t n
     w[i] = 0;
 }
 
+// p[0, n) = v.
+__global__ void __launch_bounds__(256) fill_u16_kernel(uint16_t* p, uint64_t n, uint16_t v) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 256;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
 // Zero rows rows[y] of row_words 64-bit words each (workgroup row y of the grid).
 __global__ void __launch_bounds__(256) zero_rows_kernel(uint64_t* base, uint64_t row_words, const uint32_t* rows) {
   uint64_t* w = base + static_cast<uint64_t>(rows[blockIdx.y]) * row_words;
@@ -1230,6 +1236,13 @@ hipError_t launch_zero_words(uint64_t* w, uint64_t n, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
   zero_words_kernel<<<static_cast<uint32_t>(blocks), 256, 0, stream>>>(w, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u16(uint16_t* p, uint64_t n, uint16_t v, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 4096);
+  fill_u16_kernel<<<static_cast<uint32_t>(blocks), 256, 0, stream>>>(p, n, v);
   return hipGetLastError();
 }
 

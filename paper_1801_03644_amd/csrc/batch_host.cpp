@@ -1183,6 +1183,7 @@ void free_batch(BatchWorkspace& ws) {
 namespace {
 constexpr int kCircRg = 8;                          // rows per lane: 512-row chunks
 constexpr uint64_t kCircChunkRows = 64 * kCircRg;
+constexpr int kCircPlainUnroll = 16;                // single-query steps: 4096-row tiles
 }  // namespace
 
 // Steps may be pipelined: the host builds and enqueues step k + 1 while the device runs
@@ -1228,10 +1229,15 @@ struct CircularScan {
     std::vector<std::pair<mdrq_result_t*, void*>> fin;   // finished by this step, in order
     std::vector<void*> extra;        // answered at admission before this step
     uint64_t seg_rows = 0, pairs = 0;
+    uint64_t plain_cols = 0;         // single-query steps: the requests' columns
   };
   Step steps[2];
   int next = 0;                      // buffer of the next step
   bool pipelined = false;            // else each step is waited for before the next
+  bool plain_steps = false;          // steps of few requests by single-query scans
+  uint64_t n_chunks = 0;             // 512-row chunks of a row
+  uint32_t* block_sums = nullptr;    // single-query steps: per-workgroup counts (unused)
+  uint64_t block_sums_len = 0;
 };
 
 uint64_t circular_slot_bytes(const mdrq_dataset* ds) {
@@ -1244,6 +1250,7 @@ void circular_destroy(CircularScan* c) {
   if (!c) return;
   if (c->rows) (void)hipFree(c->rows);
   if (c->tile_counts) (void)hipFree(c->tile_counts);
+  if (c->block_sums) (void)hipFree(c->block_sums);
   for (CircularScan::Step& s : c->steps) {
     if (s.h_blob) (void)hipHostFree(s.h_blob);
     if (s.d_blob) (void)hipFree(s.d_blob);
@@ -1261,11 +1268,13 @@ int circular_create(mdrq_dataset* ds, uint32_t slots, uint32_t segments, Circula
   c->ds = ds;
   c->n_slots = slots;
   c->pipelined = (ds->circular_mode & 1) != 0;
+  c->plain_steps = (ds->circular_mode & 4) != 0;
   c->n_tiles = (ds->n_rows + kTileRows - 1) / kTileRows;
   const uint64_t segs = std::max<uint64_t>(1, std::min<uint64_t>(segments, c->n_tiles));
   c->seg_tiles = std::max<uint64_t>(1, (c->n_tiles + segs - 1) / segs);
   c->n_segs = c->n_tiles ? (c->n_tiles + c->seg_tiles - 1) / c->seg_tiles : 1;
   const uint64_t n_chunks = (ds->n_rows + kCircChunkRows - 1) / kCircChunkRows;
+  c->n_chunks = n_chunks;
   c->marks_stride = align4(n_chunks);
   // The widest union whose smallest rank group (32 queries) fits LDS.
   uint32_t mu = 0;
@@ -1280,6 +1289,12 @@ int circular_create(mdrq_dataset* ds, uint32_t slots, uint32_t segments, Circula
   if (rc) return rc;
   rc = grow_device(&c->tile_counts, &c->tile_counts_len, slots * std::max<uint64_t>(1, c->n_tiles),
                    "circular scan tile counts");
+  if (rc) return rc;
+  // One count per workgroup of a single-query step (at most one workgroup per 4 tiles
+  // and resident workgroups).
+  rc = grow_device(&c->block_sums, &c->block_sums_len,
+                   static_cast<uint64_t>(scan_blocks_per_cu(kStage, kCircPlainUnroll)) * device().cus + 1,
+                   "circular scan workgroup counts");
   if (rc) return rc;
   // Per step buffer: the query tables of all groups (at most one per 32 slots), the
   // per-query arrays, two sets of output records, and the result records.
@@ -1388,11 +1403,26 @@ int circular_enqueue(CircularScan* c, CircularScan::Step& sb, hipStream_t stream
     if (m.fresh) fresh.push_back(m.slot);
     if (m.left == 1) fin_q.push_back(static_cast<uint32_t>(q));
   }
+  // Few requests: each scans the step's tiles with the single-query scan (its early
+  // break works per 4-row group, where the shared scan's needs a whole 512-row chunk to
+  // die for every query), writing the same slot row, tile counts and marks; chosen by
+  // the batched path's cost model for the step's rows.
+  const uint64_t seg_rows =
+      std::min<uint64_t>(ds->n_rows, t1 * kTileRows) - std::min<uint64_t>(ds->n_rows, t0 * kTileRows);
+  bool plain = false;
+  if (c->plain_steps) {
+    std::vector<size_t> all(nq);
+    for (uint64_t q = 0; q < nq; ++q) all[q] = q;
+    plain = plain_is_cheaper(c->items, all, n_cols, seg_rows);
+  }
   std::vector<uint32_t> table, group_first, group_table;
   uint64_t pairs = 0;
-  int rc = build_rank_tables(ds, c->items, outs, slot_of, n_cols, rank_group, rank_sw, table, group_first,
-                             group_table, &pairs);
-  if (rc) return rc;
+  int rc = MDRQ_OK;
+  if (!plain) {
+    rc = build_rank_tables(ds, c->items, outs, slot_of, n_cols, rank_group, rank_sw, table, group_first,
+                           group_table, &pairs);
+    if (rc) return rc;
+  }
   const uint32_t n_groups = static_cast<uint32_t>(group_first.size());
   group_first.push_back(static_cast<uint32_t>(nq));
   group_table.push_back(static_cast<uint32_t>(table.size()));
@@ -1465,24 +1495,65 @@ int circular_enqueue(CircularScan* c, CircularScan::Step& sb, hipStream_t stream
   fin.over_out = nullptr;
 
   const size_t lds = max_group_words * 4;
-  const int per_cu = batch_blocks_per_cu(n_cols, 4, kCircRg, 4, lds, rank_sw);
-  const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
-  const uint64_t gx = std::max<uint64_t>(1, std::min<uint64_t>(t1 - t0, resident / n_groups));
+  uint64_t gx = 1;
+  if (!plain) {
+    const int per_cu = batch_blocks_per_cu(n_cols, 4, kCircRg, 4, lds, rank_sw);
+    const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
+    gx = std::max<uint64_t>(1, std::min<uint64_t>(t1 - t0, resident / n_groups));
+  }
   MDRQ_HIP(hipMemcpyAsync(sb.d_blob, sb.h_blob, blob, hipMemcpyHostToDevice, stream), "copy query table");
   MDRQ_HIP(hipEventRecord(sb.ev0, stream), "hipEventRecord");
   if (!fresh.empty())
     MDRQ_HIP(launch_zero_rows(marks, c->marks_stride / 4, db + o_fr, static_cast<uint32_t>(fresh.size()), stream),
              "clear chunk marks");
-  if (t1 > t0)
+  if (t1 > t0 && plain) {
+    // Per request one single-query scan over tiles [t0, t1) (4096-row tiles, as the
+    // shared scan's), staging its bitmap words and tile counts straight into its slot;
+    // then its marks for the step's chunks are set (every word of them was written).
+    const uint64_t tiles = t1 - t0;
+    const uint64_t per_cu = std::min<uint64_t>(static_cast<uint64_t>(scan_blocks_per_cu(kStage, kCircPlainUnroll)),
+                                               static_cast<uint64_t>(std::max(1, ds->blocks_per_cu)));
+    const uint64_t resident = per_cu * device().cus;
+    const uint64_t want = std::min<uint64_t>((tiles + kWavesPerBlock - 1) / kWavesPerBlock, resident);
+    const uint64_t seg = (tiles + want - 1) / want;
+    const uint64_t grid = (tiles + seg - 1) / seg;
+    const uint64_t c_beg = t0 * (kTileRows / kCircChunkRows);
+    const uint64_t c_end = std::min<uint64_t>(t1 * (kTileRows / kCircChunkRows), c->n_chunks);
+    for (uint64_t q = 0; q < nq; ++q) {
+      const Plan& pl = c->items[q].plan;
+      const uint32_t slot = c->meta[q].slot;
+      ScanParams sp{};
+      sp.n_rows = ds->n_rows;
+      sp.n_tiles = t1;
+      sp.tile_begin = t0;
+      sp.n_preds = static_cast<uint32_t>(pl.preds.size());
+      sp.early_out = pl.early_out ? 1u : 0u;
+      sp.bitmap = c->rows + static_cast<uint64_t>(slot) * nw;
+      sp.capacity = nw;
+      sp.seg_tiles = seg;
+      sp.tile_counts = c->tile_counts + static_cast<uint64_t>(slot) * c->n_tiles;
+      sp.block_sums = c->block_sums;
+      sp.order = nullptr;
+      for (size_t i = 0; i < pl.preds.size(); ++i) sp.preds[i] = pl.preds[i];
+      MDRQ_HIP(launch_scan(sp, kStage, kCircPlainUnroll, static_cast<int>(grid), stream), "circular scan: single-query step");
+      MDRQ_HIP(launch_fill_u16(bp.flags + static_cast<uint64_t>(slot) * c->marks_stride + c_beg, c_end - c_beg,
+                               static_cast<uint16_t>((1u << (kCircChunkRows / 64)) - 1), stream),
+               "circular scan: chunk marks");
+    }
+  } else if (t1 > t0) {
     MDRQ_HIP(launch_batch_scan(bp, n_cols, 4, kCircRg, 4, dim3(static_cast<uint32_t>(gx), n_groups), lds, stream,
                                rank_sw),
              "circular scan launch");
+  }
   if (n_fin) MDRQ_HIP(launch_batch_finish(fin, n_fin, stream), "circular scan finish");
   MDRQ_HIP(hipEventRecord(sb.ev1, stream), "hipEventRecord");
 
   sb.inflight = true;
-  sb.seg_rows = std::min<uint64_t>(ds->n_rows, t1 * kTileRows) - std::min<uint64_t>(ds->n_rows, t0 * kTileRows);
+  sb.seg_rows = seg_rows;
   sb.pairs = pairs;
+  sb.plain_cols = 0;
+  if (plain)
+    for (const Item& it : c->items) sb.plain_cols += it.plan.preds.size();
   sb.fin.clear();
   for (uint32_t k = 0; k < n_fin; ++k) sb.fin.emplace_back(c->items[fin_q[k]].r, c->meta[fin_q[k]].tag);
   sb.extra.swap(c->answered);
@@ -1506,12 +1577,12 @@ int circular_collect(CircularScan* c, CircularScan::Step& sb, std::vector<void*>
   {
     std::lock_guard<std::mutex> lock(ds->stat_mu);
     ds->batch_lookups += sb.seg_rows * sb.pairs;
-    ds->batch_column_bytes += 4 * sb.seg_rows * sb.pairs;
+    ds->batch_column_bytes += 4 * sb.seg_rows * (sb.pairs + sb.plain_cols);
     ds->batch_scan_ms += ms;
   }
   if (st) {
     st->scans += 1;
-    st->column_bytes += 4 * sb.seg_rows * sb.pairs;
+    st->column_bytes += 4 * sb.seg_rows * (sb.pairs + sb.plain_cols);
     st->device_ms += ms;
   }
   const uint64_t nw = n_words(ds);
@@ -1601,6 +1672,31 @@ int circular_step(CircularScan* c, hipStream_t stream, std::vector<void*>& done,
     while (!c->items.empty()) circular_drop(c, c->items.size() - 1);
   }
   return rc;
+}
+
+int run_separately(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs, hipStream_t stream) {
+  for (uint32_t i = 0; i < n; ++i) {
+    Plan plan = make_plan(ds, &qs[i], &rs[i]);
+    int rc;
+    if (plan.empty || ds->n_rows == 0) {
+      if (rs[i].mode == MDRQ_OUT_AUTO) {
+        plan.mode = kIds;
+        rs[i].mode = MDRQ_OUT_IDS;
+      }
+      rc = finish_empty(ds, plan, &rs[i], stream);
+    } else {
+      // Estimated order as mdrq_query takes it: ranked on the device ahead of the scan.
+      std::unique_lock<std::mutex> est_hold;
+      if (qs[i].flags & MDRQ_Q_ORDER_ESTIMATED) {
+        rc = order_on_device(ds, &qs[i], plan, stream, est_hold);
+        if (rc) return rc;
+      }
+      rs[i].mode = plan.mode == kBitmap ? MDRQ_OUT_BITMAP : plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
+      rc = run_query(ds, plan, &rs[i], stream);
+    }
+    if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
+  }
+  return MDRQ_OK;
 }
 
 // Whether separate single-query scans answer these queries sooner than one shared scan

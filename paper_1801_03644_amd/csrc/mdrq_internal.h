@@ -43,7 +43,8 @@ struct ScanState {
 
 struct ScanParams {
   uint64_t n_rows;
-  uint64_t n_tiles;       // wave tiles of 256 * unroll rows
+  uint64_t n_tiles;       // wave tiles of 256 * unroll rows (the end of the tile range)
+  uint64_t tile_begin;    // first tile of the launch's segments (0: the whole table)
   uint32_t n_preds;
   uint32_t early_out;     // 1: rows rejected by earlier predicates are not re-read
   uint64_t* bitmap;       // kBitmap / kStage: output words
@@ -212,6 +213,8 @@ size_t batch_lds_key_bytes(int n_slots, int waves, int rg);
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream);
 // Zero n 64-bit words with a fill kernel (no memset node, so capturable).
 hipError_t launch_zero_words(uint64_t* w, uint64_t n, hipStream_t stream);
+// p[0, n) = v (16-bit words).
+hipError_t launch_fill_u16(uint16_t* p, uint64_t n, uint16_t v, hipStream_t stream);
 // Zero n_rows rows of row_words 64-bit words: row rows[i] (device array) at
 // base + rows[i] * row_words.
 hipError_t launch_zero_rows(uint64_t* base, uint64_t row_words, const uint32_t* rows, uint32_t n_rows,
@@ -456,6 +459,11 @@ int circular_admit(CircularScan* c, const mdrq_query_t* q, mdrq_result_t* r, voi
 // dropped, its tag appended to `done` and the error put in its result record.
 int circular_step(CircularScan* c, hipStream_t stream, std::vector<void*>& done, BatchRunStats* st,
                   uint64_t* active_out);
+// Answer queries one after another, each by its own single-query scan, exactly as
+// mdrq_query does (estimated order ranked on the device when asked; AUTO decided
+// exactly on the device).  Allocates nothing once the dataset's single-query buffers
+// exist.
+int run_separately(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs, hipStream_t stream);
 // Whether separate single-query scans answer these queries sooner than one shared scan
 // (the cost model of the batched path).
 bool separate_scans_cheaper(const mdrq_dataset* ds, const mdrq_query_t* qs, const mdrq_result_t* rs, uint32_t n);
@@ -565,7 +573,7 @@ struct mdrq_dataset {
   // updated per call.
   bool graph_single = false;
   bool graph_batch = false;
-  int circular_mode = 0;                 // MDRQ_OPT_CIRCULAR bits
+  int circular_mode = 4;                 // MDRQ_OPT_CIRCULAR bits
   int64_t reserve_ppm = 4000000;         // MDRQ_Q_SIZE_ESTIMATED: reserved rows per estimate (1e-6)
   std::vector<mdrq::QueryGraph> graphs;
   // Batched path.

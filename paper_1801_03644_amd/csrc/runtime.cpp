@@ -662,7 +662,7 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
       ds->reserve_ppm = value;
       return MDRQ_OK;
     case MDRQ_OPT_CIRCULAR:
-      if (value < 0 || value > 3) return fail(MDRQ_EINVAL, "circular mode must be 0..3");
+      if (value < 0 || value > 7) return fail(MDRQ_EINVAL, "circular mode must be 0..7");
       ds->circular_mode = static_cast<int>(value);
       return MDRQ_OK;
     case MDRQ_OPT_GRAPHS:

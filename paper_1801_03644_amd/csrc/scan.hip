@@ -130,8 +130,9 @@ __device__ LaneMask<U> eval_tail(const ScanParams& p, const uint32_t* ord, uint6
   return m;
 }
 
-// Workgroup b scans the contiguous segment of tiles [b*S, (b+1)*S), S = p.seg_tiles;
-// its waves take every 4th tile of the segment.
+// Workgroup b scans the contiguous segment of tiles [B + b*S, B + (b+1)*S) below
+// p.n_tiles, B = p.tile_begin, S = p.seg_tiles; its waves take every 4th tile of the
+// segment.
 template <int MODE, int U>
 __global__ void __launch_bounds__(kBlock) scan_kernel(ScanParams p) {
   constexpr uint32_t kTileRows = 256 * U;
@@ -149,7 +150,7 @@ __global__ void __launch_bounds__(kBlock) scan_kernel(ScanParams p) {
   const uint64_t n_words = (p.n_rows + 63) / 64;
   const uint64_t lim = 2 * (p.capacity < n_words ? p.capacity : n_words);  // dwords
   uint32_t* out32 = reinterpret_cast<uint32_t*>(p.bitmap);
-  const uint64_t seg_beg = static_cast<uint64_t>(blockIdx.x) * p.seg_tiles;
+  const uint64_t seg_beg = p.tile_begin + static_cast<uint64_t>(blockIdx.x) * p.seg_tiles;
   const uint64_t seg_end = seg_beg + p.seg_tiles < p.n_tiles ? seg_beg + p.seg_tiles : p.n_tiles;
   for (uint64_t tile = seg_beg + wave; tile < seg_end; tile += kWavesPerBlock) {
     const uint64_t row0 = tile * kTileRows;

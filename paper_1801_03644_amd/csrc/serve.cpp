@@ -230,11 +230,11 @@ void circular_worker_loop(mdrq_server* s, Worker* w) {
           const hipError_t e = hipStreamWaitEvent(w->stream, p->ready, 0);
           if (e != hipSuccess) rc = fail_hip(e, "serving: wait for the submitting stream");
         }
-      BatchRunStats st;
       if (rc == MDRQ_OK) {
+        // Each alone (not through the batched path, whose shared scans would grow this
+        // worker's batch workspace, unused in circular mode, by allocating).
         try {
-          rc = run_batch(s->ds, qs.data(), static_cast<uint32_t>(qs.size()), rs.data(), w->stream, &w->ws,
-                         false, &st);
+          rc = run_separately(s->ds, qs.data(), static_cast<uint32_t>(qs.size()), rs.data(), w->stream);
         } catch (...) {
           rc = fail(MDRQ_ENOMEM, "serving: host memory");
         }
@@ -247,7 +247,7 @@ void circular_worker_loop(mdrq_server* s, Worker* w) {
         if (rc && rc != MDRQ_EOVERFLOW) rs[k].status = rc;
         complete(s, take[k], rs[k], t);
       }
-      s->st.alone += st.alone;
+      s->st.alone += take.size();
       s->cv.notify_all();
       continue;
     }
@@ -420,7 +420,9 @@ int create(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, bool reserve_rows, 
     int rc = MDRQ_OK;
     if (cfg->segments) {
       // Circular scan: as many query slots as the share holds, at most max_batch.
-      const uint64_t slots = std::min<uint64_t>(cfg->max_batch, s->share / circular_slot_bytes(ds));
+      // (An empty dataset's slots take no memory.)
+      const uint64_t slot_bytes = circular_slot_bytes(ds);
+      const uint64_t slots = slot_bytes ? std::min<uint64_t>(cfg->max_batch, s->share / slot_bytes) : cfg->max_batch;
       rc = slots ? circular_create(ds, static_cast<uint32_t>(slots), cfg->segments, &w.circ)
                  : fail(MDRQ_EBUSY, "one query slot of the circular scan does not fit in one stream's share of the result budget");
     } else {

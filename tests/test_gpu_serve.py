@@ -93,13 +93,15 @@ def test_serve_results_match_oracle_and_alone():
             assert np.array_equal(ids1, payload(outs[i], answers[i], ds.n_rows))
 
 
-@pytest.mark.parametrize("segments,mode", [(1, 0), (3, 0), (8, 0), (200, 0), (3, 3), (8, 1), (8, 2)])
+@pytest.mark.parametrize("segments,mode", [(1, 0), (3, 0), (8, 0), (200, 0), (3, 3), (8, 1), (8, 2), (3, 4),
+                                            (200, 4), (8, 7)])
 def test_circular_scan_results_match_oracle_and_alone(segments, mode):
     """The circular scan: requests join the running scan at whatever part of the rows
     comes next and finish after one pass; every result is the oracle's and the query's
     alone (mixed output modes, every row, an empty interval, an unrestricted query, a
     ragged last tile; 200 parts are more than the 74 tiles: one per tile), with steps
-    pipelined or not and with or without separate scans for few requests (mode bits)."""
+    pipelined or not, with or without separate scans for few requests, and with steps of
+    few requests by single-query scans into the slots (mode bits)."""
     w, raw = c5_small(300_007)
     cols = oracle.prepare(raw)
     pool = dg.workload_queries(w, 64, sampler=w.sampler(sample_rows=1 << 16))
@@ -160,7 +162,7 @@ def test_circular_scan_slots_and_union_limit():
         _print(stats)
         check(ds, cols, qs[:8], modes[:8], outs[:8], answers, "separate")
         assert stats["scans"] == 0
-        ds.set_option(mdrq.OPT_CIRCULAR, 0)
+        ds.set_option(mdrq.OPT_CIRCULAR, 4)
         with pytest.raises(mdrq.MdrqError) as e:
             ds.serve([0], qs[:1], outputs(ds.n_rows, ["ids"]), "ids", n_streams=1,
                      budget_bytes=row, segments=4)
@@ -205,7 +207,7 @@ def test_circular_scan_edge_datasets():
          [(j, lo, hi) for j in range(3) for lo, hi in ((-0.0, 0.0), (0.0, np.inf), (-np.inf, -0.0),
                                                         (1e-45, 1.0), (-1e-45, 1e-45), (-2.5, 0.25))]),
     ]
-    for label, raw, preds in cases:
+    for (label, raw, preds), mode in [(case, m) for case in cases for m in (0, 4)]:
         cols = oracle.prepare(raw)
         qs = [dg.make_query([preds[i], preds[(3 * i + 1) % len(preds)]])
               if preds[i][0] != preds[(3 * i + 1) % len(preds)][0] else dg.make_query([preds[i]])
@@ -213,10 +215,11 @@ def test_circular_scan_edge_datasets():
         qs.append(dg.make_query([]))
         modes = [["ids", "bitmap", "count", "auto"][i % 4] for i in range(len(qs))]
         with mdrq.Dataset.from_host(raw) as ds:
+            ds.set_option(mdrq.OPT_CIRCULAR, mode)
             outs = outputs(ds.n_rows, modes)
             answers, lat, stats = ds.serve(np.zeros(len(qs), dtype=np.uint64), qs, outs, modes,
                                            max_batch=64, n_streams=1, budget_bytes=1 << 26, segments=4)
-            _print(label, stats)
+            _print(label, "mode", mode, stats)
             check(ds, cols, qs, modes, outs, answers, label)
     raw = [np.empty(0, dtype=np.float32)] * 2
     with mdrq.Dataset.from_host(raw) as ds:
