@@ -1035,7 +1035,7 @@ int run_batch(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_
         Item& it = shared[m];
         it.r->mode = it.plan.mode == kBitmap ? MDRQ_OUT_BITMAP
                      : it.plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
-        int rc = run_query(ds, it.plan, it.r, stream);
+        int rc = wsp ? run_query_on(ds, it.plan, it.r, stream, wsp->single) : run_query(ds, it.plan, it.r, stream);
         if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
       }
       if (st) st->alone += members.size();
@@ -1164,6 +1164,7 @@ int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queri
 }
 
 void free_batch(BatchWorkspace& ws) {
+  free_single(ws.single);
   if (ws.d_blob) (void)hipFree(ws.d_blob);
   if (ws.h_blob) (void)hipHostFree(ws.h_blob);
   if (ws.d_words) (void)hipFree(ws.d_words);
@@ -1674,7 +1675,8 @@ int circular_step(CircularScan* c, hipStream_t stream, std::vector<void*>& done,
   return rc;
 }
 
-int run_separately(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs, hipStream_t stream) {
+int run_separately(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs, hipStream_t stream,
+                   const SingleScratch* scratch) {
   for (uint32_t i = 0; i < n; ++i) {
     Plan plan = make_plan(ds, &qs[i], &rs[i]);
     int rc;
@@ -1692,7 +1694,7 @@ int run_separately(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_re
         if (rc) return rc;
       }
       rs[i].mode = plan.mode == kBitmap ? MDRQ_OUT_BITMAP : plan.mode == kCount ? MDRQ_OUT_COUNT : MDRQ_OUT_IDS;
-      rc = run_query(ds, plan, &rs[i], stream);
+      rc = scratch ? run_query_on(ds, plan, &rs[i], stream, *scratch) : run_query(ds, plan, &rs[i], stream);
     }
     if (rc != MDRQ_OK && rc != MDRQ_EOVERFLOW) return rc;
   }

@@ -364,7 +364,15 @@ int check_result(const mdrq_result_t* r);
 Plan make_plan(const mdrq_dataset* ds, const mdrq_query_t* q, const mdrq_result_t* r);
 uint64_t n_words(const mdrq_dataset* ds);
 int finish_empty(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream);
+struct SingleScratch;
 int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream);
+// The same on a worker's own scratch (no lock; falls back to run_query when the launch
+// shape does not fit it or the scratch is not allocated).
+int run_query_on(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream,
+                 const SingleScratch& s);
+// Allocate a worker's single-query scratch for this dataset; freed by free_single.
+int reserve_single(const mdrq_dataset* ds, SingleScratch& s);
+void free_single(SingleScratch& s);
 }  // namespace mdrq
 
 namespace mdrq {
@@ -463,7 +471,8 @@ int circular_step(CircularScan* c, hipStream_t stream, std::vector<void*>& done,
 // mdrq_query does (estimated order ranked on the device when asked; AUTO decided
 // exactly on the device).  Allocates nothing once the dataset's single-query buffers
 // exist.
-int run_separately(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs, hipStream_t stream);
+int run_separately(mdrq_dataset* ds, const mdrq_query_t* qs, uint32_t n, mdrq_result_t* rs, hipStream_t stream,
+                   const SingleScratch* scratch = nullptr);
 // Whether separate single-query scans answer these queries sooner than one shared scan
 // (the cost model of the batched path).
 bool separate_scans_cheaper(const mdrq_dataset* ds, const mdrq_query_t* qs, const mdrq_result_t* rs, uint32_t n);
@@ -482,7 +491,22 @@ int count_single_predicates(const mdrq_dataset* ds, const std::vector<mdrq_pred>
 
 namespace mdrq {
 // Device and pinned buffers of the batched path, grown on demand.
+// Single-query scratch of one serving worker: its own scan state, staged bitmap, tile
+// and workgroup counts and pinned result record, so workers' single-query scans run
+// side by side (the dataset's own scratch serialises its callers by a lock).
+struct SingleScratch {
+  ScanState* state = nullptr;        // device, zero between launches
+  uint64_t* stage_bitmap = nullptr;  // ceil(n_rows / 64) words
+  uint32_t* tile_counts = nullptr;   // one per wave tile of the smallest height
+  uint64_t tile_counts_len = 0;
+  uint32_t* block_sums = nullptr;    // one per workgroup
+  uint64_t block_sums_len = 0;
+  ScanState* host = nullptr;         // pinned, mapped: the count and AUTO's choice
+  ScanState* host_dev = nullptr;
+};
+
 struct BatchWorkspace {
+  SingleScratch single;          // serving workers: scratch of their single-query scans
   void* d_blob = nullptr;        // table words, group arrays, BatchOut records
   uint64_t d_blob_bytes = 0;
   void* h_blob = nullptr;        // pinned staging of the same

@@ -187,12 +187,15 @@ int recover_state(ScanState* state) {
   return MDRQ_OK;
 }
 
-// Device buffers of one single-query scan.
+// Device buffers of one single-query scan, and the pinned record its kernels write the
+// count and AUTO's choice into (null: the dataset's).
 struct ScanWork {
   ScanState* state;        // zero between launches
   uint64_t* stage_bitmap;  // ceil(n_rows / 64) words
   uint32_t* tile_counts;   // one per wave tile
   uint32_t* block_sums;    // one per workgroup
+  ScanState* host = nullptr;
+  ScanState* host_dev = nullptr;
 };
 
 // Launch shape of a single-query scan: grid and tiles per workgroup segment.
@@ -314,7 +317,11 @@ int scan_query(mdrq_dataset* ds, const Plan& plan, const DevPred* preds, uint32_
   p.tile_counts = w.tile_counts;
   p.block_sums = w.block_sums;
   p.state = w.state;
-  p.count_out = &ds->host_state_dev->count_out;
+  ScanState* const host_dev = w.host_dev ? w.host_dev : ds->host_state_dev;
+  const volatile ScanState* const host = w.host ? w.host : ds->host_state;
+  // The dataset's profiling events and graphs serve its own scratch only.
+  const bool profiling = ds->profiling && !w.host;
+  p.count_out = &host_dev->count_out;
   p.order = plan.order;
   for (uint32_t i = 0; i < n_preds; ++i) p.preds[i] = preds[i];
   CompactParams c{};
@@ -326,12 +333,12 @@ int scan_query(mdrq_dataset* ds, const Plan& plan, const DevPred* preds, uint32_
   c.block_sums = w.block_sums;
   c.ids = static_cast<uint32_t*>(out);
   c.capacity = plan.mode == kIds ? out_elems : 0;
-  c.count_out = &ds->host_state_dev->count_out;
+  c.count_out = &host_dev->count_out;
   c.auto_mode = plan.auto_mode ? 1u : 0u;
   c.buf_bytes = r->buf_bytes;
-  c.kind_out = &ds->host_state_dev->kind;
+  c.kind_out = &host_dev->kind;
 
-  if (ds->profiling) {
+  if (profiling) {
     if (!ds->ev0) MDRQ_HIP(hipEventCreate(&ds->ev0), "hipEventCreate");
     if (!ds->ev1) MDRQ_HIP(hipEventCreate(&ds->ev1), "hipEventCreate");
     if (!ds->ev2) MDRQ_HIP(hipEventCreate(&ds->ev2), "hipEventCreate");
@@ -340,11 +347,11 @@ int scan_query(mdrq_dataset* ds, const Plan& plan, const DevPred* preds, uint32_
   if (ds->graph_single && w.state == ds->state) {
     e = launch_query_graph(ds, p, c, kmode, grid, plan.mode == kIds, stream);
   } else {
-    if (ds->profiling) e = hipEventRecord(ds->ev0, stream);
+    if (profiling) e = hipEventRecord(ds->ev0, stream);
     if (e == hipSuccess) e = launch_scan(p, kmode, U, static_cast<int>(grid), stream);
-    if (e == hipSuccess && ds->profiling) e = hipEventRecord(ds->ev1, stream);
+    if (e == hipSuccess && profiling) e = hipEventRecord(ds->ev1, stream);
     if (e == hipSuccess && plan.mode == kIds) e = launch_compact(c, U, static_cast<int>(grid), stream);
-    if (e == hipSuccess && ds->profiling) e = hipEventRecord(ds->ev2, stream);
+    if (e == hipSuccess && profiling) e = hipEventRecord(ds->ev2, stream);
   }
   if (e != hipSuccess) {
     recover_state(w.state);
@@ -356,7 +363,7 @@ int scan_query(mdrq_dataset* ds, const Plan& plan, const DevPred* preds, uint32_
     recover_state(w.state);
     return fail_hip(e, "scan completion");
   }
-  if (ds->profiling) {
+  if (profiling) {
     float ms1 = 0.f, ms2 = 0.f;
     MDRQ_HIP(hipEventElapsedTime(&ms1, ds->ev0, ds->ev1), "hipEventElapsedTime");
     MDRQ_HIP(hipEventElapsedTime(&ms2, ds->ev0, ds->ev2), "hipEventElapsedTime");
@@ -364,7 +371,7 @@ int scan_query(mdrq_dataset* ds, const Plan& plan, const DevPred* preds, uint32_
     ds->prof_total_ms += ms2;
     ds->prof_launches += 1;
   }
-  const volatile ScanState* hs = ds->host_state;
+  const volatile ScanState* hs = host;
   const uint64_t count = hs->count_out;
   r->count = count;
   if (plan.auto_mode && hs->kind == 1) {  // AUTO chose the bitmap
@@ -420,6 +427,64 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
   const ScanWork w{ds->state, ds->stage_bitmap, ds->tile_counts, ds->block_sums};
   return scan_query(ds, plan, plan.preds.data(), static_cast<uint32_t>(plan.preds.size()), r, stream, w, out,
                     out_elems, grid, seg, host_out);
+}
+
+int run_query_on(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream, const SingleScratch& s) {
+  if (plan.empty || ds->n_rows == 0) return finish_empty(ds, plan, r, stream);
+  const bool host_out = r->mem == MDRQ_MEM_HOST && plan.mode != kCount;
+  const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(ds->unroll));
+  const uint32_t kmode = plan.mode == kIds ? kStage : plan.mode;
+  const uint64_t n_tiles = (ds->n_rows + tile - 1) / tile;
+  uint64_t grid = 0, seg = 0;
+  scan_shape(ds, kmode, n_tiles, UINT64_MAX, &grid, &seg);
+  // Host outputs need the dataset's staging; a launch wider than this scratch holds, or
+  // a scratch not allocated, takes the dataset's own path.
+  if (host_out || !s.state || grid > s.block_sums_len || n_tiles > s.tile_counts_len) return run_query(ds, plan, r, stream);
+  const uint64_t out_elems = plan.mode == kBitmap ? std::min(plan.capacity, n_words(ds)) : plan.capacity;
+  ScanWork w{s.state, s.stage_bitmap, s.tile_counts, s.block_sums};
+  w.host = s.host;
+  w.host_dev = s.host_dev;
+  return scan_query(ds, plan, plan.preds.data(), static_cast<uint32_t>(plan.preds.size()), r, stream, w, r->buf,
+                    out_elems, grid, seg, false);
+}
+
+void free_single(SingleScratch& s) {
+  if (s.state) (void)hipFree(s.state);
+  if (s.stage_bitmap) (void)hipFree(s.stage_bitmap);
+  if (s.tile_counts) (void)hipFree(s.tile_counts);
+  if (s.block_sums) (void)hipFree(s.block_sums);
+  if (s.host) (void)hipHostFree(s.host);
+  s = SingleScratch{};
+}
+
+int reserve_single(const mdrq_dataset* ds, SingleScratch& s) {
+  free_single(s);
+  const uint64_t min_tile = static_cast<uint64_t>(scan_tile_rows(1));
+  const uint64_t tiles = (ds->n_rows + min_tile - 1) / min_tile + 1;
+  const uint64_t words = (ds->n_rows + 63) / 64 + 1;
+  // Workgroups: at most every CU's occupancy limit of the widest scan kernel.
+  uint64_t grid = 1;
+  for (int u : {1, 2, 4, 8, 16})
+    for (uint32_t m : {static_cast<uint32_t>(kStage), static_cast<uint32_t>(kBitmap), static_cast<uint32_t>(kCount)})
+      grid = std::max<uint64_t>(grid, static_cast<uint64_t>(scan_blocks_per_cu(m, u)) * device().cus);
+  grid = std::max<uint64_t>(grid, ds->grid > 0 ? static_cast<uint64_t>(ds->grid) : 0);
+  auto fail_free = [&](const char* what) {
+    free_single(s);
+    return fail(MDRQ_ENOMEM, what);
+  };
+  if (hipMalloc(&s.state, sizeof(ScanState)) != hipSuccess) return fail_free("worker scan state");
+  if (hipMemset(s.state, 0, sizeof(ScanState)) != hipSuccess) return fail_free("worker scan state");
+  if (hipMalloc(&s.stage_bitmap, words * 8) != hipSuccess) return fail_free("worker stage bitmap");
+  if (hipMalloc(&s.tile_counts, tiles * 4) != hipSuccess) return fail_free("worker tile counts");
+  if (hipMalloc(&s.block_sums, grid * 4) != hipSuccess) return fail_free("worker workgroup counts");
+  s.tile_counts_len = tiles;
+  s.block_sums_len = grid;
+  if (hipHostMalloc(reinterpret_cast<void**>(&s.host), sizeof(ScanState), hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&s.host_dev), s.host, 0) != hipSuccess)
+    return fail_free("worker result record");
+  memset(s.host, 0, sizeof(ScanState));
+  return MDRQ_OK;
 }
 
 // ---------------------------------------------------------------- fixed scratch

@@ -234,7 +234,8 @@ void circular_worker_loop(mdrq_server* s, Worker* w) {
         // Each alone (not through the batched path, whose shared scans would grow this
         // worker's batch workspace, unused in circular mode, by allocating).
         try {
-          rc = run_separately(s->ds, qs.data(), static_cast<uint32_t>(qs.size()), rs.data(), w->stream);
+          rc = run_separately(s->ds, qs.data(), static_cast<uint32_t>(qs.size()), rs.data(), w->stream,
+                              &w->ws.single);
         } catch (...) {
           rc = fail(MDRQ_ENOMEM, "serving: host memory");
         }
@@ -431,6 +432,9 @@ int create(mdrq_dataset* ds, const mdrq_serve_config_t* cfg, bool reserve_rows, 
       const uint64_t bytes = std::min<uint64_t>(s->share, row * cfg->max_batch);
       rc = reserve_batch(ds, w.ws, cfg->max_batch, reserve_rows ? bytes : 0);
     }
+    // Its own single-query scratch, so workers' single-query scans do not wait for
+    // each other.
+    if (rc == MDRQ_OK) rc = reserve_single(ds, w.ws.single);
     if (rc) {
       destroy(s);
       return rc;
