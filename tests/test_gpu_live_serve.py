@@ -96,6 +96,23 @@ def test_live_server_admission_and_close():
             assert e.value.code == mdrq.EINVAL
 
 
+def test_circular_live_server_close_answers_everything():
+    """A circular-scan server closed right after a burst of submissions (none polled):
+    close waits for every pass, and every accepted request holds the oracle's answer."""
+    w, raw = c5_small(1_000_003)
+    cols = oracle.prepare(raw)
+    qs = dg.workload_queries(w, 30, sampler=w.sampler(sample_rows=1 << 16))
+    modes = ["ids", "count", "bitmap"] * 10
+    with mdrq.Dataset.from_host(raw) as ds:
+        outs = outputs(ds.n_rows, modes)
+        srv = ds.serve_open(max_batch=16, n_streams=2, budget_bytes=1 << 26, segments=6)
+        tickets = [srv.submit(q, o, m) for q, o, m in zip(qs, outs, modes)]
+        stats = srv.close()
+        res = dict(srv.results())
+        assert stats["completed"] == len(qs) and sorted(res) == sorted(tickets)
+        check(ds, cols, qs, modes, outs, [res[t] for t in tickets], "circular close")
+
+
 def test_live_server_alongside_single_queries():
     """mdrq_query on the same dataset while a server is open (other stream, no lock on
     the dataset held by the server); the dataset closes an open server first."""
