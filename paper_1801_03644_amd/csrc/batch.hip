@@ -922,18 +922,57 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t& excl, uint3
   return total;
 }
 
+constexpr uint32_t kEmitTiles = 128;   // tiles per emit chunk (two per lane of one wave)
+constexpr uint32_t kEmitStage = 2048;  // ids per wave staged in LDS (tiles of up to 4096)
+static_assert(kEmitTiles == 2 * 64, "one wave sums an emit chunk, two tiles per lane");
+
+// Inclusive prefix sum over the wave's lanes by DPP: shifts by 1, 2, 4, 8 within each
+// row of 16 lanes, then row 0's and row 2's last lane added to rows 1 and 3, then lane
+// 31 to rows 2 and 3 (lanes with no source add 0).
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xF, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xA, 0xF, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xC, 0xF, false));
+  return v;
+}
+
+__device__ __forceinline__ uint64_t finish_row(const BatchFinish& f, uint32_t q) {
+  return f.count_row ? f.count_row[q] : q;
+}
+
+// Pass 0, workgroup (x, q): one wave per emit chunk sums query q's tile counts over the
+// chunk's tiles, into the query's row of chunk sums.  Every chunk's workgroup runs at
+// once, so the count of a query no longer waits on one workgroup walking all its tiles.
+__global__ void __launch_bounds__(kFinThreads) batch_chunk_kernel(BatchFinish f) {
+  const uint32_t q = blockIdx.y;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t c = static_cast<uint64_t>(blockIdx.x) * kFinWaves + threadIdx.x / 64;
+  const uint64_t n_emit = (f.n_tiles + kEmitTiles - 1) / kEmitTiles;
+  if (c >= n_emit) return;
+  const uint64_t row = finish_row(f, q);
+  const uint32_t* counts = f.tile_counts + row * f.n_tiles;
+  const uint64_t t = c * kEmitTiles + 2 * lane;
+  const uint32_t v = (t < f.n_tiles ? counts[t] : 0u) + (t + 1 < f.n_tiles ? counts[t + 1] : 0u);
+  const uint32_t total = __builtin_amdgcn_readlane(wave_incl_sum(v), 63);
+  if (lane == 0) f.chunk_pos[row * n_emit + c] = total;
+}
+
 // Pass 1, workgroup q: the exact count of query q and its output kind (AUTO picks,
 // from the exact count, whichever of bitmap and identifiers is smaller and fits the
-// buffer); for identifier output the tile counts are replaced, in place, by their
-// exclusive prefix sums (each tile's first output position).
+// buffer); for identifier output the chunk sums are replaced, in place, by their
+// exclusive prefix sums (each chunk's first output position).
 __global__ void __launch_bounds__(kFinThreads) batch_count_kernel(BatchFinish f) {
   __shared__ uint32_t s_wave[kFinWaves];
   const uint32_t q = blockIdx.x;
   const BatchOut o = f.outs[q];
   const uint32_t tid = threadIdx.x;
-  uint32_t* counts = f.tile_counts + static_cast<uint64_t>(f.count_row ? f.count_row[q] : q) * f.n_tiles;
+  const uint64_t n_emit = (f.n_tiles + kEmitTiles - 1) / kEmitTiles;
+  uint32_t* sums = f.chunk_pos + finish_row(f, q) * n_emit;
   uint64_t part = 0;
-  for (uint64_t t = tid; t < f.n_tiles; t += kFinThreads) part += counts[t];
+  for (uint64_t c = tid; c < n_emit; c += kFinThreads) part += sums[c];
   uint32_t ignore;
   const uint64_t count = block_scan(static_cast<uint32_t>(part), ignore, s_wave);
   uint32_t kind = o.kind;
@@ -951,14 +990,14 @@ __global__ void __launch_bounds__(kFinThreads) batch_count_kernel(BatchFinish f)
   }
   if (kind != kBatchIds || count == 0 || over) return;
   uint32_t carry = 0;
-  for (uint64_t t0 = 0; t0 < f.n_tiles; t0 += kFinScan) {
-    const uint32_t nt = static_cast<uint32_t>(f.n_tiles - t0 < kFinScan ? f.n_tiles - t0 : kFinScan);
+  for (uint64_t c0 = 0; c0 < n_emit; c0 += kFinScan) {
+    const uint32_t nc = static_cast<uint32_t>(n_emit - c0 < kFinScan ? n_emit - c0 : kFinScan);
     uint32_t v[8];
     uint32_t sum = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const uint32_t t = tid * 8 + i;
-      v[i] = t < nt ? counts[t0 + t] : 0u;
+      const uint32_t c = tid * 8 + i;
+      v[i] = c < nc ? sums[c0 + c] : 0u;
       sum += v[i];
     }
     uint32_t excl;
@@ -966,32 +1005,12 @@ __global__ void __launch_bounds__(kFinThreads) batch_count_kernel(BatchFinish f)
     excl += carry;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const uint32_t t = tid * 8 + i;
-      if (t < nt) counts[t0 + t] = excl;
+      const uint32_t c = tid * 8 + i;
+      if (c < nc) sums[c0 + c] = excl;
       excl += v[i];
     }
     carry += total;
   }
-}
-
-// Pass 2, workgroup (c, q): tiles [c * kEmitTiles, (c + 1) * kEmitTiles) of query q.
-// Bitmap output copies the tiles' words; identifier output compacts each tile with a
-// hit (one wave per tile) at the tile's first output position, so the identifiers come
-// out ascending.  Nothing beyond the caller's capacity is written.
-constexpr uint32_t kEmitTiles = 128;
-constexpr uint32_t kEmitStage = 2048;   // ids per wave staged in LDS (tiles of up to 4096)
-
-// Inclusive prefix sum over the wave's lanes by DPP: shifts by 1, 2, 4, 8 within each
-// row of 16 lanes, then row 0's and row 2's last lane added to rows 1 and 3, then lane
-// 31 to rows 2 and 3 (lanes with no source add 0).
-__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
-  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xF, 0xF, false));
-  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xF, 0xF, false));
-  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xF, 0xF, false));
-  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xF, 0xF, false));
-  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xA, 0xF, false));
-  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xC, 0xF, false));
-  return v;
 }
 
 // Word w of query q's scratch row: zero unless the scan marked it as stored.  The word
@@ -1013,6 +1032,11 @@ __device__ __forceinline__ uint64_t sparse_word(const BatchFinish& f, uint32_t s
   return f.pool[at + (w & ((1u << f.chunk_shift) - 1))];
 }
 
+// Pass 2, workgroup (c, q): tiles [c * kEmitTiles, (c + 1) * kEmitTiles) of query q.
+// Bitmap output copies the tiles' words; identifier output compacts each tile with a
+// hit (one wave per tile) at the tile's first output position (its chunk's
+// position plus the tile counts before it in the chunk), so the identifiers come
+// out ascending.  Nothing beyond the caller's capacity is written.
 __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) {
   const uint32_t q = blockIdx.y;
   const uint32_t kind = f.kind_out[q];
@@ -1041,10 +1065,17 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
   // The tiles' output positions (and the end of the last) into LDS in one pass.
   __shared__ uint32_t s_pos[kEmitTiles + 1];
   __shared__ uint16_t s_stage[kFinWaves][kEmitStage];
-  const uint32_t* offs = f.tile_counts + static_cast<uint64_t>(f.count_row ? f.count_row[q] : q) * f.n_tiles;
-  for (uint64_t i = tid; i <= t_end - t_beg; i += kFinThreads) {
-    const uint64_t t = t_beg + i;
-    s_pos[i] = t < f.n_tiles ? offs[t] : static_cast<uint32_t>(count);
+  if (wave == 0) {   // two tiles per lane; lanes past the last tile add zeros
+    const uint64_t row = finish_row(f, q);
+    const uint32_t* counts = f.tile_counts + row * f.n_tiles;
+    const uint32_t base = f.chunk_pos[row * ((f.n_tiles + kEmitTiles - 1) / kEmitTiles) + blockIdx.x];
+    const uint64_t t = t_beg + 2 * lane;
+    const uint32_t a = t < t_end ? counts[t] : 0u;
+    const uint32_t b = t + 1 < t_end ? counts[t + 1] : 0u;
+    const uint32_t incl = wave_incl_sum(a + b);
+    s_pos[2 * lane] = base + incl - (a + b);
+    s_pos[2 * lane + 1] = base + incl - b;
+    if (lane == 63) s_pos[kEmitTiles] = base + incl;
   }
   __syncthreads();
   uint32_t* ids = static_cast<uint32_t*>(o.buf);
@@ -1306,19 +1337,24 @@ hipError_t batch_launches(const BatchParams& bp, const BatchFinish& f, uint32_t 
     if (e != hipSuccess) return e;
   }
   L->scan = node(fn, grid, static_cast<uint32_t>(w * 64), lds_bytes, L->scan_args);
+  const uint32_t chunks = static_cast<uint32_t>(std::max<uint64_t>(1, batch_emit_chunks(f.n_tiles)));
+  L->chunk = node(reinterpret_cast<const void*>(&batch_chunk_kernel), dim3((chunks + kFinWaves - 1) / kFinWaves, n_queries),
+                  kFinThreads, 0, L->fin_args);
   L->count = node(reinterpret_cast<const void*>(&batch_count_kernel), dim3(n_queries), kFinThreads, 0, L->fin_args);
-  const uint32_t chunks = static_cast<uint32_t>(std::max<uint64_t>(1, (f.n_tiles + kEmitTiles - 1) / kEmitTiles));
   L->emit = node(reinterpret_cast<const void*>(&batch_emit_kernel), dim3(chunks, n_queries), kFinThreads, 0,
                  L->fin_args);
   return hipSuccess;
 }
 
+uint64_t batch_emit_chunks(uint64_t n_tiles) { return (n_tiles + kEmitTiles - 1) / kEmitTiles; }
+
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream) {
   if (n_queries == 0) return hipSuccess;
+  const uint32_t chunks = static_cast<uint32_t>(batch_emit_chunks(f.n_tiles));
+  if (chunks) batch_chunk_kernel<<<dim3((chunks + kFinWaves - 1) / kFinWaves, n_queries), kFinThreads, 0, stream>>>(f);
   batch_count_kernel<<<n_queries, kFinThreads, 0, stream>>>(f);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || f.n_tiles == 0) return e;
-  const uint32_t chunks = static_cast<uint32_t>((f.n_tiles + kEmitTiles - 1) / kEmitTiles);
   batch_emit_kernel<<<dim3(chunks, n_queries), kFinThreads, 0, stream>>>(f);
   return hipGetLastError();
 }

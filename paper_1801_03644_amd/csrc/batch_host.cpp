@@ -116,6 +116,7 @@ hipError_t launch_shared_graph(BatchWorkspace& ws, const BatchParams& bp, const 
     e = hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy, ws.d_blob, ws.h_blob, blob, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->zero, &L.zero);
     if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->scan, &L.scan);
+    if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->chunk, &L.chunk);
     if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->count, &L.count);
     if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->emit, &L.emit);
     if (e == hipSuccess) return hipGraphLaunch(g->exec, stream);
@@ -138,7 +139,8 @@ hipError_t launch_shared_graph(BatchWorkspace& ws, const BatchParams& bp, const 
   if (e == hipSuccess) e = hipGraphAddKernelNode(&n.zero, n.graph, &ev, 1, &L.zero);
   if (e == hipSuccess) e = hipGraphAddKernelNode(&n.scan, n.graph, &n.zero, 1, &L.scan);
   if (e == hipSuccess) e = hipGraphAddEventRecordNode(&ev, n.graph, &n.scan, 1, ws.ev2);
-  if (e == hipSuccess) e = hipGraphAddKernelNode(&n.count, n.graph, &ev, 1, &L.count);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n.chunk, n.graph, &ev, 1, &L.chunk);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n.count, n.graph, &n.chunk, 1, &L.count);
   if (e == hipSuccess) e = hipGraphAddKernelNode(&n.emit, n.graph, &n.count, 1, &L.emit);
   if (e == hipSuccess) e = hipGraphAddEventRecordNode(&ev, n.graph, &n.emit, 1, ws.ev1);
   if (e == hipSuccess) e = hipGraphInstantiate(&n.exec, n.graph, nullptr, nullptr, 0);
@@ -532,7 +534,8 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
 
   // Device buffers (the bitmap scratch is laid out below, once the chunk size is known).
   const int rank_rg = cfg.rows_per_lane >= 8 ? 8 : 4;
-  rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, nq * n_tiles + 1, "batch tile counts");
+  rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, nq * (n_tiles + batch_emit_chunks(n_tiles)) + 1,
+                   "batch tile counts");
   if (rc) return rc;
   rc = grow_results(ws, nq);
   if (rc) return rc;
@@ -584,6 +587,7 @@ int run_shared(mdrq_dataset* ds, BatchWorkspace& ws, std::vector<Item>& items,
   fin.n_chunks = 0;
   fin.chunk_shift = 0;
   fin.tile_counts = ws.d_tile_counts;
+  fin.chunk_pos = ws.d_tile_counts + nq * n_tiles;
   fin.count_row = nullptr;
   fin.outs = reinterpret_cast<const BatchOut*>(static_cast<const uint8_t*>(ws.d_blob) + outs_off);
   fin.counts_out = static_cast<uint64_t*>(ws.h_res_dev);
@@ -1145,7 +1149,8 @@ int reserve_batch(const mdrq_dataset* ds, BatchWorkspace& ws, uint32_t max_queri
   // requests' request_scratch_bytes sum to at most scratch_bytes.
   int rc = grow_device(&ws.d_words, &ws.d_words_len, (scratch_bytes + 7) / 8 + 8, "batch bitmaps");
   if (rc) return rc;
-  rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, nq * n_tiles + 1, "batch tile counts");
+  rc = grow_device(&ws.d_tile_counts, &ws.d_tile_counts_len, nq * (n_tiles + batch_emit_chunks(n_tiles)) + 1,
+                   "batch tile counts");
   if (rc) return rc;
   rc = grow_results(ws, nq);
   if (rc) return rc;
@@ -1244,7 +1249,7 @@ struct CircularScan {
 uint64_t circular_slot_bytes(const mdrq_dataset* ds) {
   const uint64_t n_chunks = (ds->n_rows + kCircChunkRows - 1) / kCircChunkRows;
   const uint64_t n_tiles = (ds->n_rows + kTileRows - 1) / kTileRows;
-  return n_words(ds) * 8 + align4(n_chunks) * 2 + n_tiles * 4;
+  return n_words(ds) * 8 + align4(n_chunks) * 2 + (n_tiles + batch_emit_chunks(n_tiles)) * 4;
 }
 
 void circular_destroy(CircularScan* c) {
@@ -1288,7 +1293,9 @@ int circular_create(mdrq_dataset* ds, uint32_t slots, uint32_t segments, Circula
   const uint64_t nw = n_words(ds);
   int rc = grow_device(&c->rows, &c->rows_len, slots * nw + slots * c->marks_stride / 4 + 1, "circular scan rows");
   if (rc) return rc;
-  rc = grow_device(&c->tile_counts, &c->tile_counts_len, slots * std::max<uint64_t>(1, c->n_tiles),
+  // Per slot a row of tile counts, then per slot a row of emit-chunk sums.
+  rc = grow_device(&c->tile_counts, &c->tile_counts_len,
+                   slots * (std::max<uint64_t>(1, c->n_tiles) + batch_emit_chunks(c->n_tiles)),
                    "circular scan tile counts");
   if (rc) return rc;
   // One count per workgroup of a single-query step (at most one workgroup per 4 tiles
@@ -1489,6 +1496,7 @@ int circular_enqueue(CircularScan* c, CircularScan::Step& sb, hipStream_t stream
   fin.n_chunks = c->marks_stride;
   fin.chunk_shift = static_cast<uint32_t>(__builtin_ctz(static_cast<unsigned>(kCircRg)));
   fin.tile_counts = c->tile_counts;
+  fin.chunk_pos = c->tile_counts + static_cast<uint64_t>(c->n_slots) * std::max<uint64_t>(1, c->n_tiles);
   fin.count_row = db + o_fn;
   fin.outs = reinterpret_cast<const BatchOut*>(dbb + fin_off);
   fin.counts_out = static_cast<uint64_t*>(sb.h_res_dev);

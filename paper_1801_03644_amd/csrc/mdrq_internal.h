@@ -173,8 +173,10 @@ struct BatchFinish {
   uint64_t n_chunks;
   uint32_t chunk_shift;         // log2 of the bitmap words per chunk (4, 8 or 16 words)
   uint32_t pad;
-  uint32_t* tile_counts;        // [count row][tile]; becomes output positions for identifiers
-  const uint32_t* count_row;    // per query its row of tile_counts (null: its index)
+  const uint32_t* tile_counts;  // [count row][tile]
+  uint32_t* chunk_pos;          // [count row][emit chunk of 128 tiles]: the chunk's count,
+                                // then, for identifiers, its first output position
+  const uint32_t* count_row;    // per query its row of tile_counts and chunk_pos (null: its index)
   const BatchOut* outs;
   uint64_t* counts_out;         // [query] exact count
   uint32_t* kind_out;           // [query] kind used (kBatchAuto resolved)
@@ -210,6 +212,8 @@ int batch_reg_slots(int n_slots);
 constexpr bool batch_reg_uses_marks(int reg_slots) { return reg_slots <= 8; }
 // LDS bytes the LDS variant stages keys in: waves x slots x rows per lane x 64 x 4.
 size_t batch_lds_key_bytes(int n_slots, int waves, int rg);
+// Emit chunks (of 128 tiles) of a row of n_tiles tiles: the length of a chunk_pos row.
+uint64_t batch_emit_chunks(uint64_t n_tiles);
 hipError_t launch_batch_finish(const BatchFinish& f, uint32_t n_queries, hipStream_t stream);
 // Zero n 64-bit words with a fill kernel (no memset node, so capturable).
 hipError_t launch_zero_words(uint64_t* w, uint64_t n, hipStream_t stream);
@@ -229,7 +233,7 @@ struct BatchLaunches {
   void* zero_args[2];
   void* scan_args[1];
   void* fin_args[1];
-  hipKernelNodeParams zero, scan, count, emit;
+  hipKernelNodeParams zero, scan, chunk, count, emit;
 };
 hipError_t batch_launches(const BatchParams& bp, const BatchFinish& f, uint32_t n_queries, int n_slots, int waves,
                           int rg, int lds_variant, dim3 grid, size_t lds_bytes, int sw, BatchLaunches* L);
@@ -527,7 +531,7 @@ struct BatchWorkspace {
     const void* scan_fn = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy = nullptr, zero = nullptr, scan = nullptr, count = nullptr, emit = nullptr;
+    hipGraphNode_t copy = nullptr, zero = nullptr, scan = nullptr, chunk = nullptr, count = nullptr, emit = nullptr;
   };
   std::vector<Graph> graphs;
 };
