@@ -15,8 +15,8 @@
 //  * order_fused_kernel: one query's features, network and the ranking of its
 //    predicates in one workgroup, ahead of the scan on the same stream.
 //  * gemm_bf16_kernel: C = A * B with bfloat16 operands and float32 accumulation on the
-//    matrix cores (v_mfma_f32_16x16x16_bf16); one wave per 16x16 tile of C, operands
-//    read through strides so that transposed products need no copies.
+//    matrix cores (v_mfma_f32_16x16x32_bf16); four waves per 16x16 tile of C split the
+//    k steps, operands read through strides so that transposed products need no copies.
 //  * small elementwise kernels: bias + GELU (and its derivative), the masked squared
 //    loss and its gradient, column sums (bias gradients), Adam, float32 -> bfloat16.
 #include <hip/hip_bfloat16.h>
@@ -29,7 +29,8 @@
 namespace mdrq {
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short short8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // float32 -> bfloat16 bits, round to nearest, ties to even (inputs are finite).
@@ -161,7 +162,9 @@ __global__ void base_joint_kernel(float* base, uint32_t n, uint32_t d) {
 
 // C[m][n] = sum_k A(m, k) * B(k, n) (+ bias[n]) (+ add[m][n]); A(m,k) = a[m*a_m + k*a_k] and
 // B(k,n) = b[k*b_k + n*b_n] are bfloat16, out of range reads are zero.  A workgroup
-// computes a 16x16 tile of C with 16x16x16 matrix-core steps; its kGemmWaves waves take
+// computes a 16x16 tile of C with 16x16x32 matrix-core steps (lane 16 j + r holds k
+// values 8 j .. 8 j + 7 of the step for row r of A and column r of B: any k order
+// shared by both operands gives the same sum); its kGemmWaves waves take
 // every kGemmWaves-th step (wave w: steps w, w + kGemmWaves, ...), so the chains of
 // dependent operand loads are that many times shorter, and wave 0 adds the waves'
 // partial tiles in wave order.  (The products are small and the operands are read
@@ -172,13 +175,13 @@ __global__ void __launch_bounds__(64 * kGemmWaves) gemm_bf16_kernel(GemmArgs g) 
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t m0 = blockIdx.y * 16, n0 = blockIdx.x * 16;
   const uint32_t r = lane % 16;        // row of A / column of B and C held by this lane
-  const uint32_t kq = (lane / 16) * 4; // first of the 4 k values held by this lane
+  const uint32_t kq = (lane / 16) * 8; // first of the 8 k values held by this lane
   const uint32_t am = m0 + r, bn = n0 + r;
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (uint32_t k0 = 16 * wave; k0 < g.K; k0 += 16 * kGemmWaves) {
-    bf16x4 av, bv;
+  for (uint32_t k0 = 32 * wave; k0 < g.K; k0 += 32 * kGemmWaves) {
+    short8 av, bv;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 8; ++i) {
       const uint32_t k = k0 + kq + i;
       av[i] = (am < g.M && k < g.K)
                   ? static_cast<short>(g.a[static_cast<uint64_t>(am) * g.a_m + static_cast<uint64_t>(k) * g.a_k])
@@ -187,7 +190,8 @@ __global__ void __launch_bounds__(64 * kGemmWaves) gemm_bf16_kernel(GemmArgs g) 
                   ? static_cast<short>(g.b[static_cast<uint64_t>(k) * g.b_k + static_cast<uint64_t>(bn) * g.b_n])
                   : static_cast<short>(0);
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                  acc, 0, 0, 0);
   }
   if (wave > 0) part[wave - 1][lane] = acc;
   __syncthreads();
@@ -201,7 +205,7 @@ __global__ void __launch_bounds__(64 * kGemmWaves) gemm_bf16_kernel(GemmArgs g) 
   // acc[i] holds C[m0 + 4*(lane/16) + i][n0 + lane%16].
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const uint32_t m = m0 + kq + i, n = n0 + r;
+    const uint32_t m = m0 + 4 * (lane / 16) + i, n = n0 + r;
     if (m < g.M && n < g.N) {
       const uint64_t o = static_cast<uint64_t>(m) * g.c_ld + n;
       float v = acc[i] + (g.bias ? g.bias[n] : 0.0f);
