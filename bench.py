@@ -197,8 +197,9 @@ def main():
     ap.add_argument("--graphs", type=int, default=None,
                     help="MDRQ_OPT_GRAPHS: bit 0 single queries, bit 1 shared scans replayed from graphs")
     ap.add_argument("--counters", type=int, default=0, metavar="Q",
-                    help="counter-collection run: Q queries once, plus a plain copy of known "
-                         "size for calibration; prints no bench line")
+                    help="counter-collection run: Q queries once (c3: three shared scans of Q "
+                         "queries with ids output), plus a plain copy of known size for "
+                         "calibration; prints no bench line")
     ap.add_argument("--summarize", metavar="DIR", default=None,
                     help="summarise rocprofv3 CSV output found under DIR into profiles/")
     ap.add_argument("--train-queries", type=int, default=200_000, help="c4: training queries")
@@ -235,6 +236,8 @@ def main():
 
         line = {"c3": bench_extra.batched, "c4": bench_extra.learned,
                 "c5": bench_extra.serving, "syntuni": bench_extra.paper}[args.workload](args)
+        if line is None:   # a counter-collection run
+            return
         line["device"] = device_info()
         print(json.dumps(line), flush=True)
         return

@@ -161,6 +161,33 @@ def _cpu(raw, queries, n_rows, budget):
     return bench.cpu_baseline(raw, queries, n_rows, budget)
 
 
+def _batch_counters_run(ds, queries, stream):
+    """Counter-collection run of one shared scan: the queries' exact counts (a count-only
+    batch), then three batches with ids output through the rank kernel with a fixed launch
+    shape (8 waves, 512-row chunks, groups of 128), then a plain copy of known size for the
+    byte counters' calibration.  Prints no bench line."""
+    import torch
+
+    from paper_1801_03644_amd import mdrq
+
+    counts = _exact_counts(ds, queries)
+    for o, v in ((mdrq.OPT_AUTOTUNE, 0), (mdrq.OPT_BATCH_VARIANT, 5), (mdrq.OPT_BATCH_WAVES, 8),
+                 (mdrq.OPT_BATCH_ROWS, 8)):
+        ds.set_option(o, v)
+    run = Runner(ds, queries, counts, stream)
+    for _ in range(3):
+        run.batch(0, 0, len(queries), len(queries))
+    run.check_complete()
+    src = torch.empty((1 << 30) // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"counters run done: {len(queries)} queries, {int(counts.sum())} ids per batch; "
+        f"copy of {1 << 30} bytes")
+    return None
+
+
 def batched(args):
     """c3: batches of 64, 256 and 1024 queries answered by one shared scan each, against
     the same queries one at a time through mdrq_query; ids output in both."""
@@ -174,6 +201,8 @@ def batched(args):
     n_q = 1024
     queries = dg.workload_queries(w, n_q)
     ks = np.array([len(q[0]) for q in queries])
+    if args.counters:
+        return _batch_counters_run(ds, queries[:args.counters], stream)
     run = Runner(ds, queries, _exact_counts(ds, queries), stream)
     reps = max(1, args.steps)
     res = {}
