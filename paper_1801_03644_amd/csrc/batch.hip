@@ -1080,25 +1080,44 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
   __syncthreads();
   uint32_t* ids = static_cast<uint32_t*>(o.buf);
   const uint64_t capacity = o.buf_bytes / 4;
-  auto hit = [&](uint64_t t) {
-    const uint32_t i = static_cast<uint32_t>(t - t_beg);
-    return s_pos[i + 1] != s_pos[i] && s_pos[i] < capacity;
+  // Tiles are taken per wave, so a tile's position and whether it has a hit inside the
+  // caller's capacity are the same for all its lanes: kept in scalar registers.
+  auto pos_of = [&](uint64_t t) {
+    return static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(s_pos[static_cast<uint32_t>(t - t_beg)]));
   };
-  // One tile = 64 words = one wave-wide load; the wave's next tile is loaded while the
-  // current one is written.
+  auto hit = [&](uint64_t t) {
+    const uint32_t a = pos_of(t);
+    return pos_of(t + 1) != a && a < capacity;
+  };
+  // One tile = 64 words = one wave-wide load.  A word and its chunk's mark are loaded
+  // as they are and combined only when the tile is written, so the loads of the wave's
+  // next tile stay in flight while the current one is written.  (A chunk holds
+  // 2^chunk_shift words and a tile 64, so a lane's bit in its chunk's mark is its lane
+  // index modulo 2^chunk_shift.)
+  const uint32_t mark_bit = lane & ((1u << f.chunk_shift) - 1);
+  uint64_t next_word = 0;
+  uint32_t next_mark = ~0u;   // all bits: no marks, a sparse query's word, or past the end
   auto load = [&](uint64_t t) {
     const uint64_t w = t * 64 + lane;
-    if (w >= f.n_words) return uint64_t{0};
-    return sparse ? sparse_word(f, o.out_index, w) : scratch_word(f, words, o.out_index, w);
+    next_word = 0;
+    next_mark = ~0u;
+    if (w >= f.n_words) return;
+    if (sparse) {
+      next_word = sparse_word(f, o.out_index, w);
+    } else {
+      next_word = words[w];
+      if (f.flags) next_mark = f.flags[static_cast<uint64_t>(o.out_index) * f.n_chunks + (w >> f.chunk_shift)];
+    }
   };
-  uint64_t t = t_beg + wave;
-  uint64_t next = t < t_end && hit(t) ? load(t) : 0;
+  uint64_t t = t_beg + static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(wave));
+  if (t < t_end && hit(t)) load(t);
   for (; t < t_end; t += kFinWaves) {
-    const uint64_t word = next;
+    const bool use = hit(t);
+    const uint64_t word = (next_mark >> mark_bit) & 1u ? next_word : 0;
     const uint64_t tn = t + kFinWaves;
-    next = tn < t_end && hit(tn) ? load(tn) : 0;
-    if (!hit(t)) continue;
-    const uint64_t beg = s_pos[t - t_beg];
+    if (tn < t_end && hit(tn)) load(tn);
+    if (!use) continue;
+    const uint64_t beg = pos_of(t);
     const uint64_t w = t * 64 + lane;
     const uint32_t k = __popcll(word);
     const uint32_t incl = wave_incl_sum(k);
