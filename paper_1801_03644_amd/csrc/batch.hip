@@ -924,6 +924,9 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t& excl, uint3
 
 constexpr uint32_t kEmitTiles = 128;   // tiles per emit chunk (two per lane of one wave)
 constexpr uint32_t kEmitStage = 2048;  // ids per wave staged in LDS (tiles of up to 4096)
+// Tiles of at most this many ids skip the staging: their lanes hold one id or a few, so
+// the direct writes of one step already fall on consecutive positions.
+constexpr uint32_t kEmitDirect = 64;
 static_assert(kEmitTiles == 2 * 64, "one wave sums an emit chunk, two tiles per lane");
 
 // Inclusive prefix sum over the wave's lanes by DPP: shifts by 1, 2, 4, 8 within each
@@ -1058,8 +1061,21 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
     const uint64_t lim = cap < f.n_words ? cap : f.n_words;
     const uint64_t w_end = t_end * 64 < lim ? t_end * 64 : lim;
     uint64_t* dst = static_cast<uint64_t*>(o.buf);
-    for (uint64_t i = t_beg * 64 + tid; i < w_end; i += kFinThreads)
-      dst[i] = sparse ? sparse_word(f, o.out_index, i) : scratch_word(f, words, o.out_index, i);
+    // Four words per lane loaded before any is stored, so that a store's completion (which
+    // the next load's wait also covers) is not waited for once per word.
+    for (uint64_t i0 = t_beg * 64 + tid; i0 < w_end; i0 += 4 * kFinThreads) {
+      uint64_t v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint64_t i = i0 + static_cast<uint64_t>(j) * kFinThreads;
+        v[j] = i >= w_end ? 0 : sparse ? sparse_word(f, o.out_index, i) : scratch_word(f, words, o.out_index, i);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint64_t i = i0 + static_cast<uint64_t>(j) * kFinThreads;
+        if (i < w_end) dst[i] = v[j];
+      }
+    }
     return;
   }
   // The tiles' output positions (and the end of the last) into LDS in one pass.
@@ -1124,7 +1140,7 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
     const uint32_t total = __builtin_amdgcn_readlane(incl, 63);   // ids of the tile
     uint64_t bits = word;
     const uint32_t row = static_cast<uint32_t>(w * 64);
-    if (total <= kEmitStage) {
+    if (total > kEmitDirect && total <= kEmitStage) {
       // Each lane's rows (16-bit offsets in the tile) into the wave's LDS buffer at
       // their places in the tile's output, then out to HBM in consecutive 64-lane runs.
       uint16_t* buf = s_stage[wave];
@@ -1154,7 +1170,7 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {  // a dense tile: each lane writes its ids directly
+    } else {  // a dense or a sparse tile: each lane writes its ids directly
       uint64_t r = beg + incl - k;
       while (bits) {
         const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(bits));
