@@ -123,6 +123,41 @@ def test_batch_sizes_and_ragged_tails(n):
         ds.set_option(mdrq.OPT_RANK_BUCKETS, 0)
 
 
+@pytest.mark.parametrize("n", [128 * 4096 + 1, 5 * 128 * 4096, 5 * 128 * 4096 - 4095])
+def test_finish_chunk_boundaries(n):
+    """The finish sums tile counts per chunk of 128 tiles (a chunk per wave, four per
+    workgroup) and emits each chunk's tiles from its position: a last chunk of one tile,
+    chunk counts that leave waves of the sum pass idle, a ragged last tile.  Interval
+    widths give tiles of thousands of ids (direct writes), of hundreds (staged in LDS)
+    and of a few (direct writes again); capped outputs stop inside each kind."""
+    raw = [dg.column(31, j, dg.uniform(), n) for j in range(4)]
+    cols = oracle.prepare(raw)
+    rng = np.random.default_rng(n % 1000)
+    qs, caps = [], []
+    for wdt in (0.95, 0.9, 0.3, 0.1, 0.02, 0.004, 0.0005):
+        for k in (1, 2):
+            dims = rng.permutation(4)[:k]
+            preds = []
+            for j in dims:
+                lo = float(rng.uniform(0, 1 - wdt ** (1.0 / k)))
+                preds.append((int(j), lo, lo + wdt ** (1.0 / k)))
+            qs.append(dg.make_query(preds))
+    counts = [oracle.count(cols, q) for q in qs]
+    modes = (["ids", "auto", "bitmap", "count"] * 4)[:len(qs)]
+    caps = [None] * len(qs)
+    # ids outputs capped inside a dense tile, a staged tile and a sparse tile
+    extra = [(0, 4096 * 3 + 17), (6, 999), (10, 31)]
+    for i, cap in extra:
+        qs.append(qs[i])
+        modes.append("ids")
+        caps.append(min(cap, max(1, counts[i] - 1)))
+    with mdrq.Dataset.from_host(raw) as ds:
+        for variant in (0, 5):
+            ds.set_option(mdrq.OPT_BATCH_VARIANT, variant)
+            _print("finish chunks", n, "variant", variant, "queries", len(qs))
+            check_batch(ds, cols, qs, modes, f"n={n} variant={variant}", caps=caps)
+
+
 def test_batch_special_values_degenerate_and_invalid():
     vals = np.array([-np.inf, -1.0, -0.0, 0.0, 1e-45, 1.1754944e-38, 0.5, 1.0, np.inf],
                     dtype=np.float32)
