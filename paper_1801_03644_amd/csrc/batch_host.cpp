@@ -1218,6 +1218,7 @@ void free_batch(BatchWorkspace& ws) {
 
 namespace {
 constexpr int kCircRg = 8;                          // rows per lane: 512-row chunks
+constexpr int kCircWaves = 8;                       // waves per workgroup of a shared step
 constexpr uint64_t kCircChunkRows = 64 * kCircRg;
 constexpr int kCircPlainUnroll = 16;                // single-query steps: 4096-row tiles
 }  // namespace
@@ -1536,7 +1537,7 @@ int circular_enqueue(CircularScan* c, CircularScan::Step& sb, hipStream_t stream
   const size_t lds = max_group_words * 4;
   uint64_t gx = 1;
   if (!plain) {
-    const int per_cu = batch_blocks_per_cu(n_cols, 4, kCircRg, 4, lds, rank_sw);
+    const int per_cu = batch_blocks_per_cu(n_cols, kCircWaves, kCircRg, 4, lds, rank_sw);
     const uint64_t resident = static_cast<uint64_t>(per_cu) * device().cus;
     gx = std::max<uint64_t>(1, std::min<uint64_t>(t1 - t0, resident / n_groups));
   }
@@ -1580,7 +1581,7 @@ int circular_enqueue(CircularScan* c, CircularScan::Step& sb, hipStream_t stream
                "circular scan: chunk marks");
     }
   } else if (t1 > t0) {
-    MDRQ_HIP(launch_batch_scan(bp, n_cols, 4, kCircRg, 4, dim3(static_cast<uint32_t>(gx), n_groups), lds, stream,
+    MDRQ_HIP(launch_batch_scan(bp, n_cols, kCircWaves, kCircRg, 4, dim3(static_cast<uint32_t>(gx), n_groups), lds, stream,
                                rank_sw),
              "circular scan launch");
   }
