@@ -1035,6 +1035,15 @@ __device__ __forceinline__ uint64_t sparse_word(const BatchFinish& f, uint32_t s
   return f.pool[at + (w & ((1u << f.chunk_shift) - 1))];
 }
 
+// The caller's output buffer as global memory.  Its address comes from a table in memory,
+// where the compiler cannot tell its address space; a generic (flat) store would also
+// count against the wave's LDS wait counter, so every LDS read after it would wait for the
+// store to complete.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* global_out(void* p) {
+  return reinterpret_cast<__attribute__((address_space(1))) T*>(reinterpret_cast<uintptr_t>(p));
+}
+
 // Pass 2, workgroup (c, q): tiles [c * kEmitTiles, (c + 1) * kEmitTiles) of query q.
 // Bitmap output copies the tiles' words; identifier output compacts each tile with a
 // hit (one wave per tile) at the tile's first output position (its chunk's
@@ -1060,7 +1069,7 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
     const uint64_t cap = o.buf_bytes / 8;
     const uint64_t lim = cap < f.n_words ? cap : f.n_words;
     const uint64_t w_end = t_end * 64 < lim ? t_end * 64 : lim;
-    uint64_t* dst = static_cast<uint64_t*>(o.buf);
+    auto* dst = global_out<uint64_t>(o.buf);
     // Four words per lane loaded before any is stored, so that a store's completion (which
     // the next load's wait also covers) is not waited for once per word.
     for (uint64_t i0 = t_beg * 64 + tid; i0 < w_end; i0 += 4 * kFinThreads) {
@@ -1094,7 +1103,7 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
     if (lane == 63) s_pos[kEmitTiles] = base + incl;
   }
   __syncthreads();
-  uint32_t* ids = static_cast<uint32_t*>(o.buf);
+  auto* ids = global_out<uint32_t>(o.buf);
   const uint64_t capacity = o.buf_bytes / 4;
   // Tiles are taken per wave, so a tile's position and whether it has a hit inside the
   // caller's capacity are the same for all its lanes: kept in scalar registers.
@@ -1155,11 +1164,11 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (uint32_t i0 = 0; i0 < total; i0 += 256) {   // four runs' reads in flight
-        uint32_t v[4];
+        uint32_t v[4];   // read unconditionally (index 0 past the end), so the reads go together
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const uint32_t i = i0 + 64 * j + lane;
-          v[j] = i < total ? tile_row + buf[i] : 0u;
+          v[j] = tile_row + buf[i < total ? i : 0u];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
