@@ -3,6 +3,8 @@
 // autotuner, and completion.
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
+#include <functional>
 #include <system_error>
 #include <thread>
 #include <cmath>
@@ -211,6 +213,96 @@ size_t rank_lds_room() { return device().lds > 4096 ? device().lds - 4096 : 0; }
 // The groups' tables are independent: each is built into its own vector, on several
 // host threads when there are 24 or more slot tables (about 10 us each), then appended
 // in group order.
+// Host threads that build rank tables: started on first use and kept until the process
+// ends (starting threads for every batch cost a few hundred microseconds).  One caller
+// at a time uses them, a concurrent caller builds alone; the calling thread always takes
+// part, so work finishes even where no helper thread could be started.
+class TablePool {
+ public:
+  static TablePool& get() {
+    static TablePool pool;
+    return pool;
+  }
+  // f(i) for every i in [0, n); false if a call threw (the calls after it are skipped).
+  bool run(size_t n, const std::function<void(size_t)>& f) {
+    std::unique_lock<std::mutex> use(use_mu_, std::try_to_lock);
+    if (!use.owns_lock() || helpers_.empty() || n < 2) {
+      try {
+        for (size_t i = 0; i < n; ++i) f(i);
+      } catch (...) {
+        return false;
+      }
+      return true;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      f_ = &f;
+      n_ = n;
+      next_ = 0;
+      failed_ = false;
+      busy_ = helpers_.size();
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> lk(mu_);
+    done_cv_.wait(lk, [&] { return busy_ == 0; });
+    f_ = nullptr;
+    return !failed_;
+  }
+
+ private:
+  TablePool() {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned n = std::min(7u, hw - 1);
+    for (unsigned t = 0; t < n; ++t) {
+      try {
+        helpers_.emplace_back([this] { loop(); });
+      } catch (...) {
+        break;
+      }
+    }
+  }
+  ~TablePool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (std::thread& t : helpers_) t.join();
+  }
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      std::unique_lock<std::mutex> lk(mu_);
+      cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+      if (stop_) return;
+      seen = gen_;
+      lk.unlock();
+      work();
+      lk.lock();
+      if (--busy_ == 0) done_cv_.notify_all();
+    }
+  }
+  void work() {
+    try {
+      for (size_t i = next_++; i < n_ && !failed_; i = next_++) (*f_)(i);
+    } catch (...) {
+      failed_ = true;
+    }
+  }
+  std::mutex use_mu_, mu_;
+  std::condition_variable cv_, done_cv_;
+  std::vector<std::thread> helpers_;
+  const std::function<void(size_t)>* f_ = nullptr;
+  size_t n_ = 0;
+  std::atomic<size_t> next_{0};
+  std::atomic<bool> failed_{false};
+  size_t busy_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
 int build_rank_tables(const mdrq_dataset* ds, const std::vector<Item>& items, const std::vector<BatchOut>& outs,
                       const std::vector<int>& slot_of, int n_slots, uint64_t rank_group, int rank_sw,
                       std::vector<uint32_t>& table, std::vector<uint32_t>& group_first,
@@ -246,6 +338,7 @@ int build_rank_tables(const mdrq_dataset* ds, const std::vector<Item>& items, co
     std::vector<RankBuckets> buckets_of(n_slots);
     for (int sl = 0; sl < n_slots; ++sl) {
       std::vector<uint32_t>& ends = ends_of[sl];
+      ends.reserve(2 * static_cast<size_t>(gq));
       for (const KeyInterval& k : iv[sl])
         if (k.has) {
           ends.push_back(k.klo);
@@ -265,6 +358,13 @@ int build_rank_tables(const mdrq_dataset* ds, const std::vector<Item>& items, co
       return words;
     };
     if (choose(kRankBuckets) + hq > kRankLdsWords) choose(256);
+    {
+      uint64_t words = table.size();
+      for (int sl = 0; sl < n_slots; ++sl)
+        if (!ends_of[sl].empty())
+          words += slot_table_words(static_cast<uint32_t>(ends_of[sl].size()), buckets_of[sl], rank_sw) + 4;
+      table.reserve(words);
+    }
     uint64_t used = 0;
     for (int sl = 0; sl < n_slots; ++sl) used += ends_of[sl].empty() ? 0 : 1;
     used_pairs += used;
@@ -286,31 +386,21 @@ int build_rank_tables(const mdrq_dataset* ds, const std::vector<Item>& items, co
     }
   };
   const size_t slot_tables = rank_q0.size() * static_cast<size_t>(n_slots);
-  const unsigned hw_threads = std::max(1u, std::thread::hardware_concurrency());
-  const size_t n_threads = slot_tables >= 24 ? std::min<size_t>({rank_q0.size(), 8, hw_threads}) : 1;
-  {
-    // The calling thread takes part; if a helper thread cannot be started, the ones
-    // that did start and the calling thread share the groups.  An exception inside a
-    // builder (an allocation failure) is recorded and reported after the join.
-    std::atomic<size_t> next{0};
-    std::atomic<bool> failed{false};
-    auto work = [&]() {
-      try {
-        for (size_t gi = next++; gi < rank_q0.size() && !failed; gi = next++) build_rank_group(gi);
-      } catch (...) {
-        failed = true;
-      }
-    };
-    std::vector<std::thread> pool;
+  bool built = true;
+  if (slot_tables >= 24) {
+    built = TablePool::get().run(rank_q0.size(), build_rank_group);
+  } else {
     try {
-      for (size_t t = 1; t < n_threads; ++t) pool.emplace_back(work);
+      for (size_t gi = 0; gi < rank_q0.size(); ++gi) build_rank_group(gi);
     } catch (...) {
+      built = false;
     }
-    work();
-    for (std::thread& th : pool) th.join();
-    if (failed) return fail(MDRQ_ENOMEM, "shared scan: host memory for the rank tables");
   }
+  if (!built) return fail(MDRQ_ENOMEM, "shared scan: host memory for the rank tables");
   if (pairs_out) *pairs_out = used_pairs.load();
+  size_t total = table.size();
+  for (const std::vector<uint32_t>& t : rank_tables) total += t.size();
+  table.reserve(total);
   for (size_t gi = 0; gi < rank_q0.size(); ++gi) {
     group_first.push_back(static_cast<uint32_t>(rank_q0[gi]));
     group_table.push_back(static_cast<uint32_t>(table.size()));

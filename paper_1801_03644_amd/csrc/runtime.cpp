@@ -133,6 +133,8 @@ int check_result(const mdrq_result_t* r) {
 Plan make_plan(const mdrq_dataset* ds, const mdrq_query_t* q, const mdrq_result_t* r) {
   Plan plan;
   const float inf = std::numeric_limits<float>::infinity();
+  plan.preds.reserve(q->n_preds);
+  plan.dims.reserve(q->n_preds);
   for (uint32_t i = 0; i < q->n_preds; ++i) {
     const mdrq_pred& p = q->preds[i];
     if (p.lo > p.hi) plan.empty = true;
