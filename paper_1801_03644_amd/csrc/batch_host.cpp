@@ -254,7 +254,7 @@ class TablePool {
  private:
   TablePool() {
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const unsigned n = std::min(7u, hw - 1);
+    const unsigned n = std::min(15u, hw - 1);
     for (unsigned t = 0; t < n; ++t) {
       try {
         helpers_.emplace_back([this] { loop(); });
@@ -347,12 +347,19 @@ int build_rank_tables(const mdrq_dataset* ds, const std::vector<Item>& items, co
       std::sort(ends.begin(), ends.end());
       ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
     }
+    // A slot's candidate maps for a lower bucket limit are the same list when no
+    // candidate had more buckets than that limit (few ends: the walk starts at about 4
+    // buckets per end), so they are found again only where one had.
+    std::vector<std::vector<RankBuckets>> cands(n_slots);
     auto choose = [&](uint32_t max_nb) {
       uint64_t words = hq + 4 * static_cast<uint64_t>(n_slots);
       for (int sl = 0; sl < n_slots; ++sl) {
         const uint32_t M = static_cast<uint32_t>(ends_of[sl].size());
         if (M == 0) continue;
-        buckets_of[sl] = pick_buckets(bucket_candidates(ends_of[sl], ds->rank_buckets, max_nb), max_nb);
+        bool again = cands[sl].empty();
+        for (const RankBuckets& m : cands[sl]) again |= m.nb > max_nb;
+        if (again) cands[sl] = bucket_candidates(ends_of[sl], ds->rank_buckets, max_nb);
+        buckets_of[sl] = pick_buckets(cands[sl], max_nb);
         words += slot_table_words(M, buckets_of[sl], rank_sw);
       }
       return words;
@@ -928,6 +935,7 @@ std::vector<std::vector<size_t>> plan_groups(const std::vector<Item>& items, uin
   std::vector<size_t> narrow_items, wide_items;
   for (size_t i = 0; i < items.size(); ++i)
     (items[i].plan.dims.size() <= static_cast<size_t>(kMaxSlots) ? narrow_items : wide_items).push_back(i);
+  if (narrow_items.empty()) return wide;   // the split grouping would be the same
   std::vector<std::vector<size_t>> split = group_by_columns(items, narrow_items, n_dims, kMaxSlots);
   for (auto& g : group_by_columns(items, wide_items, n_dims, max_union())) split.push_back(std::move(g));
   auto cost = [&](const std::vector<std::vector<size_t>>& groups) {
