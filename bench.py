@@ -325,7 +325,8 @@ def main():
 
     ks = np.array([len(q[0]) for q in queries])
     n_words = (w.n_rows + 63) // 64
-    n_tiles = (w.n_rows + 2047) // 2048           # wave tiles of 2048 rows (default)
+    unroll = ds.get_option(mdrq.OPT_UNROLL)      # tile height in use (x 256 rows)
+    n_tiles = (w.n_rows + 256 * unroll - 1) // (256 * unroll)   # wave tiles
     # Scan kernel writes per launch: the staged result bitmap (1 bit per row) and the
     # per-tile counts.
     write_bytes = 8 * n_words + 4 * n_tiles
@@ -370,7 +371,7 @@ def main():
                    "n_rows": w.n_rows, "n_dims": w.n_dims, "queries_per_step": n_q,
                    "mean_queried_dims": float(ks.mean()), "mean_selectivity": float(sel.mean()),
                    "early_out": not args.no_earlyout, "graphs": args.graphs or 0,
-                   "unroll": args.unroll or 8, "blocks_per_cu": args.blocks_per_cu or 3,
+                   "unroll": unroll, "blocks_per_cu": args.blocks_per_cu or 3,
                    "data_seed": w.data_seed,
                    "query_seed": w.query_seed},
         "queries_per_s": total_q / elapsed,
@@ -380,7 +381,7 @@ def main():
         "p99_us": float(np.percentile(lat_us, 99)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "scan_kernel<stage,8>", "avg_kernel_us": avg_scan_s * 1e6,
+                     "kernel": f"scan_kernel<stage,{unroll}>", "avg_kernel_us": avg_scan_s * 1e6,
                      "algorithmic_bytes_per_launch": float(scan_bytes_q.mean()),
                      "probe_gbps": probe_gbps, "frac_of_probe": achieved / probe_gbps,
                      "logical_bytes_per_launch": float(dense_bytes_q.mean()),

@@ -333,7 +333,9 @@ int mdrq_get_sizing_profile(const mdrq_dataset* ds, uint64_t* sized, uint64_t* r
 /* Tuning options of a dataset's scans (results never depend on them). */
 enum {
   MDRQ_OPT_UNROLL = 1,  /* 16-byte loads per lane per column in one tile: 1, 2, 4, 8
-                           or 16 (one wave scans 256 x value rows per tile); default 8 */
+                           or 16 (one wave scans 256 x value rows per tile); 0 (default):
+                           by the table's rows per CU, 2 below 6144, 4 below 65536,
+                           else 8 */
   MDRQ_OPT_GRID = 2,    /* workgroups per scan launch; 0 = MDRQ_OPT_BLOCKS_PER_CU per CU */
   MDRQ_OPT_BLOCKS_PER_CU = 3, /* default launch width: workgroups per CU, 1..8
                                  (capped by occupancy); default 3 */
@@ -382,6 +384,9 @@ enum {
                                  Default 4 */
 };
 int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value);
+/* The value an option takes now into *value (MDRQ_OPT_UNROLL: the tile height in use,
+ * also when chosen by size).  MDRQ_EINVAL for an unknown option or a NULL argument. */
+int mdrq_get_option(const mdrq_dataset* ds, uint32_t option, int64_t* value);
 
 /* Streaming-read ceiling: read the listed columns in full (k entries of dims[],
  * no predicate, no output) with the scan kernels' launch shape, `iters` times, and

@@ -367,6 +367,9 @@ int check_query(const mdrq_dataset* ds, const mdrq_query_t* q);
 int check_result(const mdrq_result_t* r);
 Plan make_plan(const mdrq_dataset* ds, const mdrq_query_t* q, const mdrq_result_t* r);
 uint64_t n_words(const mdrq_dataset* ds);
+// Tile height of the dataset's single-query scans: MDRQ_OPT_UNROLL, else chosen from
+// its rows per CU.
+int scan_unroll(const mdrq_dataset* ds);
 int finish_empty(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream);
 struct SingleScratch;
 int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream);
@@ -595,7 +598,7 @@ struct mdrq_dataset {
   uint64_t prof_launches = 0;
   double prof_scan_ms = 0.0;
   double prof_total_ms = 0.0;
-  int unroll = 8;                        // tile height of single-query scans (x 256 rows)
+  int unroll = 0;                        // tile height of single-query scans (x 256 rows); 0: by size
   // Launch sequences replayed from graphs (MDRQ_OPT_GRAPHS): single queries (one graph
   // per launch shape) and shared scans (one per scan kernel and workspace), arguments
   // updated per call.

@@ -151,6 +151,15 @@ Plan make_plan(const mdrq_dataset* ds, const mdrq_query_t* q, const mdrq_result_
 
 uint64_t n_words(const mdrq_dataset* ds) { return (ds->n_rows + 63) / 64; }
 
+// Small tables leave most CUs idle with tall tiles, and short tiles cost more per row:
+// measured over 2.5e5 .. 1.6e7 rows of three columns, two 16-byte loads per lane were
+// fastest below about 6k rows per CU, four below 64k, eight above (within 2% at 64k).
+int scan_unroll(const mdrq_dataset* ds) {
+  if (ds->unroll) return ds->unroll;
+  const uint64_t per_cu = ds->n_rows / std::max<uint64_t>(1, device().cus);
+  return per_cu < 6144 ? 2 : per_cu < 65536 ? 4 : 8;
+}
+
 // Result of an empty answer (no launch): zero the bitmap words the buffer holds.
 int finish_empty(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream) {
   r->count = 0;
@@ -203,7 +212,7 @@ struct ScanWork {
 // Launch shape of a single-query scan: grid and tiles per workgroup segment.
 void scan_shape(const mdrq_dataset* ds, uint32_t kmode, uint64_t n_tiles, uint64_t max_grid, uint64_t* grid_out,
                 uint64_t* seg_out) {
-  const int U = ds->unroll;
+  const int U = scan_unroll(ds);
   const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(U));
   const Device& dev = device();
   const uint64_t per_cu = std::min<uint64_t>(scan_blocks_per_cu(kmode, U), ds->blocks_per_cu);
@@ -226,7 +235,7 @@ constexpr size_t kMaxQueryGraphs = 16;
 // With profiling on, the graph records the dataset's three events around the kernels.
 hipError_t launch_query_graph(mdrq_dataset* ds, const ScanParams& p, const CompactParams& c, uint32_t kmode,
                               uint64_t grid, bool compact, hipStream_t stream) {
-  const int U = ds->unroll;
+  const int U = scan_unroll(ds);
   void* sargs[] = {const_cast<ScanParams*>(&p)};
   void* cargs[] = {const_cast<CompactParams*>(&c)};
   hipKernelNodeParams ks{};
@@ -302,7 +311,7 @@ hipError_t launch_query_graph(mdrq_dataset* ds, const ScanParams& p, const Compa
 int scan_query(mdrq_dataset* ds, const Plan& plan, const DevPred* preds, uint32_t n_preds, mdrq_result_t* r,
                hipStream_t stream, const ScanWork& w, void* out, uint64_t out_elems, uint64_t grid, uint64_t seg,
                bool host_out) {
-  const int U = ds->unroll;
+  const int U = scan_unroll(ds);
   const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(U));
   const uint32_t kmode = plan.mode == kIds ? kStage : plan.mode;
   const uint64_t n_tiles = (ds->n_rows + tile - 1) / tile;
@@ -413,7 +422,7 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
     }
     out = ds->staging;
   }
-  const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(ds->unroll));
+  const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(scan_unroll(ds)));
   const uint32_t kmode = plan.mode == kIds ? kStage : plan.mode;
   const uint64_t n_tiles = (ds->n_rows + tile - 1) / tile;
   uint64_t grid = 0, seg = 0;
@@ -434,7 +443,7 @@ int run_query(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t 
 int run_query_on(mdrq_dataset* ds, const Plan& plan, mdrq_result_t* r, hipStream_t stream, const SingleScratch& s) {
   if (plan.empty || ds->n_rows == 0) return finish_empty(ds, plan, r, stream);
   const bool host_out = r->mem == MDRQ_MEM_HOST && plan.mode != kCount;
-  const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(ds->unroll));
+  const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(scan_unroll(ds)));
   const uint32_t kmode = plan.mode == kIds ? kStage : plan.mode;
   const uint64_t n_tiles = (ds->n_rows + tile - 1) / tile;
   uint64_t grid = 0, seg = 0;
@@ -738,8 +747,8 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
       ds->graph_batch = (value & 2) != 0;
       return MDRQ_OK;
     case MDRQ_OPT_UNROLL:
-      if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
-        return fail(MDRQ_EINVAL, "unroll must be 1, 2, 4, 8 or 16");
+      if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+        return fail(MDRQ_EINVAL, "unroll must be 0, 1, 2, 4, 8 or 16");
       ds->unroll = static_cast<int>(value);
       return MDRQ_OK;
     case MDRQ_OPT_BATCH_WAVES:
@@ -780,6 +789,28 @@ int mdrq_set_option(mdrq_dataset* ds, uint32_t option, int64_t value) {
   }
 }
 
+int mdrq_get_option(const mdrq_dataset* ds, uint32_t option, int64_t* value) {
+  clear_error();
+  if (!ds || !value) return fail(MDRQ_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(const_cast<mdrq_dataset*>(ds)->mu);
+  switch (option) {
+    case MDRQ_OPT_UNROLL: *value = scan_unroll(ds); return MDRQ_OK;
+    case MDRQ_OPT_GRID: *value = static_cast<int64_t>(ds->grid); return MDRQ_OK;
+    case MDRQ_OPT_BLOCKS_PER_CU: *value = ds->blocks_per_cu; return MDRQ_OK;
+    case MDRQ_OPT_BATCH_WAVES: *value = ds->batch_waves; return MDRQ_OK;
+    case MDRQ_OPT_BATCH_GROUP: *value = ds->batch_group; return MDRQ_OK;
+    case MDRQ_OPT_AUTOTUNE: *value = ds->autotune ? 1 : 0; return MDRQ_OK;
+    case MDRQ_OPT_BATCH_ROWS: *value = ds->batch_rows; return MDRQ_OK;
+    case MDRQ_OPT_BATCH_VARIANT: *value = ds->batch_variant; return MDRQ_OK;
+    case MDRQ_OPT_RANK_BUCKETS: *value = ds->rank_buckets; return MDRQ_OK;
+    case MDRQ_OPT_GRAPHS: *value = (ds->graph_single ? 1 : 0) | (ds->graph_batch ? 2 : 0); return MDRQ_OK;
+    case MDRQ_OPT_RESERVE_FACTOR: *value = static_cast<int64_t>(ds->reserve_ppm); return MDRQ_OK;
+    case MDRQ_OPT_CIRCULAR: *value = ds->circular_mode; return MDRQ_OK;
+    default:
+      return fail(MDRQ_EINVAL, "unknown option");
+  }
+}
+
 int mdrq_probe_bandwidth(mdrq_dataset* ds, const uint32_t* dims, uint32_t k, uint32_t iters,
                          void* stream_, double* ms) {
   clear_error();
@@ -797,13 +828,13 @@ int mdrq_probe_bandwidth(mdrq_dataset* ds, const uint32_t* dims, uint32_t k, uin
   }
   p.sink = reinterpret_cast<uint32_t*>(ds->state) + offsetof(ScanState, kind) / 4;  // a sink no query reads before writing
   const Device& dev = device();
-  const int grid = static_cast<int>(static_cast<uint64_t>(scan_blocks_per_cu(kCount, ds->unroll)) * dev.cus);
+  const int grid = static_cast<int>(static_cast<uint64_t>(scan_blocks_per_cu(kCount, scan_unroll(ds))) * dev.cus);
   hipEvent_t e0, e1;
   MDRQ_HIP(hipEventCreate(&e0), "hipEventCreate");
   MDRQ_HIP(hipEventCreate(&e1), "hipEventCreate");
-  hipError_t e = launch_probe(p, ds->unroll, grid, stream);  // warm-up pass
+  hipError_t e = launch_probe(p, scan_unroll(ds), grid, stream);  // warm-up pass
   if (e == hipSuccess) e = hipEventRecord(e0, stream);
-  for (uint32_t i = 0; e == hipSuccess && i < iters; ++i) e = launch_probe(p, ds->unroll, grid, stream);
+  for (uint32_t i = 0; e == hipSuccess && i < iters; ++i) e = launch_probe(p, scan_unroll(ds), grid, stream);
   if (e == hipSuccess) e = hipEventRecord(e1, stream);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float t = 0.f;
@@ -908,7 +939,7 @@ int mdrq_query_noalloc(mdrq_dataset* ds, const mdrq_query_t* q, mdrq_result_t* r
       }
       return r->status;
     }
-    const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(ds->unroll));
+    const uint64_t tile = static_cast<uint64_t>(scan_tile_rows(scan_unroll(ds)));
     const uint32_t kmode = plan.mode == kIds ? kStage : plan.mode;
     const uint64_t n_tiles = (ds->n_rows + tile - 1) / tile;
     uint64_t grid = 0, seg = 0;

@@ -27,8 +27,8 @@ _MODE_NAMES = {v: k for k, v in _MODES.items()}
 
 EXPORTS = ["mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve", "mdrq_free",
            "mdrq_last_error", "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
-           "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth",
-           "mdrq_get_batch_profile", "mdrq_version",
+           "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_get_option",
+           "mdrq_probe_bandwidth", "mdrq_get_batch_profile", "mdrq_version",
            "mdrq_estimator_create", "mdrq_estimator_free", "mdrq_estimator_histograms",
            "mdrq_estimator_features", "mdrq_estimator_param_count", "mdrq_estimator_get_params",
            "mdrq_estimator_set_params", "mdrq_label_selectivities", "mdrq_estimator_gradient",
@@ -147,6 +147,7 @@ def load_library(path: str = LIB_PATH):
     lib.mdrq_reset_profile.argtypes = [vp]
     lib.mdrq_version.restype = ctypes.c_char_p
     lib.mdrq_set_option.argtypes = [vp, u32, ctypes.c_int64]
+    lib.mdrq_get_option.argtypes = [vp, u32, P(ctypes.c_int64)]
     lib.mdrq_probe_bandwidth.argtypes = [vp, P(u32), u32, u32, vp, P(ctypes.c_double)]
     lib.mdrq_get_batch_profile.argtypes = [vp, P(u64), P(ctypes.c_double)]
     fp, u16p = P(ctypes.c_float), P(ctypes.c_uint16)
@@ -171,8 +172,8 @@ def load_library(path: str = LIB_PATH):
     lib.mdrq_query_noalloc.argtypes = [vp, P(Query), P(Result), vp]
     for f in ("mdrq_load_columns", "mdrq_query", "mdrq_query_batch", "mdrq_serve",
               "mdrq_dataset_info", "mdrq_column_range", "mdrq_set_profiling",
-              "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_probe_bandwidth",
-              "mdrq_get_batch_profile", "mdrq_estimator_create", "mdrq_estimator_histograms",
+              "mdrq_get_profile", "mdrq_reset_profile", "mdrq_set_option", "mdrq_get_option",
+              "mdrq_probe_bandwidth", "mdrq_get_batch_profile", "mdrq_estimator_create", "mdrq_estimator_histograms",
               "mdrq_estimator_features", "mdrq_estimator_param_count", "mdrq_estimator_get_params",
               "mdrq_estimator_set_params", "mdrq_label_selectivities", "mdrq_estimator_gradient",
               "mdrq_estimator_train", "mdrq_estimator_predict", "mdrq_attach_estimator",
@@ -384,6 +385,11 @@ class Dataset:
 
     def set_option(self, option: int, value: int):
         _check(load_library().mdrq_set_option(self._h, option, value))
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int64()
+        _check(load_library().mdrq_get_option(self._h, option, ctypes.byref(v)))
+        return v.value
 
     def probe_bandwidth(self, dims, iters: int = 5, stream=None) -> float:
         """Mean ms of one full read of the listed columns (no predicate, no output)."""

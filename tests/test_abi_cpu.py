@@ -65,6 +65,7 @@ def test_calls_on_null_dataset_are_rejected():
     assert lib.mdrq_dataset_info(None, None, None) == mdrq.EINVAL
     assert lib.mdrq_column_range(None, 0, None, None) == mdrq.EINVAL
     assert lib.mdrq_set_option(None, mdrq.OPT_UNROLL, 4) == mdrq.EINVAL
+    assert lib.mdrq_get_option(None, mdrq.OPT_UNROLL, None) == mdrq.EINVAL
     lib.mdrq_free(None)
 
 

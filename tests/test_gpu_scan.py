@@ -66,14 +66,20 @@ SIZES = [1, 3, 4, 5, 63, 64, 65, 255, 256, 257, 1023, 1024, 1025, 4095, 4096, 40
          32769, 300001]
 
 
-@pytest.mark.parametrize("unroll", [1, 2, 4, 8])
+@pytest.mark.parametrize("unroll", [0, 1, 2, 4, 8])
 def test_sizes_tiles_and_ragged_tails(unroll):
+    """unroll 0: the tile height chosen by rows per CU (2 below 6144, 4 below 65536)."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
     for n in SIZES:
         _print("sizes: unroll", unroll, "n", n)
         raw = [dg.column(11, j, dg.uniform(), n) for j in range(3)]
         cols = oracle.prepare(raw)
         with mdrq.Dataset.from_host(raw) as ds:
             ds.set_option(mdrq.OPT_UNROLL, unroll)
+            per_cu = n // cus
+            want_u = unroll or (2 if per_cu < 6144 else 4 if per_cu < 65536 else 8)
+            assert ds.get_option(mdrq.OPT_UNROLL) == want_u
             rng = np.random.default_rng(n + unroll)
             qs = [dg.make_query([]), dg.make_query([(0, 0.0, 1.0)])]
             for s in (0.5, 0.05, 0.001):
