@@ -243,8 +243,8 @@ constexpr uint32_t kCompactStage = 2048;   // ids per wave staged in LDS
 // from a scan of their counts in LDS; then each wave takes 64-word chunks (4096 rows):
 // one coalesced load and a wave scan of the words' popcounts; a chunk of up to 2048 ids
 // is staged in LDS as 16-bit row offsets at their output places and written out in
-// consecutive 64-lane runs, a denser one is written by each lane for its word.  Chunks
-// without a hit are skipped without being read.
+// consecutive 64-lane runs, a denser one is written word by word with one bit per lane.
+// Chunks without a hit are skipped without being read.
 template <int U>
 __global__ void __launch_bounds__(kBlock) compact_kernel(CompactParams c) {
   constexpr uint32_t kTileRows = 256 * U;
@@ -350,14 +350,22 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(CompactParams c) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      } else {   // a dense chunk: each lane writes its word's ids directly
-        uint64_t r = off + incl - k;
-        const uint32_t row = static_cast<uint32_t>(w * 64);
-        while (bits) {
-          const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(bits));
-          if (r < c.capacity) c.ids[r] = row + b;
-          ++r;
-          bits &= bits - 1;
+      } else {
+        // A dense chunk, word by word: lane l takes bit l of the word, whose place is
+        // the word's offset plus the set bits below it, so each store is one run of
+        // consecutive ids.
+        const uint32_t before = incl - k;
+        const uint32_t row0 = static_cast<uint32_t>(w0 * 64);
+        const uint32_t wlo = static_cast<uint32_t>(word);
+        const uint32_t whi = static_cast<uint32_t>(word >> 32);
+        for (uint32_t j = 0; j < kChunkWords; ++j) {
+          const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(wlo), static_cast<int>(j)));
+          const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(whi), static_cast<int>(j)));
+          const uint32_t at = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(before), static_cast<int>(j)));
+          const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+          const bool set = (((static_cast<uint64_t>(hi) << 32 | lo) >> lane) & 1u) != 0;
+          const uint64_t r = off + at + below;
+          if (set && r < c.capacity) c.ids[r] = row0 + 64 * j + lane;
         }
       }
     }

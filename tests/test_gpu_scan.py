@@ -381,3 +381,26 @@ def test_graph_replays_match_direct_launches():
             assert val == results[(0, key[1], key[2])], key
         launches, scan_ms, total_ms = ds.profile()
         assert launches > 0 and 0 < scan_ms <= total_ms
+
+
+@pytest.mark.parametrize("unroll", [0, 1, 8])
+def test_dense_chunks_and_caps(unroll):
+    """Chunks of 4096 rows with more than 2048 hits (written word by word, one bit per
+    lane) next to sparser ones (staged in LDS), whole and cut by the output's capacity
+    inside a chunk."""
+    n = 1_000_003
+    raw = [dg.column(23, j, dg.uniform(), n) for j in range(2)]
+    cols = oracle.prepare(raw)
+    with mdrq.Dataset.from_host(raw) as ds:
+        ds.set_option(mdrq.OPT_UNROLL, unroll)
+        for preds in ([(0, 0.0, 1.0)], [(0, 0.0, 0.9)], [(0, 0.2, 0.75)], [(0, 0.0, 0.52)],
+                      [(0, 0.1, 0.99), (1, 0.0, 0.97)]):
+            q = dg.make_query(preds)
+            st_, cnt, want = oracle.query(cols, q)
+            _print("dense: unroll", unroll, preds, cnt)
+            a, got = run(ds, q)
+            assert a.count == cnt and np.array_equal(got, want)
+            for cap in (cnt // 2 + 37, 3 * 4096 + 5):
+                a, got = run(ds, q, cap=cap)
+                assert a.status == mdrq.EOVERFLOW and a.count == cnt and a.written == cap
+                assert np.array_equal(got, want[:cap])
