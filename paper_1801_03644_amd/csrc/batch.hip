@@ -1181,7 +1181,23 @@ __global__ void __launch_bounds__(kFinThreads) batch_emit_kernel(BatchFinish f) 
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {  // a dense or a sparse tile: each lane writes its ids directly
+    } else if (total > kEmitStage) {
+      // A dense tile, word by word: lane l takes bit l of the word, whose place is the
+      // word's offset plus the set bits below it, so each store is one run of ids.
+      const uint32_t before = incl - k;
+      const uint32_t tile_row = static_cast<uint32_t>(t * 4096);
+      const uint32_t wlo = static_cast<uint32_t>(word);
+      const uint32_t whi = static_cast<uint32_t>(word >> 32);
+      for (uint32_t j = 0; j < 64; ++j) {
+        const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(wlo), static_cast<int>(j)));
+        const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(whi), static_cast<int>(j)));
+        const uint32_t at = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(before), static_cast<int>(j)));
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+        const bool set = (((static_cast<uint64_t>(hi) << 32 | lo) >> lane) & 1u) != 0;
+        const uint64_t r = beg + at + below;
+        if (set && r < capacity) ids[r] = tile_row + 64 * j + lane;
+      }
+    } else {  // a sparse tile: each lane writes its ids directly
       uint64_t r = beg + incl - k;
       while (bits) {
         const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(bits));
